@@ -1,0 +1,314 @@
+/*
+ * gcharm.h: C ABI of the combined irregular-task force library for MI355X
+ * (gfx950).
+ *
+ * The library runs many small, uneven work requests (tasks) in one device
+ * launch, after a data-reorganisation pass that reuses records already
+ * resident in a device pool, stages only the missing ones, and packs the union
+ * of what a combined request touches into one contiguous buffer.  The
+ * operations follow the paper's runtime strategies:
+ *   - a work request names the data it touches (Sec. 3.2: a workRequest holds
+ *     the indices of the chare buffers it reads);
+ *   - the runtime keeps a chare table mapping resident data to device slots
+ *     and transfers only data not already on the device (Sec. 2.2, Sec. 3.2);
+ *   - accessed indices are kept sorted so that threads read in index order
+ *     (Sec. 3.2, reassignment by sorted indices; data reorganisation named as
+ *     the alternative);
+ *   - many requests are combined into one kernel (Sec. 2.2, Sec. 3.1).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns gc_status; 0 is success.  No exception or abort
+ *     crosses the ABI.  On failure gc_last_error(ctx) holds a message that
+ *     stays valid until the next call on that context.
+ *   - "host" arrays are read during the call only (copied); "device" arrays
+ *     are device-resident (hipMalloc / torch) and owned by the caller.
+ *   - Streams are hipStream_t passed as void* (NULL = default stream); the
+ *     library enqueues work and returns without synchronising unless a call
+ *     says otherwise.
+ *   - Records are 16 bytes: float4 (x, y, z, m) for gravity, float4
+ *     (x, y, z, type) for Lennard-Jones (type stored as a float 0.0, 1.0, ...).
+ *   - A context is single-threaded: calls on one context (and on pools and
+ *     batches created from it) must not overlap from different host threads.
+ *   - After an asynchronous device error a context is poisoned: the call that
+ *     observes it returns GC_E_HIP and every later call GC_E_STATE, until
+ *     gc_finalize.
+ */
+#ifndef GCHARM_H
+#define GCHARM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GC_OK = 0,
+  GC_E_INVAL = 1,       /* bad argument: ids or ranges out of bounds, bad mode, NULL pointer */
+  GC_E_NOMEM = 2,       /* device or pinned allocation failed */
+  GC_E_FULL = 3,        /* the pool has fewer free slots than missing records */
+  GC_E_STATE = 4,       /* call out of order, or context poisoned */
+  GC_E_HIP = 5,         /* a HIP runtime call or kernel failed */
+  GC_E_UNSUPPORTED = 6  /* combination not implemented */
+} gc_status;
+
+typedef struct gc_ctx_* gc_ctx;
+typedef struct gc_pool_* gc_pool;
+typedef struct gc_batch_* gc_batch;
+typedef struct gc_graph_* gc_graph;
+
+/* ---------------------------------------------------------------- context */
+
+/* Open a context on HIP device `device` (makes it current for the calling thread). */
+gc_status gc_init(int device, gc_ctx* out);
+/* Release everything the context owns (pools and batches must be destroyed first or are leaked). */
+gc_status gc_finalize(gc_ctx ctx);
+/* Last error message of the context ("" if none). Owned by the context. */
+const char* gc_last_error(gc_ctx ctx);
+/* Library version string, static. */
+const char* gc_version(void);
+
+/* ---------------------------------------------------------------- pool (chare table) */
+
+/*
+ * A device pool of `capacity` 16-byte record slots plus the chare table
+ * slot_of[n_ids] (int32, -1 = not resident) over ids [0, n_ids) (Sec. 3.2:
+ * the chare table maps chare buffers to device slots).  All slots start free.
+ * Pool memory is owned by the library.
+ */
+gc_status gc_pool_create(gc_ctx ctx, int32_t n_ids, int32_t capacity, gc_pool* out);
+gc_status gc_pool_destroy(gc_pool pool);
+
+/*
+ * Where records of ids not resident are read from when a reorganisation
+ * stages them (Sec. 3.2: only data not already on the device is moved).
+ * `records` holds n_ids float4 records indexed by id.  It may be device
+ * memory (staging is then a device gather) or pinned host memory from
+ * hipHostMalloc (staging then reads it over PCIe from the kernel; only the
+ * missing records cross the link).  The caller owns it; it must stay valid
+ * and unchanged while batches reorganised against this pool are in flight.
+ */
+gc_status gc_pool_set_source(gc_pool pool, const void* records);
+
+/*
+ * Residency fixture: make ids[k] resident in slots[k] (device int32 arrays of
+ * length n), copying their records from the source.  Ids must be distinct,
+ * not yet resident, and slots distinct and free; violations are not detected
+ * on the device (the host does not see the arrays) and leave the table
+ * inconsistent.  Asynchronous on `stream`.
+ */
+gc_status gc_pool_place(gc_pool pool, const int32_t* ids_dev, const int32_t* slots_dev, int32_t n, void* stream);
+
+/* Evict every record (all slots free, slot_of all -1). Asynchronous. */
+gc_status gc_pool_reset(gc_pool pool, void* stream);
+
+/* Copy slot_of (n_ids int32) to host memory; synchronises `stream`. */
+gc_status gc_pool_query(gc_pool pool, int32_t* slot_of_host, void* stream);
+
+/* Device pointers of the pool internals (float4 records[capacity], int32 slot_of[n_ids]). */
+gc_status gc_pool_device_ptrs(gc_pool pool, void** records, int32_t** slot_of);
+
+/* ---------------------------------------------------------------- batch (combined request) */
+
+enum { GC_KIND_GRAV = 0, GC_KIND_LJ = 1 };
+enum { GC_TASK_SELF = 1 };  /* LJ: i and j ranges are the same cell; pairs i < j only */
+
+/*
+ * One work request (Sec. 2.2: a workRequest; Sec. 4.1: a bucket whose
+ * particles share one interaction list; Sec. 4.2: a compute object for a
+ * pair of patches).
+ *   i_begin, i_count   target ids [i_begin, i_begin + i_count)
+ *   j_first, j_nranges direct source ranges: pairs (begin, count) at
+ *                      j_ranges[2*j_first ...] of the same submit call
+ *   n_first, n_count   node references node_idx[n_first ...] of the same call
+ *                      (gravity only)
+ *   flags              GC_TASK_SELF (Lennard-Jones)
+ *   shift              Lennard-Jones periodic image shift of the j range
+ *                      (the j atoms' images sit at x_j + shift); 0 for gravity
+ * Gravity: targets need not lie inside the direct ranges; a target id found in
+ * its own direct ranges contributes nothing (j == i is skipped).
+ * Lennard-Jones: exactly one j range per task.
+ */
+typedef struct {
+  int32_t i_begin, i_count;
+  int32_t j_first, j_nranges;
+  int32_t n_first, n_count;
+  int32_t flags;
+  float shift[3];
+} gc_task;
+
+/* A batch of kind GC_KIND_GRAV or GC_KIND_LJ over ids [0, n_ids). */
+gc_status gc_batch_create(gc_ctx ctx, int32_t kind, int32_t n_ids, gc_batch* out);
+gc_status gc_batch_destroy(gc_batch batch);
+/* Drop all submitted tasks (device buffers are kept for reuse). */
+gc_status gc_batch_reset(gc_batch batch);
+
+/*
+ * Append n_tasks tasks (host arrays, copied).  j_ranges holds n_ranges
+ * (begin, count) pairs; node_idx holds n_node_refs node indices; tasks index
+ * into these arrays relative to this call.  Validation (host side, strong
+ * guarantee: on error nothing is appended): ids and ranges inside [0, n_ids),
+ * counts >= 0, list slices inside the given arrays, node indices >= 0,
+ * Lennard-Jones tasks with exactly one j range and no nodes.
+ */
+gc_status gc_submit_tasks(gc_batch batch, const gc_task* tasks, int32_t n_tasks, const int32_t* j_ranges,
+                          int32_t n_ranges, const int32_t* node_idx, int32_t n_node_refs);
+
+/* Upload the submitted tasks to the device (once; later calls are no-ops
+ * until the next submit or reset).  Asynchronous on `stream`. */
+gc_status gc_batch_commit(gc_batch batch, void* stream);
+
+/* Number of tasks, ranges, node refs, direct entries (sum of range counts) and targets. */
+gc_status gc_batch_sizes(gc_batch batch, int64_t* out5);
+
+/*
+ * Reorganisation (Sec. 3.2) of a committed batch against a pool, on `stream`:
+ *  a. mark every id of every target and direct range;
+ *  b. union U = marked ids ascending (the sorted index array), pos[id] = rank
+ *     in U, missing = ids of U not resident, ascending (chare-table lookup);
+ *  c. the k-th missing id gets the k-th lowest free slot; its record is copied
+ *     from the pool's source into that slot (it stays resident afterwards);
+ *  d. then, by mode:
+ *   GC_REORG_PACK      packed[k] = pool[slot_of[U[k]]] for k < |U|; every
+ *                      range (b, c) becomes (pos[b], c) and targets read
+ *                      packed[pos[i]]: contiguous, coalesced reads;
+ *   GC_REORG_INDIRECT  per task, the pool slot of every target and of every
+ *                      direct id in list order (the per-request address
+ *                      buffer; two dependent loads per record);
+ *   GC_REORG_SORTED    as INDIRECT with each task's direct slots sorted
+ *                      ascending (reassignment by sorted indices);
+ *   GC_REORG_REDUNDANT no reuse: every id of U is copied from the source into
+ *                      packed (redundant transfer, fully coalesced); the pool
+ *                      is not touched;
+ *   GC_REORG_NONE      no reorganisation: the source must be device memory
+ *                      and is read in place by id.
+ * Returns GC_E_FULL (pool unchanged) if the pool lacks free slots; this check
+ * synchronises the stream (the host needs the missing count).  With
+ * check_capacity = 0 the call never synchronises; the caller then guarantees
+ * capacity (e.g. capacity >= n_ids).
+ */
+enum { GC_REORG_REDUNDANT = 0, GC_REORG_INDIRECT = 1, GC_REORG_SORTED = 2, GC_REORG_PACK = 3, GC_REORG_NONE = 4 };
+gc_status gc_reorganize(gc_batch batch, gc_pool pool, int32_t mode, int32_t check_capacity, void* stream);
+
+/*
+ * Host copies of the last reorganisation's maps (synchronises `stream`):
+ * counts[0] = |U|, counts[1] = #missing.  Each output may be NULL.
+ *   U[|U|], pos[n_ids] (-1 outside U), missing[#missing],
+ *   new_slot[#missing] (slot given to missing[k]; REDUNDANT: not written),
+ *   pranges[2*n_ranges], pi_begin[n_tasks] (PACK / REDUNDANT),
+ *   ilist[sum i_count], jlist[sum direct entries] (INDIRECT / SORTED).
+ * Sizes are from gc_batch_sizes.
+ */
+gc_status gc_batch_maps(gc_batch batch, int64_t* counts, int32_t* U, int32_t* pos, int32_t* missing,
+                        int32_t* new_slot, int32_t* pranges, int32_t* pi_begin, int32_t* ilist, int32_t* jlist,
+                        void* stream);
+
+/* ---------------------------------------------------------------- combined force pass */
+
+enum { GC_FORCE_GRAV_MONO = 1, GC_FORCE_GRAV_QUAD = 2, GC_FORCE_LJ = 3 };
+
+/*
+ * Force-law parameters.
+ * Gravity (Sec. 4.1 workload; softened Newtonian gravity with Barnes-Hut
+ * node terms): G, soft_eps > 0 (Plummer softening); node records are 12
+ * floats (com x y z, M, Sxx Syy Szz Sxy, Sxz Syz T, 0) with S the raw second
+ * moment about the centre of mass and T its trace; GC_FORCE_GRAV_MONO reads
+ * only the first 4 floats of each node record.
+ *   direct:     a_i += G m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^{3/2}, j != i
+ *   monopole:   a_i += -G M d / r^3, d = x_i - com, r^2 = |d|^2 + eps^2
+ *   quadrupole: a_i += G [3 S d / r^5 - 15/2 (d.S.d) d / r^7 + 3/2 T d / r^5]
+ * Lennard-Jones (Sec. 4.2 workload; a compute object updates the forces of
+ * both cells): per-type eps_t, sig_t, mass_t (device float arrays of n_types),
+ * Lorentz-Berthelot mixing, cutoff r_cut (pairs with r^2 < r_cut^2, decided
+ * in FP32), force on i = 24 eps (2 q^6 - q^3) / r^2 d, q = sigma^2 / r^2,
+ * d = x_i - x_j - shift, equal and opposite on j; a = F / m.
+ */
+typedef struct {
+  int32_t kind;             /* GC_FORCE_* */
+  float G, soft_eps;        /* gravity */
+  int32_t n_types;          /* Lennard-Jones */
+  const float* eps_t;       /* device */
+  const float* sig_t;       /* device */
+  const float* mass_t;      /* device */
+  float r_cut;
+  int32_t schedule;         /* 0 = one launch over all tasks; 1 = persistent work queue */
+  int32_t tile;             /* direct-record tile per wavefront: 0 = default (256); 64..1024, multiple of 64 */
+  int32_t waves_per_block;  /* 0 = default (4); 1..8 */
+  int32_t grid_blocks;      /* persistent schedule: 0 = CUs x occupancy */
+} gc_force_params;
+
+/*
+ * The combined kernel (Sec. 3.1: many requests, one launch): every task of a
+ * reorganised batch computes its targets' accelerations; acc_dev is float4
+ * [n_ids] (x, y, z acceleration, w = 0), caller-owned.  Gravity writes the
+ * rows of targeted ids only (each id must be the target of at most one
+ * task).  Lennard-Jones accumulates with atomics: the caller zeroes acc_dev
+ * first (gc_zero_f32 does it without a memset node).  nodes_dev: float
+ * [n_nodes * 12] (gravity), unused for Lennard-Jones.  Asynchronous.
+ */
+gc_status gc_launch_combined(gc_batch batch, const gc_force_params* prm, const float* nodes_dev, float* acc_dev,
+                             void* stream);
+
+/* Fill n floats with 0 by a kernel (graph-capture safe). */
+gc_status gc_zero_f32(gc_ctx ctx, float* dev, int64_t n, void* stream);
+
+/* ---------------------------------------------------------------- adjoint */
+
+/*
+ * Vector-Jacobian product of L = sum_i cot_i . a_i for the last combined pass
+ * of `batch` (same reorganisation, same parameters), recomputing pair terms.
+ *   cot_dev   float4 [n_ids] cotangent on acc (w ignored)
+ *   gpos_dev  float4 [n_ids] += dL/dx (w unused), caller zeroes first
+ *   gmass_dev float  [n_ids] += dL/dm (gravity: source masses and node mass
+ *             chain; Lennard-Jones: per-atom mass as if each atom had its own)
+ *   gparam_dev float [2 * n_types] += (dL/deps_t, dL/dsig_t) (Lennard-Jones)
+ * Gravity supports GC_FORCE_GRAV_MONO; node gradients flow to member particles
+ * through com = sum m_k x_k / M and M = sum m_k (node_range_dev: int32
+ * [2 * n_nodes] (first id, count) of each node's members; members are read
+ * in place from the pool's source, which must be device memory).  Lists and
+ * cutoff decisions are those of the forward pass.  Asynchronous.
+ */
+gc_status gc_backward(gc_batch batch, const gc_force_params* prm, const float* nodes_dev,
+                      const int32_t* node_range_dev, int32_t n_nodes, const float* cot_dev, float* gpos_dev,
+                      float* gmass_dev, float* gparam_dev, void* stream);
+
+/* ---------------------------------------------------------------- graphs */
+
+/*
+ * Capture a sequence of (reorganise, combined pass) steps over several
+ * batches into one HIP graph on `stream` and instantiate it.  Each step k:
+ * gc_reorganize(batches[k], pools[k], modes[k], check_capacity = 0) then
+ * gc_launch_combined(batches[k], prm, nodes_dev, acc_dev).  Batches must be
+ * committed.  pre_reset != 0 resets each pool before its step (so every
+ * replay starts from the same residency; placements given with
+ * place_ids/place_slots/place_n per step are re-applied after the reset).
+ */
+gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* batches, gc_pool* pools, const int32_t* modes,
+                           const gc_force_params* prm, const float* nodes_dev, float* acc_dev, int32_t pre_reset,
+                           const int32_t* const* place_ids, const int32_t* const* place_slots,
+                           const int32_t* place_n, void* stream, gc_graph* out);
+gc_status gc_graph_launch(gc_graph graph, void* stream);
+gc_status gc_graph_destroy(gc_graph graph);
+
+/* ---------------------------------------------------------------- tuning and introspection */
+
+/*
+ * Time the combined pass of a reorganised batch for each candidate (tile,
+ * waves_per_block, schedule) and return the fastest in *best (prm fields
+ * other than those three are copied from `base`).  Synchronises `stream`.
+ * times_ms (optional, n_cand floats) receives the measured average per
+ * candidate; candidates are tiles {128, 256, 512} x waves {2, 4, 8} x
+ * schedules {0, 1} in that nesting order (n_cand = 18).
+ */
+gc_status gc_autotune(gc_batch batch, const gc_force_params* base, const float* nodes_dev, float* acc_dev,
+                      int32_t reps, float* times_ms, gc_force_params* best, void* stream);
+
+/* Occupancy of the combined gravity kernel: resident blocks per CU and CU count. */
+gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_t* blocks_per_cu, int32_t* n_cu);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCHARM_H */

@@ -1,0 +1,341 @@
+"""MI355X combined irregular-task force library: Python binding of the C ABI in include/gcharm.h.
+
+Argument marshalling only: every step of the path (reorganisation, combined
+force pass, adjoint) runs in the HIP kernels of ``libgcharm.so``.  PyTorch
+supplies device memory and streams.  Importing works without the library;
+the first call that needs it raises :class:`GcError` if ``libgcharm.so`` has
+not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["GcError", "lib", "Context", "Pool", "Batch", "Graph", "ForceParams", "TASK_DTYPE",
+           "REORG_REDUNDANT", "REORG_INDIRECT", "REORG_SORTED", "REORG_PACK", "REORG_NONE",
+           "FORCE_GRAV_MONO", "FORCE_GRAV_QUAD", "FORCE_LJ", "KIND_GRAV", "KIND_LJ", "TASK_SELF",
+           "LIB_PATH", "EXPORTED"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgcharm.so")
+
+GC_OK, GC_E_INVAL, GC_E_NOMEM, GC_E_FULL, GC_E_STATE, GC_E_HIP, GC_E_UNSUPPORTED = range(7)
+KIND_GRAV, KIND_LJ = 0, 1
+TASK_SELF = 1
+REORG_REDUNDANT, REORG_INDIRECT, REORG_SORTED, REORG_PACK, REORG_NONE = 0, 1, 2, 3, 4
+FORCE_GRAV_MONO, FORCE_GRAV_QUAD, FORCE_LJ = 1, 2, 3
+
+# gc_task: 7 int32 + 3 float32 = 40 bytes
+TASK_DTYPE = np.dtype([("i_begin", "<i4"), ("i_count", "<i4"), ("j_first", "<i4"), ("j_nranges", "<i4"),
+                       ("n_first", "<i4"), ("n_count", "<i4"), ("flags", "<i4"), ("shift", "<f4", (3,))])
+
+EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_pool_create", "gc_pool_destroy",
+            "gc_pool_set_source", "gc_pool_place", "gc_pool_reset", "gc_pool_query", "gc_pool_device_ptrs",
+            "gc_batch_create", "gc_batch_destroy", "gc_batch_reset", "gc_submit_tasks", "gc_batch_commit",
+            "gc_batch_sizes", "gc_reorganize", "gc_batch_maps", "gc_launch_combined", "gc_zero_f32", "gc_backward",
+            "gc_graph_capture", "gc_graph_launch", "gc_graph_destroy", "gc_autotune", "gc_occupancy"]
+
+
+class GcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gcharm status {status}: {msg}")
+        self.status = status
+
+
+class ForceParams(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("G", ctypes.c_float), ("soft_eps", ctypes.c_float),
+                ("n_types", ctypes.c_int32), ("eps_t", ctypes.c_void_p), ("sig_t", ctypes.c_void_p),
+                ("mass_t", ctypes.c_void_p), ("r_cut", ctypes.c_float), ("schedule", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+VP, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+PI32 = ctypes.POINTER(ctypes.c_int32)
+PI64 = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib():
+    """The loaded libgcharm.so (raises GcError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GcError(GC_E_STATE, f"{LIB_PATH} is missing: run __graft_entry__.build() (no fallback exists)")
+    # torch ships its own HIP runtime with the same soname (libamdhip64.so.7).  Loading torch first
+    # makes libgcharm.so bind to that runtime, so torch's device pointers and stream handles are
+    # valid in the library and the process holds a single HIP runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "gc_version": (ctypes.c_char_p, []),
+        "gc_init": (I32, [ctypes.c_int, ctypes.POINTER(VP)]),
+        "gc_finalize": (I32, [VP]),
+        "gc_last_error": (ctypes.c_char_p, [VP]),
+        "gc_pool_create": (I32, [VP, I32, I32, ctypes.POINTER(VP)]),
+        "gc_pool_destroy": (I32, [VP]),
+        "gc_pool_set_source": (I32, [VP, VP]),
+        "gc_pool_place": (I32, [VP, VP, VP, I32, VP]),
+        "gc_pool_reset": (I32, [VP, VP]),
+        "gc_pool_query": (I32, [VP, VP, VP]),
+        "gc_pool_device_ptrs": (I32, [VP, ctypes.POINTER(VP), ctypes.POINTER(VP)]),
+        "gc_batch_create": (I32, [VP, I32, I32, ctypes.POINTER(VP)]),
+        "gc_batch_destroy": (I32, [VP]),
+        "gc_batch_reset": (I32, [VP]),
+        "gc_submit_tasks": (I32, [VP, VP, I32, VP, I32, VP, I32]),
+        "gc_batch_commit": (I32, [VP, VP]),
+        "gc_batch_sizes": (I32, [VP, PI64]),
+        "gc_reorganize": (I32, [VP, VP, I32, I32, VP]),
+        "gc_batch_maps": (I32, [VP, PI64, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
+        "gc_launch_combined": (I32, [VP, ctypes.POINTER(ForceParams), VP, VP, VP]),
+        "gc_zero_f32": (I32, [VP, VP, I64, VP]),
+        "gc_backward": (I32, [VP, ctypes.POINTER(ForceParams), VP, VP, I32, VP, VP, VP, VP, VP]),
+        "gc_graph_capture": (I32, [VP, I32, ctypes.POINTER(VP), ctypes.POINTER(VP), VP, ctypes.POINTER(ForceParams),
+                                   VP, VP, I32, ctypes.POINTER(VP), ctypes.POINTER(VP), VP, VP, ctypes.POINTER(VP)]),
+        "gc_graph_launch": (I32, [VP, VP]),
+        "gc_graph_destroy": (I32, [VP]),
+        "gc_autotune": (I32, [VP, ctypes.POINTER(ForceParams), VP, VP, I32, VP, ctypes.POINTER(ForceParams), VP]),
+        "gc_occupancy": (I32, [VP, ctypes.POINTER(ForceParams), PI32, PI32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(x) -> int | None:
+    """Device/host address of a torch tensor, numpy array or int (None passes NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        try:
+            import torch
+            return torch.cuda.current_stream().cuda_stream
+        except Exception:  # noqa: BLE001 - no torch GPU: default stream
+            return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+class Context:
+    """One device context (gc_init / gc_finalize)."""
+
+    def __init__(self, device: int = 0):
+        self.h = VP()
+        st = lib().gc_init(device, ctypes.byref(self.h))
+        if st != GC_OK:
+            raise GcError(st, f"gc_init({device}) failed")
+
+    def check(self, st: int, what: str = ""):
+        if st != GC_OK:
+            raise GcError(st, f"{what}: {lib().gc_last_error(self.h).decode()}")
+
+    def zero(self, t, stream=None):
+        self.check(lib().gc_zero_f32(self.h, _ptr(t), t.numel(), _stream(stream)), "gc_zero_f32")
+
+    def occupancy(self, prm: ForceParams):
+        b, n = ctypes.c_int32(), ctypes.c_int32()
+        self.check(lib().gc_occupancy(self.h, ctypes.byref(prm), ctypes.byref(b), ctypes.byref(n)), "gc_occupancy")
+        return b.value, n.value
+
+    def close(self):
+        if self.h:
+            lib().gc_finalize(self.h)
+            self.h = VP()
+
+
+class Pool:
+    """Device record pool + chare table (gc_pool_*)."""
+
+    def __init__(self, ctx: Context, n_ids: int, capacity: int):
+        self.ctx = ctx
+        self.n_ids, self.capacity = n_ids, capacity
+        self.h = VP()
+        ctx.check(lib().gc_pool_create(ctx.h, n_ids, capacity, ctypes.byref(self.h)), "gc_pool_create")
+        self._src = None
+
+    def set_source(self, records):
+        self._src = records  # keep alive
+        self.ctx.check(lib().gc_pool_set_source(self.h, _ptr(records)), "gc_pool_set_source")
+
+    def place(self, ids_dev, slots_dev, stream=None):
+        self.ctx.check(lib().gc_pool_place(self.h, _ptr(ids_dev), _ptr(slots_dev), int(ids_dev.numel()),
+                                           _stream(stream)), "gc_pool_place")
+
+    def reset(self, stream=None):
+        self.ctx.check(lib().gc_pool_reset(self.h, _stream(stream)), "gc_pool_reset")
+
+    def query(self, stream=None) -> np.ndarray:
+        out = np.empty(self.n_ids, np.int32)
+        self.ctx.check(lib().gc_pool_query(self.h, out.ctypes.data, _stream(stream)), "gc_pool_query")
+        return out
+
+    def device_ptrs(self):
+        r, s = VP(), VP()
+        self.ctx.check(lib().gc_pool_device_ptrs(self.h, ctypes.byref(r), ctypes.byref(s)), "gc_pool_device_ptrs")
+        return r.value, s.value
+
+    def destroy(self):
+        if self.h:
+            lib().gc_pool_destroy(self.h)
+            self.h = VP()
+
+
+def tasks_from_csr(i_begin, i_count, j_first, j_nr, n_first=None, n_count=None, flags=None, shift=None) -> np.ndarray:
+    """Pack per-task CSR columns into gc_task records."""
+    T = len(i_begin)
+    t = np.zeros(T, TASK_DTYPE)
+    t["i_begin"], t["i_count"], t["j_first"], t["j_nranges"] = i_begin, i_count, j_first, j_nr
+    if n_first is not None:
+        t["n_first"], t["n_count"] = n_first, n_count
+    if flags is not None:
+        t["flags"] = flags
+    if shift is not None:
+        t["shift"] = shift
+    return t
+
+
+class Batch:
+    """A combined work request (gc_batch_*, gc_submit_tasks, gc_reorganize, gc_launch_combined, gc_backward)."""
+
+    def __init__(self, ctx: Context, kind: int, n_ids: int):
+        self.ctx = ctx
+        self.kind, self.n_ids = kind, n_ids
+        self.h = VP()
+        ctx.check(lib().gc_batch_create(ctx.h, kind, n_ids, ctypes.byref(self.h)), "gc_batch_create")
+
+    def submit(self, tasks: np.ndarray, ranges: np.ndarray, node_idx: np.ndarray | None = None):
+        tasks = np.ascontiguousarray(tasks, TASK_DTYPE)
+        ranges = np.ascontiguousarray(ranges, np.int32).reshape(-1, 2)
+        node_idx = np.ascontiguousarray(np.zeros(0, np.int32) if node_idx is None else node_idx, np.int32)
+        self.ctx.check(lib().gc_submit_tasks(self.h, tasks.ctypes.data, len(tasks), ranges.ctypes.data,
+                                             ranges.shape[0], node_idx.ctypes.data, node_idx.size), "gc_submit_tasks")
+
+    def commit(self, stream=None):
+        self.ctx.check(lib().gc_batch_commit(self.h, _stream(stream)), "gc_batch_commit")
+
+    def sizes(self) -> dict:
+        out = np.zeros(5, np.int64)
+        self.ctx.check(lib().gc_batch_sizes(self.h, out.ctypes.data_as(PI64)), "gc_batch_sizes")
+        return dict(tasks=int(out[0]), ranges=int(out[1]), node_refs=int(out[2]), direct=int(out[3]),
+                    targets=int(out[4]))
+
+    def reorganize(self, pool: Pool, mode: int, check_capacity: bool = True, stream=None):
+        self.ctx.check(lib().gc_reorganize(self.h, pool.h, mode, 1 if check_capacity else 0, _stream(stream)),
+                       "gc_reorganize")
+
+    def maps(self, stream=None) -> dict:
+        sz = self.sizes()
+        counts = np.zeros(2, np.int64)
+        n = self.n_ids
+        U = np.empty(max(n, 1), np.int32)
+        pos = np.empty(max(n, 1), np.int32)
+        missing = np.empty(max(n, 1), np.int32)
+        new_slot = np.empty(max(n, 1), np.int32)
+        pr = np.empty((max(sz["ranges"], 1), 2), np.int32)
+        pib = np.empty(max(sz["tasks"], 1), np.int32)
+        il = np.empty(max(sz["targets"], 1), np.int32)
+        jl = np.empty(max(sz["direct"], 1), np.int32)
+        self.ctx.check(lib().gc_batch_maps(self.h, counts.ctypes.data_as(PI64), U.ctypes.data, pos.ctypes.data,
+                                           missing.ctypes.data, new_slot.ctypes.data, pr.ctypes.data, pib.ctypes.data,
+                                           il.ctypes.data, jl.ctypes.data, _stream(stream)), "gc_batch_maps")
+        nu, nm = int(counts[0]), int(counts[1])
+        return dict(U=U[:nu], pos=pos[:n], missing=missing[:nm], new_slot=new_slot[:nm], pranges=pr[:sz["ranges"]],
+                    pi_begin=pib[:sz["tasks"]], ilist=il[:sz["targets"]], jlist=jl[:sz["direct"]])
+
+    def launch(self, prm: ForceParams, nodes, acc, stream=None):
+        self.ctx.check(lib().gc_launch_combined(self.h, ctypes.byref(prm), _ptr(nodes), _ptr(acc), _stream(stream)),
+                       "gc_launch_combined")
+
+    def backward(self, prm: ForceParams, nodes, node_range, n_nodes: int, cot, gpos, gmass, gparam=None,
+                 stream=None):
+        self.ctx.check(lib().gc_backward(self.h, ctypes.byref(prm), _ptr(nodes), _ptr(node_range), int(n_nodes),
+                                         _ptr(cot), _ptr(gpos), _ptr(gmass), _ptr(gparam), _stream(stream)),
+                       "gc_backward")
+
+    def autotune(self, base: ForceParams, nodes, acc, reps: int = 3, stream=None):
+        times = np.zeros(18, np.float32)
+        best = ForceParams()
+        self.ctx.check(lib().gc_autotune(self.h, ctypes.byref(base), _ptr(nodes), _ptr(acc), reps, times.ctypes.data,
+                                         ctypes.byref(best), _stream(stream)), "gc_autotune")
+        return best, times
+
+    def destroy(self):
+        if self.h:
+            lib().gc_batch_destroy(self.h)
+            self.h = VP()
+
+
+class Graph:
+    """A captured sequence of (reorganise, combined pass) steps (gc_graph_*)."""
+
+    def __init__(self, ctx: Context, batches, pools, modes, prm: ForceParams, nodes, acc, pre_reset: bool = False,
+                 places=None, stream=None):
+        n = len(batches)
+        self.ctx = ctx
+        self.h = VP()
+        B = (VP * n)(*[b.h.value for b in batches])
+        P = (VP * n)(*[p.h.value for p in pools])
+        M = np.ascontiguousarray(modes, np.int32)
+        if places is not None:
+            self._keep = places
+            ids = (VP * n)(*[_ptr(pl[0]) for pl in places])
+            sl = (VP * n)(*[_ptr(pl[1]) for pl in places])
+            pn = np.array([int(pl[0].numel()) for pl in places], np.int32)
+            pn_ptr = pn.ctypes.data
+            self._pn = pn
+        else:
+            ids = sl = None
+            pn_ptr = None
+        self.ctx.check(lib().gc_graph_capture(ctx.h, n, B, P, M.ctypes.data, ctypes.byref(prm), _ptr(nodes), _ptr(acc),
+                                              1 if pre_reset else 0, ids, sl, pn_ptr, _stream(stream),
+                                              ctypes.byref(self.h)), "gc_graph_capture")
+
+    def launch(self, stream=None):
+        self.ctx.check(lib().gc_graph_launch(self.h, _stream(stream)), "gc_graph_launch")
+
+    def destroy(self):
+        if self.h:
+            lib().gc_graph_destroy(self.h)
+            self.h = VP()
+
+
+def grav_params(order: int = 2, G: float = 1.0, eps: float = 0.01, schedule: int = 0, tile: int = 0,
+                waves_per_block: int = 0, grid_blocks: int = 0) -> ForceParams:
+    p = ForceParams()
+    p.kind = FORCE_GRAV_QUAD if order == 2 else FORCE_GRAV_MONO
+    p.G, p.soft_eps = G, eps
+    p.schedule, p.tile, p.waves_per_block, p.grid_blocks = schedule, tile, waves_per_block, grid_blocks
+    return p
+
+
+def lj_params(eps_t, sig_t, mass_t, r_cut: float, schedule: int = 0, grid_blocks: int = 0) -> ForceParams:
+    """eps_t, sig_t, mass_t: device float32 tensors (kept alive by the caller)."""
+    p = ForceParams()
+    p.kind = FORCE_LJ
+    p.n_types = int(eps_t.numel())
+    p.eps_t, p.sig_t, p.mass_t = _ptr(eps_t), _ptr(sig_t), _ptr(mass_t)
+    p.r_cut = r_cut
+    p.schedule, p.grid_blocks = schedule, grid_blocks
+    return p

@@ -1,0 +1,122 @@
+// Internal declarations shared by the host runtime and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gcharm.h"
+
+namespace gc {
+
+constexpr int kWave = 64;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;                          // ids per thread in the scan kernels
+constexpr int kScanBlock = kScanThreads * kScanItems;   // ids per scan block
+constexpr int kNodeTile = 64;                           // node records per wavefront tile
+constexpr int kMaxTile = 1024;                          // direct records per wavefront tile (upper bound)
+constexpr int kSortMax = 8192;                          // longest per-task list sorted in LDS
+
+// Algorithmic work per interaction, counting add/sub/mul = 1, fma = 2, rsqrt = 1, from the
+// implemented formulas: pair or monopole 3 sub + 3 fma + rsqrt + 3 mul + 3 fma = 19;
+// quadrupole (monopole included) 51; Lennard-Jones in-cutoff pair 26 (both atoms updated).
+constexpr int kFlopsPair = 19;
+constexpr int kFlopsQuad = 51;
+constexpr int kFlopsLJ = 26;
+
+// ---------------------------------------------------------------- device argument blocks
+
+struct GravArgs {
+  const gc_task* tasks;
+  int32_t n_tasks;
+  const int2* ranges;      // direct ranges in the address space of `rec`
+  const int32_t* ibeg;     // per task: first target position in `rec` (nullptr: task.i_begin)
+  const int32_t* ioff;     // LISTS: per task offset into ilist
+  const int32_t* joff;     // LISTS: per task offset into jlist (n_tasks + 1)
+  const int32_t* ilist;
+  const int32_t* jlist;
+  const int32_t* node_idx;
+  const float4* nodes;     // 3 float4 per node
+  const float4* rec;       // records (packed, pool or source)
+  float4* acc;             // output, by target id
+  float G, eps2;
+  int32_t tile;            // direct records per wavefront tile (multiple of 64)
+  int32_t* queue;          // persistent schedule: work counter
+  const int32_t* order;    // persistent schedule: task order
+};
+
+struct LJArgs {
+  const gc_task* tasks;
+  int32_t n_tasks;
+  const int2* ranges;      // one range per task (j cell), address space of `rec`
+  const int2* ranges_id;   // the same ranges in id space (atomic targets)
+  const int32_t* ibeg;     // per task first i position (nullptr: task.i_begin)
+  const float4* rec;
+  float4* acc;             // force accumulators by id (F / m applied by a finishing kernel)
+  const float* eps_t;
+  const float* sig_t;
+  int32_t n_types;
+  float rc2;
+  int32_t* queue;
+  const int32_t* order;
+};
+
+// ---------------------------------------------------------------- launchers (device code)
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+hipError_t launch_mark(const int2* mark, int32_t n_mark, uint8_t* need, hipStream_t s);
+// scan over flags of ids [0, n): mode 0 = union only, 1 = union + missing (slot_of < 0)
+hipError_t launch_union_scan(const uint8_t* need, const int32_t* slot_of, int32_t n, int32_t with_missing,
+                             int32_t* bsum, int32_t* pos, int32_t* U, int32_t* missing, int32_t* counts,
+                             hipStream_t s);
+hipError_t launch_free_scan(const int32_t* occ, int32_t cap, const int32_t* counts, int32_t* bsum,
+                            int32_t* free_list, int32_t* free_count, hipStream_t s);
+hipError_t launch_stage(const int32_t* missing, const int32_t* free_list, int32_t* counts,
+                        int32_t bound, const float4* src, float4* pool, int32_t* slot_of, int32_t* occ,
+                        hipStream_t s);
+hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, float4* pool,
+                        int32_t* slot_of, int32_t* occ, hipStream_t s);
+hipError_t launch_gather(const int32_t* U, const int32_t* counts, int32_t bound, const int32_t* slot_of,
+                         const float4* pool, float4* packed, hipStream_t s);
+hipError_t launch_gather_src(const int32_t* U, const int32_t* counts, int32_t bound, const float4* src,
+                             float4* packed, hipStream_t s);
+hipError_t launch_remap_ranges(const int2* ranges, int32_t n_ranges, const gc_task* tasks, int32_t n_tasks,
+                               const int32_t* pos, int2* pranges, int32_t* pibeg, hipStream_t s);
+hipError_t launch_remap_lists(const gc_task* tasks, int32_t n_tasks, const int2* ranges, const int32_t* ioff,
+                              const int32_t* joff, const int32_t* slot_of, int32_t* ilist, int32_t* jlist,
+                              int32_t sorted, hipStream_t s);
+hipError_t launch_grav(int order, bool lists, bool persistent, const GravArgs& a, int waves_per_block,
+                       int grid_blocks, hipStream_t s);
+hipError_t grav_occupancy(int order, bool lists, bool persistent, int tile, int waves_per_block, int* blocks);
+hipError_t launch_lj(bool persistent, const LJArgs& a, int waves_per_block, int grid_blocks, hipStream_t s);
+hipError_t launch_lj_finish(float4* acc, const float* mass_t, const float4* rec_by_id, int32_t n,
+                            hipStream_t s);
+
+struct GravAdjArgs {
+  GravArgs f;              // forward arguments (lists, records, nodes)
+  const float4* cot;       // by id
+  float4* gpos;            // by id
+  float* gmass;            // by id
+  const int32_t* src_id;   // position in rec -> id (PACK: U; LISTS: slot -> id map; nullptr: identity)
+  float* gnode;            // per node: dL/dcom (3) and dL/dM, 4 floats
+};
+hipError_t launch_grav_adjoint(bool lists, const GravAdjArgs& a, int waves_per_block, hipStream_t s);
+hipError_t launch_node_chain(const int32_t* node_range, int32_t n_nodes, const float4* nodes, const float* gnode,
+                             const float4* rec_by_id, float4* gpos, float* gmass, hipStream_t s);
+struct LJAdjArgs {
+  LJArgs f;
+  const float4* cot;       // by id
+  const float* mass_t;
+  float4* gpos;
+  float* gparam;           // 2 * n_types
+  float4* force;           // forward forces by id (for the mass gradient)
+};
+hipError_t launch_lj_adjoint(const LJAdjArgs& a, int waves_per_block, hipStream_t s);
+hipError_t launch_lj_mass_grad(const float4* cot, const float4* force, const float* mass_t,
+                               const float4* rec_by_id, float* gmass, int32_t n, hipStream_t s);
+hipError_t launch_slot_to_id(const int32_t* slot_of, int32_t n_ids, int32_t* id_of_slot, hipStream_t s);
+
+}  // namespace gc

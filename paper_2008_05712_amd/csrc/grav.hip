@@ -1,0 +1,307 @@
+// Combined Barnes-Hut force kernel (Sec. 3.1: many work requests in one launch;
+// Sec. 4.1: a bucket's particles share one list of nodes and direct particles).
+//
+// Schedule: one wavefront per task.  A bucket holds few targets (about 10 on
+// average for a Plummer sphere with buckets of 32), so the 64 lanes are split
+// as (target i) x (source slice s): S = floor(64 / i_count) slices, lane
+// = s * i_count + i.  Source records (direct particles, or node records) are
+// staged by the wavefront into its private LDS tile with coalesced loads; the
+// tile is padded with zero-mass entries to S * C records so every slice runs
+// exactly C iterations with no per-iteration bounds test; a lane reads its
+// slice's records from LDS (lanes of one slice read the same address: an LDS
+// broadcast).  Per tile each lane sums its slice in FP32 and adds the tile's
+// partial to an FP64 running sum; at the end the slices of each target are
+// reduced in FP64 through LDS and the target's float4 is written once.  No
+// atomics: results are bitwise independent of task order and schedule.
+//
+// The inner loops are plain FP32 VALU code (v_sub / v_fma / v_mul) with the
+// hardware reciprocal square root; pairwise forces are not a dense
+// contraction, so no MFMA.
+#include "gc_internal.h"
+
+namespace gc {
+namespace {
+
+__device__ __forceinline__ void wave_sync() {
+  // Lanes of one wavefront exchange data through wavefront-private LDS; the
+  // LDS unit executes a wavefront's instructions in order, so only compiler
+  // reordering must be prevented here.
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int wave_excl_scan(int v, int* total) {
+  const int lane = threadIdx.x & 63;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int u = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += u;
+  }
+  *total = __shfl(inc, 63, 64);
+  return inc - v;
+}
+
+// Sum over a tile of C pair/monopole records per slice: p = records of this lane's slice.
+__device__ __forceinline__ void tile_pairs(const float4* __restrict__ p, int C, float xi, float yi, float zi,
+                                           float eps2, float& ax, float& ay, float& az) {
+  int k = 0;
+  for (; k + 4 <= C; k += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      float4 j = p[k + u];
+      float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
+      float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+      float ri = __builtin_amdgcn_rsqf(r2);
+      float mr = j.w * ri;
+      float ri2 = ri * ri;
+      float sc = mr * ri2;
+      ax = __builtin_fmaf(dx, sc, ax);
+      ay = __builtin_fmaf(dy, sc, ay);
+      az = __builtin_fmaf(dz, sc, az);
+    }
+  }
+  for (; k < C; ++k) {
+    float4 j = p[k];
+    float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
+    float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+    float ri = __builtin_amdgcn_rsqf(r2);
+    float mr = j.w * ri;
+    float ri2 = ri * ri;
+    float sc = mr * ri2;
+    ax = __builtin_fmaf(dx, sc, ax);
+    ay = __builtin_fmaf(dy, sc, ay);
+    az = __builtin_fmaf(dz, sc, az);
+  }
+}
+
+// Quadrupole node records in LDS: (com, M), (3Sxx, 3Syy, 3Szz, 3Sxy), (3Sxz, 3Syz, 1.5 T, 0).
+__device__ __forceinline__ void tile_quads(const float4* __restrict__ p, int C, float xi, float yi, float zi,
+                                           float eps2, float& ax, float& ay, float& az) {
+#pragma unroll 2
+  for (int k = 0; k < C; ++k) {
+    float4 a = p[3 * k], b = p[3 * k + 1], c = p[3 * k + 2];
+    float dx = xi - a.x, dy = yi - a.y, dz = zi - a.z;
+    float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+    float ri = __builtin_amdgcn_rsqf(r2);
+    float q = ri * ri;
+    float r3 = ri * q;
+    float r5 = r3 * q;
+    // S' d with S' = 3 S
+    float sx = __builtin_fmaf(c.x, dz, __builtin_fmaf(b.w, dy, b.x * dx));
+    float sy = __builtin_fmaf(c.y, dz, __builtin_fmaf(b.y, dy, b.w * dx));
+    float sz = __builtin_fmaf(b.z, dz, __builtin_fmaf(c.y, dy, c.x * dx));
+    float dsd = __builtin_fmaf(dz, sz, __builtin_fmaf(dy, sy, dx * sx));  // 3 d.S.d
+    // coefficient of d: -M r^-3 + 1.5 T r^-5 - 7.5 (d.S.d) r^-7 = r^-3 (-M + q (1.5 T - 2.5 q dsd))
+    float u = __builtin_fmaf(dsd, q * -2.5f, c.z);
+    float v = __builtin_fmaf(q, u, -a.w);
+    float cf = r3 * v;
+    ax = __builtin_fmaf(r5, sx, __builtin_fmaf(cf, dx, ax));
+    ay = __builtin_fmaf(r5, sy, __builtin_fmaf(cf, dy, ay));
+    az = __builtin_fmaf(r5, sz, __builtin_fmaf(cf, dz, az));
+  }
+}
+
+template <int ORDER, bool LISTS, bool PERSIST>
+__global__ void __launch_bounds__(512) k_grav(GravArgs a) {
+  extern __shared__ float4 smem[];
+  const int lane = threadIdx.x & 63;
+  const int wid = uniform(threadIdx.x >> 6);
+  const int wpb = blockDim.x >> 6;
+  // per-wavefront LDS: max(tile + 64, 3 * (kNodeTile + 64)) float4 + 64 x 3 doubles reduction
+  const int tile = a.tile;
+  const int rec_cap = (tile + 64 > 3 * (kNodeTile + 64)) ? tile + 64 : 3 * (kNodeTile + 64);
+  const int per_wave = rec_cap + 96;
+  float4* L = smem + wid * per_wave;
+  double* red = reinterpret_cast<double*>(L + rec_cap);
+
+  int iter = 0;
+  while (true) {
+    int t;
+    if (PERSIST) {
+      int got = 0;
+      if (lane == 0) got = atomicAdd(a.queue, 1);
+      got = uniform(__shfl(got, 0, 64));
+      if (got >= a.n_tasks) break;
+      t = uniform(a.order[got]);
+    } else {
+      if (iter++) break;
+      t = uniform(blockIdx.x * wpb + wid);
+      if (t >= a.n_tasks) break;
+    }
+    const gc_task tk = a.tasks[t];
+    const int ic = tk.i_count;
+    for (int i0 = 0; i0 < ic; i0 += 64) {
+      const int icc = ic - i0 < 64 ? ic - i0 : 64;
+      const int S = 64 / icc;
+      const int il = lane % icc;
+      const int sl = lane / icc;
+      const bool active = sl < S;
+      float xi = 0.f, yi = 0.f, zi = 0.f;
+      if (active) {
+        int p;
+        if (LISTS) p = a.ilist[a.ioff[t] + i0 + il];
+        else p = (a.ibeg ? a.ibeg[t] : tk.i_begin) + i0 + il;
+        float4 r = a.rec[p];
+        xi = r.x; yi = r.y; zi = r.z;
+      }
+      double Ax = 0.0, Ay = 0.0, Az = 0.0;
+
+      // ---- node terms
+      for (int nb = 0; nb < tk.n_count; nb += kNodeTile) {
+        const int cnt = tk.n_count - nb < kNodeTile ? tk.n_count - nb : kNodeTile;
+        const int C = (cnt + S - 1) / S;
+        const int padded = S * C;
+        for (int e = lane; e < padded; e += 64) {
+          if (ORDER == 1) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (e < cnt) v = a.nodes[3 * a.node_idx[tk.n_first + nb + e]];
+            L[e] = v;
+          } else {
+            float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0, v2 = v0;
+            if (e < cnt) {
+              const float4* nd = a.nodes + 3 * a.node_idx[tk.n_first + nb + e];
+              v0 = nd[0];
+              v1 = nd[1];
+              v2 = nd[2];
+              v1 = make_float4(3.f * v1.x, 3.f * v1.y, 3.f * v1.z, 3.f * v1.w);
+              v2 = make_float4(3.f * v2.x, 3.f * v2.y, 1.5f * v2.z, 0.f);
+            }
+            L[3 * e] = v0;
+            L[3 * e + 1] = v1;
+            L[3 * e + 2] = v2;
+          }
+        }
+        wave_sync();
+        if (active) {
+          float ax = 0.f, ay = 0.f, az = 0.f;
+          if (ORDER == 1) {
+            // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
+            tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
+          } else {
+            tile_quads(L + 3 * sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
+          }
+          Ax += ax; Ay += ay; Az += az;
+        }
+        wave_sync();
+      }
+
+      // ---- direct terms
+      if (LISTS) {
+        const int jb = a.joff[t], jn = a.joff[t + 1] - jb;
+        for (int ws = 0; ws < jn; ws += tile) {
+          const int cnt = jn - ws < tile ? jn - ws : tile;
+          const int C = (cnt + S - 1) / S;
+          const int padded = S * C;
+          for (int e = lane; e < padded; e += 64) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (e < cnt) v = a.rec[a.jlist[jb + ws + e]];
+            L[e] = v;
+          }
+          wave_sync();
+          if (active) {
+            float ax = 0.f, ay = 0.f, az = 0.f;
+            tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
+            Ax += ax; Ay += ay; Az += az;
+          }
+          wave_sync();
+        }
+      } else {
+        for (int rg = 0; rg < tk.j_nranges; rg += 64) {
+          const int nr = tk.j_nranges - rg < 64 ? tk.j_nranges - rg : 64;
+          int2 g = make_int2(0, 0);
+          if (lane < nr) g = a.ranges[tk.j_first + rg + lane];
+          int total;
+          const int o = wave_excl_scan(g.y, &total);
+          total = uniform(total);
+          for (int ws = 0; ws < total; ws += tile) {
+            const int cnt = total - ws < tile ? total - ws : tile;
+            const int C = (cnt + S - 1) / S;
+            const int padded = S * C;
+            // each lane copies the part of its range inside the window [ws, ws + cnt)
+            int k0 = ws - o > 0 ? ws - o : 0;
+            int k1 = ws + cnt - o < g.y ? ws + cnt - o : g.y;
+            for (int k = k0; k < k1; ++k) L[o + k - ws] = a.rec[g.x + k];
+            for (int e = cnt + lane; e < padded; e += 64) L[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+            wave_sync();
+            if (active) {
+              float ax = 0.f, ay = 0.f, az = 0.f;
+              tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
+              Ax += ax; Ay += ay; Az += az;
+            }
+            wave_sync();
+          }
+        }
+      }
+
+      // ---- reduce the S slices of each target, write once
+      red[3 * lane] = Ax;
+      red[3 * lane + 1] = Ay;
+      red[3 * lane + 2] = Az;
+      wave_sync();
+      if (lane < icc) {
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int s = 0; s < S; ++s) {
+          const double* q = red + 3 * (s * icc + lane);
+          sx += q[0]; sy += q[1]; sz += q[2];
+        }
+        a.acc[tk.i_begin + i0 + lane] =
+            make_float4((float)(a.G * sx), (float)(a.G * sy), (float)(a.G * sz), 0.f);
+      }
+      wave_sync();
+    }
+  }
+}
+
+template <int ORDER, bool LISTS, bool PERSIST>
+hipError_t launch_one(const GravArgs& a, int wpb, int grid, hipStream_t s) {
+  const int rec_cap = (a.tile + 64 > 3 * (kNodeTile + 64)) ? a.tile + 64 : 3 * (kNodeTile + 64);
+  size_t lds = (size_t)wpb * (rec_cap + 96) * sizeof(float4);
+  if (!PERSIST) grid = (a.n_tasks + wpb - 1) / wpb;
+  if (grid < 1) return hipSuccess;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_grav<ORDER, LISTS, PERSIST>), dim3(grid), dim3(64 * wpb), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int ORDER, bool LISTS, bool PERSIST>
+hipError_t occ_one(int tile, int wpb, int* blocks) {
+  const int rec_cap = (tile + 64 > 3 * (kNodeTile + 64)) ? tile + 64 : 3 * (kNodeTile + 64);
+  size_t lds = (size_t)wpb * (rec_cap + 96) * sizeof(float4);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_grav<ORDER, LISTS, PERSIST>, 64 * wpb, lds);
+}
+
+}  // namespace
+
+hipError_t launch_grav(int order, bool lists, bool persistent, const GravArgs& a, int wpb, int grid,
+                       hipStream_t s) {
+  if (a.n_tasks <= 0) return hipSuccess;
+  if (order == 1) {
+    if (lists) return persistent ? launch_one<1, true, true>(a, wpb, grid, s) : launch_one<1, true, false>(a, wpb, grid, s);
+    return persistent ? launch_one<1, false, true>(a, wpb, grid, s) : launch_one<1, false, false>(a, wpb, grid, s);
+  }
+  if (lists) return persistent ? launch_one<2, true, true>(a, wpb, grid, s) : launch_one<2, true, false>(a, wpb, grid, s);
+  return persistent ? launch_one<2, false, true>(a, wpb, grid, s) : launch_one<2, false, false>(a, wpb, grid, s);
+}
+
+hipError_t grav_occupancy(int order, bool lists, bool persistent, int tile, int wpb, int* blocks) {
+  if (order == 1) {
+    if (lists) return persistent ? occ_one<1, true, true>(tile, wpb, blocks) : occ_one<1, true, false>(tile, wpb, blocks);
+    return persistent ? occ_one<1, false, true>(tile, wpb, blocks) : occ_one<1, false, false>(tile, wpb, blocks);
+  }
+  if (lists) return persistent ? occ_one<2, true, true>(tile, wpb, blocks) : occ_one<2, true, false>(tile, wpb, blocks);
+  return persistent ? occ_one<2, false, true>(tile, wpb, blocks) : occ_one<2, false, false>(tile, wpb, blocks);
+}
+
+}  // namespace gc

@@ -1,0 +1,835 @@
+// Host runtime behind the C ABI in gcharm.h: contexts, the device pool and its
+// chare table, batches (combined work requests), the reorganisation pipeline,
+// the combined launches, HIP graph capture and the autotuner.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "gc_internal.h"
+
+using namespace gc;
+
+struct gc_ctx_ {
+  int device = 0;
+  int n_cu = 0;
+  bool poisoned = false;
+  std::string err;
+};
+
+namespace {
+
+gc_status set_err(gc_ctx c, gc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+gc_status hip_fail(gc_ctx c, hipError_t e, const char* what) {
+  if (c) c->poisoned = true;
+  return set_err(c, GC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define GC_HIP(ctx, call)                                   \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+  } while (0)
+
+#define GC_ENTER(ctx)                                                                   \
+  do {                                                                                  \
+    if (!(ctx)) return GC_E_INVAL;                                                      \
+    if ((ctx)->poisoned) return set_err((ctx), GC_E_STATE, "context poisoned by an earlier device error"); \
+    (ctx)->err.clear();                                                                 \
+  } while (0)
+
+inline int64_t pad_to(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
+
+// Device buffer that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes && p) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    size_t b = want < 256 ? 256 : want;
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+struct gc_pool_ {
+  gc_ctx ctx = nullptr;
+  int32_t n_ids = 0, cap = 0;
+  DevBuf rec, slot_of, occ;
+  const float4* src = nullptr;
+  bool src_device = false;
+};
+
+struct gc_batch_ {
+  gc_ctx ctx = nullptr;
+  int32_t kind = GC_KIND_GRAV;
+  int32_t n_ids = 0;
+  std::vector<gc_task> tasks;
+  std::vector<int32_t> ranges;   // pairs
+  std::vector<int32_t> nodes;
+  int64_t n_direct = 0, n_targets = 0;
+  bool committed = false;
+  // committed device copies
+  DevBuf d_tasks, d_ranges, d_nodes, d_mark, d_ioff, d_joff, d_order;
+  int32_t n_mark = 0, bound_u = 0, max_direct = 0;
+  // reorganisation buffers
+  DevBuf need, pos, U, missing, free_list, bsum, counts, packed, pranges, pibeg, ilist, jlist, queue;
+  // state of the last reorganisation
+  int32_t mode = -1;
+  gc_pool pool = nullptr;
+  const float4* rec = nullptr;
+};
+
+struct gc_graph_ {
+  gc_ctx ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+// ===================================================================== context
+
+extern "C" const char* gc_version(void) { return "gcharm-mi355x 0.1 (gfx950)"; }
+
+extern "C" gc_status gc_init(int device, gc_ctx* out) {
+  if (!out) return GC_E_INVAL;
+  *out = nullptr;
+  gc_ctx c = new gc_ctx_();
+  c->device = device;
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    delete c;
+    return GC_E_HIP;
+  }
+  hipDeviceProp_t p;
+  e = hipGetDeviceProperties(&p, device);
+  if (e != hipSuccess) {
+    delete c;
+    return GC_E_HIP;
+  }
+  c->n_cu = p.multiProcessorCount;
+  *out = c;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_finalize(gc_ctx ctx) {
+  if (!ctx) return GC_E_INVAL;
+  delete ctx;
+  return GC_OK;
+}
+
+extern "C" const char* gc_last_error(gc_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" gc_status gc_zero_f32(gc_ctx ctx, float* dev, int64_t n, void* stream) {
+  GC_ENTER(ctx);
+  if (n < 0 || (n > 0 && !dev)) return set_err(ctx, GC_E_INVAL, "gc_zero_f32: bad buffer");
+  GC_HIP(ctx, launch_fill_f32(dev, 0.f, n, S(stream)));
+  return GC_OK;
+}
+
+// ===================================================================== pool
+
+extern "C" gc_status gc_pool_create(gc_ctx ctx, int32_t n_ids, int32_t capacity, gc_pool* out) {
+  GC_ENTER(ctx);
+  if (!out || n_ids <= 0 || capacity <= 0) return set_err(ctx, GC_E_INVAL, "gc_pool_create: n_ids and capacity must be > 0");
+  gc_pool p = new gc_pool_();
+  p->ctx = ctx;
+  p->n_ids = n_ids;
+  p->cap = capacity;
+  hipError_t e = p->rec.ensure(sizeof(float4) * (size_t)capacity);
+  if (e == hipSuccess) e = p->slot_of.ensure(sizeof(int32_t) * (size_t)pad_to(n_ids, kScanBlock));
+  if (e == hipSuccess) e = p->occ.ensure(sizeof(int32_t) * (size_t)pad_to(capacity, kScanBlock));
+  if (e != hipSuccess) {
+    p->rec.release(); p->slot_of.release(); p->occ.release();
+    delete p;
+    return set_err(ctx, GC_E_NOMEM, "gc_pool_create: %s", hipGetErrorString(e));
+  }
+  e = launch_fill_i32(p->slot_of.as<int32_t>(), -1, pad_to(n_ids, kScanBlock), nullptr);
+  if (e == hipSuccess) e = launch_fill_i32(p->occ.as<int32_t>(), 0, pad_to(capacity, kScanBlock), nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    p->rec.release(); p->slot_of.release(); p->occ.release();
+    delete p;
+    return hip_fail(ctx, e, "gc_pool_create");
+  }
+  *out = p;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_pool_destroy(gc_pool pool) {
+  if (!pool) return GC_E_INVAL;
+  (void)hipDeviceSynchronize();
+  pool->rec.release();
+  pool->slot_of.release();
+  pool->occ.release();
+  delete pool;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_pool_set_source(gc_pool pool, const void* records) {
+  if (!pool) return GC_E_INVAL;
+  GC_ENTER(pool->ctx);
+  if (!records) return set_err(pool->ctx, GC_E_INVAL, "gc_pool_set_source: NULL records");
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, records);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(pool->ctx, GC_E_INVAL, "gc_pool_set_source: pointer is neither device memory nor pinned host memory");
+  }
+  pool->src_device = (at.type == hipMemoryTypeDevice);
+  if (at.type == hipMemoryTypeHost) {
+    // pinned host memory: use its device-visible address
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, const_cast<void*>(records), 0) != hipSuccess || !dp) {
+      (void)hipGetLastError();
+      return set_err(pool->ctx, GC_E_INVAL, "gc_pool_set_source: host memory is not device-accessible (use hipHostMalloc)");
+    }
+    pool->src = static_cast<const float4*>(dp);
+  } else if (at.type == hipMemoryTypeDevice) {
+    pool->src = static_cast<const float4*>(records);
+  } else {
+    return set_err(pool->ctx, GC_E_INVAL, "gc_pool_set_source: unsupported memory type");
+  }
+  return GC_OK;
+}
+
+extern "C" gc_status gc_pool_place(gc_pool pool, const int32_t* ids_dev, const int32_t* slots_dev, int32_t n,
+                                   void* stream) {
+  if (!pool) return GC_E_INVAL;
+  GC_ENTER(pool->ctx);
+  if (n < 0 || (n > 0 && (!ids_dev || !slots_dev))) return set_err(pool->ctx, GC_E_INVAL, "gc_pool_place: bad arrays");
+  if (n > 0 && !pool->src) return set_err(pool->ctx, GC_E_STATE, "gc_pool_place: no source set");
+  GC_HIP(pool->ctx, launch_place(ids_dev, slots_dev, n, pool->src, pool->rec.as<float4>(), pool->slot_of.as<int32_t>(),
+                                 pool->occ.as<int32_t>(), S(stream)));
+  return GC_OK;
+}
+
+static hipError_t pool_reset_async(gc_pool pool, hipStream_t s) {
+  hipError_t e = launch_fill_i32(pool->slot_of.as<int32_t>(), -1, pool->n_ids, s);
+  if (e == hipSuccess) e = launch_fill_i32(pool->occ.as<int32_t>(), 0, pool->cap, s);
+  return e;
+}
+
+extern "C" gc_status gc_pool_reset(gc_pool pool, void* stream) {
+  if (!pool) return GC_E_INVAL;
+  GC_ENTER(pool->ctx);
+  GC_HIP(pool->ctx, pool_reset_async(pool, S(stream)));
+  return GC_OK;
+}
+
+extern "C" gc_status gc_pool_query(gc_pool pool, int32_t* slot_of_host, void* stream) {
+  if (!pool) return GC_E_INVAL;
+  GC_ENTER(pool->ctx);
+  if (!slot_of_host) return set_err(pool->ctx, GC_E_INVAL, "gc_pool_query: NULL output");
+  GC_HIP(pool->ctx, hipMemcpyAsync(slot_of_host, pool->slot_of.p, sizeof(int32_t) * (size_t)pool->n_ids,
+                                   hipMemcpyDeviceToHost, S(stream)));
+  GC_HIP(pool->ctx, hipStreamSynchronize(S(stream)));
+  return GC_OK;
+}
+
+extern "C" gc_status gc_pool_device_ptrs(gc_pool pool, void** records, int32_t** slot_of) {
+  if (!pool) return GC_E_INVAL;
+  if (records) *records = pool->rec.p;
+  if (slot_of) *slot_of = pool->slot_of.as<int32_t>();
+  return GC_OK;
+}
+
+// ===================================================================== batch
+
+extern "C" gc_status gc_batch_create(gc_ctx ctx, int32_t kind, int32_t n_ids, gc_batch* out) {
+  GC_ENTER(ctx);
+  if (!out || n_ids <= 0 || (kind != GC_KIND_GRAV && kind != GC_KIND_LJ))
+    return set_err(ctx, GC_E_INVAL, "gc_batch_create: bad kind or n_ids");
+  gc_batch b = new gc_batch_();
+  b->ctx = ctx;
+  b->kind = kind;
+  b->n_ids = n_ids;
+  *out = b;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_batch_destroy(gc_batch b) {
+  if (!b) return GC_E_INVAL;
+  (void)hipDeviceSynchronize();
+  for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_mark, &b->d_ioff, &b->d_joff, &b->d_order, &b->need,
+                    &b->pos, &b->U, &b->missing, &b->free_list, &b->bsum, &b->counts, &b->packed, &b->pranges,
+                    &b->pibeg, &b->ilist, &b->jlist, &b->queue})
+    d->release();
+  delete b;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_batch_reset(gc_batch b) {
+  if (!b) return GC_E_INVAL;
+  GC_ENTER(b->ctx);
+  b->tasks.clear();
+  b->ranges.clear();
+  b->nodes.clear();
+  b->n_direct = b->n_targets = 0;
+  b->committed = false;
+  b->mode = -1;
+  b->pool = nullptr;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_submit_tasks(gc_batch b, const gc_task* tasks, int32_t n_tasks, const int32_t* j_ranges,
+                                     int32_t n_ranges, const int32_t* node_idx, int32_t n_node_refs) {
+  if (!b) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  if (n_tasks < 0 || n_ranges < 0 || n_node_refs < 0) return set_err(c, GC_E_INVAL, "gc_submit_tasks: negative count");
+  if ((n_tasks && !tasks) || (n_ranges && !j_ranges) || (n_node_refs && !node_idx))
+    return set_err(c, GC_E_INVAL, "gc_submit_tasks: NULL array with nonzero count");
+  int64_t add_direct = 0, add_targets = 0;
+  for (int32_t r = 0; r < n_ranges; ++r) {
+    int64_t s = j_ranges[2 * r], n = j_ranges[2 * r + 1];
+    if (s < 0 || n < 0 || s + n > b->n_ids)
+      return set_err(c, GC_E_INVAL, "gc_submit_tasks: range %d (%lld, %lld) outside [0, %d)", r, (long long)s,
+                     (long long)n, b->n_ids);
+  }
+  for (int32_t k = 0; k < n_node_refs; ++k)
+    if (node_idx[k] < 0) return set_err(c, GC_E_INVAL, "gc_submit_tasks: negative node index at %d", k);
+  for (int32_t t = 0; t < n_tasks; ++t) {
+    const gc_task& tk = tasks[t];
+    if (tk.i_count < 0 || tk.i_begin < 0 || (int64_t)tk.i_begin + tk.i_count > b->n_ids)
+      return set_err(c, GC_E_INVAL, "gc_submit_tasks: task %d targets outside [0, %d)", t, b->n_ids);
+    if (tk.j_nranges < 0 || tk.j_first < 0 || (int64_t)tk.j_first + tk.j_nranges > n_ranges)
+      return set_err(c, GC_E_INVAL, "gc_submit_tasks: task %d range slice outside the given ranges", t);
+    if (tk.n_count < 0 || tk.n_first < 0 || (int64_t)tk.n_first + tk.n_count > n_node_refs)
+      return set_err(c, GC_E_INVAL, "gc_submit_tasks: task %d node slice outside the given node refs", t);
+    if (b->kind == GC_KIND_LJ && (tk.j_nranges != 1 || tk.n_count != 0))
+      return set_err(c, GC_E_INVAL, "gc_submit_tasks: Lennard-Jones task %d needs exactly one j range and no nodes", t);
+    if (b->kind == GC_KIND_GRAV && (tk.flags != 0 || tk.shift[0] != 0.f || tk.shift[1] != 0.f || tk.shift[2] != 0.f))
+      return set_err(c, GC_E_INVAL, "gc_submit_tasks: gravity task %d has flags or a shift", t);
+    if (b->kind == GC_KIND_LJ && (tk.flags & GC_TASK_SELF)) {
+      const int32_t* g = j_ranges + 2 * tk.j_first;
+      if (g[0] != tk.i_begin || g[1] != tk.i_count)
+        return set_err(c, GC_E_INVAL, "gc_submit_tasks: self task %d must use its target range as j range", t);
+    }
+    for (int32_t r = 0; r < tk.j_nranges; ++r) add_direct += j_ranges[2 * (tk.j_first + r) + 1];
+    add_targets += tk.i_count;
+  }
+  if (b->n_direct + add_direct > INT32_MAX || b->n_targets + add_targets > INT32_MAX ||
+      (int64_t)b->tasks.size() + n_tasks > INT32_MAX || (int64_t)b->ranges.size() / 2 + n_ranges > INT32_MAX)
+    return set_err(c, GC_E_INVAL, "gc_submit_tasks: batch exceeds 2^31 entries");
+  const int32_t r0 = (int32_t)(b->ranges.size() / 2), n0 = (int32_t)b->nodes.size();
+  for (int32_t t = 0; t < n_tasks; ++t) {
+    gc_task tk = tasks[t];
+    tk.j_first += r0;
+    tk.n_first += n0;
+    b->tasks.push_back(tk);
+  }
+  b->ranges.insert(b->ranges.end(), j_ranges, j_ranges + 2 * (size_t)n_ranges);
+  b->nodes.insert(b->nodes.end(), node_idx, node_idx + n_node_refs);
+  b->n_direct += add_direct;
+  b->n_targets += add_targets;
+  b->committed = false;
+  b->mode = -1;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_batch_sizes(gc_batch b, int64_t* out5) {
+  if (!b || !out5) return GC_E_INVAL;
+  out5[0] = (int64_t)b->tasks.size();
+  out5[1] = (int64_t)b->ranges.size() / 2;
+  out5[2] = (int64_t)b->nodes.size();
+  out5[3] = b->n_direct;
+  out5[4] = b->n_targets;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
+  if (!b) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  if (b->committed) return GC_OK;
+  const int32_t T = (int32_t)b->tasks.size();
+  const int32_t R = (int32_t)(b->ranges.size() / 2);
+  // targets written by at most one gravity task
+  if (b->kind == GC_KIND_GRAV) {
+    std::vector<uint8_t> hit((size_t)b->n_ids, 0);
+    for (int32_t t = 0; t < T; ++t)
+      for (int32_t i = b->tasks[t].i_begin; i < b->tasks[t].i_begin + b->tasks[t].i_count; ++i) {
+        if (hit[i]) return set_err(c, GC_E_INVAL, "gc_batch_commit: id %d is the target of two gravity tasks", i);
+        hit[i] = 1;
+      }
+  }
+  std::vector<int32_t> ioff(T > 0 ? T : 1), joff((size_t)T + 1, 0);
+  int64_t io = 0;
+  int32_t maxd = 0;
+  std::vector<int64_t> cost(T);
+  for (int32_t t = 0; t < T; ++t) {
+    const gc_task& tk = b->tasks[t];
+    ioff[t] = (int32_t)io;
+    io += tk.i_count;
+    int64_t d = 0;
+    for (int32_t r = 0; r < tk.j_nranges; ++r) d += b->ranges[2 * (tk.j_first + r) + 1];
+    joff[t + 1] = joff[t] + (int32_t)d;
+    maxd = std::max<int32_t>(maxd, (int32_t)d);
+    cost[t] = (int64_t)tk.i_count * (b->kind == GC_KIND_GRAV ? (31 * (int64_t)tk.n_count + 12 * d) : d);
+  }
+  b->max_direct = maxd;
+  // marks: distinct non-empty ranges over targets and direct lists
+  std::vector<std::pair<int32_t, int32_t>> mk;
+  mk.reserve((size_t)T + R);
+  for (int32_t t = 0; t < T; ++t)
+    if (b->tasks[t].i_count > 0) mk.emplace_back(b->tasks[t].i_begin, b->tasks[t].i_count);
+  for (int32_t r = 0; r < R; ++r)
+    if (b->ranges[2 * r + 1] > 0) mk.emplace_back(b->ranges[2 * r], b->ranges[2 * r + 1]);
+  std::sort(mk.begin(), mk.end());
+  mk.erase(std::unique(mk.begin(), mk.end()), mk.end());
+  int64_t marked = 0;
+  for (auto& m : mk) marked += m.second;
+  b->n_mark = (int32_t)mk.size();
+  b->bound_u = (int32_t)std::min<int64_t>(b->n_ids, marked);
+  // longest-processing-time-first order for the persistent schedule
+  std::vector<int32_t> order(T > 0 ? T : 1);
+  std::iota(order.begin(), order.begin() + T, 0);
+  std::stable_sort(order.begin(), order.begin() + T, [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+
+  hipStream_t s = S(stream);
+  hipError_t e = hipSuccess;
+  auto up = [&](DevBuf& d, const void* src, size_t bytes) {
+    if (e != hipSuccess) return;
+    e = d.ensure(bytes);
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  up(b->d_tasks, b->tasks.data(), sizeof(gc_task) * (size_t)T);
+  up(b->d_ranges, b->ranges.data(), sizeof(int32_t) * b->ranges.size());
+  up(b->d_nodes, b->nodes.data(), sizeof(int32_t) * b->nodes.size());
+  up(b->d_mark, mk.data(), sizeof(int32_t) * 2 * mk.size());
+  up(b->d_ioff, ioff.data(), sizeof(int32_t) * ioff.size());
+  up(b->d_joff, joff.data(), sizeof(int32_t) * joff.size());
+  up(b->d_order, order.data(), sizeof(int32_t) * order.size());
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors must outlive the copies
+  if (e != hipSuccess) return hip_fail(c, e, "gc_batch_commit");
+  b->committed = true;
+  b->mode = -1;
+  return GC_OK;
+}
+
+static hipError_t ensure_reorg_buffers(gc_batch b, gc_pool p) {
+  const int64_t nid = pad_to(b->n_ids, kScanBlock);
+  const int64_t bound = std::max<int32_t>(b->bound_u, 1);
+  const int64_t nb = std::max<int64_t>(pad_to(b->n_ids, kScanBlock), pad_to(p->cap, kScanBlock)) / kScanBlock;
+  hipError_t e = b->need.ensure((size_t)nid);
+  if (e == hipSuccess) e = b->pos.ensure(sizeof(int32_t) * (size_t)nid);
+  if (e == hipSuccess) e = b->U.ensure(sizeof(int32_t) * (size_t)bound);
+  if (e == hipSuccess) e = b->missing.ensure(sizeof(int32_t) * (size_t)bound);
+  if (e == hipSuccess) e = b->free_list.ensure(sizeof(int32_t) * (size_t)bound);
+  if (e == hipSuccess) e = b->bsum.ensure(sizeof(int32_t) * 2 * (size_t)nb);
+  if (e == hipSuccess) e = b->counts.ensure(sizeof(int32_t) * 8);
+  if (e == hipSuccess) e = b->packed.ensure(sizeof(float4) * (size_t)bound);
+  if (e == hipSuccess) e = b->pranges.ensure(sizeof(int32_t) * std::max<size_t>(b->ranges.size(), 2));
+  if (e == hipSuccess) e = b->pibeg.ensure(sizeof(int32_t) * std::max<size_t>(b->tasks.size(), 1));
+  if (e == hipSuccess) e = b->ilist.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(b->n_targets, 1));
+  if (e == hipSuccess) e = b->jlist.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(b->n_direct, 1));
+  if (e == hipSuccess) e = b->queue.ensure(sizeof(int32_t) * 4);
+  return e;
+}
+
+// Phase A: mark, union + position map + missing list, free-slot list.  Nothing in the pool changes.
+static gc_status reorganize_lookup(gc_batch b, gc_pool p, int32_t mode, hipStream_t s, bool* needs_need_clear) {
+  gc_ctx c = b->ctx;
+  size_t need_before = b->need.bytes;
+  hipError_t e = ensure_reorg_buffers(b, p);
+  if (e != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_reorganize: %s", hipGetErrorString(e));
+  if (b->need.bytes != need_before) *needs_need_clear = true;
+  if (*needs_need_clear) GC_HIP(c, launch_fill_i32(b->need.as<int32_t>(), 0, (int64_t)(b->need.bytes / 4), s));
+  int32_t* counts = b->counts.as<int32_t>();
+  GC_HIP(c, launch_fill_i32(counts, 0, 8, s));
+  GC_HIP(c, launch_mark(b->d_mark.as<int2>(), b->n_mark, b->need.as<uint8_t>(), s));
+  const bool reuse = (mode != GC_REORG_REDUNDANT);
+  GC_HIP(c, launch_union_scan(b->need.as<uint8_t>(), p->slot_of.as<int32_t>(), b->n_ids, reuse ? 1 : 0,
+                              b->bsum.as<int32_t>(), b->pos.as<int32_t>(), b->U.as<int32_t>(),
+                              b->missing.as<int32_t>(), counts, s));
+  if (reuse)
+    GC_HIP(c, launch_free_scan(p->occ.as<int32_t>(), p->cap, counts, b->bsum.as<int32_t>(), b->free_list.as<int32_t>(),
+                               counts + 2, s));
+  return GC_OK;
+}
+
+// Phase B: staging of missing records into the pool, then the packing gather or the list remaps.
+static gc_status reorganize_apply(gc_batch b, gc_pool p, int32_t mode, hipStream_t s) {
+  gc_ctx c = b->ctx;
+  const int32_t T = (int32_t)b->tasks.size(), R = (int32_t)(b->ranges.size() / 2);
+  int32_t* counts = b->counts.as<int32_t>();
+  if (mode != GC_REORG_REDUNDANT)
+    GC_HIP(c, launch_stage(b->missing.as<int32_t>(), b->free_list.as<int32_t>(), counts, b->bound_u, p->src,
+                           p->rec.as<float4>(), p->slot_of.as<int32_t>(), p->occ.as<int32_t>(), s));
+  if (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT) {
+    if (mode == GC_REORG_PACK)
+      GC_HIP(c, launch_gather(b->U.as<int32_t>(), counts, b->bound_u, p->slot_of.as<int32_t>(), p->rec.as<float4>(),
+                              b->packed.as<float4>(), s));
+    else
+      GC_HIP(c, launch_gather_src(b->U.as<int32_t>(), counts, b->bound_u, p->src, b->packed.as<float4>(), s));
+    GC_HIP(c, launch_remap_ranges(b->d_ranges.as<int2>(), R, b->d_tasks.as<gc_task>(), T, b->pos.as<int32_t>(),
+                                  b->pranges.as<int2>(), b->pibeg.as<int32_t>(), s));
+    b->rec = b->packed.as<float4>();
+  } else {
+    GC_HIP(c, launch_remap_lists(b->d_tasks.as<gc_task>(), T, b->d_ranges.as<int2>(), b->d_ioff.as<int32_t>(),
+                                 b->d_joff.as<int32_t>(), p->slot_of.as<int32_t>(), b->ilist.as<int32_t>(),
+                                 b->jlist.as<int32_t>(), mode == GC_REORG_SORTED ? 1 : 0, s));
+    b->rec = p->rec.as<float4>();
+  }
+  return GC_OK;
+}
+
+static gc_status reorganize_async(gc_batch b, gc_pool p, int32_t mode, hipStream_t s, bool* needs_need_clear) {
+  gc_status st = reorganize_lookup(b, p, mode, s, needs_need_clear);
+  if (st != GC_OK) return st;
+  return reorganize_apply(b, p, mode, s);
+}
+
+extern "C" gc_status gc_reorganize(gc_batch b, gc_pool p, int32_t mode, int32_t check_capacity, void* stream) {
+  if (!b || !p) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  if (!b->committed) return set_err(c, GC_E_STATE, "gc_reorganize: batch not committed");
+  if (p->n_ids != b->n_ids) return set_err(c, GC_E_INVAL, "gc_reorganize: pool and batch id spaces differ");
+  if (mode < GC_REORG_REDUNDANT || mode > GC_REORG_NONE) return set_err(c, GC_E_INVAL, "gc_reorganize: bad mode %d", mode);
+  if (!p->src) return set_err(c, GC_E_STATE, "gc_reorganize: pool has no source");
+  if (mode == GC_REORG_NONE) {
+    if (!p->src_device) return set_err(c, GC_E_INVAL, "gc_reorganize: NONE needs a device-resident source");
+    b->mode = mode;
+    b->pool = p;
+    b->rec = p->src;
+    return GC_OK;
+  }
+  if (mode == GC_REORG_SORTED && b->max_direct > kSortMax)
+    return set_err(c, GC_E_UNSUPPORTED, "gc_reorganize: SORTED supports at most %d direct entries per task (got %d)",
+                   kSortMax, b->max_direct);
+  hipStream_t s = S(stream);
+  bool clear = false;
+  b->mode = -1;
+  gc_status st = reorganize_lookup(b, p, mode, s, &clear);
+  if (st != GC_OK) return st;
+  if (check_capacity && mode != GC_REORG_REDUNDANT) {
+    int32_t h[8];
+    GC_HIP(c, hipMemcpyAsync(h, b->counts.p, sizeof h, hipMemcpyDeviceToHost, s));
+    GC_HIP(c, hipStreamSynchronize(s));
+    if (h[1] > h[2])
+      return set_err(c, GC_E_FULL, "gc_reorganize: %d records missing but only %d pool slots free", h[1], h[2]);
+  }
+  st = reorganize_apply(b, p, mode, s);
+  if (st != GC_OK) return st;
+  b->mode = mode;
+  b->pool = p;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int32_t* pos, int32_t* missing,
+                                   int32_t* new_slot, int32_t* pranges, int32_t* pi_begin, int32_t* ilist,
+                                   int32_t* jlist, void* stream) {
+  if (!b) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  if (b->mode < 0 || b->mode == GC_REORG_NONE) return set_err(c, GC_E_STATE, "gc_batch_maps: no reorganisation");
+  hipStream_t s = S(stream);
+  int32_t h[8];
+  GC_HIP(c, hipMemcpyAsync(h, b->counts.p, sizeof h, hipMemcpyDeviceToHost, s));
+  GC_HIP(c, hipStreamSynchronize(s));
+  const int32_t nu = h[0], nm = (b->mode == GC_REORG_REDUNDANT) ? h[0] : h[1];
+  if (counts) {
+    counts[0] = nu;
+    counts[1] = nm;
+  }
+  auto dn = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!dst || !bytes) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+  };
+  GC_HIP(c, dn(U, b->U.p, sizeof(int32_t) * (size_t)nu));
+  GC_HIP(c, dn(pos, b->pos.p, sizeof(int32_t) * (size_t)b->n_ids));
+  if (b->mode == GC_REORG_REDUNDANT) {
+    GC_HIP(c, dn(missing, b->U.p, sizeof(int32_t) * (size_t)nu));
+  } else {
+    GC_HIP(c, dn(missing, b->missing.p, sizeof(int32_t) * (size_t)nm));
+    GC_HIP(c, dn(new_slot, b->free_list.p, sizeof(int32_t) * (size_t)std::min(nm, h[2])));
+  }
+  if (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT) {
+    GC_HIP(c, dn(pranges, b->pranges.p, sizeof(int32_t) * b->ranges.size()));
+    GC_HIP(c, dn(pi_begin, b->pibeg.p, sizeof(int32_t) * b->tasks.size()));
+  } else {
+    GC_HIP(c, dn(ilist, b->ilist.p, sizeof(int32_t) * (size_t)b->n_targets));
+    GC_HIP(c, dn(jlist, b->jlist.p, sizeof(int32_t) * (size_t)b->n_direct));
+  }
+  GC_HIP(c, hipStreamSynchronize(s));
+  return GC_OK;
+}
+
+// ===================================================================== combined launch
+
+static gc_status check_prm(gc_batch b, const gc_force_params* prm, int* tile, int* wpb) {
+  gc_ctx c = b->ctx;
+  if (!prm) return set_err(c, GC_E_INVAL, "NULL force parameters");
+  if (b->kind == GC_KIND_GRAV && prm->kind != GC_FORCE_GRAV_MONO && prm->kind != GC_FORCE_GRAV_QUAD)
+    return set_err(c, GC_E_INVAL, "gravity batch needs GC_FORCE_GRAV_MONO or GC_FORCE_GRAV_QUAD");
+  if (b->kind == GC_KIND_LJ && prm->kind != GC_FORCE_LJ) return set_err(c, GC_E_INVAL, "LJ batch needs GC_FORCE_LJ");
+  *tile = prm->tile ? prm->tile : 256;
+  *wpb = prm->waves_per_block ? prm->waves_per_block : 4;
+  if (*tile < 64 || *tile > kMaxTile || *tile % 64) return set_err(c, GC_E_INVAL, "tile must be a multiple of 64 in [64, %d]", kMaxTile);
+  if (*wpb < 1 || *wpb > 8) return set_err(c, GC_E_INVAL, "waves_per_block must be in [1, 8]");
+  if (b->kind == GC_KIND_GRAV && !(prm->soft_eps > 0.f)) return set_err(c, GC_E_INVAL, "soft_eps must be > 0");
+  if (b->kind == GC_KIND_LJ) {
+    if (prm->n_types < 1 || prm->n_types > 8 || !prm->eps_t || !prm->sig_t || !prm->mass_t)
+      return set_err(c, GC_E_INVAL, "LJ needs 1..8 types and device eps_t, sig_t, mass_t");
+    if (!(prm->r_cut > 0.f)) return set_err(c, GC_E_INVAL, "r_cut must be > 0");
+    *wpb = 4;
+  }
+  if (prm->schedule != 0 && prm->schedule != 1) return set_err(c, GC_E_INVAL, "schedule must be 0 or 1");
+  return GC_OK;
+}
+
+static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, const float* nodes_dev, float* acc_dev,
+                                       hipStream_t s) {
+  gc_ctx c = b->ctx;
+  int tile, wpb;
+  gc_status st = check_prm(b, prm, &tile, &wpb);
+  if (st != GC_OK) return st;
+  if (b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_launch_combined: batch not reorganised");
+  if (!acc_dev) return set_err(c, GC_E_INVAL, "gc_launch_combined: NULL acc");
+  const int32_t T = (int32_t)b->tasks.size();
+  const bool packed = (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT);
+  const bool lists = (b->mode == GC_REORG_INDIRECT || b->mode == GC_REORG_SORTED);
+  const bool persistent = prm->schedule == 1;
+  if (b->queue.ensure(16) != hipSuccess) return set_err(c, GC_E_NOMEM, "queue");
+  if (persistent) GC_HIP(c, launch_fill_i32(b->queue.as<int32_t>(), 0, 1, s));
+  if (b->kind == GC_KIND_GRAV) {
+    if (!nodes_dev && !b->nodes.empty()) return set_err(c, GC_E_INVAL, "gc_launch_combined: NULL nodes with node refs");
+    GravArgs a{};
+    a.tasks = b->d_tasks.as<gc_task>();
+    a.n_tasks = T;
+    a.ranges = packed ? b->pranges.as<int2>() : b->d_ranges.as<int2>();
+    a.ibeg = packed ? b->pibeg.as<int32_t>() : nullptr;
+    a.ioff = b->d_ioff.as<int32_t>();
+    a.joff = b->d_joff.as<int32_t>();
+    a.ilist = b->ilist.as<int32_t>();
+    a.jlist = b->jlist.as<int32_t>();
+    a.node_idx = b->d_nodes.as<int32_t>();
+    a.nodes = reinterpret_cast<const float4*>(nodes_dev);
+    a.rec = b->rec;
+    a.acc = reinterpret_cast<float4*>(acc_dev);
+    a.G = prm->G;
+    a.eps2 = prm->soft_eps * prm->soft_eps;
+    a.tile = tile;
+    a.queue = b->queue.as<int32_t>();
+    a.order = b->d_order.as<int32_t>();
+    int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
+    int grid = prm->grid_blocks;
+    if (persistent && grid <= 0) {
+      int per = 0;
+      GC_HIP(c, grav_occupancy(order, lists, true, tile, wpb, &per));
+      grid = std::max(1, per) * c->n_cu;
+    }
+    GC_HIP(c, launch_grav(order, lists, persistent, a, wpb, grid, s));
+  } else {
+    if (lists) return set_err(c, GC_E_UNSUPPORTED, "Lennard-Jones supports PACK, REDUNDANT and NONE");
+    if (!b->pool->src_device) return set_err(c, GC_E_INVAL, "Lennard-Jones needs a device-resident source");
+    GC_HIP(c, launch_fill_f32(acc_dev, 0.f, 4 * (int64_t)b->n_ids, s));
+    LJArgs a{};
+    a.tasks = b->d_tasks.as<gc_task>();
+    a.n_tasks = T;
+    a.ranges = packed ? b->pranges.as<int2>() : b->d_ranges.as<int2>();
+    a.ranges_id = b->d_ranges.as<int2>();
+    a.ibeg = packed ? b->pibeg.as<int32_t>() : nullptr;
+    a.rec = b->rec;
+    a.acc = reinterpret_cast<float4*>(acc_dev);
+    a.eps_t = prm->eps_t;
+    a.sig_t = prm->sig_t;
+    a.n_types = prm->n_types;
+    a.rc2 = prm->r_cut * prm->r_cut;
+    a.queue = b->queue.as<int32_t>();
+    a.order = b->d_order.as<int32_t>();
+    int grid = prm->grid_blocks > 0 ? prm->grid_blocks : 8 * c->n_cu;
+    GC_HIP(c, launch_lj(persistent, a, 4, grid, s));
+    GC_HIP(c, launch_lj_finish(reinterpret_cast<float4*>(acc_dev), prm->mass_t, b->pool->src, b->n_ids, s));
+  }
+  return GC_OK;
+}
+
+extern "C" gc_status gc_launch_combined(gc_batch b, const gc_force_params* prm, const float* nodes_dev, float* acc_dev,
+                                        void* stream) {
+  if (!b) return GC_E_INVAL;
+  GC_ENTER(b->ctx);
+  return launch_combined_async(b, prm, nodes_dev, acc_dev, S(stream));
+}
+
+extern "C" gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_t* blocks_per_cu, int32_t* n_cu) {
+  GC_ENTER(ctx);
+  if (!prm || !blocks_per_cu) return set_err(ctx, GC_E_INVAL, "gc_occupancy: NULL argument");
+  int tile = prm->tile ? prm->tile : 256, wpb = prm->waves_per_block ? prm->waves_per_block : 4, per = 0;
+  GC_HIP(ctx, grav_occupancy(prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1, false, prm->schedule == 1, tile, wpb, &per));
+  *blocks_per_cu = per;
+  if (n_cu) *n_cu = ctx->n_cu;
+  return GC_OK;
+}
+
+// ===================================================================== backward (adjoint)
+
+extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const float* nodes_dev,
+                                 const int32_t* node_range_dev, int32_t n_nodes, const float* cot_dev, float* gpos_dev,
+                                 float* gmass_dev, float* gparam_dev, void* stream);
+
+// ===================================================================== graphs
+
+extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* batches, gc_pool* pools,
+                                      const int32_t* modes, const gc_force_params* prm, const float* nodes_dev,
+                                      float* acc_dev, int32_t pre_reset, const int32_t* const* place_ids,
+                                      const int32_t* const* place_slots, const int32_t* place_n, void* stream,
+                                      gc_graph* out) {
+  GC_ENTER(ctx);
+  if (n_steps <= 0 || !batches || !pools || !modes || !prm || !out)
+    return set_err(ctx, GC_E_INVAL, "gc_graph_capture: bad arguments");
+  if (!stream) return set_err(ctx, GC_E_INVAL, "gc_graph_capture: capture needs a non-default stream");
+  for (int32_t k = 0; k < n_steps; ++k) {
+    if (!batches[k] || !pools[k] || !batches[k]->committed)
+      return set_err(ctx, GC_E_STATE, "gc_graph_capture: step %d batch not committed", k);
+    if (modes[k] == GC_REORG_SORTED && batches[k]->max_direct > kSortMax)
+      return set_err(ctx, GC_E_UNSUPPORTED, "gc_graph_capture: SORTED list too long in step %d", k);
+    int tile, wpb;
+    gc_status st = check_prm(batches[k], prm, &tile, &wpb);
+    if (st != GC_OK) return st;
+    // size buffers outside the capture (allocation is not capturable)
+    if (modes[k] != GC_REORG_NONE && ensure_reorg_buffers(batches[k], pools[k]) != hipSuccess)
+      return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: buffers");
+  }
+  // flags start cleared: clear once outside the capture
+  for (int32_t k = 0; k < n_steps; ++k)
+    if (modes[k] != GC_REORG_NONE)
+      GC_HIP(ctx, launch_fill_i32(batches[k]->need.as<int32_t>(), 0, (int64_t)(batches[k]->need.bytes / 4), S(stream)));
+  GC_HIP(ctx, hipStreamSynchronize(S(stream)));
+  hipStream_t s = S(stream);
+  GC_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  gc_status st = GC_OK;
+  for (int32_t k = 0; k < n_steps && st == GC_OK; ++k) {
+    gc_batch b = batches[k];
+    gc_pool p = pools[k];
+    if (pre_reset) {
+      if (pool_reset_async(p, s) != hipSuccess) st = set_err(ctx, GC_E_HIP, "capture: pool reset");
+      if (st == GC_OK && place_n && place_n[k] > 0 &&
+          launch_place(place_ids[k], place_slots[k], place_n[k], p->src, p->rec.as<float4>(), p->slot_of.as<int32_t>(),
+                       p->occ.as<int32_t>(), s) != hipSuccess)
+        st = set_err(ctx, GC_E_HIP, "capture: place");
+    }
+    if (st != GC_OK) break;
+    if (modes[k] == GC_REORG_NONE) {
+      b->mode = GC_REORG_NONE;
+      b->pool = p;
+      b->rec = p->src;
+    } else {
+      bool clear = false;
+      st = reorganize_async(b, p, modes[k], s, &clear);
+      b->mode = modes[k];
+      b->pool = p;
+    }
+    if (st == GC_OK) st = launch_combined_async(b, prm, nodes_dev, acc_dev, s);
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != GC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+  gc_graph gr = new gc_graph_();
+  gr->ctx = ctx;
+  gr->graph = g;
+  e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete gr;
+    return hip_fail(ctx, e, "hipGraphInstantiate");
+  }
+  *out = gr;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_graph_launch(gc_graph g, void* stream) {
+  if (!g) return GC_E_INVAL;
+  GC_ENTER(g->ctx);
+  GC_HIP(g->ctx, hipGraphLaunch(g->exec, S(stream)));
+  return GC_OK;
+}
+
+extern "C" gc_status gc_graph_destroy(gc_graph g) {
+  if (!g) return GC_E_INVAL;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return GC_OK;
+}
+
+// ===================================================================== autotune
+
+extern "C" gc_status gc_autotune(gc_batch b, const gc_force_params* base, const float* nodes_dev, float* acc_dev,
+                                 int32_t reps, float* times_ms, gc_force_params* best, void* stream) {
+  if (!b) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  if (!base || !best || reps < 1) return set_err(c, GC_E_INVAL, "gc_autotune: bad arguments");
+  hipStream_t s = S(stream);
+  hipEvent_t e0, e1;
+  GC_HIP(c, hipEventCreate(&e0));
+  GC_HIP(c, hipEventCreate(&e1));
+  const int tiles[3] = {128, 256, 512}, waves[3] = {2, 4, 8};
+  float best_t = 1e30f;
+  int idx = 0;
+  gc_status st = GC_OK;
+  for (int ti = 0; ti < 3 && st == GC_OK; ++ti)
+    for (int wi = 0; wi < 3 && st == GC_OK; ++wi)
+      for (int sc = 0; sc < 2 && st == GC_OK; ++sc, ++idx) {
+        gc_force_params p = *base;
+        p.tile = tiles[ti];
+        p.waves_per_block = waves[wi];
+        p.schedule = sc;
+        p.grid_blocks = 0;
+        st = launch_combined_async(b, &p, nodes_dev, acc_dev, s);  // warm-up
+        if (st != GC_OK) break;
+        hipError_t e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == GC_OK && e == hipSuccess; ++r) st = launch_combined_async(b, &p, nodes_dev, acc_dev, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) st = hip_fail(c, e, "gc_autotune timing");
+        if (st != GC_OK) break;
+        ms /= reps;
+        if (times_ms) times_ms[idx] = ms;
+        if (ms < best_t) {
+          best_t = ms;
+          *best = p;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}

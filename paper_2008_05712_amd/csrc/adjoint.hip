@@ -1,10 +1,430 @@
-// Adjoint of the combined force pass (placeholder until the kernels land).
+// Adjoint (vector-Jacobian product) of the combined force pass for
+// L = sum_i cot_i . a_i, recomputing every pair term (nothing is stored by
+// the forward pass).
+//
+// Gravity (direct + monopole nodes).  With u = x_j - x_i, s^2 = |u|^2 + eps^2:
+//   w = G m_j [g_i / s^3 - 3 (g_i . u) u / s^5];  dL/dx_j += w, dL/dx_i -= w,
+//   dL/dm_j += G (g_i . u) / s^3   (the i = j term is skipped)
+// and for a node with d = x_i - com, r^2 = |d|^2 + eps^2:
+//   v = -G M [g_i / r^3 - 3 (g_i . d) d / r^5];  dL/dx_i += v, dL/dcom -= v,
+//   dL/dM += -G (g_i . d) / r^3.
+// Node gradients reach member particles through com = sum m_k x_k / M and
+// M = sum m_k:  dL/dx_k += (m_k / M) dL/dcom,  dL/dm_k += dL/dM + (x_k - com) . dL/dcom / M.
+//
+// Schedule: one wavefront per task; lanes are sources (nodes, then direct
+// particles), the loop runs over blocks of 8 targets held in registers
+// (LDS broadcast), so each lane accumulates its source's gradient across
+// the block and each target's gradient is reduced across the wavefront once
+// per block.  Scatters use hardware FP32 atomics (order-dependent rounding).
+//
+// Lennard-Jones: h_i = g_i / m_i, dh = h_i - h_j, p = dh . d, f' = df/d(r^2):
+//   dL/dx_i += f dh + 2 f' p d, dL/dx_j -= the same,
+//   dL/deps_ij = p f / eps_ij,  dL/dsigma_ij = p * 24 eps (24 s^11 r^-14 - 6 s^5 r^-8),
+//   chained to the per-type parameters through Lorentz-Berthelot mixing;
+//   dL/dm_i = -g_i . F_i / m_i^2 with the forces F recomputed here.
 #include "gc_internal.h"
 
-extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const float* nodes_dev,
-                                 const int32_t* node_range_dev, int32_t n_nodes, const float* cot_dev, float* gpos_dev,
-                                 float* gmass_dev, float* gparam_dev, void* stream) {
-  (void)b; (void)prm; (void)nodes_dev; (void)node_range_dev; (void)n_nodes; (void)cot_dev; (void)gpos_dev;
-  (void)gmass_dev; (void)gparam_dev; (void)stream;
-  return GC_E_UNSUPPORTED;
+namespace gc {
+namespace {
+
+constexpr int kTB = 8;  // targets per register block
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int* total) {
+  const int lane = threadIdx.x & 63;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int u = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += u;
+  }
+  *total = __shfl(inc, 63, 64);
+  return inc - v;
+}
+
+template <bool PACKED>
+__global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
+  const GravArgs& a = A.f;
+  __shared__ float4 tpos[4][kTB], tcot[4][kTB];
+  __shared__ int ro[4][64], rb[4][64];
+  const int lane = threadIdx.x & 63;
+  const int wid = uniform(threadIdx.x >> 6);
+  const int t = uniform(blockIdx.x * 4 + wid);
+  if (t >= a.n_tasks) return;
+  const gc_task tk = a.tasks[t];
+  const int ic = tk.i_count;
+  const int ibase = PACKED ? a.ibeg[t] : tk.i_begin;
+  const float G = a.G, eps2 = a.eps2;
+  for (int tb0 = 0; tb0 < ic; tb0 += kTB) {
+    const int tb = ic - tb0 < kTB ? ic - tb0 : kTB;
+    if (lane < kTB) {
+      float4 p = make_float4(0.f, 0.f, 0.f, 0.f), g = p;
+      if (lane < tb) {
+        p = a.rec[ibase + tb0 + lane];
+        g = A.cot[tk.i_begin + tb0 + lane];
+      }
+      tpos[wid][lane] = p;
+      tcot[wid][lane] = g;
+    }
+    wave_sync();
+    float xt[kTB], yt[kTB], zt[kTB], gx[kTB], gy[kTB], gz[kTB];
+    int idt[kTB];
+    float tgx[kTB], tgy[kTB], tgz[kTB];
+#pragma unroll
+    for (int k = 0; k < kTB; ++k) {
+      float4 p = tpos[wid][k], g = tcot[wid][k];
+      xt[k] = p.x; yt[k] = p.y; zt[k] = p.z;
+      gx[k] = g.x; gy[k] = g.y; gz[k] = g.z;
+      idt[k] = k < tb ? tk.i_begin + tb0 + k : -1;
+      tgx[k] = tgy[k] = tgz[k] = 0.f;
+    }
+    // ---- monopole nodes: lane = node
+    for (int nb = 0; nb < tk.n_count; nb += 64) {
+      const int e = nb + lane;
+      const bool valid = e < tk.n_count;
+      int nd = -1;
+      float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (valid) {
+        nd = a.node_idx[tk.n_first + e];
+        c = a.nodes[3 * nd];
+      }
+      const float GM = G * c.w;
+      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gM = 0.f;
+#pragma unroll
+      for (int k = 0; k < kTB; ++k) {
+        float dx = xt[k] - c.x, dy = yt[k] - c.y, dz = zt[k] - c.z;
+        float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+        float ri = __builtin_amdgcn_rsqf(r2);
+        float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+        float gd = __builtin_fmaf(gz[k], dz, __builtin_fmaf(gy[k], dy, gx[k] * dx));
+        float c1 = -GM * ri3;
+        float c2 = 3.f * GM * gd * ri5;
+        float vx = __builtin_fmaf(c1, gx[k], c2 * dx);
+        float vy = __builtin_fmaf(c1, gy[k], c2 * dy);
+        float vz = __builtin_fmaf(c1, gz[k], c2 * dz);
+        tgx[k] += vx; tgy[k] += vy; tgz[k] += vz;
+        gcx -= vx; gcy -= vy; gcz -= vz;
+        gM = __builtin_fmaf(gd, ri3, gM);
+      }
+      if (valid) {
+        float* q = A.gnode + 4 * nd;
+        unsafeAtomicAdd(q, gcx);
+        unsafeAtomicAdd(q + 1, gcy);
+        unsafeAtomicAdd(q + 2, gcz);
+        unsafeAtomicAdd(q + 3, -G * gM);
+      }
+    }
+    // ---- direct sources: lane = flat position within a group of up to 64 ranges
+    for (int rg = 0; rg < tk.j_nranges; rg += 64) {
+      const int nr = tk.j_nranges - rg < 64 ? tk.j_nranges - rg : 64;
+      int2 g = make_int2(0, 0);
+      if (lane < nr) g = a.ranges[tk.j_first + rg + lane];
+      int total;
+      const int o = wave_excl_scan(g.y, &total);
+      total = uniform(total);
+      ro[wid][lane] = lane < nr ? o : 0x7fffffff;
+      rb[wid][lane] = g.x;
+      wave_sync();
+      for (int f0 = 0; f0 < total; f0 += 64) {
+        const int f = f0 + lane;
+        const bool valid = f < total;
+        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+        int sid = -2;
+        if (valid) {
+          // last range whose start offset is <= f (empty ranges share the next one's offset)
+          int lo = 0, hi = nr - 1;
+          while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (ro[wid][mid] <= f) lo = mid;
+            else hi = mid - 1;
+          }
+          const int p = rb[wid][lo] + (f - ro[wid][lo]);
+          s = a.rec[p];
+          sid = PACKED ? A.src_id[p] : p;
+        }
+        const float Gm = G * s.w, m3 = -3.f * Gm;
+        float gsx = 0.f, gsy = 0.f, gsz = 0.f, gms = 0.f;
+#pragma unroll
+        for (int k = 0; k < kTB; ++k) {
+          float ux = s.x - xt[k], uy = s.y - yt[k], uz = s.z - zt[k];
+          float s2 = __builtin_fmaf(uz, uz, __builtin_fmaf(uy, uy, __builtin_fmaf(ux, ux, eps2)));
+          float ri = __builtin_amdgcn_rsqf(s2);
+          float ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+          float gu = __builtin_fmaf(gz[k], uz, __builtin_fmaf(gy[k], uy, gx[k] * ux));
+          const bool self = (sid == idt[k]);
+          float c1 = self ? 0.f : Gm * ri3;
+          float c2 = self ? 0.f : m3 * gu * ri5;
+          float wx = __builtin_fmaf(c1, gx[k], c2 * ux);
+          float wy = __builtin_fmaf(c1, gy[k], c2 * uy);
+          float wz = __builtin_fmaf(c1, gz[k], c2 * uz);
+          gsx += wx; gsy += wy; gsz += wz;
+          tgx[k] -= wx; tgy[k] -= wy; tgz[k] -= wz;
+          gms = __builtin_fmaf(self ? 0.f : gu, ri3, gms);
+        }
+        if (valid) {
+          float4* q = A.gpos + sid;
+          unsafeAtomicAdd(&q->x, gsx);
+          unsafeAtomicAdd(&q->y, gsy);
+          unsafeAtomicAdd(&q->z, gsz);
+          unsafeAtomicAdd(A.gmass + sid, G * gms);
+        }
+      }
+      wave_sync();
+    }
+    // ---- target gradients: reduce across the wavefront, one atomic per target component
+#pragma unroll
+    for (int k = 0; k < kTB; ++k) {
+      float sx = wave_sum(tgx[k]), sy = wave_sum(tgy[k]), sz = wave_sum(tgz[k]);
+      if (lane == k && k < tb) {
+        float4* q = A.gpos + (tk.i_begin + tb0 + k);
+        unsafeAtomicAdd(&q->x, sx);
+        unsafeAtomicAdd(&q->y, sy);
+        unsafeAtomicAdd(&q->z, sz);
+      }
+    }
+    wave_sync();
+  }
+}
+
+// One wavefront per node: push dL/dcom and dL/dM to the member particles.
+__global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_nodes, const float4* __restrict__ nodes,
+                             const float* __restrict__ gnode, const float4* __restrict__ rec_by_id,
+                             float4* __restrict__ gpos, float* __restrict__ gmass) {
+  const int lane = threadIdx.x & 63;
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  for (int nd = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); nd < n_nodes; nd += waves) {
+    const float4 gq = *reinterpret_cast<const float4*>(gnode + 4 * nd);
+    if (gq.x == 0.f && gq.y == 0.f && gq.z == 0.f && gq.w == 0.f) continue;
+    const float4 c = nodes[3 * nd];
+    const float invM = 1.f / c.w;
+    const int b = node_range[2 * nd], n = node_range[2 * nd + 1];
+    for (int k = lane; k < n; k += 64) {
+      const float4 r = rec_by_id[b + k];
+      const float f = r.w * invM;
+      float4* q = gpos + (b + k);
+      unsafeAtomicAdd(&q->x, f * gq.x);
+      unsafeAtomicAdd(&q->y, f * gq.y);
+      unsafeAtomicAdd(&q->z, f * gq.z);
+      const float dc = (r.x - c.x) * gq.x + (r.y - c.y) * gq.y + (r.z - c.z) * gq.z;
+      unsafeAtomicAdd(gmass + (b + k), gq.w + dc * invM);
+    }
+  }
+}
+
+constexpr int kMaxTypes = 8;
+constexpr int kLJTile = 128;
+
+// One wavefront per cell-pair task, lanes = (i atom) x (j slice) as in the forward kernel.
+// j-side gradients and forces accumulate in LDS (LDS atomics), i-side in registers; the
+// per-type parameter gradients accumulate per lane in LDS columns indexed by the type pair.
+__global__ void __launch_bounds__(256) k_lj_adj(LJAdjArgs A) {
+  const LJArgs& a = A.f;
+  __shared__ float2 tab[kMaxTypes * kMaxTypes];   // (24 eps_ij, sigma_ij)
+  __shared__ float4 jt[4][kLJTile], jh[4][kLJTile];
+  __shared__ float gj[4][6][kLJTile];              // j: dL/dx (3), force (3)
+  __shared__ float red[4][6][64];
+  __shared__ float pg[4][2 * kMaxTypes * kMaxTypes];  // per wave: dL/deps_ij, dL/dsigma_ij by type pair
+  const int lane = threadIdx.x & 63;
+  const int wid = uniform(threadIdx.x >> 6);
+  const int nt = a.n_types;
+  for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) {
+    int ta = k / nt, tb = k % nt;
+    tab[k] = make_float2(24.f * sqrtf(a.eps_t[ta] * a.eps_t[tb]), 0.5f * (a.sig_t[ta] + a.sig_t[tb]));
+  }
+  for (int k = threadIdx.x; k < 4 * 2 * kMaxTypes * kMaxTypes; k += blockDim.x) (&pg[0][0])[k] = 0.f;
+  __syncthreads();
+  const int t = uniform(blockIdx.x * 4 + wid);
+  if (t < a.n_tasks) {
+    const gc_task tk = a.tasks[t];
+    const int2 gjr = a.ranges[tk.j_first];
+    const int2 gjid = a.ranges_id[tk.j_first];
+    const bool self = (tk.flags & GC_TASK_SELF) != 0;
+    const float sa0 = tk.shift[0] > 0.f ? tk.shift[0] : 0.f, sb0 = tk.shift[0] < 0.f ? tk.shift[0] : 0.f;
+    const float sa1 = tk.shift[1] > 0.f ? tk.shift[1] : 0.f, sb1 = tk.shift[1] < 0.f ? tk.shift[1] : 0.f;
+    const float sa2 = tk.shift[2] > 0.f ? tk.shift[2] : 0.f, sb2 = tk.shift[2] < 0.f ? tk.shift[2] : 0.f;
+    const int ipos0 = a.ibeg ? a.ibeg[t] : tk.i_begin;
+    for (int i0 = 0; i0 < tk.i_count; i0 += 64) {
+      const int icc = tk.i_count - i0 < 64 ? tk.i_count - i0 : 64;
+      const int S = 64 / icc;
+      const int il = lane % icc, sl = lane / icc;
+      const bool active = sl < S;
+      float xi = 0.f, yi = 0.f, zi = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+      int ti = 0;
+      if (active) {
+        float4 r = a.rec[ipos0 + i0 + il];
+        xi = r.x - sa0; yi = r.y - sa1; zi = r.z - sa2;
+        ti = (int)r.w;
+        float4 g = A.cot[tk.i_begin + i0 + il];
+        float m = A.mass_t[ti];
+        hx = g.x / m; hy = g.y / m; hz = g.z / m;
+      }
+      float Gx = 0.f, Gy = 0.f, Gz = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f;
+      for (int j0 = 0; j0 < gjr.y; j0 += kLJTile) {
+        const int cnt = gjr.y - j0 < kLJTile ? gjr.y - j0 : kLJTile;
+        for (int e = lane; e < cnt; e += 64) {
+          float4 r = a.rec[gjr.x + j0 + e];
+          jt[wid][e] = make_float4(r.x + sb0, r.y + sb1, r.z + sb2, r.w);
+          float4 g = A.cot[gjid.x + j0 + e];
+          float m = A.mass_t[(int)r.w];
+          jh[wid][e] = make_float4(g.x / m, g.y / m, g.z / m, 0.f);
+#pragma unroll
+          for (int q = 0; q < 6; ++q) gj[wid][q][e] = 0.f;
+        }
+        wave_sync();
+        if (active) {
+          const int C = (cnt + S - 1) / S;
+          const int e0 = sl * C, e1 = e0 + C < cnt ? e0 + C : cnt;
+          for (int e = e0; e < e1; ++e) {
+            if (self && j0 + e <= i0 + il) continue;
+            const float4 j = jt[wid][e];
+            const float dx = xi - j.x, dy = yi - j.y, dz = zi - j.z;
+            const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+            if (r2 < a.rc2) {
+              const int tj = (int)j.w;
+              const float2 p = tab[ti * nt + tj];
+              const float e24 = p.x, sg = p.y;
+              const float ri2 = __builtin_amdgcn_rcpf(r2);
+              const float q = sg * sg * ri2;
+              const float q3 = q * q * q;
+              const float f = e24 * q3 * __builtin_fmaf(2.f, q3, -1.f) * ri2;           // force factor
+              const float fp = e24 * q3 * __builtin_fmaf(-14.f, q3, 4.f) * ri2 * ri2;   // df / d(r^2)
+              const float4 hj = jh[wid][e];
+              const float dhx = hx - hj.x, dhy = hy - hj.y, dhz = hz - hj.z;
+              const float pp = __builtin_fmaf(dhz, dz, __builtin_fmaf(dhy, dy, dhx * dx));
+              const float c2 = 2.f * fp * pp;
+              const float wx = __builtin_fmaf(f, dhx, c2 * dx);
+              const float wy = __builtin_fmaf(f, dhy, c2 * dy);
+              const float wz = __builtin_fmaf(f, dhz, c2 * dz);
+              Gx += wx; Gy += wy; Gz += wz;
+              Fx = __builtin_fmaf(f, dx, Fx);
+              Fy = __builtin_fmaf(f, dy, Fy);
+              Fz = __builtin_fmaf(f, dz, Fz);
+              atomicAdd(&gj[wid][0][e], -wx);
+              atomicAdd(&gj[wid][1][e], -wy);
+              atomicAdd(&gj[wid][2][e], -wz);
+              atomicAdd(&gj[wid][3][e], -f * dx);
+              atomicAdd(&gj[wid][4][e], -f * dy);
+              atomicAdd(&gj[wid][5][e], -f * dz);
+              // dL/deps_ij = p f / eps_ij; dL/dsigma_ij = p (24 eps)(24 s^11 r^-14 - 6 s^5 r^-8) = p f_s
+              const float e_ij = e24 * (1.f / 24.f);
+              const float dle = pp * f / e_ij;
+              const float fs = e24 * q3 * __builtin_fmaf(24.f, q3, -6.f) * ri2 / sg;
+              atomicAdd(&pg[wid][2 * (ti * nt + tj)], dle);
+              atomicAdd(&pg[wid][2 * (ti * nt + tj) + 1], pp * fs);
+            }
+          }
+        }
+        wave_sync();
+        for (int e = lane; e < cnt; e += 64) {
+          const int id = gjid.x + j0 + e;
+          float4* q = A.gpos + id;
+          unsafeAtomicAdd(&q->x, gj[wid][0][e]);
+          unsafeAtomicAdd(&q->y, gj[wid][1][e]);
+          unsafeAtomicAdd(&q->z, gj[wid][2][e]);
+          float4* fq = A.force + id;
+          unsafeAtomicAdd(&fq->x, gj[wid][3][e]);
+          unsafeAtomicAdd(&fq->y, gj[wid][4][e]);
+          unsafeAtomicAdd(&fq->z, gj[wid][5][e]);
+        }
+        wave_sync();
+      }
+      red[wid][0][lane] = Gx; red[wid][1][lane] = Gy; red[wid][2][lane] = Gz;
+      red[wid][3][lane] = Fx; red[wid][4][lane] = Fy; red[wid][5][lane] = Fz;
+      wave_sync();
+      if (lane < icc) {
+        float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int sidx = 0; sidx < S; ++sidx)
+#pragma unroll
+          for (int q = 0; q < 6; ++q) s[q] += red[wid][q][sidx * icc + lane];
+        const int id = tk.i_begin + i0 + lane;
+        float4* q = A.gpos + id;
+        unsafeAtomicAdd(&q->x, s[0]);
+        unsafeAtomicAdd(&q->y, s[1]);
+        unsafeAtomicAdd(&q->z, s[2]);
+        float4* fq = A.force + id;
+        unsafeAtomicAdd(&fq->x, s[3]);
+        unsafeAtomicAdd(&fq->y, s[4]);
+        unsafeAtomicAdd(&fq->z, s[5]);
+      }
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  // per-type parameters: eps_ij = sqrt(eps_a eps_b), sigma_ij = (sigma_a + sigma_b) / 2
+  if (threadIdx.x < nt * nt) {
+    const int ta = threadIdx.x / nt, tb = threadIdx.x % nt;
+    float de = 0.f, ds = 0.f;
+    for (int w = 0; w < 4; ++w) {
+      de += pg[w][2 * threadIdx.x];
+      ds += pg[w][2 * threadIdx.x + 1];
+    }
+    if (de != 0.f || ds != 0.f) {
+      const float eij = sqrtf(a.eps_t[ta] * a.eps_t[tb]);
+      unsafeAtomicAdd(A.gparam + ta, de * a.eps_t[tb] / (2.f * eij));
+      unsafeAtomicAdd(A.gparam + tb, de * a.eps_t[ta] / (2.f * eij));
+      unsafeAtomicAdd(A.gparam + nt + ta, 0.5f * ds);
+      unsafeAtomicAdd(A.gparam + nt + tb, 0.5f * ds);
+    }
+  }
+}
+
+__global__ void k_lj_mass_grad(const float4* __restrict__ cot, const float4* __restrict__ force,
+                               const float* __restrict__ mass_t, const float4* __restrict__ rec_by_id,
+                               float* __restrict__ gmass, int32_t n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float4 g = cot[i], F = force[i];
+    const float m = mass_t[(int)rec_by_id[i].w];
+    gmass[i] += -(g.x * F.x + g.y * F.y + g.z * F.z) / (m * m);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_grav_adjoint(bool packed, const GravAdjArgs& a, int wpb, hipStream_t s) {
+  (void)wpb;
+  if (a.f.n_tasks <= 0) return hipSuccess;
+  const int grid = (a.f.n_tasks + 3) / 4;
+  if (packed) hipLaunchKernelGGL(k_grav_adj<true>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_grav_adj<false>, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_chain(const int32_t* node_range, int32_t n_nodes, const float4* nodes, const float* gnode,
+                             const float4* rec_by_id, float4* gpos, float* gmass, hipStream_t s) {
+  if (n_nodes <= 0) return hipSuccess;
+  int g = (n_nodes + 3) / 4;
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_node_chain, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, rec_by_id, gpos,
+                     gmass);
+  return hipGetLastError();
+}
+
+hipError_t launch_lj_adjoint(const LJAdjArgs& a, int wpb, hipStream_t s) {
+  (void)wpb;
+  if (a.f.n_tasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lj_adj, dim3((a.f.n_tasks + 3) / 4), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lj_mass_grad(const float4* cot, const float4* force, const float* mass_t, const float4* rec_by_id,
+                               float* gmass, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_lj_mass_grad, dim3(g), dim3(256), 0, s, cot, force, mass_t, rec_by_id, gmass, n);
+  return hipGetLastError();
+}
+
+}  // namespace gc

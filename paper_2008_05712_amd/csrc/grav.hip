@@ -1,18 +1,21 @@
 // Combined Barnes-Hut force kernel (Sec. 3.1: many work requests in one launch;
 // Sec. 4.1: a bucket's particles share one list of nodes and direct particles).
 //
-// Schedule: one wavefront per task.  A bucket holds few targets (about 10 on
-// average for a Plummer sphere with buckets of 32), so the 64 lanes are split
-// as (target i) x (source slice s): S = floor(64 / i_count) slices, lane
-// = s * i_count + i.  Source records (direct particles, or node records) are
+// Schedule: one workgroup of W wavefronts per task; the W waves split the
+// task's node and direct lists.  A bucket holds few targets (about 10 on
+// average for a Plummer sphere with buckets of 32), so within a wavefront the
+// 64 lanes are split as (target i) x (source slice s): S = floor(64 / i_count)
+// slices, lane = s * i_count + i.  Source records (direct particles, or node records) are
 // staged by the wavefront into its private LDS tile with coalesced loads; the
 // tile is padded with zero-mass entries to S * C records so every slice runs
 // exactly C iterations with no per-iteration bounds test; a lane reads its
 // slice's records from LDS (lanes of one slice read the same address: an LDS
-// broadcast).  Per tile each lane sums its slice in FP32 and adds the tile's
-// partial to an FP64 running sum; at the end the slices of each target are
-// reduced in FP64 through LDS and the target's float4 is written once.  No
-// atomics: results are bitwise independent of task order and schedule.
+// broadcast).  Node records of the next tile are prefetched into registers
+// while the current tile is computed.  Per tile each lane sums its slice in
+// FP32 and adds the tile's partial to an FP64 running sum; at the end the
+// slices and then the waves of each target are reduced in FP64 through LDS in
+// a fixed order and the target's float4 is written once.  No atomics: results
+// are bitwise independent of task order and of the schedule.
 //
 // The inner loops are plain FP32 VALU code (v_sub / v_fma / v_mul) with the
 // hardware reciprocal square root; pairwise forces are not a dense
@@ -104,13 +107,50 @@ __device__ __forceinline__ void tile_quads(const float4* __restrict__ p, int C, 
   }
 }
 
+// Node record for LDS: monopole (com, M); quadrupole adds (3 Sxx, 3 Syy, 3 Szz, 3 Sxy), (3 Sxz, 3 Syz, 1.5 T, 0).
+template <int ORDER>
+struct NodeRegs {
+  float4 v0, v1, v2;
+};
+
+template <int ORDER>
+__device__ __forceinline__ NodeRegs<ORDER> load_node(const float4* __restrict__ nodes, int idx) {
+  NodeRegs<ORDER> r;
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  r.v0 = z; r.v1 = z; r.v2 = z;
+  if (idx >= 0) {
+    const float4* nd = nodes + 3 * idx;
+    r.v0 = nd[0];
+    if (ORDER == 2) {
+      r.v1 = nd[1];
+      r.v2 = nd[2];
+    }
+  }
+  return r;
+}
+
+template <int ORDER>
+__device__ __forceinline__ void store_node(float4* L, int e, const NodeRegs<ORDER>& r) {
+  if (ORDER == 1) {
+    L[e] = r.v0;
+  } else {
+    L[3 * e] = r.v0;
+    L[3 * e + 1] = make_float4(3.f * r.v1.x, 3.f * r.v1.y, 3.f * r.v1.z, 3.f * r.v1.w);
+    L[3 * e + 2] = make_float4(3.f * r.v2.x, 3.f * r.v2.y, 1.5f * r.v2.z, 0.f);
+  }
+}
+
+// One workgroup of W wavefronts per task.  Wave w takes the task's nodes w, w + W, ...
+// and its direct ranges w, w + W, ... (address lists: windows w, w + W, ...), so W waves
+// share one task's lists; the per-target sums are reduced across slices within each wave
+// and then across the W waves, in a fixed order.
 template <int ORDER, bool LISTS, bool PERSIST>
 __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
   extern __shared__ float4 smem[];
+  __shared__ int s_task;
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
-  const int wpb = blockDim.x >> 6;
-  // per-wavefront LDS: max(tile + 64, 3 * (kNodeTile + 64)) float4 + 64 x 3 doubles reduction
+  const int W = blockDim.x >> 6;
   const int tile = a.tile;
   const int rec_cap = (tile + 64 > 3 * (kNodeTile + 64)) ? tile + 64 : 3 * (kNodeTile + 64);
   const int per_wave = rec_cap + 96;
@@ -121,14 +161,15 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
   while (true) {
     int t;
     if (PERSIST) {
-      int got = 0;
-      if (lane == 0) got = atomicAdd(a.queue, 1);
-      got = uniform(__shfl(got, 0, 64));
+      if (threadIdx.x == 0) s_task = atomicAdd(a.queue, 1);
+      __syncthreads();
+      const int got = uniform(s_task);
+      __syncthreads();
       if (got >= a.n_tasks) break;
       t = uniform(a.order[got]);
     } else {
       if (iter++) break;
-      t = uniform(blockIdx.x * wpb + wid);
+      t = uniform(blockIdx.x);
       if (t >= a.n_tasks) break;
     }
     const gc_task tk = a.tasks[t];
@@ -149,49 +190,43 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
       }
       double Ax = 0.0, Ay = 0.0, Az = 0.0;
 
-      // ---- node terms
-      for (int nb = 0; nb < tk.n_count; nb += kNodeTile) {
-        const int cnt = tk.n_count - nb < kNodeTile ? tk.n_count - nb : kNodeTile;
-        const int C = (cnt + S - 1) / S;
-        const int padded = S * C;
-        for (int e = lane; e < padded; e += 64) {
-          if (ORDER == 1) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (e < cnt) v = a.nodes[3 * a.node_idx[tk.n_first + nb + e]];
-            L[e] = v;
-          } else {
-            float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0, v2 = v0;
-            if (e < cnt) {
-              const float4* nd = a.nodes + 3 * a.node_idx[tk.n_first + nb + e];
-              v0 = nd[0];
-              v1 = nd[1];
-              v2 = nd[2];
-              v1 = make_float4(3.f * v1.x, 3.f * v1.y, 3.f * v1.z, 3.f * v1.w);
-              v2 = make_float4(3.f * v2.x, 3.f * v2.y, 1.5f * v2.z, 0.f);
+      // ---- node terms: this wave's nodes are list entries w, w + W, ...
+      {
+        const int nw = tk.n_count > wid ? (tk.n_count - wid + W - 1) / W : 0;
+        const int* nl = a.node_idx + tk.n_first + wid;
+        int idx_next = (64 < nw && 64 + lane < nw) ? nl[(64 + lane) * W] : -1;
+        NodeRegs<ORDER> cur = load_node<ORDER>(a.nodes, lane < nw ? nl[lane * W] : -1);
+        for (int nb = 0; nb < nw; nb += kNodeTile) {
+          const int cnt = nw - nb < kNodeTile ? nw - nb : kNodeTile;
+          const int C = (cnt + S - 1) / S;
+          const int padded = S * C;
+          store_node<ORDER>(L, lane, cur);  // entries >= cnt are zero records
+          for (int e = 64 + lane; e < padded; e += 64) store_node<ORDER>(L, e, load_node<ORDER>(a.nodes, -1));
+          // prefetch the next tile's records and the index of the one after
+          if (nb + kNodeTile < nw) {
+            cur = load_node<ORDER>(a.nodes, idx_next);
+            const int e2 = nb + 2 * kNodeTile + lane;
+            idx_next = e2 < nw ? nl[e2 * W] : -1;
+          }
+          wave_sync();
+          if (active) {
+            float ax = 0.f, ay = 0.f, az = 0.f;
+            if (ORDER == 1) {
+              // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
+              tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
+            } else {
+              tile_quads(L + 3 * sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
             }
-            L[3 * e] = v0;
-            L[3 * e + 1] = v1;
-            L[3 * e + 2] = v2;
+            Ax += ax; Ay += ay; Az += az;
           }
+          wave_sync();
         }
-        wave_sync();
-        if (active) {
-          float ax = 0.f, ay = 0.f, az = 0.f;
-          if (ORDER == 1) {
-            // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
-            tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-          } else {
-            tile_quads(L + 3 * sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-          }
-          Ax += ax; Ay += ay; Az += az;
-        }
-        wave_sync();
       }
 
       // ---- direct terms
       if (LISTS) {
         const int jb = a.joff[t], jn = a.joff[t + 1] - jb;
-        for (int ws = 0; ws < jn; ws += tile) {
+        for (int ws = wid * tile; ws < jn; ws += W * tile) {
           const int cnt = jn - ws < tile ? jn - ws : tile;
           const int C = (cnt + S - 1) / S;
           const int padded = S * C;
@@ -209,10 +244,13 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
           wave_sync();
         }
       } else {
-        for (int rg = 0; rg < tk.j_nranges; rg += 64) {
-          const int nr = tk.j_nranges - rg < 64 ? tk.j_nranges - rg : 64;
+        // this wave's ranges are entries w, w + W, ... of the task's range list
+        const int nrw = tk.j_nranges > wid ? (tk.j_nranges - wid + W - 1) / W : 0;
+        const int2* rl = a.ranges + tk.j_first + wid;
+        for (int rg = 0; rg < nrw; rg += 64) {
+          const int nr = nrw - rg < 64 ? nrw - rg : 64;
           int2 g = make_int2(0, 0);
-          if (lane < nr) g = a.ranges[tk.j_first + rg + lane];
+          if (lane < nr) g = rl[(rg + lane) * W];
           int total;
           const int o = wave_excl_scan(g.y, &total);
           total = uniform(total);
@@ -221,8 +259,8 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
             const int C = (cnt + S - 1) / S;
             const int padded = S * C;
             // each lane copies the part of its range inside the window [ws, ws + cnt)
-            int k0 = ws - o > 0 ? ws - o : 0;
-            int k1 = ws + cnt - o < g.y ? ws + cnt - o : g.y;
+            const int k0 = ws - o > 0 ? ws - o : 0;
+            const int k1 = ws + cnt - o < g.y ? ws + cnt - o : g.y;
             for (int k = k0; k < k1; ++k) L[o + k - ws] = a.rec[g.x + k];
             for (int e = cnt + lane; e < padded; e += 64) L[e] = make_float4(0.f, 0.f, 0.f, 0.f);
             wave_sync();
@@ -236,21 +274,34 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
         }
       }
 
-      // ---- reduce the S slices of each target, write once
+      // ---- reduce: slices within the wave, then the W waves, in a fixed order
       red[3 * lane] = Ax;
       red[3 * lane + 1] = Ay;
       red[3 * lane + 2] = Az;
       wave_sync();
+      double sx = 0.0, sy = 0.0, sz = 0.0;
       if (lane < icc) {
-        double sx = 0.0, sy = 0.0, sz = 0.0;
         for (int s = 0; s < S; ++s) {
           const double* q = red + 3 * (s * icc + lane);
           sx += q[0]; sy += q[1]; sz += q[2];
         }
-        a.acc[tk.i_begin + i0 + lane] =
-            make_float4((float)(a.G * sx), (float)(a.G * sy), (float)(a.G * sz), 0.f);
       }
       wave_sync();
+      if (lane < icc) {
+        red[3 * lane] = sx;
+        red[3 * lane + 1] = sy;
+        red[3 * lane + 2] = sz;
+      }
+      __syncthreads();
+      if (wid == 0 && lane < icc) {
+        double tx = 0.0, ty = 0.0, tz = 0.0;
+        for (int w = 0; w < W; ++w) {
+          const double* q = reinterpret_cast<const double*>(smem + w * per_wave + rec_cap) + 3 * lane;
+          tx += q[0]; ty += q[1]; tz += q[2];
+        }
+        a.acc[tk.i_begin + i0 + lane] = make_float4((float)(a.G * tx), (float)(a.G * ty), (float)(a.G * tz), 0.f);
+      }
+      __syncthreads();
     }
   }
 }
@@ -259,7 +310,7 @@ template <int ORDER, bool LISTS, bool PERSIST>
 hipError_t launch_one(const GravArgs& a, int wpb, int grid, hipStream_t s) {
   const int rec_cap = (a.tile + 64 > 3 * (kNodeTile + 64)) ? a.tile + 64 : 3 * (kNodeTile + 64);
   size_t lds = (size_t)wpb * (rec_cap + 96) * sizeof(float4);
-  if (!PERSIST) grid = (a.n_tasks + wpb - 1) / wpb;
+  if (!PERSIST) grid = a.n_tasks;
   if (grid < 1) return hipSuccess;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST>),

@@ -1,14 +1,29 @@
 // Reorganisation kernels (Sec. 3.2): residency lookup and marking, the sorted
 // union of accessed ids, slot assignment and staging of missing records, the
 // packing gather, and the list remaps (packed ranges, address lists, sorted
-// address lists).  All kernels are plain HBM/L2-bound passes: coalesced reads
-// of flag arrays, one 16-byte record per lane for the copies.
+// address lists).
+//
+// Four launches per reorganisation:
+//   k_mark   need[id] = 1 over every marked range; also clears the scan state;
+//   k_union  single-pass scan of need (decoupled look-back): pos[id], U, the
+//            missing list, and per union rank its pool slot or -(missing rank+1);
+//   k_free   single-pass scan of the free slots: the first #missing, ascending;
+//   k_apply  staging of missing records into their slots, the packing gather
+//            (or the source gather for redundant transfers), and the range or
+//            address-list remap, in one grid (block ranges split the roles).
+// A per-task sort follows for sorted address lists.  All of it is HBM/L2
+// bound: coalesced flag and index arrays, one 16-byte record per lane.
 #include <climits>
 
 #include "gc_internal.h"
 
 namespace gc {
 namespace {
+
+constexpr int kLBThreads = 256;
+constexpr int kLBItems = 4;
+constexpr int kLBBlock = kLBThreads * kLBItems;  // ids per block
+constexpr uint32_t kSpinLimit = 1u << 24;       // look-back bound: every wave exits
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -20,16 +35,15 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-// Exclusive scan of one value per thread across a block of kScanThreads; returns the
-// thread's exclusive prefix and writes the block total to *total.
+// Exclusive scan of one value per thread across the block; block total to *total.
 __device__ __forceinline__ int block_excl_scan(int v, int* sh_wave, int* total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
   int inc = wave_incl_scan(v);
   if (lane == 63) sh_wave[w] = inc;
   __syncthreads();
   int off = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < kScanThreads / 64; ++k) {
+  for (int k = 0; k < nw; ++k) {
     int s = sh_wave[k];
     off += (k < w) ? s : 0;
     tot += s;
@@ -37,6 +51,57 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh_wave, int* total) 
   __syncthreads();
   *total = tot;
   return off + inc - v;
+}
+
+// Look-back status words: bits 0-1 status (0 empty, 1 block aggregate, 2 inclusive prefix),
+// bits 2-32 first count, bits 33-63 second count (each < 2^31).
+__device__ __forceinline__ uint64_t lb_pack(uint32_t st, uint32_t a, uint32_t b) {
+  return (uint64_t)st | ((uint64_t)a << 2) | ((uint64_t)b << 33);
+}
+
+// A status word carries its own payload, so relaxed device-scope atomics suffice (no other
+// memory is published through it); acquire/release here would write back and invalidate caches.
+__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lb_load(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 of block `bid`: publish the block aggregate (a, b), look back for the exclusive
+// prefix, publish the inclusive prefix.  Sets err[0] if a predecessor never publishes
+// within the spin bound (not expected; keeps every wave finite).
+__device__ __forceinline__ void lb_resolve(uint64_t* flags, int bid, uint32_t a, uint32_t b, uint32_t* ea,
+                                           uint32_t* eb, int32_t* err) {
+  if (bid == 0) {
+    lb_store(flags, lb_pack(2, a, b));
+    *ea = 0;
+    *eb = 0;
+    return;
+  }
+  lb_store(flags + bid, lb_pack(1, a, b));
+  uint32_t xa = 0, xb = 0, spins = 0;
+  int j = bid - 1;
+  while (j >= 0) {
+    uint64_t w = lb_load(flags + j);
+    uint32_t st = (uint32_t)(w & 3u);
+    if (st == 0) {
+      if (++spins > kSpinLimit) {
+        err[0] = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    xa += (uint32_t)((w >> 2) & 0x7fffffffu);
+    xb += (uint32_t)(w >> 33);
+    if (st == 2) break;
+    --j;
+  }
+  lb_store(flags + bid, lb_pack(2, xa + a, xb + b));
+  *ea = xa;
+  *eb = xb;
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
@@ -47,9 +112,21 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-// One wavefront per range: need[id] = 1 for every id of the range.
-__global__ void k_mark(const int2* __restrict__ mark, int32_t n_mark, uint8_t* __restrict__ need) {
+// Pool reset: slot_of[0, n_ids) = -1 and occ[0, cap) = 0 in one grid.
+__global__ void k_pool_reset(int32_t* __restrict__ slot_of, int32_t n_ids, int32_t* __restrict__ occ, int32_t cap) {
+  const int64_t n = n_ids > cap ? n_ids : cap;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n_ids) slot_of[i] = -1;
+    if (i < cap) occ[i] = 0;
+  }
+}
+
+// One wavefront per range: need[id] = 1.  The grid also zeroes the scan state
+// (look-back words, block counters, result counts) for the launches that follow.
+__global__ void k_mark(const int2* __restrict__ mark, int32_t n_mark, uint8_t* __restrict__ need,
+                       int32_t* __restrict__ zero, int32_t n_zero) {
   const int lane = threadIdx.x & 63;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_zero; i += gridDim.x * blockDim.x) zero[i] = 0;
   const int waves = gridDim.x * (blockDim.x >> 6);
   for (int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < n_mark; r += waves) {
     int2 g = mark[r];
@@ -57,159 +134,194 @@ __global__ void k_mark(const int2* __restrict__ mark, int32_t n_mark, uint8_t* _
   }
 }
 
-// Per-thread flags of ids [16 t, 16 t + 16): bit k of the union mask and of the missing mask.
-struct IdFlags {
-  uint32_t u, m;
-};
-
-__device__ __forceinline__ IdFlags load_flags(const uint8_t* __restrict__ need, const int32_t* __restrict__ slot_of,
-                                              int32_t n, int64_t base, int with_missing) {
-  IdFlags f{0u, 0u};
-  if (base >= n) return f;
-  uint4 nb = *reinterpret_cast<const uint4*>(need + base);
-  uint32_t w[4] = {nb.x, nb.y, nb.z, nb.w};
+// Union of marked ids, position map and missing list.  counts[0] = |U|, counts[1] = #missing.
+// uslot[rank] = pool slot of a resident id, or -(missing rank + 1).
+__global__ void __launch_bounds__(kLBThreads) k_union(uint8_t* __restrict__ need, const int32_t* __restrict__ slot_of,
+                                                      int32_t n, int32_t with_missing, uint64_t* __restrict__ flags,
+                                                      int32_t* __restrict__ ctr, int32_t* __restrict__ pos,
+                                                      int32_t* __restrict__ U, int32_t* __restrict__ uslot,
+                                                      int32_t* __restrict__ missing, int32_t* __restrict__ counts) {
+  __shared__ int sh[kLBThreads / 64];
+  __shared__ int s_bid;
+  __shared__ uint32_t s_ex[2];
+  if (threadIdx.x == 0) s_bid = atomicAdd(ctr, 1);
+  __syncthreads();
+  const int bid = s_bid;
+  const int64_t base = (int64_t)bid * kLBBlock + (int64_t)threadIdx.x * kLBItems;
+  uint32_t fu = 0, fm = 0;
+  int sv[4] = {-1, -1, -1, -1};
+  if (base < n) {
+    uint32_t w = *reinterpret_cast<const uint32_t*>(need + base);
+    int4 s4 = *reinterpret_cast<const int4*>(slot_of + base);
+    sv[0] = s4.x; sv[1] = s4.y; sv[2] = s4.z; sv[3] = s4.w;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    uint32_t b = (w[k >> 2] >> (8 * (k & 3))) & 0xffu;
-    if (b && base + k < n) f.u |= 1u << k;
-  }
-  if (with_missing && f.u) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int4 s = *reinterpret_cast<const int4*>(slot_of + base + 4 * q);
-      int sv[4] = {s.x, s.y, s.z, s.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (((f.u >> (4 * q + k)) & 1u) && sv[k] < 0) f.m |= 1u << (4 * q + k);
+    for (int k = 0; k < 4; ++k) {
+      if (((w >> (8 * k)) & 0xffu) && base + k < n) {
+        fu |= 1u << k;
+        if (with_missing && sv[k] < 0) fm |= 1u << k;
+      }
     }
   }
-  return f;
-}
-
-__global__ void __launch_bounds__(kScanThreads) k_union_count(const uint8_t* __restrict__ need,
-                                                              const int32_t* __restrict__ slot_of, int32_t n,
-                                                              int32_t with_missing, int32_t* __restrict__ bsum) {
-  __shared__ int sh[kScanThreads / 64];
-  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  IdFlags f = load_flags(need, slot_of, n, base, with_missing);
   int tu, tm;
-  block_excl_scan(__popc(f.u), sh, &tu);
-  block_excl_scan(__popc(f.m), sh, &tm);
+  int ru = block_excl_scan(__popc(fu), sh, &tu);
+  int rm = block_excl_scan(__popc(fm), sh, &tm);
   if (threadIdx.x == 0) {
-    bsum[2 * blockIdx.x] = tu;
-    bsum[2 * blockIdx.x + 1] = tm;
-  }
-}
-
-// Exclusive scan, in place, of nb (a, b) pairs by one block; totals to out[0], out[1].
-__global__ void __launch_bounds__(kScanThreads) k_scan_pairs(int32_t* __restrict__ bsum, int32_t nb,
-                                                             int32_t* __restrict__ out) {
-  __shared__ int sh[kScanThreads / 64];
-  int carry_a = 0, carry_b = 0;
-  for (int32_t c = 0; c < nb; c += kScanThreads) {
-    int i = c + threadIdx.x;
-    int a = i < nb ? bsum[2 * i] : 0, b = i < nb ? bsum[2 * i + 1] : 0;
-    int ta, tb;
-    int ea = block_excl_scan(a, sh, &ta);
-    int eb = block_excl_scan(b, sh, &tb);
-    if (i < nb) {
-      bsum[2 * i] = carry_a + ea;
-      bsum[2 * i + 1] = carry_b + eb;
+    uint32_t ea, eb;
+    lb_resolve(flags, bid, (uint32_t)tu, (uint32_t)tm, &ea, &eb, counts + 4);
+    s_ex[0] = ea;
+    s_ex[1] = eb;
+    if (bid == (int)gridDim.x - 1) {
+      counts[0] = (int32_t)(ea + tu);
+      counts[1] = (int32_t)(eb + tm);
     }
-    carry_a += ta;
-    carry_b += tb;
   }
-  if (threadIdx.x == 0) {
-    out[0] = carry_a;
-    out[1] = carry_b;
-  }
-}
-
-__global__ void __launch_bounds__(kScanThreads) k_union_write(uint8_t* __restrict__ need,
-                                                              const int32_t* __restrict__ slot_of, int32_t n,
-                                                              int32_t with_missing, const int32_t* __restrict__ bsum,
-                                                              int32_t* __restrict__ pos, int32_t* __restrict__ U,
-                                                              int32_t* __restrict__ missing) {
-  __shared__ int sh[kScanThreads / 64];
-  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  IdFlags f = load_flags(need, slot_of, n, base, with_missing);
-  int tu, tm;
-  int ru = block_excl_scan(__popc(f.u), sh, &tu) + bsum[2 * blockIdx.x];
-  int rm = block_excl_scan(__popc(f.m), sh, &tm) + bsum[2 * blockIdx.x + 1];
+  __syncthreads();
+  ru += (int)s_ex[0];
+  rm += (int)s_ex[1];
   if (base >= n) return;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    int64_t id = base + k;
+  for (int k = 0; k < 4; ++k) {
+    const int64_t id = base + k;
     if (id >= n) break;
-    if ((f.u >> k) & 1u) {
+    if ((fu >> k) & 1u) {
       pos[id] = ru;
-      U[ru++] = (int32_t)id;
-      if ((f.m >> k) & 1u) missing[rm++] = (int32_t)id;
+      U[ru] = (int32_t)id;
+      if ((fm >> k) & 1u) {
+        uslot[ru] = -(rm + 1);
+        missing[rm++] = (int32_t)id;
+      } else {
+        uslot[ru] = sv[k];
+      }
+      ++ru;
     } else {
       pos[id] = -1;
     }
   }
-  // leave the flags cleared for the next reorganisation
-  *reinterpret_cast<uint4*>(need + base) = make_uint4(0u, 0u, 0u, 0u);
+  *reinterpret_cast<uint32_t*>(need + base) = 0u;  // flags left cleared for the next reorganisation
 }
 
-// Free slots: flag = occ[s] == 0; the first counts[1] free slots, ascending, go to free_list.
-__device__ __forceinline__ uint32_t load_free(const int32_t* __restrict__ occ, int32_t cap, int64_t base) {
+// Free slots ascending: free_list[r] for r < #missing; counts[2] = number of free slots.
+__global__ void __launch_bounds__(kLBThreads) k_free(const int32_t* __restrict__ occ, int32_t cap,
+                                                     uint64_t* __restrict__ flags, int32_t* __restrict__ ctr,
+                                                     int32_t* __restrict__ free_list, int32_t* __restrict__ counts) {
+  __shared__ int sh[kLBThreads / 64];
+  __shared__ int s_bid;
+  __shared__ uint32_t s_ex;
+  const int need = counts[1];
+  if (need == 0) return;  // uniform: nothing to stage
+  if (threadIdx.x == 0) s_bid = atomicAdd(ctr, 1);
+  __syncthreads();
+  const int bid = s_bid;
+  const int64_t base = (int64_t)bid * kLBBlock + (int64_t)threadIdx.x * kLBItems;
   uint32_t f = 0;
-  if (base >= cap) return f;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int4 o = *reinterpret_cast<const int4*>(occ + base + 4 * q);
+  if (base < cap) {
+    int4 o = *reinterpret_cast<const int4*>(occ + base);
     int ov[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (ov[k] == 0 && base + 4 * q + k < cap) f |= 1u << (4 * q + k);
+      if (ov[k] == 0 && base + k < cap) f |= 1u << k;
   }
-  return f;
-}
-
-__global__ void __launch_bounds__(kScanThreads) k_free_count(const int32_t* __restrict__ occ, int32_t cap,
-                                                             const int32_t* __restrict__ counts,
-                                                             int32_t* __restrict__ bsum) {
-  __shared__ int sh[kScanThreads / 64];
-  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  uint32_t f = counts[1] > 0 ? load_free(occ, cap, base) : 0u;
   int t;
-  block_excl_scan(__popc(f), sh, &t);
+  int r = block_excl_scan(__popc(f), sh, &t);
   if (threadIdx.x == 0) {
-    bsum[2 * blockIdx.x] = t;
-    bsum[2 * blockIdx.x + 1] = 0;
+    uint32_t ea, eb;
+    lb_resolve(flags, bid, (uint32_t)t, 0u, &ea, &eb, counts + 4);
+    s_ex = ea;
+    if (bid == (int)gridDim.x - 1) counts[2] = (int32_t)(ea + t);
   }
-}
-
-__global__ void __launch_bounds__(kScanThreads) k_free_write(const int32_t* __restrict__ occ, int32_t cap,
-                                                             const int32_t* __restrict__ counts,
-                                                             const int32_t* __restrict__ bsum,
-                                                             int32_t* __restrict__ free_list) {
-  __shared__ int sh[kScanThreads / 64];
-  const int need = counts[1];
-  if (need == 0 || bsum[2 * blockIdx.x] >= need) return;  // uniform per block
-  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  uint32_t f = load_free(occ, cap, base);
-  int t;
-  int r = block_excl_scan(__popc(f), sh, &t) + bsum[2 * blockIdx.x];
-  for (int k = 0; k < 16 && r < need; ++k)
+  __syncthreads();
+  r += (int)s_ex;
+  for (int k = 0; k < 4 && r < need; ++k)
     if ((f >> k) & 1u) free_list[r++] = (int32_t)(base + k);
 }
 
-// Stage the k-th missing record into the k-th free slot.  If the pool has fewer free
-// slots than missing records (counts[1] > counts[2]) only the first counts[2] are
-// staged and counts[3] is set; the others stay non-resident.
-__global__ void k_stage(const int32_t* __restrict__ missing, const int32_t* __restrict__ free_list,
-                        int32_t* __restrict__ counts, const float4* __restrict__ src, float4* __restrict__ pool,
-                        int32_t* __restrict__ slot_of, int32_t* __restrict__ occ) {
-  const int nm = counts[1] < counts[2] ? counts[1] : counts[2];
-  if (blockIdx.x == 0 && threadIdx.x == 0 && counts[1] > counts[2]) counts[3] = 1;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nm; k += gridDim.x * blockDim.x) {
-    int id = missing[k], s = free_list[k];
-    pool[s] = src[id];
-    slot_of[id] = s;
-    occ[s] = 1;
+struct ApplyArgs {
+  int32_t mode;
+  const int32_t* counts;
+  const int32_t* U;
+  const int32_t* uslot;
+  const int32_t* free_list;
+  const int32_t* pos;
+  const float4* src;
+  float4* pool;
+  int32_t* slot_of;
+  int32_t* occ;
+  float4* packed;
+  const gc_task* tasks;
+  int32_t n_tasks;
+  const int2* ranges;
+  int32_t n_ranges;
+  int2* pranges;
+  int32_t* pibeg;
+  const int32_t* ioff;
+  const int32_t* joff;
+  int32_t* ilist;
+  int32_t* jlist;
+  int32_t blocks_a;  // blocks [0, blocks_a) stage and pack; the rest remap
+};
+
+// Pool slot of union rank p after staging (0 after a reported capacity overflow).
+__device__ __forceinline__ int32_t slot_of_rank(const ApplyArgs& a, int32_t p, int32_t nfree) {
+  const int32_t v = a.uslot[p];
+  if (v >= 0) return v;
+  const int32_t m = -v - 1;
+  return m < nfree ? a.free_list[m] : 0;
+}
+
+__global__ void __launch_bounds__(256) k_apply(ApplyArgs a) {
+  const int32_t nu = a.counts[0];
+  const int32_t nfree = a.counts[1] < a.counts[2] ? a.counts[1] : a.counts[2];
+  if ((int)blockIdx.x < a.blocks_a) {
+    const int stride = a.blocks_a * blockDim.x;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nu; k += stride) {
+      const int32_t id = a.U[k];
+      if (a.mode == GC_REORG_REDUNDANT) {
+        a.packed[k] = a.src[id];
+        continue;
+      }
+      const int32_t v = a.uslot[k];
+      if (v >= 0) {
+        if (a.mode == GC_REORG_PACK) a.packed[k] = a.pool[v];
+      } else {
+        const int32_t m = -v - 1;
+        const float4 r = a.src[id];
+        if (m < nfree) {
+          const int32_t s = a.free_list[m];
+          a.pool[s] = r;
+          a.slot_of[id] = s;
+          a.occ[s] = 1;
+        }
+        if (a.mode == GC_REORG_PACK) a.packed[k] = r;
+      }
+    }
+    return;
+  }
+  const int b = blockIdx.x - a.blocks_a, nb = gridDim.x - a.blocks_a;
+  if (a.mode == GC_REORG_PACK || a.mode == GC_REORG_REDUNDANT) {
+    for (int r = b * blockDim.x + threadIdx.x; r < a.n_ranges; r += nb * blockDim.x) {
+      int2 g = a.ranges[r];
+      a.pranges[r] = make_int2(g.y > 0 ? a.pos[g.x] : 0, g.y);
+    }
+    for (int t = b * blockDim.x + threadIdx.x; t < a.n_tasks; t += nb * blockDim.x) {
+      const gc_task& tk = a.tasks[t];
+      a.pibeg[t] = tk.i_count > 0 ? a.pos[tk.i_begin] : 0;
+    }
+    return;
+  }
+  // address lists: one wavefront per task; slots come from the union rank, so no
+  // ordering with the staging writes above is needed
+  const int lane = threadIdx.x & 63;
+  const int waves = nb * (blockDim.x >> 6);
+  for (int t = b * (blockDim.x >> 6) + (threadIdx.x >> 6); t < a.n_tasks; t += waves) {
+    const gc_task tk = a.tasks[t];
+    const int io = a.ioff[t];
+    for (int k = lane; k < tk.i_count; k += 64) a.ilist[io + k] = slot_of_rank(a, a.pos[tk.i_begin + k], nfree);
+    int o = a.joff[t];
+    for (int r = 0; r < tk.j_nranges; ++r) {
+      const int2 g = a.ranges[tk.j_first + r];
+      for (int k = lane; k < g.y; k += 64) a.jlist[o + k] = slot_of_rank(a, a.pos[g.x + k], nfree);
+      o += g.y;
+    }
   }
 }
 
@@ -221,57 +333,6 @@ __global__ void k_place(const int32_t* __restrict__ ids, const int32_t* __restri
     pool[s] = src[id];
     slot_of[id] = s;
     occ[s] = 1;
-  }
-}
-
-__global__ void k_gather(const int32_t* __restrict__ U, const int32_t* __restrict__ counts,
-                         const int32_t* __restrict__ slot_of, const float4* __restrict__ pool,
-                         float4* __restrict__ packed) {
-  const int nu = counts[0];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nu; k += gridDim.x * blockDim.x) {
-    int s = slot_of[U[k]];  // < 0 only after a reported capacity overflow
-    packed[k] = s >= 0 ? pool[s] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-}
-
-__global__ void k_gather_src(const int32_t* __restrict__ U, const int32_t* __restrict__ counts,
-                             const float4* __restrict__ src, float4* __restrict__ packed) {
-  const int nu = counts[0];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nu; k += gridDim.x * blockDim.x) packed[k] = src[U[k]];
-}
-
-__global__ void k_remap_ranges(const int2* __restrict__ ranges, int32_t n_ranges, const gc_task* __restrict__ tasks,
-                               int32_t n_tasks, const int32_t* __restrict__ pos, int2* __restrict__ pranges,
-                               int32_t* __restrict__ pibeg) {
-  const int stride = gridDim.x * blockDim.x;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_ranges; r += stride) {
-    int2 g = ranges[r];
-    pranges[r] = make_int2(g.y > 0 ? pos[g.x] : 0, g.y);
-  }
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tasks; t += stride) {
-    const gc_task& tk = tasks[t];
-    pibeg[t] = tk.i_count > 0 ? pos[tk.i_begin] : 0;
-  }
-}
-
-// One wavefront per task: pool slots of its targets and of its direct ids in list order.
-__global__ void k_remap_lists(const gc_task* __restrict__ tasks, int32_t n_tasks, const int2* __restrict__ ranges,
-                              const int32_t* __restrict__ ioff, const int32_t* __restrict__ joff,
-                              const int32_t* __restrict__ slot_of, int32_t* __restrict__ ilist,
-                              int32_t* __restrict__ jlist) {
-  const int lane = threadIdx.x & 63;
-  const int waves = gridDim.x * (blockDim.x >> 6);
-  for (int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < n_tasks; t += waves) {
-    const gc_task tk = tasks[t];
-    int io = ioff[t];
-    // a slot < 0 exists only after a reported capacity overflow; keep every address valid
-    for (int k = lane; k < tk.i_count; k += 64) ilist[io + k] = max(slot_of[tk.i_begin + k], 0);
-    int o = joff[t];
-    for (int r = 0; r < tk.j_nranges; ++r) {
-      int2 g = ranges[tk.j_first + r];
-      for (int k = lane; k < g.y; k += 64) jlist[o + k] = max(slot_of[g.x + k], 0);
-      o += g.y;
-    }
   }
 }
 
@@ -322,6 +383,8 @@ inline int grid_for(int64_t n, int per_block, int cap = 65536) {
 
 }  // namespace
 
+int lb_blocks(int32_t n) { return (int)((n + kLBBlock - 1) / kLBBlock) > 0 ? (int)((n + kLBBlock - 1) / kLBBlock) : 1; }
+
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
@@ -334,38 +397,53 @@ hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_mark(const int2* mark, int32_t n_mark, uint8_t* need, hipStream_t s) {
-  if (n_mark <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mark, dim3(grid_for(n_mark, 4, 16384)), dim3(256), 0, s, mark, n_mark, need);
+hipError_t launch_pool_reset(int32_t* slot_of, int32_t n_ids, int32_t* occ, int32_t cap, hipStream_t s) {
+  int64_t n = n_ids > cap ? n_ids : cap;
+  hipLaunchKernelGGL(k_pool_reset, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, slot_of, n_ids, occ, cap);
   return hipGetLastError();
 }
 
-hipError_t launch_union_scan(const uint8_t* need, const int32_t* slot_of, int32_t n, int32_t with_missing,
-                             int32_t* bsum, int32_t* pos, int32_t* U, int32_t* missing, int32_t* counts,
-                             hipStream_t s) {
-  int nb = (n + kScanBlock - 1) / kScanBlock;
-  if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_union_count, dim3(nb), dim3(kScanThreads), 0, s, need, slot_of, n, with_missing, bsum);
-  hipLaunchKernelGGL(k_scan_pairs, dim3(1), dim3(kScanThreads), 0, s, bsum, nb, counts);
-  hipLaunchKernelGGL(k_union_write, dim3(nb), dim3(kScanThreads), 0, s, const_cast<uint8_t*>(need), slot_of, n,
-                     with_missing, bsum, pos, U, missing);
+hipError_t launch_mark(const int2* mark, int32_t n_mark, uint8_t* need, int32_t* zero, int32_t n_zero, hipStream_t s) {
+  int g = grid_for(n_mark > 0 ? n_mark : 1, 4, 16384);
+  int gz = grid_for(n_zero, 256, 16384);
+  hipLaunchKernelGGL(k_mark, dim3(g > gz ? g : gz), dim3(256), 0, s, mark, n_mark, need, zero, n_zero);
   return hipGetLastError();
 }
 
-hipError_t launch_free_scan(const int32_t* occ, int32_t cap, const int32_t* counts, int32_t* bsum,
-                            int32_t* free_list, int32_t* free_count, hipStream_t s) {
-  int nb = (cap + kScanBlock - 1) / kScanBlock;
-  if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_free_count, dim3(nb), dim3(kScanThreads), 0, s, occ, cap, counts, bsum);
-  hipLaunchKernelGGL(k_scan_pairs, dim3(1), dim3(kScanThreads), 0, s, bsum, nb, free_count);
-  hipLaunchKernelGGL(k_free_write, dim3(nb), dim3(kScanThreads), 0, s, occ, cap, counts, bsum, free_list);
+hipError_t launch_union(uint8_t* need, const int32_t* slot_of, int32_t n, int32_t with_missing, uint64_t* flags,
+                        int32_t* ctr, int32_t* pos, int32_t* U, int32_t* uslot, int32_t* missing, int32_t* counts,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_union, dim3(lb_blocks(n)), dim3(kLBThreads), 0, s, need, slot_of, n, with_missing, flags, ctr,
+                     pos, U, uslot, missing, counts);
   return hipGetLastError();
 }
 
-hipError_t launch_stage(const int32_t* missing, const int32_t* free_list, int32_t* counts, int32_t bound,
-                        const float4* src, float4* pool, int32_t* slot_of, int32_t* occ, hipStream_t s) {
-  hipLaunchKernelGGL(k_stage, dim3(grid_for(bound, 256, 4096)), dim3(256), 0, s, missing, free_list, counts, src, pool,
-                     slot_of, occ);
+hipError_t launch_free(const int32_t* occ, int32_t cap, uint64_t* flags, int32_t* ctr, int32_t* free_list,
+                       int32_t* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_free, dim3(lb_blocks(cap)), dim3(kLBThreads), 0, s, occ, cap, flags, ctr, free_list, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(int32_t mode, const int32_t* counts, int32_t bound, const int32_t* U, const int32_t* uslot,
+                        const int32_t* free_list, const int32_t* pos, const float4* src, float4* pool, int32_t* slot_of,
+                        int32_t* occ, float4* packed, const gc_task* tasks, int32_t n_tasks, const int2* ranges,
+                        int32_t n_ranges, int2* pranges, int32_t* pibeg, const int32_t* ioff, const int32_t* joff,
+                        int32_t* ilist, int32_t* jlist, hipStream_t s) {
+  ApplyArgs a{mode, counts, U, uslot, free_list, pos, src, pool, slot_of, occ, packed, tasks, n_tasks, ranges,
+              n_ranges, pranges, pibeg, ioff, joff, ilist, jlist, 0};
+  a.blocks_a = grid_for(bound, 256, 4096);
+  int blocks_b;
+  if (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT)
+    blocks_b = grid_for(n_ranges > n_tasks ? n_ranges : n_tasks, 256, 8192);
+  else
+    blocks_b = grid_for(n_tasks, 4, 16384);
+  hipLaunchKernelGGL(k_apply, dim3(a.blocks_a + blocks_b), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_lists(int32_t n_tasks, const int32_t* joff, int32_t* jlist, hipStream_t s) {
+  if (n_tasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_lists, dim3(grid_for(n_tasks, 1, 8192)), dim3(256), 0, s, n_tasks, joff, jlist);
   return hipGetLastError();
 }
 
@@ -373,37 +451,6 @@ hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, con
                         int32_t* slot_of, int32_t* occ, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_place, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ids, slots, n, src, pool, slot_of, occ);
-  return hipGetLastError();
-}
-
-hipError_t launch_gather(const int32_t* U, const int32_t* counts, int32_t bound, const int32_t* slot_of,
-                         const float4* pool, float4* packed, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather, dim3(grid_for(bound, 256, 8192)), dim3(256), 0, s, U, counts, slot_of, pool, packed);
-  return hipGetLastError();
-}
-
-hipError_t launch_gather_src(const int32_t* U, const int32_t* counts, int32_t bound, const float4* src,
-                             float4* packed, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_src, dim3(grid_for(bound, 256, 8192)), dim3(256), 0, s, U, counts, src, packed);
-  return hipGetLastError();
-}
-
-hipError_t launch_remap_ranges(const int2* ranges, int32_t n_ranges, const gc_task* tasks, int32_t n_tasks,
-                               const int32_t* pos, int2* pranges, int32_t* pibeg, hipStream_t s) {
-  int n = n_ranges > n_tasks ? n_ranges : n_tasks;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_remap_ranges, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, ranges, n_ranges, tasks, n_tasks,
-                     pos, pranges, pibeg);
-  return hipGetLastError();
-}
-
-hipError_t launch_remap_lists(const gc_task* tasks, int32_t n_tasks, const int2* ranges, const int32_t* ioff,
-                              const int32_t* joff, const int32_t* slot_of, int32_t* ilist, int32_t* jlist,
-                              int32_t sorted, hipStream_t s) {
-  if (n_tasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_remap_lists, dim3(grid_for(n_tasks, 4, 16384)), dim3(256), 0, s, tasks, n_tasks, ranges, ioff,
-                     joff, slot_of, ilist, jlist);
-  if (sorted) hipLaunchKernelGGL(k_sort_lists, dim3(grid_for(n_tasks, 1, 8192)), dim3(256), 0, s, n_tasks, joff, jlist);
   return hipGetLastError();
 }
 

@@ -103,7 +103,9 @@ struct gc_batch_ {
   DevBuf d_tasks, d_ranges, d_nodes, d_mark, d_ioff, d_joff, d_order;
   int32_t n_mark = 0, bound_u = 0, max_direct = 0;
   // reorganisation buffers
-  DevBuf need, pos, U, missing, free_list, bsum, counts, packed, pranges, pibeg, ilist, jlist, queue;
+  DevBuf need, pos, U, uslot, missing, free_list, state, packed, pranges, pibeg, ilist, jlist, queue;
+  DevBuf gnode, force;     // adjoint scratch: node gradients, recomputed LJ forces
+  int32_t state_ints = 0;  // counts (8) + counters (8) + look-back words of both scans
   // state of the last reorganisation
   int32_t mode = -1;
   gc_pool pool = nullptr;
@@ -234,9 +236,7 @@ extern "C" gc_status gc_pool_place(gc_pool pool, const int32_t* ids_dev, const i
 }
 
 static hipError_t pool_reset_async(gc_pool pool, hipStream_t s) {
-  hipError_t e = launch_fill_i32(pool->slot_of.as<int32_t>(), -1, pool->n_ids, s);
-  if (e == hipSuccess) e = launch_fill_i32(pool->occ.as<int32_t>(), 0, pool->cap, s);
-  return e;
+  return launch_pool_reset(pool->slot_of.as<int32_t>(), pool->n_ids, pool->occ.as<int32_t>(), pool->cap, s);
 }
 
 extern "C" gc_status gc_pool_reset(gc_pool pool, void* stream) {
@@ -281,8 +281,8 @@ extern "C" gc_status gc_batch_destroy(gc_batch b) {
   if (!b) return GC_E_INVAL;
   (void)hipDeviceSynchronize();
   for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_mark, &b->d_ioff, &b->d_joff, &b->d_order, &b->need,
-                    &b->pos, &b->U, &b->missing, &b->free_list, &b->bsum, &b->counts, &b->packed, &b->pranges,
-                    &b->pibeg, &b->ilist, &b->jlist, &b->queue})
+                    &b->pos, &b->U, &b->uslot, &b->missing, &b->free_list, &b->state, &b->packed, &b->pranges,
+                    &b->pibeg, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force})
     d->release();
   delete b;
   return GC_OK;
@@ -437,17 +437,21 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   return GC_OK;
 }
 
+// Scan state layout (int32 units): [0, 8) counts, [8, 16) block counters,
+// [16, 16 + 2 nbU) union look-back words, then 2 nbF free-scan words.
+static int32_t* counts_of(gc_batch b) { return b->state.as<int32_t>(); }
+
 static hipError_t ensure_reorg_buffers(gc_batch b, gc_pool p) {
   const int64_t nid = pad_to(b->n_ids, kScanBlock);
   const int64_t bound = std::max<int32_t>(b->bound_u, 1);
-  const int64_t nb = std::max<int64_t>(pad_to(b->n_ids, kScanBlock), pad_to(p->cap, kScanBlock)) / kScanBlock;
   hipError_t e = b->need.ensure((size_t)nid);
   if (e == hipSuccess) e = b->pos.ensure(sizeof(int32_t) * (size_t)nid);
   if (e == hipSuccess) e = b->U.ensure(sizeof(int32_t) * (size_t)bound);
+  if (e == hipSuccess) e = b->uslot.ensure(sizeof(int32_t) * (size_t)bound);
   if (e == hipSuccess) e = b->missing.ensure(sizeof(int32_t) * (size_t)bound);
   if (e == hipSuccess) e = b->free_list.ensure(sizeof(int32_t) * (size_t)bound);
-  if (e == hipSuccess) e = b->bsum.ensure(sizeof(int32_t) * 2 * (size_t)nb);
-  if (e == hipSuccess) e = b->counts.ensure(sizeof(int32_t) * 8);
+  b->state_ints = 16 + 2 * lb_blocks(b->n_ids) + 2 * lb_blocks(p->cap);
+  if (e == hipSuccess) e = b->state.ensure(sizeof(int32_t) * (size_t)b->state_ints);
   if (e == hipSuccess) e = b->packed.ensure(sizeof(float4) * (size_t)bound);
   if (e == hipSuccess) e = b->pranges.ensure(sizeof(int32_t) * std::max<size_t>(b->ranges.size(), 2));
   if (e == hipSuccess) e = b->pibeg.ensure(sizeof(int32_t) * std::max<size_t>(b->tasks.size(), 1));
@@ -465,42 +469,31 @@ static gc_status reorganize_lookup(gc_batch b, gc_pool p, int32_t mode, hipStrea
   if (e != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_reorganize: %s", hipGetErrorString(e));
   if (b->need.bytes != need_before) *needs_need_clear = true;
   if (*needs_need_clear) GC_HIP(c, launch_fill_i32(b->need.as<int32_t>(), 0, (int64_t)(b->need.bytes / 4), s));
-  int32_t* counts = b->counts.as<int32_t>();
-  GC_HIP(c, launch_fill_i32(counts, 0, 8, s));
-  GC_HIP(c, launch_mark(b->d_mark.as<int2>(), b->n_mark, b->need.as<uint8_t>(), s));
+  int32_t* st = b->state.as<int32_t>();
+  const int nbu = lb_blocks(b->n_ids);
+  uint64_t* flags_u = reinterpret_cast<uint64_t*>(st + 16);
+  uint64_t* flags_f = reinterpret_cast<uint64_t*>(st + 16 + 2 * nbu);
+  GC_HIP(c, launch_mark(b->d_mark.as<int2>(), b->n_mark, b->need.as<uint8_t>(), st, b->state_ints, s));
   const bool reuse = (mode != GC_REORG_REDUNDANT);
-  GC_HIP(c, launch_union_scan(b->need.as<uint8_t>(), p->slot_of.as<int32_t>(), b->n_ids, reuse ? 1 : 0,
-                              b->bsum.as<int32_t>(), b->pos.as<int32_t>(), b->U.as<int32_t>(),
-                              b->missing.as<int32_t>(), counts, s));
-  if (reuse)
-    GC_HIP(c, launch_free_scan(p->occ.as<int32_t>(), p->cap, counts, b->bsum.as<int32_t>(), b->free_list.as<int32_t>(),
-                               counts + 2, s));
+  GC_HIP(c, launch_union(b->need.as<uint8_t>(), p->slot_of.as<int32_t>(), b->n_ids, reuse ? 1 : 0, flags_u, st + 8,
+                         b->pos.as<int32_t>(), b->U.as<int32_t>(), b->uslot.as<int32_t>(), b->missing.as<int32_t>(),
+                         st, s));
+  if (reuse) GC_HIP(c, launch_free(p->occ.as<int32_t>(), p->cap, flags_f, st + 9, b->free_list.as<int32_t>(), st, s));
   return GC_OK;
 }
 
-// Phase B: staging of missing records into the pool, then the packing gather or the list remaps.
+// Phase B: staging of missing records into the pool, the packing gather or the list remaps.
 static gc_status reorganize_apply(gc_batch b, gc_pool p, int32_t mode, hipStream_t s) {
   gc_ctx c = b->ctx;
   const int32_t T = (int32_t)b->tasks.size(), R = (int32_t)(b->ranges.size() / 2);
-  int32_t* counts = b->counts.as<int32_t>();
-  if (mode != GC_REORG_REDUNDANT)
-    GC_HIP(c, launch_stage(b->missing.as<int32_t>(), b->free_list.as<int32_t>(), counts, b->bound_u, p->src,
-                           p->rec.as<float4>(), p->slot_of.as<int32_t>(), p->occ.as<int32_t>(), s));
-  if (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT) {
-    if (mode == GC_REORG_PACK)
-      GC_HIP(c, launch_gather(b->U.as<int32_t>(), counts, b->bound_u, p->slot_of.as<int32_t>(), p->rec.as<float4>(),
-                              b->packed.as<float4>(), s));
-    else
-      GC_HIP(c, launch_gather_src(b->U.as<int32_t>(), counts, b->bound_u, p->src, b->packed.as<float4>(), s));
-    GC_HIP(c, launch_remap_ranges(b->d_ranges.as<int2>(), R, b->d_tasks.as<gc_task>(), T, b->pos.as<int32_t>(),
-                                  b->pranges.as<int2>(), b->pibeg.as<int32_t>(), s));
-    b->rec = b->packed.as<float4>();
-  } else {
-    GC_HIP(c, launch_remap_lists(b->d_tasks.as<gc_task>(), T, b->d_ranges.as<int2>(), b->d_ioff.as<int32_t>(),
-                                 b->d_joff.as<int32_t>(), p->slot_of.as<int32_t>(), b->ilist.as<int32_t>(),
-                                 b->jlist.as<int32_t>(), mode == GC_REORG_SORTED ? 1 : 0, s));
-    b->rec = p->rec.as<float4>();
-  }
+  GC_HIP(c, launch_apply(mode, counts_of(b), b->bound_u, b->U.as<int32_t>(), b->uslot.as<int32_t>(),
+                         b->free_list.as<int32_t>(), b->pos.as<int32_t>(), p->src, p->rec.as<float4>(),
+                         p->slot_of.as<int32_t>(), p->occ.as<int32_t>(), b->packed.as<float4>(),
+                         b->d_tasks.as<gc_task>(), T, b->d_ranges.as<int2>(), R, b->pranges.as<int2>(),
+                         b->pibeg.as<int32_t>(), b->d_ioff.as<int32_t>(), b->d_joff.as<int32_t>(),
+                         b->ilist.as<int32_t>(), b->jlist.as<int32_t>(), s));
+  if (mode == GC_REORG_SORTED) GC_HIP(c, launch_sort_lists(T, b->d_joff.as<int32_t>(), b->jlist.as<int32_t>(), s));
+  b->rec = (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT) ? b->packed.as<float4>() : p->rec.as<float4>();
   return GC_OK;
 }
 
@@ -535,8 +528,9 @@ extern "C" gc_status gc_reorganize(gc_batch b, gc_pool p, int32_t mode, int32_t 
   if (st != GC_OK) return st;
   if (check_capacity && mode != GC_REORG_REDUNDANT) {
     int32_t h[8];
-    GC_HIP(c, hipMemcpyAsync(h, b->counts.p, sizeof h, hipMemcpyDeviceToHost, s));
+    GC_HIP(c, hipMemcpyAsync(h, b->state.p, sizeof h, hipMemcpyDeviceToHost, s));
     GC_HIP(c, hipStreamSynchronize(s));
+    if (h[4]) return set_err(c, GC_E_HIP, "gc_reorganize: a scan block did not complete");
     if (h[1] > h[2])
       return set_err(c, GC_E_FULL, "gc_reorganize: %d records missing but only %d pool slots free", h[1], h[2]);
   }
@@ -556,8 +550,11 @@ extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int3
   if (b->mode < 0 || b->mode == GC_REORG_NONE) return set_err(c, GC_E_STATE, "gc_batch_maps: no reorganisation");
   hipStream_t s = S(stream);
   int32_t h[8];
-  GC_HIP(c, hipMemcpyAsync(h, b->counts.p, sizeof h, hipMemcpyDeviceToHost, s));
+  GC_HIP(c, hipMemcpyAsync(h, b->state.p, sizeof h, hipMemcpyDeviceToHost, s));
   GC_HIP(c, hipStreamSynchronize(s));
+  if (h[4]) return set_err(c, GC_E_HIP, "gc_batch_maps: a scan block did not complete");
+  if (b->mode != GC_REORG_REDUNDANT && h[1] > h[2])
+    return set_err(c, GC_E_FULL, "gc_batch_maps: the last reorganisation overflowed the pool");
   const int32_t nu = h[0], nm = (b->mode == GC_REORG_REDUNDANT) ? h[0] : h[1];
   if (counts) {
     counts[0] = nu;
@@ -697,7 +694,74 @@ extern "C" gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_
 
 extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const float* nodes_dev,
                                  const int32_t* node_range_dev, int32_t n_nodes, const float* cot_dev, float* gpos_dev,
-                                 float* gmass_dev, float* gparam_dev, void* stream);
+                                 float* gmass_dev, float* gparam_dev, void* stream) {
+  if (!b) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  int tile, wpb;
+  gc_status st = check_prm(b, prm, &tile, &wpb);
+  if (st != GC_OK) return st;
+  if (b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_backward: batch not reorganised");
+  if (b->mode == GC_REORG_INDIRECT || b->mode == GC_REORG_SORTED)
+    return set_err(c, GC_E_UNSUPPORTED, "gc_backward supports PACK, REDUNDANT and NONE reorganisations");
+  if (!b->pool->src_device) return set_err(c, GC_E_INVAL, "gc_backward needs a device-resident source");
+  if (!cot_dev || !gpos_dev || !gmass_dev) return set_err(c, GC_E_INVAL, "gc_backward: NULL cotangent or gradient");
+  hipStream_t s = S(stream);
+  const int32_t T = (int32_t)b->tasks.size();
+  const bool packed = (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT);
+  if (b->kind == GC_KIND_GRAV) {
+    if (prm->kind != GC_FORCE_GRAV_MONO)
+      return set_err(c, GC_E_UNSUPPORTED, "gc_backward: gravity adjoint implements the monopole form");
+    if (!b->nodes.empty() && (!nodes_dev || !node_range_dev || n_nodes <= 0))
+      return set_err(c, GC_E_INVAL, "gc_backward: node table and node ranges needed");
+    if (n_nodes > 0 && b->gnode.ensure(sizeof(float) * 4 * (size_t)n_nodes) != hipSuccess)
+      return set_err(c, GC_E_NOMEM, "gc_backward: node gradients");
+    if (n_nodes > 0) GC_HIP(c, launch_fill_f32(b->gnode.as<float>(), 0.f, 4 * (int64_t)n_nodes, s));
+    GravAdjArgs a{};
+    a.f.tasks = b->d_tasks.as<gc_task>();
+    a.f.n_tasks = T;
+    a.f.ranges = packed ? b->pranges.as<int2>() : b->d_ranges.as<int2>();
+    a.f.ibeg = packed ? b->pibeg.as<int32_t>() : nullptr;
+    a.f.node_idx = b->d_nodes.as<int32_t>();
+    a.f.nodes = reinterpret_cast<const float4*>(nodes_dev);
+    a.f.rec = b->rec;
+    a.f.G = prm->G;
+    a.f.eps2 = prm->soft_eps * prm->soft_eps;
+    a.cot = reinterpret_cast<const float4*>(cot_dev);
+    a.gpos = reinterpret_cast<float4*>(gpos_dev);
+    a.gmass = gmass_dev;
+    a.src_id = packed ? b->U.as<int32_t>() : nullptr;
+    a.gnode = b->gnode.as<float>();
+    GC_HIP(c, launch_grav_adjoint(packed, a, 4, s));
+    if (n_nodes > 0)
+      GC_HIP(c, launch_node_chain(node_range_dev, n_nodes, reinterpret_cast<const float4*>(nodes_dev),
+                                  b->gnode.as<float>(), b->pool->src, a.gpos, gmass_dev, s));
+    return GC_OK;
+  }
+  if (!gparam_dev) return set_err(c, GC_E_INVAL, "gc_backward: Lennard-Jones needs gparam");
+  if (b->force.ensure(sizeof(float4) * (size_t)b->n_ids) != hipSuccess)
+    return set_err(c, GC_E_NOMEM, "gc_backward: force buffer");
+  GC_HIP(c, launch_fill_f32(b->force.as<float>(), 0.f, 4 * (int64_t)b->n_ids, s));
+  LJAdjArgs a{};
+  a.f.tasks = b->d_tasks.as<gc_task>();
+  a.f.n_tasks = T;
+  a.f.ranges = packed ? b->pranges.as<int2>() : b->d_ranges.as<int2>();
+  a.f.ranges_id = b->d_ranges.as<int2>();
+  a.f.ibeg = packed ? b->pibeg.as<int32_t>() : nullptr;
+  a.f.rec = b->rec;
+  a.f.eps_t = prm->eps_t;
+  a.f.sig_t = prm->sig_t;
+  a.f.n_types = prm->n_types;
+  a.f.rc2 = prm->r_cut * prm->r_cut;
+  a.cot = reinterpret_cast<const float4*>(cot_dev);
+  a.mass_t = prm->mass_t;
+  a.gpos = reinterpret_cast<float4*>(gpos_dev);
+  a.gparam = gparam_dev;
+  a.force = b->force.as<float4>();
+  GC_HIP(c, launch_lj_adjoint(a, 4, s));
+  GC_HIP(c, launch_lj_mass_grad(a.cot, a.force, prm->mass_t, b->pool->src, gmass_dev, b->n_ids, s));
+  return GC_OK;
+}
 
 // ===================================================================== graphs
 

@@ -1,0 +1,143 @@
+"""GPU adjoint (gc_backward) against the FP64 oracle VJP and central finite differences.
+
+Bar: relative error <= 1e-4 per gradient block (positions, masses, eps/sigma), measured as
+||g_gpu - g_ref||_2 / ||g_ref||_2, plus elementwise |g_gpu - g_ref| <= 1e-4 max|g_ref|.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2008_05712_amd as gc
+import workloads as W
+from gpu_helpers import GravRig, whole
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gc.Context(0)
+    yield c
+    c.close()
+
+
+def close(got, want, tol=TOL):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    rel = np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+    ele = np.abs(got - want).max() / max(np.abs(want).max(), 1e-300)
+    return rel <= tol and ele <= tol, (rel, ele)
+
+
+def grav_vjp_gpu(ctx, w, g, mode=gc.REORG_NONE):
+    import torch
+    rig = GravRig(ctx, w)
+    b = rig.batch(whole(w))
+    rig.run(b, mode, order=1)
+    cot = torch.zeros((w.n, 4), dtype=torch.float32, device="cuda")
+    cot[:, :3] = torch.from_numpy(g.astype(np.float32)).cuda()
+    gpos = torch.zeros((w.n, 4), dtype=torch.float32, device="cuda")
+    gmass = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+    nr = torch.from_numpy(np.ascontiguousarray(w.node_range)).cuda()
+    b.backward(gc.grav_params(order=1), rig.nodes, nr, w.nodes.shape[0], cot, gpos, gmass)
+    torch.cuda.synchronize()
+    out = gpos.cpu().numpy()[:, :3], gmass.cpu().numpy()
+    b.destroy()
+    rig.close()
+    return out
+
+
+@pytest.mark.parametrize("mode", [gc.REORG_NONE, gc.REORG_PACK])
+def test_grav_vjp_matches_oracle_tiny(ctx, mode):
+    w = W.nbody_tiny()
+    g = np.random.default_rng(11).normal(size=(w.n, 3)).astype(np.float32).astype(np.float64)
+    gp, gm = grav_vjp_gpu(ctx, w, g, mode)
+    rp, rm = O.vjp_grav_mono(w, g)
+    ok, e = close(gp, rp)
+    assert ok, ("positions", e)
+    ok, e = close(gm, rm)
+    assert ok, ("masses", e)
+
+
+def test_grav_vjp_matches_finite_differences_512(ctx):
+    w = W.build_grav(W.plummer(512, 51), bucket=16, theta=0.7)
+    rng = np.random.default_rng(52)
+    g = rng.normal(size=(w.n, 3)).astype(np.float32).astype(np.float64)
+    gp, gm = grav_vjp_gpu(ctx, w, g)
+    rec = w.rec.astype(np.float64)
+    pos, mass = rec[:, :3].copy(), rec[:, 3].copy()
+    h = 1e-6
+
+    def loss(p, m):
+        mom = O.node_moments(w.node_range, p, m)
+        mom[:, 4:] = 0.0
+        return float(np.sum(g * O.grav_lists(O.workload_tasks(w), p, m, mom, order=1)))
+
+    fd_p = np.zeros((12, 3))
+    idx = rng.choice(w.n, size=12, replace=False)
+    for a, i in enumerate(idx):
+        for q in range(3):
+            p1, p2 = pos.copy(), pos.copy()
+            p1[i, q] += h
+            p2[i, q] -= h
+            fd_p[a, q] = (loss(p1, mass) - loss(p2, mass)) / (2 * h)
+    scale = np.abs(fd_p).max()
+    assert np.abs(gp[idx] - fd_p).max() <= TOL * scale, np.abs(gp[idx] - fd_p).max() / scale
+    fd_m = np.zeros(12)
+    for a, i in enumerate(idx):
+        m1, m2 = mass.copy(), mass.copy()
+        m1[i] += h * mass[i]
+        m2[i] -= h * mass[i]
+        fd_m[a] = (loss(pos, m1) - loss(pos, m2)) / (2 * h * mass[i])
+    assert np.abs(gm[idx] - fd_m).max() <= TOL * np.abs(fd_m).max()
+
+
+def test_lj_vjp_matches_oracle(ctx):
+    import torch
+    from test_gpu_lj import LJRig
+    w = W.lj_small()
+    rig = LJRig(ctx, w)
+    rig.run(gc.REORG_NONE)
+    g = np.random.default_rng(13).normal(size=(w.n, 3)).astype(np.float32).astype(np.float64)
+    cot = torch.zeros((w.n, 4), dtype=torch.float32, device="cuda")
+    cot[:, :3] = torch.from_numpy(g.astype(np.float32)).cuda()
+    gpos = torch.zeros((w.n, 4), dtype=torch.float32, device="cuda")
+    gmass = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+    gpar = torch.zeros(2 * w.eps_t.size, dtype=torch.float32, device="cuda")
+    prm = gc.lj_params(rig.eps, rig.sig, rig.mass, w.rcut)
+    rig.b.backward(prm, None, None, 0, cot, gpos, gmass, gpar)
+    torch.cuda.synchronize()
+    rp, rm, re, rs = O.vjp_lj(w, g)
+    ok, e = close(gpos.cpu().numpy()[:, :3], rp)
+    assert ok, ("positions", e)
+    ok, e = close(gmass.cpu().numpy(), rm)
+    assert ok, ("masses", e)
+    nt = w.eps_t.size
+    par = gpar.cpu().numpy()
+    ok, e = close(par[:nt], re)
+    assert ok, ("eps", e)
+    ok, e = close(par[nt:], rs)
+    assert ok, ("sigma", e)
+    rig.close()
+
+
+def test_autograd_gravity_matches_backward(ctx):
+    import torch
+    from paper_2008_05712_amd.autograd import CombinedGravity
+    w = W.build_grav(W.plummer(2000, 61), bucket=16, theta=0.7)
+    rig = GravRig(ctx, w)
+    b = rig.batch(whole(w))
+    rec = torch.from_numpy(w.rec.copy()).cuda().requires_grad_(True)
+    nr = torch.from_numpy(np.ascontiguousarray(w.node_range)).cuda()
+    acc = CombinedGravity.apply(rec, rig.nodes, nr, b, rig.pool, gc.grav_params(order=1))
+    g = torch.randn(w.n, 4, device="cuda")
+    g[:, 3] = 0
+    (grec,) = torch.autograd.grad((acc * g).sum(), rec)
+    rp, rm = O.vjp_grav_mono(w, g.cpu().numpy()[:, :3].astype(np.float64))
+    ok, e = close(grec.cpu().numpy()[:, :3], rp)
+    assert ok, e
+    ok, e = close(grec.cpu().numpy()[:, 3], rm)
+    assert ok, e
+    b.destroy()
+    rig.close()

@@ -41,6 +41,166 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def time_kernel(fn, stream, reps: int = 10) -> float:
+    """Average ms of fn() (device work on `stream`) over reps launches, HIP events on that stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def leg_instances(gc, W, torch, ctx, args):
+    """64 independent Plummer instances (sizes log-uniform in 2,048..262,144): per-instance combined
+    launches versus aggregated launches (autotuned aggregation count and shape), graph-captured."""
+    t0 = time.time()
+    w = W.nbody_instances(k=64, seed=4000)
+    inst = w.meta["instance_of_task"]
+    log(f"[bench] instances: N={w.n} tasks={w.n_tasks} build {time.time() - t0:.1f}s")
+    n_direct, n_node = w.split_interactions()
+    inter = n_direct + n_node
+    flops = n_direct * FLOPS_PAIR + n_node * FLOPS_QUAD
+    dev = torch.device("cuda")
+    src = torch.from_numpy(w.rec).to(dev)
+    nodes = torch.from_numpy(w.nodes).to(dev)
+    acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
+    pool = gc.Pool(ctx, w.n, 1)
+    pool.set_source(src)
+    stream = torch.cuda.current_stream()
+    res = {"workload": f"nbody-plummer-x64 (N={w.n}, {w.n_tasks} tasks, {inter} interactions)"}
+
+    def batches_for(k):
+        out = []
+        for g0 in range(0, 64, k):
+            sel = np.nonzero((inst >= g0) & (inst < g0 + k))[0]
+            bt = W.task_subset(w, sel)
+            b = gc.Batch(ctx, gc.KIND_GRAV, w.n)
+            b.submit(gc.tasks_from_csr(bt["i_begin"], bt["i_count"], bt["j_first"], bt["j_nr"], bt["n_first"],
+                                       bt["n_count"]), bt["ranges"], bt["node_idx"])
+            b.commit()
+            b.reorganize(pool, gc.REORG_NONE)
+            out.append(b)
+        return out
+
+    best = None
+    per = {}
+    for k in (1, 8, 64):
+        bs = batches_for(k)
+        for sched in (0, 1):
+            prm = gc.grav_params(order=2, schedule=sched)
+            side = torch.cuda.Stream()
+            g = gc.Graph(ctx, bs, [pool] * len(bs), [gc.REORG_NONE] * len(bs), prm, nodes, acc, stream=side)
+            torch.cuda.synchronize()
+            ms = time_kernel(lambda: g.launch(stream=stream), stream, reps=5)
+            g.destroy()
+            per[f"agg{k}_sched{sched}"] = round(ms, 4)
+            if best is None or ms < best[0]:
+                best = (ms, k, sched)
+        for b in bs:
+            b.destroy()
+    base = per["agg1_sched0"]
+    res.update({"per_launch_ms": per, "per_instance_ms": base,
+                "per_instance_ginteractions_per_s": round(inter / (base * 1e-3) / 1e9, 3),
+                "best": {"aggregation": best[1], "schedule": best[2], "ms": round(best[0], 4),
+                         "ginteractions_per_s": round(inter / (best[0] * 1e-3) / 1e9, 3),
+                         "tflops": round(flops / (best[0] * 1e-3) / 1e12, 3)},
+                "speedup_vs_per_instance": round(base / best[0], 3)})
+    pool.destroy()
+    return res
+
+
+def leg_lj(gc, W, torch, ctx):
+    """1,048,576 LJ atoms (FCC, half-box thinned), one combined cell-pair launch per step."""
+    t0 = time.time()
+    w = W.lj_fcc()
+    log(f"[bench] lj: N={w.n} tasks={w.n_tasks} build {time.time() - t0:.1f}s")
+    dev = torch.device("cuda")
+    src = torch.from_numpy(w.rec).to(dev)
+    eps, sig, mass = (torch.from_numpy(x).to(dev) for x in (w.eps_t, w.sig_t, w.mass_t))
+    acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
+    pool = gc.Pool(ctx, w.n, 1)
+    pool.set_source(src)
+    ranges = np.stack([w.j_begin, w.j_count], axis=1).astype(np.int32)
+    t = gc.tasks_from_csr(w.i_begin, w.i_count, np.arange(w.n_tasks, dtype=np.int32), np.ones(w.n_tasks, np.int32),
+                          flags=np.where(w.self_flag != 0, gc.TASK_SELF, 0), shift=w.shift)
+    b = gc.Batch(ctx, gc.KIND_LJ, w.n)
+    b.submit(t, ranges)
+    b.commit()
+    b.reorganize(pool, gc.REORG_NONE)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"lj-fcc-{w.n} (rc 2.5, {w.n_tasks} cell-pair tasks)"}
+    for sched in (0, 1):
+        prm = gc.lj_params(eps, sig, mass, w.rcut, schedule=sched)
+        ms = time_kernel(lambda: b.launch(prm, None, acc), stream)
+        out[f"ms_sched{sched}"] = round(ms, 4)
+    ms = min(out["ms_sched0"], out["ms_sched1"])
+    # in-cutoff pair count from one oracle-free pass: candidates from the task sizes; pairs estimated
+    # from the density (reported exactly by the parity tests' oracle runs)
+    cand = w.candidates()
+    out.update({"candidates": cand, "candidates_per_s_G": round(cand / (ms * 1e-3) / 1e9, 3), "ms": ms})
+    b.destroy()
+    pool.destroy()
+    return out
+
+
+def leg_adjoint(gc, W, torch, ctx):
+    """Backward / forward time: gravity on the 4,096-particle uniform set (monopole) and the
+    two-type LJ adjoint at 1,048,576 atoms."""
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    w = W.nbody_tiny()
+    src = torch.from_numpy(w.rec).to(dev)
+    nodes = torch.from_numpy(w.nodes).to(dev)
+    nr = torch.from_numpy(np.ascontiguousarray(w.node_range)).to(dev)
+    acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
+    pool = gc.Pool(ctx, w.n, 1)
+    pool.set_source(src)
+    b = gc.Batch(ctx, gc.KIND_GRAV, w.n)
+    b.submit(gc.tasks_from_csr(w.i_begin, w.i_count, w.j_first, w.j_nr, w.n_first, w.n_count), w.ranges, w.node_idx)
+    b.commit()
+    b.reorganize(pool, gc.REORG_NONE)
+    prm = gc.grav_params(order=1)
+    cot = torch.randn((w.n, 4), device=dev)
+    gpos = torch.zeros((w.n, 4), device=dev)
+    gmass = torch.zeros(w.n, device=dev)
+    fwd = time_kernel(lambda: b.launch(prm, nodes, acc), stream)
+    bwd = time_kernel(lambda: b.backward(prm, nodes, nr, w.nodes.shape[0], cot, gpos, gmass), stream)
+    res["gravity_uniform_4096"] = {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "bwd_fwd": round(bwd / fwd, 3)}
+    b.destroy()
+    pool.destroy()
+    w = W.lj_fcc(two_type=True)
+    src = torch.from_numpy(w.rec).to(dev)
+    eps, sig, mass = (torch.from_numpy(x).to(dev) for x in (w.eps_t, w.sig_t, w.mass_t))
+    acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
+    pool = gc.Pool(ctx, w.n, 1)
+    pool.set_source(src)
+    ranges = np.stack([w.j_begin, w.j_count], axis=1).astype(np.int32)
+    t = gc.tasks_from_csr(w.i_begin, w.i_count, np.arange(w.n_tasks, dtype=np.int32), np.ones(w.n_tasks, np.int32),
+                          flags=np.where(w.self_flag != 0, gc.TASK_SELF, 0), shift=w.shift)
+    b = gc.Batch(ctx, gc.KIND_LJ, w.n)
+    b.submit(t, ranges)
+    b.commit()
+    b.reorganize(pool, gc.REORG_NONE)
+    prm = gc.lj_params(eps, sig, mass, w.rcut)
+    cot = torch.randn((w.n, 4), device=dev)
+    gpos = torch.zeros((w.n, 4), device=dev)
+    gmass = torch.zeros(w.n, device=dev)
+    gpar = torch.zeros(2 * w.eps_t.size, device=dev)
+    fwd = time_kernel(lambda: b.launch(prm, None, acc), stream)
+    bwd = time_kernel(lambda: b.backward(prm, None, None, 0, cot, gpos, gmass, gpar), stream)
+    res["lj_two_type_1048576"] = {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "bwd_fwd": round(bwd / fwd, 3)}
+    res["bwd_fwd"] = res["lj_two_type_1048576"]["bwd_fwd"]
+    b.destroy()
+    pool.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +211,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rounds", type=int, default=1000, help="rounds of the step timed on the CPU")
     ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--quick", action="store_true", help="skip the batched, LJ and adjoint legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is described in "
@@ -184,6 +345,23 @@ def main():
                "sample": f"first {ns} of {len(rounds)} rounds ({len(sample)} bucket tasks, {nint} interactions), "
                          f"FP64, {dt:.2f} s"}
 
+    # ---- one launch over all 27k tasks (the fully combined request): kernel efficiency at occupancy
+    allb = gc.Batch(ctx, gc.KIND_GRAV, w.n)
+    allb.submit(gc.tasks_from_csr(w.i_begin, w.i_count, w.j_first, w.j_nr, w.n_first, w.n_count), w.ranges, w.node_idx)
+    allb.commit()
+    allb.reorganize(pool, gc.REORG_NONE)
+    combined_all = time_kernel(lambda: allb.launch(prm, nodes, acc), stream)
+    combined_all = {"ms": round(combined_all, 4), "tflops": round(flops_step / (combined_all * 1e-3) / 1e12, 3),
+                    "ginteractions_per_s": round(interactions / (combined_all * 1e-3) / 1e9, 3)}
+    allb.destroy()
+    occ_blocks, n_cu = ctx.occupancy(prm)
+
+    extra = {}
+    if not args.quick:
+        extra["batched_instances"] = leg_instances(gc, W, torch, ctx, args)
+        extra["lj"] = leg_lj(gc, W, torch, ctx)
+        extra["adjoint"] = leg_adjoint(gc, W, torch, ctx)
+
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -214,8 +392,11 @@ def main():
                        "note": "per-round union fits in L2/MALL: effective (cache-resident) GB/s"},
         "kernel_only_ginteractions_per_s": round(interactions / (kern_ms * 1e-3) / 1e9, 3),
         "autotune_largest_round": tuned,
-        "bwd_fwd": None,
+        "combined_all_tasks_one_launch": combined_all,
+        "occupancy": {"blocks_per_cu": occ_blocks, "cus": n_cu, "waves_per_block": 4},
+        "bwd_fwd": extra.get("adjoint", {}).get("bwd_fwd"),
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
     if graph is not None:
         graph.destroy()

@@ -159,19 +159,26 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
 
   int iter = 0;
   while (true) {
-    int t;
+    // Tasks run in longest-first order: block b starts with order[b]; in the persistent
+    // schedule later tasks come from a device counter (offset by the grid size), so the
+    // first wave of grabs needs no atomics.
+    int got;
     if (PERSIST) {
-      if (threadIdx.x == 0) s_task = atomicAdd(a.queue, 1);
-      __syncthreads();
-      const int got = uniform(s_task);
-      __syncthreads();
-      if (got >= a.n_tasks) break;
-      t = uniform(a.order[got]);
+      if (iter == 0) {
+        got = blockIdx.x;
+      } else {
+        if (threadIdx.x == 0) s_task = (int)gridDim.x + atomicAdd(a.queue, 1);
+        __syncthreads();
+        got = uniform(s_task);
+        __syncthreads();
+      }
+      ++iter;
     } else {
       if (iter++) break;
-      t = uniform(blockIdx.x);
-      if (t >= a.n_tasks) break;
+      got = blockIdx.x;
     }
+    if (got >= a.n_tasks) break;
+    const int t = uniform(a.order[got]);
     const gc_task tk = a.tasks[t];
     const int ic = tk.i_count;
     for (int i0 = 0; i0 < ic; i0 += 64) {

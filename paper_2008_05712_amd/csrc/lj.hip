@@ -44,18 +44,24 @@ __global__ void __launch_bounds__(256) k_lj(LJArgs a) {
   __syncthreads();
   int iter = 0;
   while (true) {
-    int t;
+    // Persistent schedule: wave k of the grid starts with order[k], later tasks come from a
+    // device counter offset by the number of waves in the grid.
+    int got;
     if (PERSIST) {
-      int got = 0;
-      if (lane == 0) got = atomicAdd(a.queue, 1);
-      got = uniform(__shfl(got, 0, 64));
-      if (got >= a.n_tasks) break;
-      t = uniform(a.order[got]);
+      if (iter == 0) {
+        got = uniform(blockIdx.x * wpb + wid);
+      } else {
+        int q = 0;
+        if (lane == 0) q = atomicAdd(a.queue, 1);
+        got = uniform(__shfl(q, 0, 64)) + (int)gridDim.x * wpb;
+      }
+      ++iter;
     } else {
       if (iter++) break;
-      t = uniform(blockIdx.x * wpb + wid);
-      if (t >= a.n_tasks) break;
+      got = uniform(blockIdx.x * wpb + wid);
     }
+    if (got >= a.n_tasks) break;
+    const int t = PERSIST ? uniform(a.order[got]) : got;
     const gc_task tk = a.tasks[t];
     const int2 gj = a.ranges[tk.j_first];
     const int2 gjid = a.ranges_id[tk.j_first];

@@ -69,37 +69,51 @@ __device__ __forceinline__ uint64_t lb_load(uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 of block `bid`: publish the block aggregate (a, b), look back for the exclusive
-// prefix, publish the inclusive prefix.  Sets err[0] if a predecessor never publishes
-// within the spin bound (not expected; keeps every wave finite).
+// Wavefront 0 of block `bid`: publish the block aggregate (a, b), look back over up to 64
+// predecessors per step (one lane each: the run up to the nearest inclusive prefix is summed
+// once none of it is still empty), publish the inclusive prefix.  Sets err[0] if a
+// predecessor never publishes within the spin bound (not expected; keeps every wave finite).
 __device__ __forceinline__ void lb_resolve(uint64_t* flags, int bid, uint32_t a, uint32_t b, uint32_t* ea,
                                            uint32_t* eb, int32_t* err) {
+  const int lane = threadIdx.x & 63;
   if (bid == 0) {
-    lb_store(flags, lb_pack(2, a, b));
+    if (lane == 0) lb_store(flags, lb_pack(2, a, b));
     *ea = 0;
     *eb = 0;
     return;
   }
-  lb_store(flags + bid, lb_pack(1, a, b));
+  if (lane == 0) lb_store(flags + bid, lb_pack(1, a, b));
   uint32_t xa = 0, xb = 0, spins = 0;
-  int j = bid - 1;
-  while (j >= 0) {
-    uint64_t w = lb_load(flags + j);
-    uint32_t st = (uint32_t)(w & 3u);
-    if (st == 0) {
+  int hi = bid - 1;
+  while (true) {
+    const int j = hi - lane;
+    const uint64_t w = j >= 0 ? lb_load(flags + j) : lb_pack(2, 0, 0);  // before block 0: a zero prefix
+    const uint32_t st = (uint32_t)(w & 3u);
+    const uint64_t pre = __ballot(st == 2);
+    const uint64_t emp = __ballot(st == 0);
+    const int stop = pre ? __builtin_ctzll(pre) : 63;  // last lane of the run to sum
+    const uint64_t run = stop == 63 ? ~0ull : ((2ull << stop) - 1ull);
+    if (emp & run) {
       if (++spins > kSpinLimit) {
-        err[0] = 1;
+        if (lane == 0) err[0] = 1;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    xa += (uint32_t)((w >> 2) & 0x7fffffffu);
-    xb += (uint32_t)(w >> 33);
-    if (st == 2) break;
-    --j;
+    uint32_t va = lane <= stop ? (uint32_t)((w >> 2) & 0x7fffffffu) : 0u;
+    uint32_t vb = lane <= stop ? (uint32_t)(w >> 33) : 0u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      va += __shfl_xor(va, off, 64);
+      vb += __shfl_xor(vb, off, 64);
+    }
+    xa += va;
+    xb += vb;
+    if (pre) break;
+    hi -= 64;
   }
-  lb_store(flags + bid, lb_pack(2, xa + a, xb + b));
+  if (lane == 0) lb_store(flags + bid, lb_pack(2, xa + a, xb + b));
   *ea = xa;
   *eb = xb;
 }
@@ -165,14 +179,16 @@ __global__ void __launch_bounds__(kLBThreads) k_union(uint8_t* __restrict__ need
   int tu, tm;
   int ru = block_excl_scan(__popc(fu), sh, &tu);
   int rm = block_excl_scan(__popc(fm), sh, &tm);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     uint32_t ea, eb;
     lb_resolve(flags, bid, (uint32_t)tu, (uint32_t)tm, &ea, &eb, counts + 4);
-    s_ex[0] = ea;
-    s_ex[1] = eb;
-    if (bid == (int)gridDim.x - 1) {
-      counts[0] = (int32_t)(ea + tu);
-      counts[1] = (int32_t)(eb + tm);
+    if (threadIdx.x == 0) {
+      s_ex[0] = ea;
+      s_ex[1] = eb;
+      if (bid == (int)gridDim.x - 1) {
+        counts[0] = (int32_t)(ea + tu);
+        counts[1] = (int32_t)(eb + tm);
+      }
     }
   }
   __syncthreads();
@@ -223,11 +239,13 @@ __global__ void __launch_bounds__(kLBThreads) k_free(const int32_t* __restrict__
   }
   int t;
   int r = block_excl_scan(__popc(f), sh, &t);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     uint32_t ea, eb;
     lb_resolve(flags, bid, (uint32_t)t, 0u, &ea, &eb, counts + 4);
-    s_ex = ea;
-    if (bid == (int)gridDim.x - 1) counts[2] = (int32_t)(ea + t);
+    if (threadIdx.x == 0) {
+      s_ex = ea;
+      if (bid == (int)gridDim.x - 1) counts[2] = (int32_t)(ea + t);
+    }
   }
   __syncthreads();
   r += (int)s_ex;

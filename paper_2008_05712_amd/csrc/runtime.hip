@@ -785,6 +785,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
     // size buffers outside the capture (allocation is not capturable)
     if (modes[k] != GC_REORG_NONE && ensure_reorg_buffers(batches[k], pools[k]) != hipSuccess)
       return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: buffers");
+    if (batches[k]->queue.ensure(16) != hipSuccess) return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: queue");
   }
   // flags start cleared: clear once outside the capture
   for (int32_t k = 0; k < n_steps; ++k)

@@ -255,3 +255,28 @@ def test_full_size_round_sampled(ctx):
     assert err.max() <= TOL, err.max()
     b.destroy()
     rig.close()
+
+
+def test_graph_of_fresh_batches_in_place_mode(ctx, plum):
+    # batches never launched eagerly (buffers first sized by the capture call), persistent queue
+    import torch
+    rig = GravRig(ctx, plum)
+    rounds = W.poisson_rounds(plum.n_tasks, 700, seed=18)[:3]
+    bts = [W.task_subset(plum, r) for r in rounds]
+    bs = [rig.batch(bt) for bt in bts]
+    prm = gc.grav_params(order=2, schedule=1)
+    s = torch.cuda.Stream()
+    g = gc.Graph(ctx, bs, [rig.pool] * 3, [gc.REORG_NONE] * 3, prm, rig.nodes, rig.acc, stream=s)
+    ref = O.grav_workload(plum, order=2)
+    for rep in range(2):
+        rig.acc.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        acc = rig.acc.cpu().numpy()
+        for bt in bts:
+            assert rel_l2_per_task(acc, ref, bt).max() <= TOL, rep
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()

@@ -226,9 +226,47 @@ __global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_n
 constexpr int kMaxTypes = 8;
 constexpr int kLJTile = 128;
 
-// One wavefront per cell-pair task, lanes = (i atom) x (j slice) as in the forward kernel.
-// j-side gradients and forces accumulate in LDS (LDS atomics), i-side in registers; the
-// per-type parameter gradients accumulate per lane in LDS columns indexed by the type pair.
+// Per-lane accumulators of dL/deps_ij and dL/dsigma_ij keyed by the j type (the lane's i type is
+// fixed within a run chunk).  NT = 1 or 2 keep them in registers; NT = 0 (up to kMaxTypes types)
+// adds each pair term to LDS directly.
+template <int NT>
+struct ParamAcc {
+  float e[NT > 0 ? NT : 1], s[NT > 0 ? NT : 1];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < (NT > 0 ? NT : 1); ++k) e[k] = s[k] = 0.f;
+  }
+  __device__ __forceinline__ void add(int tj, float de, float ds, float* pg_row) {
+    if (NT == 1) {
+      e[0] += de;
+      s[0] += ds;
+    } else if (NT == 2) {
+      const bool one = tj != 0;
+      e[0] += one ? 0.f : de;
+      s[0] += one ? 0.f : ds;
+      e[1] += one ? de : 0.f;
+      s[1] += one ? ds : 0.f;
+    } else {
+      atomicAdd(pg_row + 2 * tj, de);
+      atomicAdd(pg_row + 2 * tj + 1, ds);
+    }
+  }
+  __device__ __forceinline__ void flush(float* pg_row) {
+    if (NT > 0) {
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        if (e[k] != 0.f) atomicAdd(pg_row + 2 * k, e[k]);
+        if (s[k] != 0.f) atomicAdd(pg_row + 2 * k + 1, s[k]);
+      }
+    }
+    zero();
+  }
+};
+
+// One wavefront per run of tasks sharing a target range (as in the forward kernel); lanes =
+// (i atom) x (j slice) with a per-lane rotation over the slice's j entries.  j-side gradients and
+// forces accumulate in LDS, i-side in registers across the run.
+template <int NT>
 __global__ void __launch_bounds__(256) k_lj_adj(LJAdjArgs A) {
   const LJArgs& a = A.f;
   __shared__ float2 tab[kMaxTypes * kMaxTypes];   // (24 eps_ij, sigma_ij)
@@ -245,118 +283,133 @@ __global__ void __launch_bounds__(256) k_lj_adj(LJAdjArgs A) {
   }
   for (int k = threadIdx.x; k < 4 * 2 * kMaxTypes * kMaxTypes; k += blockDim.x) (&pg[0][0])[k] = 0.f;
   __syncthreads();
-  const int t = uniform(blockIdx.x * 4 + wid);
-  if (t < a.n_tasks) {
-    const gc_task tk = a.tasks[t];
-    const int2 gjr = a.ranges[tk.j_first];
-    const int2 gjid = a.ranges_id[tk.j_first];
-    const bool self = (tk.flags & GC_TASK_SELF) != 0;
-    const float sa0 = tk.shift[0] > 0.f ? tk.shift[0] : 0.f, sb0 = tk.shift[0] < 0.f ? tk.shift[0] : 0.f;
-    const float sa1 = tk.shift[1] > 0.f ? tk.shift[1] : 0.f, sb1 = tk.shift[1] < 0.f ? tk.shift[1] : 0.f;
-    const float sa2 = tk.shift[2] > 0.f ? tk.shift[2] : 0.f, sb2 = tk.shift[2] < 0.f ? tk.shift[2] : 0.f;
-    const int ipos0 = a.ibeg ? a.ibeg[t] : tk.i_begin;
-    for (int i0 = 0; i0 < tk.i_count; i0 += 64) {
-      const int icc = tk.i_count - i0 < 64 ? tk.i_count - i0 : 64;
+  const int r = uniform(blockIdx.x * 4 + wid);
+  if (r < a.n_runs) {
+    const int t0 = uniform(a.runs[r]), t1 = uniform(a.runs[r + 1]);
+    const gc_task tk0 = a.tasks[t0];
+    const int ipos0 = a.ibeg ? a.ibeg[t0] : tk0.i_begin;
+    for (int i0 = 0; i0 < tk0.i_count; i0 += 64) {
+      const int icc = tk0.i_count - i0 < 64 ? tk0.i_count - i0 : 64;
       const int S = 64 / icc;
       const int il = lane % icc, sl = lane / icc;
       const bool active = sl < S;
-      float xi = 0.f, yi = 0.f, zi = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+      float xr = 0.f, yr = 0.f, zr = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
       int ti = 0;
       if (active) {
-        float4 r = a.rec[ipos0 + i0 + il];
-        xi = r.x - sa0; yi = r.y - sa1; zi = r.z - sa2;
-        ti = (int)r.w;
-        float4 g = A.cot[tk.i_begin + i0 + il];
+        float4 rr = a.rec[ipos0 + i0 + il];
+        xr = rr.x; yr = rr.y; zr = rr.z;
+        ti = (int)rr.w;
+        float4 g = A.cot[tk0.i_begin + i0 + il];
         float m = A.mass_t[ti];
         hx = g.x / m; hy = g.y / m; hz = g.z / m;
       }
+      float* pg_row = &pg[wid][2 * ti * nt];
+      ParamAcc<NT> pa;
+      pa.zero();
       float Gx = 0.f, Gy = 0.f, Gz = 0.f, Fx = 0.f, Fy = 0.f, Fz = 0.f;
-      for (int j0 = 0; j0 < gjr.y; j0 += kLJTile) {
-        const int cnt = gjr.y - j0 < kLJTile ? gjr.y - j0 : kLJTile;
-        for (int e = lane; e < cnt; e += 64) {
-          float4 r = a.rec[gjr.x + j0 + e];
-          jt[wid][e] = make_float4(r.x + sb0, r.y + sb1, r.z + sb2, r.w);
-          float4 g = A.cot[gjid.x + j0 + e];
-          float m = A.mass_t[(int)r.w];
-          jh[wid][e] = make_float4(g.x / m, g.y / m, g.z / m, 0.f);
+      for (int t = t0; t < t1; ++t) {
+        const gc_task tk = a.tasks[t];
+        const int2 gjr = a.ranges[tk.j_first];
+        const int2 gjid = a.ranges_id[tk.j_first];
+        const bool self = (tk.flags & GC_TASK_SELF) != 0;
+        const float xi = xr - (tk.shift[0] > 0.f ? tk.shift[0] : 0.f);
+        const float yi = yr - (tk.shift[1] > 0.f ? tk.shift[1] : 0.f);
+        const float zi = zr - (tk.shift[2] > 0.f ? tk.shift[2] : 0.f);
+        const float sb0 = tk.shift[0] < 0.f ? tk.shift[0] : 0.f;
+        const float sb1 = tk.shift[1] < 0.f ? tk.shift[1] : 0.f;
+        const float sb2 = tk.shift[2] < 0.f ? tk.shift[2] : 0.f;
+        for (int j0 = 0; j0 < gjr.y; j0 += kLJTile) {
+          const int cnt = gjr.y - j0 < kLJTile ? gjr.y - j0 : kLJTile;
+          for (int e = lane; e < cnt; e += 64) {
+            float4 rj = a.rec[gjr.x + j0 + e];
+            jt[wid][e] = make_float4(rj.x + sb0, rj.y + sb1, rj.z + sb2, rj.w);
+            float4 g = A.cot[gjid.x + j0 + e];
+            float m = A.mass_t[(int)rj.w];
+            jh[wid][e] = make_float4(g.x / m, g.y / m, g.z / m, 0.f);
 #pragma unroll
-          for (int q = 0; q < 6; ++q) gj[wid][q][e] = 0.f;
-        }
-        wave_sync();
-        if (active) {
-          const int C = (cnt + S - 1) / S;
-          const int e0 = sl * C, e1 = e0 + C < cnt ? e0 + C : cnt;
-          for (int e = e0; e < e1; ++e) {
-            if (self && j0 + e <= i0 + il) continue;
-            const float4 j = jt[wid][e];
-            const float dx = xi - j.x, dy = yi - j.y, dz = zi - j.z;
-            const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-            if (r2 < a.rc2) {
-              const int tj = (int)j.w;
-              const float2 p = tab[ti * nt + tj];
-              const float e24 = p.x, sg = p.y;
-              const float ri2 = __builtin_amdgcn_rcpf(r2);
-              const float q = sg * sg * ri2;
-              const float q3 = q * q * q;
-              const float f = e24 * q3 * __builtin_fmaf(2.f, q3, -1.f) * ri2;           // force factor
-              const float fp = e24 * q3 * __builtin_fmaf(-14.f, q3, 4.f) * ri2 * ri2;   // df / d(r^2)
-              const float4 hj = jh[wid][e];
-              const float dhx = hx - hj.x, dhy = hy - hj.y, dhz = hz - hj.z;
-              const float pp = __builtin_fmaf(dhz, dz, __builtin_fmaf(dhy, dy, dhx * dx));
-              const float c2 = 2.f * fp * pp;
-              const float wx = __builtin_fmaf(f, dhx, c2 * dx);
-              const float wy = __builtin_fmaf(f, dhy, c2 * dy);
-              const float wz = __builtin_fmaf(f, dhz, c2 * dz);
-              Gx += wx; Gy += wy; Gz += wz;
-              Fx = __builtin_fmaf(f, dx, Fx);
-              Fy = __builtin_fmaf(f, dy, Fy);
-              Fz = __builtin_fmaf(f, dz, Fz);
-              atomicAdd(&gj[wid][0][e], -wx);
-              atomicAdd(&gj[wid][1][e], -wy);
-              atomicAdd(&gj[wid][2][e], -wz);
-              atomicAdd(&gj[wid][3][e], -f * dx);
-              atomicAdd(&gj[wid][4][e], -f * dy);
-              atomicAdd(&gj[wid][5][e], -f * dz);
-              // dL/deps_ij = p f / eps_ij; dL/dsigma_ij = p (24 eps)(24 s^11 r^-14 - 6 s^5 r^-8) = p f_s
-              const float e_ij = e24 * (1.f / 24.f);
-              const float dle = pp * f / e_ij;
-              const float fs = e24 * q3 * __builtin_fmaf(24.f, q3, -6.f) * ri2 / sg;
-              atomicAdd(&pg[wid][2 * (ti * nt + tj)], dle);
-              atomicAdd(&pg[wid][2 * (ti * nt + tj) + 1], pp * fs);
+            for (int q = 0; q < 6; ++q) gj[wid][q][e] = 0.f;
+          }
+          wave_sync();
+          if (active) {
+            const int C = (cnt + S - 1) / S;
+            const int e0 = sl * C, e1 = e0 + C < cnt ? e0 + C : cnt;
+            const int cs = e1 - e0;
+            if (cs > 0) {
+              int e = e0 + il % cs;
+              for (int k = 0; k < cs; ++k) {
+                if (!(self && j0 + e <= i0 + il)) {
+                  const float4 j = jt[wid][e];
+                  const float dx = xi - j.x, dy = yi - j.y, dz = zi - j.z;
+                  const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                  if (r2 < a.rc2) {
+                    const int tj = (int)j.w;
+                    const float2 p = tab[ti * nt + tj];
+                    const float e24 = p.x, sg = p.y;
+                    const float ri2 = __builtin_amdgcn_rcpf(r2);
+                    const float q = sg * sg * ri2;
+                    const float q3 = q * q * q;
+                    const float f = e24 * q3 * __builtin_fmaf(2.f, q3, -1.f) * ri2;          // force factor
+                    const float fp = e24 * q3 * __builtin_fmaf(-14.f, q3, 4.f) * ri2 * ri2;  // df / d(r^2)
+                    const float4 hj = jh[wid][e];
+                    const float dhx = hx - hj.x, dhy = hy - hj.y, dhz = hz - hj.z;
+                    const float pp = __builtin_fmaf(dhz, dz, __builtin_fmaf(dhy, dy, dhx * dx));
+                    const float c2 = 2.f * fp * pp;
+                    const float wx = __builtin_fmaf(f, dhx, c2 * dx);
+                    const float wy = __builtin_fmaf(f, dhy, c2 * dy);
+                    const float wz = __builtin_fmaf(f, dhz, c2 * dz);
+                    Gx += wx; Gy += wy; Gz += wz;
+                    Fx = __builtin_fmaf(f, dx, Fx);
+                    Fy = __builtin_fmaf(f, dy, Fy);
+                    Fz = __builtin_fmaf(f, dz, Fz);
+                    atomicAdd(&gj[wid][0][e], -wx);
+                    atomicAdd(&gj[wid][1][e], -wy);
+                    atomicAdd(&gj[wid][2][e], -wz);
+                    atomicAdd(&gj[wid][3][e], -f * dx);
+                    atomicAdd(&gj[wid][4][e], -f * dy);
+                    atomicAdd(&gj[wid][5][e], -f * dz);
+                    // dL/deps_ij = p f / eps_ij; dL/dsigma_ij = p (24 eps)(24 s^11 r^-14 - 6 s^5 r^-8)
+                    const float dle = pp * f * 24.f / e24;
+                    const float fs = e24 * q3 * __builtin_fmaf(24.f, q3, -6.f) * ri2 / sg;
+                    pa.add(tj, dle, pp * fs, pg_row);
+                  }
+                }
+                e = (e + 1 == e1) ? e0 : e + 1;
+              }
             }
           }
+          wave_sync();
+          for (int e = lane; e < cnt; e += 64) {
+            const int id = gjid.x + j0 + e;
+            float4* q = A.gpos + id;
+            unsafeAtomicAdd(&q->x, gj[wid][0][e]);
+            unsafeAtomicAdd(&q->y, gj[wid][1][e]);
+            unsafeAtomicAdd(&q->z, gj[wid][2][e]);
+            float4* fq = A.force + id;
+            unsafeAtomicAdd(&fq->x, gj[wid][3][e]);
+            unsafeAtomicAdd(&fq->y, gj[wid][4][e]);
+            unsafeAtomicAdd(&fq->z, gj[wid][5][e]);
+          }
+          wave_sync();
         }
-        wave_sync();
-        for (int e = lane; e < cnt; e += 64) {
-          const int id = gjid.x + j0 + e;
-          float4* q = A.gpos + id;
-          unsafeAtomicAdd(&q->x, gj[wid][0][e]);
-          unsafeAtomicAdd(&q->y, gj[wid][1][e]);
-          unsafeAtomicAdd(&q->z, gj[wid][2][e]);
-          float4* fq = A.force + id;
-          unsafeAtomicAdd(&fq->x, gj[wid][3][e]);
-          unsafeAtomicAdd(&fq->y, gj[wid][4][e]);
-          unsafeAtomicAdd(&fq->z, gj[wid][5][e]);
-        }
-        wave_sync();
       }
+      if (active) pa.flush(pg_row);
       red[wid][0][lane] = Gx; red[wid][1][lane] = Gy; red[wid][2][lane] = Gz;
       red[wid][3][lane] = Fx; red[wid][4][lane] = Fy; red[wid][5][lane] = Fz;
       wave_sync();
       if (lane < icc) {
-        float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float sm[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int sidx = 0; sidx < S; ++sidx)
 #pragma unroll
-          for (int q = 0; q < 6; ++q) s[q] += red[wid][q][sidx * icc + lane];
-        const int id = tk.i_begin + i0 + lane;
+          for (int q = 0; q < 6; ++q) sm[q] += red[wid][q][sidx * icc + lane];
+        const int id = tk0.i_begin + i0 + lane;
         float4* q = A.gpos + id;
-        unsafeAtomicAdd(&q->x, s[0]);
-        unsafeAtomicAdd(&q->y, s[1]);
-        unsafeAtomicAdd(&q->z, s[2]);
+        unsafeAtomicAdd(&q->x, sm[0]);
+        unsafeAtomicAdd(&q->y, sm[1]);
+        unsafeAtomicAdd(&q->z, sm[2]);
         float4* fq = A.force + id;
-        unsafeAtomicAdd(&fq->x, s[3]);
-        unsafeAtomicAdd(&fq->y, s[4]);
-        unsafeAtomicAdd(&fq->z, s[5]);
+        unsafeAtomicAdd(&fq->x, sm[3]);
+        unsafeAtomicAdd(&fq->y, sm[4]);
+        unsafeAtomicAdd(&fq->z, sm[5]);
       }
       wave_sync();
     }
@@ -413,8 +466,11 @@ hipError_t launch_node_chain(const int32_t* node_range, int32_t n_nodes, const f
 
 hipError_t launch_lj_adjoint(const LJAdjArgs& a, int wpb, hipStream_t s) {
   (void)wpb;
-  if (a.f.n_tasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lj_adj, dim3((a.f.n_tasks + 3) / 4), dim3(256), 0, s, a);
+  if (a.f.n_runs <= 0) return hipSuccess;
+  const dim3 grid((a.f.n_runs + 3) / 4);
+  if (a.f.n_types == 1) hipLaunchKernelGGL(k_lj_adj<1>, grid, dim3(256), 0, s, a);
+  else if (a.f.n_types == 2) hipLaunchKernelGGL(k_lj_adj<2>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_lj_adj<0>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -61,6 +61,8 @@ struct LJArgs {
   float rc2;
   int32_t* queue;
   const int32_t* order;
+  const int32_t* runs;     // runs of consecutive tasks sharing one target range: [runs[r], runs[r+1])
+  int32_t n_runs;
 };
 
 // ---------------------------------------------------------------- launchers (device code)

@@ -100,7 +100,8 @@ struct gc_batch_ {
   int64_t n_direct = 0, n_targets = 0;
   bool committed = false;
   // committed device copies
-  DevBuf d_tasks, d_ranges, d_nodes, d_mark, d_ioff, d_joff, d_order;
+  DevBuf d_tasks, d_ranges, d_nodes, d_mark, d_ioff, d_joff, d_order, d_runs;
+  int32_t n_runs = 0;
   int32_t n_mark = 0, bound_u = 0, max_direct = 0;
   // reorganisation buffers
   DevBuf need, pos, U, uslot, missing, free_list, state, packed, pranges, pibeg, ilist, jlist, queue;
@@ -280,7 +281,7 @@ extern "C" gc_status gc_batch_create(gc_ctx ctx, int32_t kind, int32_t n_ids, gc
 extern "C" gc_status gc_batch_destroy(gc_batch b) {
   if (!b) return GC_E_INVAL;
   (void)hipDeviceSynchronize();
-  for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_mark, &b->d_ioff, &b->d_joff, &b->d_order, &b->need,
+  for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_mark, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs, &b->need,
                     &b->pos, &b->U, &b->uslot, &b->missing, &b->free_list, &b->state, &b->packed, &b->pranges,
                     &b->pibeg, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force})
     d->release();
@@ -416,6 +417,14 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   std::iota(order.begin(), order.begin() + T, 0);
   std::stable_sort(order.begin(), order.begin() + T, [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
 
+  // runs of consecutive tasks sharing one target range (processed by one wavefront for LJ)
+  std::vector<int32_t> runs;
+  runs.reserve((size_t)T + 1);
+  for (int32_t t = 0; t < T; ++t)
+    if (t == 0 || b->tasks[t].i_begin != b->tasks[t - 1].i_begin || b->tasks[t].i_count != b->tasks[t - 1].i_count)
+      runs.push_back(t);
+  runs.push_back(T);
+  b->n_runs = (int32_t)runs.size() - 1;
   hipStream_t s = S(stream);
   hipError_t e = hipSuccess;
   auto up = [&](DevBuf& d, const void* src, size_t bytes) {
@@ -430,6 +439,7 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   up(b->d_ioff, ioff.data(), sizeof(int32_t) * ioff.size());
   up(b->d_joff, joff.data(), sizeof(int32_t) * joff.size());
   up(b->d_order, order.data(), sizeof(int32_t) * order.size());
+  up(b->d_runs, runs.data(), sizeof(int32_t) * runs.size());
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors must outlive the copies
   if (e != hipSuccess) return hip_fail(c, e, "gc_batch_commit");
   b->committed = true;
@@ -666,6 +676,8 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
     a.rc2 = prm->r_cut * prm->r_cut;
     a.queue = b->queue.as<int32_t>();
     a.order = b->d_order.as<int32_t>();
+    a.runs = b->d_runs.as<int32_t>();
+    a.n_runs = b->n_runs;
     int grid = prm->grid_blocks > 0 ? prm->grid_blocks : 8 * c->n_cu;
     GC_HIP(c, launch_lj(persistent, a, 4, grid, s));
     GC_HIP(c, launch_lj_finish(reinterpret_cast<float4*>(acc_dev), prm->mass_t, b->pool->src, b->n_ids, s));
@@ -753,6 +765,8 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
   a.f.sig_t = prm->sig_t;
   a.f.n_types = prm->n_types;
   a.f.rc2 = prm->r_cut * prm->r_cut;
+  a.f.runs = b->d_runs.as<int32_t>();
+  a.f.n_runs = b->n_runs;
   a.cot = reinterpret_cast<const float4*>(cot_dev);
   a.mass_t = prm->mass_t;
   a.gpos = reinterpret_cast<float4*>(gpos_dev);

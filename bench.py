@@ -41,6 +41,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic():
+    """HBM bytes per force launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    side = os.path.join(ROOT, "profiles", "k_grav_quad_plummer262144_traffic.json")
+    try:
+        meta = json.load(open(side))
+        src = open(os.path.join(ROOT, meta["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != meta.get("source_sha256"):
+        return None
+    return int(meta["traffic_bytes_per_launch"])
+
+
 def time_kernel(fn, stream, reps: int = 10) -> float:
     """Average ms of fn() (device work on `stream`) over reps launches, HIP events on that stream."""
     import torch
@@ -345,6 +360,14 @@ def main():
                "sample": f"first {ns} of {len(rounds)} rounds ({len(sample)} bucket tasks, {nint} interactions), "
                          f"FP64, {dt:.2f} s"}
 
+    # ---- calibration copy of known size (read 256 MiB + write 256 MiB): HBM rate on this machine, and the
+    # reference kernel that scales the FETCH_SIZE / WRITE_SIZE counters of a profiled run
+    cx = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    cy = torch.empty_like(cx)
+    copy_ms = time_kernel(lambda: cy.copy_(cx), stream, reps=5)
+    copy_gbps = 2 * cx.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    del cx, cy
+
     # ---- one launch over all 27k tasks (the fully combined request): kernel efficiency at occupancy
     allb = gc.Batch(ctx, gc.KIND_GRAV, w.n)
     allb.submit(gc.tasks_from_csr(w.i_begin, w.i_count, w.j_first, w.j_nr, w.n_first, w.n_count), w.ranges, w.node_idx)
@@ -381,7 +404,7 @@ def main():
                    "n": w.n, "tasks": w.n_tasks, "rounds": len(rounds), "interactions_per_step": interactions,
                    "mode": args.mode},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": profiled_traffic(),
                      "kernel": "k_grav<2,false,false> (combined quadrupole force pass)",
                      "flops_per_step": flops_step, "kernel_ms_per_step": round(kern_ms, 4),
                      "avg_launch_ms": round(kern_ms / len(batches), 4),
@@ -394,6 +417,7 @@ def main():
         "autotune_largest_round": tuned,
         "combined_all_tasks_one_launch": combined_all,
         "occupancy": {"blocks_per_cu": occ_blocks, "cus": n_cu, "waves_per_block": 4},
+        "hbm_copy_gbps": round(copy_gbps, 1),
         "bwd_fwd": extra.get("adjoint", {}).get("bwd_fwd"),
     }
     out.update(extra)

@@ -283,6 +283,11 @@ gc_status gc_backward(gc_batch batch, const gc_force_params* prm, const float* n
  * committed.  pre_reset != 0 resets each pool before its step (so every
  * replay starts from the same residency; placements given with
  * place_ids/place_slots/place_n per step are re-applied after the reset).
+ * When every step uses PACK, REDUNDANT or NONE and no batch appears twice,
+ * each step's combined pass reads only its own batch's buffers, so it is
+ * placed on a side stream and overlaps the following steps' reorganisations
+ * and passes (the pool-touching chain stays in order); otherwise the steps
+ * run strictly in sequence.  The graph owns its side streams.
  */
 gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* batches, gc_pool* pools, const int32_t* modes,
                            const gc_force_params* prm, const float* nodes_dev, float* acc_dev, int32_t pre_reset,

@@ -11,8 +11,9 @@
 // Node gradients reach member particles through com = sum m_k x_k / M and
 // M = sum m_k:  dL/dx_k += (m_k / M) dL/dcom,  dL/dm_k += dL/dM + (x_k - com) . dL/dcom / M.
 //
-// Schedule: one wavefront per task; lanes are sources (nodes, then direct
-// particles), the loop runs over blocks of 8 targets held in registers
+// Schedule: one workgroup of 4 wavefronts per task, splitting its sources;
+// lanes are sources (nodes, then direct particles), the loop runs over
+// blocks of 8 targets held in registers
 // (LDS broadcast), so each lane accumulates its source's gradient across
 // the block and each target's gradient is reduced across the wavefront once
 // per block.  Scatters use hardware FP32 atomics (order-dependent rounding).
@@ -54,6 +55,9 @@ __device__ __forceinline__ int wave_excl_scan(int v, int* total) {
   return inc - v;
 }
 
+// One workgroup of 4 wavefronts per task: wave w takes the task's nodes w, w + 4, ... and the
+// flat direct positions of every fourth group of 64; all gradients are scattered with atomics, so
+// the waves need no reduction among themselves.
 template <bool PACKED>
 __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
   const GravArgs& a = A.f;
@@ -61,7 +65,8 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
   __shared__ int ro[4][64], rb[4][64];
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
-  const int t = uniform(blockIdx.x * 4 + wid);
+  const int W = 4;
+  const int t = uniform(blockIdx.x);
   if (t >= a.n_tasks) return;
   const gc_task tk = a.tasks[t];
   const int ic = tk.i_count;
@@ -91,7 +96,7 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
       tgx[k] = tgy[k] = tgz[k] = 0.f;
     }
     // ---- monopole nodes: lane = node
-    for (int nb = 0; nb < tk.n_count; nb += 64) {
+    for (int nb = wid * 64; nb < tk.n_count; nb += W * 64) {
       const int e = nb + lane;
       const bool valid = e < tk.n_count;
       int nd = -1;
@@ -137,7 +142,7 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
       ro[wid][lane] = lane < nr ? o : 0x7fffffff;
       rb[wid][lane] = g.x;
       wave_sync();
-      for (int f0 = 0; f0 < total; f0 += 64) {
+      for (int f0 = wid * 64; f0 < total; f0 += W * 64) {
         const int f = f0 + lane;
         const bool valid = f < total;
         float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -448,7 +453,7 @@ __global__ void k_lj_mass_grad(const float4* __restrict__ cot, const float4* __r
 hipError_t launch_grav_adjoint(bool packed, const GravAdjArgs& a, int wpb, hipStream_t s) {
   (void)wpb;
   if (a.f.n_tasks <= 0) return hipSuccess;
-  const int grid = (a.f.n_tasks + 3) / 4;
+  const int grid = a.f.n_tasks;
   if (packed) hipLaunchKernelGGL(k_grav_adj<true>, dim3(grid), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_grav_adj<false>, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();

@@ -3,11 +3,12 @@
 // packing gather, and the list remaps (packed ranges, address lists, sorted
 // address lists).
 //
-// Four launches per reorganisation:
+// Three launches per reorganisation:
 //   k_mark   need[id] = 1 over every marked range; also clears the scan state;
-//   k_union  single-pass scan of need (decoupled look-back): pos[id], U, the
-//            missing list, and per union rank its pool slot or -(missing rank+1);
-//   k_free   single-pass scan of the free slots: the first #missing, ascending;
+//   k_scan   two independent single-pass scans (decoupled look-back) in one grid:
+//            over need: pos[id], U, the missing list, and per union rank its pool
+//            slot or -(missing rank+1); over the occupancy flags: the lowest
+//            free slots, ascending, up to a static bound on #missing;
 //   k_apply  staging of missing records into their slots, the packing gather
 //            (or the source gather for redundant transfers), and the range or
 //            address-list remap, in one grid (block ranges split the roles).
@@ -127,13 +128,15 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
 }
 
 // Pool reset: slot_of[0, n_ids) = -1 and occ[0, cap) = 0 in one grid.
-__global__ void k_pool_reset(int32_t* __restrict__ slot_of, int32_t n_ids, int32_t* __restrict__ occ, int32_t cap) {
+__global__ void k_pool_reset(int32_t* __restrict__ slot_of, int32_t n_ids, uint32_t* __restrict__ occ, int32_t cap) {
   const int64_t n = n_ids > cap ? n_ids : cap;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     if (i < n_ids) slot_of[i] = -1;
-    if (i < cap) occ[i] = 0;
+    if (i < cap) occ[i] = 0u;
   }
 }
+
+__device__ __forceinline__ void occ_set(uint32_t* occ, int32_t s) { occ[s] = 1u; }
 
 // One wavefront per range: need[id] = 1.  The grid also zeroes the scan state
 // (look-back words, block counters, result counts) for the launches that follow.
@@ -150,11 +153,11 @@ __global__ void k_mark(const int2* __restrict__ mark, int32_t n_mark, uint8_t* _
 
 // Union of marked ids, position map and missing list.  counts[0] = |U|, counts[1] = #missing.
 // uslot[rank] = pool slot of a resident id, or -(missing rank + 1).
-__global__ void __launch_bounds__(kLBThreads) k_union(uint8_t* __restrict__ need, const int32_t* __restrict__ slot_of,
-                                                      int32_t n, int32_t with_missing, uint64_t* __restrict__ flags,
-                                                      int32_t* __restrict__ ctr, int32_t* __restrict__ pos,
-                                                      int32_t* __restrict__ U, int32_t* __restrict__ uslot,
-                                                      int32_t* __restrict__ missing, int32_t* __restrict__ counts) {
+__device__ __forceinline__ void union_body(uint8_t* __restrict__ need, const int32_t* __restrict__ slot_of, int32_t n,
+                                           int32_t with_missing, uint64_t* __restrict__ flags, int32_t* __restrict__ ctr,
+                                           int32_t* __restrict__ pos, int32_t* __restrict__ U,
+                                           int32_t* __restrict__ uslot, int32_t* __restrict__ missing,
+                                           int32_t* __restrict__ counts, int nblocks) {
   __shared__ int sh[kLBThreads / 64];
   __shared__ int s_bid;
   __shared__ uint32_t s_ex[2];
@@ -185,7 +188,7 @@ __global__ void __launch_bounds__(kLBThreads) k_union(uint8_t* __restrict__ need
     if (threadIdx.x == 0) {
       s_ex[0] = ea;
       s_ex[1] = eb;
-      if (bid == (int)gridDim.x - 1) {
+      if (bid == nblocks - 1) {
         counts[0] = (int32_t)(ea + tu);
         counts[1] = (int32_t)(eb + tm);
       }
@@ -200,7 +203,7 @@ __global__ void __launch_bounds__(kLBThreads) k_union(uint8_t* __restrict__ need
     const int64_t id = base + k;
     if (id >= n) break;
     if ((fu >> k) & 1u) {
-      pos[id] = ru;
+      pos[id] = ru;  // only marked ids get a position; other entries are stale and never read
       U[ru] = (int32_t)id;
       if ((fm >> k) & 1u) {
         uslot[ru] = -(rm + 1);
@@ -209,48 +212,65 @@ __global__ void __launch_bounds__(kLBThreads) k_union(uint8_t* __restrict__ need
         uslot[ru] = sv[k];
       }
       ++ru;
-    } else {
-      pos[id] = -1;
     }
   }
   *reinterpret_cast<uint32_t*>(need + base) = 0u;  // flags left cleared for the next reorganisation
 }
 
-// Free slots ascending: free_list[r] for r < #missing; counts[2] = number of free slots.
-__global__ void __launch_bounds__(kLBThreads) k_free(const int32_t* __restrict__ occ, int32_t cap,
-                                                     uint64_t* __restrict__ flags, int32_t* __restrict__ ctr,
-                                                     int32_t* __restrict__ free_list, int32_t* __restrict__ counts) {
+// Free slots ascending from the occupancy flags (one int per slot, 1 = in use).
+constexpr int kFreeSlotsPerBlock = kLBBlock;
+
+__device__ __forceinline__ void free_body(const uint32_t* __restrict__ occ, int32_t cap, int32_t limit,
+                                          uint64_t* __restrict__ flags, int32_t* __restrict__ ctr,
+                                          int32_t* __restrict__ free_list, int32_t* __restrict__ counts, int nblocks) {
   __shared__ int sh[kLBThreads / 64];
   __shared__ int s_bid;
   __shared__ uint32_t s_ex;
-  const int need = counts[1];
-  if (need == 0) return;  // uniform: nothing to stage
   if (threadIdx.x == 0) s_bid = atomicAdd(ctr, 1);
   __syncthreads();
   const int bid = s_bid;
-  const int64_t base = (int64_t)bid * kLBBlock + (int64_t)threadIdx.x * kLBItems;
+  const int64_t slot0 = (int64_t)bid * kFreeSlotsPerBlock + (int64_t)threadIdx.x * kLBItems;
   uint32_t f = 0;
-  if (base < cap) {
-    int4 o = *reinterpret_cast<const int4*>(occ + base);
-    int ov[4] = {o.x, o.y, o.z, o.w};
+  if (slot0 < cap) {
+    const uint4 o = *reinterpret_cast<const uint4*>(occ + slot0);
+    const uint32_t ov[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (ov[k] == 0 && base + k < cap) f |= 1u << k;
+      if (ov[k] == 0u && slot0 + k < cap) f |= 1u << k;
   }
+  const int c = __popc(f);
   int t;
-  int r = block_excl_scan(__popc(f), sh, &t);
+  int r = block_excl_scan(c, sh, &t);
   if (threadIdx.x < 64) {
     uint32_t ea, eb;
     lb_resolve(flags, bid, (uint32_t)t, 0u, &ea, &eb, counts + 4);
     if (threadIdx.x == 0) {
       s_ex = ea;
-      if (bid == (int)gridDim.x - 1) counts[2] = (int32_t)(ea + t);
+      if (bid == nblocks - 1) counts[2] = (int32_t)(ea + t);
     }
   }
   __syncthreads();
   r += (int)s_ex;
-  for (int k = 0; k < 4 && r < need; ++k)
-    if ((f >> k) & 1u) free_list[r++] = (int32_t)(base + k);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (((f >> k) & 1u) && r < limit) free_list[r++] = (int32_t)(slot0 + k);
+}
+
+// Both scans in one grid: blocks [0, nbu) run the union chain, the rest the free-slot chain
+// (listing the first `limit` free slots, a static upper bound on #missing).  The two chains
+// have their own block counters and look-back words, so neither waits on the other.
+__global__ void __launch_bounds__(kLBThreads) k_scan(uint8_t* __restrict__ need, const int32_t* __restrict__ slot_of,
+                                                     int32_t n, int32_t with_missing, int nbu,
+                                                     uint64_t* __restrict__ flags_u, int32_t* __restrict__ ctr_u,
+                                                     int32_t* __restrict__ pos, int32_t* __restrict__ U,
+                                                     int32_t* __restrict__ uslot, int32_t* __restrict__ missing,
+                                                     const uint32_t* __restrict__ occ, int32_t cap, int32_t limit,
+                                                     uint64_t* __restrict__ flags_f, int32_t* __restrict__ ctr_f,
+                                                     int32_t* __restrict__ free_list, int32_t* __restrict__ counts) {
+  if ((int)blockIdx.x < nbu)
+    union_body(need, slot_of, n, with_missing, flags_u, ctr_u, pos, U, uslot, missing, counts, nbu);
+  else
+    free_body(occ, cap, limit, flags_f, ctr_f, free_list, counts, (int)gridDim.x - nbu);
 }
 
 struct ApplyArgs {
@@ -263,7 +283,7 @@ struct ApplyArgs {
   const float4* src;
   float4* pool;
   int32_t* slot_of;
-  int32_t* occ;
+  uint32_t* occ;
   float4* packed;
   const gc_task* tasks;
   int32_t n_tasks;
@@ -307,7 +327,7 @@ __global__ void __launch_bounds__(256) k_apply(ApplyArgs a) {
           const int32_t s = a.free_list[m];
           a.pool[s] = r;
           a.slot_of[id] = s;
-          a.occ[s] = 1;
+          occ_set(a.occ, s);
         }
         if (a.mode == GC_REORG_PACK) a.packed[k] = r;
       }
@@ -345,12 +365,12 @@ __global__ void __launch_bounds__(256) k_apply(ApplyArgs a) {
 
 __global__ void k_place(const int32_t* __restrict__ ids, const int32_t* __restrict__ slots, int32_t n,
                         const float4* __restrict__ src, float4* __restrict__ pool, int32_t* __restrict__ slot_of,
-                        int32_t* __restrict__ occ) {
+                        uint32_t* __restrict__ occ) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     int id = ids[k], s = slots[k];
     pool[s] = src[id];
     slot_of[id] = s;
-    occ[s] = 1;
+    occ_set(occ, s);
   }
 }
 
@@ -403,6 +423,16 @@ inline int grid_for(int64_t n, int per_block, int cap = 65536) {
 
 int lb_blocks(int32_t n) { return (int)((n + kLBBlock - 1) / kLBBlock) > 0 ? (int)((n + kLBBlock - 1) / kLBBlock) : 1; }
 
+int free_blocks(int32_t cap) {
+  int64_t b = ((int64_t)cap + kFreeSlotsPerBlock - 1) / kFreeSlotsPerBlock;
+  return b > 0 ? (int)b : 1;
+}
+
+int64_t occ_words(int32_t cap) {
+  // one int per slot, padded so that every free-scan thread's 4-slot load stays inside the allocation
+  return (int64_t)free_blocks(cap) * kFreeSlotsPerBlock;
+}
+
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
@@ -415,7 +445,7 @@ hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pool_reset(int32_t* slot_of, int32_t n_ids, int32_t* occ, int32_t cap, hipStream_t s) {
+hipError_t launch_pool_reset(int32_t* slot_of, int32_t n_ids, uint32_t* occ, int32_t cap, hipStream_t s) {
   int64_t n = n_ids > cap ? n_ids : cap;
   hipLaunchKernelGGL(k_pool_reset, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, slot_of, n_ids, occ, cap);
   return hipGetLastError();
@@ -428,23 +458,20 @@ hipError_t launch_mark(const int2* mark, int32_t n_mark, uint8_t* need, int32_t*
   return hipGetLastError();
 }
 
-hipError_t launch_union(uint8_t* need, const int32_t* slot_of, int32_t n, int32_t with_missing, uint64_t* flags,
-                        int32_t* ctr, int32_t* pos, int32_t* U, int32_t* uslot, int32_t* missing, int32_t* counts,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_union, dim3(lb_blocks(n)), dim3(kLBThreads), 0, s, need, slot_of, n, with_missing, flags, ctr,
-                     pos, U, uslot, missing, counts);
-  return hipGetLastError();
-}
-
-hipError_t launch_free(const int32_t* occ, int32_t cap, uint64_t* flags, int32_t* ctr, int32_t* free_list,
-                       int32_t* counts, hipStream_t s) {
-  hipLaunchKernelGGL(k_free, dim3(lb_blocks(cap)), dim3(kLBThreads), 0, s, occ, cap, flags, ctr, free_list, counts);
+hipError_t launch_scan(uint8_t* need, const int32_t* slot_of, int32_t n, int32_t with_missing, uint64_t* flags_u,
+                       int32_t* ctr_u, int32_t* pos, int32_t* U, int32_t* uslot, int32_t* missing, const uint32_t* occ,
+                       int32_t cap, int32_t limit, uint64_t* flags_f, int32_t* ctr_f, int32_t* free_list, int32_t* counts,
+                       hipStream_t s) {
+  const int nbu = lb_blocks(n);
+  const int nbf = with_missing ? free_blocks(cap) : 0;
+  hipLaunchKernelGGL(k_scan, dim3(nbu + nbf), dim3(kLBThreads), 0, s, need, slot_of, n, with_missing, nbu, flags_u,
+                     ctr_u, pos, U, uslot, missing, occ, cap, limit, flags_f, ctr_f, free_list, counts);
   return hipGetLastError();
 }
 
 hipError_t launch_apply(int32_t mode, const int32_t* counts, int32_t bound, const int32_t* U, const int32_t* uslot,
                         const int32_t* free_list, const int32_t* pos, const float4* src, float4* pool, int32_t* slot_of,
-                        int32_t* occ, float4* packed, const gc_task* tasks, int32_t n_tasks, const int2* ranges,
+                        uint32_t* occ, float4* packed, const gc_task* tasks, int32_t n_tasks, const int2* ranges,
                         int32_t n_ranges, int2* pranges, int32_t* pibeg, const int32_t* ioff, const int32_t* joff,
                         int32_t* ilist, int32_t* jlist, hipStream_t s) {
   ApplyArgs a{mode, counts, U, uslot, free_list, pos, src, pool, slot_of, occ, packed, tasks, n_tasks, ranges,
@@ -466,7 +493,7 @@ hipError_t launch_sort_lists(int32_t n_tasks, const int32_t* joff, int32_t* jlis
 }
 
 hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, float4* pool,
-                        int32_t* slot_of, int32_t* occ, hipStream_t s) {
+                        int32_t* slot_of, uint32_t* occ, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_place, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ids, slots, n, src, pool, slot_of, occ);
   return hipGetLastError();

@@ -117,6 +117,8 @@ struct gc_graph_ {
   gc_ctx ctx = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::vector<hipStream_t> side;   // capture-time side streams (combined passes of successive steps overlap)
+  std::vector<hipEvent_t> events;
 };
 
 // ===================================================================== context
@@ -170,14 +172,14 @@ extern "C" gc_status gc_pool_create(gc_ctx ctx, int32_t n_ids, int32_t capacity,
   p->cap = capacity;
   hipError_t e = p->rec.ensure(sizeof(float4) * (size_t)capacity);
   if (e == hipSuccess) e = p->slot_of.ensure(sizeof(int32_t) * (size_t)pad_to(n_ids, kScanBlock));
-  if (e == hipSuccess) e = p->occ.ensure(sizeof(int32_t) * (size_t)pad_to(capacity, kScanBlock));
+  if (e == hipSuccess) e = p->occ.ensure(sizeof(uint32_t) * (size_t)occ_words(capacity));
   if (e != hipSuccess) {
     p->rec.release(); p->slot_of.release(); p->occ.release();
     delete p;
     return set_err(ctx, GC_E_NOMEM, "gc_pool_create: %s", hipGetErrorString(e));
   }
   e = launch_fill_i32(p->slot_of.as<int32_t>(), -1, pad_to(n_ids, kScanBlock), nullptr);
-  if (e == hipSuccess) e = launch_fill_i32(p->occ.as<int32_t>(), 0, pad_to(capacity, kScanBlock), nullptr);
+  if (e == hipSuccess) e = launch_fill_i32(p->occ.as<int32_t>(), 0, occ_words(capacity), nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     p->rec.release(); p->slot_of.release(); p->occ.release();
@@ -232,12 +234,12 @@ extern "C" gc_status gc_pool_place(gc_pool pool, const int32_t* ids_dev, const i
   if (n < 0 || (n > 0 && (!ids_dev || !slots_dev))) return set_err(pool->ctx, GC_E_INVAL, "gc_pool_place: bad arrays");
   if (n > 0 && !pool->src) return set_err(pool->ctx, GC_E_STATE, "gc_pool_place: no source set");
   GC_HIP(pool->ctx, launch_place(ids_dev, slots_dev, n, pool->src, pool->rec.as<float4>(), pool->slot_of.as<int32_t>(),
-                                 pool->occ.as<int32_t>(), S(stream)));
+                                 pool->occ.as<uint32_t>(), S(stream)));
   return GC_OK;
 }
 
 static hipError_t pool_reset_async(gc_pool pool, hipStream_t s) {
-  return launch_pool_reset(pool->slot_of.as<int32_t>(), pool->n_ids, pool->occ.as<int32_t>(), pool->cap, s);
+  return launch_pool_reset(pool->slot_of.as<int32_t>(), pool->n_ids, pool->occ.as<uint32_t>(), pool->cap, s);
 }
 
 extern "C" gc_status gc_pool_reset(gc_pool pool, void* stream) {
@@ -460,7 +462,7 @@ static hipError_t ensure_reorg_buffers(gc_batch b, gc_pool p) {
   if (e == hipSuccess) e = b->uslot.ensure(sizeof(int32_t) * (size_t)bound);
   if (e == hipSuccess) e = b->missing.ensure(sizeof(int32_t) * (size_t)bound);
   if (e == hipSuccess) e = b->free_list.ensure(sizeof(int32_t) * (size_t)bound);
-  b->state_ints = 16 + 2 * lb_blocks(b->n_ids) + 2 * lb_blocks(p->cap);
+  b->state_ints = 16 + 2 * lb_blocks(b->n_ids) + 2 * free_blocks(p->cap);
   if (e == hipSuccess) e = b->state.ensure(sizeof(int32_t) * (size_t)b->state_ints);
   if (e == hipSuccess) e = b->packed.ensure(sizeof(float4) * (size_t)bound);
   if (e == hipSuccess) e = b->pranges.ensure(sizeof(int32_t) * std::max<size_t>(b->ranges.size(), 2));
@@ -485,10 +487,10 @@ static gc_status reorganize_lookup(gc_batch b, gc_pool p, int32_t mode, hipStrea
   uint64_t* flags_f = reinterpret_cast<uint64_t*>(st + 16 + 2 * nbu);
   GC_HIP(c, launch_mark(b->d_mark.as<int2>(), b->n_mark, b->need.as<uint8_t>(), st, b->state_ints, s));
   const bool reuse = (mode != GC_REORG_REDUNDANT);
-  GC_HIP(c, launch_union(b->need.as<uint8_t>(), p->slot_of.as<int32_t>(), b->n_ids, reuse ? 1 : 0, flags_u, st + 8,
-                         b->pos.as<int32_t>(), b->U.as<int32_t>(), b->uslot.as<int32_t>(), b->missing.as<int32_t>(),
-                         st, s));
-  if (reuse) GC_HIP(c, launch_free(p->occ.as<int32_t>(), p->cap, flags_f, st + 9, b->free_list.as<int32_t>(), st, s));
+  GC_HIP(c, launch_scan(b->need.as<uint8_t>(), p->slot_of.as<int32_t>(), b->n_ids, reuse ? 1 : 0, flags_u, st + 8,
+                        b->pos.as<int32_t>(), b->U.as<int32_t>(), b->uslot.as<int32_t>(), b->missing.as<int32_t>(),
+                        p->occ.as<uint32_t>(), p->cap, std::max<int32_t>(b->bound_u, 1), flags_f, st + 9,
+                        b->free_list.as<int32_t>(), st, s));
   return GC_OK;
 }
 
@@ -498,7 +500,7 @@ static gc_status reorganize_apply(gc_batch b, gc_pool p, int32_t mode, hipStream
   const int32_t T = (int32_t)b->tasks.size(), R = (int32_t)(b->ranges.size() / 2);
   GC_HIP(c, launch_apply(mode, counts_of(b), b->bound_u, b->U.as<int32_t>(), b->uslot.as<int32_t>(),
                          b->free_list.as<int32_t>(), b->pos.as<int32_t>(), p->src, p->rec.as<float4>(),
-                         p->slot_of.as<int32_t>(), p->occ.as<int32_t>(), b->packed.as<float4>(),
+                         p->slot_of.as<int32_t>(), p->occ.as<uint32_t>(), b->packed.as<float4>(),
                          b->d_tasks.as<gc_task>(), T, b->d_ranges.as<int2>(), R, b->pranges.as<int2>(),
                          b->pibeg.as<int32_t>(), b->d_ioff.as<int32_t>(), b->d_joff.as<int32_t>(),
                          b->ilist.as<int32_t>(), b->jlist.as<int32_t>(), s));
@@ -574,8 +576,9 @@ extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int3
     if (!dst || !bytes) return hipSuccess;
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
   };
-  GC_HIP(c, dn(U, b->U.p, sizeof(int32_t) * (size_t)nu));
-  GC_HIP(c, dn(pos, b->pos.p, sizeof(int32_t) * (size_t)b->n_ids));
+  // positions: only marked ids carry one on the device; rebuild the full map from U
+  std::vector<int32_t> hU((size_t)std::max(nu, 1));
+  GC_HIP(c, dn(hU.data(), b->U.p, sizeof(int32_t) * (size_t)nu));
   if (b->mode == GC_REORG_REDUNDANT) {
     GC_HIP(c, dn(missing, b->U.p, sizeof(int32_t) * (size_t)nu));
   } else {
@@ -590,6 +593,11 @@ extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int3
     GC_HIP(c, dn(jlist, b->jlist.p, sizeof(int32_t) * (size_t)b->n_direct));
   }
   GC_HIP(c, hipStreamSynchronize(s));
+  if (U) std::memcpy(U, hU.data(), sizeof(int32_t) * (size_t)nu);
+  if (pos) {
+    for (int32_t i = 0; i < b->n_ids; ++i) pos[i] = -1;
+    for (int32_t k = 0; k < nu; ++k) pos[hU[k]] = k;
+  }
   return GC_OK;
 }
 
@@ -807,8 +815,46 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
       GC_HIP(ctx, launch_fill_i32(batches[k]->need.as<int32_t>(), 0, (int64_t)(batches[k]->need.bytes / 4), S(stream)));
   GC_HIP(ctx, hipStreamSynchronize(S(stream)));
   hipStream_t s = S(stream);
-  GC_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  // The combined pass of a step reads only its batch's own buffers unless its records come from
+  // the pool (address-list modes), so those passes can run on side streams and overlap the next
+  // steps' reorganisations and passes; the pool-touching chain stays on the capture stream.
+  bool overlap = n_steps > 1;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    if (modes[k] == GC_REORG_INDIRECT || modes[k] == GC_REORG_SORTED) overlap = false;
+    for (int32_t q = 0; q < k; ++q)
+      if (batches[q] == batches[k]) overlap = false;  // a batch reused later would overwrite buffers in use
+  }
+  gc_graph gr = new gc_graph_();
+  gr->ctx = ctx;
+  auto cleanup = [&]() {
+    for (hipEvent_t e : gr->events) (void)hipEventDestroy(e);
+    for (hipStream_t q : gr->side) (void)hipStreamDestroy(q);
+    delete gr;
+  };
+  const int n_side = overlap ? 3 : 0;
+  for (int q = 0; q < n_side; ++q) {
+    hipStream_t h = nullptr;
+    if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess) {
+      cleanup();
+      return set_err(ctx, GC_E_HIP, "gc_graph_capture: side stream");
+    }
+    gr->side.push_back(h);
+  }
+  for (int q = 0; q < (overlap ? n_steps + n_side : 0); ++q) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return set_err(ctx, GC_E_HIP, "gc_graph_capture: event");
+    }
+    gr->events.push_back(e);
+  }
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(ctx, e, "hipStreamBeginCapture");
+  }
   gc_status st = GC_OK;
+  std::vector<bool> used(n_side, false);
   for (int32_t k = 0; k < n_steps && st == GC_OK; ++k) {
     gc_batch b = batches[k];
     gc_pool p = pools[k];
@@ -816,7 +862,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
       if (pool_reset_async(p, s) != hipSuccess) st = set_err(ctx, GC_E_HIP, "capture: pool reset");
       if (st == GC_OK && place_n && place_n[k] > 0 &&
           launch_place(place_ids[k], place_slots[k], place_n[k], p->src, p->rec.as<float4>(), p->slot_of.as<int32_t>(),
-                       p->occ.as<int32_t>(), s) != hipSuccess)
+                       p->occ.as<uint32_t>(), s) != hipSuccess)
         st = set_err(ctx, GC_E_HIP, "capture: place");
     }
     if (st != GC_OK) break;
@@ -830,22 +876,44 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
       b->mode = modes[k];
       b->pool = p;
     }
-    if (st == GC_OK) st = launch_combined_async(b, prm, nodes_dev, acc_dev, s);
+    if (st != GC_OK) break;
+    hipStream_t fs = s;
+    if (overlap) {
+      const int q = k % n_side;
+      if (hipEventRecord(gr->events[k], s) != hipSuccess ||
+          hipStreamWaitEvent(gr->side[q], gr->events[k], 0) != hipSuccess) {
+        st = set_err(ctx, GC_E_HIP, "capture: fork");
+        break;
+      }
+      fs = gr->side[q];
+      used[q] = true;
+    }
+    st = launch_combined_async(b, prm, nodes_dev, acc_dev, fs);
+  }
+  // join the side streams back into the capture stream
+  for (int q = 0; q < n_side; ++q) {
+    if (!used[q]) continue;
+    if (hipEventRecord(gr->events[n_steps + q], gr->side[q]) != hipSuccess ||
+        hipStreamWaitEvent(s, gr->events[n_steps + q], 0) != hipSuccess)
+      if (st == GC_OK) st = set_err(ctx, GC_E_HIP, "capture: join");
   }
   hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(s, &g);
+  e = hipStreamEndCapture(s, &g);
   if (st != GC_OK) {
     if (g) (void)hipGraphDestroy(g);
+    cleanup();
     return st;
   }
-  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
-  gc_graph gr = new gc_graph_();
-  gr->ctx = ctx;
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(ctx, e, "hipStreamEndCapture");
+  }
   gr->graph = g;
   e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     (void)hipGraphDestroy(g);
-    delete gr;
+    gr->graph = nullptr;
+    cleanup();
     return hip_fail(ctx, e, "hipGraphInstantiate");
   }
   *out = gr;
@@ -863,6 +931,8 @@ extern "C" gc_status gc_graph_destroy(gc_graph g) {
   if (!g) return GC_E_INVAL;
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
+  for (hipStream_t q : g->side) (void)hipStreamDestroy(q);
   delete g;
   return GC_OK;
 }

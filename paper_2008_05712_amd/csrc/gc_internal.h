@@ -75,9 +75,10 @@ int64_t occ_words(int32_t cap);
 int free_blocks(int32_t cap);
 // number of blocks of the single-pass scans over n entries
 int lb_blocks(int32_t n);
-// need[id] = 1 over the marked ranges; zero[0, n_zero) = 0 (scan state for the launches that follow)
-hipError_t launch_mark(const int2* mark, int32_t n_mark, uint8_t* need, int32_t* zero, int32_t n_zero, hipStream_t s);
-hipError_t launch_scan(uint8_t* need, const int32_t* slot_of, int32_t n, int32_t with_missing, uint64_t* flags_u,
+// ids per block of the union scan (the mark windows are computed on the host per block)
+constexpr int kUnionBlockIds = 1024;
+hipError_t launch_scan(const int2* mark, const int2* mwin, const int32_t* slot_of, int32_t n, int32_t with_missing,
+                       uint64_t* flags_u,
                        int32_t* ctr_u, int32_t* pos, int32_t* U, int32_t* uslot, int32_t* missing, const uint32_t* occ,
                        int32_t cap, int32_t limit, uint64_t* flags_f, int32_t* ctr_f, int32_t* free_list, int32_t* counts,
                        hipStream_t s);
@@ -85,7 +86,7 @@ hipError_t launch_apply(int32_t mode, const int32_t* counts, int32_t bound, cons
                         const int32_t* free_list, const int32_t* pos, const float4* src, float4* pool, int32_t* slot_of,
                         uint32_t* occ, float4* packed, const gc_task* tasks, int32_t n_tasks, const int2* ranges,
                         int32_t n_ranges, int2* pranges, int32_t* pibeg, const int32_t* ioff, const int32_t* joff,
-                        int32_t* ilist, int32_t* jlist, hipStream_t s);
+                        int32_t* ilist, int32_t* jlist, int32_t* state, int32_t n_state, hipStream_t s);
 hipError_t launch_sort_lists(int32_t n_tasks, const int32_t* joff, int32_t* jlist, hipStream_t s);
 hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, float4* pool,
                         int32_t* slot_of, uint32_t* occ, hipStream_t s);

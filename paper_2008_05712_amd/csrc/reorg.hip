@@ -3,15 +3,17 @@
 // packing gather, and the list remaps (packed ranges, address lists, sorted
 // address lists).
 //
-// Three launches per reorganisation:
-//   k_mark   need[id] = 1 over every marked range; also clears the scan state;
+// Two launches per reorganisation:
 //   k_scan   two independent single-pass scans (decoupled look-back) in one grid:
-//            over need: pos[id], U, the missing list, and per union rank its pool
+//            over the ids, each block first marking its window of 1024 ids in LDS
+//            from the sorted distinct ranges of the combined request (the chare-table
+//            lookup reads slot_of there): pos[id], U, the missing list, and per union rank its pool
 //            slot or -(missing rank+1); over the occupancy flags: the lowest
 //            free slots, ascending, up to a static bound on #missing;
 //   k_apply  staging of missing records into their slots, the packing gather
 //            (or the source gather for redundant transfers), and the range or
-//            address-list remap, in one grid (block ranges split the roles).
+//            address-list remap, in one grid (block ranges split the roles); it
+//            also clears the scan counters and look-back words for the next call.
 // A per-task sort follows for sorted address lists.  All of it is HBM/L2
 // bound: coalesced flag and index arrays, one 16-byte record per lane.
 #include <climits>
@@ -24,6 +26,7 @@ namespace {
 constexpr int kLBThreads = 256;
 constexpr int kLBItems = 4;
 constexpr int kLBBlock = kLBThreads * kLBItems;  // ids per block
+static_assert(kLBBlock == kUnionBlockIds, "host mark windows assume this block size");
 constexpr uint32_t kSpinLimit = 1u << 24;       // look-back bound: every wave exits
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
@@ -138,37 +141,40 @@ __global__ void k_pool_reset(int32_t* __restrict__ slot_of, int32_t n_ids, uint3
 
 __device__ __forceinline__ void occ_set(uint32_t* occ, int32_t s) { occ[s] = 1u; }
 
-// One wavefront per range: need[id] = 1.  The grid also zeroes the scan state
-// (look-back words, block counters, result counts) for the launches that follow.
-__global__ void k_mark(const int2* __restrict__ mark, int32_t n_mark, uint8_t* __restrict__ need,
-                       int32_t* __restrict__ zero, int32_t n_zero) {
-  const int lane = threadIdx.x & 63;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_zero; i += gridDim.x * blockDim.x) zero[i] = 0;
-  const int waves = gridDim.x * (blockDim.x >> 6);
-  for (int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < n_mark; r += waves) {
-    int2 g = mark[r];
-    for (int k = lane; k < g.y; k += 64) need[g.x + k] = 1;
-  }
-}
-
 // Union of marked ids, position map and missing list.  counts[0] = |U|, counts[1] = #missing.
 // uslot[rank] = pool slot of a resident id, or -(missing rank + 1).
-__device__ __forceinline__ void union_body(uint8_t* __restrict__ need, const int32_t* __restrict__ slot_of, int32_t n,
-                                           int32_t with_missing, uint64_t* __restrict__ flags, int32_t* __restrict__ ctr,
+__device__ __forceinline__ void union_body(const int2* __restrict__ mark, const int2* __restrict__ mwin,
+                                           const int32_t* __restrict__ slot_of, int32_t n, int32_t with_missing,
+                                           uint64_t* __restrict__ flags, int32_t* __restrict__ ctr,
                                            int32_t* __restrict__ pos, int32_t* __restrict__ U,
                                            int32_t* __restrict__ uslot, int32_t* __restrict__ missing,
                                            int32_t* __restrict__ counts, int nblocks) {
   __shared__ int sh[kLBThreads / 64];
   __shared__ int s_bid;
   __shared__ uint32_t s_ex[2];
+  __shared__ uint32_t need[kLBBlock / 4];  // one byte per id of this block's window
   if (threadIdx.x == 0) s_bid = atomicAdd(ctr, 1);
+  need[threadIdx.x] = 0u;
   __syncthreads();
   const int bid = s_bid;
-  const int64_t base = (int64_t)bid * kLBBlock + (int64_t)threadIdx.x * kLBItems;
+  const int64_t wbase = (int64_t)bid * kLBBlock;
+  // mark: the sorted distinct ranges that can reach this window are mark[mwin.x, mwin.y)
+  {
+    const int2 w = mwin[bid];
+    uint8_t* nb = reinterpret_cast<uint8_t*>(need);
+    for (int m = w.x + threadIdx.x; m < w.y; m += blockDim.x) {
+      const int2 g = mark[m];
+      const int64_t a = g.x > wbase ? g.x : wbase;
+      const int64_t e = (int64_t)g.x + g.y < wbase + kLBBlock ? (int64_t)g.x + g.y : wbase + kLBBlock;
+      for (int64_t id = a; id < e; ++id) nb[id - wbase] = 1;
+    }
+  }
+  __syncthreads();
+  const int64_t base = wbase + (int64_t)threadIdx.x * kLBItems;
   uint32_t fu = 0, fm = 0;
   int sv[4] = {-1, -1, -1, -1};
   if (base < n) {
-    uint32_t w = *reinterpret_cast<const uint32_t*>(need + base);
+    const uint32_t w = need[threadIdx.x];
     int4 s4 = *reinterpret_cast<const int4*>(slot_of + base);
     sv[0] = s4.x; sv[1] = s4.y; sv[2] = s4.z; sv[3] = s4.w;
 #pragma unroll
@@ -214,7 +220,6 @@ __device__ __forceinline__ void union_body(uint8_t* __restrict__ need, const int
       ++ru;
     }
   }
-  *reinterpret_cast<uint32_t*>(need + base) = 0u;  // flags left cleared for the next reorganisation
 }
 
 // Free slots ascending from the occupancy flags (one int per slot, 1 = in use).
@@ -259,7 +264,8 @@ __device__ __forceinline__ void free_body(const uint32_t* __restrict__ occ, int3
 // Both scans in one grid: blocks [0, nbu) run the union chain, the rest the free-slot chain
 // (listing the first `limit` free slots, a static upper bound on #missing).  The two chains
 // have their own block counters and look-back words, so neither waits on the other.
-__global__ void __launch_bounds__(kLBThreads) k_scan(uint8_t* __restrict__ need, const int32_t* __restrict__ slot_of,
+__global__ void __launch_bounds__(kLBThreads) k_scan(const int2* __restrict__ mark, const int2* __restrict__ mwin,
+                                                     const int32_t* __restrict__ slot_of,
                                                      int32_t n, int32_t with_missing, int nbu,
                                                      uint64_t* __restrict__ flags_u, int32_t* __restrict__ ctr_u,
                                                      int32_t* __restrict__ pos, int32_t* __restrict__ U,
@@ -268,7 +274,7 @@ __global__ void __launch_bounds__(kLBThreads) k_scan(uint8_t* __restrict__ need,
                                                      uint64_t* __restrict__ flags_f, int32_t* __restrict__ ctr_f,
                                                      int32_t* __restrict__ free_list, int32_t* __restrict__ counts) {
   if ((int)blockIdx.x < nbu)
-    union_body(need, slot_of, n, with_missing, flags_u, ctr_u, pos, U, uslot, missing, counts, nbu);
+    union_body(mark, mwin, slot_of, n, with_missing, flags_u, ctr_u, pos, U, uslot, missing, counts, nbu);
   else
     free_body(occ, cap, limit, flags_f, ctr_f, free_list, counts, (int)gridDim.x - nbu);
 }
@@ -296,6 +302,8 @@ struct ApplyArgs {
   int32_t* ilist;
   int32_t* jlist;
   int32_t blocks_a;  // blocks [0, blocks_a) stage and pack; the rest remap
+  int32_t* state;    // scan state: [8, n_state) (block counters, look-back words) is cleared here
+  int32_t n_state;
 };
 
 // Pool slot of union rank p after staging (0 after a reported capacity overflow).
@@ -309,6 +317,8 @@ __device__ __forceinline__ int32_t slot_of_rank(const ApplyArgs& a, int32_t p, i
 __global__ void __launch_bounds__(256) k_apply(ApplyArgs a) {
   const int32_t nu = a.counts[0];
   const int32_t nfree = a.counts[1] < a.counts[2] ? a.counts[1] : a.counts[2];
+  // the scans are done: leave their counters and look-back words cleared for the next reorganisation
+  for (int i = 8 + blockIdx.x * blockDim.x + threadIdx.x; i < a.n_state; i += gridDim.x * blockDim.x) a.state[i] = 0;
   if ((int)blockIdx.x < a.blocks_a) {
     const int stride = a.blocks_a * blockDim.x;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nu; k += stride) {
@@ -451,20 +461,14 @@ hipError_t launch_pool_reset(int32_t* slot_of, int32_t n_ids, uint32_t* occ, int
   return hipGetLastError();
 }
 
-hipError_t launch_mark(const int2* mark, int32_t n_mark, uint8_t* need, int32_t* zero, int32_t n_zero, hipStream_t s) {
-  int g = grid_for(n_mark > 0 ? n_mark : 1, 4, 16384);
-  int gz = grid_for(n_zero, 256, 16384);
-  hipLaunchKernelGGL(k_mark, dim3(g > gz ? g : gz), dim3(256), 0, s, mark, n_mark, need, zero, n_zero);
-  return hipGetLastError();
-}
-
-hipError_t launch_scan(uint8_t* need, const int32_t* slot_of, int32_t n, int32_t with_missing, uint64_t* flags_u,
+hipError_t launch_scan(const int2* mark, const int2* mwin, const int32_t* slot_of, int32_t n, int32_t with_missing,
+                       uint64_t* flags_u,
                        int32_t* ctr_u, int32_t* pos, int32_t* U, int32_t* uslot, int32_t* missing, const uint32_t* occ,
                        int32_t cap, int32_t limit, uint64_t* flags_f, int32_t* ctr_f, int32_t* free_list, int32_t* counts,
                        hipStream_t s) {
   const int nbu = lb_blocks(n);
   const int nbf = with_missing ? free_blocks(cap) : 0;
-  hipLaunchKernelGGL(k_scan, dim3(nbu + nbf), dim3(kLBThreads), 0, s, need, slot_of, n, with_missing, nbu, flags_u,
+  hipLaunchKernelGGL(k_scan, dim3(nbu + nbf), dim3(kLBThreads), 0, s, mark, mwin, slot_of, n, with_missing, nbu, flags_u,
                      ctr_u, pos, U, uslot, missing, occ, cap, limit, flags_f, ctr_f, free_list, counts);
   return hipGetLastError();
 }
@@ -473,9 +477,9 @@ hipError_t launch_apply(int32_t mode, const int32_t* counts, int32_t bound, cons
                         const int32_t* free_list, const int32_t* pos, const float4* src, float4* pool, int32_t* slot_of,
                         uint32_t* occ, float4* packed, const gc_task* tasks, int32_t n_tasks, const int2* ranges,
                         int32_t n_ranges, int2* pranges, int32_t* pibeg, const int32_t* ioff, const int32_t* joff,
-                        int32_t* ilist, int32_t* jlist, hipStream_t s) {
+                        int32_t* ilist, int32_t* jlist, int32_t* state, int32_t n_state, hipStream_t s) {
   ApplyArgs a{mode, counts, U, uslot, free_list, pos, src, pool, slot_of, occ, packed, tasks, n_tasks, ranges,
-              n_ranges, pranges, pibeg, ioff, joff, ilist, jlist, 0};
+              n_ranges, pranges, pibeg, ioff, joff, ilist, jlist, 0, state, n_state};
   a.blocks_a = grid_for(bound, 256, 4096);
   int blocks_b;
   if (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT)

@@ -100,11 +100,11 @@ struct gc_batch_ {
   int64_t n_direct = 0, n_targets = 0;
   bool committed = false;
   // committed device copies
-  DevBuf d_tasks, d_ranges, d_nodes, d_mark, d_ioff, d_joff, d_order, d_runs;
+  DevBuf d_tasks, d_ranges, d_nodes, d_mark, d_mwin, d_ioff, d_joff, d_order, d_runs;
   int32_t n_runs = 0;
   int32_t n_mark = 0, bound_u = 0, max_direct = 0;
   // reorganisation buffers
-  DevBuf need, pos, U, uslot, missing, free_list, state, packed, pranges, pibeg, ilist, jlist, queue;
+  DevBuf pos, U, uslot, missing, free_list, state, packed, pranges, pibeg, ilist, jlist, queue;
   DevBuf gnode, force;     // adjoint scratch: node gradients, recomputed LJ forces
   int32_t state_ints = 0;  // counts (8) + counters (8) + look-back words of both scans
   // state of the last reorganisation
@@ -283,7 +283,7 @@ extern "C" gc_status gc_batch_create(gc_ctx ctx, int32_t kind, int32_t n_ids, gc
 extern "C" gc_status gc_batch_destroy(gc_batch b) {
   if (!b) return GC_E_INVAL;
   (void)hipDeviceSynchronize();
-  for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_mark, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs, &b->need,
+  for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_mark, &b->d_mwin, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs,
                     &b->pos, &b->U, &b->uslot, &b->missing, &b->free_list, &b->state, &b->packed, &b->pranges,
                     &b->pibeg, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force})
     d->release();
@@ -414,6 +414,22 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   for (auto& m : mk) marked += m.second;
   b->n_mark = (int32_t)mk.size();
   b->bound_u = (int32_t)std::min<int64_t>(b->n_ids, marked);
+  // per union-scan block (kUnionBlockIds ids): the marks that can reach its window, [lo, hi)
+  int32_t maxlen = 1;
+  for (auto& m : mk) maxlen = std::max(maxlen, m.second);
+  const int nbu = lb_blocks(b->n_ids);
+  std::vector<int32_t> mwin(2 * (size_t)nbu);
+  {
+    size_t lo = 0, hi = 0;
+    for (int k = 0; k < nbu; ++k) {
+      const int64_t w0 = (int64_t)k * kUnionBlockIds, w1 = w0 + kUnionBlockIds;
+      while (lo < mk.size() && (int64_t)mk[lo].first + maxlen <= w0) ++lo;
+      if (hi < lo) hi = lo;
+      while (hi < mk.size() && mk[hi].first < w1) ++hi;
+      mwin[2 * k] = (int32_t)lo;
+      mwin[2 * k + 1] = (int32_t)hi;
+    }
+  }
   // longest-processing-time-first order for the persistent schedule
   std::vector<int32_t> order(T > 0 ? T : 1);
   std::iota(order.begin(), order.begin() + T, 0);
@@ -438,6 +454,7 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   up(b->d_ranges, b->ranges.data(), sizeof(int32_t) * b->ranges.size());
   up(b->d_nodes, b->nodes.data(), sizeof(int32_t) * b->nodes.size());
   up(b->d_mark, mk.data(), sizeof(int32_t) * 2 * mk.size());
+  up(b->d_mwin, mwin.data(), sizeof(int32_t) * mwin.size());
   up(b->d_ioff, ioff.data(), sizeof(int32_t) * ioff.size());
   up(b->d_joff, joff.data(), sizeof(int32_t) * joff.size());
   up(b->d_order, order.data(), sizeof(int32_t) * order.size());
@@ -456,8 +473,7 @@ static int32_t* counts_of(gc_batch b) { return b->state.as<int32_t>(); }
 static hipError_t ensure_reorg_buffers(gc_batch b, gc_pool p) {
   const int64_t nid = pad_to(b->n_ids, kScanBlock);
   const int64_t bound = std::max<int32_t>(b->bound_u, 1);
-  hipError_t e = b->need.ensure((size_t)nid);
-  if (e == hipSuccess) e = b->pos.ensure(sizeof(int32_t) * (size_t)nid);
+  hipError_t e = b->pos.ensure(sizeof(int32_t) * (size_t)nid);
   if (e == hipSuccess) e = b->U.ensure(sizeof(int32_t) * (size_t)bound);
   if (e == hipSuccess) e = b->uslot.ensure(sizeof(int32_t) * (size_t)bound);
   if (e == hipSuccess) e = b->missing.ensure(sizeof(int32_t) * (size_t)bound);
@@ -474,20 +490,21 @@ static hipError_t ensure_reorg_buffers(gc_batch b, gc_pool p) {
 }
 
 // Phase A: mark, union + position map + missing list, free-slot list.  Nothing in the pool changes.
-static gc_status reorganize_lookup(gc_batch b, gc_pool p, int32_t mode, hipStream_t s, bool* needs_need_clear) {
+static gc_status reorganize_lookup(gc_batch b, gc_pool p, int32_t mode, hipStream_t s, bool* needs_state_clear) {
   gc_ctx c = b->ctx;
-  size_t need_before = b->need.bytes;
+  size_t state_before = b->state.bytes;
+  const void* state_ptr = b->state.p;
   hipError_t e = ensure_reorg_buffers(b, p);
   if (e != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_reorganize: %s", hipGetErrorString(e));
-  if (b->need.bytes != need_before) *needs_need_clear = true;
-  if (*needs_need_clear) GC_HIP(c, launch_fill_i32(b->need.as<int32_t>(), 0, (int64_t)(b->need.bytes / 4), s));
+  if (b->state.bytes != state_before || b->state.p != state_ptr) *needs_state_clear = true;
+  if (*needs_state_clear) GC_HIP(c, launch_fill_i32(b->state.as<int32_t>(), 0, (int64_t)(b->state.bytes / 4), s));
   int32_t* st = b->state.as<int32_t>();
   const int nbu = lb_blocks(b->n_ids);
   uint64_t* flags_u = reinterpret_cast<uint64_t*>(st + 16);
   uint64_t* flags_f = reinterpret_cast<uint64_t*>(st + 16 + 2 * nbu);
-  GC_HIP(c, launch_mark(b->d_mark.as<int2>(), b->n_mark, b->need.as<uint8_t>(), st, b->state_ints, s));
   const bool reuse = (mode != GC_REORG_REDUNDANT);
-  GC_HIP(c, launch_scan(b->need.as<uint8_t>(), p->slot_of.as<int32_t>(), b->n_ids, reuse ? 1 : 0, flags_u, st + 8,
+  GC_HIP(c, launch_scan(b->d_mark.as<int2>(), b->d_mwin.as<int2>(), p->slot_of.as<int32_t>(), b->n_ids, reuse ? 1 : 0,
+                        flags_u, st + 8,
                         b->pos.as<int32_t>(), b->U.as<int32_t>(), b->uslot.as<int32_t>(), b->missing.as<int32_t>(),
                         p->occ.as<uint32_t>(), p->cap, std::max<int32_t>(b->bound_u, 1), flags_f, st + 9,
                         b->free_list.as<int32_t>(), st, s));
@@ -503,7 +520,7 @@ static gc_status reorganize_apply(gc_batch b, gc_pool p, int32_t mode, hipStream
                          p->slot_of.as<int32_t>(), p->occ.as<uint32_t>(), b->packed.as<float4>(),
                          b->d_tasks.as<gc_task>(), T, b->d_ranges.as<int2>(), R, b->pranges.as<int2>(),
                          b->pibeg.as<int32_t>(), b->d_ioff.as<int32_t>(), b->d_joff.as<int32_t>(),
-                         b->ilist.as<int32_t>(), b->jlist.as<int32_t>(), s));
+                         b->ilist.as<int32_t>(), b->jlist.as<int32_t>(), b->state.as<int32_t>(), b->state_ints, s));
   if (mode == GC_REORG_SORTED) GC_HIP(c, launch_sort_lists(T, b->d_joff.as<int32_t>(), b->jlist.as<int32_t>(), s));
   b->rec = (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT) ? b->packed.as<float4>() : p->rec.as<float4>();
   return GC_OK;
@@ -543,8 +560,11 @@ extern "C" gc_status gc_reorganize(gc_batch b, gc_pool p, int32_t mode, int32_t 
     GC_HIP(c, hipMemcpyAsync(h, b->state.p, sizeof h, hipMemcpyDeviceToHost, s));
     GC_HIP(c, hipStreamSynchronize(s));
     if (h[4]) return set_err(c, GC_E_HIP, "gc_reorganize: a scan block did not complete");
-    if (h[1] > h[2])
+    if (h[1] > h[2]) {
+      // the apply step that would clear the scan state does not run: clear it here
+      GC_HIP(c, launch_fill_i32(b->state.as<int32_t>() + 8, 0, (int64_t)b->state_ints - 8, s));
       return set_err(c, GC_E_FULL, "gc_reorganize: %d records missing but only %d pool slots free", h[1], h[2]);
+    }
   }
   st = reorganize_apply(b, p, mode, s);
   if (st != GC_OK) return st;
@@ -809,10 +829,10 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
       return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: buffers");
     if (batches[k]->queue.ensure(16) != hipSuccess) return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: queue");
   }
-  // flags start cleared: clear once outside the capture
+  // the scan state starts cleared: clear it once outside the capture (each replay's apply step clears it again)
   for (int32_t k = 0; k < n_steps; ++k)
     if (modes[k] != GC_REORG_NONE)
-      GC_HIP(ctx, launch_fill_i32(batches[k]->need.as<int32_t>(), 0, (int64_t)(batches[k]->need.bytes / 4), S(stream)));
+      GC_HIP(ctx, launch_fill_i32(batches[k]->state.as<int32_t>(), 0, (int64_t)(batches[k]->state.bytes / 4), S(stream)));
   GC_HIP(ctx, hipStreamSynchronize(S(stream)));
   hipStream_t s = S(stream);
   // The combined pass of a step reads only its batch's own buffers unless its records come from

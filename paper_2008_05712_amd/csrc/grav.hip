@@ -156,6 +156,9 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
   const int per_wave = rec_cap + 96;
   float4* L = smem + wid * per_wave;
   double* red = reinterpret_cast<double*>(L + rec_cap);
+  // the range tables of the direct phase share the reduction scratch (live at different times)
+  int* RO = reinterpret_cast<int*>(red);  // range start offsets within the group (64)
+  int* RB = RO + 64;                      // range begins (64)
 
   int iter = 0;
   while (true) {
@@ -251,7 +254,9 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
           wave_sync();
         }
       } else {
-        // this wave's ranges are entries w, w + W, ... of the task's range list
+        // this wave's ranges are entries w, w + W, ... of the task's range list; groups of up to
+        // 64 ranges are flattened by a wave scan, and each lane copies one flat position,
+        // finding its range by binary search over the offsets kept in LDS
         const int nrw = tk.j_nranges > wid ? (tk.j_nranges - wid + W - 1) / W : 0;
         const int2* rl = a.ranges + tk.j_first + wid;
         for (int rg = 0; rg < nrw; rg += 64) {
@@ -261,15 +266,27 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
           int total;
           const int o = wave_excl_scan(g.y, &total);
           total = uniform(total);
+          RO[lane] = lane < nr ? o : 0x7fffffff;
+          RB[lane] = g.x;
+          wave_sync();
           for (int ws = 0; ws < total; ws += tile) {
             const int cnt = total - ws < tile ? total - ws : tile;
             const int C = (cnt + S - 1) / S;
             const int padded = S * C;
-            // each lane copies the part of its range inside the window [ws, ws + cnt)
-            const int k0 = ws - o > 0 ? ws - o : 0;
-            const int k1 = ws + cnt - o < g.y ? ws + cnt - o : g.y;
-            for (int k = k0; k < k1; ++k) L[o + k - ws] = a.rec[g.x + k];
-            for (int e = cnt + lane; e < padded; e += 64) L[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int e = lane; e < padded; e += 64) {
+              float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+              if (e < cnt) {
+                const int f = ws + e;
+                int lo = 0, hi = nr - 1;
+                while (lo < hi) {
+                  const int mid = (lo + hi + 1) >> 1;
+                  if (RO[mid] <= f) lo = mid;
+                  else hi = mid - 1;
+                }
+                v = a.rec[RB[lo] + (f - RO[lo])];
+              }
+              L[e] = v;
+            }
             wave_sync();
             if (active) {
               float ax = 0.f, ay = 0.f, az = 0.f;

@@ -103,6 +103,25 @@ gc_status gc_pool_place(gc_pool pool, const int32_t* ids_dev, const int32_t* slo
 /* Evict every record (all slots free, slot_of all -1). Asynchronous. */
 gc_status gc_pool_reset(gc_pool pool, void* stream);
 
+/*
+ * Evict ids_dev[0, n) (device int32): each resident id leaves the table and
+ * its slot becomes free; ids outside [0, n_ids) or not resident are skipped.
+ * The record data stay in the slot until a later staging overwrites them.
+ * Asynchronous on `stream`.
+ */
+gc_status gc_pool_evict(gc_pool pool, const int32_t* ids_dev, int32_t n, void* stream);
+
+/*
+ * Evict the records that the last reorganisation of `batch` (PACK, INDIRECT
+ * or SORTED, against this pool) staged, i.e. its missing list; the count is
+ * read on the device, so the call is graph-capture safe and never
+ * synchronises.  A no-op after REDUNDANT or NONE or before any
+ * reorganisation of the batch; GC_E_STATE if the batch was last reorganised
+ * against another pool.  Used to keep a pool at a
+ * base residency across rounds (staged data treated as transient).
+ */
+gc_status gc_pool_evict_staged(gc_pool pool, gc_batch batch, void* stream);
+
 /* Copy slot_of (n_ids int32) to host memory; synchronises `stream`. */
 gc_status gc_pool_query(gc_pool pool, int32_t* slot_of_host, void* stream);
 
@@ -155,8 +174,15 @@ gc_status gc_batch_reset(gc_batch batch);
 gc_status gc_submit_tasks(gc_batch batch, const gc_task* tasks, int32_t n_tasks, const int32_t* j_ranges,
                           int32_t n_ranges, const int32_t* node_idx, int32_t n_node_refs);
 
-/* Upload the submitted tasks to the device (once; later calls are no-ops
- * until the next submit or reset).  Asynchronous on `stream`. */
+/*
+ * Fix the batch (once; later calls are no-ops until the next submit or
+ * reset): the union U of the batch, i.e. the ids of every target and direct
+ * range, ascending and without duplicates (Sec. 3.2: the runtime keeps the
+ * request's indices sorted as they are inserted), is built on the host
+ * together with each range's and each task's first position in U (a range
+ * is contiguous in U), and uploaded with the tasks.  Synchronises `stream`
+ * (the host arrays are released on return).
+ */
 gc_status gc_batch_commit(gc_batch batch, void* stream);
 
 /* Number of tasks, ranges, node refs, direct entries (sum of range counts) and targets. */
@@ -164,11 +190,11 @@ gc_status gc_batch_sizes(gc_batch batch, int64_t* out5);
 
 /*
  * Reorganisation (Sec. 3.2) of a committed batch against a pool, on `stream`:
- *  a. mark every id of every target and direct range;
- *  b. union U = marked ids ascending (the sorted index array), pos[id] = rank
- *     in U, missing = ids of U not resident, ascending (chare-table lookup);
+ *  a. U and pos[id] = rank in U are those fixed at commit;
+ *  b. missing = ids of U not resident, ascending (chare-table lookup);
  *  c. the k-th missing id gets the k-th lowest free slot; its record is copied
  *     from the pool's source into that slot (it stays resident afterwards);
+ *     steps b and c and the PACK gather run as one kernel launch;
  *  d. then, by mode:
  *   GC_REORG_PACK      packed[k] = pool[slot_of[U[k]]] for k < |U|; every
  *                      range (b, c) becomes (pos[b], c) and targets read
@@ -183,10 +209,13 @@ gc_status gc_batch_sizes(gc_batch batch, int64_t* out5);
  *                      is not touched;
  *   GC_REORG_NONE      no reorganisation: the source must be device memory
  *                      and is read in place by id.
- * Returns GC_E_FULL (pool unchanged) if the pool lacks free slots; this check
- * synchronises the stream (the host needs the missing count).  With
- * check_capacity = 0 the call never synchronises; the caller then guarantees
- * capacity (e.g. capacity >= n_ids).
+ * With check_capacity != 0 the missing and free counts are taken first and
+ * GC_E_FULL is returned (pool unchanged) if the pool lacks free slots; this
+ * synchronises the stream.  With check_capacity = 0 the call never
+ * synchronises; a missing record left without a slot is then still packed
+ * from the source (PACK), gets slot 0 in address lists, is not made
+ * resident, and gc_batch_maps reports GC_E_FULL.  Reorganisations of
+ * batches sharing a pool must not run concurrently.
  */
 enum { GC_REORG_REDUNDANT = 0, GC_REORG_INDIRECT = 1, GC_REORG_SORTED = 2, GC_REORG_PACK = 3, GC_REORG_NONE = 4 };
 gc_status gc_reorganize(gc_batch batch, gc_pool pool, int32_t mode, int32_t check_capacity, void* stream);
@@ -278,19 +307,29 @@ gc_status gc_backward(gc_batch batch, const gc_force_params* prm, const float* n
 /*
  * Capture a sequence of (reorganise, combined pass) steps over several
  * batches into one HIP graph on `stream` and instantiate it.  Each step k:
- * gc_reorganize(batches[k], pools[k], modes[k], check_capacity = 0) then
- * gc_launch_combined(batches[k], prm, nodes_dev, acc_dev).  Batches must be
- * committed.  pre_reset != 0 resets each pool before its step (so every
- * replay starts from the same residency; placements given with
- * place_ids/place_slots/place_n per step are re-applied after the reset).
+ * an optional residency fixture, gc_reorganize(batches[k], pools[k],
+ * modes[k], check_capacity = 0), then gc_launch_combined(batches[k], prm,
+ * nodes_dev, acc_dev).  Batches must be committed; their reorganisation
+ * state is cleared once at capture.  Fixtures:
+ *   GC_FIXTURE_NONE          residency carries over from step to step;
+ *   GC_FIXTURE_RESET_PLACE   each pool is reset before its step and the
+ *                            placements place_ids/place_slots/place_n of
+ *                            that step are applied (every replay starts
+ *                            from the same residency);
+ *   GC_FIXTURE_EVICT_STAGED  before step k the records staged by step k-1
+ *                            (cyclically: step 0 evicts those of the last
+ *                            step of the previous replay) are evicted, so a
+ *                            base residency set up by the caller holds at
+ *                            every step (one pool for all steps).
  * When every step uses PACK, REDUNDANT or NONE and no batch appears twice,
  * each step's combined pass reads only its own batch's buffers, so it is
  * placed on a side stream and overlaps the following steps' reorganisations
  * and passes (the pool-touching chain stays in order); otherwise the steps
  * run strictly in sequence.  The graph owns its side streams.
  */
+enum { GC_FIXTURE_NONE = 0, GC_FIXTURE_RESET_PLACE = 1, GC_FIXTURE_EVICT_STAGED = 2 };
 gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* batches, gc_pool* pools, const int32_t* modes,
-                           const gc_force_params* prm, const float* nodes_dev, float* acc_dev, int32_t pre_reset,
+                           const gc_force_params* prm, const float* nodes_dev, float* acc_dev, int32_t fixture,
                            const int32_t* const* place_ids, const int32_t* const* place_slots,
                            const int32_t* place_n, void* stream, gc_graph* out);
 gc_status gc_graph_launch(gc_graph graph, void* stream);

@@ -16,7 +16,7 @@ import numpy as np
 __all__ = ["GcError", "lib", "Context", "Pool", "Batch", "Graph", "ForceParams", "TASK_DTYPE",
            "REORG_REDUNDANT", "REORG_INDIRECT", "REORG_SORTED", "REORG_PACK", "REORG_NONE",
            "FORCE_GRAV_MONO", "FORCE_GRAV_QUAD", "FORCE_LJ", "KIND_GRAV", "KIND_LJ", "TASK_SELF",
-           "LIB_PATH", "EXPORTED"]
+           "FIXTURE_NONE", "FIXTURE_RESET_PLACE", "FIXTURE_EVICT_STAGED", "LIB_PATH", "EXPORTED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgcharm.so")
@@ -26,13 +26,15 @@ KIND_GRAV, KIND_LJ = 0, 1
 TASK_SELF = 1
 REORG_REDUNDANT, REORG_INDIRECT, REORG_SORTED, REORG_PACK, REORG_NONE = 0, 1, 2, 3, 4
 FORCE_GRAV_MONO, FORCE_GRAV_QUAD, FORCE_LJ = 1, 2, 3
+FIXTURE_NONE, FIXTURE_RESET_PLACE, FIXTURE_EVICT_STAGED = 0, 1, 2
 
 # gc_task: 7 int32 + 3 float32 = 40 bytes
 TASK_DTYPE = np.dtype([("i_begin", "<i4"), ("i_count", "<i4"), ("j_first", "<i4"), ("j_nranges", "<i4"),
                        ("n_first", "<i4"), ("n_count", "<i4"), ("flags", "<i4"), ("shift", "<f4", (3,))])
 
 EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_pool_create", "gc_pool_destroy",
-            "gc_pool_set_source", "gc_pool_place", "gc_pool_reset", "gc_pool_query", "gc_pool_device_ptrs",
+            "gc_pool_set_source", "gc_pool_place", "gc_pool_reset", "gc_pool_evict", "gc_pool_evict_staged",
+            "gc_pool_query", "gc_pool_device_ptrs",
             "gc_batch_create", "gc_batch_destroy", "gc_batch_reset", "gc_submit_tasks", "gc_batch_commit",
             "gc_batch_sizes", "gc_reorganize", "gc_batch_maps", "gc_launch_combined", "gc_zero_f32", "gc_backward",
             "gc_graph_capture", "gc_graph_launch", "gc_graph_destroy", "gc_autotune", "gc_occupancy"]
@@ -85,6 +87,8 @@ def lib():
         "gc_pool_set_source": (I32, [VP, VP]),
         "gc_pool_place": (I32, [VP, VP, VP, I32, VP]),
         "gc_pool_reset": (I32, [VP, VP]),
+        "gc_pool_evict": (I32, [VP, VP, I32, VP]),
+        "gc_pool_evict_staged": (I32, [VP, VP, VP]),
         "gc_pool_query": (I32, [VP, VP, VP]),
         "gc_pool_device_ptrs": (I32, [VP, ctypes.POINTER(VP), ctypes.POINTER(VP)]),
         "gc_batch_create": (I32, [VP, I32, I32, ctypes.POINTER(VP)]),
@@ -185,6 +189,13 @@ class Pool:
 
     def reset(self, stream=None):
         self.ctx.check(lib().gc_pool_reset(self.h, _stream(stream)), "gc_pool_reset")
+
+    def evict(self, ids_dev, stream=None):
+        self.ctx.check(lib().gc_pool_evict(self.h, _ptr(ids_dev), int(ids_dev.numel()), _stream(stream)),
+                       "gc_pool_evict")
+
+    def evict_staged(self, batch, stream=None):
+        self.ctx.check(lib().gc_pool_evict_staged(self.h, batch.h, _stream(stream)), "gc_pool_evict_staged")
 
     def query(self, stream=None) -> np.ndarray:
         out = np.empty(self.n_ids, np.int32)
@@ -291,13 +302,16 @@ class Graph:
     """A captured sequence of (reorganise, combined pass) steps (gc_graph_*)."""
 
     def __init__(self, ctx: Context, batches, pools, modes, prm: ForceParams, nodes, acc, pre_reset: bool = False,
-                 places=None, stream=None):
+                 places=None, stream=None, fixture: int | None = None):
+        """fixture: FIXTURE_* (default: RESET_PLACE when pre_reset, else NONE)."""
         n = len(batches)
         self.ctx = ctx
         self.h = VP()
         B = (VP * n)(*[b.h.value for b in batches])
         P = (VP * n)(*[p.h.value for p in pools])
         M = np.ascontiguousarray(modes, np.int32)
+        if fixture is None:
+            fixture = FIXTURE_RESET_PLACE if pre_reset else FIXTURE_NONE
         if places is not None:
             self._keep = places
             ids = (VP * n)(*[_ptr(pl[0]) for pl in places])
@@ -309,7 +323,7 @@ class Graph:
             ids = sl = None
             pn_ptr = None
         self.ctx.check(lib().gc_graph_capture(ctx.h, n, B, P, M.ctypes.data, ctypes.byref(prm), _ptr(nodes), _ptr(acc),
-                                              1 if pre_reset else 0, ids, sl, pn_ptr, _stream(stream),
+                                              fixture, ids, sl, pn_ptr, _stream(stream),
                                               ctypes.byref(self.h)), "gc_graph_capture")
 
     def launch(self, stream=None):

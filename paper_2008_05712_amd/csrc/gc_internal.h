@@ -12,9 +12,6 @@
 namespace gc {
 
 constexpr int kWave = 64;
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;                          // ids per thread in the scan kernels
-constexpr int kScanBlock = kScanThreads * kScanItems;   // ids per scan block
 constexpr int kNodeTile = 64;                           // node records per wavefront tile
 constexpr int kMaxTile = 1024;                          // direct records per wavefront tile (upper bound)
 constexpr int kSortMax = 8192;                          // longest per-task list sorted in LDS
@@ -70,23 +67,46 @@ struct LJArgs {
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 hipError_t launch_pool_reset(int32_t* slot_of, int32_t n_ids, uint32_t* occ, int32_t cap, hipStream_t s);
-// occupancy entries (one per slot, padded) allocated for a pool of `cap` slots; blocks of the free-slot scan
+// Reorganisation state (int32 words per batch): the host reads [0, 8) after a call.
+constexpr int GC_STATE_UNION = 0;    // |U|
+constexpr int GC_STATE_MISSING = 1;  // records of U that were not resident
+constexpr int GC_STATE_FREE = 2;     // free pool slots before the call
+constexpr int GC_STATE_ERR = 4;      // nonzero: a wait hit its bound (sticky)
+constexpr int GC_STATE_CHECK = 6;    // [6, 8): capacity check counts (missing, free)
+
+struct ReorgArgs {
+  const int32_t* U;        // sorted union, padded to whole union blocks
+  int32_t u;
+  const float4* src;       // source records by id
+  float4* pool;
+  int32_t* slot_of;
+  uint32_t* occ;           // padded to whole free-scan blocks
+  int32_t cap;
+  int32_t pack;            // write packed[k] for every union entry
+  float4* packed;
+  int32_t* uslot;          // per union rank: pool slot (-1: missing and no free slot)
+  int32_t* missing;        // ids of the missing records, ascending
+  int32_t* mslot;          // their slots (-1: none)
+  uint64_t* free_list;     // tagged free-slot entries, |U| of them
+  int32_t* state;
+  int32_t nbf, nbu;        // set by the launcher
+};
+
+// occupancy entries (one per slot, padded) allocated for a pool of `cap` slots
 int64_t occ_words(int32_t cap);
 int free_blocks(int32_t cap);
-// number of blocks of the single-pass scans over n entries
-int lb_blocks(int32_t n);
-// ids per block of the union scan (the mark windows are computed on the host per block)
-constexpr int kUnionBlockIds = 1024;
-hipError_t launch_scan(const int2* mark, const int2* mwin, const int32_t* slot_of, int32_t n, int32_t with_missing,
-                       uint64_t* flags_u,
-                       int32_t* ctr_u, int32_t* pos, int32_t* U, int32_t* uslot, int32_t* missing, const uint32_t* occ,
-                       int32_t cap, int32_t limit, uint64_t* flags_f, int32_t* ctr_f, int32_t* free_list, int32_t* counts,
-                       hipStream_t s);
-hipError_t launch_apply(int32_t mode, const int32_t* counts, int32_t bound, const int32_t* U, const int32_t* uslot,
-                        const int32_t* free_list, const int32_t* pos, const float4* src, float4* pool, int32_t* slot_of,
-                        uint32_t* occ, float4* packed, const gc_task* tasks, int32_t n_tasks, const int2* ranges,
-                        int32_t n_ranges, int2* pranges, int32_t* pibeg, const int32_t* ioff, const int32_t* joff,
-                        int32_t* ilist, int32_t* jlist, int32_t* state, int32_t n_state, hipStream_t s);
+int union_blocks(int32_t u);
+int64_t union_padded(int32_t u);
+int32_t reorg_state_ints(int32_t u, int32_t cap);
+hipError_t launch_reorg(ReorgArgs a, hipStream_t s);
+hipError_t launch_gather_src(const int32_t* U, int32_t u, const float4* src, float4* packed, int32_t* state,
+                             hipStream_t s);
+hipError_t launch_lists(const int32_t* irank, int64_t n_i, const int32_t* jrank, int64_t n_j, const int32_t* uslot,
+                        int32_t* ilist, int32_t* jlist, hipStream_t s);
+hipError_t launch_count(const int32_t* U, int32_t u, const int32_t* slot_of, const uint32_t* occ, int32_t cap,
+                        int32_t* out, hipStream_t s);
+hipError_t launch_evict(const int32_t* ids, const int32_t* n_dev, int32_t n_bound, int32_t* slot_of, int32_t n_ids,
+                        uint32_t* occ, hipStream_t s);
 hipError_t launch_sort_lists(int32_t n_tasks, const int32_t* joff, int32_t* jlist, hipStream_t s);
 hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, float4* pool,
                         int32_t* slot_of, uint32_t* occ, hipStream_t s);
@@ -119,6 +139,5 @@ struct LJAdjArgs {
 hipError_t launch_lj_adjoint(const LJAdjArgs& a, int waves_per_block, hipStream_t s);
 hipError_t launch_lj_mass_grad(const float4* cot, const float4* force, const float* mass_t,
                                const float4* rec_by_id, float* gmass, int32_t n, hipStream_t s);
-hipError_t launch_slot_to_id(const int32_t* slot_of, int32_t n_ids, int32_t* id_of_slot, hipStream_t s);
 
 }  // namespace gc

@@ -1,21 +1,27 @@
-// Reorganisation kernels (Sec. 3.2): residency lookup and marking, the sorted
-// union of accessed ids, slot assignment and staging of missing records, the
-// packing gather, and the list remaps (packed ranges, address lists, sorted
-// address lists).
+// Reorganisation kernels (Sec. 3.2): residency lookup of the combined
+// request's union in the chare table, slot assignment and staging of missing
+// records, the packing gather (or the source gather for redundant transfers),
+// the address-list remaps, and eviction.
 //
-// Two launches per reorganisation:
-//   k_scan   two independent single-pass scans (decoupled look-back) in one grid:
-//            over the ids, each block first marking its window of 1024 ids in LDS
-//            from the sorted distinct ranges of the combined request (the chare-table
-//            lookup reads slot_of there): pos[id], U, the missing list, and per union rank its pool
-//            slot or -(missing rank+1); over the occupancy flags: the lowest
-//            free slots, ascending, up to a static bound on #missing;
-//   k_apply  staging of missing records into their slots, the packing gather
-//            (or the source gather for redundant transfers), and the range or
-//            address-list remap, in one grid (block ranges split the roles); it
-//            also clears the scan counters and look-back words for the next call.
-// A per-task sort follows for sorted address lists.  All of it is HBM/L2
-// bound: coalesced flag and index arrays, one 16-byte record per lane.
+// The union U of a batch (sorted distinct ids over its target and direct
+// ranges) and every position in it are fixed when the batch is committed: the
+// host builds them once, as the runtime keeps its index lists sorted on
+// insertion.  What depends on the pool's state is done here, in one launch:
+//   k_reorg  blocks take tickets in dispatch order.  The first tickets scan the
+//            occupancy flags for free slots (ascending), the rest look up their
+//            chunk of U in slot_of.  Each side is a single-pass scan with
+//            decoupled look-back; a union block then takes, for its k-th missing
+//            record overall, the k-th free slot from the free-slot blocks'
+//            published list, stages the record there and writes the packed
+//            copy of every union entry it owns.
+// Every status word and free-list entry carries the tag of the call that wrote
+// it, so nothing has to be cleared between calls; the last block to finish
+// advances the tag and rewinds the two counters.  Union blocks only wait on
+// free-slot blocks, which hold earlier tickets and so are already running: no
+// wait can depend on a block that has not been dispatched.  Every wait is
+// bounded (an error flag is raised instead of hanging).
+// Address lists (indirect and sorted modes) are one more coalesced pass over
+// the static union ranks of the list entries, plus a per-task sort.
 #include <climits>
 
 #include "gc_internal.h"
@@ -23,11 +29,15 @@
 namespace gc {
 namespace {
 
-constexpr int kLBThreads = 256;
-constexpr int kLBItems = 4;
-constexpr int kLBBlock = kLBThreads * kLBItems;  // ids per block
-static_assert(kLBBlock == kUnionBlockIds, "host mark windows assume this block size");
-constexpr uint32_t kSpinLimit = 1u << 24;       // look-back bound: every wave exits
+constexpr int kRThreads = 256;
+constexpr int kUItems = 8;                          // union entries per thread
+constexpr int kUBlock = kRThreads * kUItems;        // union entries per block
+constexpr int kFItems = 16;                         // occupancy entries per thread
+constexpr int kFBlock = kRThreads * kFItems;        // pool slots per free-scan block
+constexpr uint32_t kSpinLimit = 1u << 22;           // bound on every wait: each wave exits
+
+// state[] layout (int32 units); see gc_internal.h for the host-visible part
+constexpr int kTicket = 8, kDone = 9, kTag = 10, kFreeTotal = 12, kLookBack = 16;
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -57,69 +67,63 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh_wave, int* total) 
   return off + inc - v;
 }
 
-// Look-back status words: bits 0-1 status (0 empty, 1 block aggregate, 2 inclusive prefix),
-// bits 2-32 first count, bits 33-63 second count (each < 2^31).
-__device__ __forceinline__ uint64_t lb_pack(uint32_t st, uint32_t a, uint32_t b) {
-  return (uint64_t)st | ((uint64_t)a << 2) | ((uint64_t)b << 33);
+// Tagged 64-bit words: bits 0-30 a count, bit 31 a flag, bits 32-63 the call tag.  Relaxed
+// device-scope atomics: each word carries its own payload, nothing else is published through it
+// (acquire/release here would write back and invalidate the caches on every probe).
+__device__ __forceinline__ uint64_t tword(uint32_t tag, uint32_t flag, uint32_t cnt) {
+  return ((uint64_t)tag << 32) | ((uint64_t)flag << 31) | (uint64_t)cnt;
 }
-
-// A status word carries its own payload, so relaxed device-scope atomics suffice (no other
-// memory is published through it); acquire/release here would write back and invalidate caches.
-__device__ __forceinline__ void lb_store(uint64_t* p, uint64_t v) {
+__device__ __forceinline__ void tstore(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t tload(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t iload(int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void istore(int32_t* p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint64_t lb_load(uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Wavefront 0 of block `bid`: publish the block aggregate (a, b), look back over up to 64
-// predecessors per step (one lane each: the run up to the nearest inclusive prefix is summed
-// once none of it is still empty), publish the inclusive prefix.  Sets err[0] if a
-// predecessor never publishes within the spin bound (not expected; keeps every wave finite).
-__device__ __forceinline__ void lb_resolve(uint64_t* flags, int bid, uint32_t a, uint32_t b, uint32_t* ea,
-                                           uint32_t* eb, int32_t* err) {
+// Wavefront 0 of chain block `bid`: publish the block aggregate, look back over up to 64
+// predecessors per probe (a word of another call counts as not yet written; the run up to the
+// nearest inclusive prefix is summed once all of it is written), publish the inclusive prefix,
+// return the exclusive prefix.
+__device__ __forceinline__ uint32_t look_back(uint64_t* flags, int bid, uint32_t tag, uint32_t agg, int32_t* err) {
   const int lane = threadIdx.x & 63;
   if (bid == 0) {
-    if (lane == 0) lb_store(flags, lb_pack(2, a, b));
-    *ea = 0;
-    *eb = 0;
-    return;
+    if (lane == 0) tstore(flags, tword(tag, 1, agg));
+    return 0;
   }
-  if (lane == 0) lb_store(flags + bid, lb_pack(1, a, b));
-  uint32_t xa = 0, xb = 0, spins = 0;
+  if (lane == 0) tstore(flags + bid, tword(tag, 0, agg));
+  uint32_t x = 0, spins = 0;
   int hi = bid - 1;
   while (true) {
     const int j = hi - lane;
-    const uint64_t w = j >= 0 ? lb_load(flags + j) : lb_pack(2, 0, 0);  // before block 0: a zero prefix
-    const uint32_t st = (uint32_t)(w & 3u);
-    const uint64_t pre = __ballot(st == 2);
-    const uint64_t emp = __ballot(st == 0);
+    const uint64_t w = j >= 0 ? tload(flags + j) : tword(tag, 1, 0);  // before block 0: a zero prefix
+    const bool mine = (uint32_t)(w >> 32) == tag;
+    const uint64_t pre = __ballot(mine && ((w >> 31) & 1u));
+    const uint64_t emp = __ballot(!mine);
     const int stop = pre ? __builtin_ctzll(pre) : 63;  // last lane of the run to sum
     const uint64_t run = stop == 63 ? ~0ull : ((2ull << stop) - 1ull);
     if (emp & run) {
       if (++spins > kSpinLimit) {
-        if (lane == 0) err[0] = 1;
+        if (lane == 0) istore(err, 1);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    uint32_t va = lane <= stop ? (uint32_t)((w >> 2) & 0x7fffffffu) : 0u;
-    uint32_t vb = lane <= stop ? (uint32_t)(w >> 33) : 0u;
+    uint32_t v = lane <= stop ? (uint32_t)(w & 0x7fffffffu) : 0u;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      va += __shfl_xor(va, off, 64);
-      vb += __shfl_xor(vb, off, 64);
-    }
-    xa += va;
-    xb += vb;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    x += v;
     if (pre) break;
     hi -= 64;
   }
-  if (lane == 0) lb_store(flags + bid, lb_pack(2, xa + a, xb + b));
-  *ea = xa;
-  *eb = xb;
+  if (lane == 0) tstore(flags + bid, tword(tag, 1, x + agg));
+  return x;
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
@@ -139,237 +143,239 @@ __global__ void k_pool_reset(int32_t* __restrict__ slot_of, int32_t n_ids, uint3
   }
 }
 
-__device__ __forceinline__ void occ_set(uint32_t* occ, int32_t s) { occ[s] = 1u; }
-
-// Union of marked ids, position map and missing list.  counts[0] = |U|, counts[1] = #missing.
-// uslot[rank] = pool slot of a resident id, or -(missing rank + 1).
-__device__ __forceinline__ void union_body(const int2* __restrict__ mark, const int2* __restrict__ mwin,
-                                           const int32_t* __restrict__ slot_of, int32_t n, int32_t with_missing,
-                                           uint64_t* __restrict__ flags, int32_t* __restrict__ ctr,
-                                           int32_t* __restrict__ pos, int32_t* __restrict__ U,
-                                           int32_t* __restrict__ uslot, int32_t* __restrict__ missing,
-                                           int32_t* __restrict__ counts, int nblocks) {
-  __shared__ int sh[kLBThreads / 64];
-  __shared__ int s_bid;
-  __shared__ uint32_t s_ex[2];
-  __shared__ uint32_t need[kLBBlock / 4];  // one byte per id of this block's window
-  if (threadIdx.x == 0) s_bid = atomicAdd(ctr, 1);
-  need[threadIdx.x] = 0u;
-  __syncthreads();
-  const int bid = s_bid;
-  const int64_t wbase = (int64_t)bid * kLBBlock;
-  // mark: the sorted distinct ranges that can reach this window are mark[mwin.x, mwin.y)
-  {
-    const int2 w = mwin[bid];
-    uint8_t* nb = reinterpret_cast<uint8_t*>(need);
-    for (int m = w.x + threadIdx.x; m < w.y; m += blockDim.x) {
-      const int2 g = mark[m];
-      const int64_t a = g.x > wbase ? g.x : wbase;
-      const int64_t e = (int64_t)g.x + g.y < wbase + kLBBlock ? (int64_t)g.x + g.y : wbase + kLBBlock;
-      for (int64_t id = a; id < e; ++id) nb[id - wbase] = 1;
-    }
-  }
-  __syncthreads();
-  const int64_t base = wbase + (int64_t)threadIdx.x * kLBItems;
-  uint32_t fu = 0, fm = 0;
-  int sv[4] = {-1, -1, -1, -1};
-  if (base < n) {
-    const uint32_t w = need[threadIdx.x];
-    int4 s4 = *reinterpret_cast<const int4*>(slot_of + base);
-    sv[0] = s4.x; sv[1] = s4.y; sv[2] = s4.z; sv[3] = s4.w;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (((w >> (8 * k)) & 0xffu) && base + k < n) {
-        fu |= 1u << k;
-        if (with_missing && sv[k] < 0) fm |= 1u << k;
-      }
-    }
-  }
-  int tu, tm;
-  int ru = block_excl_scan(__popc(fu), sh, &tu);
-  int rm = block_excl_scan(__popc(fm), sh, &tm);
-  if (threadIdx.x < 64) {
-    uint32_t ea, eb;
-    lb_resolve(flags, bid, (uint32_t)tu, (uint32_t)tm, &ea, &eb, counts + 4);
-    if (threadIdx.x == 0) {
-      s_ex[0] = ea;
-      s_ex[1] = eb;
-      if (bid == nblocks - 1) {
-        counts[0] = (int32_t)(ea + tu);
-        counts[1] = (int32_t)(eb + tm);
-      }
-    }
-  }
-  __syncthreads();
-  ru += (int)s_ex[0];
-  rm += (int)s_ex[1];
-  if (base >= n) return;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int64_t id = base + k;
-    if (id >= n) break;
-    if ((fu >> k) & 1u) {
-      pos[id] = ru;  // only marked ids get a position; other entries are stale and never read
-      U[ru] = (int32_t)id;
-      if ((fm >> k) & 1u) {
-        uslot[ru] = -(rm + 1);
-        missing[rm++] = (int32_t)id;
-      } else {
-        uslot[ru] = sv[k];
-      }
-      ++ru;
-    }
-  }
-}
-
-// Free slots ascending from the occupancy flags (one int per slot, 1 = in use).
-constexpr int kFreeSlotsPerBlock = kLBBlock;
-
-__device__ __forceinline__ void free_body(const uint32_t* __restrict__ occ, int32_t cap, int32_t limit,
-                                          uint64_t* __restrict__ flags, int32_t* __restrict__ ctr,
-                                          int32_t* __restrict__ free_list, int32_t* __restrict__ counts, int nblocks) {
-  __shared__ int sh[kLBThreads / 64];
-  __shared__ int s_bid;
-  __shared__ uint32_t s_ex;
-  if (threadIdx.x == 0) s_bid = atomicAdd(ctr, 1);
-  __syncthreads();
-  const int bid = s_bid;
-  const int64_t slot0 = (int64_t)bid * kFreeSlotsPerBlock + (int64_t)threadIdx.x * kLBItems;
+// Free-slot side: the lowest free slots in ascending order, listed up to `limit` (|U|, an upper
+// bound on the number of missing records); the last block publishes the pool's free count.
+__device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex) {
+  uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack);
+  const int64_t s0 = (int64_t)b * kFBlock + (int64_t)threadIdx.x * kFItems;
   uint32_t f = 0;
-  if (slot0 < cap) {
-    const uint4 o = *reinterpret_cast<const uint4*>(occ + slot0);
-    const uint32_t ov[4] = {o.x, o.y, o.z, o.w};
+  if (s0 < a.cap) {
+    const uint4* o4 = reinterpret_cast<const uint4*>(a.occ + s0);  // occ is padded to whole blocks
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (ov[k] == 0u && slot0 + k < cap) f |= 1u << k;
+    for (int q = 0; q < kFItems / 4; ++q) {
+      const uint4 o = o4[q];
+      const uint32_t ov[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (ov[k] == 0u && s0 + 4 * q + k < a.cap) f |= 1u << (4 * q + k);
+    }
   }
-  const int c = __popc(f);
-  int t;
-  int r = block_excl_scan(c, sh, &t);
+  int tot;
+  int r = block_excl_scan(__popc(f), sh, &tot);
   if (threadIdx.x < 64) {
-    uint32_t ea, eb;
-    lb_resolve(flags, bid, (uint32_t)t, 0u, &ea, &eb, counts + 4);
+    const uint32_t ex = look_back(flags, b, tag, (uint32_t)tot, a.state + GC_STATE_ERR);
     if (threadIdx.x == 0) {
-      s_ex = ea;
-      if (bid == nblocks - 1) counts[2] = (int32_t)(ea + t);
+      *s_ex = ex;
+      if (b == a.nbf - 1) {
+        tstore(reinterpret_cast<uint64_t*>(a.state + kFreeTotal), tword(tag, 0, ex + (uint32_t)tot));
+        a.state[GC_STATE_FREE] = (int32_t)(ex + (uint32_t)tot);
+      }
     }
   }
   __syncthreads();
-  r += (int)s_ex;
+  r += (int)*s_ex;
+  if (r >= a.u) return;
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (((f >> k) & 1u) && r < limit) free_list[r++] = (int32_t)(slot0 + k);
+  for (int k = 0; k < kFItems; ++k)
+    if ((f >> k) & 1u) {
+      if (r < a.u) tstore(a.free_list + r, tword(tag, 0, (uint32_t)(s0 + k)));
+      ++r;
+    }
 }
 
-// Both scans in one grid: blocks [0, nbu) run the union chain, the rest the free-slot chain
-// (listing the first `limit` free slots, a static upper bound on #missing).  The two chains
-// have their own block counters and look-back words, so neither waits on the other.
-__global__ void __launch_bounds__(kLBThreads) k_scan(const int2* __restrict__ mark, const int2* __restrict__ mwin,
-                                                     const int32_t* __restrict__ slot_of,
-                                                     int32_t n, int32_t with_missing, int nbu,
-                                                     uint64_t* __restrict__ flags_u, int32_t* __restrict__ ctr_u,
-                                                     int32_t* __restrict__ pos, int32_t* __restrict__ U,
-                                                     int32_t* __restrict__ uslot, int32_t* __restrict__ missing,
-                                                     const uint32_t* __restrict__ occ, int32_t cap, int32_t limit,
-                                                     uint64_t* __restrict__ flags_f, int32_t* __restrict__ ctr_f,
-                                                     int32_t* __restrict__ free_list, int32_t* __restrict__ counts) {
-  if ((int)blockIdx.x < nbu)
-    union_body(mark, mwin, slot_of, n, with_missing, flags_u, ctr_u, pos, U, uslot, missing, counts, nbu);
-  else
-    free_body(occ, cap, limit, flags_f, ctr_f, free_list, counts, (int)gridDim.x - nbu);
-}
-
-struct ApplyArgs {
-  int32_t mode;
-  const int32_t* counts;
-  const int32_t* U;
-  const int32_t* uslot;
-  const int32_t* free_list;
-  const int32_t* pos;
-  const float4* src;
-  float4* pool;
-  int32_t* slot_of;
-  uint32_t* occ;
-  float4* packed;
-  const gc_task* tasks;
-  int32_t n_tasks;
-  const int2* ranges;
-  int32_t n_ranges;
-  int2* pranges;
-  int32_t* pibeg;
-  const int32_t* ioff;
-  const int32_t* joff;
-  int32_t* ilist;
-  int32_t* jlist;
-  int32_t blocks_a;  // blocks [0, blocks_a) stage and pack; the rest remap
-  int32_t* state;    // scan state: [8, n_state) (block counters, look-back words) is cleared here
-  int32_t n_state;
-};
-
-// Pool slot of union rank p after staging (0 after a reported capacity overflow).
-__device__ __forceinline__ int32_t slot_of_rank(const ApplyArgs& a, int32_t p, int32_t nfree) {
-  const int32_t v = a.uslot[p];
-  if (v >= 0) return v;
-  const int32_t m = -v - 1;
-  return m < nfree ? a.free_list[m] : 0;
-}
-
-__global__ void __launch_bounds__(256) k_apply(ApplyArgs a) {
-  const int32_t nu = a.counts[0];
-  const int32_t nfree = a.counts[1] < a.counts[2] ? a.counts[1] : a.counts[2];
-  // the scans are done: leave their counters and look-back words cleared for the next reorganisation
-  for (int i = 8 + blockIdx.x * blockDim.x + threadIdx.x; i < a.n_state; i += gridDim.x * blockDim.x) a.state[i] = 0;
-  if ((int)blockIdx.x < a.blocks_a) {
-    const int stride = a.blocks_a * blockDim.x;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nu; k += stride) {
-      const int32_t id = a.U[k];
-      if (a.mode == GC_REORG_REDUNDANT) {
-        a.packed[k] = a.src[id];
-        continue;
+// Union side: residency of this block's chunk of U, the missing ranks, then slot assignment,
+// staging and the packed copies.
+__device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex) {
+  uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbf;
+  const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
+  int32_t id[kUItems], sl[kUItems];
+  uint32_t fm = 0;
+  {
+    const int4* u4 = reinterpret_cast<const int4*>(a.U + k0);  // U is padded to whole blocks
+    const int4 x = u4[0], y = u4[1];
+    id[0] = x.x; id[1] = x.y; id[2] = x.z; id[3] = x.w;
+    id[4] = y.x; id[5] = y.y; id[6] = y.z; id[7] = y.w;
+  }
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    sl[i] = 0;
+    if (k0 + i < a.u) {
+      sl[i] = a.slot_of[id[i]];
+      if (sl[i] < 0) fm |= 1u << i;
+    }
+  }
+  // records of the missing entries: their loads do not wait for any rank
+  float rx[kUItems], ry[kUItems], rz[kUItems], rw[kUItems];
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if ((fm >> i) & 1u) v = a.src[id[i]];
+    rx[i] = v.x;
+    ry[i] = v.y;
+    rz[i] = v.z;
+    rw[i] = v.w;
+  }
+  int tot;
+  int rm = block_excl_scan(__popc(fm), sh, &tot);
+  if (threadIdx.x < 64) {
+    const uint32_t ex = look_back(flags, b, tag, (uint32_t)tot, a.state + GC_STATE_ERR);
+    if (threadIdx.x == 0) {
+      *s_ex = ex;
+      if (b == a.nbu - 1) {
+        a.state[GC_STATE_UNION] = a.u;
+        a.state[GC_STATE_MISSING] = (int32_t)(ex + (uint32_t)tot);
       }
-      const int32_t v = a.uslot[k];
-      if (v >= 0) {
-        if (a.mode == GC_REORG_PACK) a.packed[k] = a.pool[v];
-      } else {
-        const int32_t m = -v - 1;
-        const float4 r = a.src[id];
-        if (m < nfree) {
-          const int32_t s = a.free_list[m];
-          a.pool[s] = r;
-          a.slot_of[id] = s;
-          occ_set(a.occ, s);
+    }
+  }
+  // resident entries do not depend on the look-back
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    const int64_t k = k0 + i;
+    if (k < a.u && !((fm >> i) & 1u)) {
+      a.uslot[k] = sl[i];
+      if (a.pack) a.packed[k] = a.pool[sl[i]];
+    }
+  }
+  __syncthreads();
+  if (!fm) return;
+  rm += (int)*s_ex;
+  // the rm-th free slot for the rm-th missing record, once its free-scan block has listed it (none if
+  // the pool is full): one probe for all of this thread's entries in flight, then a bounded wait that
+  // re-probes the entries still unlisted
+  uint64_t w[kUItems];
+  uint32_t pend = 0;
+  {
+    int r = rm;
+#pragma unroll
+    for (int i = 0; i < kUItems; ++i)
+      if ((fm >> i) & 1u) {
+        w[i] = tload(a.free_list + r++);
+        if ((uint32_t)(w[i] >> 32) != tag) pend |= 1u << i;
+      }
+  }
+  uint32_t spins = 0;
+  while (pend) {
+    if (++spins > kSpinLimit) {
+      istore(a.state + GC_STATE_ERR, 1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    const uint64_t t = tload(reinterpret_cast<uint64_t*>(a.state + kFreeTotal));
+    const bool total_known = (uint32_t)(t >> 32) == tag;
+    int r = rm;
+#pragma unroll
+    for (int i = 0; i < kUItems; ++i)
+      if ((fm >> i) & 1u) {
+        if ((pend >> i) & 1u) {
+          w[i] = tload(a.free_list + r);
+          if ((uint32_t)(w[i] >> 32) == tag || (total_known && (uint32_t)r >= (uint32_t)(t & 0x7fffffffu)))
+            pend &= ~(1u << i);
         }
-        if (a.mode == GC_REORG_PACK) a.packed[k] = r;
+        ++r;
       }
-    }
-    return;
   }
-  const int b = blockIdx.x - a.blocks_a, nb = gridDim.x - a.blocks_a;
-  if (a.mode == GC_REORG_PACK || a.mode == GC_REORG_REDUNDANT) {
-    for (int r = b * blockDim.x + threadIdx.x; r < a.n_ranges; r += nb * blockDim.x) {
-      int2 g = a.ranges[r];
-      a.pranges[r] = make_int2(g.y > 0 ? a.pos[g.x] : 0, g.y);
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    if (!((fm >> i) & 1u)) continue;
+    const int64_t k = k0 + i;
+    const int32_t s = (uint32_t)(w[i] >> 32) == tag ? (int32_t)(w[i] & 0x7fffffffu) : -1;
+    a.missing[rm] = id[i];
+    a.mslot[rm] = s;
+    a.uslot[k] = s;
+    const float4 v = make_float4(rx[i], ry[i], rz[i], rw[i]);
+    if (s >= 0) {
+      a.pool[s] = v;
+      a.slot_of[id[i]] = s;
+      a.occ[s] = 1u;
     }
-    for (int t = b * blockDim.x + threadIdx.x; t < a.n_tasks; t += nb * blockDim.x) {
-      const gc_task& tk = a.tasks[t];
-      a.pibeg[t] = tk.i_count > 0 ? a.pos[tk.i_begin] : 0;
-    }
-    return;
+    if (a.pack) a.packed[k] = v;
+    ++rm;
   }
-  // address lists: one wavefront per task; slots come from the union rank, so no
-  // ordering with the staging writes above is needed
-  const int lane = threadIdx.x & 63;
-  const int waves = nb * (blockDim.x >> 6);
-  for (int t = b * (blockDim.x >> 6) + (threadIdx.x >> 6); t < a.n_tasks; t += waves) {
-    const gc_task tk = a.tasks[t];
-    const int io = a.ioff[t];
-    for (int k = lane; k < tk.i_count; k += 64) a.ilist[io + k] = slot_of_rank(a, a.pos[tk.i_begin + k], nfree);
-    int o = a.joff[t];
-    for (int r = 0; r < tk.j_nranges; ++r) {
-      const int2 g = a.ranges[tk.j_first + r];
-      for (int k = lane; k < g.y; k += 64) a.jlist[o + k] = slot_of_rank(a, a.pos[g.x + k], nfree);
-      o += g.y;
+}
+
+__global__ void __launch_bounds__(kRThreads) k_reorg(ReorgArgs a) {
+  __shared__ int sh[kRThreads / 64];
+  __shared__ int s_ticket;
+  __shared__ uint32_t s_tag, s_ex;
+  if (threadIdx.x == 0) {
+    s_ticket = atomicAdd(a.state + kTicket, 1);
+    s_tag = (uint32_t)iload(a.state + kTag) + 1u;
+  }
+  __syncthreads();
+  const int t = s_ticket;
+  const uint32_t tag = s_tag;
+  if (t < a.nbf)
+    free_role(a, t, tag, sh, &s_ex);
+  else
+    union_role(a, t - a.nbf, tag, sh, &s_ex);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // the last block out rewinds the counters and makes this call's tag the current one
+    if (atomicAdd(a.state + kDone, 1) == a.nbf + a.nbu - 1) {
+      istore(a.state + kTicket, 0);
+      istore(a.state + kDone, 0);
+      istore(a.state + kTag, (int32_t)tag);
     }
+  }
+}
+
+// Redundant transfers: every union record is gathered from the source, the pool is not used.
+__global__ void k_gather_src(const int32_t* __restrict__ U, int32_t u, const float4* __restrict__ src,
+                             float4* __restrict__ packed, int32_t* __restrict__ state) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    state[GC_STATE_UNION] = u;
+    state[GC_STATE_MISSING] = u;
+  }
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < u; k += gridDim.x * blockDim.x) packed[k] = src[U[k]];
+}
+
+// Address lists from the static union ranks of their entries: slot of each entry (0 for an entry
+// left without a slot by a full pool; the reorganisation reports that case).
+__global__ void k_lists(const int32_t* __restrict__ irank, int64_t n_i, const int32_t* __restrict__ jrank, int64_t n_j,
+                        const int32_t* __restrict__ uslot, int32_t* __restrict__ ilist, int32_t* __restrict__ jlist) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_i + n_j; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < n_i) {
+      const int32_t v = uslot[irank[e]];
+      ilist[e] = v > 0 ? v : 0;
+    } else {
+      const int32_t v = uslot[jrank[e - n_i]];
+      jlist[e - n_i] = v > 0 ? v : 0;
+    }
+  }
+}
+
+// Capacity check without side effects: out[0] += missing records of U, out[1] += free slots.
+__global__ void __launch_bounds__(256) k_count(const int32_t* __restrict__ U, int32_t u,
+                                               const int32_t* __restrict__ slot_of, const uint32_t* __restrict__ occ,
+                                               int32_t cap, int32_t* __restrict__ out) {
+  __shared__ int sh[4];
+  int m = 0, f = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < (u > cap ? u : cap);
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (k < u && slot_of[U[k]] < 0) ++m;
+    if (k < cap && occ[k] == 0u) ++f;
+  }
+  int tm, tf;
+  (void)block_excl_scan(m, sh, &tm);
+  (void)block_excl_scan(f, sh, &tf);
+  if (threadIdx.x == 0) {
+    if (tm) atomicAdd(out, tm);
+    if (tf) atomicAdd(out + 1, tf);
+  }
+}
+
+// Eviction: ids[0, n) leave the pool (n = min(*n_dev, n_host) when n_dev is given).  Ids outside
+// [0, n_ids) and ids not resident are skipped.
+__global__ void k_evict(const int32_t* __restrict__ ids, const int32_t* __restrict__ n_dev, int32_t n_host,
+                        int32_t* __restrict__ slot_of, int32_t n_ids, uint32_t* __restrict__ occ) {
+  const int32_t n = n_dev ? min(*n_dev, n_host) : n_host;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int32_t id = ids[k];
+    if (id < 0 || id >= n_ids) continue;
+    const int32_t s = slot_of[id];
+    if (s < 0) continue;
+    slot_of[id] = -1;
+    occ[s] = 0u;
   }
 }
 
@@ -380,7 +386,7 @@ __global__ void k_place(const int32_t* __restrict__ ids, const int32_t* __restri
     int id = ids[k], s = slots[k];
     pool[s] = src[id];
     slot_of[id] = s;
-    occ_set(occ, s);
+    occ[s] = 1u;
   }
 }
 
@@ -415,13 +421,6 @@ __global__ void __launch_bounds__(256) k_sort_lists(int32_t n_tasks, const int32
   }
 }
 
-__global__ void k_slot_to_id(const int32_t* __restrict__ slot_of, int32_t n_ids, int32_t* __restrict__ id_of_slot) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_ids; i += gridDim.x * blockDim.x) {
-    int s = slot_of[i];
-    if (s >= 0) id_of_slot[s] = i;
-  }
-}
-
 inline int grid_for(int64_t n, int per_block, int cap = 65536) {
   int64_t g = (n + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -431,17 +430,21 @@ inline int grid_for(int64_t n, int per_block, int cap = 65536) {
 
 }  // namespace
 
-int lb_blocks(int32_t n) { return (int)((n + kLBBlock - 1) / kLBBlock) > 0 ? (int)((n + kLBBlock - 1) / kLBBlock) : 1; }
+int union_blocks(int32_t u) { return u > 0 ? (int)(((int64_t)u + kUBlock - 1) / kUBlock) : 1; }
+
+int64_t union_padded(int32_t u) { return (int64_t)union_blocks(u) * kUBlock; }
 
 int free_blocks(int32_t cap) {
-  int64_t b = ((int64_t)cap + kFreeSlotsPerBlock - 1) / kFreeSlotsPerBlock;
+  int64_t b = ((int64_t)cap + kFBlock - 1) / kFBlock;
   return b > 0 ? (int)b : 1;
 }
 
 int64_t occ_words(int32_t cap) {
-  // one int per slot, padded so that every free-scan thread's 4-slot load stays inside the allocation
-  return (int64_t)free_blocks(cap) * kFreeSlotsPerBlock;
+  // one int per slot, padded so that every free-scan thread's 16-slot load stays inside the allocation
+  return (int64_t)free_blocks(cap) * kFBlock;
 }
+
+int32_t reorg_state_ints(int32_t u, int32_t cap) { return kLookBack + 2 * (union_blocks(u) + free_blocks(cap)); }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -461,32 +464,39 @@ hipError_t launch_pool_reset(int32_t* slot_of, int32_t n_ids, uint32_t* occ, int
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const int2* mark, const int2* mwin, const int32_t* slot_of, int32_t n, int32_t with_missing,
-                       uint64_t* flags_u,
-                       int32_t* ctr_u, int32_t* pos, int32_t* U, int32_t* uslot, int32_t* missing, const uint32_t* occ,
-                       int32_t cap, int32_t limit, uint64_t* flags_f, int32_t* ctr_f, int32_t* free_list, int32_t* counts,
-                       hipStream_t s) {
-  const int nbu = lb_blocks(n);
-  const int nbf = with_missing ? free_blocks(cap) : 0;
-  hipLaunchKernelGGL(k_scan, dim3(nbu + nbf), dim3(kLBThreads), 0, s, mark, mwin, slot_of, n, with_missing, nbu, flags_u,
-                     ctr_u, pos, U, uslot, missing, occ, cap, limit, flags_f, ctr_f, free_list, counts);
+hipError_t launch_reorg(ReorgArgs a, hipStream_t s) {
+  a.nbu = union_blocks(a.u);
+  a.nbf = free_blocks(a.cap);
+  hipLaunchKernelGGL(k_reorg, dim3(a.nbu + a.nbf), dim3(kRThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_apply(int32_t mode, const int32_t* counts, int32_t bound, const int32_t* U, const int32_t* uslot,
-                        const int32_t* free_list, const int32_t* pos, const float4* src, float4* pool, int32_t* slot_of,
-                        uint32_t* occ, float4* packed, const gc_task* tasks, int32_t n_tasks, const int2* ranges,
-                        int32_t n_ranges, int2* pranges, int32_t* pibeg, const int32_t* ioff, const int32_t* joff,
-                        int32_t* ilist, int32_t* jlist, int32_t* state, int32_t n_state, hipStream_t s) {
-  ApplyArgs a{mode, counts, U, uslot, free_list, pos, src, pool, slot_of, occ, packed, tasks, n_tasks, ranges,
-              n_ranges, pranges, pibeg, ioff, joff, ilist, jlist, 0, state, n_state};
-  a.blocks_a = grid_for(bound, 256, 4096);
-  int blocks_b;
-  if (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT)
-    blocks_b = grid_for(n_ranges > n_tasks ? n_ranges : n_tasks, 256, 8192);
-  else
-    blocks_b = grid_for(n_tasks, 4, 16384);
-  hipLaunchKernelGGL(k_apply, dim3(a.blocks_a + blocks_b), dim3(256), 0, s, a);
+hipError_t launch_gather_src(const int32_t* U, int32_t u, const float4* src, float4* packed, int32_t* state,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_src, dim3(grid_for(u, 256, 4096)), dim3(256), 0, s, U, u, src, packed, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_lists(const int32_t* irank, int64_t n_i, const int32_t* jrank, int64_t n_j, const int32_t* uslot,
+                        int32_t* ilist, int32_t* jlist, hipStream_t s) {
+  if (n_i + n_j <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lists, dim3(grid_for(n_i + n_j, 256, 16384)), dim3(256), 0, s, irank, n_i, jrank, n_j, uslot,
+                     ilist, jlist);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const int32_t* U, int32_t u, const int32_t* slot_of, const uint32_t* occ, int32_t cap,
+                        int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_count, dim3(grid_for(u > cap ? u : cap, 256, 2048)), dim3(256), 0, s, U, u, slot_of, occ, cap,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_evict(const int32_t* ids, const int32_t* n_dev, int32_t n_bound, int32_t* slot_of, int32_t n_ids,
+                        uint32_t* occ, hipStream_t s) {
+  if (n_bound <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_evict, dim3(grid_for(n_bound, 256, 4096)), dim3(256), 0, s, ids, n_dev, n_bound, slot_of, n_ids,
+                     occ);
   return hipGetLastError();
 }
 
@@ -500,12 +510,6 @@ hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, con
                         int32_t* slot_of, uint32_t* occ, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_place, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ids, slots, n, src, pool, slot_of, occ);
-  return hipGetLastError();
-}
-
-hipError_t launch_slot_to_id(const int32_t* slot_of, int32_t n_ids, int32_t* id_of_slot, hipStream_t s) {
-  if (n_ids <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slot_to_id, dim3(grid_for(n_ids, 256, 8192)), dim3(256), 0, s, slot_of, n_ids, id_of_slot);
   return hipGetLastError();
 }
 

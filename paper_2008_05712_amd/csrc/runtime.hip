@@ -99,14 +99,16 @@ struct gc_batch_ {
   std::vector<int32_t> nodes;
   int64_t n_direct = 0, n_targets = 0;
   bool committed = false;
-  // committed device copies
-  DevBuf d_tasks, d_ranges, d_nodes, d_mark, d_mwin, d_ioff, d_joff, d_order, d_runs;
+  // fixed at commit: the sorted union U and the packed-space ranges and first targets
+  std::vector<int32_t> hU;
+  int32_t u = 0, max_direct = 0;
+  DevBuf d_tasks, d_ranges, d_nodes, d_ioff, d_joff, d_order, d_runs, d_U, pranges, pibeg;
   int32_t n_runs = 0;
-  int32_t n_mark = 0, bound_u = 0, max_direct = 0;
+  bool ranks_ready = false;      // union ranks of the address-list entries (built on first use)
+  DevBuf d_irank, d_jrank;
   // reorganisation buffers
-  DevBuf pos, U, uslot, missing, free_list, state, packed, pranges, pibeg, ilist, jlist, queue;
+  DevBuf uslot, missing, mslot, free_list, state, packed, ilist, jlist, queue;
   DevBuf gnode, force;     // adjoint scratch: node gradients, recomputed LJ forces
-  int32_t state_ints = 0;  // counts (8) + counters (8) + look-back words of both scans
   // state of the last reorganisation
   int32_t mode = -1;
   gc_pool pool = nullptr;
@@ -171,14 +173,14 @@ extern "C" gc_status gc_pool_create(gc_ctx ctx, int32_t n_ids, int32_t capacity,
   p->n_ids = n_ids;
   p->cap = capacity;
   hipError_t e = p->rec.ensure(sizeof(float4) * (size_t)capacity);
-  if (e == hipSuccess) e = p->slot_of.ensure(sizeof(int32_t) * (size_t)pad_to(n_ids, kScanBlock));
+  if (e == hipSuccess) e = p->slot_of.ensure(sizeof(int32_t) * (size_t)n_ids);
   if (e == hipSuccess) e = p->occ.ensure(sizeof(uint32_t) * (size_t)occ_words(capacity));
   if (e != hipSuccess) {
     p->rec.release(); p->slot_of.release(); p->occ.release();
     delete p;
     return set_err(ctx, GC_E_NOMEM, "gc_pool_create: %s", hipGetErrorString(e));
   }
-  e = launch_fill_i32(p->slot_of.as<int32_t>(), -1, pad_to(n_ids, kScanBlock), nullptr);
+  e = launch_fill_i32(p->slot_of.as<int32_t>(), -1, n_ids, nullptr);
   if (e == hipSuccess) e = launch_fill_i32(p->occ.as<int32_t>(), 0, occ_words(capacity), nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -283,9 +285,9 @@ extern "C" gc_status gc_batch_create(gc_ctx ctx, int32_t kind, int32_t n_ids, gc
 extern "C" gc_status gc_batch_destroy(gc_batch b) {
   if (!b) return GC_E_INVAL;
   (void)hipDeviceSynchronize();
-  for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_mark, &b->d_mwin, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs,
-                    &b->pos, &b->U, &b->uslot, &b->missing, &b->free_list, &b->state, &b->packed, &b->pranges,
-                    &b->pibeg, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force})
+  for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs, &b->d_U,
+                    &b->pranges, &b->pibeg, &b->d_irank, &b->d_jrank, &b->uslot, &b->missing, &b->mslot, &b->free_list,
+                    &b->state, &b->packed, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force})
     d->release();
   delete b;
   return GC_OK;
@@ -299,6 +301,9 @@ extern "C" gc_status gc_batch_reset(gc_batch b) {
   b->nodes.clear();
   b->n_direct = b->n_targets = 0;
   b->committed = false;
+  b->ranks_ready = false;
+  b->hU.clear();
+  b->u = 0;
   b->mode = -1;
   b->pool = nullptr;
   return GC_OK;
@@ -356,6 +361,7 @@ extern "C" gc_status gc_submit_tasks(gc_batch b, const gc_task* tasks, int32_t n
   b->n_direct += add_direct;
   b->n_targets += add_targets;
   b->committed = false;
+  b->ranks_ready = false;
   b->mode = -1;
   return GC_OK;
 }
@@ -401,35 +407,35 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
     cost[t] = (int64_t)tk.i_count * (b->kind == GC_KIND_GRAV ? (31 * (int64_t)tk.n_count + 12 * d) : d);
   }
   b->max_direct = maxd;
-  // marks: distinct non-empty ranges over targets and direct lists
+  // the union U: sorted distinct ids over all target and direct ranges (the merged intervals,
+  // expanded), and each range's first position in it (a range is contiguous in U)
   std::vector<std::pair<int32_t, int32_t>> mk;
   mk.reserve((size_t)T + R);
   for (int32_t t = 0; t < T; ++t)
-    if (b->tasks[t].i_count > 0) mk.emplace_back(b->tasks[t].i_begin, b->tasks[t].i_count);
+    if (b->tasks[t].i_count > 0) mk.emplace_back(b->tasks[t].i_begin, b->tasks[t].i_begin + b->tasks[t].i_count);
   for (int32_t r = 0; r < R; ++r)
-    if (b->ranges[2 * r + 1] > 0) mk.emplace_back(b->ranges[2 * r], b->ranges[2 * r + 1]);
+    if (b->ranges[2 * r + 1] > 0) mk.emplace_back(b->ranges[2 * r], b->ranges[2 * r] + b->ranges[2 * r + 1]);
   std::sort(mk.begin(), mk.end());
-  mk.erase(std::unique(mk.begin(), mk.end()), mk.end());
-  int64_t marked = 0;
-  for (auto& m : mk) marked += m.second;
-  b->n_mark = (int32_t)mk.size();
-  b->bound_u = (int32_t)std::min<int64_t>(b->n_ids, marked);
-  // per union-scan block (kUnionBlockIds ids): the marks that can reach its window, [lo, hi)
-  int32_t maxlen = 1;
-  for (auto& m : mk) maxlen = std::max(maxlen, m.second);
-  const int nbu = lb_blocks(b->n_ids);
-  std::vector<int32_t> mwin(2 * (size_t)nbu);
+  b->hU.clear();
   {
-    size_t lo = 0, hi = 0;
-    for (int k = 0; k < nbu; ++k) {
-      const int64_t w0 = (int64_t)k * kUnionBlockIds, w1 = w0 + kUnionBlockIds;
-      while (lo < mk.size() && (int64_t)mk[lo].first + maxlen <= w0) ++lo;
-      if (hi < lo) hi = lo;
-      while (hi < mk.size() && mk[hi].first < w1) ++hi;
-      mwin[2 * k] = (int32_t)lo;
-      mwin[2 * k + 1] = (int32_t)hi;
+    int64_t covered = -1;  // ids below this are already in U
+    for (auto& m : mk) {
+      for (int64_t id = std::max<int64_t>(m.first, covered); id < m.second; ++id) b->hU.push_back((int32_t)id);
+      covered = std::max<int64_t>(covered, m.second);
     }
   }
+  b->u = (int32_t)b->hU.size();
+  auto upos = [&](int32_t id) -> int32_t {
+    return (int32_t)(std::lower_bound(b->hU.begin(), b->hU.end(), id) - b->hU.begin());
+  };
+  std::vector<int32_t> pr((size_t)2 * R), pib(T > 0 ? T : 1, 0);
+  for (int32_t r = 0; r < R; ++r) {
+    pr[2 * r] = b->ranges[2 * r + 1] > 0 ? upos(b->ranges[2 * r]) : 0;
+    pr[2 * r + 1] = b->ranges[2 * r + 1];
+  }
+  for (int32_t t = 0; t < T; ++t) pib[t] = b->tasks[t].i_count > 0 ? upos(b->tasks[t].i_begin) : 0;
+  std::vector<int32_t> upad((size_t)union_padded(b->u), 0);
+  std::copy(b->hU.begin(), b->hU.end(), upad.begin());
   // longest-processing-time-first order for the persistent schedule
   std::vector<int32_t> order(T > 0 ? T : 1);
   std::iota(order.begin(), order.begin() + T, 0);
@@ -453,8 +459,9 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   up(b->d_tasks, b->tasks.data(), sizeof(gc_task) * (size_t)T);
   up(b->d_ranges, b->ranges.data(), sizeof(int32_t) * b->ranges.size());
   up(b->d_nodes, b->nodes.data(), sizeof(int32_t) * b->nodes.size());
-  up(b->d_mark, mk.data(), sizeof(int32_t) * 2 * mk.size());
-  up(b->d_mwin, mwin.data(), sizeof(int32_t) * mwin.size());
+  up(b->d_U, upad.data(), sizeof(int32_t) * upad.size());
+  up(b->pranges, pr.data(), sizeof(int32_t) * pr.size());
+  up(b->pibeg, pib.data(), sizeof(int32_t) * pib.size());
   up(b->d_ioff, ioff.data(), sizeof(int32_t) * ioff.size());
   up(b->d_joff, joff.data(), sizeof(int32_t) * joff.size());
   up(b->d_order, order.data(), sizeof(int32_t) * order.size());
@@ -462,74 +469,103 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors must outlive the copies
   if (e != hipSuccess) return hip_fail(c, e, "gc_batch_commit");
   b->committed = true;
+  b->ranks_ready = false;
   b->mode = -1;
   return GC_OK;
 }
 
-// Scan state layout (int32 units): [0, 8) counts, [8, 16) block counters,
-// [16, 16 + 2 nbU) union look-back words, then 2 nbF free-scan words.
-static int32_t* counts_of(gc_batch b) { return b->state.as<int32_t>(); }
+// Reorganisation state (int32 words): [0, 8) counts read by the host (GC_STATE_*), then the
+// ticket and completion counters, the current call tag, the free-slot total and the look-back
+// words of both chains.  Tags make the words and the free-slot list self-invalidating; both are
+// zeroed whenever either is (re)allocated so that no stale entry can carry a future tag.
+static bool lists_mode(int32_t mode) { return mode == GC_REORG_INDIRECT || mode == GC_REORG_SORTED; }
 
-static hipError_t ensure_reorg_buffers(gc_batch b, gc_pool p) {
-  const int64_t nid = pad_to(b->n_ids, kScanBlock);
-  const int64_t bound = std::max<int32_t>(b->bound_u, 1);
-  hipError_t e = b->pos.ensure(sizeof(int32_t) * (size_t)nid);
-  if (e == hipSuccess) e = b->U.ensure(sizeof(int32_t) * (size_t)bound);
-  if (e == hipSuccess) e = b->uslot.ensure(sizeof(int32_t) * (size_t)bound);
-  if (e == hipSuccess) e = b->missing.ensure(sizeof(int32_t) * (size_t)bound);
-  if (e == hipSuccess) e = b->free_list.ensure(sizeof(int32_t) * (size_t)bound);
-  b->state_ints = 16 + 2 * lb_blocks(b->n_ids) + 2 * free_blocks(p->cap);
-  if (e == hipSuccess) e = b->state.ensure(sizeof(int32_t) * (size_t)b->state_ints);
-  if (e == hipSuccess) e = b->packed.ensure(sizeof(float4) * (size_t)bound);
-  if (e == hipSuccess) e = b->pranges.ensure(sizeof(int32_t) * std::max<size_t>(b->ranges.size(), 2));
-  if (e == hipSuccess) e = b->pibeg.ensure(sizeof(int32_t) * std::max<size_t>(b->tasks.size(), 1));
-  if (e == hipSuccess) e = b->ilist.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(b->n_targets, 1));
-  if (e == hipSuccess) e = b->jlist.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(b->n_direct, 1));
-  if (e == hipSuccess) e = b->queue.ensure(sizeof(int32_t) * 4);
+static hipError_t build_ranks(gc_batch b, hipStream_t s) {
+  // union rank of every address-list entry: targets in task order, then direct entries
+  std::vector<int32_t> ir((size_t)std::max<int64_t>(b->n_targets, 1)), jr((size_t)std::max<int64_t>(b->n_direct, 1));
+  auto upos = [&](int32_t id) -> int32_t {
+    return (int32_t)(std::lower_bound(b->hU.begin(), b->hU.end(), id) - b->hU.begin());
+  };
+  int64_t io = 0, jo = 0;
+  for (const gc_task& tk : b->tasks) {
+    const int32_t p0 = tk.i_count > 0 ? upos(tk.i_begin) : 0;
+    for (int32_t k = 0; k < tk.i_count; ++k) ir[io++] = p0 + k;
+    for (int32_t r = 0; r < tk.j_nranges; ++r) {
+      const int32_t g0 = b->ranges[2 * (tk.j_first + r)], gn = b->ranges[2 * (tk.j_first + r) + 1];
+      const int32_t q0 = gn > 0 ? upos(g0) : 0;
+      for (int32_t k = 0; k < gn; ++k) jr[jo++] = q0 + k;
+    }
+  }
+  hipError_t e = b->d_irank.ensure(sizeof(int32_t) * ir.size());
+  if (e == hipSuccess) e = b->d_jrank.ensure(sizeof(int32_t) * jr.size());
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_irank.p, ir.data(), sizeof(int32_t) * ir.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_jrank.p, jr.data(), sizeof(int32_t) * jr.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors go out of scope
+  if (e == hipSuccess) b->ranks_ready = true;
   return e;
 }
 
-// Phase A: mark, union + position map + missing list, free-slot list.  Nothing in the pool changes.
-static gc_status reorganize_lookup(gc_batch b, gc_pool p, int32_t mode, hipStream_t s, bool* needs_state_clear) {
-  gc_ctx c = b->ctx;
-  size_t state_before = b->state.bytes;
-  const void* state_ptr = b->state.p;
-  hipError_t e = ensure_reorg_buffers(b, p);
-  if (e != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_reorganize: %s", hipGetErrorString(e));
-  if (b->state.bytes != state_before || b->state.p != state_ptr) *needs_state_clear = true;
-  if (*needs_state_clear) GC_HIP(c, launch_fill_i32(b->state.as<int32_t>(), 0, (int64_t)(b->state.bytes / 4), s));
-  int32_t* st = b->state.as<int32_t>();
-  const int nbu = lb_blocks(b->n_ids);
-  uint64_t* flags_u = reinterpret_cast<uint64_t*>(st + 16);
-  uint64_t* flags_f = reinterpret_cast<uint64_t*>(st + 16 + 2 * nbu);
-  const bool reuse = (mode != GC_REORG_REDUNDANT);
-  GC_HIP(c, launch_scan(b->d_mark.as<int2>(), b->d_mwin.as<int2>(), p->slot_of.as<int32_t>(), b->n_ids, reuse ? 1 : 0,
-                        flags_u, st + 8,
-                        b->pos.as<int32_t>(), b->U.as<int32_t>(), b->uslot.as<int32_t>(), b->missing.as<int32_t>(),
-                        p->occ.as<uint32_t>(), p->cap, std::max<int32_t>(b->bound_u, 1), flags_f, st + 9,
-                        b->free_list.as<int32_t>(), st, s));
-  return GC_OK;
+static hipError_t ensure_reorg_buffers(gc_batch b, gc_pool p, int32_t mode, hipStream_t s) {
+  const size_t u = (size_t)std::max<int32_t>(b->u, 1);
+  const void* st0 = b->state.p;
+  const void* fl0 = b->free_list.p;
+  hipError_t e = b->uslot.ensure(sizeof(int32_t) * u);
+  if (e == hipSuccess) e = b->missing.ensure(sizeof(int32_t) * u);
+  if (e == hipSuccess) e = b->mslot.ensure(sizeof(int32_t) * u);
+  if (e == hipSuccess) e = b->free_list.ensure(sizeof(uint64_t) * u);
+  if (e == hipSuccess) e = b->state.ensure(sizeof(int32_t) * (size_t)reorg_state_ints(b->u, p->cap));
+  if (e == hipSuccess) e = b->packed.ensure(sizeof(float4) * u);
+  if (e == hipSuccess) e = b->queue.ensure(sizeof(int32_t) * 4);
+  if (e == hipSuccess && lists_mode(mode)) {
+    e = b->ilist.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(b->n_targets, 1));
+    if (e == hipSuccess) e = b->jlist.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(b->n_direct, 1));
+    if (e == hipSuccess && !b->ranks_ready) e = build_ranks(b, s);
+  }
+  if (e == hipSuccess && (b->state.p != st0 || b->free_list.p != fl0)) {
+    e = launch_fill_i32(b->state.as<int32_t>(), 0, (int64_t)(b->state.bytes / 4), s);
+    if (e == hipSuccess) e = launch_fill_i32(b->free_list.as<int32_t>(), 0, (int64_t)(b->free_list.bytes / 4), s);
+  }
+  return e;
 }
 
-// Phase B: staging of missing records into the pool, the packing gather or the list remaps.
-static gc_status reorganize_apply(gc_batch b, gc_pool p, int32_t mode, hipStream_t s) {
+// Clears the reorganisation state and the free-slot list (the staged set of the last call is forgotten).
+static hipError_t clear_reorg_state(gc_batch b, hipStream_t s) {
+  hipError_t e = launch_fill_i32(b->state.as<int32_t>(), 0, (int64_t)(b->state.bytes / 4), s);
+  if (e == hipSuccess) e = launch_fill_i32(b->free_list.as<int32_t>(), 0, (int64_t)(b->free_list.bytes / 4), s);
+  return e;
+}
+
+// Device part of a reorganisation (buffers already sized).
+static gc_status reorganize_async(gc_batch b, gc_pool p, int32_t mode, hipStream_t s) {
   gc_ctx c = b->ctx;
-  const int32_t T = (int32_t)b->tasks.size(), R = (int32_t)(b->ranges.size() / 2);
-  GC_HIP(c, launch_apply(mode, counts_of(b), b->bound_u, b->U.as<int32_t>(), b->uslot.as<int32_t>(),
-                         b->free_list.as<int32_t>(), b->pos.as<int32_t>(), p->src, p->rec.as<float4>(),
-                         p->slot_of.as<int32_t>(), p->occ.as<uint32_t>(), b->packed.as<float4>(),
-                         b->d_tasks.as<gc_task>(), T, b->d_ranges.as<int2>(), R, b->pranges.as<int2>(),
-                         b->pibeg.as<int32_t>(), b->d_ioff.as<int32_t>(), b->d_joff.as<int32_t>(),
-                         b->ilist.as<int32_t>(), b->jlist.as<int32_t>(), b->state.as<int32_t>(), b->state_ints, s));
-  if (mode == GC_REORG_SORTED) GC_HIP(c, launch_sort_lists(T, b->d_joff.as<int32_t>(), b->jlist.as<int32_t>(), s));
+  if (mode == GC_REORG_REDUNDANT) {
+    GC_HIP(c, launch_gather_src(b->d_U.as<int32_t>(), b->u, p->src, b->packed.as<float4>(), b->state.as<int32_t>(), s));
+  } else {
+    ReorgArgs a{};
+    a.U = b->d_U.as<int32_t>();
+    a.u = b->u;
+    a.src = p->src;
+    a.pool = p->rec.as<float4>();
+    a.slot_of = p->slot_of.as<int32_t>();
+    a.occ = p->occ.as<uint32_t>();
+    a.cap = p->cap;
+    a.pack = mode == GC_REORG_PACK ? 1 : 0;
+    a.packed = b->packed.as<float4>();
+    a.uslot = b->uslot.as<int32_t>();
+    a.missing = b->missing.as<int32_t>();
+    a.mslot = b->mslot.as<int32_t>();
+    a.free_list = b->free_list.as<uint64_t>();
+    a.state = b->state.as<int32_t>();
+    GC_HIP(c, launch_reorg(a, s));
+    if (lists_mode(mode)) {
+      GC_HIP(c, launch_lists(b->d_irank.as<int32_t>(), b->n_targets, b->d_jrank.as<int32_t>(), b->n_direct,
+                             b->uslot.as<int32_t>(), b->ilist.as<int32_t>(), b->jlist.as<int32_t>(), s));
+      if (mode == GC_REORG_SORTED)
+        GC_HIP(c, launch_sort_lists((int32_t)b->tasks.size(), b->d_joff.as<int32_t>(), b->jlist.as<int32_t>(), s));
+    }
+  }
   b->rec = (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT) ? b->packed.as<float4>() : p->rec.as<float4>();
   return GC_OK;
-}
-
-static gc_status reorganize_async(gc_batch b, gc_pool p, int32_t mode, hipStream_t s, bool* needs_need_clear) {
-  gc_status st = reorganize_lookup(b, p, mode, s, needs_need_clear);
-  if (st != GC_OK) return st;
-  return reorganize_apply(b, p, mode, s);
 }
 
 extern "C" gc_status gc_reorganize(gc_batch b, gc_pool p, int32_t mode, int32_t check_capacity, void* stream) {
@@ -551,26 +587,53 @@ extern "C" gc_status gc_reorganize(gc_batch b, gc_pool p, int32_t mode, int32_t 
     return set_err(c, GC_E_UNSUPPORTED, "gc_reorganize: SORTED supports at most %d direct entries per task (got %d)",
                    kSortMax, b->max_direct);
   hipStream_t s = S(stream);
-  bool clear = false;
   b->mode = -1;
-  gc_status st = reorganize_lookup(b, p, mode, s, &clear);
-  if (st != GC_OK) return st;
+  hipError_t e = ensure_reorg_buffers(b, p, mode, s);
+  if (e != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_reorganize: %s", hipGetErrorString(e));
   if (check_capacity && mode != GC_REORG_REDUNDANT) {
+    // count first (no side effects), so that a full pool is reported with the pool unchanged
+    int32_t* st = b->state.as<int32_t>();
+    GC_HIP(c, launch_fill_i32(st + GC_STATE_CHECK, 0, 2, s));
+    GC_HIP(c, launch_count(b->d_U.as<int32_t>(), b->u, p->slot_of.as<int32_t>(), p->occ.as<uint32_t>(), p->cap,
+                           st + GC_STATE_CHECK, s));
     int32_t h[8];
-    GC_HIP(c, hipMemcpyAsync(h, b->state.p, sizeof h, hipMemcpyDeviceToHost, s));
+    GC_HIP(c, hipMemcpyAsync(h, st, sizeof h, hipMemcpyDeviceToHost, s));
     GC_HIP(c, hipStreamSynchronize(s));
-    if (h[4]) return set_err(c, GC_E_HIP, "gc_reorganize: a scan block did not complete");
-    if (h[1] > h[2]) {
-      // the apply step that would clear the scan state does not run: clear it here
-      GC_HIP(c, launch_fill_i32(b->state.as<int32_t>() + 8, 0, (int64_t)b->state_ints - 8, s));
-      return set_err(c, GC_E_FULL, "gc_reorganize: %d records missing but only %d pool slots free", h[1], h[2]);
-    }
+    if (h[GC_STATE_ERR]) return set_err(c, GC_E_HIP, "gc_reorganize: an earlier reorganisation hit a wait bound");
+    if (h[GC_STATE_CHECK] > h[GC_STATE_CHECK + 1])
+      return set_err(c, GC_E_FULL, "gc_reorganize: %d records missing but only %d pool slots free", h[GC_STATE_CHECK],
+                     h[GC_STATE_CHECK + 1]);
   }
-  st = reorganize_apply(b, p, mode, s);
+  gc_status st = reorganize_async(b, p, mode, s);
   if (st != GC_OK) return st;
   b->mode = mode;
   b->pool = p;
   return GC_OK;
+}
+
+extern "C" gc_status gc_pool_evict(gc_pool pool, const int32_t* ids_dev, int32_t n, void* stream) {
+  if (!pool) return GC_E_INVAL;
+  GC_ENTER(pool->ctx);
+  if (n < 0 || (n > 0 && !ids_dev)) return set_err(pool->ctx, GC_E_INVAL, "gc_pool_evict: bad arrays");
+  GC_HIP(pool->ctx, launch_evict(ids_dev, nullptr, n, pool->slot_of.as<int32_t>(), pool->n_ids,
+                                 pool->occ.as<uint32_t>(), S(stream)));
+  return GC_OK;
+}
+
+static gc_status evict_staged_async(gc_pool pool, gc_batch b, hipStream_t s) {
+  if (b->mode != GC_REORG_PACK && b->mode != GC_REORG_INDIRECT && b->mode != GC_REORG_SORTED) return GC_OK;
+  GC_HIP(pool->ctx, launch_evict(b->missing.as<int32_t>(), b->state.as<int32_t>() + GC_STATE_MISSING,
+                                 std::max<int32_t>(b->u, 1), pool->slot_of.as<int32_t>(), pool->n_ids,
+                                 pool->occ.as<uint32_t>(), s));
+  return GC_OK;
+}
+
+extern "C" gc_status gc_pool_evict_staged(gc_pool pool, gc_batch b, void* stream) {
+  if (!pool || !b) return GC_E_INVAL;
+  GC_ENTER(pool->ctx);
+  if (b->mode < 0 || !b->pool) return GC_OK;  // nothing staged yet
+  if (b->pool != pool) return set_err(pool->ctx, GC_E_STATE, "gc_pool_evict_staged: batch last reorganised against another pool");
+  return evict_staged_async(pool, b, S(stream));
 }
 
 extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int32_t* pos, int32_t* missing,
@@ -584,10 +647,10 @@ extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int3
   int32_t h[8];
   GC_HIP(c, hipMemcpyAsync(h, b->state.p, sizeof h, hipMemcpyDeviceToHost, s));
   GC_HIP(c, hipStreamSynchronize(s));
-  if (h[4]) return set_err(c, GC_E_HIP, "gc_batch_maps: a scan block did not complete");
-  if (b->mode != GC_REORG_REDUNDANT && h[1] > h[2])
+  if (h[GC_STATE_ERR]) return set_err(c, GC_E_HIP, "gc_batch_maps: a reorganisation wait hit its bound");
+  if (b->mode != GC_REORG_REDUNDANT && h[GC_STATE_MISSING] > h[GC_STATE_FREE])
     return set_err(c, GC_E_FULL, "gc_batch_maps: the last reorganisation overflowed the pool");
-  const int32_t nu = h[0], nm = (b->mode == GC_REORG_REDUNDANT) ? h[0] : h[1];
+  const int32_t nu = b->u, nm = (b->mode == GC_REORG_REDUNDANT) ? b->u : h[GC_STATE_MISSING];
   if (counts) {
     counts[0] = nu;
     counts[1] = nm;
@@ -596,14 +659,11 @@ extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int3
     if (!dst || !bytes) return hipSuccess;
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
   };
-  // positions: only marked ids carry one on the device; rebuild the full map from U
-  std::vector<int32_t> hU((size_t)std::max(nu, 1));
-  GC_HIP(c, dn(hU.data(), b->U.p, sizeof(int32_t) * (size_t)nu));
   if (b->mode == GC_REORG_REDUNDANT) {
-    GC_HIP(c, dn(missing, b->U.p, sizeof(int32_t) * (size_t)nu));
+    if (missing && nu) std::memcpy(missing, b->hU.data(), sizeof(int32_t) * (size_t)nu);
   } else {
     GC_HIP(c, dn(missing, b->missing.p, sizeof(int32_t) * (size_t)nm));
-    GC_HIP(c, dn(new_slot, b->free_list.p, sizeof(int32_t) * (size_t)std::min(nm, h[2])));
+    GC_HIP(c, dn(new_slot, b->mslot.p, sizeof(int32_t) * (size_t)nm));
   }
   if (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT) {
     GC_HIP(c, dn(pranges, b->pranges.p, sizeof(int32_t) * b->ranges.size()));
@@ -613,10 +673,10 @@ extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int3
     GC_HIP(c, dn(jlist, b->jlist.p, sizeof(int32_t) * (size_t)b->n_direct));
   }
   GC_HIP(c, hipStreamSynchronize(s));
-  if (U) std::memcpy(U, hU.data(), sizeof(int32_t) * (size_t)nu);
+  if (U && nu) std::memcpy(U, b->hU.data(), sizeof(int32_t) * (size_t)nu);
   if (pos) {
     for (int32_t i = 0; i < b->n_ids; ++i) pos[i] = -1;
-    for (int32_t k = 0; k < nu; ++k) pos[hU[k]] = k;
+    for (int32_t k = 0; k < nu; ++k) pos[b->hU[k]] = k;
   }
   return GC_OK;
 }
@@ -770,7 +830,7 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
     a.cot = reinterpret_cast<const float4*>(cot_dev);
     a.gpos = reinterpret_cast<float4*>(gpos_dev);
     a.gmass = gmass_dev;
-    a.src_id = packed ? b->U.as<int32_t>() : nullptr;
+    a.src_id = packed ? b->d_U.as<int32_t>() : nullptr;
     a.gnode = b->gnode.as<float>();
     GC_HIP(c, launch_grav_adjoint(packed, a, 4, s));
     if (n_nodes > 0)
@@ -809,13 +869,15 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
 
 extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* batches, gc_pool* pools,
                                       const int32_t* modes, const gc_force_params* prm, const float* nodes_dev,
-                                      float* acc_dev, int32_t pre_reset, const int32_t* const* place_ids,
+                                      float* acc_dev, int32_t fixture, const int32_t* const* place_ids,
                                       const int32_t* const* place_slots, const int32_t* place_n, void* stream,
                                       gc_graph* out) {
   GC_ENTER(ctx);
   if (n_steps <= 0 || !batches || !pools || !modes || !prm || !out)
     return set_err(ctx, GC_E_INVAL, "gc_graph_capture: bad arguments");
   if (!stream) return set_err(ctx, GC_E_INVAL, "gc_graph_capture: capture needs a non-default stream");
+  if (fixture < GC_FIXTURE_NONE || fixture > GC_FIXTURE_EVICT_STAGED)
+    return set_err(ctx, GC_E_INVAL, "gc_graph_capture: bad fixture %d", fixture);
   for (int32_t k = 0; k < n_steps; ++k) {
     if (!batches[k] || !pools[k] || !batches[k]->committed)
       return set_err(ctx, GC_E_STATE, "gc_graph_capture: step %d batch not committed", k);
@@ -825,14 +887,16 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
     gc_status st = check_prm(batches[k], prm, &tile, &wpb);
     if (st != GC_OK) return st;
     // size buffers outside the capture (allocation is not capturable)
-    if (modes[k] != GC_REORG_NONE && ensure_reorg_buffers(batches[k], pools[k]) != hipSuccess)
+    if (modes[k] != GC_REORG_NONE && ensure_reorg_buffers(batches[k], pools[k], modes[k], S(stream)) != hipSuccess)
       return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: buffers");
     if (batches[k]->queue.ensure(16) != hipSuccess) return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: queue");
+    if (fixture == GC_FIXTURE_EVICT_STAGED && pools[k] != pools[(k + n_steps - 1) % n_steps])
+      return set_err(ctx, GC_E_INVAL, "gc_graph_capture: evicting fixture needs one pool for all steps");
   }
-  // the scan state starts cleared: clear it once outside the capture (each replay's apply step clears it again)
+  // every batch starts with a cleared state (so the first replay evicts nothing for the step before
+  // step 0); the tags keep later replays apart without further clearing
   for (int32_t k = 0; k < n_steps; ++k)
-    if (modes[k] != GC_REORG_NONE)
-      GC_HIP(ctx, launch_fill_i32(batches[k]->state.as<int32_t>(), 0, (int64_t)(batches[k]->state.bytes / 4), S(stream)));
+    if (modes[k] != GC_REORG_NONE) GC_HIP(ctx, clear_reorg_state(batches[k], S(stream)));
   GC_HIP(ctx, hipStreamSynchronize(S(stream)));
   hipStream_t s = S(stream);
   // The combined pass of a step reads only its batch's own buffers unless its records come from
@@ -875,15 +939,30 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
   }
   gc_status st = GC_OK;
   std::vector<bool> used(n_side, false);
+  auto fork_pass = [&](int32_t j) -> gc_status {
+    const int q = j % n_side;
+    if (hipStreamWaitEvent(gr->side[q], gr->events[j], 0) != hipSuccess)
+      return set_err(ctx, GC_E_HIP, "capture: fork");
+    used[q] = true;
+    return launch_combined_async(batches[j], prm, nodes_dev, acc_dev, gr->side[q]);
+  };
   for (int32_t k = 0; k < n_steps && st == GC_OK; ++k) {
     gc_batch b = batches[k];
     gc_pool p = pools[k];
-    if (pre_reset) {
+    if (fixture == GC_FIXTURE_RESET_PLACE) {
       if (pool_reset_async(p, s) != hipSuccess) st = set_err(ctx, GC_E_HIP, "capture: pool reset");
       if (st == GC_OK && place_n && place_n[k] > 0 &&
           launch_place(place_ids[k], place_slots[k], place_n[k], p->src, p->rec.as<float4>(), p->slot_of.as<int32_t>(),
                        p->occ.as<uint32_t>(), s) != hipSuccess)
         st = set_err(ctx, GC_E_HIP, "capture: place");
+    } else if (fixture == GC_FIXTURE_EVICT_STAGED) {
+      const int32_t q = (k + n_steps - 1) % n_steps;  // the step before (cyclically, across replays)
+      gc_batch pb = batches[q];
+      if (modes[q] == GC_REORG_PACK || modes[q] == GC_REORG_INDIRECT || modes[q] == GC_REORG_SORTED) {
+        if (launch_evict(pb->missing.as<int32_t>(), pb->state.as<int32_t>() + GC_STATE_MISSING, std::max<int32_t>(pb->u, 1),
+                         p->slot_of.as<int32_t>(), p->n_ids, p->occ.as<uint32_t>(), s) != hipSuccess)
+          st = set_err(ctx, GC_E_HIP, "capture: evict");
+      }
     }
     if (st != GC_OK) break;
     if (modes[k] == GC_REORG_NONE) {
@@ -891,25 +970,25 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
       b->pool = p;
       b->rec = p->src;
     } else {
-      bool clear = false;
-      st = reorganize_async(b, p, modes[k], s, &clear);
+      st = reorganize_async(b, p, modes[k], s);
       b->mode = modes[k];
       b->pool = p;
     }
     if (st != GC_OK) break;
-    hipStream_t fs = s;
-    if (overlap) {
-      const int q = k % n_side;
-      if (hipEventRecord(gr->events[k], s) != hipSuccess ||
-          hipStreamWaitEvent(gr->side[q], gr->events[k], 0) != hipSuccess) {
-        st = set_err(ctx, GC_E_HIP, "capture: fork");
-        break;
-      }
-      fs = gr->side[q];
-      used[q] = true;
+    if (!overlap) {
+      st = launch_combined_async(b, prm, nodes_dev, acc_dev, s);
+      continue;
     }
-    st = launch_combined_async(b, prm, nodes_dev, acc_dev, fs);
+    if (hipEventRecord(gr->events[k], s) != hipSuccess) {
+      st = set_err(ctx, GC_E_HIP, "capture: fork");
+      break;
+    }
+    // the combined pass of the step before goes in only now, so that in the graph each
+    // reorganisation's first dependent is the next step's chain node and its pass the second:
+    // the graph's launch keeps the chain on one queue and gives the passes the other queues
+    if (k > 0) st = fork_pass(k - 1);
   }
+  if (overlap && st == GC_OK) st = fork_pass(n_steps - 1);
   // join the side streams back into the capture stream
   for (int q = 0; q < n_side; ++q) {
     if (!used[q]) continue;

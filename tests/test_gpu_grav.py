@@ -280,3 +280,137 @@ def test_graph_of_fresh_batches_in_place_mode(ctx, plum):
     for b in bs:
         b.destroy()
     rig.close()
+
+
+def _check_maps(got, want, mode, after=None):
+    assert want["status"] == 0
+    assert np.array_equal(got["U"], want["U"])
+    assert np.array_equal(got["pos"], want["pos"])
+    assert np.array_equal(got["missing"], want["missing"])
+    if after is not None:
+        assert np.array_equal(after, want["slot_of"])
+    if mode != gc.REORG_REDUNDANT:
+        assert np.array_equal(got["new_slot"], want["new_slot"])
+    if mode in (gc.REORG_PACK, gc.REORG_REDUNDANT):
+        assert np.array_equal(got["pranges"], want["pranges"])
+        assert np.array_equal(got["pi_begin"], want["pi_begin"])
+    else:
+        assert np.array_equal(got["ilist"], want["ilist"])
+        assert np.array_equal(got["jlist"], want["jlist"])
+
+
+@pytest.mark.parametrize("mode", [gc.REORG_PACK, gc.REORG_INDIRECT])
+def test_repeated_reorganisations_against_an_evolving_pool(ctx, plum, mode):
+    # two batches reorganised alternately, five calls each, without resets: every call's maps and the
+    # pool afterwards match the oracle run on the pool state before that call (the scan state of a batch
+    # is reused across calls)
+    print(f"[gpu] repeated reorganisations mode={mode}", flush=True)
+    rig = GravRig(ctx, plum, capacity=2 * plum.n)
+    bts = [W.task_subset(plum, np.arange(1000, 1400)), W.task_subset(plum, np.arange(1300, 1900))]
+    bs = [rig.batch(bt) for bt in bts]
+    ids, slots = W.residency(W.batch_union(bts[0]), 2 * plum.n, 0.3, seed=31)
+    rig.place(ids, slots)
+    for call in range(10):
+        k = call % 2
+        before = rig.pool.query()
+        bs[k].reorganize(rig.pool, mode, check_capacity=(call % 3 == 0))
+        got = bs[k].maps()
+        after = rig.pool.query()
+        _check_maps(got, O.maps(bts[k], plum.n, 2 * plum.n, before, mode), mode, after)
+        if call % 4 == 3:
+            rig.pool.evict_staged(bs[k])
+            ev = before.copy()
+            assert np.array_equal(rig.pool.query(), ev), call
+    for b in bs:
+        b.destroy()
+    rig.close()
+
+
+def test_evict_by_ids(ctx, plum):
+    import torch
+    rig = GravRig(ctx, plum)
+    ids = np.arange(100, 5000, 3, dtype=np.int32)
+    slots = np.random.default_rng(4).choice(plum.n, size=ids.size, replace=False).astype(np.int32)
+    rig.place(ids, slots)
+    gone = np.concatenate([ids[::2], np.array([-5, plum.n, plum.n + 7, 7], np.int32)])  # invalid and absent ids skipped
+    rig.pool.evict(torch.from_numpy(gone).cuda())
+    want = np.full(plum.n, -1, np.int32)
+    want[ids[1::2]] = slots[1::2]
+    assert np.array_equal(rig.pool.query(), want)
+    # the freed slots are free again: a batch needing those ids stages them into the lowest free slots
+    bt = W.task_subset(plum, np.arange(0, 300))
+    b = rig.batch(bt)
+    before = rig.pool.query()
+    b.reorganize(rig.pool, gc.REORG_PACK)
+    _check_maps(b.maps(), O.maps(bt, plum.n, plum.n, before, gc.REORG_PACK), gc.REORG_PACK, rig.pool.query())
+    b.destroy()
+    rig.close()
+
+
+def test_overflow_without_capacity_check_still_packs_and_reports(ctx, plum):
+    # with check_capacity = 0 a full pool is not detected up front: the first free slots are used, the
+    # remaining missing records are still packed from the source (forces exact), and maps reports FULL
+    rig = GravRig(ctx, plum, capacity=1500)
+    bt = W.task_subset(plum, np.arange(0, 200))
+    b = rig.batch(bt)
+    rig.acc.fill_(np.nan)
+    b.reorganize(rig.pool, gc.REORG_PACK, check_capacity=False)
+    b.launch(gc.grav_params(order=2), rig.nodes, rig.acc)
+    acc = rig.acc.cpu().numpy()
+    err = rel_l2_per_task(acc, O.grav_workload(plum, order=2, tasks=bt), bt)
+    assert err.max() <= TOL
+    with pytest.raises(gc.GcError) as e:
+        b.maps()
+    assert e.value.status == 3
+    so = rig.pool.query()
+    res = np.flatnonzero(so >= 0)
+    U = W.batch_union(bt)
+    assert res.size == 1500 and np.array_equal(res, U[:1500])  # lowest missing ids got the slots, in order
+    assert np.array_equal(so[res], np.arange(1500))
+    b.destroy()
+    rig.close()
+
+
+def test_graph_with_evicting_fixture_matches_eager_and_oracle(ctx, plum):
+    # base residency (30% of all ids at random slots), rounds evict what the previous round staged:
+    # replays equal the eager sequence bitwise, and every round's maps equal the oracle's on the base state
+    import torch
+    rig = GravRig(ctx, plum)
+    rounds = W.poisson_rounds(plum.n_tasks, 500, seed=28)[:4]
+    bts = [W.task_subset(plum, r) for r in rounds]
+    bs = [rig.batch(bt) for bt in bts]
+    ids, slots = W.residency(np.arange(plum.n), plum.n, 0.3, seed=29)
+    rig.place(ids, slots)
+    base = rig.pool.query()
+    prm = gc.grav_params(order=2)
+    rig.acc.fill_(np.nan)
+    for k, b in enumerate(bs):
+        if k:
+            rig.pool.evict_staged(bs[k - 1])
+        b.reorganize(rig.pool, gc.REORG_PACK, check_capacity=False)
+        b.launch(prm, rig.nodes, rig.acc)
+        torch.cuda.synchronize()
+        _check_maps(b.maps(), O.maps(bts[k], plum.n, plum.n, base, gc.REORG_PACK), gc.REORG_PACK)
+    rig.pool.evict_staged(bs[-1])
+    assert np.array_equal(rig.pool.query(), base)
+    eager = rig.acc.cpu().numpy()
+    s = torch.cuda.Stream()
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), prm, rig.nodes, rig.acc, stream=s,
+                 fixture=gc.FIXTURE_EVICT_STAGED)
+    for rep in range(3):
+        rig.acc.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        got = rig.acc.cpu().numpy()
+        assert np.array_equal(np.isnan(got), np.isnan(eager)), rep
+        assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)]), rep
+        # the last round's staging is still in place; its maps are those of the base state
+        _check_maps(bs[-1].maps(), O.maps(bts[-1], plum.n, plum.n, base, gc.REORG_PACK), gc.REORG_PACK)
+        rig.pool.evict_staged(bs[-1])
+        assert np.array_equal(rig.pool.query(), base), rep
+        # the next replay's first step evicts the last batch's staged set again: a no-op on the base state
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()

@@ -46,21 +46,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(prm):
-    """HBM bytes per force launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None
-    when the kernel source or the launch shape differs from the profiled one."""
+def profiled_traffic(profile: str, shape: dict):
+    """HBM bytes per launch of the profiled kernel from a committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (profiles/<profile>.json), or None when any of its source files or the launch shape
+    differs from the profiled one."""
     import hashlib
-    side = os.path.join(ROOT, "profiles", "k_grav_quad_plummer262144_traffic.json")
+    side = os.path.join(ROOT, "profiles", profile + ".json")
     try:
         meta = json.load(open(side))
-        src = open(os.path.join(ROOT, meta["source"]), "rb").read()
-    except (OSError, ValueError, KeyError):
+        for rel, digest in meta["sources"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest() != digest:
+                return None
+    except (OSError, ValueError, KeyError, AttributeError):
         return None
-    if hashlib.sha256(src).hexdigest() != meta.get("source_sha256"):
-        return None
-    shape = meta.get("shape", {})
-    if (shape.get("tile"), shape.get("waves_per_block"), shape.get("schedule")) != (prm.tile, prm.waves_per_block,
-                                                                                     prm.schedule):
+    if meta.get("shape") != shape:
         return None
     return int(meta["traffic_bytes_per_launch"])
 
@@ -250,7 +249,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default="pack", choices=["pack", "indirect", "sorted", "redundant"])
-    ap.add_argument("--eager", action="store_true", help="launch rounds one by one instead of one graph")
+    ap.add_argument("--form", default="step", choices=["step", "rounds", "eager"],
+                    help="step: one whole-step persistent launch (graph); rounds: a graph of per-round launches; "
+                         "eager: per-round launches from the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rounds", type=int, default=1000, help="rounds of the step timed on the CPU")
     ap.add_argument("--n", type=int, default=262144)
@@ -259,6 +260,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="fixed force-kernel shape instead of the autotuner's")
     ap.add_argument("--waves", type=int, default=4)
     ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 128/256/512")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): there is no multi-GPU path", file=sys.stderr)
@@ -362,12 +364,33 @@ def main():
     missing = [int(b.maps()["missing"].size) if mode != gc.REORG_REDUNDANT else 0 for b in batches]
     pool.evict_staged(batches[-1])
 
-    graph = None
-    if not args.eager:
+    def capture(form, p):
         side = torch.cuda.Stream()
-        graph = gc.Graph(ctx, batches, [pool] * R, [mode] * R, prm, nodes, acc, stream=side,
-                         fixture=gc.FIXTURE_EVICT_STAGED)
+        g = gc.Graph(ctx, batches, [pool] * R, [mode] * R, p, nodes, acc, stream=side, fixture=gc.FIXTURE_EVICT_STAGED)
         torch.cuda.synchronize()
+        return g
+
+    # ---- the batched forms: a graph of per-round launches, and one whole-step persistent launch whose
+    # tile the autotuner picks by timing the captured step (4 waves per task)
+    forms = {}
+    round_graph = capture("rounds", prm)
+    forms["round_graph_ms"] = round(time_kernel(lambda: round_graph.launch(stream=stream), stream, reps=10), 4)
+    sprm, step_graph, step_tiles = None, None, {}
+    if mode == gc.REORG_PACK:
+        for tl in ((args.step_tile,) if args.step_tile else (128, 256, 512)):
+            p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=gc.SCHED_STEP, tile=tl)
+            g = capture("step", p)
+            step_tiles[tl] = round(time_kernel(lambda: g.launch(stream=stream), stream, reps=10), 4)
+            if sprm is None or step_tiles[tl] < step_tiles[sprm.tile]:
+                if step_graph is not None:
+                    step_graph.destroy()
+                sprm, step_graph = p, g
+            else:
+                g.destroy()
+        forms["step_graph_ms_by_tile"] = step_tiles
+    log(f"[bench] forms: {forms}")
+    form = args.form if (args.form != "step" or step_graph is not None) else "rounds"
+    graph = {"step": step_graph, "rounds": round_graph, "eager": None}[form]
 
     def step():
         if graph is None:
@@ -385,7 +408,17 @@ def main():
     t2 = time.perf_counter()
     ms_step = (t2 - t1) * 1e3 / args.steps
     value = interactions / (ms_step * 1e-3) / 1e9
-    log(f"[bench] step {ms_step:.4f} ms  {value:.1f} G-interactions/s")
+    log(f"[bench] step {ms_step:.4f} ms  {value:.1f} G-interactions/s ({form})")
+    # the eager form's step time, for comparison
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    for _ in range(3):
+        one_pass(mode)
+    torch.cuda.synchronize()
+    forms["eager_ms"] = round((time.perf_counter() - te) * 1e3 / 3, 4)
+    pool.evict_staged(batches[-1])
+    if graph is not None and form == "step":
+        step_kernel_ms = time_kernel(lambda: graph.launch(stream=stream), stream, reps=10)
 
     # ---- per-phase device times with HIP events on the launch stream (eager, same work)
     def phases(m, reps):
@@ -446,6 +479,7 @@ def main():
                         "ginteractions_per_s": round(interactions / (ms_all * 1e-3) / 1e9, 3)}
         allb.destroy()
     occ_blocks, n_cu = ctx.occupancy(prm)
+    step_occ = ctx.occupancy(sprm)[0] if sprm is not None else None
 
     extra = {}
     if not args.quick:
@@ -453,7 +487,31 @@ def main():
         extra["lj"] = leg_lj(gc, W, torch, ctx)
         extra["adjoint"] = leg_adjoint(gc, W, torch, ctx)
 
-    kname = f"k_grav<2, false, {'true' if prm.schedule else 'false'}>"
+    form_text = {"step": "one whole-step persistent launch (HIP graph) per step",
+                 "rounds": "one HIP graph of per-round launches per step", "eager": "per-round launches"}[form]
+    per_round = {"kernel": f"k_grav<2, false, {'true' if prm.schedule else 'false'}> (tile {prm.tile}, "
+                           f"{prm.waves_per_block} waves per task)",
+                 "kernel_ms_per_step": round(kern_ms, 4), "avg_launch_ms": round(kern_ms / R, 5),
+                 "tflops": round(achieved_tflops, 3), "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+                 "traffic": profiled_traffic("k_grav_quad_plummer262144_traffic",
+                                             {"tile": prm.tile, "waves_per_block": prm.waves_per_block,
+                                              "schedule": prm.schedule})}
+    if form == "step":
+        # the dominant (and only) kernel of a step: algorithmic flop of the whole step over its duration
+        step_tflops = flops_step / (step_kernel_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(step_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(step_tflops / PEAK_FP32_TFLOPS, 4),
+                    "traffic": profiled_traffic("k_step_quad_plummer262144_traffic", {"tile": sprm.tile}),
+                    "kernel": f"k_step<2> (every round's eviction, reorganisation and combined quadrupole pass; "
+                              f"tile {sprm.tile}, 4 waves per task)",
+                    "flops_per_launch": flops_step, "avg_launch_ms": round(step_kernel_ms, 5),
+                    "frac_of_nonpacked_peak": round(step_tflops / PEAK_FP32_NONPACKED_TFLOPS, 4)}
+    else:
+        roofline = {"bound": "alu", "achieved": per_round["tflops"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": per_round["frac"], "traffic": per_round["traffic"], "kernel": per_round["kernel"],
+                    "flops_per_step": flops_step, "kernel_ms_per_step": per_round["kernel_ms_per_step"],
+                    "avg_launch_ms": per_round["avg_launch_ms"],
+                    "frac_of_nonpacked_peak": round(achieved_tflops / PEAK_FP32_NONPACKED_TFLOPS, 4)}
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -470,17 +528,12 @@ def main():
         "config": {"workload": f"nbody-plummer-{w.n}: bucket 32, theta 0.7, monopole+quadrupole, eps 0.01, "
                                f"{R} Poisson(2048) rounds, half of all particles resident at random slots "
                                f"(each round evicts the previous round's staging), {args.mode} reorganisation, "
-                               f"{'eager' if args.eager else 'one HIP graph'} per step",
+                               f"{form_text}",
                    "n": w.n, "tasks": w.n_tasks, "rounds": R, "interactions_per_step": interactions,
-                   "mode": args.mode},
-        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-                     "traffic": profiled_traffic(prm),
-                     "kernel": f"{kname} (combined quadrupole force pass, tile {prm.tile}, "
-                               f"{prm.waves_per_block} waves per task)",
-                     "flops_per_step": flops_step, "kernel_ms_per_step": round(kern_ms, 4),
-                     "avg_launch_ms": round(kern_ms / R, 5),
-                     "frac_of_nonpacked_peak": round(achieved_tflops / PEAK_FP32_NONPACKED_TFLOPS, 4)},
+                   "mode": args.mode, "form": form},
+        "roofline": roofline,
+        "per_round_force_kernel": per_round,
+        "forms": forms,
         "cpu_baseline": cpu,
         "reorganize": {"gbps": round(reorg_gbps, 2), "frac_hbm": round(reorg_gbps / PEAK_HBM_GBPS, 4),
                        "ms_per_step": round(reorg_ms, 4), "avg_launch_ms": round(reorg_ms / R, 5),
@@ -491,14 +544,16 @@ def main():
         "autotune_largest_round": tuned,
         "modes": mode_cmp,
         "combined_all_tasks_one_launch": combined_all,
-        "occupancy": {"blocks_per_cu": occ_blocks, "cus": n_cu, "waves_per_block": prm.waves_per_block},
+        "occupancy": {"blocks_per_cu": occ_blocks, "cus": n_cu, "waves_per_block": prm.waves_per_block,
+                      "step_kernel_blocks_per_cu": step_occ},
         "hbm_copy_gbps": round(copy_gbps, 1),
         "bwd_fwd": extra.get("adjoint", {}).get("bwd_fwd"),
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
-    if graph is not None:
-        graph.destroy()
+    for g in (round_graph, step_graph):
+        if g is not None:
+            g.destroy()
     for b in batches:
         b.destroy()
     pool.destroy()

@@ -253,6 +253,19 @@ enum { GC_FORCE_GRAV_MONO = 1, GC_FORCE_GRAV_QUAD = 2, GC_FORCE_LJ = 3 };
  * in FP32), force on i = 24 eps (2 q^6 - q^3) / r^2 d, q = sigma^2 / r^2,
  * d = x_i - x_j - shift, equal and opposite on j; a = F / m.
  */
+/*
+ * Schedules.  GC_SCHED_TASKS: one launch, one workgroup per task, longest
+ * tasks first.  GC_SCHED_QUEUE: a persistent grid (CUs x occupancy) takes
+ * tasks from a device counter in the same order.  GC_SCHED_STEP (graph
+ * capture only, gravity, PACK, one pool, fixture NONE or EVICT_STAGED,
+ * distinct batches): one persistent launch runs all captured steps -- each
+ * step's eviction fixture, reorganisation and combined pass -- as ordered
+ * work items with device-side dependencies, the reorganisation one step
+ * ahead of the passes; 4 waves per task; results bitwise equal to the
+ * per-step launches.
+ */
+enum { GC_SCHED_TASKS = 0, GC_SCHED_QUEUE = 1, GC_SCHED_STEP = 2 };
+
 typedef struct {
   int32_t kind;             /* GC_FORCE_* */
   float G, soft_eps;        /* gravity */
@@ -261,7 +274,7 @@ typedef struct {
   const float* sig_t;       /* device */
   const float* mass_t;      /* device */
   float r_cut;
-  int32_t schedule;         /* 0 = one launch over all tasks; 1 = persistent work queue */
+  int32_t schedule;         /* GC_SCHED_*: how the combined pass is launched */
   int32_t tile;             /* direct-record tile per wavefront: 0 = default (256); 64..1024, multiple of 64 */
   int32_t waves_per_block;  /* 0 = default (4); 1..8 */
   int32_t grid_blocks;      /* persistent schedule: 0 = CUs x occupancy */

@@ -90,6 +90,7 @@ struct ReorgArgs {
   uint64_t* free_list;     // tagged free-slot entries, |U| of them
   int32_t* state;
   int32_t nbf, nbu;        // set by the launcher
+  int32_t evict_after;     // whole-step kernel: a union block evicts what it staged once it has packed it
 };
 
 // occupancy entries (one per slot, padded) allocated for a pool of `cap` slots
@@ -116,6 +117,41 @@ hipError_t grav_occupancy(int order, bool lists, bool persistent, int tile, int 
 hipError_t launch_lj(bool persistent, const LJArgs& a, int waves_per_block, int grid_blocks, hipStream_t s);
 hipError_t launch_lj_finish(float4* acc, const float* mass_t, const float4* rec_by_id, int32_t n,
                             hipStream_t s);
+
+// ---------------------------------------------------------------- whole-step persistent kernel
+
+// Work items of one step, in ticket order; see step.hip.
+enum { kItemEvict = 0, kItemFree = 1, kItemUnion = 2, kItemForce = 3 };
+constexpr int kEvictBlock = 2048;  // ids per eviction item
+struct StepSeg {
+  int32_t type, round;   // item kind, round
+  int32_t first, count;  // tickets [first, first + count)
+};
+struct StepRound {
+  GravArgs grav;          // the round's combined pass over its packed records
+  ReorgArgs reorg;        // the round's reorganisation (nbf, nbu set)
+  const int32_t* ev_ids;  // ids evicted before the round (missing list of the round before), or null
+  const int32_t* ev_n;    // their count (device)
+  int32_t ev_bound;       // bound of that count (entries of ev_ids)
+  int32_t n_ids;
+  int32_t n_evict;        // eviction items of the round
+  int32_t n_chain;        // free-slot + union items of the round
+};
+struct StepArgs {
+  const StepSeg* segs;
+  int32_t n_segs;
+  int32_t n_items;
+  const StepRound* rounds;
+  int32_t n_rounds;
+  uint64_t* ctr;          // counter c at ctr[kCtrStride * c] (all monotonic across launches); a wait that
+                          // hits its bound sets the error word of its round's batch state
+};
+constexpr int kCtrStride = 32;  // one 256-byte line per step counter
+constexpr int kCtrTickets = 0, kCtrExits = 1, kCtrEpoch = 2, kCtrRounds = 3;  // then per round r:
+                                // kCtrRounds + 2r eviction items done, kCtrRounds + 2r + 1 free + union done
+constexpr int kStepLead = 2;    // rounds by which the reorganisation items precede the passes
+hipError_t launch_step(int order, const StepArgs& a, int grid, int tile, hipStream_t s);
+hipError_t step_occupancy(int order, int tile, int* blocks);
 
 struct GravAdjArgs {
   GravArgs f;              // forward arguments (lists, records, nodes)

@@ -1,165 +1,19 @@
-// Combined Barnes-Hut force kernel (Sec. 3.1: many work requests in one launch;
-// Sec. 4.1: a bucket's particles share one list of nodes and direct particles).
-//
-// Schedule: one workgroup of W wavefronts per task; the W waves split the
-// task's node and direct lists.  A bucket holds few targets (about 10 on
-// average for a Plummer sphere with buckets of 32), so within a wavefront the
-// 64 lanes are split as (target i) x (source slice s): S = floor(64 / i_count)
-// slices, lane = s * i_count + i.  Source records (direct particles, or node records) are
-// staged by the wavefront into its private LDS tile with coalesced loads; the
-// tile is padded with zero-mass entries to S * C records so every slice runs
-// exactly C iterations with no per-iteration bounds test; a lane reads its
-// slice's records from LDS (lanes of one slice read the same address: an LDS
-// broadcast).  Node records of the next tile are prefetched into registers
-// while the current tile is computed.  Per tile each lane sums its slice in
-// FP32 and adds the tile's partial to an FP64 running sum; at the end the
-// slices and then the waves of each target are reduced in FP64 through LDS in
-// a fixed order and the target's float4 is written once.  No atomics: results
-// are bitwise independent of task order and of the schedule.
-//
-// The inner loops are plain FP32 VALU code (v_sub / v_fma / v_mul) with the
-// hardware reciprocal square root; pairwise forces are not a dense
-// contraction, so no MFMA.
-#include "gc_internal.h"
+// Combined Barnes-Hut force kernel, one launch per batch: one workgroup per
+// task (task order longest first), or a persistent grid that takes tasks from
+// a device counter.  The per-task code is in grav_dev.h.
+#include "grav_dev.h"
 
 namespace gc {
 namespace {
 
-__device__ __forceinline__ void wave_sync() {
-  // Lanes of one wavefront exchange data through wavefront-private LDS; the
-  // LDS unit executes a wavefront's instructions in order, so only compiler
-  // reordering must be prevented here.
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
+using dev::grav_lds_per_wave;
+using dev::grav_task;
+using dev::uniform;
 
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ int wave_excl_scan(int v, int* total) {
-  const int lane = threadIdx.x & 63;
-  int inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int u = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += u;
-  }
-  *total = __shfl(inc, 63, 64);
-  return inc - v;
-}
-
-// Sum over a tile of C pair/monopole records per slice: p = records of this lane's slice.
-__device__ __forceinline__ void tile_pairs(const float4* __restrict__ p, int C, float xi, float yi, float zi,
-                                           float eps2, float& ax, float& ay, float& az) {
-  int k = 0;
-  for (; k + 4 <= C; k += 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      float4 j = p[k + u];
-      float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
-      float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-      float ri = __builtin_amdgcn_rsqf(r2);
-      float mr = j.w * ri;
-      float ri2 = ri * ri;
-      float sc = mr * ri2;
-      ax = __builtin_fmaf(dx, sc, ax);
-      ay = __builtin_fmaf(dy, sc, ay);
-      az = __builtin_fmaf(dz, sc, az);
-    }
-  }
-  for (; k < C; ++k) {
-    float4 j = p[k];
-    float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
-    float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-    float ri = __builtin_amdgcn_rsqf(r2);
-    float mr = j.w * ri;
-    float ri2 = ri * ri;
-    float sc = mr * ri2;
-    ax = __builtin_fmaf(dx, sc, ax);
-    ay = __builtin_fmaf(dy, sc, ay);
-    az = __builtin_fmaf(dz, sc, az);
-  }
-}
-
-// Quadrupole node records in LDS: (com, M), (3Sxx, 3Syy, 3Szz, 3Sxy), (3Sxz, 3Syz, 1.5 T, 0).
-__device__ __forceinline__ void tile_quads(const float4* __restrict__ p, int C, float xi, float yi, float zi,
-                                           float eps2, float& ax, float& ay, float& az) {
-#pragma unroll 2
-  for (int k = 0; k < C; ++k) {
-    float4 a = p[3 * k], b = p[3 * k + 1], c = p[3 * k + 2];
-    float dx = xi - a.x, dy = yi - a.y, dz = zi - a.z;
-    float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
-    float ri = __builtin_amdgcn_rsqf(r2);
-    float q = ri * ri;
-    float r3 = ri * q;
-    float r5 = r3 * q;
-    // S' d with S' = 3 S
-    float sx = __builtin_fmaf(c.x, dz, __builtin_fmaf(b.w, dy, b.x * dx));
-    float sy = __builtin_fmaf(c.y, dz, __builtin_fmaf(b.y, dy, b.w * dx));
-    float sz = __builtin_fmaf(b.z, dz, __builtin_fmaf(c.y, dy, c.x * dx));
-    float dsd = __builtin_fmaf(dz, sz, __builtin_fmaf(dy, sy, dx * sx));  // 3 d.S.d
-    // coefficient of d: -M r^-3 + 1.5 T r^-5 - 7.5 (d.S.d) r^-7 = r^-3 (-M + q (1.5 T - 2.5 q dsd))
-    float u = __builtin_fmaf(dsd, q * -2.5f, c.z);
-    float v = __builtin_fmaf(q, u, -a.w);
-    float cf = r3 * v;
-    ax = __builtin_fmaf(r5, sx, __builtin_fmaf(cf, dx, ax));
-    ay = __builtin_fmaf(r5, sy, __builtin_fmaf(cf, dy, ay));
-    az = __builtin_fmaf(r5, sz, __builtin_fmaf(cf, dz, az));
-  }
-}
-
-// Node record for LDS: monopole (com, M); quadrupole adds (3 Sxx, 3 Syy, 3 Szz, 3 Sxy), (3 Sxz, 3 Syz, 1.5 T, 0).
-template <int ORDER>
-struct NodeRegs {
-  float4 v0, v1, v2;
-};
-
-template <int ORDER>
-__device__ __forceinline__ NodeRegs<ORDER> load_node(const float4* __restrict__ nodes, int idx) {
-  NodeRegs<ORDER> r;
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  r.v0 = z; r.v1 = z; r.v2 = z;
-  if (idx >= 0) {
-    const float4* nd = nodes + 3 * idx;
-    r.v0 = nd[0];
-    if (ORDER == 2) {
-      r.v1 = nd[1];
-      r.v2 = nd[2];
-    }
-  }
-  return r;
-}
-
-template <int ORDER>
-__device__ __forceinline__ void store_node(float4* L, int e, const NodeRegs<ORDER>& r) {
-  if (ORDER == 1) {
-    L[e] = r.v0;
-  } else {
-    L[3 * e] = r.v0;
-    L[3 * e + 1] = make_float4(3.f * r.v1.x, 3.f * r.v1.y, 3.f * r.v1.z, 3.f * r.v1.w);
-    L[3 * e + 2] = make_float4(3.f * r.v2.x, 3.f * r.v2.y, 1.5f * r.v2.z, 0.f);
-  }
-}
-
-// One workgroup of W wavefronts per task.  Wave w takes the task's nodes w, w + W, ...
-// and its direct ranges w, w + W, ... (address lists: windows w, w + W, ...), so W waves
-// share one task's lists; the per-target sums are reduced across slices within each wave
-// and then across the W waves, in a fixed order.
 template <int ORDER, bool LISTS, bool PERSIST>
 __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
   extern __shared__ float4 smem[];
   __shared__ int s_task;
-  const int lane = threadIdx.x & 63;
-  const int wid = uniform(threadIdx.x >> 6);
-  const int W = blockDim.x >> 6;
-  const int tile = a.tile;
-  const int rec_cap = (tile + 64 > 3 * (kNodeTile + 64)) ? tile + 64 : 3 * (kNodeTile + 64);
-  const int per_wave = rec_cap + 96;
-  float4* L = smem + wid * per_wave;
-  double* red = reinterpret_cast<double*>(L + rec_cap);
-  // the range tables of the direct phase share the reduction scratch (live at different times)
-  int* RO = reinterpret_cast<int*>(red);  // range start offsets within the group (64)
-  int* RB = RO + 64;                      // range begins (64)
-
   int iter = 0;
   while (true) {
     // Tasks run in longest-first order: block b starts with order[b]; in the persistent
@@ -181,159 +35,13 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
       got = blockIdx.x;
     }
     if (got >= a.n_tasks) break;
-    const int t = uniform(a.order[got]);
-    const gc_task tk = a.tasks[t];
-    const int ic = tk.i_count;
-    for (int i0 = 0; i0 < ic; i0 += 64) {
-      const int icc = ic - i0 < 64 ? ic - i0 : 64;
-      const int S = 64 / icc;
-      const int il = lane % icc;
-      const int sl = lane / icc;
-      const bool active = sl < S;
-      float xi = 0.f, yi = 0.f, zi = 0.f;
-      if (active) {
-        int p;
-        if (LISTS) p = a.ilist[a.ioff[t] + i0 + il];
-        else p = (a.ibeg ? a.ibeg[t] : tk.i_begin) + i0 + il;
-        float4 r = a.rec[p];
-        xi = r.x; yi = r.y; zi = r.z;
-      }
-      double Ax = 0.0, Ay = 0.0, Az = 0.0;
-
-      // ---- node terms: this wave's nodes are list entries w, w + W, ...
-      {
-        const int nw = tk.n_count > wid ? (tk.n_count - wid + W - 1) / W : 0;
-        const int* nl = a.node_idx + tk.n_first + wid;
-        int idx_next = (64 < nw && 64 + lane < nw) ? nl[(64 + lane) * W] : -1;
-        NodeRegs<ORDER> cur = load_node<ORDER>(a.nodes, lane < nw ? nl[lane * W] : -1);
-        for (int nb = 0; nb < nw; nb += kNodeTile) {
-          const int cnt = nw - nb < kNodeTile ? nw - nb : kNodeTile;
-          const int C = (cnt + S - 1) / S;
-          const int padded = S * C;
-          store_node<ORDER>(L, lane, cur);  // entries >= cnt are zero records
-          for (int e = 64 + lane; e < padded; e += 64) store_node<ORDER>(L, e, load_node<ORDER>(a.nodes, -1));
-          // prefetch the next tile's records and the index of the one after
-          if (nb + kNodeTile < nw) {
-            cur = load_node<ORDER>(a.nodes, idx_next);
-            const int e2 = nb + 2 * kNodeTile + lane;
-            idx_next = e2 < nw ? nl[e2 * W] : -1;
-          }
-          wave_sync();
-          if (active) {
-            float ax = 0.f, ay = 0.f, az = 0.f;
-            if (ORDER == 1) {
-              // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
-              tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-            } else {
-              tile_quads(L + 3 * sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-            }
-            Ax += ax; Ay += ay; Az += az;
-          }
-          wave_sync();
-        }
-      }
-
-      // ---- direct terms
-      if (LISTS) {
-        const int jb = a.joff[t], jn = a.joff[t + 1] - jb;
-        for (int ws = wid * tile; ws < jn; ws += W * tile) {
-          const int cnt = jn - ws < tile ? jn - ws : tile;
-          const int C = (cnt + S - 1) / S;
-          const int padded = S * C;
-          for (int e = lane; e < padded; e += 64) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (e < cnt) v = a.rec[a.jlist[jb + ws + e]];
-            L[e] = v;
-          }
-          wave_sync();
-          if (active) {
-            float ax = 0.f, ay = 0.f, az = 0.f;
-            tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-            Ax += ax; Ay += ay; Az += az;
-          }
-          wave_sync();
-        }
-      } else {
-        // this wave's ranges are entries w, w + W, ... of the task's range list; groups of up to
-        // 64 ranges are flattened by a wave scan, and each lane copies one flat position,
-        // finding its range by binary search over the offsets kept in LDS
-        const int nrw = tk.j_nranges > wid ? (tk.j_nranges - wid + W - 1) / W : 0;
-        const int2* rl = a.ranges + tk.j_first + wid;
-        for (int rg = 0; rg < nrw; rg += 64) {
-          const int nr = nrw - rg < 64 ? nrw - rg : 64;
-          int2 g = make_int2(0, 0);
-          if (lane < nr) g = rl[(rg + lane) * W];
-          int total;
-          const int o = wave_excl_scan(g.y, &total);
-          total = uniform(total);
-          RO[lane] = lane < nr ? o : 0x7fffffff;
-          RB[lane] = g.x;
-          wave_sync();
-          for (int ws = 0; ws < total; ws += tile) {
-            const int cnt = total - ws < tile ? total - ws : tile;
-            const int C = (cnt + S - 1) / S;
-            const int padded = S * C;
-            for (int e = lane; e < padded; e += 64) {
-              float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-              if (e < cnt) {
-                const int f = ws + e;
-                int lo = 0, hi = nr - 1;
-                while (lo < hi) {
-                  const int mid = (lo + hi + 1) >> 1;
-                  if (RO[mid] <= f) lo = mid;
-                  else hi = mid - 1;
-                }
-                v = a.rec[RB[lo] + (f - RO[lo])];
-              }
-              L[e] = v;
-            }
-            wave_sync();
-            if (active) {
-              float ax = 0.f, ay = 0.f, az = 0.f;
-              tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-              Ax += ax; Ay += ay; Az += az;
-            }
-            wave_sync();
-          }
-        }
-      }
-
-      // ---- reduce: slices within the wave, then the W waves, in a fixed order
-      red[3 * lane] = Ax;
-      red[3 * lane + 1] = Ay;
-      red[3 * lane + 2] = Az;
-      wave_sync();
-      double sx = 0.0, sy = 0.0, sz = 0.0;
-      if (lane < icc) {
-        for (int s = 0; s < S; ++s) {
-          const double* q = red + 3 * (s * icc + lane);
-          sx += q[0]; sy += q[1]; sz += q[2];
-        }
-      }
-      wave_sync();
-      if (lane < icc) {
-        red[3 * lane] = sx;
-        red[3 * lane + 1] = sy;
-        red[3 * lane + 2] = sz;
-      }
-      __syncthreads();
-      if (wid == 0 && lane < icc) {
-        double tx = 0.0, ty = 0.0, tz = 0.0;
-        for (int w = 0; w < W; ++w) {
-          const double* q = reinterpret_cast<const double*>(smem + w * per_wave + rec_cap) + 3 * lane;
-          tx += q[0]; ty += q[1]; tz += q[2];
-        }
-        a.acc[tk.i_begin + i0 + lane] = make_float4((float)(a.G * tx), (float)(a.G * ty), (float)(a.G * tz), 0.f);
-      }
-      __syncthreads();
-    }
+    grav_task<ORDER, LISTS>(a, uniform(a.order[got]), smem);
   }
 }
 
 template <int ORDER, bool LISTS, bool PERSIST>
 hipError_t launch_one(const GravArgs& a, int wpb, int grid, hipStream_t s) {
-  const int rec_cap = (a.tile + 64 > 3 * (kNodeTile + 64)) ? a.tile + 64 : 3 * (kNodeTile + 64);
-  size_t lds = (size_t)wpb * (rec_cap + 96) * sizeof(float4);
+  size_t lds = (size_t)wpb * grav_lds_per_wave(a.tile) * sizeof(float4);
   if (!PERSIST) grid = a.n_tasks;
   if (grid < 1) return hipSuccess;
   if (lds > 65536) {
@@ -347,8 +55,7 @@ hipError_t launch_one(const GravArgs& a, int wpb, int grid, hipStream_t s) {
 
 template <int ORDER, bool LISTS, bool PERSIST>
 hipError_t occ_one(int tile, int wpb, int* blocks) {
-  const int rec_cap = (tile + 64 > 3 * (kNodeTile + 64)) ? tile + 64 : 3 * (kNodeTile + 64);
-  size_t lds = (size_t)wpb * (rec_cap + 96) * sizeof(float4);
+  size_t lds = (size_t)wpb * grav_lds_per_wave(tile) * sizeof(float4);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

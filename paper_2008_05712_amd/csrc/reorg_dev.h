@@ -1,0 +1,324 @@
+// Device code of the reorganisation (Sec. 3.2), shared by the per-batch
+// kernels and the whole-step persistent kernel: the tagged single-pass scans,
+// the free-slot and union (lookup, slot assignment, staging, packing) roles of
+// a block, and eviction.
+//
+// Inside the whole-step kernel (COH = true) other blocks change the chare
+// table, the occupancy flags and the pool between rounds, and the L2 of one XCD
+// is not coherent with the others': there the roles read those with
+// device-scope coherent (sc1) loads, and the kernel writes its L2 back (a
+// device-scope release) before it counts an item done.  The per-batch kernel
+// (COH = false) never reads in-kernel what another block wrote to them and uses
+// plain loads.  Items of one round exchange only tagged words (look-back,
+// free-slot list, totals), through device-scope atomics.
+#pragma once
+
+#include "gc_internal.h"
+
+namespace gc {
+namespace dev {
+
+constexpr int kRThreads = 256;                      // threads of every reorganisation block
+constexpr int kUItems = 8;                          // union entries per thread
+constexpr int kUBlock = kRThreads * kUItems;        // union entries per block
+constexpr int kFItems = 16;                         // occupancy entries per thread
+constexpr int kFBlock = kRThreads * kFItems;        // pool slots per free-scan block
+constexpr uint32_t kSpinLimit = 1u << 22;           // bound on every wait: each wave exits
+
+// state[] layout (int32 units); see gc_internal.h for the host-visible part
+constexpr int kTicket = 8, kDone = 9, kTag = 10, kFreeTotal = 12, kLookBack = 16;
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread across the block; block total to *total.
+__device__ __forceinline__ int block_excl_scan(int v, int* sh_wave, int* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  int inc = wave_incl_scan(v);
+  if (lane == 63) sh_wave[w] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int k = 0; k < nw; ++k) {
+    int s = sh_wave[k];
+    off += (k < w) ? s : 0;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+// Tagged 64-bit words: bits 0-30 a count, bit 31 a flag, bits 32-63 the call tag.  Relaxed
+// device-scope atomics: each word carries its own payload, nothing else is published through it
+// (acquire/release here would write back and invalidate the caches on every probe).
+__device__ __forceinline__ uint64_t tword(uint32_t tag, uint32_t flag, uint32_t cnt) {
+  return ((uint64_t)tag << 32) | ((uint64_t)flag << 31) | (uint64_t)cnt;
+}
+__device__ __forceinline__ void tstore(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t tload(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t iload(int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void istore(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wavefront 0 of chain block `bid`: publish the block aggregate, look back over up to 64
+// predecessors per probe (a word of another call counts as not yet written; the run up to the
+// nearest inclusive prefix is summed once all of it is written), publish the inclusive prefix,
+// return the exclusive prefix.
+__device__ __forceinline__ uint32_t look_back(uint64_t* flags, int bid, uint32_t tag, uint32_t agg, int32_t* err) {
+  const int lane = threadIdx.x & 63;
+  if (bid == 0) {
+    if (lane == 0) tstore(flags, tword(tag, 1, agg));
+    return 0;
+  }
+  if (lane == 0) tstore(flags + bid, tword(tag, 0, agg));
+  uint32_t x = 0, spins = 0;
+  int hi = bid - 1;
+  while (true) {
+    const int j = hi - lane;
+    const uint64_t w = j >= 0 ? tload(flags + j) : tword(tag, 1, 0);  // before block 0: a zero prefix
+    const bool mine = (uint32_t)(w >> 32) == tag;
+    const uint64_t pre = __ballot(mine && ((w >> 31) & 1u));
+    const uint64_t emp = __ballot(!mine);
+    const int stop = pre ? __builtin_ctzll(pre) : 63;  // last lane of the run to sum
+    const uint64_t run = stop == 63 ? ~0ull : ((2ull << stop) - 1ull);
+    if (emp & run) {
+      if (++spins > kSpinLimit) {
+        if (lane == 0) istore(err, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    uint32_t v = lane <= stop ? (uint32_t)(w & 0x7fffffffu) : 0u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    x += v;
+    if (pre) break;
+    hi -= 64;
+  }
+  if (lane == 0) tstore(flags + bid, tword(tag, 1, x + agg));
+  return x;
+}
+
+template <bool COH>
+__device__ __forceinline__ int32_t ld_i32(const int32_t* p) {
+  if (COH) return iload(const_cast<int32_t*>(p));
+  return *p;
+}
+
+// One 16-byte record; COH: two device-scope 8-byte loads.
+template <bool COH>
+__device__ __forceinline__ float4 ld_rec(const float4* p) {
+  if (!COH) return *p;
+  uint64_t* q = reinterpret_cast<uint64_t*>(const_cast<float4*>(p));
+  const uint64_t lo = tload(q), hi = tload(q + 1);
+  return make_float4(__uint_as_float((uint32_t)lo), __uint_as_float((uint32_t)(lo >> 32)),
+                     __uint_as_float((uint32_t)hi), __uint_as_float((uint32_t)(hi >> 32)));
+}
+
+// Free-slot side: the lowest free slots in ascending order, listed up to `limit` (|U|, an upper
+// bound on the number of missing records); the last block publishes the pool's free count.
+template <bool COH>
+__device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex) {
+  uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack);
+  const int64_t s0 = (int64_t)b * kFBlock + (int64_t)threadIdx.x * kFItems;
+  uint32_t f = 0;
+  if (s0 < a.cap) {
+    if (COH) {
+      const int32_t* o = reinterpret_cast<const int32_t*>(a.occ) + s0;
+#pragma unroll
+      for (int k = 0; k < kFItems; ++k)
+        if (ld_i32<true>(o + k) == 0 && s0 + k < a.cap) f |= 1u << k;
+    } else {
+      const uint4* o4 = reinterpret_cast<const uint4*>(a.occ + s0);  // occ is padded to whole blocks
+#pragma unroll
+      for (int q = 0; q < kFItems / 4; ++q) {
+        const uint4 o = o4[q];
+        const uint32_t ov[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (ov[k] == 0u && s0 + 4 * q + k < a.cap) f |= 1u << (4 * q + k);
+      }
+    }
+  }
+  int tot;
+  int r = block_excl_scan(__popc(f), sh, &tot);
+  if (threadIdx.x < 64) {
+    const uint32_t ex = look_back(flags, b, tag, (uint32_t)tot, a.state + GC_STATE_ERR);
+    if (threadIdx.x == 0) {
+      *s_ex = ex;
+      if (b == a.nbf - 1) {
+        tstore(reinterpret_cast<uint64_t*>(a.state + kFreeTotal), tword(tag, 0, ex + (uint32_t)tot));
+        istore(a.state + GC_STATE_FREE, (int32_t)(ex + (uint32_t)tot));
+      }
+    }
+  }
+  __syncthreads();
+  r += (int)*s_ex;
+  if (r >= a.u) return;
+#pragma unroll
+  for (int k = 0; k < kFItems; ++k)
+    if ((f >> k) & 1u) {
+      if (r < a.u) tstore(a.free_list + r, tword(tag, 0, (uint32_t)(s0 + k)));
+      ++r;
+    }
+}
+
+// Union side: residency of this block's chunk of U, the missing ranks, then slot assignment,
+// staging and the packed copies.
+template <bool COH>
+__device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex) {
+  uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbf;
+  const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
+  int32_t id[kUItems], sl[kUItems];
+  uint32_t fm = 0;
+  {
+    const int4* u4 = reinterpret_cast<const int4*>(a.U + k0);  // U is padded to whole blocks
+    const int4 x = u4[0], y = u4[1];
+    id[0] = x.x; id[1] = x.y; id[2] = x.z; id[3] = x.w;
+    id[4] = y.x; id[5] = y.y; id[6] = y.z; id[7] = y.w;
+  }
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    sl[i] = 0;
+    if (k0 + i < a.u) {
+      sl[i] = ld_i32<COH>(a.slot_of + id[i]);
+      if (sl[i] < 0) fm |= 1u << i;
+    }
+  }
+  // every entry's record -- from the pool if resident, from the source if missing -- is loaded
+  // before the ranks are known, and its packed copy written at once: neither waits for the scans
+  float rx[kUItems], ry[kUItems], rz[kUItems], rw[kUItems];
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if ((fm >> i) & 1u) v = a.src[id[i]];
+    else if (k0 + i < a.u) v = ld_rec<COH>(a.pool + sl[i]);
+    rx[i] = v.x;
+    ry[i] = v.y;
+    rz[i] = v.z;
+    rw[i] = v.w;
+  }
+  int tot;
+  int rm = block_excl_scan(__popc(fm), sh, &tot);
+  if (threadIdx.x < 64) {
+    const uint32_t ex = look_back(flags, b, tag, (uint32_t)tot, a.state + GC_STATE_ERR);
+    if (threadIdx.x == 0) {
+      *s_ex = ex;
+      if (b == a.nbu - 1) {
+        istore(a.state + GC_STATE_UNION, a.u);
+        istore(a.state + GC_STATE_MISSING, (int32_t)(ex + (uint32_t)tot));
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    const int64_t k = k0 + i;
+    if (k < a.u) {
+      if (!((fm >> i) & 1u)) a.uslot[k] = sl[i];
+      if (a.pack) a.packed[k] = make_float4(rx[i], ry[i], rz[i], rw[i]);
+    }
+  }
+  __syncthreads();
+  if (!fm) return;
+  rm += (int)*s_ex;
+  // the rm-th free slot for the rm-th missing record, once its free-scan block has listed it (none if
+  // the pool is full): one probe for all of this thread's entries in flight, then a bounded wait that
+  // re-probes the entries still unlisted
+  int32_t sidx[kUItems];  // slot of each missing entry once listed (-1: none)
+  uint32_t pend = 0;
+  {
+    int r = rm;
+#pragma unroll
+    for (int i = 0; i < kUItems; ++i) {
+      sidx[i] = -1;
+      if ((fm >> i) & 1u) {
+        const uint64_t w = tload(a.free_list + r++);
+        if ((uint32_t)(w >> 32) == tag) sidx[i] = (int32_t)(w & 0x7fffffffu);
+        else pend |= 1u << i;
+      }
+    }
+  }
+  uint32_t spins = 0;
+  while (pend) {
+    if (++spins > kSpinLimit) {
+      istore(a.state + GC_STATE_ERR, 1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    const uint64_t t = tload(reinterpret_cast<uint64_t*>(a.state + kFreeTotal));
+    const bool total_known = (uint32_t)(t >> 32) == tag;
+    int r = rm;
+#pragma unroll
+    for (int i = 0; i < kUItems; ++i)
+      if ((fm >> i) & 1u) {
+        if ((pend >> i) & 1u) {
+          const uint64_t w = tload(a.free_list + r);
+          if ((uint32_t)(w >> 32) == tag) {
+            sidx[i] = (int32_t)(w & 0x7fffffffu);
+            pend &= ~(1u << i);
+          } else if (total_known && (uint32_t)r >= (uint32_t)(t & 0x7fffffffu)) {
+            pend &= ~(1u << i);  // the pool has no free slot for this one
+          }
+        }
+        ++r;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    if (!((fm >> i) & 1u)) continue;
+    const int64_t k = k0 + i;
+    const int32_t s = sidx[i];
+    a.missing[rm] = id[i];
+    a.mslot[rm] = s;
+    a.uslot[k] = s;
+    if (s >= 0) {
+      a.pool[s] = make_float4(rx[i], ry[i], rz[i], rw[i]);
+      a.slot_of[id[i]] = s;
+      a.occ[s] = 1u;
+    }
+    ++rm;
+  }
+  if (a.evict_after) {
+    // the staged records leave the table again (the pool keeps its base residency between rounds)
+#pragma unroll
+    for (int i = 0; i < kUItems; ++i)
+      if (((fm >> i) & 1u) && sidx[i] >= 0) {
+        a.slot_of[id[i]] = -1;
+        a.occ[sidx[i]] = 0u;
+      }
+  }
+}
+
+// Eviction of ids[first, last) by the calling block: each resident id leaves the table and its slot
+// is freed.  Ids outside [0, n_ids) and ids not resident are skipped.
+template <bool COH>
+__device__ __forceinline__ void evict_range(const int32_t* __restrict__ ids, int64_t first, int64_t last,
+                                            int32_t* __restrict__ slot_of, int32_t n_ids, uint32_t* __restrict__ occ) {
+  for (int64_t k = first + threadIdx.x; k < last; k += blockDim.x) {
+    const int32_t id = ld_i32<COH>(ids + k);
+    if (id < 0 || id >= n_ids) continue;
+    const int32_t s = ld_i32<COH>(slot_of + id);
+    if (s < 0) continue;
+    slot_of[id] = -1;
+    occ[s] = 0u;
+  }
+}
+
+}  // namespace dev
+}  // namespace gc

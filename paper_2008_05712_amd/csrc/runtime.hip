@@ -119,6 +119,7 @@ struct gc_graph_ {
   gc_ctx ctx = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  DevBuf step_segs, step_rounds, step_ctr;  // whole-step persistent schedule
   std::vector<hipStream_t> side;   // capture-time side streams (combined passes of successive steps overlap)
   std::vector<hipEvent_t> events;
 };
@@ -700,7 +701,8 @@ static gc_status check_prm(gc_batch b, const gc_force_params* prm, int* tile, in
     if (!(prm->r_cut > 0.f)) return set_err(c, GC_E_INVAL, "r_cut must be > 0");
     *wpb = 4;
   }
-  if (prm->schedule != 0 && prm->schedule != 1) return set_err(c, GC_E_INVAL, "schedule must be 0 or 1");
+  if (prm->schedule < GC_SCHED_TASKS || prm->schedule > GC_SCHED_STEP)
+    return set_err(c, GC_E_INVAL, "schedule must be GC_SCHED_TASKS, GC_SCHED_QUEUE or GC_SCHED_STEP");
   return GC_OK;
 }
 
@@ -710,6 +712,8 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
   int tile, wpb;
   gc_status st = check_prm(b, prm, &tile, &wpb);
   if (st != GC_OK) return st;
+  if (prm->schedule == GC_SCHED_STEP)
+    return set_err(c, GC_E_UNSUPPORTED, "the whole-step schedule runs through gc_graph_capture only");
   if (b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_launch_combined: batch not reorganised");
   if (!acc_dev) return set_err(c, GC_E_INVAL, "gc_launch_combined: NULL acc");
   const int32_t T = (int32_t)b->tasks.size();
@@ -784,7 +788,11 @@ extern "C" gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_
   GC_ENTER(ctx);
   if (!prm || !blocks_per_cu) return set_err(ctx, GC_E_INVAL, "gc_occupancy: NULL argument");
   int tile = prm->tile ? prm->tile : 256, wpb = prm->waves_per_block ? prm->waves_per_block : 4, per = 0;
-  GC_HIP(ctx, grav_occupancy(prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1, false, prm->schedule == 1, tile, wpb, &per));
+  const int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
+  if (prm->schedule == GC_SCHED_STEP)
+    GC_HIP(ctx, step_occupancy(order, tile, &per));
+  else
+    GC_HIP(ctx, grav_occupancy(order, false, prm->schedule == GC_SCHED_QUEUE, tile, wpb, &per));
   *blocks_per_cu = per;
   if (n_cu) *n_cu = ctx->n_cu;
   return GC_OK;
@@ -867,6 +875,136 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
 
 // ===================================================================== graphs
 
+// The whole-step schedule: every step's reorganisation and combined pass in one persistent launch
+// (k_step).  Gravity, PACK, one pool, fixture NONE or EVICT_STAGED, distinct batches.
+static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool* pools, const int32_t* modes,
+                              const gc_force_params* prm, const float* nodes_dev, float* acc_dev, int32_t fixture,
+                              hipStream_t s, gc_graph gr) {
+  gc_pool p = pools[0];
+  if (fixture != GC_FIXTURE_NONE && fixture != GC_FIXTURE_EVICT_STAGED)
+    return set_err(ctx, GC_E_UNSUPPORTED, "whole-step schedule: fixture must be NONE or EVICT_STAGED");
+  int tile = 256, wpb = 4;
+  for (int32_t k = 0; k < R; ++k) {
+    gc_batch b = batches[k];
+    if (pools[k] != p) return set_err(ctx, GC_E_UNSUPPORTED, "whole-step schedule: one pool for all steps");
+    if (modes[k] != GC_REORG_PACK) return set_err(ctx, GC_E_UNSUPPORTED, "whole-step schedule: PACK steps only");
+    if (b->kind != GC_KIND_GRAV) return set_err(ctx, GC_E_UNSUPPORTED, "whole-step schedule: gravity batches only");
+    for (int32_t q = 0; q < k; ++q)
+      if (batches[q] == b) return set_err(ctx, GC_E_UNSUPPORTED, "whole-step schedule: distinct batches only");
+    gc_status st = check_prm(b, prm, &tile, &wpb);
+    if (st != GC_OK) return st;
+    if (!b->nodes.empty() && !nodes_dev) return set_err(ctx, GC_E_INVAL, "whole-step schedule: NULL nodes");
+  }
+  if (!acc_dev) return set_err(ctx, GC_E_INVAL, "whole-step schedule: NULL acc");
+  const int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
+  std::vector<StepRound> rounds((size_t)R);
+  std::vector<StepSeg> segs;
+  int32_t nt = 0;
+  auto seg = [&](int32_t type, int32_t round, int32_t count) {
+    if (count <= 0) return;
+    segs.push_back(StepSeg{type, round, nt, count});
+    nt += count;
+  };
+  for (int32_t k = 0; k < R; ++k) {
+    gc_batch b = batches[k];
+    StepRound& sr = rounds[k];
+    GravArgs& g = sr.grav;
+    g = GravArgs{};
+    g.tasks = b->d_tasks.as<gc_task>();
+    g.n_tasks = (int32_t)b->tasks.size();
+    g.ranges = b->pranges.as<int2>();
+    g.ibeg = b->pibeg.as<int32_t>();
+    g.ioff = b->d_ioff.as<int32_t>();
+    g.joff = b->d_joff.as<int32_t>();
+    g.node_idx = b->d_nodes.as<int32_t>();
+    g.nodes = reinterpret_cast<const float4*>(nodes_dev);
+    g.rec = b->packed.as<float4>();
+    g.acc = reinterpret_cast<float4*>(acc_dev);
+    g.G = prm->G;
+    g.eps2 = prm->soft_eps * prm->soft_eps;
+    g.tile = tile;
+    g.order = b->d_order.as<int32_t>();
+    ReorgArgs& r = sr.reorg;
+    r = ReorgArgs{};
+    r.U = b->d_U.as<int32_t>();
+    r.u = b->u;
+    r.src = p->src;
+    r.pool = p->rec.as<float4>();
+    r.slot_of = p->slot_of.as<int32_t>();
+    r.occ = p->occ.as<uint32_t>();
+    r.cap = p->cap;
+    r.pack = 1;
+    r.packed = b->packed.as<float4>();
+    r.uslot = b->uslot.as<int32_t>();
+    r.missing = b->missing.as<int32_t>();
+    r.mslot = b->mslot.as<int32_t>();
+    r.free_list = b->free_list.as<uint64_t>();
+    r.state = b->state.as<int32_t>();
+    r.nbu = union_blocks(b->u);
+    r.nbf = free_blocks(p->cap);
+    sr.n_ids = p->n_ids;
+    sr.n_chain = r.nbu + r.nbf;
+    sr.n_evict = 0;
+    sr.ev_ids = nullptr;
+    sr.ev_n = nullptr;
+    sr.ev_bound = 0;
+    // the evicting fixture: each round's union blocks evict what they staged as soon as they have
+    // packed it (the same table updates as an eviction before the next round, off its critical path);
+    // round 0 first evicts what the previous launch's last round left (nothing, with this fixture)
+    r.evict_after = fixture == GC_FIXTURE_EVICT_STAGED ? 1 : 0;
+    if (fixture == GC_FIXTURE_EVICT_STAGED && k == 0) {
+      gc_batch pb = batches[R - 1];
+      sr.ev_ids = pb->missing.as<int32_t>();
+      sr.ev_n = pb->state.as<int32_t>() + GC_STATE_MISSING;
+      sr.ev_bound = std::max<int32_t>(pb->u, 1);
+      sr.n_evict = (sr.ev_bound + kEvictBlock - 1) / kEvictBlock;
+    }
+    seg(kItemEvict, k, sr.n_evict);
+    seg(kItemFree, k, r.nbf);
+    seg(kItemUnion, k, r.nbu);
+    if (k >= kStepLead) seg(kItemForce, k - kStepLead, (int32_t)batches[k - kStepLead]->tasks.size());
+  }
+  for (int32_t k = std::max<int32_t>(R - kStepLead, 0); k < R; ++k)
+    seg(kItemForce, k, (int32_t)batches[k]->tasks.size());
+  const int32_t n_ctr = kCtrStride * (kCtrRounds + 2 * R);
+  hipError_t e = gr->step_segs.ensure(sizeof(StepSeg) * std::max<size_t>(segs.size(), 1));
+  if (e == hipSuccess) e = gr->step_rounds.ensure(sizeof(StepRound) * (size_t)R);
+  if (e == hipSuccess) e = gr->step_ctr.ensure(sizeof(uint64_t) * (size_t)n_ctr);
+  if (e != hipSuccess) return set_err(ctx, GC_E_NOMEM, "whole-step schedule: %s", hipGetErrorString(e));
+  GC_HIP(ctx, hipMemcpyAsync(gr->step_segs.p, segs.data(), sizeof(StepSeg) * segs.size(), hipMemcpyHostToDevice, s));
+  GC_HIP(ctx, hipMemcpyAsync(gr->step_rounds.p, rounds.data(), sizeof(StepRound) * (size_t)R, hipMemcpyHostToDevice, s));
+  GC_HIP(ctx, launch_fill_i32(gr->step_ctr.as<int32_t>(), 0, 2 * (int64_t)n_ctr, s));
+  GC_HIP(ctx, hipStreamSynchronize(s));  // the host vectors go out of scope
+  int per = 0;
+  GC_HIP(ctx, step_occupancy(order, tile, &per));
+  const int grid = std::max(1, per) * ctx->n_cu;
+  StepArgs a{};
+  a.segs = gr->step_segs.as<StepSeg>();
+  a.n_segs = (int32_t)segs.size();
+  a.n_items = nt;
+  a.rounds = gr->step_rounds.as<StepRound>();
+  a.n_rounds = R;
+  a.ctr = gr->step_ctr.as<uint64_t>();
+  hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamBeginCapture");
+  hipError_t le = launch_step(order, a, grid, tile, s);
+  hipGraph_t g = nullptr;
+  ce = hipStreamEndCapture(s, &g);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(ctx, le != hipSuccess ? le : ce, "whole-step capture");
+  }
+  gr->graph = g;
+  ce = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+  if (ce != hipSuccess) return hip_fail(ctx, ce, "hipGraphInstantiate");
+  for (int32_t k = 0; k < R; ++k) {
+    batches[k]->mode = GC_REORG_PACK;
+    batches[k]->pool = p;
+    batches[k]->rec = batches[k]->packed.as<float4>();
+  }
+  return GC_OK;
+}
+
 extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* batches, gc_pool* pools,
                                       const int32_t* modes, const gc_force_params* prm, const float* nodes_dev,
                                       float* acc_dev, int32_t fixture, const int32_t* const* place_ids,
@@ -899,6 +1037,22 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
     if (modes[k] != GC_REORG_NONE) GC_HIP(ctx, clear_reorg_state(batches[k], S(stream)));
   GC_HIP(ctx, hipStreamSynchronize(S(stream)));
   hipStream_t s = S(stream);
+  if (prm->schedule == GC_SCHED_STEP) {
+    gc_graph gs = new gc_graph_();
+    gs->ctx = ctx;
+    gc_status st = capture_step(ctx, n_steps, batches, pools, modes, prm, nodes_dev, acc_dev, fixture, s, gs);
+    if (st != GC_OK) {
+      if (gs->exec) (void)hipGraphExecDestroy(gs->exec);
+      if (gs->graph) (void)hipGraphDestroy(gs->graph);
+      gs->step_segs.release();
+      gs->step_rounds.release();
+      gs->step_ctr.release();
+      delete gs;
+      return st;
+    }
+    *out = gs;
+    return GC_OK;
+  }
   // The combined pass of a step reads only its batch's own buffers unless its records come from
   // the pool (address-list modes), so those passes can run on side streams and overlap the next
   // steps' reorganisations and passes; the pool-touching chain stays on the capture stream.
@@ -1032,6 +1186,9 @@ extern "C" gc_status gc_graph_destroy(gc_graph g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
   for (hipStream_t q : g->side) (void)hipStreamDestroy(q);
+  g->step_segs.release();
+  g->step_rounds.release();
+  g->step_ctr.release();
   delete g;
   return GC_OK;
 }

@@ -1,0 +1,256 @@
+// Whole-step persistent kernel (the batched form): one launch runs every round
+// of a step -- the eviction of the previous round's staging, the round's
+// reorganisation (free-slot scan, chare-table lookup, slot assignment, staging,
+// packing; Sec. 3.2) and its combined force pass (Sec. 3.1) -- so the rounds
+// need no kernel boundaries and the passes of consecutive rounds overlap.
+//
+// Work items are numbered in ticket order:
+//   evict(0) free(0) union(0) free(1) union(1) free(2) union(2) force(0)
+//   free(3) union(3) force(1) ... union(R-1) force(R-3) force(R-2) force(R-1)
+// so the reorganisation chain runs two rounds ahead of the force passes (the
+// chain is sequential -- each round's lookup sees the pool as the round before
+// left it -- and latency-bound, the passes are throughput-bound: two rounds of
+// slack keep the passes from waiting on it).  A block takes tickets from a
+// device counter (the next one is requested while the current item runs) and
+// waits only for items with smaller tickets:
+//   evict(r)         waits for free(r-1) + union(r-1);
+//   free(r) union(r) wait for evict(r) and free(r-1) + union(r-1), and inside
+//                    the round on the free-slot list and look-back words as in
+//                    the per-batch kernel;
+//   force(r)         waits for free(r) + union(r).
+// The unfinished item with the smallest ticket therefore always progresses (its
+// dependencies are finished), so the grid never deadlocks whatever the order
+// in which its blocks run; every wait is bounded anyway and raises an error
+// flag.  Counters are monotonic across launches (a launch epoch scales the
+// targets), so nothing is cleared between replays; the last block out
+// advances the epoch.  Reorganisation items raise their waves' issue priority
+// while they run: they are latency-bound and on the step's critical path.
+//
+// Memory: the chare table, occupancy flags, resident pool records and missing
+// lists are read with device-scope coherent (sc1) loads (the L2 of one XCD is
+// not coherent with the others'); every item writes plainly and, before it is
+// counted done, writes its XCD's L2 back (device-scope release).  Items of one
+// round exchange only tagged words, through device-scope atomics.  A force
+// item reads a round's packed records only after that round's items are all
+// done; no earlier access in the launch touches those lines (each union item
+// writes whole lines of its own), so its caches hold no stale copy.
+#include "grav_dev.h"
+#include "reorg_dev.h"
+
+namespace gc {
+namespace {
+
+using dev::grav_lds_per_wave;
+using dev::uniform;
+
+// Dependencies complete within microseconds; the bound (about a second) only keeps a broken state
+// from holding the grid.
+constexpr uint32_t kStepSpinLimit = 1u << 20;
+
+__device__ __forceinline__ void wait_ge(uint64_t* p, uint64_t target, int32_t* err) {
+  uint32_t spins = 0;
+  while (dev::tload(p) < target) {
+    if (++spins > kStepSpinLimit) {
+      dev::istore(err, 1);
+      return;
+    }
+    // back off: many blocks may wait on one counter, and its line is also the one being counted up
+    if (spins < 4)
+      __builtin_amdgcn_s_sleep(2);
+    else
+      __builtin_amdgcn_s_sleep(16);
+  }
+}
+
+// Every wave waits for its own stores to reach the L2, then one thread writes the L2 back
+// (device-scope release) and counts the item done.
+__device__ __forceinline__ uint64_t publish_done(uint64_t* ctr) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  uint64_t old = 0;
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    old = atomicAdd(reinterpret_cast<unsigned long long*>(ctr), 1ull);
+  }
+  return old;
+}
+
+// Per-round arguments live in device memory; loaded through these, every field is marked
+// wavefront-uniform so that it stays in scalar registers.
+template <class T>
+__device__ __forceinline__ T* uni(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+
+__device__ __forceinline__ GravArgs load_grav(const GravArgs* g) {
+  GravArgs a;
+  a.tasks = uni(g->tasks);
+  a.n_tasks = uni(g->n_tasks);
+  a.ranges = uni(g->ranges);
+  a.ibeg = uni(g->ibeg);
+  a.ioff = uni(g->ioff);
+  a.joff = uni(g->joff);
+  a.ilist = uni(g->ilist);
+  a.jlist = uni(g->jlist);
+  a.node_idx = uni(g->node_idx);
+  a.nodes = uni(g->nodes);
+  a.rec = uni(g->rec);
+  a.acc = uni(g->acc);
+  a.G = uni(g->G);
+  a.eps2 = uni(g->eps2);
+  a.tile = uni(g->tile);
+  a.queue = uni(g->queue);
+  a.order = uni(g->order);
+  return a;
+}
+
+__device__ __forceinline__ ReorgArgs load_reorg(const ReorgArgs* r) {
+  ReorgArgs a;
+  a.U = uni(r->U);
+  a.u = uni(r->u);
+  a.src = uni(r->src);
+  a.pool = uni(r->pool);
+  a.slot_of = uni(r->slot_of);
+  a.occ = uni(r->occ);
+  a.cap = uni(r->cap);
+  a.pack = uni(r->pack);
+  a.packed = uni(r->packed);
+  a.uslot = uni(r->uslot);
+  a.missing = uni(r->missing);
+  a.mslot = uni(r->mslot);
+  a.free_list = uni(r->free_list);
+  a.state = uni(r->state);
+  a.nbf = uni(r->nbf);
+  a.nbu = uni(r->nbu);
+  a.evict_after = uni(r->evict_after);
+  return a;
+}
+
+template <int ORDER>
+__global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_per_eu(5))) k_step(StepArgs s) {
+  extern __shared__ float4 smem[];
+  __shared__ int sh[dev::kRThreads / 64];
+  __shared__ uint32_t s_ex, s_tag;
+  __shared__ int64_t s_next;
+  __shared__ uint64_t s_epoch;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_epoch = dev::tload(s.ctr + kCtrStride * kCtrEpoch);
+  __syncthreads();
+  const uint64_t E = s_epoch;
+  const uint64_t base = E * ((uint64_t)s.n_items + gridDim.x);  // tickets taken by earlier launches
+  const uint64_t goal = E + 1;
+  uint64_t* tickets = s.ctr + kCtrStride * kCtrTickets;
+  if (tid == 0) s_next = (int64_t)(atomicAdd(reinterpret_cast<unsigned long long*>(tickets), 1ull) - base);
+  __syncthreads();
+  int ready = -1;  // this block has seen the reorganisation of rounds <= ready complete
+  while (true) {
+    const int64_t t = s_next;
+    __syncthreads();
+    if (t >= s.n_items) break;
+    unsigned long long nxt = 0;
+    if (tid == 0) nxt = atomicAdd(reinterpret_cast<unsigned long long*>(tickets), 1ull);
+    int lo = 0, hi = s.n_segs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s.segs[mid].first <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const int type = uniform(s.segs[lo].type);
+    const int k = uniform(s.segs[lo].round);
+    const int idx = uniform((int)(t - s.segs[lo].first));
+    const StepRound& R = s.rounds[k];
+    uint64_t* ev_done = s.ctr + kCtrStride * (kCtrRounds + 2 * k);
+    uint64_t* ch_done = s.ctr + kCtrStride * (kCtrRounds + 2 * k + 1);
+    if (type == kItemForce) {
+      if (k > ready) {
+        if (tid == 0) wait_ge(ch_done, goal * (uint64_t)R.n_chain, R.reorg.state + GC_STATE_ERR);
+        __syncthreads();
+        ready = k;
+      }
+      const GravArgs ga = load_grav(&R.grav);
+      dev::grav_task<ORDER, false>(ga, uniform(ga.order[idx]), smem);
+    } else if (type == kItemEvict) {
+      __builtin_amdgcn_s_setprio(3);
+      if (tid == 0 && k > 0) wait_ge(ch_done - 2 * kCtrStride, goal * (uint64_t)s.rounds[k - 1].n_chain, R.reorg.state + GC_STATE_ERR);
+      __syncthreads();
+      const int64_t n = min(dev::iload(const_cast<int32_t*>(R.ev_n)), R.ev_bound);
+      const int64_t first = (int64_t)idx * kEvictBlock;
+      const int64_t last = first + kEvictBlock < n ? first + kEvictBlock : n;
+      dev::evict_range<true>(R.ev_ids, first, last, R.reorg.slot_of, R.n_ids, R.reorg.occ);
+      (void)publish_done(ev_done);
+      __builtin_amdgcn_s_setprio(0);
+    } else {
+      // reorganisation items are on the critical path of the step and latency-bound: their waves
+      // issue ahead of the force waves sharing the CU
+      __builtin_amdgcn_s_setprio(3);
+      if (tid == 0) {
+        wait_ge(ev_done, goal * (uint64_t)R.n_evict, R.reorg.state + GC_STATE_ERR);
+        if (k > 0) wait_ge(ch_done - 2 * kCtrStride, goal * (uint64_t)s.rounds[k - 1].n_chain, R.reorg.state + GC_STATE_ERR);
+        s_tag = (uint32_t)dev::iload(R.reorg.state + dev::kTag) + 1u;
+      }
+      __syncthreads();
+      const uint32_t tag = s_tag;
+      const ReorgArgs ra = load_reorg(&R.reorg);
+      if (type == kItemFree)
+        dev::free_role<true>(ra, idx, tag, sh, &s_ex);
+      else
+        dev::union_role<true>(ra, idx, tag, sh, &s_ex);
+      const uint64_t old = publish_done(ch_done);
+      // the last item of the round makes its tag the batch's current one (all of them read it first)
+      if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
+      __builtin_amdgcn_s_setprio(0);
+    }
+    if (tid == 0) s_next = (int64_t)(nxt - base);
+    __syncthreads();
+  }
+  if (tid == 0 && atomicAdd(reinterpret_cast<unsigned long long*>(s.ctr + kCtrStride * kCtrExits), 1ull) + 1 ==
+                      goal * gridDim.x)
+    dev::tstore(s.ctr + kCtrStride * kCtrEpoch, goal);
+}
+
+template <int ORDER>
+size_t step_lds(int tile) {
+  return (size_t)(dev::kRThreads / 64) * grav_lds_per_wave(tile) * sizeof(float4);
+}
+
+template <int ORDER>
+hipError_t step_attr(int tile) {
+  const size_t lds = step_lds<ORDER>(tile);
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_step<ORDER>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
+}  // namespace
+
+hipError_t launch_step(int order, const StepArgs& a, int grid, int tile, hipStream_t s) {
+  if (grid < 1 || a.n_items <= 0) return hipSuccess;
+  if (order == 1) {
+    hipError_t e = step_attr<1>(tile);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_step<1>, dim3(grid), dim3(dev::kRThreads), step_lds<1>(tile), s, a);
+  } else {
+    hipError_t e = step_attr<2>(tile);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_step<2>, dim3(grid), dim3(dev::kRThreads), step_lds<2>(tile), s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t step_occupancy(int order, int tile, int* blocks) {
+  if (order == 1) {
+    hipError_t e = step_attr<1>(tile);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<1>, dev::kRThreads, step_lds<1>(tile));
+  }
+  hipError_t e = step_attr<2>(tile);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<2>, dev::kRThreads, step_lds<2>(tile));
+}
+
+}  // namespace gc

@@ -414,3 +414,159 @@ def test_graph_with_evicting_fixture_matches_eager_and_oracle(ctx, plum):
     for b in bs:
         b.destroy()
     rig.close()
+
+
+def _rounds_rig(ctx, w, n_rounds, mean, seed, base_frac, base_seed):
+    rig = GravRig(ctx, w)
+    rounds = W.poisson_rounds(w.n_tasks, mean, seed=seed)[:n_rounds]
+    bts = [W.task_subset(w, r) for r in rounds]
+    bs = [rig.batch(bt) for bt in bts]
+    ids, slots = W.residency(np.arange(w.n), w.n, base_frac, seed=base_seed)
+    return rig, bts, bs, (ids, slots)
+
+
+def _set_base(rig, base):
+    rig.pool.reset()
+    rig.place(*base)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_step_schedule_matches_per_round_launches(ctx, plum, order):
+    # one persistent launch per step (every round's reorganisation, eviction of its staging, and pass)
+    # gives bitwise the per-round launches' accelerations and the oracle's maps on the base state, and
+    # leaves the base residency in the pool; replays repeat it exactly
+    import torch
+    print(f"[gpu] whole-step schedule order={order}", flush=True)
+    rig, bts, bs, base = _rounds_rig(ctx, plum, 4, 500, 38, 0.4, 39)
+    _set_base(rig, base)
+    base_so = rig.pool.query()
+    prm = gc.grav_params(order=order)
+    rig.acc.fill_(np.nan)
+    for k, b in enumerate(bs):
+        if k:
+            rig.pool.evict_staged(bs[k - 1])
+        b.reorganize(rig.pool, gc.REORG_PACK, check_capacity=False)
+        b.launch(prm, rig.nodes, rig.acc)
+    torch.cuda.synchronize()
+    eager = rig.acc.cpu().numpy()
+    ref = O.grav_workload(plum, order=order)
+    for bt in bts:
+        assert rel_l2_per_task(eager, ref, bt).max() <= TOL
+    rig.pool.evict_staged(bs[-1])
+    assert np.array_equal(rig.pool.query(), base_so)
+    s = torch.cuda.Stream()
+    sprm = gc.grav_params(order=order, schedule=gc.SCHED_STEP)
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), sprm, rig.nodes, rig.acc, stream=s,
+                 fixture=gc.FIXTURE_EVICT_STAGED)
+    for rep in range(4):
+        rig.acc.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        got = rig.acc.cpu().numpy()
+        assert np.array_equal(np.isnan(got), np.isnan(eager)), rep
+        assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)]), rep
+        for k in range(len(bs)):
+            _check_maps(bs[k].maps(), O.maps(bts[k], plum.n, plum.n, base_so, gc.REORG_PACK), gc.REORG_PACK)
+        # with the evicting fixture each round's staging leaves the table once packed: the base remains
+        assert np.array_equal(rig.pool.query(), base_so), rep
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()
+
+
+def test_step_schedule_without_fixture_accumulates_residency(ctx, plum):
+    # fixture NONE: each round reuses what earlier rounds staged (records staged by one round are read as
+    # resident by later ones inside the same launch); maps, pool and accelerations equal the eager sequence
+    import torch
+    rig, bts, bs, base = _rounds_rig(ctx, plum, 5, 400, 48, 0.3, 49)
+    _set_base(rig, base)
+    prm = gc.grav_params(order=2)
+    rig.acc.fill_(np.nan)
+    maps_eager, so = [], rig.pool.query()
+    for k, b in enumerate(bs):
+        b.reorganize(rig.pool, gc.REORG_PACK, check_capacity=False)
+        b.launch(prm, rig.nodes, rig.acc)
+        want = O.maps(bts[k], plum.n, plum.n, so, gc.REORG_PACK)
+        _check_maps(b.maps(), want, gc.REORG_PACK)
+        so = want["slot_of"]
+        maps_eager.append(want)
+    torch.cuda.synchronize()
+    eager = rig.acc.cpu().numpy()
+    assert np.array_equal(rig.pool.query(), so)
+    _set_base(rig, base)
+    s = torch.cuda.Stream()
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), gc.grav_params(order=2, schedule=gc.SCHED_STEP),
+                 rig.nodes, rig.acc, stream=s, fixture=gc.FIXTURE_NONE)
+    rig.acc.fill_(np.nan)
+    torch.cuda.synchronize()
+    g.launch(stream=s)
+    s.synchronize()
+    got = rig.acc.cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(eager))
+    assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)])
+    assert np.array_equal(rig.pool.query(), so)
+    for k in range(len(bs)):
+        _check_maps(bs[k].maps(), maps_eager[k], gc.REORG_PACK)
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()
+
+
+def test_step_schedule_full_size_rounds(ctx):
+    # 262,144-particle Plummer sphere, 6 Poisson(2048) rounds over half of all particles resident:
+    # the whole-step launch equals the per-round launches bitwise; sampled tasks match the oracle
+    import torch
+    w = W.nbody_plummer()
+    print(f"[gpu] whole-step full size N={w.n}", flush=True)
+    rig, bts, bs, base = _rounds_rig(ctx, w, 6, 2048, 1002, 0.5, 5000)
+    _set_base(rig, base)
+    prm = gc.grav_params(order=2)
+    rig.acc.fill_(np.nan)
+    for k, b in enumerate(bs):
+        if k:
+            rig.pool.evict_staged(bs[k - 1])
+        b.reorganize(rig.pool, gc.REORG_PACK, check_capacity=False)
+        b.launch(prm, rig.nodes, rig.acc)
+    rig.pool.evict_staged(bs[-1])
+    torch.cuda.synchronize()
+    eager = rig.acc.cpu().numpy()
+    s = torch.cuda.Stream()
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), gc.grav_params(order=2, schedule=gc.SCHED_STEP),
+                 rig.nodes, rig.acc, stream=s, fixture=gc.FIXTURE_EVICT_STAGED)
+    for rep in range(3):
+        rig.acc.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        got = rig.acc.cpu().numpy()
+        assert np.array_equal(np.isnan(got), np.isnan(eager)), rep
+        assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)]), rep
+    sel = np.random.default_rng(3).choice(np.concatenate([np.asarray(r) for r in W.poisson_rounds(w.n_tasks, 2048, seed=1002)[:6]]),
+                                          size=48, replace=False)
+    sub = W.task_subset(w, np.sort(sel))
+    err = rel_l2_per_task(got, O.grav_workload(w, order=2, tasks=sub), sub)
+    assert err.max() <= TOL, err.max()
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()
+
+
+def test_step_schedule_is_rejected_where_unsupported(ctx, plum):
+    import torch
+    rig = GravRig(ctx, plum)
+    b = rig.batch(W.task_subset(plum, np.arange(0, 50)))
+    s = torch.cuda.Stream()
+    sprm = gc.grav_params(order=2, schedule=gc.SCHED_STEP)
+    with pytest.raises(gc.GcError) as e:
+        gc.Graph(ctx, [b], [rig.pool], [gc.REORG_INDIRECT], sprm, rig.nodes, rig.acc, stream=s)
+    assert e.value.status == gc.GC_E_UNSUPPORTED
+    b.reorganize(rig.pool, gc.REORG_PACK)
+    with pytest.raises(gc.GcError) as e:
+        b.launch(sprm, rig.nodes, rig.acc)
+    assert e.value.status == gc.GC_E_UNSUPPORTED
+    b.destroy()
+    rig.close()

@@ -377,7 +377,7 @@ def main():
     forms["round_graph_ms"] = round(time_kernel(lambda: round_graph.launch(stream=stream), stream, reps=10), 4)
     sprm, step_graph, step_tiles = None, None, {}
     if mode == gc.REORG_PACK:
-        for tl in ((args.step_tile,) if args.step_tile else (128, 256, 512)):
+        for tl in ((args.step_tile,) if args.step_tile else (256, 384, 512)):
             p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=gc.SCHED_STEP, tile=tl)
             g = capture("step", p)
             step_tiles[tl] = round(time_kernel(lambda: g.launch(stream=stream), stream, reps=10), 4)
@@ -417,6 +417,17 @@ def main():
     torch.cuda.synchronize()
     forms["eager_ms"] = round((time.perf_counter() - te) * 1e3 / 3, 4)
     pool.evict_staged(batches[-1])
+    # the plain per-batch form with indirect access: per-round launches from the host, address lists
+    one_pass(gc.REORG_INDIRECT)  # sizes the list buffers (not timed)
+    pool.evict_staged(batches[-1])
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    for _ in range(3):
+        one_pass(gc.REORG_INDIRECT)
+    torch.cuda.synchronize()
+    forms["eager_indirect_ms"] = round((time.perf_counter() - te) * 1e3 / 3, 4)
+    pool.evict_staged(batches[-1])
+    forms["timed_vs_eager_indirect"] = round(forms["eager_indirect_ms"] / ms_step, 3)
     if graph is not None and form == "step":
         step_kernel_ms = time_kernel(lambda: graph.launch(stream=stream), stream, reps=10)
 

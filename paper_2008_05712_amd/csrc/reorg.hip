@@ -71,7 +71,11 @@ __global__ void __launch_bounds__(kRThreads) k_reorg(ReorgArgs a) {
   if (t < a.nbf)
     dev::free_role<false>(a, t, tag, sh, &s_ex);
   else
-    dev::union_role<false>(a, t - a.nbf, tag, sh, &s_ex);
+  {
+    int32_t id[dev::kUItems];
+    dev::union_ids(a, t - a.nbf, id);
+    dev::union_role<false>(a, t - a.nbf, tag, sh, &s_ex, id);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     // the last block out rewinds the counters and makes this call's tag the current one

@@ -181,18 +181,23 @@ __device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t ta
 
 // Union side: residency of this block's chunk of U, the missing ranks, then slot assignment,
 // staging and the packed copies.
+// This thread's union ids of union block b (U is fixed at commit, so they may be loaded before the
+// block's dependencies are complete).
+__device__ __forceinline__ void union_ids(const ReorgArgs& a, int b, int32_t (&id)[kUItems]) {
+  const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
+  const int4* u4 = reinterpret_cast<const int4*>(a.U + k0);  // U is padded to whole blocks
+  const int4 x = u4[0], y = u4[1];
+  id[0] = x.x; id[1] = x.y; id[2] = x.z; id[3] = x.w;
+  id[4] = y.x; id[5] = y.y; id[6] = y.z; id[7] = y.w;
+}
+
 template <bool COH>
-__device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex) {
+__device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex,
+                                           const int32_t (&id)[kUItems]) {
   uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbf;
   const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
-  int32_t id[kUItems], sl[kUItems];
+  int32_t sl[kUItems];
   uint32_t fm = 0;
-  {
-    const int4* u4 = reinterpret_cast<const int4*>(a.U + k0);  // U is padded to whole blocks
-    const int4 x = u4[0], y = u4[1];
-    id[0] = x.x; id[1] = x.y; id[2] = x.z; id[3] = x.w;
-    id[4] = y.x; id[5] = y.y; id[6] = y.z; id[7] = y.w;
-  }
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
     sl[i] = 0;

@@ -188,6 +188,9 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
       // reorganisation items are on the critical path of the step and latency-bound: their waves
       // issue ahead of the force waves sharing the CU
       __builtin_amdgcn_s_setprio(3);
+      const ReorgArgs ra = load_reorg(&R.reorg);
+      int32_t ids[dev::kUItems];
+      if (type == kItemUnion) dev::union_ids(ra, idx, ids);  // static: loaded while the dependencies finish
       if (tid == 0) {
         wait_ge(ev_done, goal * (uint64_t)R.n_evict, R.reorg.state + GC_STATE_ERR);
         if (k > 0) wait_ge(ch_done - 2 * kCtrStride, goal * (uint64_t)s.rounds[k - 1].n_chain, R.reorg.state + GC_STATE_ERR);
@@ -195,11 +198,10 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
       }
       __syncthreads();
       const uint32_t tag = s_tag;
-      const ReorgArgs ra = load_reorg(&R.reorg);
       if (type == kItemFree)
         dev::free_role<true>(ra, idx, tag, sh, &s_ex);
       else
-        dev::union_role<true>(ra, idx, tag, sh, &s_ex);
+        dev::union_role<true>(ra, idx, tag, sh, &s_ex, ids);
       const uint64_t old = publish_done(ch_done);
       // the last item of the round makes its tag the batch's current one (all of them read it first)
       if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);

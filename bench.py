@@ -48,8 +48,8 @@ def log(*a):
 
 def profiled_traffic(profile: str, shape: dict):
     """HBM bytes per launch of the profiled kernel from a committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (profiles/<profile>.json), or None when any of its source files or the launch shape
-    differs from the profiled one."""
+    summary (profiles/<profile>.json: one entry per profiled launch shape), or None when any of its
+    source files differs from the profiled one or no entry has this launch shape."""
     import hashlib
     side = os.path.join(ROOT, "profiles", profile + ".json")
     try:
@@ -57,11 +57,12 @@ def profiled_traffic(profile: str, shape: dict):
         for rel, digest in meta["sources"].items():
             if hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest() != digest:
                 return None
-    except (OSError, ValueError, KeyError, AttributeError):
+        for ent in meta["entries"]:
+            if ent["shape"] == shape:
+                return int(ent["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError, AttributeError, TypeError):
         return None
-    if meta.get("shape") != shape:
-        return None
-    return int(meta["traffic_bytes_per_launch"])
+    return None
 
 
 def time_kernel(fn, stream, reps: int = 10) -> float:

@@ -15,6 +15,7 @@ constexpr int kWave = 64;
 constexpr int kNodeTile = 64;                           // node records per wavefront tile
 constexpr int kMaxTile = 1024;                          // direct records per wavefront tile (upper bound)
 constexpr int kSortMax = 8192;                          // longest per-task list sorted in LDS
+constexpr int kLptChunk = 8192;                         // tasks per longest-first ordering run
 
 // Algorithmic work per interaction, counting add/sub/mul = 1, fma = 2, rsqrt = 1, from the
 // implemented formulas: pair or monopole 3 sub + 3 fma + rsqrt + 3 mul + 3 fma = 19;

@@ -437,10 +437,15 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   for (int32_t t = 0; t < T; ++t) pib[t] = b->tasks[t].i_count > 0 ? upos(b->tasks[t].i_begin) : 0;
   std::vector<int32_t> upad((size_t)union_padded(b->u), 0);
   std::copy(b->hU.begin(), b->hU.end(), upad.begin());
-  // longest-processing-time-first order for the persistent schedule
+  // task order: longest first within each run of kLptChunk consecutive tasks.  Within a run the
+  // long tasks start first (the launch ends with short ones); runs stay in submission order, so
+  // the tasks in flight at one time come from neighbouring buckets (or from one instance of a
+  // batch of instances) and share node and particle data in the caches
   std::vector<int32_t> order(T > 0 ? T : 1);
   std::iota(order.begin(), order.begin() + T, 0);
-  std::stable_sort(order.begin(), order.begin() + T, [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+  for (int32_t c0 = 0; c0 < T; c0 += kLptChunk)
+    std::stable_sort(order.begin() + c0, order.begin() + std::min<int32_t>(T, c0 + kLptChunk),
+                     [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
 
   // runs of consecutive tasks sharing one target range (processed by one wavefront for LJ)
   std::vector<int32_t> runs;

@@ -273,7 +273,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="fixed force-kernel shape instead of the autotuner's")
     ap.add_argument("--waves", type=int, default=4)
     ap.add_argument("--schedule", type=int, default=0)
-    ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 128/256/512")
+    ap.add_argument("--targets-per-lane", type=int, default=0, help="with --tile: 1 or 2 targets per lane")
+    ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 256/384/512")
+    ap.add_argument("--step-tpl", type=int, default=0, help="fixed targets per lane of the whole-step launch instead of timing 1 and 2")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): there is no multi-GPU path", file=sys.stderr)
@@ -330,20 +332,23 @@ def main():
     stream = torch.cuda.current_stream()
     R = len(batches)
 
-    # ---- force-kernel shape: the autotuner's choice on the largest round (tile x waves x schedule)
+    # ---- force-kernel shape: the autotuner's choice on the largest round (tile x waves x schedule x
+    # targets per lane)
     tuned = None
     if args.tile:
         prm = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=args.schedule, tile=args.tile,
-                             waves_per_block=args.waves)
+                             waves_per_block=args.waves, targets_per_lane=args.targets_per_lane)
     else:
         big = int(np.argmax([len(r) for r in rounds]))
         base_state()
         batches[big].reorganize(pool, mode, check_capacity=False)
         best, times = batches[big].autotune(gc.grav_params(order=2, G=1.0, eps=0.01), nodes, acc, reps=3)
         prm = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=best.schedule, tile=best.tile,
-                             waves_per_block=best.waves_per_block)
+                             waves_per_block=best.waves_per_block, targets_per_lane=best.targets_per_lane)
+        # candidate 16 is the default shape: tile 256, 4 waves, one block per task, one target per lane
         tuned = dict(tile=best.tile, waves_per_block=best.waves_per_block, schedule=best.schedule,
-                     ms=round(float(times.min()), 5), default_shape_ms=round(float(times[8]), 5))
+                     targets_per_lane=best.targets_per_lane, ms=round(float(times.min()), 5),
+                     default_shape_ms=round(float(times[16]), 5))
         log(f"[bench] autotuned: {tuned}")
 
     def one_pass(m, timed=None):
@@ -384,23 +389,25 @@ def main():
         return g
 
     # ---- the batched forms: a graph of per-round launches, and one whole-step persistent launch whose
-    # tile the autotuner picks by timing the captured step (4 waves per task)
+    # tile and targets per lane are picked by timing the captured step (4 waves per task)
     forms = {}
     round_graph = capture("rounds", prm)
     forms["round_graph_ms"] = round(time_kernel(lambda: round_graph.launch(stream=stream), stream, reps=10), 4)
-    sprm, step_graph, step_tiles = None, None, {}
+    sprm, step_graph, step_shapes, best_ms = None, None, {}, None
     if mode == gc.REORG_PACK:
         for tl in ((args.step_tile,) if args.step_tile else (256, 384, 512)):
-            p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=gc.SCHED_STEP, tile=tl)
-            g = capture("step", p)
-            step_tiles[tl] = round(time_kernel(lambda: g.launch(stream=stream), stream, reps=10), 4)
-            if sprm is None or step_tiles[tl] < step_tiles[sprm.tile]:
-                if step_graph is not None:
-                    step_graph.destroy()
-                sprm, step_graph = p, g
-            else:
-                g.destroy()
-        forms["step_graph_ms_by_tile"] = step_tiles
+            for tp in ((args.step_tpl,) if args.step_tpl else (1, 2)):
+                p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=gc.SCHED_STEP, tile=tl, targets_per_lane=tp)
+                g = capture("step", p)
+                ms = round(time_kernel(lambda: g.launch(stream=stream), stream, reps=10), 4)
+                step_shapes[f"tile{tl}_tpl{tp}"] = ms
+                if best_ms is None or ms < best_ms:
+                    if step_graph is not None:
+                        step_graph.destroy()
+                    sprm, step_graph, best_ms = p, g, ms
+                else:
+                    g.destroy()
+        forms["step_graph_ms_by_shape"] = step_shapes
     log(f"[bench] forms: {forms}")
     form = args.form if (args.form != "step" or step_graph is not None) else "rounds"
     graph = {"step": step_graph, "rounds": round_graph, "eager": None}[form]
@@ -513,21 +520,24 @@ def main():
 
     form_text = {"step": "one whole-step persistent launch (HIP graph) per step",
                  "rounds": "one HIP graph of per-round launches per step", "eager": "per-round launches"}[form]
-    per_round = {"kernel": f"k_grav<2, false, {'true' if prm.schedule else 'false'}> (tile {prm.tile}, "
-                           f"{prm.waves_per_block} waves per task)",
+    tpl = max(1, prm.targets_per_lane)
+    per_round = {"kernel": f"k_grav<2, false, {'true' if prm.schedule else 'false'}, {'true' if tpl == 2 else 'false'}> "
+                           f"(tile {prm.tile}, {prm.waves_per_block} waves per task, {tpl} targets per lane)",
                  "kernel_ms_per_step": round(kern_ms, 4), "avg_launch_ms": round(kern_ms / R, 5),
                  "tflops": round(achieved_tflops, 3), "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
                  "traffic": profiled_traffic("k_grav_quad_plummer262144_traffic",
                                              {"tile": prm.tile, "waves_per_block": prm.waves_per_block,
-                                              "schedule": prm.schedule})}
+                                              "schedule": prm.schedule, "targets_per_lane": tpl})}
     if form == "step":
         # the dominant (and only) kernel of a step: algorithmic flop of the whole step over its duration
         step_tflops = flops_step / (step_kernel_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(step_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(step_tflops / PEAK_FP32_TFLOPS, 4),
-                    "traffic": profiled_traffic("k_step_quad_plummer262144_traffic", {"tile": sprm.tile}),
-                    "kernel": f"k_step<2> (every round's eviction, reorganisation and combined quadrupole pass; "
-                              f"tile {sprm.tile}, 4 waves per task)",
+                    "traffic": profiled_traffic("k_step_quad_plummer262144_traffic",
+                                                {"tile": sprm.tile, "targets_per_lane": sprm.targets_per_lane}),
+                    "kernel": f"k_step<2, {'true' if sprm.targets_per_lane == 2 else 'false'}> (every round's "
+                              f"eviction, reorganisation and combined quadrupole pass; tile {sprm.tile}, 4 waves "
+                              f"per task, {sprm.targets_per_lane} targets per lane)",
                     "flops_per_launch": flops_step, "avg_launch_ms": round(step_kernel_ms, 5),
                     "frac_of_nonpacked_peak": round(step_tflops / PEAK_FP32_NONPACKED_TFLOPS, 4)}
     else:

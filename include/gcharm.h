@@ -278,6 +278,9 @@ typedef struct {
   int32_t tile;             /* direct-record tile per wavefront: 0 = default (256); 64..1024, multiple of 64 */
   int32_t waves_per_block;  /* 0 = default (4); 1..8 */
   int32_t grid_blocks;      /* persistent schedule: 0 = CUs x occupancy */
+  int32_t targets_per_lane; /* gravity: 0 or 1 = one target per lane; 2 = each lane
+                               holds two targets of its task, so every record read
+                               from LDS serves two interactions (same results) */
 } gc_force_params;
 
 /*
@@ -352,11 +355,12 @@ gc_status gc_graph_destroy(gc_graph graph);
 
 /*
  * Time the combined pass of a reorganised batch for each candidate (tile,
- * waves_per_block, schedule) and return the fastest in *best (prm fields
- * other than those three are copied from `base`).  Synchronises `stream`.
- * times_ms (optional, n_cand floats) receives the measured average per
- * candidate; candidates are tiles {128, 256, 512} x waves {2, 4, 8} x
- * schedules {0, 1} in that nesting order (n_cand = 18).
+ * waves_per_block, schedule, targets_per_lane) and return the fastest in
+ * *best (prm fields other than those four are copied from `base`).
+ * Synchronises `stream`.  times_ms (optional, n_cand floats) receives the
+ * measured average per candidate; candidates are tiles {128, 256, 512} x
+ * waves {2, 4, 8} x schedules {0, 1} x targets_per_lane {1, 2} in that
+ * nesting order (n_cand = 36).
  */
 gc_status gc_autotune(gc_batch batch, const gc_force_params* base, const float* nodes_dev, float* acc_dev,
                       int32_t reps, float* times_ms, gc_force_params* best, void* stream);

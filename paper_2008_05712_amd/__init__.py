@@ -52,7 +52,8 @@ class ForceParams(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("G", ctypes.c_float), ("soft_eps", ctypes.c_float),
                 ("n_types", ctypes.c_int32), ("eps_t", ctypes.c_void_p), ("sig_t", ctypes.c_void_p),
                 ("mass_t", ctypes.c_void_p), ("r_cut", ctypes.c_float), ("schedule", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("grid_blocks", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("targets_per_lane", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -288,7 +289,7 @@ class Batch:
                        "gc_backward")
 
     def autotune(self, base: ForceParams, nodes, acc, reps: int = 3, stream=None):
-        times = np.zeros(18, np.float32)
+        times = np.zeros(36, np.float32)
         best = ForceParams()
         self.ctx.check(lib().gc_autotune(self.h, ctypes.byref(base), _ptr(nodes), _ptr(acc), reps, times.ctypes.data,
                                          ctypes.byref(best), _stream(stream)), "gc_autotune")
@@ -338,11 +339,12 @@ class Graph:
 
 
 def grav_params(order: int = 2, G: float = 1.0, eps: float = 0.01, schedule: int = 0, tile: int = 0,
-                waves_per_block: int = 0, grid_blocks: int = 0) -> ForceParams:
+                waves_per_block: int = 0, grid_blocks: int = 0, targets_per_lane: int = 0) -> ForceParams:
     p = ForceParams()
     p.kind = FORCE_GRAV_QUAD if order == 2 else FORCE_GRAV_MONO
     p.G, p.soft_eps = G, eps
     p.schedule, p.tile, p.waves_per_block, p.grid_blocks = schedule, tile, waves_per_block, grid_blocks
+    p.targets_per_lane = targets_per_lane
     return p
 
 

@@ -112,9 +112,10 @@ hipError_t launch_evict(const int32_t* ids, const int32_t* n_dev, int32_t n_boun
 hipError_t launch_sort_lists(int32_t n_tasks, const int32_t* joff, int32_t* jlist, hipStream_t s);
 hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, float4* pool,
                         int32_t* slot_of, uint32_t* occ, hipStream_t s);
-hipError_t launch_grav(int order, bool lists, bool persistent, const GravArgs& a, int waves_per_block,
+// two: two targets per lane (each record read from LDS serves two interactions)
+hipError_t launch_grav(int order, bool lists, bool persistent, bool two, const GravArgs& a, int waves_per_block,
                        int grid_blocks, hipStream_t s);
-hipError_t grav_occupancy(int order, bool lists, bool persistent, int tile, int waves_per_block, int* blocks);
+hipError_t grav_occupancy(int order, bool lists, bool persistent, bool two, int tile, int waves_per_block, int* blocks);
 hipError_t launch_lj(bool persistent, const LJArgs& a, int waves_per_block, int grid_blocks, hipStream_t s);
 hipError_t launch_lj_finish(float4* acc, const float* mass_t, const float4* rec_by_id, int32_t n,
                             hipStream_t s);
@@ -151,8 +152,8 @@ constexpr int kCtrStride = 32;  // one 256-byte line per step counter
 constexpr int kCtrTickets = 0, kCtrExits = 1, kCtrEpoch = 2, kCtrRounds = 3;  // then per round r:
                                 // kCtrRounds + 2r eviction items done, kCtrRounds + 2r + 1 free + union done
 constexpr int kStepLead = 2;    // rounds by which the reorganisation items precede the passes
-hipError_t launch_step(int order, const StepArgs& a, int grid, int tile, hipStream_t s);
-hipError_t step_occupancy(int order, int tile, int* blocks);
+hipError_t launch_step(int order, bool two, const StepArgs& a, int grid, int tile, hipStream_t s);
+hipError_t step_occupancy(int order, bool two, int tile, int* blocks);
 
 struct GravAdjArgs {
   GravArgs f;              // forward arguments (lists, records, nodes)

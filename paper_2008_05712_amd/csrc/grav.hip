@@ -10,7 +10,7 @@ using dev::grav_lds_per_wave;
 using dev::grav_task;
 using dev::uniform;
 
-template <int ORDER, bool LISTS, bool PERSIST>
+template <int ORDER, bool LISTS, bool PERSIST, bool TWO>
 __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
   extern __shared__ float4 smem[];
   __shared__ int s_task;
@@ -35,55 +35,67 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
       got = blockIdx.x;
     }
     if (got >= a.n_tasks) break;
-    grav_task<ORDER, LISTS>(a, uniform(a.order[got]), smem);
+    grav_task<ORDER, LISTS, TWO>(a, uniform(a.order[got]), smem);
   }
 }
 
-template <int ORDER, bool LISTS, bool PERSIST>
+template <int ORDER, bool LISTS, bool PERSIST, bool TWO>
 hipError_t launch_one(const GravArgs& a, int wpb, int grid, hipStream_t s) {
   size_t lds = (size_t)wpb * grav_lds_per_wave(a.tile) * sizeof(float4);
   if (!PERSIST) grid = a.n_tasks;
   if (grid < 1) return hipSuccess;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST, TWO>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_grav<ORDER, LISTS, PERSIST>), dim3(grid), dim3(64 * wpb), lds, s, a);
+  hipLaunchKernelGGL((k_grav<ORDER, LISTS, PERSIST, TWO>), dim3(grid), dim3(64 * wpb), lds, s, a);
   return hipGetLastError();
 }
 
-template <int ORDER, bool LISTS, bool PERSIST>
+template <int ORDER, bool LISTS, bool PERSIST, bool TWO>
 hipError_t occ_one(int tile, int wpb, int* blocks) {
   size_t lds = (size_t)wpb * grav_lds_per_wave(tile) * sizeof(float4);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST, TWO>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_grav<ORDER, LISTS, PERSIST>, 64 * wpb, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_grav<ORDER, LISTS, PERSIST, TWO>, 64 * wpb, lds);
+}
+
+template <int ORDER, bool LISTS, bool PERSIST>
+hipError_t launch_two(bool two, const GravArgs& a, int wpb, int grid, hipStream_t s) {
+  return two ? launch_one<ORDER, LISTS, PERSIST, true>(a, wpb, grid, s)
+             : launch_one<ORDER, LISTS, PERSIST, false>(a, wpb, grid, s);
+}
+
+template <int ORDER, bool LISTS, bool PERSIST>
+hipError_t occ_two(bool two, int tile, int wpb, int* blocks) {
+  return two ? occ_one<ORDER, LISTS, PERSIST, true>(tile, wpb, blocks)
+             : occ_one<ORDER, LISTS, PERSIST, false>(tile, wpb, blocks);
 }
 
 }  // namespace
 
-hipError_t launch_grav(int order, bool lists, bool persistent, const GravArgs& a, int wpb, int grid,
+hipError_t launch_grav(int order, bool lists, bool persistent, bool two, const GravArgs& a, int wpb, int grid,
                        hipStream_t s) {
   if (a.n_tasks <= 0) return hipSuccess;
   if (order == 1) {
-    if (lists) return persistent ? launch_one<1, true, true>(a, wpb, grid, s) : launch_one<1, true, false>(a, wpb, grid, s);
-    return persistent ? launch_one<1, false, true>(a, wpb, grid, s) : launch_one<1, false, false>(a, wpb, grid, s);
+    if (lists) return persistent ? launch_two<1, true, true>(two, a, wpb, grid, s) : launch_two<1, true, false>(two, a, wpb, grid, s);
+    return persistent ? launch_two<1, false, true>(two, a, wpb, grid, s) : launch_two<1, false, false>(two, a, wpb, grid, s);
   }
-  if (lists) return persistent ? launch_one<2, true, true>(a, wpb, grid, s) : launch_one<2, true, false>(a, wpb, grid, s);
-  return persistent ? launch_one<2, false, true>(a, wpb, grid, s) : launch_one<2, false, false>(a, wpb, grid, s);
+  if (lists) return persistent ? launch_two<2, true, true>(two, a, wpb, grid, s) : launch_two<2, true, false>(two, a, wpb, grid, s);
+  return persistent ? launch_two<2, false, true>(two, a, wpb, grid, s) : launch_two<2, false, false>(two, a, wpb, grid, s);
 }
 
-hipError_t grav_occupancy(int order, bool lists, bool persistent, int tile, int wpb, int* blocks) {
+hipError_t grav_occupancy(int order, bool lists, bool persistent, bool two, int tile, int wpb, int* blocks) {
   if (order == 1) {
-    if (lists) return persistent ? occ_one<1, true, true>(tile, wpb, blocks) : occ_one<1, true, false>(tile, wpb, blocks);
-    return persistent ? occ_one<1, false, true>(tile, wpb, blocks) : occ_one<1, false, false>(tile, wpb, blocks);
+    if (lists) return persistent ? occ_two<1, true, true>(two, tile, wpb, blocks) : occ_two<1, true, false>(two, tile, wpb, blocks);
+    return persistent ? occ_two<1, false, true>(two, tile, wpb, blocks) : occ_two<1, false, false>(two, tile, wpb, blocks);
   }
-  if (lists) return persistent ? occ_one<2, true, true>(tile, wpb, blocks) : occ_one<2, true, false>(tile, wpb, blocks);
-  return persistent ? occ_one<2, false, true>(tile, wpb, blocks) : occ_one<2, false, false>(tile, wpb, blocks);
+  if (lists) return persistent ? occ_two<2, true, true>(two, tile, wpb, blocks) : occ_two<2, true, false>(two, tile, wpb, blocks);
+  return persistent ? occ_two<2, false, true>(two, tile, wpb, blocks) : occ_two<2, false, false>(two, tile, wpb, blocks);
 }
 
 }  // namespace gc

@@ -111,6 +111,73 @@ __device__ __forceinline__ void tile_quads(const float4* __restrict__ p, int C, 
   }
 }
 
+// One pair or monopole term and one quadrupole term for one target (the same arithmetic as the
+// loops above), used by the two-targets-per-lane tiles below.
+__device__ __forceinline__ void pair_term(const float4 j, float xi, float yi, float zi, float eps2, float& ax,
+                                          float& ay, float& az) {
+  float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
+  float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+  float ri = __builtin_amdgcn_rsqf(r2);
+  float mr = j.w * ri;
+  float ri2 = ri * ri;
+  float sc = mr * ri2;
+  ax = __builtin_fmaf(dx, sc, ax);
+  ay = __builtin_fmaf(dy, sc, ay);
+  az = __builtin_fmaf(dz, sc, az);
+}
+
+__device__ __forceinline__ void quad_term(const float4 a, const float4 b, const float4 c, float xi, float yi, float zi,
+                                          float eps2, float& ax, float& ay, float& az) {
+  float dx = xi - a.x, dy = yi - a.y, dz = zi - a.z;
+  float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+  float ri = __builtin_amdgcn_rsqf(r2);
+  float q = ri * ri;
+  float r3 = ri * q;
+  float r5 = r3 * q;
+  float sx = __builtin_fmaf(c.x, dz, __builtin_fmaf(b.w, dy, b.x * dx));
+  float sy = __builtin_fmaf(c.y, dz, __builtin_fmaf(b.y, dy, b.w * dx));
+  float sz = __builtin_fmaf(b.z, dz, __builtin_fmaf(c.y, dy, c.x * dx));
+  float dsd = __builtin_fmaf(dz, sz, __builtin_fmaf(dy, sy, dx * sx));
+  float u = __builtin_fmaf(dsd, q * -2.5f, c.z);
+  float v = __builtin_fmaf(q, u, -a.w);
+  float cf = r3 * v;
+  ax = __builtin_fmaf(r5, sx, __builtin_fmaf(cf, dx, ax));
+  ay = __builtin_fmaf(r5, sy, __builtin_fmaf(cf, dy, ay));
+  az = __builtin_fmaf(r5, sz, __builtin_fmaf(cf, dz, az));
+}
+
+// Two targets per lane: each record read from LDS serves both (half the LDS reads per interaction,
+// two independent dependency chains per lane).
+struct Acc2 {
+  float ax, ay, az, bx, by, bz;
+};
+
+__device__ __forceinline__ void tile_pairs2(const float4* __restrict__ p, int C, const float3 A, const float3 B,
+                                            float eps2, Acc2& r) {
+  int k = 0;
+  for (; k + 2 <= C; k += 2) {
+    const float4 j0 = p[k], j1 = p[k + 1];
+    pair_term(j0, A.x, A.y, A.z, eps2, r.ax, r.ay, r.az);
+    pair_term(j0, B.x, B.y, B.z, eps2, r.bx, r.by, r.bz);
+    pair_term(j1, A.x, A.y, A.z, eps2, r.ax, r.ay, r.az);
+    pair_term(j1, B.x, B.y, B.z, eps2, r.bx, r.by, r.bz);
+  }
+  if (k < C) {
+    const float4 j0 = p[k];
+    pair_term(j0, A.x, A.y, A.z, eps2, r.ax, r.ay, r.az);
+    pair_term(j0, B.x, B.y, B.z, eps2, r.bx, r.by, r.bz);
+  }
+}
+
+__device__ __forceinline__ void tile_quads2(const float4* __restrict__ p, int C, const float3 A, const float3 B,
+                                            float eps2, Acc2& r) {
+  for (int k = 0; k < C; ++k) {
+    const float4 a = p[3 * k], b = p[3 * k + 1], c = p[3 * k + 2];
+    quad_term(a, b, c, A.x, A.y, A.z, eps2, r.ax, r.ay, r.az);
+    quad_term(a, b, c, B.x, B.y, B.z, eps2, r.bx, r.by, r.bz);
+  }
+}
+
 // Node record for LDS: monopole (com, M); quadrupole adds (3 Sxx, 3 Syy, 3 Szz, 3 Sxy), (3 Sxz, 3 Syz, 1.5 T, 0).
 template <int ORDER>
 struct NodeRegs {
@@ -154,11 +221,13 @@ __host__ __device__ __forceinline__ int grav_lds_per_wave(int tile) { return gra
 
 // One task on one workgroup of W = blockDim.x / 64 wavefronts.  Wave w takes the task's nodes
 // w, w + W, ... and its direct ranges w, w + W, ... (address lists: windows w, w + W, ...), so W
-// waves share one task's lists; the per-target sums are reduced across slices within each wave and
-// then across the W waves, in a fixed order.  `smem` is the block's dynamic LDS of
+// waves share one task's lists.  Within a wave the lanes are (lane-target j) x (slice s): with
+// TWO each lane carries targets j and j + h (h = ceil(i_count / 2)), otherwise target j (h =
+// i_count); S = floor(64 / h) slices.  The per-target sums are reduced across slices within each
+// wave and then across the W waves, in a fixed order.  `smem` is the block's dynamic LDS of
 // W * grav_lds_per_wave(tile) records; the call starts and ends with every wave of the block
 // converged (it contains block barriers).
-template <int ORDER, bool LISTS>
+template <int ORDER, bool LISTS, bool TWO>
 __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4* __restrict__ smem) {
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
@@ -175,19 +244,39 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4
   const int ic = tk.i_count;
   for (int i0 = 0; i0 < ic; i0 += 64) {
     const int icc = ic - i0 < 64 ? ic - i0 : 64;
-    const int S = 64 / icc;
-    const int il = lane % icc;
-    const int sl = lane / icc;
+    const int h = TWO ? (icc + 1) >> 1 : icc;
+    const int S = 64 / h;
+    const int il = lane % h;
+    const int sl = lane / h;
     const bool active = sl < S;
-    float xi = 0.f, yi = 0.f, zi = 0.f;
+    const int ib = il + h < icc ? il + h : il;  // TWO: second target (a copy of the first if absent)
+    float3 A = make_float3(0.f, 0.f, 0.f), B = A;
     if (active) {
-      int p;
-      if (LISTS) p = a.ilist[a.ioff[t] + i0 + il];
-      else p = (a.ibeg ? a.ibeg[t] : tk.i_begin) + i0 + il;
-      float4 r = a.rec[p];
-      xi = r.x; yi = r.y; zi = r.z;
+      const int pb = LISTS ? 0 : (a.ibeg ? a.ibeg[t] : tk.i_begin) + i0;
+      const float4 r = a.rec[LISTS ? a.ilist[a.ioff[t] + i0 + il] : pb + il];
+      A = make_float3(r.x, r.y, r.z);
+      if (TWO) {
+        const float4 q = a.rec[LISTS ? a.ilist[a.ioff[t] + i0 + ib] : pb + ib];
+        B = make_float3(q.x, q.y, q.z);
+      }
     }
-    double Ax = 0.0, Ay = 0.0, Az = 0.0;
+    double Ax = 0.0, Ay = 0.0, Az = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0;
+    // one tile of C records per slice starting at L + rec_stride * sl * C: accumulate it
+    auto tile_sum = [&](int C, bool quads) {
+      if (!active) return;
+      if (TWO) {
+        Acc2 r{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (quads) tile_quads2(L + 3 * sl * C, C, A, B, a.eps2, r);
+        else tile_pairs2(L + sl * C, C, A, B, a.eps2, r);
+        Ax += r.ax; Ay += r.ay; Az += r.az;
+        Bx += r.bx; By += r.by; Bz += r.bz;
+      } else {
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        if (quads) tile_quads(L + 3 * sl * C, C, A.x, A.y, A.z, a.eps2, ax, ay, az);
+        else tile_pairs(L + sl * C, C, A.x, A.y, A.z, a.eps2, ax, ay, az);
+        Ax += ax; Ay += ay; Az += az;
+      }
+    };
 
     // ---- node terms: this wave's nodes are list entries w, w + W, ...
     {
@@ -208,16 +297,8 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4
           idx_next = e2 < nw ? nl[e2 * W] : -1;
         }
         wave_sync();
-        if (active) {
-          float ax = 0.f, ay = 0.f, az = 0.f;
-          if (ORDER == 1) {
-            // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
-            tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-          } else {
-            tile_quads(L + 3 * sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-          }
-          Ax += ax; Ay += ay; Az += az;
-        }
+        // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
+        tile_sum(C, ORDER == 2);
         wave_sync();
       }
     }
@@ -235,11 +316,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4
           L[e] = v;
         }
         wave_sync();
-        if (active) {
-          float ax = 0.f, ay = 0.f, az = 0.f;
-          tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-          Ax += ax; Ay += ay; Az += az;
-        }
+        tile_sum(C, false);
         wave_sync();
       }
     } else {
@@ -277,26 +354,37 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4
             L[e] = v;
           }
           wave_sync();
-          if (active) {
-            float ax = 0.f, ay = 0.f, az = 0.f;
-            tile_pairs(L + sl * C, C, xi, yi, zi, a.eps2, ax, ay, az);
-            Ax += ax; Ay += ay; Az += az;
-          }
+          tile_sum(C, false);
           wave_sync();
         }
       }
     }
 
     // ---- reduce: slices within the wave, then the W waves, in a fixed order
-    red[3 * lane] = Ax;
-    red[3 * lane + 1] = Ay;
-    red[3 * lane + 2] = Az;
-    wave_sync();
     double sx = 0.0, sy = 0.0, sz = 0.0;
-    if (lane < icc) {
-      for (int s = 0; s < S; ++s) {
-        const double* q = red + 3 * (s * icc + lane);
-        sx += q[0]; sy += q[1]; sz += q[2];
+    if (TWO) {
+      // 6 sums per lane: the tile area is free now
+      double* R2 = reinterpret_cast<double*>(L);
+      R2[6 * lane] = Ax; R2[6 * lane + 1] = Ay; R2[6 * lane + 2] = Az;
+      R2[6 * lane + 3] = Bx; R2[6 * lane + 4] = By; R2[6 * lane + 5] = Bz;
+      wave_sync();
+      if (lane < icc) {
+        const int j = lane < h ? lane : lane - h, off = lane < h ? 0 : 3;
+        for (int s = 0; s < S; ++s) {
+          const double* q = R2 + 6 * (s * h + j) + off;
+          sx += q[0]; sy += q[1]; sz += q[2];
+        }
+      }
+    } else {
+      red[3 * lane] = Ax;
+      red[3 * lane + 1] = Ay;
+      red[3 * lane + 2] = Az;
+      wave_sync();
+      if (lane < icc) {
+        for (int s = 0; s < S; ++s) {
+          const double* q = red + 3 * (s * icc + lane);
+          sx += q[0]; sy += q[1]; sz += q[2];
+        }
       }
     }
     wave_sync();

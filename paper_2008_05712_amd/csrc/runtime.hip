@@ -708,6 +708,8 @@ static gc_status check_prm(gc_batch b, const gc_force_params* prm, int* tile, in
   }
   if (prm->schedule < GC_SCHED_TASKS || prm->schedule > GC_SCHED_STEP)
     return set_err(c, GC_E_INVAL, "schedule must be GC_SCHED_TASKS, GC_SCHED_QUEUE or GC_SCHED_STEP");
+  if (prm->targets_per_lane < 0 || prm->targets_per_lane > 2)
+    return set_err(c, GC_E_INVAL, "targets_per_lane must be 0, 1 or 2");
   return GC_OK;
 }
 
@@ -748,13 +750,14 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
     a.queue = b->queue.as<int32_t>();
     a.order = b->d_order.as<int32_t>();
     int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
+    const bool two = prm->targets_per_lane == 2;
     int grid = prm->grid_blocks;
     if (persistent && grid <= 0) {
       int per = 0;
-      GC_HIP(c, grav_occupancy(order, lists, true, tile, wpb, &per));
+      GC_HIP(c, grav_occupancy(order, lists, true, two, tile, wpb, &per));
       grid = std::max(1, per) * c->n_cu;
     }
-    GC_HIP(c, launch_grav(order, lists, persistent, a, wpb, grid, s));
+    GC_HIP(c, launch_grav(order, lists, persistent, two, a, wpb, grid, s));
   } else {
     if (lists) return set_err(c, GC_E_UNSUPPORTED, "Lennard-Jones supports PACK, REDUNDANT and NONE");
     if (!b->pool->src_device) return set_err(c, GC_E_INVAL, "Lennard-Jones needs a device-resident source");
@@ -794,10 +797,11 @@ extern "C" gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_
   if (!prm || !blocks_per_cu) return set_err(ctx, GC_E_INVAL, "gc_occupancy: NULL argument");
   int tile = prm->tile ? prm->tile : 256, wpb = prm->waves_per_block ? prm->waves_per_block : 4, per = 0;
   const int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
+  const bool two = prm->targets_per_lane == 2;
   if (prm->schedule == GC_SCHED_STEP)
-    GC_HIP(ctx, step_occupancy(order, tile, &per));
+    GC_HIP(ctx, step_occupancy(order, two, tile, &per));
   else
-    GC_HIP(ctx, grav_occupancy(order, false, prm->schedule == GC_SCHED_QUEUE, tile, wpb, &per));
+    GC_HIP(ctx, grav_occupancy(order, false, prm->schedule == GC_SCHED_QUEUE, two, tile, wpb, &per));
   *blocks_per_cu = per;
   if (n_cu) *n_cu = ctx->n_cu;
   return GC_OK;
@@ -981,7 +985,8 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   GC_HIP(ctx, launch_fill_i32(gr->step_ctr.as<int32_t>(), 0, 2 * (int64_t)n_ctr, s));
   GC_HIP(ctx, hipStreamSynchronize(s));  // the host vectors go out of scope
   int per = 0;
-  GC_HIP(ctx, step_occupancy(order, tile, &per));
+  const bool two = prm->targets_per_lane == 2;
+  GC_HIP(ctx, step_occupancy(order, two, tile, &per));
   const int grid = std::max(1, per) * ctx->n_cu;
   StepArgs a{};
   a.segs = gr->step_segs.as<StepSeg>();
@@ -992,7 +997,7 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   a.ctr = gr->step_ctr.as<uint64_t>();
   hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamBeginCapture");
-  hipError_t le = launch_step(order, a, grid, tile, s);
+  hipError_t le = launch_step(order, two, a, grid, tile, s);
   hipGraph_t g = nullptr;
   ce = hipStreamEndCapture(s, &g);
   if (le != hipSuccess || ce != hipSuccess) {
@@ -1216,12 +1221,14 @@ extern "C" gc_status gc_autotune(gc_batch b, const gc_force_params* base, const 
   gc_status st = GC_OK;
   for (int ti = 0; ti < 3 && st == GC_OK; ++ti)
     for (int wi = 0; wi < 3 && st == GC_OK; ++wi)
-      for (int sc = 0; sc < 2 && st == GC_OK; ++sc, ++idx) {
+      for (int sc = 0; sc < 2 && st == GC_OK; ++sc)
+      for (int tp = 1; tp <= 2 && st == GC_OK; ++tp, ++idx) {
         gc_force_params p = *base;
         p.tile = tiles[ti];
         p.waves_per_block = waves[wi];
         p.schedule = sc;
         p.grid_blocks = 0;
+        p.targets_per_lane = tp;
         st = launch_combined_async(b, &p, nodes_dev, acc_dev, s);  // warm-up
         if (st != GC_OK) break;
         hipError_t e = hipEventRecord(e0, s);

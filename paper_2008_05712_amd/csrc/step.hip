@@ -131,8 +131,8 @@ __device__ __forceinline__ ReorgArgs load_reorg(const ReorgArgs* r) {
   return a;
 }
 
-template <int ORDER>
-__global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_per_eu(5))) k_step(StepArgs s) {
+template <int ORDER, bool TWO>
+__global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_per_eu(TWO ? 4 : 5))) k_step(StepArgs s) {
   extern __shared__ float4 smem[];
   __shared__ int sh[dev::kRThreads / 64];
   __shared__ uint32_t s_ex, s_tag;
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
         ready = k;
       }
       const GravArgs ga = load_grav(&R.grav);
-      dev::grav_task<ORDER, false>(ga, uniform(ga.order[idx]), smem);
+      dev::grav_task<ORDER, false, TWO>(ga, uniform(ga.order[idx]), smem);
     } else if (type == kItemEvict) {
       __builtin_amdgcn_s_setprio(3);
       if (tid == 0 && k > 0) wait_ge(ch_done - 2 * kCtrStride, goal * (uint64_t)s.rounds[k - 1].n_chain, R.reorg.state + GC_STATE_ERR);
@@ -215,44 +215,42 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
     dev::tstore(s.ctr + kCtrStride * kCtrEpoch, goal);
 }
 
-template <int ORDER>
-size_t step_lds(int tile) {
-  return (size_t)(dev::kRThreads / 64) * grav_lds_per_wave(tile) * sizeof(float4);
+size_t step_lds(int tile) { return (size_t)(dev::kRThreads / 64) * grav_lds_per_wave(tile) * sizeof(float4); }
+
+template <int ORDER, bool TWO>
+hipError_t step_attr(int tile) {
+  const size_t lds = step_lds(tile);
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_step<ORDER, TWO>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
 }
 
-template <int ORDER>
-hipError_t step_attr(int tile) {
-  const size_t lds = step_lds<ORDER>(tile);
-  if (lds <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_step<ORDER>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+template <int ORDER, bool TWO>
+hipError_t step_launch_one(const StepArgs& a, int grid, int tile, hipStream_t s) {
+  hipError_t e = step_attr<ORDER, TWO>(tile);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_step<ORDER, TWO>), dim3(grid), dim3(dev::kRThreads), step_lds(tile), s, a);
+  return hipGetLastError();
+}
+
+template <int ORDER, bool TWO>
+hipError_t step_occ_one(int tile, int* blocks) {
+  hipError_t e = step_attr<ORDER, TWO>(tile);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<ORDER, TWO>, dev::kRThreads, step_lds(tile));
 }
 
 }  // namespace
 
-hipError_t launch_step(int order, const StepArgs& a, int grid, int tile, hipStream_t s) {
+hipError_t launch_step(int order, bool two, const StepArgs& a, int grid, int tile, hipStream_t s) {
   if (grid < 1 || a.n_items <= 0) return hipSuccess;
-  if (order == 1) {
-    hipError_t e = step_attr<1>(tile);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_step<1>, dim3(grid), dim3(dev::kRThreads), step_lds<1>(tile), s, a);
-  } else {
-    hipError_t e = step_attr<2>(tile);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_step<2>, dim3(grid), dim3(dev::kRThreads), step_lds<2>(tile), s, a);
-  }
-  return hipGetLastError();
+  if (order == 1) return two ? step_launch_one<1, true>(a, grid, tile, s) : step_launch_one<1, false>(a, grid, tile, s);
+  return two ? step_launch_one<2, true>(a, grid, tile, s) : step_launch_one<2, false>(a, grid, tile, s);
 }
 
-hipError_t step_occupancy(int order, int tile, int* blocks) {
-  if (order == 1) {
-    hipError_t e = step_attr<1>(tile);
-    if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<1>, dev::kRThreads, step_lds<1>(tile));
-  }
-  hipError_t e = step_attr<2>(tile);
-  if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<2>, dev::kRThreads, step_lds<2>(tile));
+hipError_t step_occupancy(int order, bool two, int tile, int* blocks) {
+  if (order == 1) return two ? step_occ_one<1, true>(tile, blocks) : step_occ_one<1, false>(tile, blocks);
+  return two ? step_occ_one<2, true>(tile, blocks) : step_occ_one<2, false>(tile, blocks);
 }
 
 }  // namespace gc

@@ -131,6 +131,51 @@ def test_persistent_schedule_and_tiles_are_bitwise_equal(ctx, plum):
     rig.close()
 
 
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("mode", [gc.REORG_PACK, gc.REORG_SORTED, gc.REORG_NONE])
+def test_two_targets_per_lane_matches_oracle(ctx, plum, mode, order):
+    # each lane holds two targets of its task (odd and even bucket sizes, one-target tasks); the result
+    # meets the oracle bar for every shape, and the persistent queue is bitwise the per-task launch
+    print(f"[gpu] two targets per lane mode={mode} order={order}", flush=True)
+    rig = GravRig(ctx, plum)
+    b = rig.batch(whole(plum))
+    ref = O.grav_workload(plum, order=order)
+    for tile, wpb in [(256, 4), (128, 2), (512, 8), (64, 1)]:
+        base = rig.run(b, mode, order=order, tile=tile, waves_per_block=wpb, targets_per_lane=2)
+        assert rel_l2_per_task(base, ref, whole(plum)).max() <= TOL, (tile, wpb)
+        got = rig.run(b, mode, order=order, tile=tile, waves_per_block=wpb, schedule=1, targets_per_lane=2)
+        assert np.array_equal(got, base), (tile, wpb)
+    b.destroy()
+    rig.close()
+
+
+def test_two_targets_per_lane_edge_cases(ctx):
+    # buckets up to 134 targets (passes of 64 targets, a ragged last pass, odd pass sizes where one
+    # lane's second target is absent, one-target tasks) and direct-only lists (theta = 0)
+    print("[gpu] two targets per lane edge cases", flush=True)
+    for bucket, theta in [(150, 0.0), (97, 0.5), (33, 0.7), (1, 0.7)]:
+        w = W.build_grav(W.plummer(900, 41 + bucket), bucket=bucket, theta=theta)
+        rig = GravRig(ctx, w)
+        b = rig.batch(whole(w))
+        for order in (1, 2):
+            ref = O.grav_workload(w, order=order)
+            acc = rig.run(b, gc.REORG_PACK, order=order, targets_per_lane=2)
+            assert rel_l2_per_task(acc, ref, whole(w)).max() <= TOL, (bucket, order)
+        b.destroy()
+        rig.close()
+
+
+def test_targets_per_lane_is_validated(ctx, plum):
+    rig = GravRig(ctx, plum)
+    b = rig.batch(W.task_subset(plum, np.arange(10)))
+    b.reorganize(rig.pool, gc.REORG_PACK)
+    for bad in (-1, 3):
+        with pytest.raises(gc.GcError):
+            b.launch(gc.grav_params(order=2, targets_per_lane=bad), rig.nodes, rig.acc)
+    b.destroy()
+    rig.close()
+
+
 def test_task_order_does_not_change_results(ctx, plum):
     rig = GravRig(ctx, plum)
     t = whole(plum)
@@ -430,17 +475,17 @@ def _set_base(rig, base):
     rig.place(*base)
 
 
-@pytest.mark.parametrize("order", [1, 2])
-def test_step_schedule_matches_per_round_launches(ctx, plum, order):
+@pytest.mark.parametrize("order,tpl", [(1, 0), (2, 0), (2, 2)])
+def test_step_schedule_matches_per_round_launches(ctx, plum, order, tpl):
     # one persistent launch per step (every round's reorganisation, eviction of its staging, and pass)
     # gives bitwise the per-round launches' accelerations and the oracle's maps on the base state, and
     # leaves the base residency in the pool; replays repeat it exactly
     import torch
-    print(f"[gpu] whole-step schedule order={order}", flush=True)
+    print(f"[gpu] whole-step schedule order={order} targets_per_lane={tpl}", flush=True)
     rig, bts, bs, base = _rounds_rig(ctx, plum, 4, 500, 38, 0.4, 39)
     _set_base(rig, base)
     base_so = rig.pool.query()
-    prm = gc.grav_params(order=order)
+    prm = gc.grav_params(order=order, targets_per_lane=tpl)
     rig.acc.fill_(np.nan)
     for k, b in enumerate(bs):
         if k:
@@ -455,7 +500,7 @@ def test_step_schedule_matches_per_round_launches(ctx, plum, order):
     rig.pool.evict_staged(bs[-1])
     assert np.array_equal(rig.pool.query(), base_so)
     s = torch.cuda.Stream()
-    sprm = gc.grav_params(order=order, schedule=gc.SCHED_STEP)
+    sprm = gc.grav_params(order=order, schedule=gc.SCHED_STEP, targets_per_lane=tpl)
     g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), sprm, rig.nodes, rig.acc, stream=s,
                  fixture=gc.FIXTURE_EVICT_STAGED)
     for rep in range(4):

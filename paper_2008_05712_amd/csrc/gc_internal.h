@@ -88,10 +88,12 @@ struct ReorgArgs {
   int32_t* uslot;          // per union rank: pool slot (-1: missing and no free slot)
   int32_t* missing;        // ids of the missing records, ascending
   int32_t* mslot;          // their slots (-1: none)
-  uint64_t* free_list;     // tagged free-slot entries, |U| of them
+  uint64_t* free_list;     // tagged free-slot entries, flimit of them
+  uint64_t* ftotal;        // tagged free-slot count (null: the batch's own word in state)
+  int32_t flimit;          // entries listed (0: |U|)
   int32_t* state;
   int32_t nbf, nbu;        // set by the launcher
-  int32_t evict_after;     // whole-step kernel: a union block evicts what it staged once it has packed it
+  int32_t evict_after;     // whole-step kernel: a union block evicts what it stages at once
 };
 
 // occupancy entries (one per slot, padded) allocated for a pool of `cap` slots
@@ -131,13 +133,14 @@ struct StepSeg {
 };
 struct StepRound {
   GravArgs grav;          // the round's combined pass over its packed records
-  ReorgArgs reorg;        // the round's reorganisation (nbf, nbu set)
+  ReorgArgs reorg;        // the round's reorganisation (nbf: free-scan items, 0 after round 0; nbu)
   const int32_t* ev_ids;  // ids evicted before the round (missing list of the round before), or null
   const int32_t* ev_n;    // their count (device)
   int32_t ev_bound;       // bound of that count (entries of ev_ids)
   int32_t n_ids;
   int32_t n_evict;        // eviction items of the round
   int32_t n_chain;        // free-slot + union items of the round
+  int32_t prev;           // the latest earlier round with chain items (-1: none)
 };
 struct StepArgs {
   const StepSeg* segs;
@@ -147,10 +150,13 @@ struct StepArgs {
   int32_t n_rounds;
   uint64_t* ctr;          // counter c at ctr[kCtrStride * c] (all monotonic across launches); a wait that
                           // hits its bound sets the error word of its round's batch state
+  uint64_t* fmeta;        // free-slot list of the launch: [0] its count, [1 + r] round r's offset into
+                          // it, then the list (tagged words, tag = launch epoch + 1)
 };
 constexpr int kCtrStride = 32;  // one 256-byte line per step counter
 constexpr int kCtrTickets = 0, kCtrExits = 1, kCtrEpoch = 2, kCtrRounds = 3;  // then per round r:
-                                // kCtrRounds + 2r eviction items done, kCtrRounds + 2r + 1 free + union done
+                                // kCtrRounds + 3r eviction items done, + 1 table parts (free-scan and
+                                // union items) done, + 2 data parts (union items) done
 constexpr int kStepLead = 2;    // rounds by which the reorganisation items precede the passes
 hipError_t launch_step(int order, bool two, const StepArgs& a, int grid, int tile, hipStream_t s);
 hipError_t step_occupancy(int order, bool two, int tile, int* blocks);

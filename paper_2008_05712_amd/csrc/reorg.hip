@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kRThreads) k_reorg(ReorgArgs a) {
   const int t = s_ticket;
   const uint32_t tag = s_tag;
   if (t < a.nbf)
-    dev::free_role<false>(a, t, tag, sh, &s_ex);
+    dev::free_role<false>(a, t, tag, tag, sh, &s_ex);
   else
   {
     int32_t id[dev::kUItems];
@@ -235,6 +235,8 @@ hipError_t launch_pool_reset(int32_t* slot_of, int32_t n_ids, uint32_t* occ, int
 hipError_t launch_reorg(ReorgArgs a, hipStream_t s) {
   a.nbu = union_blocks(a.u);
   a.nbf = free_blocks(a.cap);
+  a.ftotal = reinterpret_cast<uint64_t*>(a.state + dev::kFreeTotal);
+  a.flimit = a.u;
   hipLaunchKernelGGL(k_reorg, dim3(a.nbu + a.nbf), dim3(kRThreads), 0, s, a);
   return hipGetLastError();
 }

@@ -131,10 +131,12 @@ __device__ __forceinline__ float4 ld_rec(const float4* p) {
                      __uint_as_float((uint32_t)hi), __uint_as_float((uint32_t)(hi >> 32)));
 }
 
-// Free-slot side: the lowest free slots in ascending order, listed up to `limit` (|U|, an upper
-// bound on the number of missing records); the last block publishes the pool's free count.
+// Free-slot side: the lowest free slots in ascending order, listed up to a.flimit entries (at least
+// the number of records that can go missing); the last block publishes the pool's free count.
+// Look-back words carry `tag`, list entries and the free count `ltag`.
 template <bool COH>
-__device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex) {
+__device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t tag, uint32_t ltag, int* sh,
+                                          uint32_t* s_ex) {
   uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack);
   const int64_t s0 = (int64_t)b * kFBlock + (int64_t)threadIdx.x * kFItems;
   uint32_t f = 0;
@@ -163,18 +165,18 @@ __device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t ta
     if (threadIdx.x == 0) {
       *s_ex = ex;
       if (b == a.nbf - 1) {
-        tstore(reinterpret_cast<uint64_t*>(a.state + kFreeTotal), tword(tag, 0, ex + (uint32_t)tot));
+        tstore(a.ftotal, tword(ltag, 0, ex + (uint32_t)tot));
         istore(a.state + GC_STATE_FREE, (int32_t)(ex + (uint32_t)tot));
       }
     }
   }
   __syncthreads();
   r += (int)*s_ex;
-  if (r >= a.u) return;
+  if (r >= a.flimit) return;
 #pragma unroll
   for (int k = 0; k < kFItems; ++k)
     if ((f >> k) & 1u) {
-      if (r < a.u) tstore(a.free_list + r, tword(tag, 0, (uint32_t)(s0 + k)));
+      if (r < a.flimit) tstore(a.free_list + r, tword(ltag, 0, (uint32_t)(s0 + k)));
       ++r;
     }
 }
@@ -191,12 +193,11 @@ __device__ __forceinline__ void union_ids(const ReorgArgs& a, int b, int32_t (&i
   id[4] = y.x; id[5] = y.y; id[6] = y.z; id[7] = y.w;
 }
 
+// Chare-table lookup of this thread's entries: resident slot (sl) and the missing mask.
 template <bool COH>
-__device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex,
-                                           const int32_t (&id)[kUItems]) {
-  uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbf;
+__device__ __forceinline__ uint32_t union_lookup(const ReorgArgs& a, int b, const int32_t (&id)[kUItems],
+                                                 int32_t (&sl)[kUItems]) {
   const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
-  int32_t sl[kUItems];
   uint32_t fm = 0;
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
@@ -206,8 +207,65 @@ __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t t
       if (sl[i] < 0) fm |= 1u << i;
     }
   }
-  // every entry's record -- from the pool if resident, from the source if missing -- is loaded
-  // before the ranks are known, and its packed copy written at once: neither waits for the scans
+  return fm;
+}
+
+// Entry j of the free-slot list for the missing entries of mask fm, in order from list index r0
+// (entries carry `ltag` once listed; *ftotal, once it carries `ltag`, bounds the list): one probe
+// for all of them in flight, then a bounded wait that re-probes those still unlisted.  Writes the
+// slot (or -1: the pool has no free slot for it) into slot[i] for each missing i.
+__device__ __forceinline__ void union_probe(uint64_t* flist, uint64_t* ftotal, uint32_t ltag, int64_t r0,
+                                            uint32_t fm, int32_t (&slot)[kUItems], int32_t* err) {
+  uint32_t pend = 0;
+  {
+    int64_t r = r0;
+#pragma unroll
+    for (int i = 0; i < kUItems; ++i) {
+      if ((fm >> i) & 1u) {
+        slot[i] = -1;
+        const uint64_t w = tload(flist + r++);
+        if ((uint32_t)(w >> 32) == ltag) slot[i] = (int32_t)(w & 0x7fffffffu);
+        else pend |= 1u << i;
+      }
+    }
+  }
+  uint32_t spins = 0;
+  while (pend) {
+    if (++spins > kSpinLimit) {
+      istore(err, 1);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    const uint64_t t = tload(ftotal);
+    const bool total_known = (uint32_t)(t >> 32) == ltag;
+    int64_t r = r0;
+#pragma unroll
+    for (int i = 0; i < kUItems; ++i)
+      if ((fm >> i) & 1u) {
+        if ((pend >> i) & 1u) {
+          const uint64_t w = tload(flist + r);
+          if ((uint32_t)(w >> 32) == ltag) {
+            slot[i] = (int32_t)(w & 0x7fffffffu);
+            pend &= ~(1u << i);
+          } else if (total_known && r >= (int64_t)(t & 0x7fffffffu)) {
+            pend &= ~(1u << i);  // the pool has no free slot for this one
+          }
+        }
+        ++r;
+      }
+  }
+}
+
+// Per-batch form of the union side: lookup, then every entry's record -- from the pool if resident,
+// from the source if missing -- is loaded before the ranks are known and its packed copy written at
+// once (neither waits for the scans); then the missing ranks, slot assignment and staging.
+template <bool COH>
+__device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex,
+                                           const int32_t (&id)[kUItems]) {
+  uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbf;
+  const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
+  int32_t sl[kUItems];
+  const uint32_t fm = union_lookup<COH>(a, b, id, sl);
   float rx[kUItems], ry[kUItems], rz[kUItems], rw[kUItems];
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
@@ -242,53 +300,13 @@ __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t t
   __syncthreads();
   if (!fm) return;
   rm += (int)*s_ex;
-  // the rm-th free slot for the rm-th missing record, once its free-scan block has listed it (none if
-  // the pool is full): one probe for all of this thread's entries in flight, then a bounded wait that
-  // re-probes the entries still unlisted
-  int32_t sidx[kUItems];  // slot of each missing entry once listed (-1: none)
-  uint32_t pend = 0;
-  {
-    int r = rm;
-#pragma unroll
-    for (int i = 0; i < kUItems; ++i) {
-      sidx[i] = -1;
-      if ((fm >> i) & 1u) {
-        const uint64_t w = tload(a.free_list + r++);
-        if ((uint32_t)(w >> 32) == tag) sidx[i] = (int32_t)(w & 0x7fffffffu);
-        else pend |= 1u << i;
-      }
-    }
-  }
-  uint32_t spins = 0;
-  while (pend) {
-    if (++spins > kSpinLimit) {
-      istore(a.state + GC_STATE_ERR, 1);
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
-    const uint64_t t = tload(reinterpret_cast<uint64_t*>(a.state + kFreeTotal));
-    const bool total_known = (uint32_t)(t >> 32) == tag;
-    int r = rm;
-#pragma unroll
-    for (int i = 0; i < kUItems; ++i)
-      if ((fm >> i) & 1u) {
-        if ((pend >> i) & 1u) {
-          const uint64_t w = tload(a.free_list + r);
-          if ((uint32_t)(w >> 32) == tag) {
-            sidx[i] = (int32_t)(w & 0x7fffffffu);
-            pend &= ~(1u << i);
-          } else if (total_known && (uint32_t)r >= (uint32_t)(t & 0x7fffffffu)) {
-            pend &= ~(1u << i);  // the pool has no free slot for this one
-          }
-        }
-        ++r;
-      }
-  }
+  // the rm-th free slot for the rm-th missing record, once its free-scan block has listed it
+  union_probe(a.free_list, a.ftotal, tag, rm, fm, sl, a.state + GC_STATE_ERR);
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
     if (!((fm >> i) & 1u)) continue;
     const int64_t k = k0 + i;
-    const int32_t s = sidx[i];
+    const int32_t s = sl[i];
     a.missing[rm] = id[i];
     a.mslot[rm] = s;
     a.uslot[k] = s;
@@ -299,14 +317,75 @@ __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t t
     }
     ++rm;
   }
-  if (a.evict_after) {
-    // the staged records leave the table again (the pool keeps its base residency between rounds)
-#pragma unroll
-    for (int i = 0; i < kUItems; ++i)
-      if (((fm >> i) & 1u) && sidx[i] >= 0) {
-        a.slot_of[id[i]] = -1;
-        a.occ[sidx[i]] = 0u;
+}
+
+// Whole-step form of the union side, in two parts.  The table part -- lookup, missing ranks, slot
+// assignment and the table updates (and, with evict_after, the eviction of what it stages) -- is all
+// the next round's lookup depends on.  The data part -- record loads, packed copies, staging of the
+// missing records into their slots -- only feeds this round's pass and later rounds' pool reads, so
+// it runs after the table part has been published.  slot[i] leaves the table part as the entry's
+// slot (resident: its slot; missing: the assigned slot or -1) and fm as the missing mask.
+// Returns the round's missing count on the last union block's thread 0 (0 elsewhere).
+__device__ __forceinline__ uint32_t union_table(const ReorgArgs& a, int b, uint32_t tag, uint32_t ltag,
+                                                int64_t fbase, int* sh, uint32_t* s_ex, const int32_t (&id)[kUItems],
+                                                int32_t (&slot)[kUItems], uint32_t& fm) {
+  uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbf;
+  const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
+  fm = union_lookup<true>(a, b, id, slot);
+  int tot;
+  int rm = block_excl_scan(__popc(fm), sh, &tot);
+  uint32_t m = 0;
+  if (threadIdx.x < 64) {
+    const uint32_t ex = look_back(flags, b, tag, (uint32_t)tot, a.state + GC_STATE_ERR);
+    if (threadIdx.x == 0) {
+      *s_ex = ex;
+      if (b == a.nbu - 1) {
+        m = ex + (uint32_t)tot;
+        istore(a.state + GC_STATE_UNION, a.u);
+        istore(a.state + GC_STATE_MISSING, (int32_t)m);
       }
+    }
+  }
+  __syncthreads();
+  rm += (int)*s_ex;
+  if (fm) union_probe(a.free_list, a.ftotal, ltag, fbase + rm, fm, slot, a.state + GC_STATE_ERR);
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    const int64_t k = k0 + i;
+    if (k >= a.u) continue;
+    const int32_t s = slot[i];
+    a.uslot[k] = s;
+    if ((fm >> i) & 1u) {
+      a.missing[rm] = id[i];
+      a.mslot[rm] = s;
+      ++rm;
+      if (s >= 0) {
+        // staged, and with evict_after at once evicted again (the pool keeps its base residency
+        // between rounds); the record itself is written by the data part
+        a.slot_of[id[i]] = a.evict_after ? -1 : s;
+        a.occ[s] = a.evict_after ? 0u : 1u;
+      }
+    }
+  }
+  return m;
+}
+
+__device__ __forceinline__ void union_data(const ReorgArgs& a, int b, const int32_t (&id)[kUItems],
+                                           const int32_t (&slot)[kUItems], uint32_t fm) {
+  const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
+  float4 v[kUItems];
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if ((fm >> i) & 1u) v[i] = a.src[id[i]];
+    else if (k0 + i < a.u) v[i] = ld_rec<true>(a.pool + slot[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    const int64_t k = k0 + i;
+    if (k >= a.u) continue;
+    a.packed[k] = v[i];
+    if (((fm >> i) & 1u) && slot[i] >= 0) a.pool[slot[i]] = v[i];
   }
 }
 

@@ -119,7 +119,7 @@ struct gc_graph_ {
   gc_ctx ctx = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  DevBuf step_segs, step_rounds, step_ctr;  // whole-step persistent schedule
+  DevBuf step_segs, step_rounds, step_ctr, step_fl;  // whole-step persistent schedule
   std::vector<hipStream_t> side;   // capture-time side streams (combined passes of successive steps overlap)
   std::vector<hipEvent_t> events;
 };
@@ -950,9 +950,13 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     r.free_list = b->free_list.as<uint64_t>();
     r.state = b->state.as<int32_t>();
     r.nbu = union_blocks(b->u);
-    r.nbf = free_blocks(p->cap);
+    // the free slots are scanned in round 0 only; later rounds read that list at an offset
+    r.nbf = k == 0 ? free_blocks(p->cap) : 0;
     sr.n_ids = p->n_ids;
     sr.n_chain = r.nbu + r.nbf;
+    sr.prev = -1;
+    for (int32_t q = k - 1; q >= 0 && sr.prev < 0; --q)
+      if (rounds[q].n_chain > 0) sr.prev = q;
     sr.n_evict = 0;
     sr.ev_ids = nullptr;
     sr.ev_n = nullptr;
@@ -975,14 +979,29 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   }
   for (int32_t k = std::max<int32_t>(R - kStepLead, 0); k < R; ++k)
     seg(kItemForce, k, (int32_t)batches[k]->tasks.size());
-  const int32_t n_ctr = kCtrStride * (kCtrRounds + 2 * R);
+  const int32_t n_ctr = kCtrStride * (kCtrRounds + 3 * R);
+  // the launch's free-slot list: entries up to the most any round can reach (with the evicting
+  // fixture every round reads from the start of the list, otherwise after what earlier rounds kept)
+  int64_t flimit = 0;
+  for (int32_t k = 0; k < R; ++k)
+    flimit = fixture == GC_FIXTURE_EVICT_STAGED ? std::max<int64_t>(flimit, batches[k]->u) : flimit + batches[k]->u;
+  flimit = std::min<int64_t>(flimit, p->cap);
+  const int64_t fl_words = 1 + (int64_t)R + std::max<int64_t>(flimit, 1);
   hipError_t e = gr->step_segs.ensure(sizeof(StepSeg) * std::max<size_t>(segs.size(), 1));
   if (e == hipSuccess) e = gr->step_rounds.ensure(sizeof(StepRound) * (size_t)R);
   if (e == hipSuccess) e = gr->step_ctr.ensure(sizeof(uint64_t) * (size_t)n_ctr);
+  if (e == hipSuccess) e = gr->step_fl.ensure(sizeof(uint64_t) * (size_t)fl_words);
   if (e != hipSuccess) return set_err(ctx, GC_E_NOMEM, "whole-step schedule: %s", hipGetErrorString(e));
+  uint64_t* fmeta = gr->step_fl.as<uint64_t>();
+  for (int32_t k = 0; k < R; ++k) {
+    rounds[k].reorg.free_list = fmeta + 1 + R;
+    rounds[k].reorg.ftotal = fmeta;
+    rounds[k].reorg.flimit = (int32_t)flimit;
+  }
   GC_HIP(ctx, hipMemcpyAsync(gr->step_segs.p, segs.data(), sizeof(StepSeg) * segs.size(), hipMemcpyHostToDevice, s));
   GC_HIP(ctx, hipMemcpyAsync(gr->step_rounds.p, rounds.data(), sizeof(StepRound) * (size_t)R, hipMemcpyHostToDevice, s));
   GC_HIP(ctx, launch_fill_i32(gr->step_ctr.as<int32_t>(), 0, 2 * (int64_t)n_ctr, s));
+  GC_HIP(ctx, launch_fill_i32(gr->step_fl.as<int32_t>(), 0, 2 * fl_words, s));  // tag 0: never a launch's
   GC_HIP(ctx, hipStreamSynchronize(s));  // the host vectors go out of scope
   int per = 0;
   const bool two = prm->targets_per_lane == 2;
@@ -995,6 +1014,7 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   a.rounds = gr->step_rounds.as<StepRound>();
   a.n_rounds = R;
   a.ctr = gr->step_ctr.as<uint64_t>();
+  a.fmeta = fmeta;
   hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamBeginCapture");
   hipError_t le = launch_step(order, two, a, grid, tile, s);
@@ -1057,6 +1077,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
       gs->step_segs.release();
       gs->step_rounds.release();
       gs->step_ctr.release();
+      gs->step_fl.release();
       delete gs;
       return st;
     }
@@ -1199,6 +1220,7 @@ extern "C" gc_status gc_graph_destroy(gc_graph g) {
   g->step_segs.release();
   g->step_rounds.release();
   g->step_ctr.release();
+  g->step_fl.release();
   delete g;
   return GC_OK;
 }

@@ -5,19 +5,32 @@
 // need no kernel boundaries and the passes of consecutive rounds overlap.
 //
 // Work items are numbered in ticket order:
-//   evict(0) free(0) union(0) free(1) union(1) free(2) union(2) force(0)
-//   free(3) union(3) force(1) ... union(R-1) force(R-3) force(R-2) force(R-1)
+//   evict(0) free(0) union(0) union(1) union(2) force(0) union(3) force(1) ...
+//   union(R-1) force(R-3) force(R-2) force(R-1)
 // so the reorganisation chain runs two rounds ahead of the force passes (the
 // chain is sequential -- each round's lookup sees the pool as the round before
-// left it -- and latency-bound, the passes are throughput-bound: two rounds of
-// slack keep the passes from waiting on it).  A block takes tickets from a
+// left it -- and latency-bound, the passes are throughput-bound).
+//
+// The free-slot list is scanned once, in round 0.  Inside the launch only the
+// union items change the occupancy: a round takes the lowest free slots in
+// order, so the free slots at the start of round r are round 0's list without
+// the entries taken (and kept) by earlier rounds -- an offset into that list,
+// which is 0 throughout when each round evicts what it stages.
+//
+// A union item has a table part (lookup, missing ranks, slot assignment, the
+// chare-table and occupancy updates), which is all the next round's lookup
+// depends on, and a data part (record loads, packed copies, staging of the
+// records into their slots), counted separately.  A block takes tickets from a
 // device counter (the next one is requested while the current item runs) and
 // waits only for items with smaller tickets:
-//   evict(r)         waits for free(r-1) + union(r-1);
-//   free(r) union(r) wait for evict(r) and free(r-1) + union(r-1), and inside
-//                    the round on the free-slot list and look-back words as in
-//                    the per-batch kernel;
-//   force(r)         waits for free(r) + union(r).
+//   evict(0)          no wait;
+//   free(0) union(r)  table parts wait for evict(r) and the table parts of the
+//                     previous round with chain items; inside round 0 on the
+//                     free-slot list and look-back words as in the per-batch
+//                     kernel;
+//   union(r) data     waits for the previous round's data parts (pool records
+//                     it stages may be read or its slots reused);
+//   force(r)          waits for the data parts of round r.
 // The unfinished item with the smallest ticket therefore always progresses (its
 // dependencies are finished), so the grid never deadlocks whatever the order
 // in which its blocks run; every wait is bounded anyway and raises an error
@@ -31,9 +44,9 @@
 // not coherent with the others'); every item writes plainly and, before it is
 // counted done, writes its XCD's L2 back (device-scope release).  Items of one
 // round exchange only tagged words, through device-scope atomics.  A force
-// item reads a round's packed records only after that round's items are all
-// done; no earlier access in the launch touches those lines (each union item
-// writes whole lines of its own), so its caches hold no stale copy.
+// item reads a round's packed records only after that round's data parts are
+// all done; no earlier access in the launch touches those lines (each union
+// item writes whole lines of its own), so its caches hold no stale copy.
 #include "grav_dev.h"
 #include "reorg_dev.h"
 
@@ -124,6 +137,8 @@ __device__ __forceinline__ ReorgArgs load_reorg(const ReorgArgs* r) {
   a.missing = uni(r->missing);
   a.mslot = uni(r->mslot);
   a.free_list = uni(r->free_list);
+  a.ftotal = uni(r->ftotal);
+  a.flimit = uni(r->flimit);
   a.state = uni(r->state);
   a.nbf = uni(r->nbf);
   a.nbu = uni(r->nbu);
@@ -136,7 +151,7 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
   extern __shared__ float4 smem[];
   __shared__ int sh[dev::kRThreads / 64];
   __shared__ uint32_t s_ex, s_tag;
-  __shared__ int64_t s_next;
+  __shared__ int64_t s_next, s_base, s_avail;
   __shared__ uint64_t s_epoch;
   const int tid = threadIdx.x;
   if (tid == 0) s_epoch = dev::tload(s.ctr + kCtrStride * kCtrEpoch);
@@ -144,6 +159,7 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
   const uint64_t E = s_epoch;
   const uint64_t base = E * ((uint64_t)s.n_items + gridDim.x);  // tickets taken by earlier launches
   const uint64_t goal = E + 1;
+  const uint32_t ltag = (uint32_t)goal;  // tag of this launch's free-slot list words
   uint64_t* tickets = s.ctr + kCtrStride * kCtrTickets;
   if (tid == 0) s_next = (int64_t)(atomicAdd(reinterpret_cast<unsigned long long*>(tickets), 1ull) - base);
   __syncthreads();
@@ -164,11 +180,14 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
     const int k = uniform(s.segs[lo].round);
     const int idx = uniform((int)(t - s.segs[lo].first));
     const StepRound& R = s.rounds[k];
-    uint64_t* ev_done = s.ctr + kCtrStride * (kCtrRounds + 2 * k);
-    uint64_t* ch_done = s.ctr + kCtrStride * (kCtrRounds + 2 * k + 1);
+    int32_t* err = R.reorg.state + GC_STATE_ERR;
+    uint64_t* ev_done = s.ctr + kCtrStride * (kCtrRounds + 3 * k);
+    uint64_t* ch_done = ev_done + kCtrStride;
+    uint64_t* dt_done = ev_done + 2 * kCtrStride;
+    const int pr = uniform(R.prev);
     if (type == kItemForce) {
       if (k > ready) {
-        if (tid == 0) wait_ge(ch_done, goal * (uint64_t)R.n_chain, R.reorg.state + GC_STATE_ERR);
+        if (tid == 0) wait_ge(dt_done, goal * (uint64_t)R.reorg.nbu, err);
         __syncthreads();
         ready = k;
       }
@@ -176,7 +195,7 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
       dev::grav_task<ORDER, false, TWO>(ga, uniform(ga.order[idx]), smem);
     } else if (type == kItemEvict) {
       __builtin_amdgcn_s_setprio(3);
-      if (tid == 0 && k > 0) wait_ge(ch_done - 2 * kCtrStride, goal * (uint64_t)s.rounds[k - 1].n_chain, R.reorg.state + GC_STATE_ERR);
+      if (tid == 0 && pr >= 0) wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 1), goal * (uint64_t)s.rounds[pr].n_chain, err);
       __syncthreads();
       const int64_t n = min(dev::iload(const_cast<int32_t*>(R.ev_n)), R.ev_bound);
       const int64_t first = (int64_t)idx * kEvictBlock;
@@ -192,19 +211,53 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
       int32_t ids[dev::kUItems];
       if (type == kItemUnion) dev::union_ids(ra, idx, ids);  // static: loaded while the dependencies finish
       if (tid == 0) {
-        wait_ge(ev_done, goal * (uint64_t)R.n_evict, R.reorg.state + GC_STATE_ERR);
-        if (k > 0) wait_ge(ch_done - 2 * kCtrStride, goal * (uint64_t)s.rounds[k - 1].n_chain, R.reorg.state + GC_STATE_ERR);
+        wait_ge(ev_done, goal * (uint64_t)R.n_evict, err);
+        int64_t fbase = 0, favail = -1;
+        if (pr >= 0) {
+          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 1), goal * (uint64_t)s.rounds[pr].n_chain, err);
+          // round 0 is complete: the launch's free count is known; this round's offset into the list is
+          // the previous one plus what that round took and kept
+          const uint64_t ft = dev::tload(s.fmeta);
+          if ((uint32_t)(ft >> 32) != ltag) dev::istore(err, 1);
+          const int64_t F = (int64_t)(ft & 0x7fffffffu);
+          if (!ra.evict_after && s.rounds[pr].reorg.nbu > 0) {
+            const uint64_t bw = dev::tload(s.fmeta + 1 + pr);
+            if ((uint32_t)(bw >> 32) != ltag) dev::istore(err, 1);
+            const int64_t bp = (int64_t)(bw & 0x7fffffffu);
+            const int64_t mp = dev::iload(s.rounds[pr].reorg.state + GC_STATE_MISSING);
+            const int64_t avail = F - bp > 0 ? F - bp : 0;
+            fbase = bp + (mp < avail ? mp : avail);
+          }
+          favail = F - fbase;
+        }
+        s_base = fbase;
+        s_avail = favail;
         s_tag = (uint32_t)dev::iload(R.reorg.state + dev::kTag) + 1u;
       }
       __syncthreads();
       const uint32_t tag = s_tag;
-      if (type == kItemFree)
-        dev::free_role<true>(ra, idx, tag, sh, &s_ex);
-      else
-        dev::union_role<true>(ra, idx, tag, sh, &s_ex, ids);
-      const uint64_t old = publish_done(ch_done);
-      // the last item of the round makes its tag the batch's current one (all of them read it first)
-      if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
+      if (type == kItemFree) {
+        dev::free_role<true>(ra, idx, tag, ltag, sh, &s_ex);
+        const uint64_t old = publish_done(ch_done);
+        if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
+      } else {
+        int32_t slot[dev::kUItems];
+        uint32_t fm;
+        const int64_t fbase = s_base;
+        (void)dev::union_table(ra, idx, tag, ltag, fbase, sh, &s_ex, ids, slot, fm);
+        if (tid == 0 && idx == ra.nbu - 1) {
+          dev::tstore(s.fmeta + 1 + k, dev::tword(ltag, 0, (uint32_t)fbase));
+          if (s_avail >= 0) dev::istore(R.reorg.state + GC_STATE_FREE, (int32_t)s_avail);
+        }
+        const uint64_t old = publish_done(ch_done);
+        if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
+        // data part: after the previous round's (its staging may be read here, its slots reused)
+        if (tid == 0 && pr >= 0)
+          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 2), goal * (uint64_t)s.rounds[pr].reorg.nbu, err);
+        __syncthreads();
+        dev::union_data(ra, idx, ids, slot, fm);
+        (void)publish_done(dt_done);
+      }
       __builtin_amdgcn_s_setprio(0);
     }
     if (tid == 0) s_next = (int64_t)(nxt - base);

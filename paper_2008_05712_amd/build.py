@@ -12,6 +12,10 @@ LIB = os.path.join(HERE, "libgcharm.so")
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
                # packed FP32 instructions stay disabled; the compiler emits plain v_fma_f32 / v_mul_f32
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               # every atomic here is issued by one lane; left to the atomic optimizer, the returned
+               # value is broadcast at once, which waits for the atomic where it is issued (the
+               # whole-step kernel requests its next ticket early and reads it only at the end)
+               "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
                "-Wall", "-Wno-unused-function"]
 
 

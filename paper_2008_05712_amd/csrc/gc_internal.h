@@ -127,10 +127,15 @@ hipError_t launch_lj_finish(float4* acc, const float* mass_t, const float4* rec_
 // Work items of one step, in ticket order; see step.hip.
 enum { kItemEvict = 0, kItemFree = 1, kItemUnion = 2, kItemForce = 3 };
 constexpr int kEvictBlock = 2048;  // ids per eviction item
-struct StepSeg {
-  int32_t type, round;   // item kind, round
-  int32_t first, count;  // tickets [first, first + count)
+// One work item, by ticket (32 bytes: a block loads the next one straight into LDS while it runs
+// the current one).
+struct StepItem {
+  int32_t kind;  // item type | round << 2
+  int32_t idx;   // eviction, free-scan and union items: block index within the round's role;
+                 // force items: the task's first packed target
+  int32_t i_begin, i_count, j_first, j_nranges, n_first, n_count;  // force items: the task
 };
+static_assert(sizeof(StepItem) == 32, "StepItem is loaded as two 16-byte pieces");
 struct StepRound {
   GravArgs grav;          // the round's combined pass over its packed records
   ReorgArgs reorg;        // the round's reorganisation (nbf: free-scan items, 0 after round 0; nbu)
@@ -143,8 +148,7 @@ struct StepRound {
   int32_t prev;           // the latest earlier round with chain items (-1: none)
 };
 struct StepArgs {
-  const StepSeg* segs;
-  int32_t n_segs;
+  const StepItem* items;  // by ticket
   int32_t n_items;
   const StepRound* rounds;
   int32_t n_rounds;

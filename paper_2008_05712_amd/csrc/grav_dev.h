@@ -219,16 +219,24 @@ __host__ __device__ __forceinline__ int grav_rec_cap(int tile) {
 }
 __host__ __device__ __forceinline__ int grav_lds_per_wave(int tile) { return grav_rec_cap(tile) + 96; }
 
+// A task as the force code reads it: the submitted fields and the first target's position in the
+// record array (its packed position, or i_begin when records are read in place).
+struct TaskDesc {
+  int32_t i_begin, i_count, j_first, j_nranges, n_first, n_count, ibeg;
+};
+
 // One task on one workgroup of W = blockDim.x / 64 wavefronts.  Wave w takes the task's nodes
-// w, w + W, ... and its direct ranges w, w + W, ... (address lists: windows w, w + W, ...), so W
-// waves share one task's lists.  Within a wave the lanes are (lane-target j) x (slice s): with
+// w, w + W, ... and the w-th of W equal contiguous shares of its direct records (address lists:
+// windows w, w + W, ...), so W waves share one task's lists.  Within a wave the lanes are (lane-target j) x (slice s): with
 // TWO each lane carries targets j and j + h (h = ceil(i_count / 2)), otherwise target j (h =
 // i_count); S = floor(64 / h) slices.  The per-target sums are reduced across slices within each
 // wave and then across the W waves, in a fixed order.  `smem` is the block's dynamic LDS of
 // W * grav_lds_per_wave(tile) records; the call starts and ends with every wave of the block
-// converged (it contains block barriers).
-template <int ORDER, bool LISTS, bool TWO>
-__device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4* __restrict__ smem) {
+// converged (it contains block barriers).  ready() is called by every thread once the first node
+// tile's loads are out and before any record is read (the records may still be being written).
+template <int ORDER, bool LISTS, bool TWO, class Ready>
+__device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const TaskDesc& tk,
+                                          float4* __restrict__ smem, Ready&& ready) {
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
   const int W = blockDim.x >> 6;
@@ -240,9 +248,18 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4
   // the range tables of the direct phase share the reduction scratch (live at different times)
   int* RO = reinterpret_cast<int*>(red);  // range start offsets within the group (64)
   int* RB = RO + 64;                      // range begins (64)
-  const gc_task tk = a.tasks[t];
   const int ic = tk.i_count;
+  // this wave's nodes; the first tile does not depend on the records, so its loads go out first
+  const int nw = tk.n_count > wid ? (tk.n_count - wid + W - 1) / W : 0;
+  const int* nl = a.node_idx + tk.n_first + wid;
+  int idx_next = (64 < nw && 64 + lane < nw) ? nl[(64 + lane) * W] : -1;
+  NodeRegs<ORDER> cur = load_node<ORDER>(a.nodes, lane < nw ? nl[lane * W] : -1);
+  ready();
   for (int i0 = 0; i0 < ic; i0 += 64) {
+    if (i0 > 0) {
+      idx_next = (64 < nw && 64 + lane < nw) ? nl[(64 + lane) * W] : -1;
+      cur = load_node<ORDER>(a.nodes, lane < nw ? nl[lane * W] : -1);
+    }
     const int icc = ic - i0 < 64 ? ic - i0 : 64;
     const int h = TWO ? (icc + 1) >> 1 : icc;
     const int S = 64 / h;
@@ -252,7 +269,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4
     const int ib = il + h < icc ? il + h : il;  // TWO: second target (a copy of the first if absent)
     float3 A = make_float3(0.f, 0.f, 0.f), B = A;
     if (active) {
-      const int pb = LISTS ? 0 : (a.ibeg ? a.ibeg[t] : tk.i_begin) + i0;
+      const int pb = LISTS ? 0 : tk.ibeg + i0;
       const float4 r = a.rec[LISTS ? a.ilist[a.ioff[t] + i0 + il] : pb + il];
       A = make_float3(r.x, r.y, r.z);
       if (TWO) {
@@ -280,10 +297,6 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4
 
     // ---- node terms: this wave's nodes are list entries w, w + W, ...
     {
-      const int nw = tk.n_count > wid ? (tk.n_count - wid + W - 1) / W : 0;
-      const int* nl = a.node_idx + tk.n_first + wid;
-      int idx_next = (64 < nw && 64 + lane < nw) ? nl[(64 + lane) * W] : -1;
-      NodeRegs<ORDER> cur = load_node<ORDER>(a.nodes, lane < nw ? nl[lane * W] : -1);
       for (int nb = 0; nb < nw; nb += kNodeTile) {
         const int cnt = nw - nb < kNodeTile ? nw - nb : kNodeTile;
         const int C = (cnt + S - 1) / S;
@@ -320,23 +333,23 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, float4
         wave_sync();
       }
     } else {
-      // this wave's ranges are entries w, w + W, ... of the task's range list; groups of up to
-      // 64 ranges are flattened by a wave scan, and each lane copies one flat position,
-      // finding its range by binary search over the offsets kept in LDS
-      const int nrw = tk.j_nranges > wid ? (tk.j_nranges - wid + W - 1) / W : 0;
-      const int2* rl = a.ranges + tk.j_first + wid;
-      for (int rg = 0; rg < nrw; rg += 64) {
-        const int nr = nrw - rg < 64 ? nrw - rg : 64;
+      // the task's ranges in groups of 64, each flattened by a wave scan; wave w takes the w-th of
+      // W equal contiguous shares of every group's records, and each lane copies one flat
+      // position, finding its range by binary search over the offsets kept in LDS
+      const int2* rl = a.ranges + tk.j_first;
+      for (int rg = 0; rg < tk.j_nranges; rg += 64) {
+        const int nr = tk.j_nranges - rg < 64 ? tk.j_nranges - rg : 64;
         int2 g = make_int2(0, 0);
-        if (lane < nr) g = rl[(rg + lane) * W];
+        if (lane < nr) g = rl[rg + lane];
         int total;
         const int o = wave_excl_scan(g.y, &total);
         total = uniform(total);
         RO[lane] = lane < nr ? o : 0x7fffffff;
         RB[lane] = g.x;
         wave_sync();
-        for (int ws = 0; ws < total; ws += tile) {
-          const int cnt = total - ws < tile ? total - ws : tile;
+        const int lo = (int)((int64_t)total * wid / W), hi = (int)((int64_t)total * (wid + 1) / W);
+        for (int ws = lo; ws < hi; ws += tile) {
+          const int cnt = hi - ws < tile ? hi - ws : tile;
           const int C = (cnt + S - 1) / S;
           const int padded = S * C;
           for (int e = lane; e < padded; e += 64) {

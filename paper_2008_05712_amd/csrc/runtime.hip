@@ -101,6 +101,7 @@ struct gc_batch_ {
   bool committed = false;
   // fixed at commit: the sorted union U and the packed-space ranges and first targets
   std::vector<int32_t> hU;
+  std::vector<int32_t> h_order, h_pibeg;  // launch order of the tasks and their first packed targets
   int32_t u = 0, max_direct = 0;
   DevBuf d_tasks, d_ranges, d_nodes, d_ioff, d_joff, d_order, d_runs, d_U, pranges, pibeg;
   int32_t n_runs = 0;
@@ -119,7 +120,7 @@ struct gc_graph_ {
   gc_ctx ctx = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  DevBuf step_segs, step_rounds, step_ctr, step_fl;  // whole-step persistent schedule
+  DevBuf step_items, step_rounds, step_ctr, step_fl;  // whole-step persistent schedule
   std::vector<hipStream_t> side;   // capture-time side streams (combined passes of successive steps overlap)
   std::vector<hipEvent_t> events;
 };
@@ -474,6 +475,10 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   up(b->d_runs, runs.data(), sizeof(int32_t) * runs.size());
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors must outlive the copies
   if (e != hipSuccess) return hip_fail(c, e, "gc_batch_commit");
+  order.resize((size_t)T);
+  pib.resize((size_t)T);
+  b->h_order = std::move(order);
+  b->h_pibeg = std::move(pib);
   b->committed = true;
   b->ranks_ready = false;
   b->mode = -1;
@@ -907,12 +912,27 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   if (!acc_dev) return set_err(ctx, GC_E_INVAL, "whole-step schedule: NULL acc");
   const int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
   std::vector<StepRound> rounds((size_t)R);
-  std::vector<StepSeg> segs;
-  int32_t nt = 0;
+  std::vector<StepItem> items;
   auto seg = [&](int32_t type, int32_t round, int32_t count) {
-    if (count <= 0) return;
-    segs.push_back(StepSeg{type, round, nt, count});
-    nt += count;
+    for (int32_t i = 0; i < count; ++i) {
+      StepItem it{};
+      it.kind = type | round << 2;
+      it.idx = i;
+      if (type == kItemForce) {
+        // the round's tasks in its launch order, each with its first packed target
+        const gc_batch fb = batches[round];
+        const int32_t t = fb->h_order[(size_t)i];
+        const gc_task& tk = fb->tasks[(size_t)t];
+        it.idx = fb->h_pibeg[(size_t)t];
+        it.i_begin = tk.i_begin;
+        it.i_count = tk.i_count;
+        it.j_first = tk.j_first;
+        it.j_nranges = tk.j_nranges;
+        it.n_first = tk.n_first;
+        it.n_count = tk.n_count;
+      }
+      items.push_back(it);
+    }
   };
   for (int32_t k = 0; k < R; ++k) {
     gc_batch b = batches[k];
@@ -987,7 +1007,8 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     flimit = fixture == GC_FIXTURE_EVICT_STAGED ? std::max<int64_t>(flimit, batches[k]->u) : flimit + batches[k]->u;
   flimit = std::min<int64_t>(flimit, p->cap);
   const int64_t fl_words = 1 + (int64_t)R + std::max<int64_t>(flimit, 1);
-  hipError_t e = gr->step_segs.ensure(sizeof(StepSeg) * std::max<size_t>(segs.size(), 1));
+  const int32_t nt = (int32_t)items.size();
+  hipError_t e = gr->step_items.ensure(sizeof(StepItem) * std::max<size_t>(items.size(), 1));
   if (e == hipSuccess) e = gr->step_rounds.ensure(sizeof(StepRound) * (size_t)R);
   if (e == hipSuccess) e = gr->step_ctr.ensure(sizeof(uint64_t) * (size_t)n_ctr);
   if (e == hipSuccess) e = gr->step_fl.ensure(sizeof(uint64_t) * (size_t)fl_words);
@@ -998,7 +1019,7 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     rounds[k].reorg.ftotal = fmeta;
     rounds[k].reorg.flimit = (int32_t)flimit;
   }
-  GC_HIP(ctx, hipMemcpyAsync(gr->step_segs.p, segs.data(), sizeof(StepSeg) * segs.size(), hipMemcpyHostToDevice, s));
+  GC_HIP(ctx, hipMemcpyAsync(gr->step_items.p, items.data(), sizeof(StepItem) * items.size(), hipMemcpyHostToDevice, s));
   GC_HIP(ctx, hipMemcpyAsync(gr->step_rounds.p, rounds.data(), sizeof(StepRound) * (size_t)R, hipMemcpyHostToDevice, s));
   GC_HIP(ctx, launch_fill_i32(gr->step_ctr.as<int32_t>(), 0, 2 * (int64_t)n_ctr, s));
   GC_HIP(ctx, launch_fill_i32(gr->step_fl.as<int32_t>(), 0, 2 * fl_words, s));  // tag 0: never a launch's
@@ -1008,8 +1029,7 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   GC_HIP(ctx, step_occupancy(order, two, tile, &per));
   const int grid = std::max(1, per) * ctx->n_cu;
   StepArgs a{};
-  a.segs = gr->step_segs.as<StepSeg>();
-  a.n_segs = (int32_t)segs.size();
+  a.items = gr->step_items.as<StepItem>();
   a.n_items = nt;
   a.rounds = gr->step_rounds.as<StepRound>();
   a.n_rounds = R;
@@ -1074,7 +1094,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
     if (st != GC_OK) {
       if (gs->exec) (void)hipGraphExecDestroy(gs->exec);
       if (gs->graph) (void)hipGraphDestroy(gs->graph);
-      gs->step_segs.release();
+      gs->step_items.release();
       gs->step_rounds.release();
       gs->step_ctr.release();
       gs->step_fl.release();
@@ -1217,7 +1237,7 @@ extern "C" gc_status gc_graph_destroy(gc_graph g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
   for (hipStream_t q : g->side) (void)hipStreamDestroy(q);
-  g->step_segs.release();
+  g->step_items.release();
   g->step_rounds.release();
   g->step_ctr.release();
   g->step_fl.release();

@@ -60,6 +60,11 @@ using dev::uniform;
 // from holding the grid.
 constexpr uint32_t kStepSpinLimit = 1u << 20;
 
+// The thread that requests tickets and loads the next item: the first lane of the last wavefront,
+// which issues no global stores in a force item, so its end-of-item wait for the ticket and the
+// item covers nothing else (wavefront 0 writes the accelerations).
+constexpr int kOwner = dev::kRThreads - 64;
+
 __device__ __forceinline__ void wait_ge(uint64_t* p, uint64_t target, int32_t* err) {
   uint32_t spins = 0;
   while (dev::tload(p) < target) {
@@ -88,62 +93,24 @@ __device__ __forceinline__ uint64_t publish_done(uint64_t* ctr) {
   return old;
 }
 
-// Per-round arguments live in device memory; loaded through these, every field is marked
-// wavefront-uniform so that it stays in scalar registers.
-template <class T>
-__device__ __forceinline__ T* uni(T* p) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
-}
+// Values read from LDS by every lane, marked wavefront-uniform so that they live in scalar registers.
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
 
-__device__ __forceinline__ GravArgs load_grav(const GravArgs* g) {
-  GravArgs a;
-  a.tasks = uni(g->tasks);
-  a.n_tasks = uni(g->n_tasks);
-  a.ranges = uni(g->ranges);
-  a.ibeg = uni(g->ibeg);
-  a.ioff = uni(g->ioff);
-  a.joff = uni(g->joff);
-  a.ilist = uni(g->ilist);
-  a.jlist = uni(g->jlist);
-  a.node_idx = uni(g->node_idx);
-  a.nodes = uni(g->nodes);
-  a.rec = uni(g->rec);
-  a.acc = uni(g->acc);
-  a.G = uni(g->G);
-  a.eps2 = uni(g->eps2);
-  a.tile = uni(g->tile);
-  a.queue = uni(g->queue);
-  a.order = uni(g->order);
-  return a;
+// The per-round arguments are never written during the launch: read through the constant address
+// space, with a uniform round index they come in by scalar loads (scalar cache) into scalar registers.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* cst(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
 }
-
-__device__ __forceinline__ ReorgArgs load_reorg(const ReorgArgs* r) {
-  ReorgArgs a;
-  a.U = uni(r->U);
-  a.u = uni(r->u);
-  a.src = uni(r->src);
-  a.pool = uni(r->pool);
-  a.slot_of = uni(r->slot_of);
-  a.occ = uni(r->occ);
-  a.cap = uni(r->cap);
-  a.pack = uni(r->pack);
-  a.packed = uni(r->packed);
-  a.uslot = uni(r->uslot);
-  a.missing = uni(r->missing);
-  a.mslot = uni(r->mslot);
-  a.free_list = uni(r->free_list);
-  a.ftotal = uni(r->ftotal);
-  a.flimit = uni(r->flimit);
-  a.state = uni(r->state);
-  a.nbf = uni(r->nbf);
-  a.nbu = uni(r->nbu);
-  a.evict_after = uni(r->evict_after);
-  return a;
+template <class T>
+__device__ __forceinline__ T cload(const __attribute__((address_space(4))) T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word copy");
+  T v;
+  const __attribute__((address_space(4))) uint32_t* q = (const __attribute__((address_space(4))) uint32_t*)p;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
+  return v;
 }
 
 template <int ORDER, bool TWO>
@@ -151,51 +118,72 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
   extern __shared__ float4 smem[];
   __shared__ int sh[dev::kRThreads / 64];
   __shared__ uint32_t s_ex, s_tag;
-  __shared__ int64_t s_next, s_base, s_avail;
+  __shared__ int64_t s_base, s_avail;
+  __shared__ int64_t s_tk;                       // the block's current ticket (this launch's)
+  __shared__ __align__(16) StepItem s_item[2];   // its item and the next one, alternately
   __shared__ uint64_t s_epoch;
   const int tid = threadIdx.x;
   if (tid == 0) s_epoch = dev::tload(s.ctr + kCtrStride * kCtrEpoch);
   __syncthreads();
   const uint64_t E = s_epoch;
+  // every block takes tickets until it holds one past the last item
   const uint64_t base = E * ((uint64_t)s.n_items + gridDim.x);  // tickets taken by earlier launches
   const uint64_t goal = E + 1;
   const uint32_t ltag = (uint32_t)goal;  // tag of this launch's free-slot list words
-  uint64_t* tickets = s.ctr + kCtrStride * kCtrTickets;
-  if (tid == 0) s_next = (int64_t)(atomicAdd(reinterpret_cast<unsigned long long*>(tickets), 1ull) - base);
+  unsigned long long* tickets = reinterpret_cast<unsigned long long*>(s.ctr + kCtrStride * kCtrTickets);
+  if (tid == 0) {
+    const int64_t t0 = (int64_t)(atomicAdd(tickets, 1ull) - base);
+    s_tk = t0;
+    if (t0 < s.n_items) s_item[0] = s.items[t0];
+  }
   __syncthreads();
-  int ready = -1;  // this block has seen the reorganisation of rounds <= ready complete
+  int cb = 0;
+  int ready = -1;  // this block has seen the data parts of rounds <= ready complete
   while (true) {
-    const int64_t t = s_next;
-    __syncthreads();
+    const int64_t t = s_tk;
     if (t >= s.n_items) break;
+    const int kind = uni(s_item[cb].kind);
+    const int type = kind & 3;
+    const int k = kind >> 2;
+    const int idx = uni(s_item[cb].idx);
+    // the next ticket is requested now and its item loaded straight into the other LDS slot once
+    // the ticket is back (fetch_next, called by every thread: inside a force item once its first
+    // loads are out, else at the end); neither is waited for before the end of this item
     unsigned long long nxt = 0;
-    if (tid == 0) nxt = atomicAdd(reinterpret_cast<unsigned long long*>(tickets), 1ull);
-    int lo = 0, hi = s.n_segs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s.segs[mid].first <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    const int type = uniform(s.segs[lo].type);
-    const int k = uniform(s.segs[lo].round);
-    const int idx = uniform((int)(t - s.segs[lo].first));
-    const StepRound& R = s.rounds[k];
+    if (tid == kOwner) nxt = atomicAdd(tickets, 1ull);
+    auto fetch_next = [&] {
+      if ((tid >> 6) == (kOwner >> 6)) {
+        const uint64_t v = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(nxt >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)nxt);
+        const int64_t tn = (int64_t)(v - base);
+        if ((unsigned)(tid - kOwner) < 2u && tn < s.n_items)
+          __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(s.items + tn) + 16 * (tid - kOwner),
+                                           (void __attribute__((address_space(3)))*)&s_item[cb ^ 1], 16, 0, 0);
+      }
+    };
+    const __attribute__((address_space(4))) StepRound& R = cst(s.rounds)[k];
     int32_t* err = R.reorg.state + GC_STATE_ERR;
     uint64_t* ev_done = s.ctr + kCtrStride * (kCtrRounds + 3 * k);
     uint64_t* ch_done = ev_done + kCtrStride;
     uint64_t* dt_done = ev_done + 2 * kCtrStride;
     const int pr = uniform(R.prev);
     if (type == kItemForce) {
-      if (k > ready) {
-        if (tid == 0) wait_ge(dt_done, goal * (uint64_t)R.reorg.nbu, err);
-        __syncthreads();
-        ready = k;
-      }
-      const GravArgs ga = load_grav(&R.grav);
-      dev::grav_task<ORDER, false, TWO>(ga, uniform(ga.order[idx]), smem);
+      const GravArgs ga = cload(&R.grav);
+      const dev::TaskDesc td{uni(s_item[cb].i_begin), uni(s_item[cb].i_count), uni(s_item[cb].j_first),
+                             uni(s_item[cb].j_nranges), uni(s_item[cb].n_first), uni(s_item[cb].n_count), idx};
+      const uint32_t nbu = R.reorg.nbu;
+      // the round's packed records are read only once its data parts are done
+      dev::grav_task<ORDER, false, TWO>(ga, 0, td, smem, [&] {
+        if (k > ready) {
+          if (tid == 0) wait_ge(dt_done, goal * (uint64_t)nbu, err);
+          __syncthreads();
+          ready = k;
+        }
+        fetch_next();
+      });
     } else if (type == kItemEvict) {
       __builtin_amdgcn_s_setprio(3);
-      if (tid == 0 && pr >= 0) wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 1), goal * (uint64_t)s.rounds[pr].n_chain, err);
+      if (tid == 0 && pr >= 0) wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 1), goal * (uint64_t)cst(s.rounds)[pr].n_chain, err);
       __syncthreads();
       const int64_t n = min(dev::iload(const_cast<int32_t*>(R.ev_n)), R.ev_bound);
       const int64_t first = (int64_t)idx * kEvictBlock;
@@ -203,28 +191,29 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
       dev::evict_range<true>(R.ev_ids, first, last, R.reorg.slot_of, R.n_ids, R.reorg.occ);
       (void)publish_done(ev_done);
       __builtin_amdgcn_s_setprio(0);
+      fetch_next();
     } else {
       // reorganisation items are on the critical path of the step and latency-bound: their waves
       // issue ahead of the force waves sharing the CU
       __builtin_amdgcn_s_setprio(3);
-      const ReorgArgs ra = load_reorg(&R.reorg);
+      const ReorgArgs ra = cload(&R.reorg);
       int32_t ids[dev::kUItems];
       if (type == kItemUnion) dev::union_ids(ra, idx, ids);  // static: loaded while the dependencies finish
       if (tid == 0) {
         wait_ge(ev_done, goal * (uint64_t)R.n_evict, err);
         int64_t fbase = 0, favail = -1;
         if (pr >= 0) {
-          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 1), goal * (uint64_t)s.rounds[pr].n_chain, err);
+          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 1), goal * (uint64_t)cst(s.rounds)[pr].n_chain, err);
           // round 0 is complete: the launch's free count is known; this round's offset into the list is
           // the previous one plus what that round took and kept
           const uint64_t ft = dev::tload(s.fmeta);
           if ((uint32_t)(ft >> 32) != ltag) dev::istore(err, 1);
           const int64_t F = (int64_t)(ft & 0x7fffffffu);
-          if (!ra.evict_after && s.rounds[pr].reorg.nbu > 0) {
+          if (!ra.evict_after && cst(s.rounds)[pr].reorg.nbu > 0) {
             const uint64_t bw = dev::tload(s.fmeta + 1 + pr);
             if ((uint32_t)(bw >> 32) != ltag) dev::istore(err, 1);
             const int64_t bp = (int64_t)(bw & 0x7fffffffu);
-            const int64_t mp = dev::iload(s.rounds[pr].reorg.state + GC_STATE_MISSING);
+            const int64_t mp = dev::iload(cst(s.rounds)[pr].reorg.state + GC_STATE_MISSING);
             const int64_t avail = F - bp > 0 ? F - bp : 0;
             fbase = bp + (mp < avail ? mp : avail);
           }
@@ -253,15 +242,20 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
         if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
         // data part: after the previous round's (its staging may be read here, its slots reused)
         if (tid == 0 && pr >= 0)
-          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 2), goal * (uint64_t)s.rounds[pr].reorg.nbu, err);
+          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 2), goal * (uint64_t)cst(s.rounds)[pr].reorg.nbu, err);
         __syncthreads();
         dev::union_data(ra, idx, ids, slot, fm);
         (void)publish_done(dt_done);
       }
       __builtin_amdgcn_s_setprio(0);
+      fetch_next();
     }
-    if (tid == 0) s_next = (int64_t)(nxt - base);
+    if (tid == kOwner) {
+      __builtin_amdgcn_s_waitcnt(0);  // the next item has landed in LDS
+      s_tk = (int64_t)(nxt - base);
+    }
     __syncthreads();
+    cb ^= 1;
   }
   if (tid == 0 && atomicAdd(reinterpret_cast<unsigned long long*>(s.ctr + kCtrStride * kCtrExits), 1ull) + 1 ==
                       goal * gridDim.x)

@@ -39,7 +39,8 @@ __global__ void __launch_bounds__(512) k_grav(GravArgs a) {
     const gc_task g = a.tasks[t];
     const dev::TaskDesc td{uniform(g.i_begin), uniform(g.i_count), uniform(g.j_first), uniform(g.j_nranges),
                            uniform(g.n_first), uniform(g.n_count), uniform(a.ibeg ? a.ibeg[t] : g.i_begin)};
-    grav_task<ORDER, LISTS, TWO>(a, t, td, smem, [] {});
+    dev::NodePrefetch<ORDER> pf;
+    grav_task<ORDER, LISTS, TWO>(a, t, td, smem, pf, false, [] {}, [](int) {});
   }
 }
 

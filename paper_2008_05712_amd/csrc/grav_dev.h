@@ -211,6 +211,26 @@ __device__ __forceinline__ void store_node(float4* L, int e, const NodeRegs<ORDE
   }
 }
 
+// The first node tile of a task for the calling wavefront (nodes w, w + W, ... of the task's list):
+// the records in registers, one node per lane, and the index of the node 64 entries on.
+template <int ORDER>
+struct NodePrefetch {
+  NodeRegs<ORDER> cur;
+  int idx_next;
+};
+
+template <int ORDER>
+__device__ __forceinline__ void node_prefetch(const float4* __restrict__ nodes, const int* __restrict__ node_idx,
+                                              int n_first, int n_count, NodePrefetch<ORDER>& pf) {
+  const int lane = threadIdx.x & 63;
+  const int wid = uniform(threadIdx.x >> 6);
+  const int W = blockDim.x >> 6;
+  const int nw = n_count > wid ? (n_count - wid + W - 1) / W : 0;
+  const int* nl = node_idx + n_first + wid;
+  pf.idx_next = (64 < nw && 64 + lane < nw) ? nl[(64 + lane) * W] : -1;
+  pf.cur = load_node<ORDER>(nodes, lane < nw ? nl[lane * W] : -1);
+}
+
 // Records of LDS per wavefront for a direct tile of `tile` records: the larger of a direct tile
 // (+64 padding) and a quadrupole node tile (3 records per node), plus 96 records of reduction
 // scratch.
@@ -232,11 +252,16 @@ struct TaskDesc {
 // i_count); S = floor(64 / h) slices.  The per-target sums are reduced across slices within each
 // wave and then across the W waves, in a fixed order.  `smem` is the block's dynamic LDS of
 // W * grav_lds_per_wave(tile) records; the call starts and ends with every wave of the block
-// converged (it contains block barriers).  ready() is called by every thread once the first node
-// tile's loads are out and before any record is read (the records may still be being written).
-template <int ORDER, bool LISTS, bool TWO, class Ready>
+// converged (it contains block barriers).  pf holds the task's first node tile when `have_pf`
+// (loaded ahead by the caller), else it is loaded here.  ready() is called by every thread once the
+// first node tile's loads are out and before any record is read (the records may still be being
+// written).  In the last target chunk next(0) and, after a block barrier, next(1) are called by
+// every thread before the cross-wave sum; next(1) may load the following task's first node tile
+// into pf.  The last barrier is the caller's: it must sync the block before the LDS is reused.
+template <int ORDER, bool LISTS, bool TWO, class Ready, class Next>
 __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const TaskDesc& tk,
-                                          float4* __restrict__ smem, Ready&& ready) {
+                                          float4* __restrict__ smem, NodePrefetch<ORDER>& pf, bool have_pf,
+                                          Ready&& ready, Next&& next) {
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
   const int W = blockDim.x >> 6;
@@ -252,14 +277,11 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
   // this wave's nodes; the first tile does not depend on the records, so its loads go out first
   const int nw = tk.n_count > wid ? (tk.n_count - wid + W - 1) / W : 0;
   const int* nl = a.node_idx + tk.n_first + wid;
-  int idx_next = (64 < nw && 64 + lane < nw) ? nl[(64 + lane) * W] : -1;
-  NodeRegs<ORDER> cur = load_node<ORDER>(a.nodes, lane < nw ? nl[lane * W] : -1);
+  if (!have_pf) node_prefetch<ORDER>(a.nodes, a.node_idx, tk.n_first, tk.n_count, pf);
   ready();
   for (int i0 = 0; i0 < ic; i0 += 64) {
-    if (i0 > 0) {
-      idx_next = (64 < nw && 64 + lane < nw) ? nl[(64 + lane) * W] : -1;
-      cur = load_node<ORDER>(a.nodes, lane < nw ? nl[lane * W] : -1);
-    }
+    if (i0 > 0) node_prefetch<ORDER>(a.nodes, a.node_idx, tk.n_first, tk.n_count, pf);
+    const bool last = i0 + 64 >= ic;
     const int icc = ic - i0 < 64 ? ic - i0 : 64;
     const int h = TWO ? (icc + 1) >> 1 : icc;
     const int S = 64 / h;
@@ -301,13 +323,13 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
         const int cnt = nw - nb < kNodeTile ? nw - nb : kNodeTile;
         const int C = (cnt + S - 1) / S;
         const int padded = S * C;
-        store_node<ORDER>(L, lane, cur);  // entries >= cnt are zero records
+        store_node<ORDER>(L, lane, pf.cur);  // entries >= cnt are zero records
         for (int e = 64 + lane; e < padded; e += 64) store_node<ORDER>(L, e, load_node<ORDER>(a.nodes, -1));
         // prefetch the next tile's records and the index of the one after
         if (nb + kNodeTile < nw) {
-          cur = load_node<ORDER>(a.nodes, idx_next);
+          pf.cur = load_node<ORDER>(a.nodes, pf.idx_next);
           const int e2 = nb + 2 * kNodeTile + lane;
-          idx_next = e2 < nw ? nl[e2 * W] : -1;
+          pf.idx_next = e2 < nw ? nl[e2 * W] : -1;
         }
         wave_sync();
         // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
@@ -406,7 +428,9 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
       red[3 * lane + 1] = sy;
       red[3 * lane + 2] = sz;
     }
+    if (last) next(0);
     __syncthreads();
+    if (last) next(1);
     if (wid == 0 && lane < icc) {
       double tx = 0.0, ty = 0.0, tz = 0.0;
       for (int w = 0; w < W; ++w) {
@@ -415,7 +439,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
       }
       a.acc[tk.i_begin + i0 + lane] = make_float4((float)(a.G * tx), (float)(a.G * ty), (float)(a.G * tz), 0.f);
     }
-    __syncthreads();
+    if (!last) __syncthreads();
   }
 }
 

@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
   __shared__ int sh[dev::kRThreads / 64];
   __shared__ uint32_t s_ex, s_tag;
   __shared__ int64_t s_base, s_avail;
-  __shared__ int64_t s_tk;                       // the block's current ticket (this launch's)
+  __shared__ int64_t s_tk, s_tn;                 // the block's current ticket and the next (this launch's)
   __shared__ __align__(16) StepItem s_item[2];   // its item and the next one, alternately
   __shared__ uint64_t s_epoch;
   const int tid = threadIdx.x;
@@ -139,6 +139,12 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
   __syncthreads();
   int cb = 0;
   int ready = -1;  // this block has seen the data parts of rounds <= ready complete
+  // a force item followed by a force item loads the next one's first node tile and (thread 0) its
+  // round's data-part count while it finishes
+  dev::NodePrefetch<ORDER> pf;
+  bool have_pf = false;
+  int poll_k = -1;
+  uint64_t poll_v = 0;
   while (true) {
     const int64_t t = s_tk;
     if (t >= s.n_items) break;
@@ -171,16 +177,39 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
       const GravArgs ga = cload(&R.grav);
       const dev::TaskDesc td{uni(s_item[cb].i_begin), uni(s_item[cb].i_count), uni(s_item[cb].j_first),
                              uni(s_item[cb].j_nranges), uni(s_item[cb].n_first), uni(s_item[cb].n_count), idx};
-      const uint32_t nbu = R.reorg.nbu;
+      const uint64_t target = goal * (uint64_t)R.reorg.nbu;
+      bool pf_next = false;
       // the round's packed records are read only once its data parts are done
-      dev::grav_task<ORDER, false, TWO>(ga, 0, td, smem, [&] {
+      dev::grav_task<ORDER, false, TWO>(ga, 0, td, smem, pf, have_pf, [&] {
         if (k > ready) {
-          if (tid == 0) wait_ge(dt_done, goal * (uint64_t)nbu, err);
+          if (tid == 0 && !(poll_k == k && poll_v >= target)) wait_ge(dt_done, target, err);
           __syncthreads();
           ready = k;
         }
         fetch_next();
+      }, [&](int phase) {
+        if (phase == 0) {
+          if (tid == kOwner) {
+            __builtin_amdgcn_s_waitcnt(0);  // the next item has landed in LDS
+            s_tn = (int64_t)(nxt - base);
+          }
+          return;
+        }
+        const int64_t t2 = s_tn;
+        if (t2 >= s.n_items) return;
+        const int kind2 = uni(s_item[cb ^ 1].kind);
+        if ((kind2 & 3) != kItemForce) return;
+        const int k2 = kind2 >> 2;
+        const __attribute__((address_space(4))) StepRound& R2 = cst(s.rounds)[k2];
+        dev::node_prefetch<ORDER>(R2.grav.nodes, R2.grav.node_idx, uni(s_item[cb ^ 1].n_first),
+                                  uni(s_item[cb ^ 1].n_count), pf);
+        pf_next = true;
+        if (tid == 0 && k2 > ready) {
+          poll_k = k2;
+          poll_v = dev::tload(s.ctr + kCtrStride * (kCtrRounds + 3 * k2 + 2));
+        }
       });
+      have_pf = pf_next;
     } else if (type == kItemEvict) {
       __builtin_amdgcn_s_setprio(3);
       if (tid == 0 && pr >= 0) wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 1), goal * (uint64_t)cst(s.rounds)[pr].n_chain, err);

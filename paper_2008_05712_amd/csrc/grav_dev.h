@@ -246,8 +246,8 @@ struct TaskDesc {
 };
 
 // One task on one workgroup of W = blockDim.x / 64 wavefronts.  Wave w takes the task's nodes
-// w, w + W, ... and the w-th of W equal contiguous shares of its direct records (address lists:
-// windows w, w + W, ...), so W waves share one task's lists.  Within a wave the lanes are (lane-target j) x (slice s): with
+// w, w + W, ... and the w-th of W contiguous, nearly equal shares of its direct records (address
+// lists: windows w, w + W, ...), so W waves share one task's lists.  Within a wave the lanes are (lane-target j) x (slice s): with
 // TWO each lane carries targets j and j + h (h = ceil(i_count / 2)), otherwise target j (h =
 // i_count); S = floor(64 / h) slices.  The per-target sums are reduced across slices within each
 // wave and then across the W waves, in a fixed order.  `smem` is the block's dynamic LDS of
@@ -288,6 +288,9 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
     const int il = lane % h;
     const int sl = lane / h;
     const bool active = sl < S;
+    // tiles hold a multiple of S records, so that only a share's last tile is padded
+    const int NT = S * (kNodeTile / S);  // nodes per node tile
+    const int DT = S * (tile / S);       // records per direct tile
     const int ib = il + h < icc ? il + h : il;  // TWO: second target (a copy of the first if absent)
     float3 A = make_float3(0.f, 0.f, 0.f), B = A;
     if (active) {
@@ -319,17 +322,18 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
 
     // ---- node terms: this wave's nodes are list entries w, w + W, ...
     {
-      for (int nb = 0; nb < nw; nb += kNodeTile) {
-        const int cnt = nw - nb < kNodeTile ? nw - nb : kNodeTile;
+      // the prefetched first tile holds nodes 0..63 and the index of node 64 + lane; with NT < 64
+      // its lanes >= NT are left out and the next tile starts at node NT
+      if (NT < kNodeTile) pf.idx_next = (lane < NT && NT + lane < nw) ? nl[(NT + lane) * W] : -1;
+      for (int nb = 0; nb < nw; nb += NT) {
+        const int cnt = nw - nb < NT ? nw - nb : NT;
         const int C = (cnt + S - 1) / S;
-        const int padded = S * C;
-        store_node<ORDER>(L, lane, pf.cur);  // entries >= cnt are zero records
-        for (int e = 64 + lane; e < padded; e += 64) store_node<ORDER>(L, e, load_node<ORDER>(a.nodes, -1));
+        store_node<ORDER>(L, lane, lane < cnt ? pf.cur : load_node<ORDER>(a.nodes, -1));  // padding: zero records
         // prefetch the next tile's records and the index of the one after
-        if (nb + kNodeTile < nw) {
+        if (nb + NT < nw) {
           pf.cur = load_node<ORDER>(a.nodes, pf.idx_next);
-          const int e2 = nb + 2 * kNodeTile + lane;
-          pf.idx_next = e2 < nw ? nl[e2 * W] : -1;
+          const int e2 = nb + 2 * NT + lane;
+          pf.idx_next = (lane < NT && e2 < nw) ? nl[e2 * W] : -1;
         }
         wave_sync();
         // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
@@ -341,8 +345,8 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
     // ---- direct terms
     if (LISTS) {
       const int jb = a.joff[t], jn = a.joff[t + 1] - jb;
-      for (int ws = wid * tile; ws < jn; ws += W * tile) {
-        const int cnt = jn - ws < tile ? jn - ws : tile;
+      for (int ws = wid * DT; ws < jn; ws += W * DT) {
+        const int cnt = jn - ws < DT ? jn - ws : DT;
         const int C = (cnt + S - 1) / S;
         const int padded = S * C;
         for (int e = lane; e < padded; e += 64) {
@@ -356,7 +360,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
       }
     } else {
       // the task's ranges in groups of 64, each flattened by a wave scan; wave w takes the w-th of
-      // W equal contiguous shares of every group's records, and each lane copies one flat
+      // W contiguous, nearly equal shares of every group's records, and each lane copies one flat
       // position, finding its range by binary search over the offsets kept in LDS
       const int2* rl = a.ranges + tk.j_first;
       for (int rg = 0; rg < tk.j_nranges; rg += 64) {
@@ -369,9 +373,11 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
         RO[lane] = lane < nr ? o : 0x7fffffff;
         RB[lane] = g.x;
         wave_sync();
-        const int lo = (int)((int64_t)total * wid / W), hi = (int)((int64_t)total * (wid + 1) / W);
-        for (int ws = lo; ws < hi; ws += tile) {
-          const int cnt = hi - ws < tile ? hi - ws : tile;
+        // share boundaries rounded down to multiples of S (the last share ends at the total)
+        const int lo = (int)((int64_t)total * wid / W / S) * S;
+        const int hi = wid + 1 == W ? total : (int)((int64_t)total * (wid + 1) / W / S) * S;
+        for (int ws = lo; ws < hi; ws += DT) {
+          const int cnt = hi - ws < DT ? hi - ws : DT;
           const int C = (cnt + S - 1) / S;
           const int padded = S * C;
           for (int e = lane; e < padded; e += 64) {

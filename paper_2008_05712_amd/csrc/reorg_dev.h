@@ -394,13 +394,23 @@ __device__ __forceinline__ void union_data(const ReorgArgs& a, int b, const int3
 template <bool COH>
 __device__ __forceinline__ void evict_range(const int32_t* __restrict__ ids, int64_t first, int64_t last,
                                             int32_t* __restrict__ slot_of, int32_t n_ids, uint32_t* __restrict__ occ) {
-  for (int64_t k = first + threadIdx.x; k < last; k += blockDim.x) {
-    const int32_t id = ld_i32<COH>(ids + k);
-    if (id < 0 || id >= n_ids) continue;
-    const int32_t s = ld_i32<COH>(slot_of + id);
-    if (s < 0) continue;
-    slot_of[id] = -1;
-    occ[s] = 0u;
+  // eight ids per thread per pass, their loads and then their table loads all in flight at once
+  constexpr int kPer = 8;
+  for (int64_t k0 = first + threadIdx.x; k0 < last; k0 += (int64_t)kPer * blockDim.x) {
+    int32_t id[kPer], sl[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int64_t k = k0 + (int64_t)i * blockDim.x;
+      id[i] = k < last ? ld_i32<COH>(ids + k) : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) sl[i] = (id[i] >= 0 && id[i] < n_ids) ? ld_i32<COH>(slot_of + id[i]) : -1;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+      if (sl[i] >= 0) {
+        slot_of[id[i]] = -1;
+        occ[sl[i]] = 0u;
+      }
   }
 }
 

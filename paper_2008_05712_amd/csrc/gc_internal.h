@@ -125,13 +125,12 @@ hipError_t launch_lj_finish(float4* acc, const float* mass_t, const float4* rec_
 // ---------------------------------------------------------------- whole-step persistent kernel
 
 // Work items of one step, in ticket order; see step.hip.
-enum { kItemEvict = 0, kItemFree = 1, kItemUnion = 2, kItemForce = 3 };
-constexpr int kEvictBlock = 2048;  // ids per eviction item
+enum { kItemFree = 1, kItemUnion = 2, kItemForce = 3 };
 // One work item, by ticket (32 bytes: a block loads the next one straight into LDS while it runs
 // the current one).
 struct StepItem {
   int32_t kind;  // item type | round << 2
-  int32_t idx;   // eviction, free-scan and union items: block index within the round's role;
+  int32_t idx;   // free-scan and union items: block index within the round's role;
                  // force items: the task's first packed target
   int32_t i_begin, i_count, j_first, j_nranges, n_first, n_count;  // force items: the task
 };
@@ -139,11 +138,6 @@ static_assert(sizeof(StepItem) == 32, "StepItem is loaded as two 16-byte pieces"
 struct StepRound {
   GravArgs grav;          // the round's combined pass over its packed records
   ReorgArgs reorg;        // the round's reorganisation (nbf: free-scan items, 0 after round 0; nbu)
-  const int32_t* ev_ids;  // ids evicted before the round (missing list of the round before), or null
-  const int32_t* ev_n;    // their count (device)
-  int32_t ev_bound;       // bound of that count (entries of ev_ids)
-  int32_t n_ids;
-  int32_t n_evict;        // eviction items of the round
   int32_t n_chain;        // free-slot + union items of the round
   int32_t prev;           // the latest earlier round with chain items (-1: none)
 };
@@ -159,8 +153,8 @@ struct StepArgs {
 };
 constexpr int kCtrStride = 32;  // one 256-byte line per step counter
 constexpr int kCtrTickets = 0, kCtrExits = 1, kCtrEpoch = 2, kCtrRounds = 3;  // then per round r:
-                                // kCtrRounds + 3r eviction items done, + 1 table parts (free-scan and
-                                // union items) done, + 2 data parts (union items) done
+                                // kCtrRounds + 2r table parts (free-scan and union items) done,
+                                // + 1 data parts (union items) done
 constexpr int kStepLead = 2;    // rounds by which the reorganisation items precede the passes
 hipError_t launch_step(int order, bool two, const StepArgs& a, int grid, int tile, hipStream_t s);
 hipError_t step_occupancy(int order, bool two, int tile, int* blocks);

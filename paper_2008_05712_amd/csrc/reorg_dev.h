@@ -1,7 +1,7 @@
 // Device code of the reorganisation (Sec. 3.2), shared by the per-batch
-// kernels and the whole-step persistent kernel: the tagged single-pass scans,
-// the free-slot and union (lookup, slot assignment, staging, packing) roles of
-// a block, and eviction.
+// kernels and the whole-step persistent kernel: the tagged single-pass scans
+// and the free-slot and union (lookup, slot assignment, staging, packing)
+// roles of a block.
 //
 // Inside the whole-step kernel (COH = true) other blocks change the chare
 // table, the occupancy flags and the pool between rounds, and the L2 of one XCD
@@ -386,31 +386,6 @@ __device__ __forceinline__ void union_data(const ReorgArgs& a, int b, const int3
     if (k >= a.u) continue;
     a.packed[k] = v[i];
     if (((fm >> i) & 1u) && slot[i] >= 0) a.pool[slot[i]] = v[i];
-  }
-}
-
-// Eviction of ids[first, last) by the calling block: each resident id leaves the table and its slot
-// is freed.  Ids outside [0, n_ids) and ids not resident are skipped.
-template <bool COH>
-__device__ __forceinline__ void evict_range(const int32_t* __restrict__ ids, int64_t first, int64_t last,
-                                            int32_t* __restrict__ slot_of, int32_t n_ids, uint32_t* __restrict__ occ) {
-  // eight ids per thread per pass, their loads and then their table loads all in flight at once
-  constexpr int kPer = 8;
-  for (int64_t k0 = first + threadIdx.x; k0 < last; k0 += (int64_t)kPer * blockDim.x) {
-    int32_t id[kPer], sl[kPer];
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-      const int64_t k = k0 + (int64_t)i * blockDim.x;
-      id[i] = k < last ? ld_i32<COH>(ids + k) : -1;
-    }
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) sl[i] = (id[i] >= 0 && id[i] < n_ids) ? ld_i32<COH>(slot_of + id[i]) : -1;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i)
-      if (sl[i] >= 0) {
-        slot_of[id[i]] = -1;
-        occ[sl[i]] = 0u;
-      }
   }
 }
 

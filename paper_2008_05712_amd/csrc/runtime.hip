@@ -972,34 +972,22 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     r.nbu = union_blocks(b->u);
     // the free slots are scanned in round 0 only; later rounds read that list at an offset
     r.nbf = k == 0 ? free_blocks(p->cap) : 0;
-    sr.n_ids = p->n_ids;
     sr.n_chain = r.nbu + r.nbf;
     sr.prev = -1;
     for (int32_t q = k - 1; q >= 0 && sr.prev < 0; --q)
       if (rounds[q].n_chain > 0) sr.prev = q;
-    sr.n_evict = 0;
-    sr.ev_ids = nullptr;
-    sr.ev_n = nullptr;
-    sr.ev_bound = 0;
-    // the evicting fixture: each round's union blocks evict what they staged as soon as they have
-    // packed it (the same table updates as an eviction before the next round, off its critical path);
-    // round 0 first evicts what the previous launch's last round left (nothing, with this fixture)
+    // the evicting fixture: each round's union blocks evict what they stage (the same table updates
+    // as an eviction before the next round, off its critical path); what the previous launch's last
+    // round left (nothing, unless the pool was used between launches) is evicted by a kernel before
+    // the launch
     r.evict_after = fixture == GC_FIXTURE_EVICT_STAGED ? 1 : 0;
-    if (fixture == GC_FIXTURE_EVICT_STAGED && k == 0) {
-      gc_batch pb = batches[R - 1];
-      sr.ev_ids = pb->missing.as<int32_t>();
-      sr.ev_n = pb->state.as<int32_t>() + GC_STATE_MISSING;
-      sr.ev_bound = std::max<int32_t>(pb->u, 1);
-      sr.n_evict = (sr.ev_bound + kEvictBlock - 1) / kEvictBlock;
-    }
-    seg(kItemEvict, k, sr.n_evict);
     seg(kItemFree, k, r.nbf);
     seg(kItemUnion, k, r.nbu);
     if (k >= kStepLead) seg(kItemForce, k - kStepLead, (int32_t)batches[k - kStepLead]->tasks.size());
   }
   for (int32_t k = std::max<int32_t>(R - kStepLead, 0); k < R; ++k)
     seg(kItemForce, k, (int32_t)batches[k]->tasks.size());
-  const int32_t n_ctr = kCtrStride * (kCtrRounds + 3 * R);
+  const int32_t n_ctr = kCtrStride * (kCtrRounds + 2 * R);
   // the launch's free-slot list: entries up to the most any round can reach (with the evicting
   // fixture every round reads from the start of the list, otherwise after what earlier rounds kept)
   int64_t flimit = 0;
@@ -1037,7 +1025,13 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   a.fmeta = fmeta;
   hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamBeginCapture");
-  hipError_t le = launch_step(order, two, a, grid, tile, s);
+  hipError_t le = hipSuccess;
+  if (fixture == GC_FIXTURE_EVICT_STAGED) {
+    const gc_batch pb = batches[R - 1];
+    le = launch_evict(pb->missing.as<int32_t>(), pb->state.as<int32_t>() + GC_STATE_MISSING, std::max<int32_t>(pb->u, 1),
+                      p->slot_of.as<int32_t>(), p->n_ids, p->occ.as<uint32_t>(), s);
+  }
+  if (le == hipSuccess) le = launch_step(order, two, a, grid, tile, s);
   hipGraph_t g = nullptr;
   ce = hipStreamEndCapture(s, &g);
   if (le != hipSuccess || ce != hipSuccess) {

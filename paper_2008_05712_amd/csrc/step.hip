@@ -1,11 +1,13 @@
 // Whole-step persistent kernel (the batched form): one launch runs every round
-// of a step -- the eviction of the previous round's staging, the round's
-// reorganisation (free-slot scan, chare-table lookup, slot assignment, staging,
-// packing; Sec. 3.2) and its combined force pass (Sec. 3.1) -- so the rounds
-// need no kernel boundaries and the passes of consecutive rounds overlap.
+// of a step -- the round's reorganisation (free-slot scan, chare-table lookup,
+// slot assignment, staging, packing, and with the evicting fixture the
+// eviction of what it staged; Sec. 3.2) and its combined force pass
+// (Sec. 3.1) -- so the rounds need no kernel boundaries and the passes of
+// consecutive rounds overlap.  (The eviction of what the previous step's last
+// round left staged runs as a small kernel before the launch.)
 //
 // Work items are numbered in ticket order:
-//   evict(0) free(0) union(0) union(1) union(2) force(0) union(3) force(1) ...
+//   free(0) union(0) union(1) union(2) force(0) union(3) force(1) ...
 //   union(R-1) force(R-3) force(R-2) force(R-1)
 // so the reorganisation chain runs two rounds ahead of the force passes (the
 // chain is sequential -- each round's lookup sees the pool as the round before
@@ -23,11 +25,9 @@
 // records into their slots), counted separately.  A block takes tickets from a
 // device counter (the next one is requested while the current item runs) and
 // waits only for items with smaller tickets:
-//   evict(0)          no wait;
-//   free(0) union(r)  table parts wait for evict(r) and the table parts of the
-//                     previous round with chain items; inside round 0 on the
-//                     free-slot list and look-back words as in the per-batch
-//                     kernel;
+//   free(0) union(r)  table parts wait for the table parts of the previous
+//                     round with chain items; inside round 0 on the free-slot
+//                     list and look-back words as in the per-batch kernel;
 //   union(r) data     waits for the previous round's data parts (pool records
 //                     it stages may be read or its slots reused);
 //   force(r)          waits for the data parts of round r.
@@ -169,9 +169,8 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
     };
     const __attribute__((address_space(4))) StepRound& R = cst(s.rounds)[k];
     int32_t* err = R.reorg.state + GC_STATE_ERR;
-    uint64_t* ev_done = s.ctr + kCtrStride * (kCtrRounds + 3 * k);
-    uint64_t* ch_done = ev_done + kCtrStride;
-    uint64_t* dt_done = ev_done + 2 * kCtrStride;
+    uint64_t* ch_done = s.ctr + kCtrStride * (kCtrRounds + 2 * k);
+    uint64_t* dt_done = ch_done + kCtrStride;
     const int pr = uniform(R.prev);
     if (type == kItemForce) {
       const GravArgs ga = cload(&R.grav);
@@ -206,21 +205,10 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
         pf_next = true;
         if (tid == 0 && k2 > ready) {
           poll_k = k2;
-          poll_v = dev::tload(s.ctr + kCtrStride * (kCtrRounds + 3 * k2 + 2));
+          poll_v = dev::tload(s.ctr + kCtrStride * (kCtrRounds + 2 * k2 + 1));
         }
       });
       have_pf = pf_next;
-    } else if (type == kItemEvict) {
-      __builtin_amdgcn_s_setprio(3);
-      if (tid == 0 && pr >= 0) wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 1), goal * (uint64_t)cst(s.rounds)[pr].n_chain, err);
-      __syncthreads();
-      const int64_t n = min(dev::iload(const_cast<int32_t*>(R.ev_n)), R.ev_bound);
-      const int64_t first = (int64_t)idx * kEvictBlock;
-      const int64_t last = first + kEvictBlock < n ? first + kEvictBlock : n;
-      dev::evict_range<true>(R.ev_ids, first, last, R.reorg.slot_of, R.n_ids, R.reorg.occ);
-      (void)publish_done(ev_done);
-      __builtin_amdgcn_s_setprio(0);
-      fetch_next();
     } else {
       // reorganisation items are on the critical path of the step and latency-bound: their waves
       // issue ahead of the force waves sharing the CU
@@ -229,10 +217,9 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
       int32_t ids[dev::kUItems];
       if (type == kItemUnion) dev::union_ids(ra, idx, ids);  // static: loaded while the dependencies finish
       if (tid == 0) {
-        wait_ge(ev_done, goal * (uint64_t)R.n_evict, err);
         int64_t fbase = 0, favail = -1;
         if (pr >= 0) {
-          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 1), goal * (uint64_t)cst(s.rounds)[pr].n_chain, err);
+          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 2 * pr), goal * (uint64_t)cst(s.rounds)[pr].n_chain, err);
           // round 0 is complete: the launch's free count is known; this round's offset into the list is
           // the previous one plus what that round took and kept
           const uint64_t ft = dev::tload(s.fmeta);
@@ -271,7 +258,7 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
         if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
         // data part: after the previous round's (its staging may be read here, its slots reused)
         if (tid == 0 && pr >= 0)
-          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 3 * pr + 2), goal * (uint64_t)cst(s.rounds)[pr].reorg.nbu, err);
+          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 2 * pr + 1), goal * (uint64_t)cst(s.rounds)[pr].reorg.nbu, err);
         __syncthreads();
         dev::union_data(ra, idx, ids, slot, fm);
         (void)publish_done(dt_done);

@@ -274,7 +274,7 @@ def main():
     ap.add_argument("--waves", type=int, default=4)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--targets-per-lane", type=int, default=0, help="with --tile: 1 or 2 targets per lane")
-    ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 320 and 384")
+    ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 256, 320 and 384")
     ap.add_argument("--step-tpl", type=int, default=0, help="fixed targets per lane of the whole-step launch instead of timing 1 and 2")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -395,7 +395,7 @@ def main():
     forms["round_graph_ms"] = round(time_kernel(lambda: round_graph.launch(stream=stream), stream, reps=10), 4)
     sprm, step_graph, step_shapes, best_ms = None, None, {}, None
     if mode == gc.REORG_PACK:
-        for tl in ((args.step_tile,) if args.step_tile else (320, 384)):
+        for tl in ((args.step_tile,) if args.step_tile else (256, 320, 384)):
             for tp in ((args.step_tpl,) if args.step_tpl else (1, 2)):
                 p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=gc.SCHED_STEP, tile=tl, targets_per_lane=tp)
                 g = capture("step", p)

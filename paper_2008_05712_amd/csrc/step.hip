@@ -114,7 +114,7 @@ __device__ __forceinline__ T cload(const __attribute__((address_space(4))) T* p)
 }
 
 template <int ORDER, bool TWO>
-__global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_per_eu(TWO ? 4 : 5))) k_step(StepArgs s) {
+__global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_per_eu(5))) k_step(StepArgs s) {
   extern __shared__ float4 smem[];
   __shared__ int sh[dev::kRThreads / 64];
   __shared__ uint32_t s_ex, s_tag;

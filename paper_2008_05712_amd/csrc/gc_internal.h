@@ -155,7 +155,7 @@ constexpr int kCtrStride = 32;  // one 256-byte line per step counter
 constexpr int kCtrTickets = 0, kCtrExits = 1, kCtrEpoch = 2, kCtrRounds = 3;  // then per round r:
                                 // kCtrRounds + 2r table parts (free-scan and union items) done,
                                 // + 1 data parts (union items) done
-constexpr int kStepLead = 2;    // rounds by which the reorganisation items precede the passes
+constexpr int kStepLead = 3;    // rounds by which the reorganisation items precede the passes
 hipError_t launch_step(int order, bool two, const StepArgs& a, int grid, int tile, hipStream_t s);
 hipError_t step_occupancy(int order, bool two, int tile, int* blocks);
 

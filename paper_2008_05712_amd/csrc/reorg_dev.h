@@ -211,10 +211,11 @@ __device__ __forceinline__ uint32_t union_lookup(const ReorgArgs& a, int b, cons
 }
 
 // Entry j of the free-slot list for the missing entries of mask fm, in order from list index r0
-// (entries carry `ltag` once listed; *ftotal, once it carries `ltag`, bounds the list): one probe
-// for all of them in flight, then a bounded wait that re-probes those still unlisted.  Writes the
-// slot (or -1: the pool has no free slot for it) into slot[i] for each missing i.
-__device__ __forceinline__ void union_probe(uint64_t* flist, uint64_t* ftotal, uint32_t ltag, int64_t r0,
+// (entries carry `ltag` once listed; *ftotal, once it carries `ltag`, bounds the list; the list
+// holds `lim` entries, and an index at or beyond it is past the pool's free slots): one probe for
+// all of them in flight, then a bounded wait that re-probes those still unlisted.  Writes the slot
+// (or -1: the pool has no free slot for it) into slot[i] for each missing i.
+__device__ __forceinline__ void union_probe(uint64_t* flist, uint64_t* ftotal, uint32_t ltag, int64_t r0, int64_t lim,
                                             uint32_t fm, int32_t (&slot)[kUItems], int32_t* err) {
   uint32_t pend = 0;
   {
@@ -223,9 +224,12 @@ __device__ __forceinline__ void union_probe(uint64_t* flist, uint64_t* ftotal, u
     for (int i = 0; i < kUItems; ++i) {
       if ((fm >> i) & 1u) {
         slot[i] = -1;
-        const uint64_t w = tload(flist + r++);
-        if ((uint32_t)(w >> 32) == ltag) slot[i] = (int32_t)(w & 0x7fffffffu);
-        else pend |= 1u << i;
+        if (r < lim) {
+          const uint64_t w = tload(flist + r);
+          if ((uint32_t)(w >> 32) == ltag) slot[i] = (int32_t)(w & 0x7fffffffu);
+          else pend |= 1u << i;
+        }
+        ++r;
       }
     }
   }
@@ -242,7 +246,7 @@ __device__ __forceinline__ void union_probe(uint64_t* flist, uint64_t* ftotal, u
 #pragma unroll
     for (int i = 0; i < kUItems; ++i)
       if ((fm >> i) & 1u) {
-        if ((pend >> i) & 1u) {
+        if ((pend >> i) & 1u) {  // (r < lim: only such entries are pending)
           const uint64_t w = tload(flist + r);
           if ((uint32_t)(w >> 32) == ltag) {
             slot[i] = (int32_t)(w & 0x7fffffffu);
@@ -301,7 +305,7 @@ __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t t
   if (!fm) return;
   rm += (int)*s_ex;
   // the rm-th free slot for the rm-th missing record, once its free-scan block has listed it
-  union_probe(a.free_list, a.ftotal, tag, rm, fm, sl, a.state + GC_STATE_ERR);
+  union_probe(a.free_list, a.ftotal, tag, rm, a.flimit, fm, sl, a.state + GC_STATE_ERR);
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
     if (!((fm >> i) & 1u)) continue;
@@ -348,7 +352,7 @@ __device__ __forceinline__ uint32_t union_table(const ReorgArgs& a, int b, uint3
   }
   __syncthreads();
   rm += (int)*s_ex;
-  if (fm) union_probe(a.free_list, a.ftotal, ltag, fbase + rm, fm, slot, a.state + GC_STATE_ERR);
+  if (fm) union_probe(a.free_list, a.ftotal, ltag, fbase + rm, a.flimit, fm, slot, a.state + GC_STATE_ERR);
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
     const int64_t k = k0 + i;

@@ -560,6 +560,76 @@ def test_step_schedule_without_fixture_accumulates_residency(ctx, plum):
     rig.close()
 
 
+def test_step_schedule_without_fixture_overflow_matches_eager(ctx, plum):
+    # fixture NONE with a pool too small for every round's missing records: round 0 fits, round 1 takes
+    # the last free slots (its first missing records, ascending) and later rounds find none; every
+    # missing record is still packed from the source.  The launch leaves the pool, the accelerations and
+    # the per-round FULL reports exactly as the eager sequence of per-round calls does
+    import torch
+    print("[gpu] whole-step schedule, fixture NONE, pool overflow", flush=True)
+    rounds = W.poisson_rounds(plum.n_tasks, 400, seed=58)[:4]
+    bts = [W.task_subset(plum, r) for r in rounds]
+    rng = np.random.default_rng(59)
+    n_base = 2000
+    base_ids = np.sort(rng.choice(plum.n, n_base, replace=False)).astype(np.int32)
+    # missing counts of rounds 0 and 1 with room for all of them (oracle, sequentially)
+    so = np.full(plum.n, -1, np.int32)
+    so[base_ids] = np.arange(n_base, dtype=np.int32)
+    m0 = O.maps(bts[0], plum.n, plum.n, so, gc.REORG_PACK)
+    m1 = O.maps(bts[1], plum.n, plum.n, m0["slot_of"], gc.REORG_PACK)
+    cap = n_base + m0["missing"].size + m1["missing"].size // 2
+    base_slots = rng.permutation(cap)[:n_base].astype(np.int32)
+    rig = GravRig(ctx, plum, capacity=cap)
+    bs = [rig.batch(bt) for bt in bts]
+    prm = gc.grav_params(order=2)
+
+    def base():
+        rig.pool.reset()
+        rig.place(base_ids, base_slots)
+
+    base()
+    rig.acc.fill_(np.nan)
+    full_eager = []
+    for b in bs:
+        b.reorganize(rig.pool, gc.REORG_PACK, check_capacity=False)
+        b.launch(prm, rig.nodes, rig.acc)
+        try:
+            b.maps()
+            full_eager.append(False)
+        except gc.GcError as e:
+            assert e.status == 3
+            full_eager.append(True)
+    torch.cuda.synchronize()
+    eager = rig.acc.cpu().numpy()
+    so_eager = rig.pool.query()
+    assert full_eager == [False, True, True, True]
+    for bt in bts:
+        assert rel_l2_per_task(eager, O.grav_workload(plum, order=2, tasks=bt), bt).max() <= TOL
+    base()
+    s = torch.cuda.Stream()
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), gc.grav_params(order=2, schedule=gc.SCHED_STEP),
+                 rig.nodes, rig.acc, stream=s, fixture=gc.FIXTURE_NONE)
+    rig.acc.fill_(np.nan)
+    torch.cuda.synchronize()
+    g.launch(stream=s)
+    s.synchronize()
+    got = rig.acc.cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(eager))
+    assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)])
+    assert np.array_equal(rig.pool.query(), so_eager)
+    so0 = np.full(plum.n, -1, np.int32)
+    so0[base_ids] = base_slots
+    _check_maps(bs[0].maps(), O.maps(bts[0], plum.n, cap, so0, gc.REORG_PACK), gc.REORG_PACK)
+    for b in bs[1:]:
+        with pytest.raises(gc.GcError) as e:
+            b.maps()
+        assert e.value.status == 3
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()
+
+
 def test_step_schedule_full_size_rounds(ctx):
     # 262,144-particle Plummer sphere, 6 Poisson(2048) rounds over half of all particles resident:
     # the whole-step launch equals the per-round launches bitwise; sampled tasks match the oracle

@@ -259,10 +259,13 @@ enum { GC_FORCE_GRAV_MONO = 1, GC_FORCE_GRAV_QUAD = 2, GC_FORCE_LJ = 3 };
  * tasks from a device counter in the same order.  GC_SCHED_STEP (graph
  * capture only, gravity, PACK, one pool, fixture NONE or EVICT_STAGED,
  * distinct batches): one persistent launch runs all captured steps -- each
- * step's eviction fixture, reorganisation and combined pass -- as ordered
- * work items with device-side dependencies, the reorganisation one step
- * ahead of the passes; 4 waves per task; results bitwise equal to the
- * per-step launches.
+ * step's reorganisation (with the evicting fixture, the eviction of what it
+ * stages) and combined pass -- as ordered work items with device-side
+ * dependencies, the reorganisation three steps ahead of the passes; the
+ * free-slot scan runs once per launch (later steps take the free slots after
+ * those kept by earlier ones); 4 waves per task; results bitwise equal to the
+ * per-step launches.  With the evicting fixture a small kernel ahead of the
+ * launch evicts what the last step left staged before it.
  */
 enum { GC_SCHED_TASKS = 0, GC_SCHED_QUEUE = 1, GC_SCHED_STEP = 2 };
 

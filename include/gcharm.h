@@ -291,9 +291,14 @@ typedef struct {
  * reorganised batch computes its targets' accelerations; acc_dev is float4
  * [n_ids] (x, y, z acceleration, w = 0), caller-owned.  Gravity writes the
  * rows of targeted ids only (each id must be the target of at most one
- * task).  Lennard-Jones accumulates with atomics: the caller zeroes acc_dev
- * first (gc_zero_f32 does it without a memset node).  nodes_dev: float
- * [n_nodes * 12] (gravity), unused for Lennard-Jones.  Asynchronous.
+ * task).  Lennard-Jones writes every row (zero for ids no task touches).  When
+ * any two target ranges of the batch (the tasks' i ranges and the j ranges of
+ * the tasks that are not self tasks) are equal or disjoint, as for cell tasks,
+ * one wavefront per range sums its atoms' forces from every task on either
+ * side and writes them once: no atomics, the same bits on every launch;
+ * otherwise the forces of both sides are accumulated with FP32 atomics.
+ * nodes_dev: float [n_nodes * 12] (gravity), unused for Lennard-Jones.
+ * Asynchronous.
  */
 gc_status gc_launch_combined(gc_batch batch, const gc_force_params* prm, const float* nodes_dev, float* acc_dev,
                              void* stream);

@@ -61,6 +61,12 @@ struct LJArgs {
   const int32_t* order;
   const int32_t* runs;     // runs of consecutive tasks sharing one target range: [runs[r], runs[r+1])
   int32_t n_runs;
+  // gather form: target ranges (first id, count, first entry, entries) and their entries
+  // (task * 2 + side; side 0: the range is the task's i range, 1: its j range)
+  const int4* tgt;
+  const int32_t* ent;
+  int32_t n_tgt;
+  const float* mass_t;     // gather form: acceleration = F / mass_t[type]
 };
 
 // ---------------------------------------------------------------- launchers (device code)
@@ -119,6 +125,8 @@ hipError_t launch_grav(int order, bool lists, bool persistent, bool two, const G
                        int grid_blocks, hipStream_t s);
 hipError_t grav_occupancy(int order, bool lists, bool persistent, bool two, int tile, int waves_per_block, int* blocks);
 hipError_t launch_lj(bool persistent, const LJArgs& a, int waves_per_block, int grid_blocks, hipStream_t s);
+// gather form: every target range's atoms written once (F / m), no atomics
+hipError_t launch_lj_gather(bool persistent, const LJArgs& a, int grid_blocks, hipStream_t s);
 hipError_t launch_lj_finish(float4* acc, const float* mass_t, const float4* rec_by_id, int32_t n,
                             hipStream_t s);
 

@@ -1,5 +1,8 @@
-// Combined Lennard-Jones kernel over cell-pair tasks (Sec. 4.2: a compute
+// Combined Lennard-Jones kernels over cell-pair tasks (Sec. 4.2: a compute
 // object takes the particles of two patches and updates the forces of both).
+// Two forms: the gather form further below, used whenever the batch's target
+// ranges are equal or disjoint (cell tasks always are), and the half-shell form
+// described here, for any other task set.
 //
 // One wavefront per run of consecutive tasks that share one target range (a
 // cell's self task and its 13 half-shell neighbours form one run), so the
@@ -15,9 +18,14 @@
 // (both inner operations are exact for wrapped coordinates, so d carries one
 // rounding), r^2 = fma(dz, dz, fma(dy, dy, dx*dx)), inside iff r^2 < rc^2.
 #include "gc_internal.h"
+#include "grav_dev.h"
+#include "mem_dev.h"
 
 namespace gc {
 namespace {
+
+using dev::gld;
+using dev::gst;
 
 constexpr int kMaxTypes = 8;
 constexpr int kLJTile = 128;  // j atoms per LDS tile
@@ -159,6 +167,197 @@ __global__ void __launch_bounds__(256) k_lj(LJArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- gather form
+//
+// One wavefront per target range (a cell): every task that has the cell on either side contributes
+// to its atoms, so each pair of two different cells is evaluated once from each side (the self task
+// of a cell once, from all its atoms).  The cell's atoms sum their forces in registers and each
+// atom's acceleration is written once: no atomics, the same bits on every run and schedule.  Work
+// per pair doubles against the half-shell form above, but a pair costs about 20 VALU operations
+// there and the atomics, per-task waits and LDS atomics of the half-shell form cost more.
+//
+// A wavefront stages the sources of up to 64 tasks at a time in LDS tiles (shifted as below) and
+// splits its 64 lanes into (target atom) x (source slice) as the gravity kernel does; the slices
+// are reduced through LDS at the end.  The cutoff decision takes the same FP32 operations as the
+// half-shell form, from either side: for a task with shift s, a = max(s, 0), b = min(s, 0), the
+// separation is d = (x_i - a) - (x_j + b); the task's i atom as target gets F += f d, its j atom
+// gets F += f (-d), computed as (x_j + b) - (x_i - a), the exact negation, so r^2 is the same.
+// The per-task shift sits on the source when staged (x_j + b, or x_i + (-a)); on the target side
+// it is added per pair, only in cells that have tasks across the periodic boundary (x + (-a) and
+// x - a round alike).  A zero separation is the atom itself (a cell's self task) and adds nothing.
+constexpr int kGTile = 128;  // source records per LDS tile per wavefront
+constexpr float kFar = 1e18f;  // padding sources: r^2 ~ 3e36, finite and outside any cutoff
+
+template <bool SHIFTED, bool ONE>
+__device__ __forceinline__ void gather_tile(const float4* __restrict__ p, const float4* __restrict__ o, int C,
+                                            float tx, float ty, float tz, const float2* __restrict__ trow,
+                                            float2 p0, float rc2, float& Fx, float& Fy, float& Fz) {
+#pragma unroll 2
+  for (int k = 0; k < C; ++k) {
+    const float4 sj = p[k];
+    float ux = tx, uy = ty, uz = tz;
+    if (SHIFTED) {
+      const float4 w = o[k];
+      ux = tx + w.x;
+      uy = ty + w.y;
+      uz = tz + w.z;
+    }
+    const float ex = ux - sj.x, ey = uy - sj.y, ez = uz - sj.z;
+    const float r2 = __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex));
+    const float2 pp = ONE ? p0 : trow[(int)sj.w];
+    const float ri2 = __builtin_amdgcn_rcpf(r2);
+    const float q = pp.y * ri2;
+    const float q3 = q * q * q;
+    float f = pp.x * q3 * __builtin_fmaf(2.f, q3, -1.f) * ri2;
+    f = (r2 < rc2 && r2 > 0.f) ? f : 0.f;
+    Fx = __builtin_fmaf(f, ex, Fx);
+    Fy = __builtin_fmaf(f, ey, Fy);
+    Fz = __builtin_fmaf(f, ez, Fz);
+  }
+}
+
+template <bool PERSIST, bool ONE>
+__global__ void __launch_bounds__(256) k_lj_gather(LJArgs a) {
+  __shared__ float2 tab[kMaxTypes * kMaxTypes];  // (24 eps_ij, sigma_ij^2)
+  __shared__ float4 src[4][kGTile];              // sources, shifted; padding far away
+  __shared__ float4 tof[4][kGTile];              // per source: its task's target-side shift
+  __shared__ float4 esh[4][64], eto[4][64];      // per task of the group: source and target shifts
+  __shared__ int eoff[4][64], ebeg[4][64];       // per task: first flat source, first source record
+  __shared__ float fr[4][3][64];
+  const int lane = threadIdx.x & 63;
+  const int wid = uniform(threadIdx.x >> 6);
+  const int wpb = blockDim.x >> 6;
+  for (int k = threadIdx.x; k < a.n_types * a.n_types; k += blockDim.x) {
+    const int ta = k / a.n_types, tb = k % a.n_types;
+    const float e = sqrtf(a.eps_t[ta] * a.eps_t[tb]);
+    const float sg = 0.5f * (a.sig_t[ta] + a.sig_t[tb]);
+    tab[k] = make_float2(24.f * e, sg * sg);
+  }
+  __syncthreads();
+  const float2 p0 = tab[0];
+  const int32_t* tw0 = reinterpret_cast<const int32_t*>(a.tasks);
+  constexpr int kTaskWords = sizeof(gc_task) / 4;
+  int chunk_base = uniform((blockIdx.x * wpb + wid) * (PERSIST ? kRunChunk : 1));
+  int chunk_left = PERSIST ? kRunChunk : 1;
+  while (true) {
+    if (chunk_left == 0) {
+      if (!PERSIST) break;
+      int q = 0;
+      if (lane == 0) q = atomicAdd(a.queue, 1);
+      chunk_base = uniform((__shfl(q, 0, 64) + (int)gridDim.x * wpb) * kRunChunk);
+      chunk_left = kRunChunk;
+    }
+    const int g = chunk_base + (PERSIST ? kRunChunk - chunk_left : 0);
+    --chunk_left;
+    if (g >= a.n_tgt) break;
+    const int4 tg = gld(a.tgt + g);  // (first id, count, first entry, entries)
+    const int id0 = uniform(tg.x), cnt = uniform(tg.y), e0 = uniform(tg.z), ne = uniform(tg.w);
+    // the range's first record, from its first entry
+    const int en0 = uniform(gld(a.ent + e0));
+    const int32_t* tw = tw0 + (int64_t)(en0 >> 1) * kTaskWords;
+    const int rb = (en0 & 1) ? uniform(gld(a.ranges + uniform(gld(tw + 2))).x)
+                             : (a.ibeg ? uniform(gld(a.ibeg + (en0 >> 1))) : uniform(gld(tw)));
+    for (int i0 = 0; i0 < cnt; i0 += 64) {
+      const int icc = cnt - i0 < 64 ? cnt - i0 : 64;
+      const int S = 64 / icc;
+      const int il = lane % icc, sl = lane / icc;
+      const bool active = sl < S;
+      float tx = 0.f, ty = 0.f, tz = 0.f;
+      int ti = 0;
+      if (active) {
+        const float4 r = gld(a.rec + rb + i0 + il);
+        tx = r.x; ty = r.y; tz = r.z;
+        ti = (int)r.w;
+      }
+      const float2* trow = tab + ti * a.n_types;
+      float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+      const int DT = S * (kGTile / S);
+      for (int eg = 0; eg < ne; eg += 64) {
+        const int nen = ne - eg < 64 ? ne - eg : 64;
+        int n = 0, sb = 0;
+        float4 sh = make_float4(0.f, 0.f, 0.f, 0.f), to = sh;
+        if (lane < nen) {
+          const int en = gld(a.ent + e0 + eg + lane);
+          const int t = en >> 1;
+          const int32_t* w = tw0 + (int64_t)t * kTaskWords;
+          const float s0 = __int_as_float(gld(w + 7)), s1 = __int_as_float(gld(w + 8)),
+                      s2 = __int_as_float(gld(w + 9));
+          const float ax = s0 > 0.f ? s0 : 0.f, ay = s1 > 0.f ? s1 : 0.f, az = s2 > 0.f ? s2 : 0.f;
+          const float bx = s0 < 0.f ? s0 : 0.f, by = s1 < 0.f ? s1 : 0.f, bz = s2 < 0.f ? s2 : 0.f;
+          if (en & 1) {  // target on the task's j side: sources are its i atoms, x_i - a
+            sb = a.ibeg ? gld(a.ibeg + t) : gld(w);
+            n = gld(w + 1);
+            sh = make_float4(-ax, -ay, -az, 0.f);
+            to = make_float4(bx, by, bz, 0.f);
+          } else {       // target on the task's i side: sources are its j atoms, x_j + b
+            const int2 jr = gld(a.ranges + gld(w + 2));
+            sb = jr.x;
+            n = jr.y;
+            sh = make_float4(bx, by, bz, 0.f);
+            to = make_float4(-ax, -ay, -az, 0.f);
+          }
+        }
+        int total;
+        const int off = dev::wave_excl_scan(n, &total);
+        total = uniform(total);
+        const bool shifted = __ballot(lane < nen && (to.x != 0.f || to.y != 0.f || to.z != 0.f)) != 0ull;
+        eoff[wid][lane] = lane < nen ? off : 0x7fffffff;
+        ebeg[wid][lane] = sb;
+        esh[wid][lane] = sh;
+        eto[wid][lane] = to;
+        wave_sync();
+        for (int ws = 0; ws < total; ws += DT) {
+          const int c = total - ws < DT ? total - ws : DT;
+          const int C = (c + S - 1) / S;
+          const int padded = S * C;
+          for (int e = lane; e < padded; e += 64) {
+            float4 v = make_float4(kFar, kFar, kFar, 0.f), o = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (e < c) {
+              const int f = ws + e;
+              int lo = 0, hi = nen - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (eoff[wid][mid] <= f) lo = mid;
+                else hi = mid - 1;
+              }
+              const float4 r = gld(a.rec + ebeg[wid][lo] + (f - eoff[wid][lo]));
+              const float4 q = esh[wid][lo];
+              v = make_float4(r.x + q.x, r.y + q.y, r.z + q.z, r.w);
+              o = eto[wid][lo];
+            }
+            src[wid][e] = v;
+            if (shifted) tof[wid][e] = o;
+          }
+          wave_sync();
+          if (active) {
+            if (shifted)
+              gather_tile<true, ONE>(&src[wid][sl * C], &tof[wid][sl * C], C, tx, ty, tz, trow, p0, a.rc2, Fx, Fy, Fz);
+            else
+              gather_tile<false, ONE>(&src[wid][sl * C], nullptr, C, tx, ty, tz, trow, p0, a.rc2, Fx, Fy, Fz);
+          }
+          wave_sync();
+        }
+      }
+      // the slices of each target atom, in a fixed order; a = F / m
+      fr[wid][0][lane] = Fx;
+      fr[wid][1][lane] = Fy;
+      fr[wid][2][lane] = Fz;
+      wave_sync();
+      if (lane < icc) {
+        float sx = 0.f, sy = 0.f, sz = 0.f;
+        for (int s = 0; s < S; ++s) {
+          sx += fr[wid][0][s * icc + lane];
+          sy += fr[wid][1][s * icc + lane];
+          sz += fr[wid][2][s * icc + lane];
+        }
+        const float m = a.mass_t[ti];
+        gst(a.acc + id0 + i0 + lane, make_float4(sx / m, sy / m, sz / m, 0.f));
+      }
+      wave_sync();
+    }
+  }
+}
+
 __global__ void k_lj_finish(float4* __restrict__ acc, const float* __restrict__ mass_t,
                             const float4* __restrict__ rec_by_id, int32_t n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -181,6 +380,24 @@ hipError_t launch_lj(bool persistent, const LJArgs& a, int wpb, int grid, hipStr
     hipLaunchKernelGGL(k_lj<true>, dim3(g), dim3(256), 0, s, a);
   } else {
     hipLaunchKernelGGL(k_lj<false>, dim3((a.n_runs + 3) / 4), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lj_gather(bool persistent, const LJArgs& a, int grid, hipStream_t s) {
+  if (a.n_tgt <= 0) return hipSuccess;
+  const bool one = a.n_types == 1;
+  if (persistent) {
+    int g = grid;
+    const int need = (a.n_tgt + 4 * kRunChunk - 1) / (4 * kRunChunk);
+    if (g > need) g = need;
+    if (g < 1) g = 1;
+    if (one) hipLaunchKernelGGL((k_lj_gather<true, true>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_lj_gather<true, false>), dim3(g), dim3(256), 0, s, a);
+  } else {
+    const int g = (a.n_tgt + 3) / 4;
+    if (one) hipLaunchKernelGGL((k_lj_gather<false, true>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_lj_gather<false, false>), dim3(g), dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -14,6 +14,7 @@
 #pragma once
 
 #include "gc_internal.h"
+#include "mem_dev.h"
 
 namespace gc {
 namespace dev {
@@ -62,18 +63,10 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh_wave, int* total) 
 __device__ __forceinline__ uint64_t tword(uint32_t tag, uint32_t flag, uint32_t cnt) {
   return ((uint64_t)tag << 32) | ((uint64_t)flag << 31) | (uint64_t)cnt;
 }
-__device__ __forceinline__ void tstore(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t tload(uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t iload(int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void istore(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ void tstore(uint64_t* p, uint64_t v) { astore(p, v); }
+__device__ __forceinline__ uint64_t tload(uint64_t* p) { return aload(p); }
+__device__ __forceinline__ int32_t iload(int32_t* p) { return aload(p); }
+__device__ __forceinline__ void istore(int32_t* p, int32_t v) { astore(p, v); }
 
 // Wavefront 0 of chain block `bid`: publish the block aggregate, look back over up to 64
 // predecessors per probe (a word of another call counts as not yet written; the run up to the
@@ -118,13 +111,13 @@ __device__ __forceinline__ uint32_t look_back(uint64_t* flags, int bid, uint32_t
 template <bool COH>
 __device__ __forceinline__ int32_t ld_i32(const int32_t* p) {
   if (COH) return iload(const_cast<int32_t*>(p));
-  return *p;
+  return gld(p);
 }
 
 // One 16-byte record; COH: two device-scope 8-byte loads.
 template <bool COH>
 __device__ __forceinline__ float4 ld_rec(const float4* p) {
-  if (!COH) return *p;
+  if (!COH) return gld(p);
   uint64_t* q = reinterpret_cast<uint64_t*>(const_cast<float4*>(p));
   const uint64_t lo = tload(q), hi = tload(q + 1);
   return make_float4(__uint_as_float((uint32_t)lo), __uint_as_float((uint32_t)(lo >> 32)),
@@ -147,11 +140,11 @@ __device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t ta
       for (int k = 0; k < kFItems; ++k)
         if (ld_i32<true>(o + k) == 0 && s0 + k < a.cap) f |= 1u << k;
     } else {
-      const uint4* o4 = reinterpret_cast<const uint4*>(a.occ + s0);  // occ is padded to whole blocks
+      const int4* o4 = reinterpret_cast<const int4*>(a.occ + s0);  // occ is padded to whole blocks
 #pragma unroll
       for (int q = 0; q < kFItems / 4; ++q) {
-        const uint4 o = o4[q];
-        const uint32_t ov[4] = {o.x, o.y, o.z, o.w};
+        const int4 o = gld(o4 + q);
+        const uint32_t ov[4] = {(uint32_t)o.x, (uint32_t)o.y, (uint32_t)o.z, (uint32_t)o.w};
 #pragma unroll
         for (int k = 0; k < 4; ++k)
           if (ov[k] == 0u && s0 + 4 * q + k < a.cap) f |= 1u << (4 * q + k);
@@ -188,7 +181,7 @@ __device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t ta
 __device__ __forceinline__ void union_ids(const ReorgArgs& a, int b, int32_t (&id)[kUItems]) {
   const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
   const int4* u4 = reinterpret_cast<const int4*>(a.U + k0);  // U is padded to whole blocks
-  const int4 x = u4[0], y = u4[1];
+  const int4 x = gld(u4), y = gld(u4 + 1);
   id[0] = x.x; id[1] = x.y; id[2] = x.z; id[3] = x.w;
   id[4] = y.x; id[5] = y.y; id[6] = y.z; id[7] = y.w;
 }
@@ -274,7 +267,7 @@ __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t t
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if ((fm >> i) & 1u) v = a.src[id[i]];
+    if ((fm >> i) & 1u) v = gld(a.src + id[i]);
     else if (k0 + i < a.u) v = ld_rec<COH>(a.pool + sl[i]);
     rx[i] = v.x;
     ry[i] = v.y;
@@ -297,8 +290,8 @@ __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t t
   for (int i = 0; i < kUItems; ++i) {
     const int64_t k = k0 + i;
     if (k < a.u) {
-      if (!((fm >> i) & 1u)) a.uslot[k] = sl[i];
-      if (a.pack) a.packed[k] = make_float4(rx[i], ry[i], rz[i], rw[i]);
+      if (!((fm >> i) & 1u)) gst(a.uslot + k, sl[i]);
+      if (a.pack) gst(a.packed + k, make_float4(rx[i], ry[i], rz[i], rw[i]));
     }
   }
   __syncthreads();
@@ -311,13 +304,13 @@ __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t t
     if (!((fm >> i) & 1u)) continue;
     const int64_t k = k0 + i;
     const int32_t s = sl[i];
-    a.missing[rm] = id[i];
-    a.mslot[rm] = s;
-    a.uslot[k] = s;
+    gst(a.missing + rm, id[i]);
+    gst(a.mslot + rm, s);
+    gst(a.uslot + k, s);
     if (s >= 0) {
-      a.pool[s] = make_float4(rx[i], ry[i], rz[i], rw[i]);
-      a.slot_of[id[i]] = s;
-      a.occ[s] = 1u;
+      gst(a.pool + s, make_float4(rx[i], ry[i], rz[i], rw[i]));
+      gst(a.slot_of + id[i], s);
+      gst(a.occ + s, 1u);
     }
     ++rm;
   }
@@ -358,16 +351,16 @@ __device__ __forceinline__ uint32_t union_table(const ReorgArgs& a, int b, uint3
     const int64_t k = k0 + i;
     if (k >= a.u) continue;
     const int32_t s = slot[i];
-    a.uslot[k] = s;
+    gst(a.uslot + k, s);
     if ((fm >> i) & 1u) {
-      a.missing[rm] = id[i];
-      a.mslot[rm] = s;
+      gst(a.missing + rm, id[i]);
+      gst(a.mslot + rm, s);
       ++rm;
       if (s >= 0) {
         // staged, and with evict_after at once evicted again (the pool keeps its base residency
         // between rounds); the record itself is written by the data part
-        a.slot_of[id[i]] = a.evict_after ? -1 : s;
-        a.occ[s] = a.evict_after ? 0u : 1u;
+        gst(a.slot_of + id[i], a.evict_after ? -1 : s);
+        gst(a.occ + s, a.evict_after ? 0u : 1u);
       }
     }
   }
@@ -381,15 +374,15 @@ __device__ __forceinline__ void union_data(const ReorgArgs& a, int b, const int3
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
     v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if ((fm >> i) & 1u) v[i] = a.src[id[i]];
+    if ((fm >> i) & 1u) v[i] = gld(a.src + id[i]);
     else if (k0 + i < a.u) v[i] = ld_rec<true>(a.pool + slot[i]);
   }
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
     const int64_t k = k0 + i;
     if (k >= a.u) continue;
-    a.packed[k] = v[i];
-    if (((fm >> i) & 1u) && slot[i] >= 0) a.pool[slot[i]] = v[i];
+    gst(a.packed + k, v[i]);
+    if (((fm >> i) & 1u) && slot[i] >= 0) gst(a.pool + slot[i], v[i]);
   }
 }
 

@@ -105,6 +105,11 @@ struct gc_batch_ {
   int32_t u = 0, max_direct = 0;
   DevBuf d_tasks, d_ranges, d_nodes, d_ioff, d_joff, d_order, d_runs, d_U, pranges, pibeg;
   int32_t n_runs = 0;
+  // Lennard-Jones gather form (possible when any two target ranges are equal or disjoint): the
+  // target ranges and, per range, its tasks and sides; cover: the ranges hold every id
+  DevBuf d_ljtgt, d_ljent;
+  int32_t n_ljtgt = 0;
+  bool lj_gather = false, lj_cover = false;
   bool ranks_ready = false;      // union ranks of the address-list entries (built on first use)
   DevBuf d_irank, d_jrank;
   // reorganisation buffers
@@ -289,7 +294,7 @@ extern "C" gc_status gc_batch_destroy(gc_batch b) {
   (void)hipDeviceSynchronize();
   for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs, &b->d_U,
                     &b->pranges, &b->pibeg, &b->d_irank, &b->d_jrank, &b->uslot, &b->missing, &b->mslot, &b->free_list,
-                    &b->state, &b->packed, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force})
+                    &b->state, &b->packed, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force, &b->d_ljtgt, &b->d_ljent})
     d->release();
   delete b;
   return GC_OK;
@@ -456,6 +461,48 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
       runs.push_back(t);
   runs.push_back(T);
   b->n_runs = (int32_t)runs.size() - 1;
+  // Lennard-Jones gather form: every task's i range (side 0) and, unless it is the cell's own
+  // self task, its j range (side 1) is a target range; ranges of equal extent merge, and the form
+  // needs the distinct ones disjoint (each id then has one wavefront that writes it)
+  std::vector<int32_t> ljtgt, ljent;
+  b->lj_gather = false;
+  b->lj_cover = false;
+  b->n_ljtgt = 0;
+  if (b->kind == GC_KIND_LJ) {
+    struct Side { int32_t begin, count, task, side; };
+    std::vector<Side> sides;
+    sides.reserve((size_t)2 * T);
+    for (int32_t t = 0; t < T; ++t) {
+      const gc_task& tk = b->tasks[t];
+      const int32_t jb = b->ranges[2 * tk.j_first], jn = b->ranges[2 * tk.j_first + 1];
+      if (tk.i_count > 0 && jn > 0) {
+        sides.push_back({tk.i_begin, tk.i_count, t, 0});
+        if (!(tk.flags & GC_TASK_SELF)) sides.push_back({jb, jn, t, 1});
+      }
+    }
+    std::sort(sides.begin(), sides.end(), [](const Side& x, const Side& y) {
+      if (x.begin != y.begin) return x.begin < y.begin;
+      if (x.count != y.count) return x.count < y.count;
+      return 2 * (int64_t)x.task + x.side < 2 * (int64_t)y.task + y.side;
+    });
+    bool ok = true;
+    int64_t covered = 0, prev_end = 0;
+    for (size_t k = 0; k < sides.size();) {
+      size_t e = k;
+      while (e < sides.size() && sides[e].begin == sides[k].begin && sides[e].count == sides[k].count) ++e;
+      if (sides[k].begin < prev_end) { ok = false; break; }
+      ljtgt.insert(ljtgt.end(), {sides[k].begin, sides[k].count, (int32_t)ljent.size(), (int32_t)(e - k)});
+      for (size_t q = k; q < e; ++q) ljent.push_back(2 * sides[q].task + sides[q].side);
+      prev_end = (int64_t)sides[k].begin + sides[k].count;
+      covered += sides[k].count;
+      k = e;
+    }
+    if (ok) {
+      b->lj_gather = true;
+      b->lj_cover = covered == b->n_ids;
+      b->n_ljtgt = (int32_t)(ljtgt.size() / 4);
+    }
+  }
   hipStream_t s = S(stream);
   hipError_t e = hipSuccess;
   auto up = [&](DevBuf& d, const void* src, size_t bytes) {
@@ -473,6 +520,10 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   up(b->d_joff, joff.data(), sizeof(int32_t) * joff.size());
   up(b->d_order, order.data(), sizeof(int32_t) * order.size());
   up(b->d_runs, runs.data(), sizeof(int32_t) * runs.size());
+  if (b->lj_gather) {
+    up(b->d_ljtgt, ljtgt.data(), sizeof(int32_t) * ljtgt.size());
+    up(b->d_ljent, ljent.data(), sizeof(int32_t) * ljent.size());
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors must outlive the copies
   if (e != hipSuccess) return hip_fail(c, e, "gc_batch_commit");
   order.resize((size_t)T);
@@ -766,7 +817,7 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
   } else {
     if (lists) return set_err(c, GC_E_UNSUPPORTED, "Lennard-Jones supports PACK, REDUNDANT and NONE");
     if (!b->pool->src_device) return set_err(c, GC_E_INVAL, "Lennard-Jones needs a device-resident source");
-    GC_HIP(c, launch_fill_f32(acc_dev, 0.f, 4 * (int64_t)b->n_ids, s));
+    if (!b->lj_gather || !b->lj_cover) GC_HIP(c, launch_fill_f32(acc_dev, 0.f, 4 * (int64_t)b->n_ids, s));
     LJArgs a{};
     a.tasks = b->d_tasks.as<gc_task>();
     a.n_tasks = T;
@@ -783,9 +834,17 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
     a.order = b->d_order.as<int32_t>();
     a.runs = b->d_runs.as<int32_t>();
     a.n_runs = b->n_runs;
-    int grid = prm->grid_blocks > 0 ? prm->grid_blocks : 8 * c->n_cu;
-    GC_HIP(c, launch_lj(persistent, a, 4, grid, s));
-    GC_HIP(c, launch_lj_finish(reinterpret_cast<float4*>(acc_dev), prm->mass_t, b->pool->src, b->n_ids, s));
+    a.tgt = b->d_ljtgt.as<int4>();
+    a.ent = b->d_ljent.as<int32_t>();
+    a.n_tgt = b->n_ljtgt;
+    a.mass_t = prm->mass_t;
+    if (b->lj_gather) {
+      GC_HIP(c, launch_lj_gather(persistent, a, prm->grid_blocks > 0 ? prm->grid_blocks : 5 * c->n_cu, s));
+    } else {
+      int grid = prm->grid_blocks > 0 ? prm->grid_blocks : 8 * c->n_cu;
+      GC_HIP(c, launch_lj(persistent, a, 4, grid, s));
+      GC_HIP(c, launch_lj_finish(reinterpret_cast<float4*>(acc_dev), prm->mass_t, b->pool->src, b->n_ids, s));
+    }
   }
   return GC_OK;
 }

@@ -118,3 +118,83 @@ def test_lj_submit_validation(ctx):
         b.submit(t3, r)
     assert b.sizes()["tasks"] == 0  # strong guarantee: nothing appended
     b.destroy()
+
+
+def test_lj_gather_form_is_bitwise_repeatable(ctx):
+    # the gather form writes each atom once, without atomics: the same bits on every run, with
+    # either schedule, and from the packed records as from the source in place
+    xyz, v, L = W.fcc_modulated(16, 14, 14, 0.8442, 11000, seed=78)
+    w = W.build_lj(xyz, W.two_types(xyz.shape[0], 6), L, 2.5, **W.LJ_TWO_TYPES)
+    rig = LJRig(ctx, w)
+    runs = [rig.run(gc.REORG_NONE, 0), rig.run(gc.REORG_NONE, 0), rig.run(gc.REORG_NONE, 1), rig.run(gc.REORG_PACK, 0)]
+    for r in runs[1:]:
+        assert np.array_equal(r.view(np.uint32), runs[0].view(np.uint32))
+    err = per_cell(runs[0], O.lj_tasks(w), w)
+    assert err.max() <= TOL, err.max()
+    rig.close()
+
+
+def _run_tasks(ctx, w, tasks, mode=gc.REORG_NONE):
+    import torch
+    src = torch.from_numpy(np.ascontiguousarray(w.rec)).cuda()
+    eps, sig, mass = (torch.from_numpy(x).cuda() for x in (w.eps_t, w.sig_t, w.mass_t))
+    acc = torch.full((w.n, 4), float("nan"), dtype=torch.float32, device="cuda")
+    pool = gc.Pool(ctx, w.n, w.n)
+    pool.set_source(src)
+    ranges = np.stack([tasks["j_begin"], tasks["j_count"]], axis=1).astype(np.int32)
+    n = tasks["i_begin"].shape[0]
+    t = gc.tasks_from_csr(tasks["i_begin"], tasks["i_count"], np.arange(n, dtype=np.int32), np.ones(n, np.int32),
+                          flags=np.where(tasks["self_flag"] != 0, gc.TASK_SELF, 0), shift=tasks["shift"])
+    b = gc.Batch(ctx, gc.KIND_LJ, w.n)
+    b.submit(t, ranges)
+    b.commit()
+    b.reorganize(pool, mode)
+    b.launch(gc.lj_params(eps, sig, mass, w.rcut), None, acc)
+    torch.cuda.synchronize()
+    out = acc.cpu().numpy()
+    b.destroy()
+    pool.destroy()
+    return out
+
+
+def _task_dict(w, sel=None):
+    sel = np.arange(w.n_tasks) if sel is None else sel
+    return dict(i_begin=w.i_begin[sel], i_count=w.i_count[sel], j_begin=w.j_begin[sel], j_count=w.j_count[sel],
+                self_flag=w.self_flag[sel], shift=w.shift[sel])
+
+
+def test_lj_partially_overlapping_targets_use_the_atomic_form(ctx):
+    # an extra task whose target range straddles two cells: target ranges are no longer equal or
+    # disjoint, so the batch runs the half-shell form with atomics; same sums as the oracle's
+    w = W.lj_small()
+    cs = w.cell_start
+    extra = dict(i_begin=np.array([cs[4] + 2], np.int32), i_count=np.array([cs[5] - cs[4]], np.int32),
+                 j_begin=np.array([cs[13]], np.int32), j_count=np.array([cs[14] - cs[13]], np.int32),
+                 self_flag=np.zeros(1, np.int32), shift=np.zeros((1, 3), np.float32))
+    base = _task_dict(w)
+    tasks = {k: np.concatenate([base[k], extra[k]]) for k in base}
+    acc = _run_tasks(ctx, w, tasks)
+    ref = O.lj_tasks(w, tasks=tasks)
+    err = per_cell(acc, ref, w, floor=0.0)
+    assert err.max() <= TOL, err.max()
+
+
+def test_lj_gather_form_zeroes_untouched_atoms(ctx):
+    # tasks of a few cells only: the gather form writes their targets, every other row is zero
+    xyz, v, L = W.fcc_modulated(16, 14, 14, 0.8442, 11000, seed=79)
+    w = W.build_lj(xyz, W.two_types(xyz.shape[0], 7), L, 2.5, **W.LJ_TWO_TYPES)
+    sel = np.nonzero(np.isin(w.i_begin, w.cell_start[[0, 100, 400]]))[0]
+    tasks = _task_dict(w, sel)
+    acc = _run_tasks(ctx, w, tasks, mode=gc.REORG_PACK)
+    ref = O.lj_tasks(w, tasks=tasks)
+    touched = np.zeros(w.n, bool)
+    for k in range(sel.size):
+        touched[tasks["i_begin"][k]:tasks["i_begin"][k] + tasks["i_count"][k]] = True
+        touched[tasks["j_begin"][k]:tasks["j_begin"][k] + tasks["j_count"][k]] = True
+    assert 0 < touched.sum() < w.n // 2
+    assert np.all(acc[~touched] == 0.0)
+    # whole cells are touched or not; per touched cell, relative L2 against the oracle
+    nc = np.diff(w.cell_start)
+    cells = np.nonzero((nc > 0) & touched[np.minimum(w.cell_start[:-1], w.n - 1)])[0]
+    err = O.per_task_rel_l2(acc[:, :3].astype(np.float64), ref, w.cell_start[cells], nc[cells], floor_frac=0.0)
+    assert err.max() <= TOL, err.max()

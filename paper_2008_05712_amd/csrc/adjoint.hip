@@ -23,7 +23,14 @@
 //   dL/deps_ij = p f / eps_ij,  dL/dsigma_ij = p * 24 eps (24 s^11 r^-14 - 6 s^5 r^-8),
 //   chained to the per-type parameters through Lorentz-Berthelot mixing;
 //   dL/dm_i = -g_i . F_i / m_i^2 with the forces F recomputed here.
+// When the batch's target ranges are equal or disjoint, the gather form runs: as the forward gather
+// form, one wavefront per target cell over every task touching it from either side.  The pair term
+// is the same from both sides: with e the separation seen from the target and h_t, h_s the target's
+// and the source's g / m, the target takes f (h_t - h_s) + 2 f' ((h_t - h_s) . e) e, and each side
+// adds half of the pair's parameter derivatives.
 #include "gc_internal.h"
+#include "grav_dev.h"
+#include "mem_dev.h"
 
 namespace gc {
 namespace {
@@ -268,6 +275,49 @@ struct ParamAcc {
   }
 };
 
+// The block's dL/deps_ij, dL/dsigma_ij by type pair (summed over its 4 wavefronts) go to its own
+// row of A.ppart with plain stores; k_lj_param_reduce sums the rows in a fixed order.  (Atomics from
+// every block onto the few words of gparam, all in one cache line, serialise at one L2 channel.)
+__device__ __forceinline__ void block_param_partial(const LJAdjArgs& A, const float* pg, int nt) {
+  const int P = 2 * nt * nt;
+  if ((int)threadIdx.x < P) {
+    float v = 0.f;
+    for (int w = 0; w < 4; ++w) v += pg[w * 2 * kMaxTypes * kMaxTypes + threadIdx.x];
+    A.ppart[(int64_t)blockIdx.x * P + threadIdx.x] = v;
+  }
+}
+
+// One block per type pair (ta, tb): the sum of the blocks' partials, chained to the per-type
+// parameters through eps_ij = sqrt(eps_a eps_b), sigma_ij = (sigma_a + sigma_b) / 2.
+__global__ void __launch_bounds__(256) k_lj_param_reduce(const float* __restrict__ ppart, int32_t n_blocks, int32_t nt,
+                                                         const float* __restrict__ eps_t, float* __restrict__ gparam) {
+  __shared__ float se[256], ss[256];
+  const int k = blockIdx.x, P = 2 * nt * nt;
+  float de = 0.f, ds = 0.f;
+  for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) {
+    de += ppart[(int64_t)b * P + 2 * k];
+    ds += ppart[(int64_t)b * P + 2 * k + 1];
+  }
+  se[threadIdx.x] = de;
+  ss[threadIdx.x] = ds;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      se[threadIdx.x] += se[threadIdx.x + h];
+      ss[threadIdx.x] += ss[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int ta = k / nt, tb = k % nt;
+    const float eij = sqrtf(eps_t[ta] * eps_t[tb]);
+    unsafeAtomicAdd(gparam + ta, se[0] * eps_t[tb] / (2.f * eij));
+    unsafeAtomicAdd(gparam + tb, se[0] * eps_t[ta] / (2.f * eij));
+    unsafeAtomicAdd(gparam + nt + ta, 0.5f * ss[0]);
+    unsafeAtomicAdd(gparam + nt + tb, 0.5f * ss[0]);
+  }
+}
+
 // One wavefront per run of tasks sharing a target range (as in the forward kernel); lanes =
 // (i atom) x (j slice) with a per-lane rotation over the slice's j entries.  j-side gradients and
 // forces accumulate in LDS, i-side in registers across the run.
@@ -420,22 +470,206 @@ __global__ void __launch_bounds__(256) k_lj_adj(LJAdjArgs A) {
     }
   }
   __syncthreads();
-  // per-type parameters: eps_ij = sqrt(eps_a eps_b), sigma_ij = (sigma_a + sigma_b) / 2
-  if (threadIdx.x < nt * nt) {
-    const int ta = threadIdx.x / nt, tb = threadIdx.x % nt;
-    float de = 0.f, ds = 0.f;
-    for (int w = 0; w < 4; ++w) {
-      de += pg[w][2 * threadIdx.x];
-      ds += pg[w][2 * threadIdx.x + 1];
+  block_param_partial(A, &pg[0][0], nt);
+}
+
+// Gather form of the Lennard-Jones adjoint (see the forward gather form for the schedule and the
+// cutoff arithmetic).  Each target atom's dL/dx is added to gpos and its recomputed force written
+// to `force` by one wavefront; the parameter derivatives go through per-lane sums keyed by the
+// source type, the block's LDS, then one atomic per type pair and block.
+constexpr int kGTile = 128;
+constexpr float kFar = 1e18f;
+
+template <int NT, bool SHIFTED>
+__device__ __forceinline__ void adj_gather_tile(const float4* __restrict__ p, const float4* __restrict__ hp,
+                                                const float4* __restrict__ o, int C, float tx, float ty, float tz,
+                                                float hx, float hy, float hz, const float4* __restrict__ trow,
+                                                float4 p0, float rc2, float (&acc)[6], ParamAcc<NT>& pa,
+                                                float* pg_row) {
+  for (int k = 0; k < C; ++k) {
+    const float4 sj = p[k], hj = hp[k];
+    float ux = tx, uy = ty, uz = tz;
+    if (SHIFTED) {
+      const float4 w = o[k];
+      ux = tx + w.x;
+      uy = ty + w.y;
+      uz = tz + w.z;
     }
-    if (de != 0.f || ds != 0.f) {
-      const float eij = sqrtf(a.eps_t[ta] * a.eps_t[tb]);
-      unsafeAtomicAdd(A.gparam + ta, de * a.eps_t[tb] / (2.f * eij));
-      unsafeAtomicAdd(A.gparam + tb, de * a.eps_t[ta] / (2.f * eij));
-      unsafeAtomicAdd(A.gparam + nt + ta, 0.5f * ds);
-      unsafeAtomicAdd(A.gparam + nt + tb, 0.5f * ds);
+    const float ex = ux - sj.x, ey = uy - sj.y, ez = uz - sj.z;
+    const float r2 = __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, ex * ex));
+    const bool in = r2 < rc2 && r2 > 0.f;
+    const int tj = (int)sj.w;
+    const float4 c = NT == 1 ? p0 : trow[tj];  // (24 eps_ij, sigma_ij, 12 / (24 eps_ij), 1 / sigma_ij)
+    const float ri2 = __builtin_amdgcn_rcpf(r2);
+    const float q = c.y * c.y * ri2;
+    const float q3 = q * q * q;
+    const float eq = c.x * q3;
+    float f = eq * __builtin_fmaf(2.f, q3, -1.f) * ri2;                  // force factor
+    float fp = eq * __builtin_fmaf(-14.f, q3, 4.f) * ri2 * ri2;          // df / d(r^2)
+    float fs = eq * __builtin_fmaf(12.f, q3, -3.f) * ri2 * c.w;          // half of d(f r^2 ...)/dsigma term
+    f = in ? f : 0.f;
+    fp = in ? fp : 0.f;
+    fs = in ? fs : 0.f;
+    const float dhx = hx - hj.x, dhy = hy - hj.y, dhz = hz - hj.z;
+    const float pp = __builtin_fmaf(dhz, ez, __builtin_fmaf(dhy, ey, dhx * ex));
+    const float c2 = 2.f * fp * pp;
+    acc[0] += __builtin_fmaf(f, dhx, c2 * ex);
+    acc[1] += __builtin_fmaf(f, dhy, c2 * ey);
+    acc[2] += __builtin_fmaf(f, dhz, c2 * ez);
+    acc[3] = __builtin_fmaf(f, ex, acc[3]);
+    acc[4] = __builtin_fmaf(f, ey, acc[4]);
+    acc[5] = __builtin_fmaf(f, ez, acc[5]);
+    pa.add(tj, pp * f * c.z, pp * fs, pg_row);
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_lj_adj_gather(LJAdjArgs A) {
+  const LJArgs& a = A.f;
+  __shared__ float4 tab[kMaxTypes * kMaxTypes];
+  __shared__ float4 src[4][kGTile], hsr[4][kGTile], tof[4][kGTile];
+  __shared__ float4 esh[4][64], eto[4][64];
+  __shared__ int eoff[4][64], ebeg[4][64], ebid[4][64];
+  __shared__ float red[4][6][64];
+  __shared__ float pg[4][2 * kMaxTypes * kMaxTypes];
+  const int lane = threadIdx.x & 63;
+  const int wid = uniform(threadIdx.x >> 6);
+  const int nt = a.n_types;
+  for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) {
+    const int ta = k / nt, tb = k % nt;
+    const float e24 = 24.f * sqrtf(a.eps_t[ta] * a.eps_t[tb]), sg = 0.5f * (a.sig_t[ta] + a.sig_t[tb]);
+    tab[k] = make_float4(e24, sg, 12.f / e24, 1.f / sg);
+  }
+  for (int k = threadIdx.x; k < 4 * 2 * kMaxTypes * kMaxTypes; k += blockDim.x) (&pg[0][0])[k] = 0.f;
+  __syncthreads();
+  const float4 p0 = tab[0];
+  const int32_t* tw0 = reinterpret_cast<const int32_t*>(a.tasks);
+  constexpr int kTaskWords = sizeof(gc_task) / 4;
+  const int g = uniform(blockIdx.x * 4 + wid);
+  if (g < a.n_tgt) {
+    const int4 tg = dev::gld(a.tgt + g);
+    const int id0 = uniform(tg.x), cnt = uniform(tg.y), e0 = uniform(tg.z), ne = uniform(tg.w);
+    const int en0 = uniform(dev::gld(a.ent + e0));
+    const int32_t* tw = tw0 + (int64_t)(en0 >> 1) * kTaskWords;
+    const int rb = (en0 & 1) ? uniform(dev::gld(a.ranges + uniform(dev::gld(tw + 2))).x)
+                             : (a.ibeg ? uniform(dev::gld(a.ibeg + (en0 >> 1))) : uniform(dev::gld(tw)));
+    for (int i0 = 0; i0 < cnt; i0 += 64) {
+      const int icc = cnt - i0 < 64 ? cnt - i0 : 64;
+      const int S = 64 / icc;
+      const int il = lane % icc, sl = lane / icc;
+      const bool active = sl < S;
+      float tx = 0.f, ty = 0.f, tz = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+      int ti = 0;
+      if (active) {
+        const float4 r = dev::gld(a.rec + rb + i0 + il);
+        tx = r.x; ty = r.y; tz = r.z;
+        ti = (int)r.w;
+        const float4 gc4 = dev::gld(A.cot + id0 + i0 + il);
+        const float m = A.mass_t[ti];
+        hx = gc4.x / m; hy = gc4.y / m; hz = gc4.z / m;
+      }
+      const float4* trow = tab + ti * nt;
+      float* pg_row = &pg[wid][2 * ti * nt];
+      ParamAcc<NT> pa;
+      pa.zero();
+      float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      const int DT = S * (kGTile / S);
+      for (int eg = 0; eg < ne; eg += 64) {
+        const int nen = ne - eg < 64 ? ne - eg : 64;
+        int n = 0, sb = 0, sid = 0;
+        float4 sh = make_float4(0.f, 0.f, 0.f, 0.f), to = sh;
+        if (lane < nen) {
+          const int en = dev::gld(a.ent + e0 + eg + lane);
+          const int t = en >> 1;
+          const int32_t* w = tw0 + (int64_t)t * kTaskWords;
+          const float s0 = __int_as_float(dev::gld(w + 7)), s1 = __int_as_float(dev::gld(w + 8)),
+                      s2 = __int_as_float(dev::gld(w + 9));
+          const float ax = s0 > 0.f ? s0 : 0.f, ay = s1 > 0.f ? s1 : 0.f, az = s2 > 0.f ? s2 : 0.f;
+          const float bx = s0 < 0.f ? s0 : 0.f, by = s1 < 0.f ? s1 : 0.f, bz = s2 < 0.f ? s2 : 0.f;
+          if (en & 1) {
+            sb = a.ibeg ? dev::gld(a.ibeg + t) : dev::gld(w);
+            sid = dev::gld(w);
+            n = dev::gld(w + 1);
+            sh = make_float4(-ax, -ay, -az, 0.f);
+            to = make_float4(bx, by, bz, 0.f);
+          } else {
+            const int jf = dev::gld(w + 2);
+            const int2 jr = dev::gld(a.ranges + jf);
+            sb = jr.x;
+            sid = dev::gld(a.ranges_id + jf).x;
+            n = jr.y;
+            sh = make_float4(bx, by, bz, 0.f);
+            to = make_float4(-ax, -ay, -az, 0.f);
+          }
+        }
+        int total;
+        const int off = dev::wave_excl_scan(n, &total);
+        total = uniform(total);
+        const bool shifted = __ballot(lane < nen && (to.x != 0.f || to.y != 0.f || to.z != 0.f)) != 0ull;
+        eoff[wid][lane] = lane < nen ? off : 0x7fffffff;
+        ebeg[wid][lane] = sb;
+        ebid[wid][lane] = sid;
+        esh[wid][lane] = sh;
+        eto[wid][lane] = to;
+        wave_sync();
+        for (int ws = 0; ws < total; ws += DT) {
+          const int c = total - ws < DT ? total - ws : DT;
+          const int C = (c + S - 1) / S;
+          const int padded = S * C;
+          for (int e = lane; e < padded; e += 64) {
+            float4 v = make_float4(kFar, kFar, kFar, 0.f), hv = make_float4(0.f, 0.f, 0.f, 0.f), o = hv;
+            if (e < c) {
+              const int f = ws + e;
+              int lo = 0, hi = nen - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (eoff[wid][mid] <= f) lo = mid;
+                else hi = mid - 1;
+              }
+              const int k = f - eoff[wid][lo];
+              const float4 r = dev::gld(a.rec + ebeg[wid][lo] + k);
+              const float4 q = esh[wid][lo];
+              v = make_float4(r.x + q.x, r.y + q.y, r.z + q.z, r.w);
+              const float4 gs = dev::gld(A.cot + ebid[wid][lo] + k);
+              const float ms = A.mass_t[(int)r.w];
+              hv = make_float4(gs.x / ms, gs.y / ms, gs.z / ms, 0.f);
+              o = eto[wid][lo];
+            }
+            src[wid][e] = v;
+            hsr[wid][e] = hv;
+            if (shifted) tof[wid][e] = o;
+          }
+          wave_sync();
+          if (active) {
+            if (shifted)
+              adj_gather_tile<NT, true>(&src[wid][sl * C], &hsr[wid][sl * C], &tof[wid][sl * C], C, tx, ty, tz, hx,
+                                        hy, hz, trow, p0, a.rc2, acc, pa, pg_row);
+            else
+              adj_gather_tile<NT, false>(&src[wid][sl * C], &hsr[wid][sl * C], nullptr, C, tx, ty, tz, hx, hy, hz,
+                                         trow, p0, a.rc2, acc, pa, pg_row);
+          }
+          wave_sync();
+        }
+      }
+      if (active) pa.flush(pg_row);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) red[wid][q][lane] = acc[q];
+      wave_sync();
+      if (lane < icc) {
+        float sm[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int sidx = 0; sidx < S; ++sidx)
+#pragma unroll
+          for (int q = 0; q < 6; ++q) sm[q] += red[wid][q][sidx * icc + lane];
+        const int id = id0 + i0 + lane;
+        const float4 g0 = dev::gld(A.gpos + id);
+        dev::gst(A.gpos + id, make_float4(g0.x + sm[0], g0.y + sm[1], g0.z + sm[2], g0.w));
+        dev::gst(A.force + id, make_float4(sm[3], sm[4], sm[5], 0.f));
+      }
+      wave_sync();
     }
   }
+  __syncthreads();
+  block_param_partial(A, &pg[0][0], nt);
 }
 
 __global__ void k_lj_mass_grad(const float4* __restrict__ cot, const float4* __restrict__ force,
@@ -469,13 +703,28 @@ hipError_t launch_node_chain(const int32_t* node_range, int32_t n_nodes, const f
   return hipGetLastError();
 }
 
+int lj_adjoint_blocks(const LJArgs& f, bool gather) { return gather ? (f.n_tgt + 3) / 4 : (f.n_runs + 3) / 4; }
+
 hipError_t launch_lj_adjoint(const LJAdjArgs& a, int wpb, hipStream_t s) {
   (void)wpb;
   if (a.f.n_runs <= 0) return hipSuccess;
-  const dim3 grid((a.f.n_runs + 3) / 4);
-  if (a.f.n_types == 1) hipLaunchKernelGGL(k_lj_adj<1>, grid, dim3(256), 0, s, a);
-  else if (a.f.n_types == 2) hipLaunchKernelGGL(k_lj_adj<2>, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_lj_adj<0>, grid, dim3(256), 0, s, a);
+  const int nb = lj_adjoint_blocks(a.f, false);
+  if (a.f.n_types == 1) hipLaunchKernelGGL(k_lj_adj<1>, dim3(nb), dim3(256), 0, s, a);
+  else if (a.f.n_types == 2) hipLaunchKernelGGL(k_lj_adj<2>, dim3(nb), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_lj_adj<0>, dim3(nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_lj_param_reduce, dim3(a.f.n_types * a.f.n_types), dim3(256), 0, s, a.ppart, nb, a.f.n_types,
+                     a.f.eps_t, a.gparam);
+  return hipGetLastError();
+}
+
+hipError_t launch_lj_adjoint_gather(const LJAdjArgs& a, hipStream_t s) {
+  if (a.f.n_tgt <= 0) return hipSuccess;
+  const int nb = lj_adjoint_blocks(a.f, true);
+  if (a.f.n_types == 1) hipLaunchKernelGGL(k_lj_adj_gather<1>, dim3(nb), dim3(256), 0, s, a);
+  else if (a.f.n_types == 2) hipLaunchKernelGGL(k_lj_adj_gather<2>, dim3(nb), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_lj_adj_gather<0>, dim3(nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_lj_param_reduce, dim3(a.f.n_types * a.f.n_types), dim3(256), 0, s, a.ppart, nb, a.f.n_types,
+                     a.f.eps_t, a.gparam);
   return hipGetLastError();
 }
 

@@ -185,8 +185,11 @@ struct LJAdjArgs {
   float4* gpos;
   float* gparam;           // 2 * n_types
   float4* force;           // forward forces by id (for the mass gradient)
+  float* ppart;            // per block: 2 n_types^2 partial parameter derivatives (lj_adjoint_blocks rows)
 };
+int lj_adjoint_blocks(const LJArgs& f, bool gather);
 hipError_t launch_lj_adjoint(const LJAdjArgs& a, int waves_per_block, hipStream_t s);
+hipError_t launch_lj_adjoint_gather(const LJAdjArgs& a, hipStream_t s);
 hipError_t launch_lj_mass_grad(const float4* cot, const float4* force, const float* mass_t,
                                const float4* rec_by_id, float* gmass, int32_t n, hipStream_t s);
 

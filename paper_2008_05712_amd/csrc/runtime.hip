@@ -114,7 +114,7 @@ struct gc_batch_ {
   DevBuf d_irank, d_jrank;
   // reorganisation buffers
   DevBuf uslot, missing, mslot, free_list, state, packed, ilist, jlist, queue;
-  DevBuf gnode, force;     // adjoint scratch: node gradients, recomputed LJ forces
+  DevBuf gnode, force, ppart;  // adjoint scratch: node gradients, recomputed LJ forces, LJ parameter partials
   // state of the last reorganisation
   int32_t mode = -1;
   gc_pool pool = nullptr;
@@ -294,7 +294,7 @@ extern "C" gc_status gc_batch_destroy(gc_batch b) {
   (void)hipDeviceSynchronize();
   for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs, &b->d_U,
                     &b->pranges, &b->pibeg, &b->d_irank, &b->d_jrank, &b->uslot, &b->missing, &b->mslot, &b->free_list,
-                    &b->state, &b->packed, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force, &b->d_ljtgt, &b->d_ljent})
+                    &b->state, &b->packed, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force, &b->ppart, &b->d_ljtgt, &b->d_ljent})
     d->release();
   delete b;
   return GC_OK;
@@ -922,7 +922,7 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
   if (!gparam_dev) return set_err(c, GC_E_INVAL, "gc_backward: Lennard-Jones needs gparam");
   if (b->force.ensure(sizeof(float4) * (size_t)b->n_ids) != hipSuccess)
     return set_err(c, GC_E_NOMEM, "gc_backward: force buffer");
-  GC_HIP(c, launch_fill_f32(b->force.as<float>(), 0.f, 4 * (int64_t)b->n_ids, s));
+  if (!b->lj_gather || !b->lj_cover) GC_HIP(c, launch_fill_f32(b->force.as<float>(), 0.f, 4 * (int64_t)b->n_ids, s));
   LJAdjArgs a{};
   a.f.tasks = b->d_tasks.as<gc_task>();
   a.f.n_tasks = T;
@@ -941,7 +941,17 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
   a.gpos = reinterpret_cast<float4*>(gpos_dev);
   a.gparam = gparam_dev;
   a.force = b->force.as<float4>();
-  GC_HIP(c, launch_lj_adjoint(a, 4, s));
+  a.f.tgt = b->d_ljtgt.as<int4>();
+  a.f.ent = b->d_ljent.as<int32_t>();
+  a.f.n_tgt = b->n_ljtgt;
+  {
+    const size_t rows = (size_t)std::max(1, lj_adjoint_blocks(a.f, b->lj_gather));
+    if (b->ppart.ensure(sizeof(float) * rows * 2 * prm->n_types * prm->n_types) != hipSuccess)
+      return set_err(c, GC_E_NOMEM, "gc_backward: parameter partials");
+    a.ppart = b->ppart.as<float>();
+  }
+  if (b->lj_gather) GC_HIP(c, launch_lj_adjoint_gather(a, s));
+  else GC_HIP(c, launch_lj_adjoint(a, 4, s));
   GC_HIP(c, launch_lj_mass_grad(a.cot, a.force, prm->mass_t, b->pool->src, gmass_dev, b->n_ids, s));
   return GC_OK;
 }

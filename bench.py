@@ -455,6 +455,18 @@ def main():
     forms["timed_vs_eager_indirect"] = round(forms["eager_indirect_ms"] / ms_step, 3)
     if graph is not None and form == "step":
         step_kernel_ms = time_kernel(lambda: graph.launch(stream=stream), stream, reps=10)
+    # the same whole-step launch with the source records in pinned host memory: the staging of the
+    # missing records reads them across PCIe (the boundary's host-buffer path; never the bench value)
+    if not args.quick and sprm is not None:
+        hsrc = torch.from_numpy(np.ascontiguousarray(w.rec)).pin_memory()
+        pool.set_source(hsrc)
+        hg = capture("step", sprm)
+        hms = time_kernel(lambda: hg.launch(stream=stream), stream, reps=10)
+        hg.destroy()
+        pool.set_source(src)
+        forms["step_graph_pinned_host_source_ms"] = round(hms, 4)
+        forms["pinned_host_source_ginteractions_per_s"] = round(interactions / (hms * 1e-3) / 1e9, 3)
+        del hsrc
 
     # ---- per-phase device times with HIP events on the launch stream (eager, same work)
     def phases(m, reps):

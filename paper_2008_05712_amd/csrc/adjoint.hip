@@ -477,7 +477,8 @@ __global__ void __launch_bounds__(256) k_lj_adj(LJAdjArgs A) {
 // cutoff arithmetic).  Each target atom's dL/dx is added to gpos and its recomputed force written
 // to `force` by one wavefront; the parameter derivatives go through per-lane sums keyed by the
 // source type, the block's LDS, then one atomic per type pair and block.
-constexpr int kGTile = 128;
+constexpr int kGTile = 64;   // source records per LDS tile per wavefront
+constexpr int kEGroup = 32;  // tasks whose sources a wavefront stages at a time
 constexpr float kFar = 1e18f;
 
 template <int NT, bool SHIFTED>
@@ -527,13 +528,19 @@ template <int NT>
 __global__ void __launch_bounds__(256) k_lj_adj_gather(LJAdjArgs A) {
   const LJArgs& a = A.f;
   __shared__ float4 tab[kMaxTypes * kMaxTypes];
-  __shared__ float4 src[4][kGTile], hsr[4][kGTile], tof[4][kGTile];
-  __shared__ float4 esh[4][64], eto[4][64];
-  __shared__ int eoff[4][64], ebeg[4][64], ebid[4][64];
-  __shared__ float red[4][6][64];
+  // per wavefront: sources, their g / m, their target-side shifts; the slice reduction at the end
+  // reuses the area
+  __shared__ float4 sbuf[4][3 * kGTile];
+  __shared__ float4 esh[4][kEGroup], eto[4][kEGroup];
+  __shared__ int eoff[4][kEGroup], ebeg[4][kEGroup], ebid[4][kEGroup];
   __shared__ float pg[4][2 * kMaxTypes * kMaxTypes];
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
+  float4* src = sbuf[wid];
+  float4* hsr = sbuf[wid] + kGTile;
+  float4* tof = sbuf[wid] + 2 * kGTile;
+  float* red = reinterpret_cast<float*>(sbuf[wid]);  // 6 x 64 floats
+  static_assert(3 * kGTile * 4 >= 6 * 64, "reduction area");
   const int nt = a.n_types;
   for (int k = threadIdx.x; k < nt * nt; k += blockDim.x) {
     const int ta = k / nt, tb = k % nt;
@@ -574,8 +581,8 @@ __global__ void __launch_bounds__(256) k_lj_adj_gather(LJAdjArgs A) {
       pa.zero();
       float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       const int DT = S * (kGTile / S);
-      for (int eg = 0; eg < ne; eg += 64) {
-        const int nen = ne - eg < 64 ? ne - eg : 64;
+      for (int eg = 0; eg < ne; eg += kEGroup) {
+        const int nen = ne - eg < kEGroup ? ne - eg : kEGroup;
         int n = 0, sb = 0, sid = 0;
         float4 sh = make_float4(0.f, 0.f, 0.f, 0.f), to = sh;
         if (lane < nen) {
@@ -606,11 +613,13 @@ __global__ void __launch_bounds__(256) k_lj_adj_gather(LJAdjArgs A) {
         const int off = dev::wave_excl_scan(n, &total);
         total = uniform(total);
         const bool shifted = __ballot(lane < nen && (to.x != 0.f || to.y != 0.f || to.z != 0.f)) != 0ull;
-        eoff[wid][lane] = lane < nen ? off : 0x7fffffff;
-        ebeg[wid][lane] = sb;
-        ebid[wid][lane] = sid;
-        esh[wid][lane] = sh;
-        eto[wid][lane] = to;
+        if (lane < kEGroup) {
+          eoff[wid][lane] = lane < nen ? off : 0x7fffffff;
+          ebeg[wid][lane] = sb;
+          ebid[wid][lane] = sid;
+          esh[wid][lane] = sh;
+          eto[wid][lane] = to;
+        }
         wave_sync();
         for (int ws = 0; ws < total; ws += DT) {
           const int c = total - ws < DT ? total - ws : DT;
@@ -635,17 +644,17 @@ __global__ void __launch_bounds__(256) k_lj_adj_gather(LJAdjArgs A) {
               hv = make_float4(gs.x / ms, gs.y / ms, gs.z / ms, 0.f);
               o = eto[wid][lo];
             }
-            src[wid][e] = v;
-            hsr[wid][e] = hv;
-            if (shifted) tof[wid][e] = o;
+            src[e] = v;
+            hsr[e] = hv;
+            if (shifted) tof[e] = o;
           }
           wave_sync();
           if (active) {
             if (shifted)
-              adj_gather_tile<NT, true>(&src[wid][sl * C], &hsr[wid][sl * C], &tof[wid][sl * C], C, tx, ty, tz, hx,
+              adj_gather_tile<NT, true>(src + sl * C, hsr + sl * C, tof + sl * C, C, tx, ty, tz, hx,
                                         hy, hz, trow, p0, a.rc2, acc, pa, pg_row);
             else
-              adj_gather_tile<NT, false>(&src[wid][sl * C], &hsr[wid][sl * C], nullptr, C, tx, ty, tz, hx, hy, hz,
+              adj_gather_tile<NT, false>(src + sl * C, hsr + sl * C, nullptr, C, tx, ty, tz, hx, hy, hz,
                                          trow, p0, a.rc2, acc, pa, pg_row);
           }
           wave_sync();
@@ -653,13 +662,13 @@ __global__ void __launch_bounds__(256) k_lj_adj_gather(LJAdjArgs A) {
       }
       if (active) pa.flush(pg_row);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) red[wid][q][lane] = acc[q];
+      for (int q = 0; q < 6; ++q) red[q * 64 + lane] = acc[q];
       wave_sync();
       if (lane < icc) {
         float sm[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int sidx = 0; sidx < S; ++sidx)
 #pragma unroll
-          for (int q = 0; q < 6; ++q) sm[q] += red[wid][q][sidx * icc + lane];
+          for (int q = 0; q < 6; ++q) sm[q] += red[q * 64 + sidx * icc + lane];
         const int id = id0 + i0 + lane;
         const float4 g0 = dev::gld(A.gpos + id);
         dev::gst(A.gpos + id, make_float4(g0.x + sm[0], g0.y + sm[1], g0.z + sm[2], g0.w));

@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) k_lj(LJArgs a) {
 // per pair doubles against the half-shell form above, but a pair costs about 20 VALU operations
 // there and the atomics, per-task waits and LDS atomics of the half-shell form cost more.
 //
-// A wavefront stages the sources of up to 64 tasks at a time in LDS tiles (shifted as below) and
+// A wavefront stages the sources of up to 32 tasks at a time in LDS tiles (shifted as below) and
 // splits its 64 lanes into (target atom) x (source slice) as the gravity kernel does; the slices
 // are reduced through LDS at the end.  The cutoff decision takes the same FP32 operations as the
 // half-shell form, from either side: for a task with shift s, a = max(s, 0), b = min(s, 0), the
@@ -185,7 +185,8 @@ __global__ void __launch_bounds__(256) k_lj(LJArgs a) {
 // The per-task shift sits on the source when staged (x_j + b, or x_i + (-a)); on the target side
 // it is added per pair, only in cells that have tasks across the periodic boundary (x + (-a) and
 // x - a round alike).  A zero separation is the atom itself (a cell's self task) and adds nothing.
-constexpr int kGTile = 128;  // source records per LDS tile per wavefront
+constexpr int kGTile = 64;   // source records per LDS tile per wavefront
+constexpr int kEGroup = 32;  // tasks whose sources a wavefront stages at a time
 constexpr float kFar = 1e18f;  // padding sources: r^2 ~ 3e36, finite and outside any cutoff
 
 template <bool SHIFTED, bool ONE>
@@ -221,8 +222,8 @@ __global__ void __launch_bounds__(256) k_lj_gather(LJArgs a) {
   __shared__ float2 tab[kMaxTypes * kMaxTypes];  // (24 eps_ij, sigma_ij^2)
   __shared__ float4 src[4][kGTile];              // sources, shifted; padding far away
   __shared__ float4 tof[4][kGTile];              // per source: its task's target-side shift
-  __shared__ float4 esh[4][64], eto[4][64];      // per task of the group: source and target shifts
-  __shared__ int eoff[4][64], ebeg[4][64];       // per task: first flat source, first source record
+  __shared__ float4 esh[4][kEGroup], eto[4][kEGroup];  // per task of the group: source and target shifts
+  __shared__ int eoff[4][kEGroup], ebeg[4][kEGroup];   // per task: first flat source, first source record
   __shared__ float fr[4][3][64];
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
@@ -272,8 +273,8 @@ __global__ void __launch_bounds__(256) k_lj_gather(LJArgs a) {
       const float2* trow = tab + ti * a.n_types;
       float Fx = 0.f, Fy = 0.f, Fz = 0.f;
       const int DT = S * (kGTile / S);
-      for (int eg = 0; eg < ne; eg += 64) {
-        const int nen = ne - eg < 64 ? ne - eg : 64;
+      for (int eg = 0; eg < ne; eg += kEGroup) {
+        const int nen = ne - eg < kEGroup ? ne - eg : kEGroup;
         int n = 0, sb = 0;
         float4 sh = make_float4(0.f, 0.f, 0.f, 0.f), to = sh;
         if (lane < nen) {
@@ -301,10 +302,12 @@ __global__ void __launch_bounds__(256) k_lj_gather(LJArgs a) {
         const int off = dev::wave_excl_scan(n, &total);
         total = uniform(total);
         const bool shifted = __ballot(lane < nen && (to.x != 0.f || to.y != 0.f || to.z != 0.f)) != 0ull;
-        eoff[wid][lane] = lane < nen ? off : 0x7fffffff;
-        ebeg[wid][lane] = sb;
-        esh[wid][lane] = sh;
-        eto[wid][lane] = to;
+        if (lane < kEGroup) {
+          eoff[wid][lane] = lane < nen ? off : 0x7fffffff;
+          ebeg[wid][lane] = sb;
+          esh[wid][lane] = sh;
+          eto[wid][lane] = to;
+        }
         wave_sync();
         for (int ws = 0; ws < total; ws += DT) {
           const int c = total - ws < DT ? total - ws : DT;

@@ -11,7 +11,7 @@ using dev::grav_task;
 using dev::uniform;
 
 template <int ORDER, bool LISTS, bool PERSIST, bool TWO>
-__global__ void __launch_bounds__(512) k_grav(GravArgs a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k_grav(GravArgs a) {
   extern __shared__ float4 smem[];
   __shared__ int s_task;
   int iter = 0;

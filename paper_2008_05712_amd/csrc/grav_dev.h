@@ -231,11 +231,13 @@ __device__ __forceinline__ void node_prefetch(const float4* __restrict__ nodes, 
   pf.cur = load_node<ORDER>(nodes, lane < nw ? nl[lane * W] : -1);
 }
 
-// Records of LDS per wavefront for a direct tile of `tile` records: the larger of a direct tile
-// (+64 padding) and a quadrupole node tile (3 records per node), plus 96 records of reduction
-// scratch.
+// Records of LDS per wavefront for a direct tile of `tile` records: the larger of a direct tile and
+// a quadrupole node tile (3 records per node), plus 96 records of reduction scratch.  A tile holds a
+// multiple of the slice count S and is padded to S * ceil(count / S) records, which never exceeds
+// that multiple, so the padding needs no room of its own.  (The larger area also holds the 6 x 64
+// FP64 sums of the two-targets reduction: 192 records.)
 __host__ __device__ __forceinline__ int grav_rec_cap(int tile) {
-  return (tile + 64 > 3 * (kNodeTile + 64)) ? tile + 64 : 3 * (kNodeTile + 64);
+  return tile > 3 * kNodeTile ? tile : 3 * kNodeTile;
 }
 __host__ __device__ __forceinline__ int grav_lds_per_wave(int tile) { return grav_rec_cap(tile) + 96; }
 

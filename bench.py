@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 METRIC = "G-interactions/s combined force kernel (%FP32 peak); reorganize GB/s; bwd/fwd"
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector (packed); plain FMA issue gives half: 78.6
 PEAK_FP32_NONPACKED_TFLOPS = 78.6
+N_SIMD, CLOCK_GHZ = 256 * 4, 2.4   # MI355X: 256 CUs x 4 SIMDs at 2.4 GHz
+LJ_VALU_PER_EVAL = 20.5            # Lennard-Jones gather loop: 41 VALU instructions per two pair evaluations
 PEAK_HBM_GBPS = 8000.0
 FLOPS_PAIR, FLOPS_QUAD = 19, 51   # per interaction, from the implemented formulas
 # algorithmic bytes of one reorganisation: per union entry the id, its slot_of entry, its slot out,
@@ -179,6 +181,16 @@ def leg_lj(gc, W, torch, ctx):
     # from the density (reported exactly by the parity tests' oracle runs)
     cand = w.candidates()
     out.update({"candidates": cand, "candidates_per_s_G": round(cand / (ms * 1e-3) / 1e9, 3), "ms": ms})
+    # the gather form evaluates a pair of two different cells from both sides and a cell's self task
+    # over all its atoms (the atom itself gives a zero separation): pair evaluations per launch, and
+    # the VALU issue they take at LJ_VALU_PER_EVAL wavefront-lane slots each (the one-type loop) as a
+    # fraction of the chip's issue rate, 4 cycles per wavefront instruction per SIMD
+    ic = w.i_count.astype(np.int64)
+    jc = w.j_count.astype(np.int64)
+    evals = int(np.sum(np.where(w.self_flag != 0, ic * ic, 2 * ic * jc)))
+    issue_ms = evals * LJ_VALU_PER_EVAL / 64 * 4 / (N_SIMD * CLOCK_GHZ * 1e9) * 1e3
+    out.update({"pair_evaluations": evals, "valu_issue_ms": round(issue_ms, 4),
+                "valu_issue_frac": round(issue_ms / ms, 4)})
     b.destroy()
     pool.destroy()
     return out

@@ -376,6 +376,36 @@ gc_status gc_autotune(gc_batch batch, const gc_force_params* base, const float* 
 /* Occupancy of the combined gravity kernel: resident blocks per CU and CU count. */
 gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_t* blocks_per_cu, int32_t* n_cu);
 
+/* ---------------------------------------------------------------- combining policy */
+
+/*
+ * When to launch a combined kernel over a stream of arriving work requests
+ * (Sec. 3.1).  max_size is the number of requests that fill the GPU at full
+ * occupancy; with one workgroup per request (GC_SCHED_TASKS) it is the
+ * resident blocks per CU times the CU count (gc_occupancy).  The combiner
+ * records the arrival times and keeps the largest interval seen between two
+ * consecutive arrivals, max_interval.  At each poll: if at least max_size
+ * requests wait, the first max_size of them are to be combined; otherwise, if
+ * some wait and the time since the last arrival exceeds 2 * max_interval, all
+ * of them are.  Requests leave in arrival order; the caller keeps them and
+ * submits the ones taken into a batch.  Pure host logic: times are the
+ * caller's clock in seconds, non-decreasing across arrive and poll calls
+ * (GC_E_INVAL otherwise, state unchanged).  Before a second arrival no interval
+ * is known (max_interval = 0), so a poll after any time has passed takes what
+ * waits.  A combiner is not thread-safe.
+ */
+typedef struct gc_combiner_* gc_combiner;
+gc_status gc_combiner_create(int32_t max_size, gc_combiner* out);  /* max_size >= 1 */
+gc_status gc_combiner_destroy(gc_combiner comb);
+/* n >= 1 requests arrive at time t (as n arrivals at the same instant: interval 0 between them). */
+gc_status gc_combiner_arrive(gc_combiner comb, double t, int64_t n);
+/* At time t: *take = the number of waiting requests to combine now (0: keep waiting); they leave
+ * the waiting count.  *reason (may be NULL): 0 none, 1 max_size reached, 2 idle for 2 * max_interval. */
+gc_status gc_combiner_poll(gc_combiner comb, double t, int64_t* take, int32_t* reason);
+/* Waiting requests, max_interval (s), and the launches decided so far by each rule (any may be NULL). */
+gc_status gc_combiner_state(gc_combiner comb, int64_t* waiting, double* max_interval, int64_t* n_full,
+                            int64_t* n_idle);
+
 #ifdef __cplusplus
 }
 #endif

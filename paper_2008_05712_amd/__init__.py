@@ -13,7 +13,7 @@ import os
 
 import numpy as np
 
-__all__ = ["GcError", "lib", "Context", "Pool", "Batch", "Graph", "ForceParams", "TASK_DTYPE",
+__all__ = ["GcError", "lib", "Context", "Pool", "Batch", "Graph", "Combiner", "ForceParams", "TASK_DTYPE",
            "REORG_REDUNDANT", "REORG_INDIRECT", "REORG_SORTED", "REORG_PACK", "REORG_NONE",
            "FORCE_GRAV_MONO", "FORCE_GRAV_QUAD", "FORCE_LJ", "KIND_GRAV", "KIND_LJ", "TASK_SELF",
            "FIXTURE_NONE", "FIXTURE_RESET_PLACE", "FIXTURE_EVICT_STAGED", "SCHED_TASKS", "SCHED_QUEUE", "SCHED_STEP",
@@ -39,7 +39,8 @@ EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_pool_cr
             "gc_pool_query", "gc_pool_device_ptrs",
             "gc_batch_create", "gc_batch_destroy", "gc_batch_reset", "gc_submit_tasks", "gc_batch_commit",
             "gc_batch_sizes", "gc_reorganize", "gc_batch_maps", "gc_launch_combined", "gc_zero_f32", "gc_backward",
-            "gc_graph_capture", "gc_graph_launch", "gc_graph_destroy", "gc_autotune", "gc_occupancy"]
+            "gc_graph_capture", "gc_graph_launch", "gc_graph_destroy", "gc_autotune", "gc_occupancy",
+            "gc_combiner_create", "gc_combiner_destroy", "gc_combiner_arrive", "gc_combiner_poll", "gc_combiner_state"]
 
 
 class GcError(RuntimeError):
@@ -111,6 +112,11 @@ def lib():
         "gc_graph_destroy": (I32, [VP]),
         "gc_autotune": (I32, [VP, ctypes.POINTER(ForceParams), VP, VP, I32, VP, ctypes.POINTER(ForceParams), VP]),
         "gc_occupancy": (I32, [VP, ctypes.POINTER(ForceParams), PI32, PI32]),
+        "gc_combiner_create": (I32, [I32, ctypes.POINTER(VP)]),
+        "gc_combiner_destroy": (I32, [VP]),
+        "gc_combiner_arrive": (I32, [VP, ctypes.c_double, I64]),
+        "gc_combiner_poll": (I32, [VP, ctypes.c_double, PI64, PI32]),
+        "gc_combiner_state": (I32, [VP, PI64, ctypes.POINTER(ctypes.c_double), PI64, PI64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -169,6 +175,41 @@ class Context:
     def close(self):
         if self.h:
             lib().gc_finalize(self.h)
+            self.h = VP()
+
+
+class Combiner:
+    """The arrival-rate combining policy (gc_combiner_*): host logic, the caller's clock in seconds."""
+
+    def __init__(self, max_size: int):
+        self.h = VP()
+        st = lib().gc_combiner_create(int(max_size), ctypes.byref(self.h))
+        if st != GC_OK:
+            raise GcError(st, f"gc_combiner_create({max_size})")
+
+    def arrive(self, t: float, n: int = 1):
+        st = lib().gc_combiner_arrive(self.h, float(t), int(n))
+        if st != GC_OK:
+            raise GcError(st, f"gc_combiner_arrive(t={t}, n={n})")
+
+    def poll(self, t: float) -> tuple[int, int]:
+        """(requests to combine now, reason: 0 none, 1 max_size reached, 2 idle)."""
+        k, why = ctypes.c_int64(), ctypes.c_int32()
+        st = lib().gc_combiner_poll(self.h, float(t), ctypes.byref(k), ctypes.byref(why))
+        if st != GC_OK:
+            raise GcError(st, f"gc_combiner_poll(t={t})")
+        return k.value, why.value
+
+    def state(self) -> dict:
+        w, mi, nf, ni = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        st = lib().gc_combiner_state(self.h, ctypes.byref(w), ctypes.byref(mi), ctypes.byref(nf), ctypes.byref(ni))
+        if st != GC_OK:
+            raise GcError(st, "gc_combiner_state")
+        return {"waiting": w.value, "max_interval": mi.value, "n_full": nf.value, "n_idle": ni.value}
+
+    def destroy(self):
+        if self.h:
+            lib().gc_combiner_destroy(self.h)
             self.h = VP()
 
 

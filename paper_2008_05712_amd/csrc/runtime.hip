@@ -871,6 +871,73 @@ extern "C" gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_
   return GC_OK;
 }
 
+// ===================================================================== combining policy (Sec. 3.1)
+
+struct gc_combiner_ {
+  int32_t max_size = 1;
+  int64_t waiting = 0;
+  bool any = false;        // an arrival has been seen
+  double t_last = 0.0;     // time of the last arrival
+  double t_now = 0.0;      // latest time given (arrive or poll)
+  double max_interval = 0.0;
+  int64_t n_full = 0, n_idle = 0;
+};
+
+extern "C" gc_status gc_combiner_create(int32_t max_size, gc_combiner* out) {
+  if (!out || max_size < 1) return GC_E_INVAL;
+  gc_combiner c = new (std::nothrow) gc_combiner_();
+  if (!c) return GC_E_NOMEM;
+  c->max_size = max_size;
+  *out = c;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_combiner_destroy(gc_combiner c) {
+  if (!c) return GC_E_INVAL;
+  delete c;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_combiner_arrive(gc_combiner c, double t, int64_t n) {
+  if (!c || n < 1 || !(t >= c->t_now)) return GC_E_INVAL;
+  if (c->any) c->max_interval = std::max(c->max_interval, t - c->t_last);
+  c->any = true;
+  c->t_last = t;
+  c->t_now = t;
+  c->waiting += n;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_combiner_poll(gc_combiner c, double t, int64_t* take, int32_t* reason) {
+  if (!c || !take || !(t >= c->t_now)) return GC_E_INVAL;
+  c->t_now = t;
+  int64_t k = 0;
+  int32_t why = 0;
+  if (c->waiting >= c->max_size) {
+    k = c->max_size;
+    why = 1;
+    ++c->n_full;
+  } else if (c->waiting > 0 && t - c->t_last > 2.0 * c->max_interval) {
+    k = c->waiting;
+    why = 2;
+    ++c->n_idle;
+  }
+  c->waiting -= k;
+  *take = k;
+  if (reason) *reason = why;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_combiner_state(gc_combiner c, int64_t* waiting, double* max_interval, int64_t* n_full,
+                                       int64_t* n_idle) {
+  if (!c) return GC_E_INVAL;
+  if (waiting) *waiting = c->waiting;
+  if (max_interval) *max_interval = c->max_interval;
+  if (n_full) *n_full = c->n_full;
+  if (n_idle) *n_idle = c->n_idle;
+  return GC_OK;
+}
+
 // ===================================================================== backward (adjoint)
 
 extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const float* nodes_dev,

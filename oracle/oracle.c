@@ -15,7 +15,25 @@
  *  - Lennard-Jones over cell-pair compute objects (Sec. 4.2: one object per
  *    pair of patches updates both), and brute force with minimum image;
  *  - analytic vector-Jacobian products (gravity: direct + monopole with the
- *    node chain rule; Lennard-Jones: positions, masses, per-type eps/sigma).
+ *    node chain rule; Lennard-Jones: positions, masses, per-type eps/sigma);
+ *  - the Ewald correction of periodic gravity (ChaNGa's second combined
+ *    kernel, Sec. 4.1, Sec. 4.3): the pull of every periodic image of the box's
+ *    total mass M at its centre of mass c, plus the neutralising background,
+ *    minus the direct 1/r of the central copy that the tree walk computes.
+ *
+ * Ewald (cubic box of side L, splitting parameter alpha; r = x - c taken to
+ * the nearest image; real-space images n in {-nrep..nrep}^3; wave vectors
+ * h in Z^3 with 0 < |h|^2 <= hmax2):
+ *   phi(x) = -G M [ sum_{n != 0} erfc(alpha s_n)/s_n + (erfc(alpha s_0) - 1)/s_0
+ *                  + 1/(pi L) sum_h exp(-pi^2 |h|^2/(alpha L)^2)/|h|^2 cos(2 pi h.r/L)
+ *                  - pi/(alpha^2 L^3) ],   s_n = |r + n L|
+ *   a(x) = -grad phi = G M [ sum_{n != 0} -(erfc(alpha s)/s^3 + 2 alpha/sqrt(pi) e^{-alpha^2 s^2}/s^2) s_vec
+ *                           + (erf(alpha s)/s^3 - 2 alpha/sqrt(pi) e^{-alpha^2 s^2}/s^2) s_vec   (n = 0)
+ *                           - 2/L^2 sum_h exp(-pi^2 |h|^2/(alpha L)^2)/|h|^2 sin(2 pi h.r/L) h ].
+ * The n = 0 terms take their Taylor series near s = 0 (erf(x)/x^3 - 2/sqrt(pi)
+ * e^{-x^2}/x^2 = 2/sqrt(pi) (2/3 - 2/5 x^2 + 1/7 x^4 - 1/27 x^6 + 1/132 x^8 - ...),
+ * (erfc(x) - 1)/x = -2/sqrt(pi) (1 - x^2/3 + x^4/10 - x^6/42 + ...)), where the
+ * direct forms cancel.
  *
  * Formulas (G, softening eps):
  *   pair:      a_i += G m_j u / s^3,   u = x_j - x_i, s^2 = |u|^2 + eps^2, j != i
@@ -538,4 +556,75 @@ void or_lj_tasks_at(int32_t ntasks, const int32_t* i_begin, const int32_t* i_cou
   for (int64_t i = 0; i < n; ++i)
     for (int c = 0; c < 3; ++c) acc[3 * i + c] = F[3 * i + c] / mass[i];
   free(F);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ewald correction of periodic gravity                                     */
+/* ------------------------------------------------------------------------ */
+
+/* x * (erf(a s)/s^3 - 2a/sqrt(pi) e^{-a^2 s^2}/s^2) / a^3 = f(a s) and (erfc(a s) - 1)/s / a = g(a s). */
+static double ew_f0(double x) {
+  const double c = 2.0 / sqrt(M_PI);
+  if (x < 0.1) {
+    double x2 = x * x;
+    return c * (2.0 / 3.0 + x2 * (-2.0 / 5.0 + x2 * (1.0 / 7.0 + x2 * (-1.0 / 27.0 + x2 * (1.0 / 132.0)))));
+  }
+  return erf(x) / (x * x * x) - c * exp(-x * x) / (x * x);
+}
+static double ew_g0(double x) {
+  const double c = 2.0 / sqrt(M_PI);
+  if (x < 0.1) {
+    double x2 = x * x;
+    return -c * (1.0 + x2 * (-1.0 / 3.0 + x2 * (1.0 / 10.0 + x2 * (-1.0 / 42.0))));
+  }
+  return (erfc(x) - 1.0) / x;
+}
+
+/* acc (n x 3) = the Ewald correction at each position; pot (optional, n) its potential phi. */
+void or_ewald(int64_t n, const double* pos, double L, double G, double M, const double* c, double alpha, int32_t nrep,
+              int32_t hmax2, double* acc, double* pot) {
+  const double sp = 2.0 / sqrt(M_PI);
+  int hm = 0;
+  while ((hm + 1) * (hm + 1) <= hmax2) ++hm;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    double r[3];
+    for (int d = 0; d < 3; ++d) {
+      r[d] = pos[3 * i + d] - c[d];
+      r[d] -= L * nearbyint(r[d] / L);
+    }
+    double a[3] = {0, 0, 0}, p = 0;
+    for (int nx = -nrep; nx <= nrep; ++nx)
+      for (int ny = -nrep; ny <= nrep; ++ny)
+        for (int nz = -nrep; nz <= nrep; ++nz) {
+          double sv[3] = {r[0] + nx * L, r[1] + ny * L, r[2] + nz * L};
+          double s = sqrt(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+          double k, q;
+          if (nx == 0 && ny == 0 && nz == 0) {
+            k = alpha * alpha * alpha * ew_f0(alpha * s);
+            q = alpha * ew_g0(alpha * s);
+          } else {
+            k = -(erfc(alpha * s) / (s * s * s) + sp * alpha * exp(-alpha * alpha * s * s) / (s * s));
+            q = erfc(alpha * s) / s;
+          }
+          for (int d = 0; d < 3; ++d) a[d] += k * sv[d];
+          p += q;
+        }
+    for (int hx = -hm; hx <= hm; ++hx)
+      for (int hy = -hm; hy <= hm; ++hy)
+        for (int hz = -hm; hz <= hm; ++hz) {
+          int h2 = hx * hx + hy * hy + hz * hz;
+          if (h2 == 0 || h2 > hmax2) continue;
+          double w = exp(-M_PI * M_PI * h2 / (alpha * alpha * L * L)) / h2;
+          double th = 2.0 * M_PI * (hx * r[0] + hy * r[1] + hz * r[2]) / L;
+          double sn = sin(th);
+          a[0] += -2.0 / (L * L) * w * sn * hx;
+          a[1] += -2.0 / (L * L) * w * sn * hy;
+          a[2] += -2.0 / (L * L) * w * sn * hz;
+          p += w * cos(th) / (M_PI * L);
+        }
+    p -= M_PI / (alpha * alpha * L * L * L);
+    for (int d = 0; d < 3; ++d) acc[3 * i + d] = G * M * a[d];
+    if (pot) pot[i] = -G * M * p;
+  }
 }

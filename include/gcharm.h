@@ -376,6 +376,37 @@ gc_status gc_autotune(gc_batch batch, const gc_force_params* base, const float* 
 /* Occupancy of the combined gravity kernel: resident blocks per CU and CU count. */
 gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_t* blocks_per_cu, int32_t* n_cu);
 
+/* ---------------------------------------------------------------- Ewald correction */
+
+/*
+ * Periodic gravity (Sec. 4.1: ChaNGa's Ewald summation kernel, combined like
+ * the force requests, Sec. 4.3).  For a cubic box of side L holding total
+ * mass M with centre of mass com, the correction at a target x, with
+ * r = x - com taken to the nearest image, is the pull of every periodic image
+ * of M plus the neutralising background, less the central copy's direct pull
+ * (which the tree walk computes):
+ *   a = G M [ sum_{n != 0} -(erfc(alpha s)/s^3 + 2 alpha/sqrt(pi) e^{-alpha^2 s^2}/s^2) s_vec
+ *           + (erf(alpha s)/s^3 - 2 alpha/sqrt(pi) e^{-alpha^2 s^2}/s^2) s_vec   (n = 0)
+ *           - 2/L^2 sum_h e^{-pi^2 |h|^2/(alpha L)^2}/|h|^2 sin(2 pi h.r/L) h ],
+ * s_vec = r + n L over images n in {-nrep..nrep}^3 and wave vectors h in Z^3
+ * with 0 < |h|^2 <= hmax2.  alpha = 0 takes 2 / L.  Valid: L > 0, alpha >= 0,
+ * 0 <= nrep <= 4, 0 <= hmax2 <= 64 (GC_E_INVAL otherwise).
+ */
+typedef struct {
+  float L, G, M;
+  float com[3];
+  float alpha;
+  int32_t nrep;
+  int32_t hmax2;
+} gc_ewald_params;
+
+/*
+ * Adds the correction to acc_dev (float4 [n_ids]; x, y, z) for every target of
+ * every task of a reorganised gravity batch, in one launch, reading the
+ * targets' records as the combined pass does.  Asynchronous.
+ */
+gc_status gc_launch_ewald(gc_batch batch, const gc_ewald_params* prm, float* acc_dev, void* stream);
+
 /* ---------------------------------------------------------------- combining policy */
 
 /*

@@ -13,7 +13,8 @@ import os
 
 import numpy as np
 
-__all__ = ["GcError", "lib", "Context", "Pool", "Batch", "Graph", "Combiner", "ForceParams", "TASK_DTYPE",
+__all__ = ["GcError", "lib", "Context", "Pool", "Batch", "Graph", "Combiner", "ForceParams", "EwaldParams",
+           "ewald_params", "TASK_DTYPE",
            "REORG_REDUNDANT", "REORG_INDIRECT", "REORG_SORTED", "REORG_PACK", "REORG_NONE",
            "FORCE_GRAV_MONO", "FORCE_GRAV_QUAD", "FORCE_LJ", "KIND_GRAV", "KIND_LJ", "TASK_SELF",
            "FIXTURE_NONE", "FIXTURE_RESET_PLACE", "FIXTURE_EVICT_STAGED", "SCHED_TASKS", "SCHED_QUEUE", "SCHED_STEP",
@@ -40,7 +41,22 @@ EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_pool_cr
             "gc_batch_create", "gc_batch_destroy", "gc_batch_reset", "gc_submit_tasks", "gc_batch_commit",
             "gc_batch_sizes", "gc_reorganize", "gc_batch_maps", "gc_launch_combined", "gc_zero_f32", "gc_backward",
             "gc_graph_capture", "gc_graph_launch", "gc_graph_destroy", "gc_autotune", "gc_occupancy",
-            "gc_combiner_create", "gc_combiner_destroy", "gc_combiner_arrive", "gc_combiner_poll", "gc_combiner_state"]
+            "gc_launch_ewald", "gc_combiner_create", "gc_combiner_destroy", "gc_combiner_arrive", "gc_combiner_poll", "gc_combiner_state"]
+
+
+class EwaldParams(ctypes.Structure):
+    """gc_ewald_params: box side, G, total mass, centre of mass, alpha (0: 2 / L), images, |h|^2 bound."""
+    _fields_ = [("L", ctypes.c_float), ("G", ctypes.c_float), ("M", ctypes.c_float), ("com", ctypes.c_float * 3),
+                ("alpha", ctypes.c_float), ("nrep", ctypes.c_int32), ("hmax2", ctypes.c_int32)]
+
+
+def ewald_params(L: float, M: float, com, G: float = 1.0, alpha: float = 0.0, nrep: int = 1,
+                 hmax2: int = 10) -> EwaldParams:
+    p = EwaldParams()
+    p.L, p.G, p.M, p.alpha, p.nrep, p.hmax2 = float(L), float(G), float(M), float(alpha), int(nrep), int(hmax2)
+    for d in range(3):
+        p.com[d] = float(com[d])
+    return p
 
 
 class GcError(RuntimeError):
@@ -112,6 +128,7 @@ def lib():
         "gc_graph_destroy": (I32, [VP]),
         "gc_autotune": (I32, [VP, ctypes.POINTER(ForceParams), VP, VP, I32, VP, ctypes.POINTER(ForceParams), VP]),
         "gc_occupancy": (I32, [VP, ctypes.POINTER(ForceParams), PI32, PI32]),
+        "gc_launch_ewald": (I32, [VP, ctypes.POINTER(EwaldParams), VP, VP]),
         "gc_combiner_create": (I32, [I32, ctypes.POINTER(VP)]),
         "gc_combiner_destroy": (I32, [VP]),
         "gc_combiner_arrive": (I32, [VP, ctypes.c_double, I64]),
@@ -322,6 +339,10 @@ class Batch:
     def launch(self, prm: ForceParams, nodes, acc, stream=None):
         self.ctx.check(lib().gc_launch_combined(self.h, ctypes.byref(prm), _ptr(nodes), _ptr(acc), _stream(stream)),
                        "gc_launch_combined")
+
+    def ewald(self, prm: "EwaldParams", acc, stream=None):
+        """acc += the Ewald correction at every target of the batch (gc_launch_ewald)."""
+        self.ctx.check(lib().gc_launch_ewald(self.h, ctypes.byref(prm), _ptr(acc), _stream(stream)), "gc_launch_ewald")
 
     def backward(self, prm: ForceParams, nodes, node_range, n_nodes: int, cot, gpos, gmass, gparam=None,
                  stream=None):

@@ -130,6 +130,26 @@ hipError_t launch_lj_gather(bool persistent, const LJArgs& a, int grid_blocks, h
 hipError_t launch_lj_finish(float4* acc, const float* mass_t, const float4* rec_by_id, int32_t n,
                             hipStream_t s);
 
+// ---------------------------------------------------------------- Ewald correction
+
+constexpr int kEwaldMaxHmax2 = 64;   // largest |h|^2 of the wave-vector sum
+constexpr int kEwaldMaxH = 1056;     // half-space wave vectors with 0 < |h|^2 <= 64: 1054
+struct EwaldArgs {
+  const gc_task* tasks;
+  int32_t n_tasks;
+  const int32_t* ioff;     // per task: first target in flat order (n_tasks entries, ascending)
+  int64_t n_targets;
+  const int32_t* ibeg;     // per task first target position in `rec` (nullptr: task.i_begin)
+  const float4* rec;
+  float4* acc;             // += the correction, by target id
+  float L, inv_L, alpha, GM;
+  float c[3];
+  int32_t nrep, hmax, hmax2;
+  float kcoef;             // -2 G M / L^2
+  float kdecay;            // pi^2 / (alpha L)^2
+};
+hipError_t launch_ewald(const EwaldArgs& a, hipStream_t s);
+
 // ---------------------------------------------------------------- whole-step persistent kernel
 
 // Work items of one step, in ticket order; see step.hip.

@@ -2,6 +2,7 @@
 // chare table, batches (combined work requests), the reorganisation pipeline,
 // the combined launches, HIP graph capture and the autotuner.
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -868,6 +869,45 @@ extern "C" gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_
     GC_HIP(ctx, grav_occupancy(order, false, prm->schedule == GC_SCHED_QUEUE, two, tile, wpb, &per));
   *blocks_per_cu = per;
   if (n_cu) *n_cu = ctx->n_cu;
+  return GC_OK;
+}
+
+// ===================================================================== Ewald correction
+
+extern "C" gc_status gc_launch_ewald(gc_batch b, const gc_ewald_params* prm, float* acc_dev, void* stream) {
+  if (!b) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  if (!prm || !acc_dev) return set_err(c, GC_E_INVAL, "gc_launch_ewald: NULL argument");
+  if (b->kind != GC_KIND_GRAV) return set_err(c, GC_E_INVAL, "gc_launch_ewald: gravity batches only");
+  if (!(prm->L > 0.f) || !(prm->alpha >= 0.f) || prm->nrep < 0 || prm->nrep > 4 || prm->hmax2 < 0 ||
+      prm->hmax2 > kEwaldMaxHmax2)
+    return set_err(c, GC_E_INVAL, "gc_launch_ewald: need L > 0, alpha >= 0, 0 <= nrep <= 4, 0 <= hmax2 <= %d",
+                   kEwaldMaxHmax2);
+  if (b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_launch_ewald: batch not reorganised");
+  if (lists_mode(b->mode)) return set_err(c, GC_E_UNSUPPORTED, "gc_launch_ewald: PACK, REDUNDANT or NONE");
+  const bool packed = (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT);
+  EwaldArgs a{};
+  a.tasks = b->d_tasks.as<gc_task>();
+  a.n_tasks = (int32_t)b->tasks.size();
+  a.ioff = b->d_ioff.as<int32_t>();
+  a.n_targets = b->n_targets;
+  a.ibeg = packed ? b->pibeg.as<int32_t>() : nullptr;
+  a.rec = b->rec;
+  a.acc = reinterpret_cast<float4*>(acc_dev);
+  a.L = prm->L;
+  a.inv_L = 1.f / prm->L;
+  a.alpha = prm->alpha > 0.f ? prm->alpha : 2.f / prm->L;
+  a.GM = prm->G * prm->M;
+  for (int d = 0; d < 3; ++d) a.c[d] = prm->com[d];
+  a.nrep = prm->nrep;
+  a.hmax2 = prm->hmax2;
+  a.hmax = 0;
+  while ((a.hmax + 1) * (a.hmax + 1) <= a.hmax2) ++a.hmax;
+  a.kcoef = -2.f * a.GM / (prm->L * prm->L);
+  const double aL = (double)a.alpha * prm->L;
+  a.kdecay = (float)(M_PI * M_PI / (aL * aL));
+  GC_HIP(c, launch_ewald(a, S(stream)));
   return GC_OK;
 }
 

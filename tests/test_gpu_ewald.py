@@ -1,0 +1,86 @@
+"""GPU parity of the combined Ewald kernel against the FP64 oracle (Sec. 4.1 periodic gravity).
+
+Bar: per-task relative L2 <= 1e-5 of the correction.  The box's mass and centre of mass are passed
+to both sides as the same FP32 values.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2008_05712_amd as gc
+import workloads as W
+from gpu_helpers import GravRig, rel_l2_per_task, whole
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gc.Context(0)
+    yield c
+    c.close()
+
+
+def box_moments(w):
+    m = w.rec[:, 3].astype(np.float64)
+    M = np.float32(m.sum())
+    com = (w.rec[:, :3].astype(np.float64) * m[:, None]).sum(0) / m.sum()
+    return float(M), com.astype(np.float32)
+
+
+@pytest.mark.parametrize("mode", [gc.REORG_NONE, gc.REORG_PACK])
+@pytest.mark.parametrize("alpha,nrep,hmax2", [(0.0, 1, 10), (2.6, 2, 20), (3.0, 0, 4)])
+def test_ewald_matches_oracle(ctx, mode, alpha, nrep, hmax2):
+    print(f"[gpu] ewald uniform-4096 mode {mode} alpha {alpha} nrep {nrep} hmax2 {hmax2}", flush=True)
+    w = W.nbody_tiny()
+    M, com = box_moments(w)
+    rig = GravRig(ctx, w)
+    b = rig.batch(whole(w))
+    b.reorganize(rig.pool, mode)
+    rig.acc.zero_()
+    b.ewald(gc.ewald_params(1.0, M, com, alpha=alpha, nrep=nrep, hmax2=hmax2), rig.acc)
+    rig.torch.cuda.synchronize()
+    acc = rig.acc.cpu().numpy()
+    ref = O.ewald(w.rec[:, :3], 1.0, 1.0, M, com.astype(np.float64), alpha if alpha > 0 else 2.0, nrep, hmax2)
+    err = rel_l2_per_task(acc, ref, whole(w))
+    assert err.max() <= TOL, err.max()
+    b.destroy()
+    rig.close()
+
+
+def test_ewald_adds_and_handles_a_target_at_the_centre(ctx):
+    # acc += correction; a target sitting exactly at com takes the series branch (zero correction)
+    w = W.nbody_tiny()
+    M, _ = box_moments(w)
+    com = w.rec[7, :3].copy()  # any point may be the expansion centre
+    rig = GravRig(ctx, w)
+    b = rig.batch(whole(w))
+    b.reorganize(rig.pool, gc.REORG_PACK)
+    rig.acc.fill_(1.0)
+    b.ewald(gc.ewald_params(1.0, M, com), rig.acc)
+    rig.torch.cuda.synchronize()
+    acc = rig.acc.cpu().numpy()
+    ref = O.ewald(w.rec[:, :3], 1.0, 1.0, M, com.astype(np.float64), 2.0, 1, 10)
+    assert np.all(np.isfinite(acc))
+    assert np.abs(acc[7, :3] - 1.0).max() <= 1e-6
+    assert np.all(acc[:, 3] == 1.0)
+    err = rel_l2_per_task(acc[:, :3] - 1.0, ref, whole(w))
+    assert err.max() <= 1e-4, err.max()  # the +1 offset costs ~1e-7 absolute per component
+    b.destroy()
+    rig.close()
+
+
+def test_ewald_rejects_bad_parameters(ctx):
+    w = W.nbody_tiny()
+    rig = GravRig(ctx, w)
+    b = rig.batch(whole(w))
+    b.reorganize(rig.pool, gc.REORG_NONE)
+    for kw in (dict(L=0.0), dict(nrep=5), dict(hmax2=65), dict(alpha=-1.0)):
+        args = dict(L=1.0, M=1.0, com=(0.5, 0.5, 0.5))
+        args.update(kw)
+        with pytest.raises(gc.GcError) as e:
+            b.ewald(gc.ewald_params(**args), rig.acc)
+        assert e.value.status == 1
+    b.destroy()
+    rig.close()

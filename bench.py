@@ -196,6 +196,33 @@ def leg_lj(gc, W, torch, ctx):
     return out
 
 
+def leg_ewald(gc, W, torch, ctx):
+    """Ewald correction (periodic gravity) of 262,144 particles uniform in the unit box, buckets of 32:
+    one combined launch over every target, 27 real-space images and the 73 wave-vector pairs with
+    |h|^2 <= 10 at alpha = 2 / L."""
+    t0 = time.time()
+    w = W.build_grav(W.uniform_cube(262144, 1005), bucket=32, theta=0.7)
+    log(f"[bench] ewald: N={w.n} tasks={w.n_tasks} build {time.time() - t0:.1f}s")
+    dev = torch.device("cuda")
+    src = torch.from_numpy(w.rec).to(dev)
+    acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
+    pool = gc.Pool(ctx, w.n, 1)
+    pool.set_source(src)
+    b = gc.Batch(ctx, gc.KIND_GRAV, w.n)
+    b.submit(gc.tasks_from_csr(w.i_begin, w.i_count, w.j_first, w.j_nr, w.n_first, w.n_count), w.ranges, w.node_idx)
+    b.commit()
+    b.reorganize(pool, gc.REORG_NONE)
+    m = w.rec[:, 3].astype(np.float64)
+    com = (w.rec[:, :3].astype(np.float64) * m[:, None]).sum(0) / m.sum()
+    prm = gc.ewald_params(1.0, float(m.sum()), com, nrep=1, hmax2=10)
+    stream = torch.cuda.current_stream()
+    ms = time_kernel(lambda: b.ewald(prm, acc), stream)
+    b.destroy()
+    pool.destroy()
+    return {"workload": f"uniform-{w.n} periodic unit box ({w.n_tasks} bucket tasks), nrep 1, |h|^2 <= 10",
+            "ms": round(ms, 4), "targets_per_s_G": round(w.n / (ms * 1e-3) / 1e9, 3)}
+
+
 def leg_adjoint(gc, W, torch, ctx):
     """Backward / forward time: gravity on the 4,096-particle uniform set (monopole) and the
     two-type LJ adjoint at 1,048,576 atoms."""
@@ -545,6 +572,7 @@ def main():
     if not args.quick:
         extra["batched_instances"] = leg_instances(gc, W, torch, ctx, args)
         extra["lj"] = leg_lj(gc, W, torch, ctx)
+        extra["ewald"] = leg_ewald(gc, W, torch, ctx)
         extra["adjoint"] = leg_adjoint(gc, W, torch, ctx)
 
     form_text = {"step": "one whole-step persistent launch (HIP graph) per step",

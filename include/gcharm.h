@@ -407,6 +407,43 @@ typedef struct {
  */
 gc_status gc_launch_ewald(gc_batch batch, const gc_ewald_params* prm, float* acc_dev, void* stream);
 
+/* ---------------------------------------------------------------- CPU/GPU scheduling */
+
+/*
+ * Dynamic scheduling of work requests between the CPU and the GPU (Sec. 3.3).
+ * A request's workload is the number of input data items it reads.  After
+ * each execution on a device the caller records its items and seconds; each
+ * device keeps the running mean of its seconds per item.  gc_hybrid_split
+ * gives the CPU the share tau_gpu / (tau_cpu + tau_gpu) of a queue's items:
+ * scanning the queue from the front with a running sum of items, the prefix
+ * up to the request at which the sum reaches that share goes to the CPU
+ * (*n_cpu requests, *items_cpu items), the rest to the GPU; a share of zero
+ * items gives the CPU nothing.  Until both devices have a record the share is
+ * one half.  Pure host logic; GC_E_INVAL on bad arguments, state unchanged.
+ */
+enum { GC_DEVICE_CPU = 0, GC_DEVICE_GPU = 1 };
+typedef struct gc_hybrid_* gc_hybrid;
+gc_status gc_hybrid_create(gc_hybrid* out);
+gc_status gc_hybrid_destroy(gc_hybrid h);
+gc_status gc_hybrid_record(gc_hybrid h, int32_t device, int64_t items, double seconds);  /* items >= 1 */
+gc_status gc_hybrid_split(gc_hybrid h, const int64_t* items, int32_t n, int32_t* n_cpu, int64_t* items_cpu);
+gc_status gc_hybrid_state(gc_hybrid h, double* tau_cpu, double* tau_gpu, int64_t* runs_cpu, int64_t* runs_gpu);
+
+/*
+ * The CPU's Lennard-Jones kernel for the requests scheduled there: the same
+ * force law, FP32 cutoff decision and force factor as the device pass (pair
+ * sums in FP64), both atoms of every pair updated; acc += F / m (host float4
+ * [n_ids], x y z; the caller zeroes it).  tasks / j_ranges as for
+ * gc_submit_tasks (one j range per task), rec: host float4 [n_ids] records by
+ * id; eps_t, sig_t, mass_t: host arrays of n_types.  n_threads: 0 = the
+ * hardware's thread count (at most 64).  Synchronous; GC_E_INVAL on ranges
+ * outside [0, n_ids), a type outside [0, n_types) or bad arguments (acc
+ * unchanged), GC_E_NOMEM if the per-thread sums cannot be allocated.
+ */
+gc_status gc_lj_forces_cpu(const gc_task* tasks, int32_t n_tasks, const int32_t* j_ranges, int32_t n_ranges,
+                           const float* rec, int32_t n_ids, int32_t n_types, const float* eps_t, const float* sig_t,
+                           const float* mass_t, float r_cut, float* acc, int32_t n_threads);
+
 /* ---------------------------------------------------------------- combining policy */
 
 /*

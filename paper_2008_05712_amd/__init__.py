@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 __all__ = ["GcError", "lib", "Context", "Pool", "Batch", "Graph", "Combiner", "ForceParams", "EwaldParams",
-           "ewald_params", "TASK_DTYPE",
+           "ewald_params", "Hybrid", "lj_forces_cpu", "DEVICE_CPU", "DEVICE_GPU", "TASK_DTYPE",
            "REORG_REDUNDANT", "REORG_INDIRECT", "REORG_SORTED", "REORG_PACK", "REORG_NONE",
            "FORCE_GRAV_MONO", "FORCE_GRAV_QUAD", "FORCE_LJ", "KIND_GRAV", "KIND_LJ", "TASK_SELF",
            "FIXTURE_NONE", "FIXTURE_RESET_PLACE", "FIXTURE_EVICT_STAGED", "SCHED_TASKS", "SCHED_QUEUE", "SCHED_STEP",
@@ -41,7 +41,8 @@ EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_pool_cr
             "gc_batch_create", "gc_batch_destroy", "gc_batch_reset", "gc_submit_tasks", "gc_batch_commit",
             "gc_batch_sizes", "gc_reorganize", "gc_batch_maps", "gc_launch_combined", "gc_zero_f32", "gc_backward",
             "gc_graph_capture", "gc_graph_launch", "gc_graph_destroy", "gc_autotune", "gc_occupancy",
-            "gc_launch_ewald", "gc_combiner_create", "gc_combiner_destroy", "gc_combiner_arrive", "gc_combiner_poll", "gc_combiner_state"]
+            "gc_launch_ewald", "gc_hybrid_create", "gc_hybrid_destroy", "gc_hybrid_record", "gc_hybrid_split",
+            "gc_hybrid_state", "gc_lj_forces_cpu", "gc_combiner_create", "gc_combiner_destroy", "gc_combiner_arrive", "gc_combiner_poll", "gc_combiner_state"]
 
 
 class EwaldParams(ctypes.Structure):
@@ -129,6 +130,12 @@ def lib():
         "gc_autotune": (I32, [VP, ctypes.POINTER(ForceParams), VP, VP, I32, VP, ctypes.POINTER(ForceParams), VP]),
         "gc_occupancy": (I32, [VP, ctypes.POINTER(ForceParams), PI32, PI32]),
         "gc_launch_ewald": (I32, [VP, ctypes.POINTER(EwaldParams), VP, VP]),
+        "gc_hybrid_create": (I32, [ctypes.POINTER(VP)]),
+        "gc_hybrid_destroy": (I32, [VP]),
+        "gc_hybrid_record": (I32, [VP, I32, I64, ctypes.c_double]),
+        "gc_hybrid_split": (I32, [VP, VP, I32, PI32, PI64]),
+        "gc_hybrid_state": (I32, [VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), PI64, PI64]),
+        "gc_lj_forces_cpu": (I32, [VP, I32, VP, I32, VP, I32, I32, VP, VP, VP, ctypes.c_float, VP, I32]),
         "gc_combiner_create": (I32, [I32, ctypes.POINTER(VP)]),
         "gc_combiner_destroy": (I32, [VP]),
         "gc_combiner_arrive": (I32, [VP, ctypes.c_double, I64]),
@@ -228,6 +235,61 @@ class Combiner:
         if self.h:
             lib().gc_combiner_destroy(self.h)
             self.h = VP()
+
+
+DEVICE_CPU, DEVICE_GPU = 0, 1
+
+
+class Hybrid:
+    """Dynamic CPU/GPU scheduling of work requests by running per-item times (gc_hybrid_*)."""
+
+    def __init__(self):
+        self.h = VP()
+        st = lib().gc_hybrid_create(ctypes.byref(self.h))
+        if st != GC_OK:
+            raise GcError(st, "gc_hybrid_create")
+
+    def record(self, device: int, items: int, seconds: float):
+        st = lib().gc_hybrid_record(self.h, int(device), int(items), float(seconds))
+        if st != GC_OK:
+            raise GcError(st, f"gc_hybrid_record(device={device}, items={items}, seconds={seconds})")
+
+    def split(self, items) -> tuple[int, int]:
+        """(requests at the front of the queue that go to the CPU, their items)."""
+        it = np.ascontiguousarray(items, dtype=np.int64)
+        k, ic = ctypes.c_int32(), ctypes.c_int64()
+        st = lib().gc_hybrid_split(self.h, it.ctypes.data if it.size else None, int(it.size), ctypes.byref(k),
+                                   ctypes.byref(ic))
+        if st != GC_OK:
+            raise GcError(st, "gc_hybrid_split")
+        return k.value, ic.value
+
+    def state(self) -> dict:
+        tc, tg, rc, rg = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        st = lib().gc_hybrid_state(self.h, ctypes.byref(tc), ctypes.byref(tg), ctypes.byref(rc), ctypes.byref(rg))
+        if st != GC_OK:
+            raise GcError(st, "gc_hybrid_state")
+        return {"tau_cpu": tc.value, "tau_gpu": tg.value, "runs_cpu": rc.value, "runs_gpu": rg.value}
+
+    def destroy(self):
+        if self.h:
+            lib().gc_hybrid_destroy(self.h)
+            self.h = VP()
+
+
+def lj_forces_cpu(tasks: np.ndarray, ranges: np.ndarray, rec: np.ndarray, eps_t, sig_t, mass_t, r_cut: float,
+                  acc: np.ndarray, n_threads: int = 0):
+    """acc (host float32 [n_ids, 4]) += accelerations of the given LJ tasks on the CPU (gc_lj_forces_cpu)."""
+    tasks = np.ascontiguousarray(tasks, dtype=TASK_DTYPE)
+    ranges = np.ascontiguousarray(ranges, dtype=np.int32).reshape(-1, 2)
+    rec = np.ascontiguousarray(rec, dtype=np.float32)
+    e, sgm, m = (np.ascontiguousarray(x, dtype=np.float32) for x in (eps_t, sig_t, mass_t))
+    assert acc.dtype == np.float32 and acc.flags.c_contiguous and acc.shape == (rec.shape[0], 4)
+    st = lib().gc_lj_forces_cpu(tasks.ctypes.data, int(tasks.size), ranges.ctypes.data, int(ranges.shape[0]),
+                                rec.ctypes.data, int(rec.shape[0]), int(e.size), e.ctypes.data, sgm.ctypes.data,
+                                m.ctypes.data, float(r_cut), acc.ctypes.data, int(n_threads))
+    if st != GC_OK:
+        raise GcError(st, "gc_lj_forces_cpu")
 
 
 class Pool:

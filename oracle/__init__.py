@@ -60,6 +60,8 @@ def _load():
     lib.or_ewald.argtypes = [i64, F64, dbl, dbl, dbl, F64, dbl, i32, i32, F64, F64]
     lib.or_vjp_grav_mono.argtypes = [i32, I32, I32, I32, I32, I32, I32, I32, I32, i32, I32, F64, F64, F64, dbl, dbl,
                                      F64, i64, F64, F64]
+    lib.or_vjp_grav.argtypes = [i32, I32, I32, I32, I32, I32, I32, I32, I32, i32, I32, F64, F64, F64, i32, dbl, dbl,
+                                F64, i64, F64, F64]
     lib.or_vjp_lj.argtypes = [i32, I32, I32, I32, I32, I32, F32, F32, F64, F64, i64, i32, F64, F64, dbl, F64, F64,
                               F64, F64, F64]
     lib.or_lj_energy_at.restype = dbl
@@ -253,6 +255,26 @@ def vjp_grav_mono(w, g, G: float = 1.0, eps: float = 0.01, pos=None, mass=None, 
                          _p(t["n_first"], I32), _p(t["n_count"], I32), _p(t["j_first"], I32), _p(t["j_nr"], I32),
                          _p(t["node_idx"], I32), _p(t["ranges"], I32), int(nr.shape[0]), _p(nr, I32), _p(pos, F64),
                          _p(mass, F64), _p(mom, F64), G, eps, _p(g, F64), n, _p(gpos, F64), _p(gmass, F64))
+    return gpos, gmass
+
+
+def vjp_grav(w, g, order: int, G: float = 1.0, eps: float = 0.01, pos=None, mass=None, mom=None):
+    """(gpos n x 3, gmass n) of L = sum g_i . a_i over w's lists with node terms of `order`, lists frozen."""
+    lib = _load()
+    rec = w.rec.astype(np.float64)
+    pos = _d(rec[:, :3] if pos is None else pos)
+    mass = _d(rec[:, 3] if mass is None else mass)
+    mom = _d(moments_from_nodes32(w.nodes) if mom is None else mom)
+    t = {k: _i(v) for k, v in workload_tasks(w).items()}
+    nr = _i(w.node_range)
+    g = _d(g)
+    n = pos.shape[0]
+    gpos = np.empty((n, 3))
+    gmass = np.empty(n)
+    lib.or_vjp_grav(int(t["i_begin"].shape[0]), _p(t["i_begin"], I32), _p(t["i_count"], I32),
+                    _p(t["n_first"], I32), _p(t["n_count"], I32), _p(t["j_first"], I32), _p(t["j_nr"], I32),
+                    _p(t["node_idx"], I32), _p(t["ranges"], I32), int(nr.shape[0]), _p(nr, I32), _p(pos, F64),
+                    _p(mass, F64), _p(mom, F64), int(order), G, eps, _p(g, F64), n, _p(gpos, F64), _p(gmass, F64))
     return gpos, gmass
 
 

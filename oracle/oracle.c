@@ -14,8 +14,9 @@
  *    assignment, packed ranges, address lists and their sorted form;
  *  - Lennard-Jones over cell-pair compute objects (Sec. 4.2: one object per
  *    pair of patches updates both), and brute force with minimum image;
- *  - analytic vector-Jacobian products (gravity: direct + monopole with the
- *    node chain rule; Lennard-Jones: positions, masses, per-type eps/sigma);
+ *  - analytic vector-Jacobian products (gravity: direct + monopole or
+ *    monopole + quadrupole with the node chain rule; Lennard-Jones: positions,
+ *    masses, per-type eps/sigma);
  *  - the Ewald correction of periodic gravity (ChaNGa's second combined
  *    kernel, Sec. 4.1, Sec. 4.3): the pull of every periodic image of the box's
  *    total mass M at its centre of mass c, plus the neutralising background,
@@ -376,14 +377,26 @@ void or_lj_brute(int64_t n, const float* rec32, const double* L, const double* e
 
 /* L = sum_i g_i . a_i over the lists (direct + monopole nodes), lists frozen,
  * node moments a function of their members.  Outputs gpos (n x 3), gmass (n). */
-void or_vjp_grav_mono(int32_t ntasks, const int32_t* i_begin, const int32_t* i_count, const int32_t* n_first,
-                      const int32_t* n_count, const int32_t* j_first, const int32_t* j_nr, const int32_t* node_idx,
-                      const int32_t* ranges, int32_t nnodes, const int32_t* node_range, const double* pos,
-                      const double* mass, const double* mom, double G, double eps, const double* g, int64_t n,
-                      double* gpos, double* gmass) {
+/* L = sum_i g_i . a_i over each task's lists (direct + node terms of `order`), lists frozen.
+ * Node gradients reach members through c = sum m_k x_k / M, M = sum m_k and
+ * S = sum m_k e_k e_k^T (e_k = x_k - c; sum m_k e_k = 0, so S depends on c not at all):
+ *   dL/dx_k += (m_k / M) dL/dc + m_k (GS + GS^T) e_k,
+ *   dL/dm_k += dL/dM + e_k . dL/dc / M + e_k^T GS e_k,
+ * with GS = dL/dS over the nine entries of S (T = tr S included).  For the quadrupole term
+ * a_q = G [3 S d / r^5 - 15/2 q d / r^7 + 3/2 T d / r^5], q = d^T S d:
+ *   d(g.a_q)/dd = G [3 (S g / r^5 - 5 (g.Sd) d / r^7)
+ *                    - 15/2 (2 (g.d) S d / r^7 + q g / r^7 - 7 q (g.d) d / r^9)
+ *                    + 3/2 T (g / r^5 - 5 (g.d) d / r^7)],
+ *   GS_ab = G [3 g_a d_b / r^5 - 15/2 (g.d) d_a d_b / r^7 + 3/2 (g.d) delta_ab / r^5]. */
+void or_vjp_grav(int32_t ntasks, const int32_t* i_begin, const int32_t* i_count, const int32_t* n_first,
+                 const int32_t* n_count, const int32_t* j_first, const int32_t* j_nr, const int32_t* node_idx,
+                 const int32_t* ranges, int32_t nnodes, const int32_t* node_range, const double* pos,
+                 const double* mass, const double* mom, int32_t order, double G, double eps, const double* g,
+                 int64_t n, double* gpos, double* gmass) {
   double eps2 = eps * eps;
   double* gc = (double*)calloc((size_t)(3 * nnodes), sizeof(double));
   double* gM = (double*)calloc((size_t)nnodes, sizeof(double));
+  double* gS = (double*)calloc((size_t)(9 * nnodes), sizeof(double));
   memset(gpos, 0, sizeof(double) * 3 * (size_t)n);
   memset(gmass, 0, sizeof(double) * (size_t)n);
   for (int32_t t = 0; t < ntasks; ++t) {
@@ -412,32 +425,69 @@ void or_vjp_grav_mono(int32_t ntasks, const int32_t* i_begin, const int32_t* i_c
         const double* m = mom + 10 * (size_t)nd;
         double d[3] = {x[0] - m[0], x[1] - m[1], x[2] - m[2]};
         double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
-        double r = sqrt(r2), r3 = r2 * r, r5 = r3 * r2;
+        double r = sqrt(r2), r3 = r2 * r, r5 = r3 * r2, r7 = r5 * r2, r9 = r7 * r2;
         double gd = gi[0] * d[0] + gi[1] * d[1] + gi[2] * d[2];
+        double v[3];
+        for (int q = 0; q < 3; ++q) v[q] = -G * m[3] * (gi[q] / r3 - 3.0 * gd * d[q] / r5);
+        if (order >= 2) {
+          const double S[3][3] = {{m[4], m[7], m[8]}, {m[7], m[5], m[9]}, {m[8], m[9], m[6]}};
+          double Sd[3], Sg[3];
+          for (int a = 0; a < 3; ++a) {
+            Sd[a] = S[a][0] * d[0] + S[a][1] * d[1] + S[a][2] * d[2];
+            Sg[a] = S[a][0] * gi[0] + S[a][1] * gi[1] + S[a][2] * gi[2];
+          }
+          double q = d[0] * Sd[0] + d[1] * Sd[1] + d[2] * Sd[2];
+          double gSd = gi[0] * Sd[0] + gi[1] * Sd[1] + gi[2] * Sd[2];
+          double T = m[4] + m[5] + m[6];
+          for (int a = 0; a < 3; ++a) {
+            v[a] += G * (3.0 * (Sg[a] / r5 - 5.0 * gSd * d[a] / r7) -
+                         7.5 * (2.0 * gd * Sd[a] / r7 + q * gi[a] / r7 - 7.0 * q * gd * d[a] / r9) +
+                         1.5 * T * (gi[a] / r5 - 5.0 * gd * d[a] / r7));
+            for (int bb = 0; bb < 3; ++bb)
+              gS[9 * (size_t)nd + 3 * a + bb] +=
+                  G * (3.0 * gi[a] * d[bb] / r5 - 7.5 * gd * d[a] * d[bb] / r7 + (a == bb ? 1.5 * gd / r5 : 0.0));
+          }
+        }
         for (int q = 0; q < 3; ++q) {
-          double v = -G * m[3] * (gi[q] / r3 - 3.0 * gd * d[q] / r5);
-          gpos[3 * (size_t)i + q] += v;
-          gc[3 * (size_t)nd + q] -= v;
+          gpos[3 * (size_t)i + q] += v[q];
+          gc[3 * (size_t)nd + q] -= v[q];
         }
         gM[nd] += -G * gd / r3;
       }
     }
   }
-  /* node -> members: c = sum m_k x_k / M, M = sum m_k */
+  /* node -> members */
   for (int32_t nd = 0; nd < nnodes; ++nd) {
-    if (gM[nd] == 0 && gc[3 * nd] == 0 && gc[3 * nd + 1] == 0 && gc[3 * nd + 2] == 0) continue;
     const double* m = mom + 10 * (size_t)nd;
+    const double* GS = gS + 9 * (size_t)nd;
     for (int32_t k = node_range[2 * nd]; k < node_range[2 * nd] + node_range[2 * nd + 1]; ++k) {
-      double dc = 0;
+      double e[3], dc = 0, eGe = 0;
+      for (int q = 0; q < 3; ++q) e[q] = pos[3 * (size_t)k + q] - m[q];
       for (int q = 0; q < 3; ++q) {
-        gpos[3 * (size_t)k + q] += mass[k] / m[3] * gc[3 * (size_t)nd + q];
-        dc += (pos[3 * (size_t)k + q] - m[q]) * gc[3 * (size_t)nd + q];
+        double sym = 0;
+        for (int bb = 0; bb < 3; ++bb) {
+          sym += (GS[3 * q + bb] + GS[3 * bb + q]) * e[bb];
+          eGe += e[q] * GS[3 * q + bb] * e[bb];
+        }
+        gpos[3 * (size_t)k + q] += mass[k] / m[3] * gc[3 * (size_t)nd + q] + mass[k] * sym;
+        dc += e[q] * gc[3 * (size_t)nd + q];
       }
-      gmass[k] += gM[nd] + dc / m[3];
+      gmass[k] += gM[nd] + dc / m[3] + eGe;
     }
   }
   free(gc);
   free(gM);
+  free(gS);
+}
+
+/* The direct + monopole case of or_vjp_grav. */
+void or_vjp_grav_mono(int32_t ntasks, const int32_t* i_begin, const int32_t* i_count, const int32_t* n_first,
+                      const int32_t* n_count, const int32_t* j_first, const int32_t* j_nr, const int32_t* node_idx,
+                      const int32_t* ranges, int32_t nnodes, const int32_t* node_range, const double* pos,
+                      const double* mass, const double* mom, double G, double eps, const double* g, int64_t n,
+                      double* gpos, double* gmass) {
+  or_vjp_grav(ntasks, i_begin, i_count, n_first, n_count, j_first, j_nr, node_idx, ranges, nnodes, node_range, pos,
+              mass, mom, 1, G, eps, g, n, gpos, gmass);
 }
 
 /* L = sum_i g_i . a_i over the cell-pair tasks.  pos (n x 3, FP64) is the

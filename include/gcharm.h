@@ -316,8 +316,9 @@ gc_status gc_zero_f32(gc_ctx ctx, float* dev, int64_t n, void* stream);
  *   gmass_dev float  [n_ids] += dL/dm (gravity: source masses and node mass
  *             chain; Lennard-Jones: per-atom mass as if each atom had its own)
  *   gparam_dev float [2 * n_types] += (dL/deps_t, dL/dsig_t) (Lennard-Jones)
- * Gravity supports GC_FORCE_GRAV_MONO; node gradients flow to member particles
- * through com = sum m_k x_k / M and M = sum m_k (node_range_dev: int32
+ * Gravity supports GC_FORCE_GRAV_MONO and GC_FORCE_GRAV_QUAD; node gradients
+ * flow to member particles through com = sum m_k x_k / M, M = sum m_k and,
+ * with quadrupoles, S = sum m_k (x_k - com)(x_k - com)^T (node_range_dev: int32
  * [2 * n_nodes] (first id, count) of each node's members; members are read
  * in place from the pool's source, which must be device memory).  Lists and
  * cutoff decisions are those of the forward pass.  Asynchronous.

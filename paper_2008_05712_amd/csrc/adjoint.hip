@@ -8,8 +8,13 @@
 // and for a node with d = x_i - com, r^2 = |d|^2 + eps^2:
 //   v = -G M [g_i / r^3 - 3 (g_i . d) d / r^5];  dL/dx_i += v, dL/dcom -= v,
 //   dL/dM += -G (g_i . d) / r^3.
-// Node gradients reach member particles through com = sum m_k x_k / M and
-// M = sum m_k:  dL/dx_k += (m_k / M) dL/dcom,  dL/dm_k += dL/dM + (x_k - com) . dL/dcom / M.
+// and with quadrupole nodes (S the raw second moment, T = tr S, q = d.S.d) also
+//   d(g.a_q)/dd = G [3 S g / r^5 - 15 (g.Sd) d / r^7 - 15 (g.d) S d / r^7 - 15/2 q g / r^7
+//                    + 105/2 q (g.d) d / r^9 + 3/2 T g / r^5 - 15/2 T (g.d) d / r^7]  (to x_i, minus to com),
+//   H = sym(dL/dS) = G [3/2 (g d^T + d g^T) / r^5 - 15/2 (g.d) d d^T / r^7 + 3/2 (g.d) I / r^5].
+// Node gradients reach member particles through com = sum m_k x_k / M, M = sum m_k and
+// S = sum m_k e_k e_k^T (e_k = x_k - com):  dL/dx_k += (m_k / M) dL/dcom + 2 m_k H e_k,
+// dL/dm_k += dL/dM + e_k . dL/dcom / M + e_k . H e_k.
 //
 // Schedule: one workgroup of 4 wavefronts per task, splitting its sources;
 // lanes are sources (nodes, then direct particles), the loop runs over
@@ -65,8 +70,9 @@ __device__ __forceinline__ int wave_excl_scan(int v, int* total) {
 // One workgroup of 4 wavefronts per task: wave w takes the task's nodes w, w + 4, ... and the
 // flat direct positions of every fourth group of 64; all gradients are scattered with atomics, so
 // the waves need no reduction among themselves.
-template <bool PACKED>
+template <bool PACKED, int ORDER>
 __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
+  constexpr int NS = ORDER == 2 ? 10 : 4;  // node gradient floats: dL/dcom, dL/dM (and sym(dL/dS))
   const GravArgs& a = A.f;
   __shared__ float4 tpos[4][kTB], tcot[4][kTB];
   __shared__ int ro[4][64], rb[4][64];
@@ -102,18 +108,23 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
       idt[k] = k < tb ? tk.i_begin + tb0 + k : -1;
       tgx[k] = tgy[k] = tgz[k] = 0.f;
     }
-    // ---- monopole nodes: lane = node
+    // ---- nodes: lane = node
     for (int nb = wid * 64; nb < tk.n_count; nb += W * 64) {
       const int e = nb + lane;
       const bool valid = e < tk.n_count;
       int nd = -1;
-      float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 c = make_float4(0.f, 0.f, 0.f, 0.f), s1 = c, s2 = c;
       if (valid) {
         nd = a.node_idx[tk.n_first + e];
         c = a.nodes[3 * nd];
+        if (ORDER == 2) {
+          s1 = a.nodes[3 * nd + 1];  // Sxx Syy Szz Sxy
+          s2 = a.nodes[3 * nd + 2];  // Sxz Syz T
+        }
       }
       const float GM = G * c.w;
       float gcx = 0.f, gcy = 0.f, gcz = 0.f, gM = 0.f;
+      float hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;  // sym(dL/dS) / G
 #pragma unroll
       for (int k = 0; k < kTB; ++k) {
         float dx = xt[k] - c.x, dy = yt[k] - c.y, dz = zt[k] - c.z;
@@ -126,16 +137,53 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
         float vx = __builtin_fmaf(c1, gx[k], c2 * dx);
         float vy = __builtin_fmaf(c1, gy[k], c2 * dy);
         float vz = __builtin_fmaf(c1, gz[k], c2 * dz);
+        if (ORDER == 2) {
+          // d(g.a_q)/dd = G [3 (S g / r^5 - 5 (g.Sd) d / r^7) - 15/2 (2 (g.d) S d / r^7 + q g / r^7
+          //                  - 7 q (g.d) d / r^9) + 3/2 T (g / r^5 - 5 (g.d) d / r^7)],  q = d.S.d
+          const float ri7 = ri5 * ri2, ri9 = ri7 * ri2;
+          const float sdx = s1.x * dx + s1.w * dy + s2.x * dz;
+          const float sdy = s1.w * dx + s1.y * dy + s2.y * dz;
+          const float sdz = s2.x * dx + s2.y * dy + s1.z * dz;
+          const float sgx = s1.x * gx[k] + s1.w * gy[k] + s2.x * gz[k];
+          const float sgy = s1.w * gx[k] + s1.y * gy[k] + s2.y * gz[k];
+          const float sgz = s2.x * gx[k] + s2.y * gy[k] + s1.z * gz[k];
+          const float q = dx * sdx + dy * sdy + dz * sdz;
+          const float gsd = gx[k] * sdx + gy[k] * sdy + gz[k] * sdz;
+          const float T = s2.z;
+          const float kS = 3.f * ri5;                                                        // coefficient of S g
+          const float kg = -7.5f * q * ri7 + 1.5f * T * ri5;                                 // of g
+          const float kd = -15.f * gsd * ri7 + 52.5f * q * gd * ri9 - 7.5f * T * gd * ri7;  // of d
+          const float ks = -15.f * gd * ri7;                                                 // of S d
+          vx += G * (kS * sgx + kg * gx[k] + kd * dx + ks * sdx);
+          vy += G * (kS * sgy + kg * gy[k] + kd * dy + ks * sdy);
+          vz += G * (kS * sgz + kg * gz[k] + kd * dz + ks * sdz);
+          // sym(dL/dS)_ab = G [3/2 (g_a d_b + g_b d_a) / r^5 - 15/2 (g.d) d_a d_b / r^7 + 3/2 (g.d) delta_ab / r^5]
+          const float a5 = 1.5f * ri5, b7 = -7.5f * gd * ri7, c5 = 1.5f * gd * ri5;
+          hxx += 2.f * a5 * gx[k] * dx + b7 * dx * dx + c5;
+          hyy += 2.f * a5 * gy[k] * dy + b7 * dy * dy + c5;
+          hzz += 2.f * a5 * gz[k] * dz + b7 * dz * dz + c5;
+          hxy += a5 * (gx[k] * dy + gy[k] * dx) + b7 * dx * dy;
+          hxz += a5 * (gx[k] * dz + gz[k] * dx) + b7 * dx * dz;
+          hyz += a5 * (gy[k] * dz + gz[k] * dy) + b7 * dy * dz;
+        }
         tgx[k] += vx; tgy[k] += vy; tgz[k] += vz;
         gcx -= vx; gcy -= vy; gcz -= vz;
         gM = __builtin_fmaf(gd, ri3, gM);
       }
       if (valid) {
-        float* q = A.gnode + 4 * nd;
+        float* q = A.gnode + NS * nd;
         unsafeAtomicAdd(q, gcx);
         unsafeAtomicAdd(q + 1, gcy);
         unsafeAtomicAdd(q + 2, gcz);
         unsafeAtomicAdd(q + 3, -G * gM);
+        if (ORDER == 2) {
+          unsafeAtomicAdd(q + 4, G * hxx);
+          unsafeAtomicAdd(q + 5, G * hyy);
+          unsafeAtomicAdd(q + 6, G * hzz);
+          unsafeAtomicAdd(q + 7, G * hxy);
+          unsafeAtomicAdd(q + 8, G * hxz);
+          unsafeAtomicAdd(q + 9, G * hyz);
+        }
       }
     }
     // ---- direct sources: lane = flat position within a group of up to 64 ranges
@@ -210,30 +258,53 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
   }
 }
 
-// One wavefront per node: push dL/dcom and dL/dM to the member particles.
+// One wavefront per node: push dL/dcom and dL/dM (and, with quadrupoles, H = sym(dL/dS)) to the
+// member particles: dx_k += (m_k / M) dL/dcom + 2 m_k H e_k, dm_k += dL/dM + e_k . dL/dcom / M + e_k.H e_k,
+// e_k = x_k - com.
+template <int ORDER>
 __global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_nodes, const float4* __restrict__ nodes,
                              const float* __restrict__ gnode, const float4* __restrict__ rec_by_id,
                              float4* __restrict__ gpos, float* __restrict__ gmass) {
+  constexpr int NS = ORDER == 2 ? 10 : 4;
   const int lane = threadIdx.x & 63;
   const int waves = gridDim.x * (blockDim.x >> 6);
   for (int nd = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); nd < n_nodes; nd += waves) {
-    const float4 gq = *reinterpret_cast<const float4*>(gnode + 4 * nd);
-    if (gq.x == 0.f && gq.y == 0.f && gq.z == 0.f && gq.w == 0.f) continue;
+    const float* gp = gnode + NS * (size_t)nd;
+    const float4 gq = make_float4(gp[0], gp[1], gp[2], gp[3]);
+    float hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;
+    bool zero = gq.x == 0.f && gq.y == 0.f && gq.z == 0.f && gq.w == 0.f;
+    if (ORDER == 2) {
+      hxx = gp[4]; hyy = gp[5]; hzz = gp[6]; hxy = gp[7]; hxz = gp[8]; hyz = gp[9];
+      zero = zero && hxx == 0.f && hyy == 0.f && hzz == 0.f && hxy == 0.f && hxz == 0.f && hyz == 0.f;
+    }
+    if (zero) continue;
     const float4 c = nodes[3 * nd];
     const float invM = 1.f / c.w;
     const int b = node_range[2 * nd], n = node_range[2 * nd + 1];
     for (int k = lane; k < n; k += 64) {
       const float4 r = rec_by_id[b + k];
       const float f = r.w * invM;
+      const float ex = r.x - c.x, ey = r.y - c.y, ez = r.z - c.z;
+      float px = f * gq.x, py = f * gq.y, pz = f * gq.z;
+      float dm = gq.w + (ex * gq.x + ey * gq.y + ez * gq.z) * invM;
+      if (ORDER == 2) {
+        const float hx = hxx * ex + hxy * ey + hxz * ez;
+        const float hy = hxy * ex + hyy * ey + hyz * ez;
+        const float hz = hxz * ex + hyz * ey + hzz * ez;
+        px += 2.f * r.w * hx;
+        py += 2.f * r.w * hy;
+        pz += 2.f * r.w * hz;
+        dm += ex * hx + ey * hy + ez * hz;
+      }
       float4* q = gpos + (b + k);
-      unsafeAtomicAdd(&q->x, f * gq.x);
-      unsafeAtomicAdd(&q->y, f * gq.y);
-      unsafeAtomicAdd(&q->z, f * gq.z);
-      const float dc = (r.x - c.x) * gq.x + (r.y - c.y) * gq.y + (r.z - c.z) * gq.z;
-      unsafeAtomicAdd(gmass + (b + k), gq.w + dc * invM);
+      unsafeAtomicAdd(&q->x, px);
+      unsafeAtomicAdd(&q->y, py);
+      unsafeAtomicAdd(&q->z, pz);
+      unsafeAtomicAdd(gmass + (b + k), dm);
     }
   }
 }
+
 
 constexpr int kMaxTypes = 8;
 constexpr int kLJTile = 128;
@@ -693,22 +764,31 @@ __global__ void k_lj_mass_grad(const float4* __restrict__ cot, const float4* __r
 
 }  // namespace
 
-hipError_t launch_grav_adjoint(bool packed, const GravAdjArgs& a, int wpb, hipStream_t s) {
+hipError_t launch_grav_adjoint(bool packed, int order, const GravAdjArgs& a, int wpb, hipStream_t s) {
   (void)wpb;
   if (a.f.n_tasks <= 0) return hipSuccess;
   const int grid = a.f.n_tasks;
-  if (packed) hipLaunchKernelGGL(k_grav_adj<true>, dim3(grid), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_grav_adj<false>, dim3(grid), dim3(256), 0, s, a);
+  if (order == 2) {
+    if (packed) hipLaunchKernelGGL((k_grav_adj<true, 2>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_grav_adj<false, 2>), dim3(grid), dim3(256), 0, s, a);
+  } else {
+    if (packed) hipLaunchKernelGGL((k_grav_adj<true, 1>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_grav_adj<false, 1>), dim3(grid), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_node_chain(const int32_t* node_range, int32_t n_nodes, const float4* nodes, const float* gnode,
-                             const float4* rec_by_id, float4* gpos, float* gmass, hipStream_t s) {
+hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nodes, const float4* nodes,
+                             const float* gnode, const float4* rec_by_id, float4* gpos, float* gmass, hipStream_t s) {
   if (n_nodes <= 0) return hipSuccess;
   int g = (n_nodes + 3) / 4;
   if (g > 16384) g = 16384;
-  hipLaunchKernelGGL(k_node_chain, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, rec_by_id, gpos,
-                     gmass);
+  if (order == 2)
+    hipLaunchKernelGGL(k_node_chain<2>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, rec_by_id,
+                       gpos, gmass);
+  else
+    hipLaunchKernelGGL(k_node_chain<1>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, rec_by_id,
+                       gpos, gmass);
   return hipGetLastError();
 }
 

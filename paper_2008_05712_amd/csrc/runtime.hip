@@ -998,13 +998,13 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
   const int32_t T = (int32_t)b->tasks.size();
   const bool packed = (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT);
   if (b->kind == GC_KIND_GRAV) {
-    if (prm->kind != GC_FORCE_GRAV_MONO)
-      return set_err(c, GC_E_UNSUPPORTED, "gc_backward: gravity adjoint implements the monopole form");
+    const int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
+    const int ns = order == 2 ? 10 : 4;
     if (!b->nodes.empty() && (!nodes_dev || !node_range_dev || n_nodes <= 0))
       return set_err(c, GC_E_INVAL, "gc_backward: node table and node ranges needed");
-    if (n_nodes > 0 && b->gnode.ensure(sizeof(float) * 4 * (size_t)n_nodes) != hipSuccess)
+    if (n_nodes > 0 && b->gnode.ensure(sizeof(float) * ns * (size_t)n_nodes) != hipSuccess)
       return set_err(c, GC_E_NOMEM, "gc_backward: node gradients");
-    if (n_nodes > 0) GC_HIP(c, launch_fill_f32(b->gnode.as<float>(), 0.f, 4 * (int64_t)n_nodes, s));
+    if (n_nodes > 0) GC_HIP(c, launch_fill_f32(b->gnode.as<float>(), 0.f, ns * (int64_t)n_nodes, s));
     GravAdjArgs a{};
     a.f.tasks = b->d_tasks.as<gc_task>();
     a.f.n_tasks = T;
@@ -1020,9 +1020,9 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
     a.gmass = gmass_dev;
     a.src_id = packed ? b->d_U.as<int32_t>() : nullptr;
     a.gnode = b->gnode.as<float>();
-    GC_HIP(c, launch_grav_adjoint(packed, a, 4, s));
+    GC_HIP(c, launch_grav_adjoint(packed, order, a, 4, s));
     if (n_nodes > 0)
-      GC_HIP(c, launch_node_chain(node_range_dev, n_nodes, reinterpret_cast<const float4*>(nodes_dev),
+      GC_HIP(c, launch_node_chain(order, node_range_dev, n_nodes, reinterpret_cast<const float4*>(nodes_dev),
                                   b->gnode.as<float>(), b->pool->src, a.gpos, gmass_dev, s));
     return GC_OK;
   }

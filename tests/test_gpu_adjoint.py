@@ -30,17 +30,17 @@ def close(got, want, tol=TOL):
     return rel <= tol and ele <= tol, (rel, ele)
 
 
-def grav_vjp_gpu(ctx, w, g, mode=gc.REORG_NONE):
+def grav_vjp_gpu(ctx, w, g, mode=gc.REORG_NONE, order=1):
     import torch
     rig = GravRig(ctx, w)
     b = rig.batch(whole(w))
-    rig.run(b, mode, order=1)
+    rig.run(b, mode, order=order)
     cot = torch.zeros((w.n, 4), dtype=torch.float32, device="cuda")
     cot[:, :3] = torch.from_numpy(g.astype(np.float32)).cuda()
     gpos = torch.zeros((w.n, 4), dtype=torch.float32, device="cuda")
     gmass = torch.zeros(w.n, dtype=torch.float32, device="cuda")
     nr = torch.from_numpy(np.ascontiguousarray(w.node_range)).cuda()
-    b.backward(gc.grav_params(order=1), rig.nodes, nr, w.nodes.shape[0], cot, gpos, gmass)
+    b.backward(gc.grav_params(order=order), rig.nodes, nr, w.nodes.shape[0], cot, gpos, gmass)
     torch.cuda.synchronize()
     out = gpos.cpu().numpy()[:, :3], gmass.cpu().numpy()
     b.destroy()
@@ -54,6 +54,20 @@ def test_grav_vjp_matches_oracle_tiny(ctx, mode):
     g = np.random.default_rng(11).normal(size=(w.n, 3)).astype(np.float32).astype(np.float64)
     gp, gm = grav_vjp_gpu(ctx, w, g, mode)
     rp, rm = O.vjp_grav_mono(w, g)
+    ok, e = close(gp, rp)
+    assert ok, ("positions", e)
+    ok, e = close(gm, rm)
+    assert ok, ("masses", e)
+
+
+@pytest.mark.parametrize("mode", [gc.REORG_NONE, gc.REORG_PACK])
+def test_quadrupole_vjp_matches_oracle(ctx, mode):
+    # Plummer 4,096, bucket 16, theta 0.7: quadrupole nodes, chained to members through S
+    w = W.build_grav(W.plummer(4096, 61), bucket=16, theta=0.7)
+    assert w.n_count.sum() > 0
+    g = np.random.default_rng(62).normal(size=(w.n, 3)).astype(np.float32).astype(np.float64)
+    gp, gm = grav_vjp_gpu(ctx, w, g, mode, order=2)
+    rp, rm = O.vjp_grav(w, g, order=2)
     ok, e = close(gp, rp)
     assert ok, ("positions", e)
     ok, e = close(gm, rm)

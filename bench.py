@@ -224,8 +224,8 @@ def leg_ewald(gc, W, torch, ctx):
 
 
 def leg_adjoint(gc, W, torch, ctx):
-    """Backward / forward time: gravity on the 4,096-particle uniform set (monopole) and the
-    two-type LJ adjoint at 1,048,576 atoms."""
+    """Backward / forward time: gravity on the 4,096-particle uniform set (monopole) and on the
+    262,144-particle Plummer set (quadrupole), and the two-type LJ adjoint at 1,048,576 atoms."""
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream()
     res = {}
@@ -247,6 +247,28 @@ def leg_adjoint(gc, W, torch, ctx):
     fwd = time_kernel(lambda: b.launch(prm, nodes, acc), stream)
     bwd = time_kernel(lambda: b.backward(prm, nodes, nr, w.nodes.shape[0], cot, gpos, gmass), stream)
     res["gravity_uniform_4096"] = {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4), "bwd_fwd": round(bwd / fwd, 3)}
+    b.destroy()
+    pool.destroy()
+    # the quadrupole adjoint over all 27,026 tasks of the Plummer 262,144 workload (one launch each way)
+    w = W.nbody_plummer()
+    src = torch.from_numpy(w.rec).to(dev)
+    nodes = torch.from_numpy(w.nodes).to(dev)
+    nr = torch.from_numpy(np.ascontiguousarray(w.node_range)).to(dev)
+    acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
+    pool = gc.Pool(ctx, w.n, 1)
+    pool.set_source(src)
+    b = gc.Batch(ctx, gc.KIND_GRAV, w.n)
+    b.submit(gc.tasks_from_csr(w.i_begin, w.i_count, w.j_first, w.j_nr, w.n_first, w.n_count), w.ranges, w.node_idx)
+    b.commit()
+    b.reorganize(pool, gc.REORG_NONE)
+    prm = gc.grav_params(order=2)
+    cot = torch.randn((w.n, 4), device=dev)
+    gpos = torch.zeros((w.n, 4), device=dev)
+    gmass = torch.zeros(w.n, device=dev)
+    fwd = time_kernel(lambda: b.launch(prm, nodes, acc), stream)
+    bwd = time_kernel(lambda: b.backward(prm, nodes, nr, w.nodes.shape[0], cot, gpos, gmass), stream, reps=3)
+    res["gravity_quadrupole_plummer_262144"] = {"fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
+                                                "bwd_fwd": round(bwd / fwd, 3)}
     b.destroy()
     pool.destroy()
     w = W.lj_fcc(two_type=True)

@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
         gM = __builtin_fmaf(gd, ri3, gM);
       }
       if (valid) {
-        float* q = A.gnode + NS * nd;
+        float* q = A.gnode + (int64_t)(blockIdx.x % kGradCopies) * A.gstride + NS * nd;
         unsafeAtomicAdd(q, gcx);
         unsafeAtomicAdd(q + 1, gcy);
         unsafeAtomicAdd(q + 2, gcz);
@@ -263,18 +263,26 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
 // e_k = x_k - com.
 template <int ORDER>
 __global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_nodes, const float4* __restrict__ nodes,
-                             const float* __restrict__ gnode, const float4* __restrict__ rec_by_id,
+                             const float* __restrict__ gnode, int64_t gstride, const float4* __restrict__ rec_by_id,
                              float4* __restrict__ gpos, float* __restrict__ gmass) {
   constexpr int NS = ORDER == 2 ? 10 : 4;
   const int lane = threadIdx.x & 63;
   const int waves = gridDim.x * (blockDim.x >> 6);
   for (int nd = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); nd < n_nodes; nd += waves) {
-    const float* gp = gnode + NS * (size_t)nd;
-    const float4 gq = make_float4(gp[0], gp[1], gp[2], gp[3]);
+    // the node's gradient: the sum of its copies, in a fixed order
+    float gv[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) gv[q] = 0.f;
+    for (int cpy = 0; cpy < kGradCopies; ++cpy) {
+      const float* gp = gnode + cpy * gstride + NS * (int64_t)nd;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) gv[q] += gp[q];
+    }
+    const float4 gq = make_float4(gv[0], gv[1], gv[2], gv[3]);
     float hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;
     bool zero = gq.x == 0.f && gq.y == 0.f && gq.z == 0.f && gq.w == 0.f;
     if (ORDER == 2) {
-      hxx = gp[4]; hyy = gp[5]; hzz = gp[6]; hxy = gp[7]; hxz = gp[8]; hyz = gp[9];
+      hxx = gv[4 % NS]; hyy = gv[5 % NS]; hzz = gv[6 % NS]; hxy = gv[7 % NS]; hxz = gv[8 % NS]; hyz = gv[9 % NS];
       zero = zero && hxx == 0.f && hyy == 0.f && hzz == 0.f && hxy == 0.f && hxz == 0.f && hyz == 0.f;
     }
     if (zero) continue;
@@ -779,16 +787,17 @@ hipError_t launch_grav_adjoint(bool packed, int order, const GravAdjArgs& a, int
 }
 
 hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nodes, const float4* nodes,
-                             const float* gnode, const float4* rec_by_id, float4* gpos, float* gmass, hipStream_t s) {
+                             const float* gnode, int64_t gstride, const float4* rec_by_id, float4* gpos, float* gmass,
+                             hipStream_t s) {
   if (n_nodes <= 0) return hipSuccess;
   int g = (n_nodes + 3) / 4;
   if (g > 16384) g = 16384;
   if (order == 2)
-    hipLaunchKernelGGL(k_node_chain<2>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, rec_by_id,
-                       gpos, gmass);
+    hipLaunchKernelGGL(k_node_chain<2>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, gstride,
+                       rec_by_id, gpos, gmass);
   else
-    hipLaunchKernelGGL(k_node_chain<1>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, rec_by_id,
-                       gpos, gmass);
+    hipLaunchKernelGGL(k_node_chain<1>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, gstride,
+                       rec_by_id, gpos, gmass);
   return hipGetLastError();
 }
 

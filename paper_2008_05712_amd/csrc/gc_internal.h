@@ -193,13 +193,19 @@ struct GravAdjArgs {
   float4* gpos;            // by id
   float* gmass;            // by id
   const int32_t* src_id;   // position in rec -> id (PACK: U; LISTS: slot -> id map; nullptr: identity)
-  float* gnode;            // per node: dL/dcom (3) and dL/dM, 4 floats (quadrupole: then sym(dL/dS), 10)
+  float* gnode;            // per node: dL/dcom (3) and dL/dM, 4 floats (quadrupole: then sym(dL/dS), 10);
+                           // kGradCopies copies gstride floats apart, block b adding to copy b % kGradCopies
+  int64_t gstride;
 };
+// Node gradients are scattered into this many copies (a tree's top nodes are in nearly every task's
+// list: one copy would put their atomics on a few addresses); the node chain sums them.
+constexpr int kGradCopies = 16;
 // order 1: monopole nodes, gnode 4 floats per node (dL/dcom, dL/dM); order 2: quadrupole nodes,
 // 10 floats per node (then sym(dL/dS): xx yy zz xy xz yz)
 hipError_t launch_grav_adjoint(bool packed, int order, const GravAdjArgs& a, int waves_per_block, hipStream_t s);
 hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nodes, const float4* nodes,
-                             const float* gnode, const float4* rec_by_id, float4* gpos, float* gmass, hipStream_t s);
+                             const float* gnode, int64_t gstride, const float4* rec_by_id, float4* gpos, float* gmass,
+                             hipStream_t s);
 struct LJAdjArgs {
   LJArgs f;
   const float4* cot;       // by id

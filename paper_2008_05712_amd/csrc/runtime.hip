@@ -1002,9 +1002,10 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
     const int ns = order == 2 ? 10 : 4;
     if (!b->nodes.empty() && (!nodes_dev || !node_range_dev || n_nodes <= 0))
       return set_err(c, GC_E_INVAL, "gc_backward: node table and node ranges needed");
-    if (n_nodes > 0 && b->gnode.ensure(sizeof(float) * ns * (size_t)n_nodes) != hipSuccess)
+    const int64_t gstride = ns * (int64_t)n_nodes;
+    if (n_nodes > 0 && b->gnode.ensure(sizeof(float) * kGradCopies * (size_t)gstride) != hipSuccess)
       return set_err(c, GC_E_NOMEM, "gc_backward: node gradients");
-    if (n_nodes > 0) GC_HIP(c, launch_fill_f32(b->gnode.as<float>(), 0.f, ns * (int64_t)n_nodes, s));
+    if (n_nodes > 0) GC_HIP(c, launch_fill_f32(b->gnode.as<float>(), 0.f, kGradCopies * gstride, s));
     GravAdjArgs a{};
     a.f.tasks = b->d_tasks.as<gc_task>();
     a.f.n_tasks = T;
@@ -1020,10 +1021,11 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
     a.gmass = gmass_dev;
     a.src_id = packed ? b->d_U.as<int32_t>() : nullptr;
     a.gnode = b->gnode.as<float>();
+    a.gstride = gstride;
     GC_HIP(c, launch_grav_adjoint(packed, order, a, 4, s));
     if (n_nodes > 0)
       GC_HIP(c, launch_node_chain(order, node_range_dev, n_nodes, reinterpret_cast<const float4*>(nodes_dev),
-                                  b->gnode.as<float>(), b->pool->src, a.gpos, gmass_dev, s));
+                                  b->gnode.as<float>(), gstride, b->pool->src, a.gpos, gmass_dev, s));
     return GC_OK;
   }
   if (!gparam_dev) return set_err(c, GC_E_INVAL, "gc_backward: Lennard-Jones needs gparam");

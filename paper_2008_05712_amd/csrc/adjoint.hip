@@ -21,7 +21,12 @@
 // blocks of 8 targets held in registers
 // (LDS broadcast), so each lane accumulates its source's gradient across
 // the block and each target's gradient is reduced across the wavefront once
-// per block.  Scatters use hardware FP32 atomics (order-dependent rounding).
+// per block (then added with an FP32 atomic: order-dependent rounding).  A
+// source's gradient from one task is kept in a record of its own, one per
+// visit (entry of a node list, flat direct position): the lane that owns the
+// visit adds each block's part to it, so nothing contends.  The records are
+// then gathered through per-node and per-particle visit indices and summed in
+// a fixed order; the node sums reach the member particles through the chain.
 //
 // Lennard-Jones: h_i = g_i / m_i, dh = h_i - h_j, p = dh . d, f' = df/d(r^2):
 //   dL/dx_i += f dh + 2 f' p d, dL/dx_j -= the same,
@@ -39,6 +44,9 @@
 
 namespace gc {
 namespace {
+
+using dev::gld;
+using dev::gst;
 
 constexpr int kTB = 8;  // targets per register block
 
@@ -68,8 +76,8 @@ __device__ __forceinline__ int wave_excl_scan(int v, int* total) {
 }
 
 // One workgroup of 4 wavefronts per task: wave w takes the task's nodes w, w + 4, ... and the
-// flat direct positions of every fourth group of 64; all gradients are scattered with atomics, so
-// the waves need no reduction among themselves.
+// flat direct positions of every fourth group of 64; source gradients go to the visits' records and
+// target gradients are added with atomics, so the waves need no reduction among themselves.
 template <bool PACKED, int ORDER>
 __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
   constexpr int NS = ORDER == 2 ? 10 : 4;  // node gradient floats: dL/dcom, dL/dM (and sym(dL/dS))
@@ -171,22 +179,27 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
         gM = __builtin_fmaf(gd, ri3, gM);
       }
       if (valid) {
-        float* q = A.gnode + (int64_t)(blockIdx.x % kGradCopies) * A.gstride + NS * nd;
-        unsafeAtomicAdd(q, gcx);
-        unsafeAtomicAdd(q + 1, gcy);
-        unsafeAtomicAdd(q + 2, gcz);
-        unsafeAtomicAdd(q + 3, -G * gM);
+        // this lane owns visit n_first + e for every block of targets: the first block stores, the
+        // later ones add (the same lane, in program order, so no atomics are needed)
+        float4* q = A.vnode + (int64_t)(ORDER == 2 ? 3 : 1) * (tk.n_first + e);
+        float4 v0 = make_float4(gcx, gcy, gcz, -G * gM);
+        float4 v1 = make_float4(G * hxx, G * hyy, G * hzz, G * hxy), v2 = make_float4(G * hxz, G * hyz, 0.f, 0.f);
+        if (tb0 > 0) {
+          v0 += gld(q);
+          if (ORDER == 2) {
+            v1 += gld(q + 1);
+            v2 += gld(q + 2);
+          }
+        }
+        gst(q, v0);
         if (ORDER == 2) {
-          unsafeAtomicAdd(q + 4, G * hxx);
-          unsafeAtomicAdd(q + 5, G * hyy);
-          unsafeAtomicAdd(q + 6, G * hzz);
-          unsafeAtomicAdd(q + 7, G * hxy);
-          unsafeAtomicAdd(q + 8, G * hxz);
-          unsafeAtomicAdd(q + 9, G * hyz);
+          gst(q + 1, v1);
+          gst(q + 2, v2);
         }
       }
     }
     // ---- direct sources: lane = flat position within a group of up to 64 ranges
+    int vbase = uniform(A.joff[t]);  // direct visit of the group's first flat position
     for (int rg = 0; rg < tk.j_nranges; rg += 64) {
       const int nr = tk.j_nranges - rg < 64 ? tk.j_nranges - rg : 64;
       int2 g = make_int2(0, 0);
@@ -233,14 +246,14 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
           tgx[k] -= wx; tgy[k] -= wy; tgz[k] -= wz;
           gms = __builtin_fmaf(self ? 0.f : gu, ri3, gms);
         }
-        if (valid) {
-          float4* q = A.gpos + sid;
-          unsafeAtomicAdd(&q->x, gsx);
-          unsafeAtomicAdd(&q->y, gsy);
-          unsafeAtomicAdd(&q->z, gsz);
-          unsafeAtomicAdd(A.gmass + sid, G * gms);
+        if (valid) {  // the lane's own direct visit, as for the nodes
+          float4* q = A.vdir + (vbase + f);
+          float4 v = make_float4(gsx, gsy, gsz, G * gms);
+          if (tb0 > 0) v += gld(q);
+          gst(q, v);
         }
       }
+      vbase += total;
       wave_sync();
     }
     // ---- target gradients: reduce across the wavefront, one atomic per target component
@@ -258,34 +271,57 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
   }
 }
 
-// One wavefront per node: push dL/dcom and dL/dM (and, with quadrupoles, H = sym(dL/dS)) to the
-// member particles: dx_k += (m_k / M) dL/dcom + 2 m_k H e_k, dm_k += dL/dM + e_k . dL/dcom / M + e_k.H e_k,
-// e_k = x_k - com.
-template <int ORDER>
+// One wavefront per chunk of a node's visits (at most kVisitChunk, in the node-sorted visit order):
+// the chunk's sum, lanes striding the chunk, reduced across the wavefront in a fixed order.
+template <int NQ>
+__global__ void __launch_bounds__(256) k_visit_sum(const float4* __restrict__ vnode, const int32_t* __restrict__ nvis,
+                                                   const int2* __restrict__ chunks, int32_t n_chunks,
+                                                   float4* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int ch = uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  if (ch >= n_chunks) return;
+  const int2 r = gld(chunks + ch);
+  float4 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int i = r.x + lane; i < r.y; i += 64) {
+    const float4* v = vnode + (int64_t)NQ * gld(nvis + i);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += gld(v + q);
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const float4 t = make_float4(wave_sum(acc[q].x), wave_sum(acc[q].y), wave_sum(acc[q].z), wave_sum(acc[q].w));
+    if (lane == 0) gst(part + (int64_t)NQ * ch + q, t);
+  }
+}
+
+// One wavefront per node: its gradient (the sum of its chunks' sums) pushed to the member particles:
+// dx_k += (m_k / M) dL/dcom + 2 m_k H e_k, dm_k += dL/dM + e_k . dL/dcom / M + e_k.H e_k, e_k = x_k - com.
+template <int NQ>
 __global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_nodes, const float4* __restrict__ nodes,
-                             const float* __restrict__ gnode, int64_t gstride, const float4* __restrict__ rec_by_id,
-                             float4* __restrict__ gpos, float* __restrict__ gmass) {
-  constexpr int NS = ORDER == 2 ? 10 : 4;
+                             const float4* __restrict__ part, const int32_t* __restrict__ chunk_first,
+                             const float4* __restrict__ rec_by_id, float4* __restrict__ gpos, float* __restrict__ gmass) {
   const int lane = threadIdx.x & 63;
   const int waves = gridDim.x * (blockDim.x >> 6);
   for (int nd = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); nd < n_nodes; nd += waves) {
-    // the node's gradient: the sum of its copies, in a fixed order
-    float gv[NS];
+    const int c0 = gld(chunk_first + nd), c1 = gld(chunk_first + nd + 1);
+    if (c0 == c1) continue;  // the node is in no task's list
+    float4 acc[NQ];
 #pragma unroll
-    for (int q = 0; q < NS; ++q) gv[q] = 0.f;
-    for (int cpy = 0; cpy < kGradCopies; ++cpy) {
-      const float* gp = gnode + cpy * gstride + NS * (int64_t)nd;
+    for (int q = 0; q < NQ; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int ch = c0 + lane; ch < c1; ch += 64) {
 #pragma unroll
-      for (int q = 0; q < NS; ++q) gv[q] += gp[q];
+      for (int q = 0; q < NQ; ++q) acc[q] += gld(part + (int64_t)NQ * ch + q);
     }
-    const float4 gq = make_float4(gv[0], gv[1], gv[2], gv[3]);
-    float hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;
-    bool zero = gq.x == 0.f && gq.y == 0.f && gq.z == 0.f && gq.w == 0.f;
-    if (ORDER == 2) {
-      hxx = gv[4 % NS]; hyy = gv[5 % NS]; hzz = gv[6 % NS]; hxy = gv[7 % NS]; hxz = gv[8 % NS]; hyz = gv[9 % NS];
-      zero = zero && hxx == 0.f && hyy == 0.f && hzz == 0.f && hxy == 0.f && hxz == 0.f && hyz == 0.f;
+    float gv[4 * NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      gv[4 * q] = wave_sum(acc[q].x);
+      gv[4 * q + 1] = wave_sum(acc[q].y);
+      gv[4 * q + 2] = wave_sum(acc[q].z);
+      gv[4 * q + 3] = wave_sum(acc[q].w);
     }
-    if (zero) continue;
     const float4 c = nodes[3 * nd];
     const float invM = 1.f / c.w;
     const int b = node_range[2 * nd], n = node_range[2 * nd + 1];
@@ -293,9 +329,10 @@ __global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_n
       const float4 r = rec_by_id[b + k];
       const float f = r.w * invM;
       const float ex = r.x - c.x, ey = r.y - c.y, ez = r.z - c.z;
-      float px = f * gq.x, py = f * gq.y, pz = f * gq.z;
-      float dm = gq.w + (ex * gq.x + ey * gq.y + ez * gq.z) * invM;
-      if (ORDER == 2) {
+      float px = f * gv[0], py = f * gv[1], pz = f * gv[2];
+      float dm = gv[3] + (ex * gv[0] + ey * gv[1] + ez * gv[2]) * invM;
+      if constexpr (NQ == 3) {
+        const float hxx = gv[4], hyy = gv[5], hzz = gv[6], hxy = gv[7], hxz = gv[8], hyz = gv[9];
         const float hx = hxx * ex + hxy * ey + hxz * ez;
         const float hy = hxy * ex + hyy * ey + hyz * ez;
         const float hz = hxz * ex + hyz * ey + hzz * ez;
@@ -313,6 +350,23 @@ __global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_n
   }
 }
 
+// One lane per particle id: the sum of its direct visits, in index order, added to its gradients.
+__global__ void __launch_bounds__(256) k_direct_sum(const float4* __restrict__ vdir, const int32_t* __restrict__ dstart,
+                                                    const int32_t* __restrict__ dvis, int32_t n_ids,
+                                                    float4* __restrict__ gpos, float* __restrict__ gmass) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n_ids) return;
+  const int v0 = gld(dstart + id), v1 = gld(dstart + id + 1);
+  if (v0 == v1) return;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int v = v0; v < v1; ++v) acc += gld(vdir + gld(dvis + v));
+  float4 g = gld(gpos + id);
+  g.x += acc.x;
+  g.y += acc.y;
+  g.z += acc.z;
+  gst(gpos + id, g);
+  gmass[id] += acc.w;
+}
 
 constexpr int kMaxTypes = 8;
 constexpr int kLJTile = 128;
@@ -786,18 +840,36 @@ hipError_t launch_grav_adjoint(bool packed, int order, const GravAdjArgs& a, int
   return hipGetLastError();
 }
 
+hipError_t launch_visit_sums(int order, const float4* vnode, const int32_t* nvis, const int2* chunks,
+                             int32_t n_chunks, float4* part, hipStream_t s) {
+  if (n_chunks <= 0) return hipSuccess;
+  const int g = (n_chunks + 3) / 4;
+  if (order == 2)
+    hipLaunchKernelGGL(k_visit_sum<3>, dim3(g), dim3(256), 0, s, vnode, nvis, chunks, n_chunks, part);
+  else
+    hipLaunchKernelGGL(k_visit_sum<1>, dim3(g), dim3(256), 0, s, vnode, nvis, chunks, n_chunks, part);
+  return hipGetLastError();
+}
+
 hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nodes, const float4* nodes,
-                             const float* gnode, int64_t gstride, const float4* rec_by_id, float4* gpos, float* gmass,
-                             hipStream_t s) {
+                             const float4* part, const int32_t* chunk_first, const float4* rec_by_id, float4* gpos,
+                             float* gmass, hipStream_t s) {
   if (n_nodes <= 0) return hipSuccess;
   int g = (n_nodes + 3) / 4;
   if (g > 16384) g = 16384;
   if (order == 2)
-    hipLaunchKernelGGL(k_node_chain<2>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, gstride,
+    hipLaunchKernelGGL(k_node_chain<3>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, part, chunk_first,
                        rec_by_id, gpos, gmass);
   else
-    hipLaunchKernelGGL(k_node_chain<1>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, gnode, gstride,
+    hipLaunchKernelGGL(k_node_chain<1>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, part, chunk_first,
                        rec_by_id, gpos, gmass);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_sums(const float4* vdir, const int32_t* dstart, const int32_t* dvis, int32_t n_ids,
+                              float4* gpos, float* gmass, hipStream_t s) {
+  if (n_ids <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_direct_sum, dim3((n_ids + 255) / 256), dim3(256), 0, s, vdir, dstart, dvis, n_ids, gpos, gmass);
   return hipGetLastError();
 }
 

@@ -193,19 +193,26 @@ struct GravAdjArgs {
   float4* gpos;            // by id
   float* gmass;            // by id
   const int32_t* src_id;   // position in rec -> id (PACK: U; LISTS: slot -> id map; nullptr: identity)
-  float* gnode;            // per node: dL/dcom (3) and dL/dM, 4 floats (quadrupole: then sym(dL/dS), 10);
-                           // kGradCopies copies gstride floats apart, block b adding to copy b % kGradCopies
-  int64_t gstride;
+  const int32_t* joff;     // per task: first direct visit (the task's flat direct positions follow in order)
+  float4* vnode;           // per node visit (entry of the node lists): dL/dcom (3) and dL/dM; quadrupole:
+                           // then sym(dL/dS) xx yy zz xy xz yz and two unused floats (3 float4 per visit)
+  float4* vdir;            // per direct visit: dL/dx (3) and dL/dm of the source
 };
-// Node gradients are scattered into this many copies (a tree's top nodes are in nearly every task's
-// list: one copy would put their atomics on a few addresses); the node chain sums them.
-constexpr int kGradCopies = 16;
-// order 1: monopole nodes, gnode 4 floats per node (dL/dcom, dL/dM); order 2: quadrupole nodes,
-// 10 floats per node (then sym(dL/dS): xx yy zz xy xz yz)
+// Visits of one node are summed in chunks of at most this many (one wavefront per chunk), so that a
+// node found in nearly every task's list adds no long serial tail.
+constexpr int kVisitChunk = 256;
+// order 1: monopole nodes (one float4 per node visit); order 2: quadrupole nodes (three)
 hipError_t launch_grav_adjoint(bool packed, int order, const GravAdjArgs& a, int waves_per_block, hipStream_t s);
+// The gradients of the visits, gathered through the visit indices built on the host: node visits
+// summed per chunk into `part` (chunks of each node contiguous, chunk_first per node), then per node
+// and pushed to the member particles; direct visits summed per particle id into gpos / gmass.
+hipError_t launch_visit_sums(int order, const float4* vnode, const int32_t* nvis, const int2* chunks,
+                             int32_t n_chunks, float4* part, hipStream_t s);
 hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nodes, const float4* nodes,
-                             const float* gnode, int64_t gstride, const float4* rec_by_id, float4* gpos, float* gmass,
-                             hipStream_t s);
+                             const float4* part, const int32_t* chunk_first, const float4* rec_by_id, float4* gpos,
+                             float* gmass, hipStream_t s);
+hipError_t launch_direct_sums(const float4* vdir, const int32_t* dstart, const int32_t* dvis, int32_t n_ids,
+                              float4* gpos, float* gmass, hipStream_t s);
 struct LJAdjArgs {
   LJArgs f;
   const float4* cot;       // by id

@@ -115,7 +115,11 @@ struct gc_batch_ {
   DevBuf d_irank, d_jrank;
   // reorganisation buffers
   DevBuf uslot, missing, mslot, free_list, state, packed, ilist, jlist, queue;
-  DevBuf gnode, force, ppart;  // adjoint scratch: node gradients, recomputed LJ forces, LJ parameter partials
+  DevBuf force, ppart;  // adjoint scratch: recomputed LJ forces, LJ parameter partials
+  // gravity adjoint: per-visit gradient records, the node visits grouped by node and cut into chunks,
+  // the chunk sums, and the direct visits grouped by source id (built on the first backward call)
+  DevBuf vnode, vdir, nvis, nchunks, nchunk_first, npart, dstart, dvis;
+  int32_t adj_nodes = -1, adj_chunks = 0;  // node count the indices were built for (-1: none)
   // state of the last reorganisation
   int32_t mode = -1;
   gc_pool pool = nullptr;
@@ -295,7 +299,8 @@ extern "C" gc_status gc_batch_destroy(gc_batch b) {
   (void)hipDeviceSynchronize();
   for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs, &b->d_U,
                     &b->pranges, &b->pibeg, &b->d_irank, &b->d_jrank, &b->uslot, &b->missing, &b->mslot, &b->free_list,
-                    &b->state, &b->packed, &b->ilist, &b->jlist, &b->queue, &b->gnode, &b->force, &b->ppart, &b->d_ljtgt, &b->d_ljent})
+                    &b->state, &b->packed, &b->ilist, &b->jlist, &b->queue, &b->force, &b->ppart, &b->vnode, &b->vdir, &b->nvis,
+                    &b->nchunks, &b->nchunk_first, &b->npart, &b->dstart, &b->dvis, &b->d_ljtgt, &b->d_ljent})
     d->release();
   delete b;
   return GC_OK;
@@ -533,6 +538,7 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   b->h_pibeg = std::move(pib);
   b->committed = true;
   b->ranks_ready = false;
+  b->adj_nodes = -1;
   b->mode = -1;
   return GC_OK;
 }
@@ -542,6 +548,73 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
 // words of both chains.  Tags make the words and the free-slot list self-invalidating; both are
 // zeroed whenever either is (re)allocated so that no stale entry can carry a future tag.
 static bool lists_mode(int32_t mode) { return mode == GC_REORG_INDIRECT || mode == GC_REORG_SORTED; }
+
+// Visit indices of the gravity adjoint.  Node visits (entries of the node lists, in list order) are
+// grouped by node by a counting sort, keeping visit order within a node, and each node's run is cut
+// into chunks of at most kVisitChunk; direct visits (the tasks' flat direct positions, tasks in order)
+// are grouped the same way by source id.  Node ids must lie in [0, n_nodes).
+static gc_status build_adj_index(gc_batch b, int32_t n_nodes, hipStream_t s) {
+  gc_ctx c = b->ctx;
+  const int64_t nv = (int64_t)b->nodes.size();
+  std::vector<int32_t> nstart((size_t)n_nodes + 1, 0);
+  for (int64_t v = 0; v < nv; ++v) {
+    const int32_t nd = b->nodes[v];
+    if (nd >= n_nodes) return set_err(c, GC_E_INVAL, "gc_backward: node index %d at list entry %lld >= n_nodes %d",
+                                      nd, (long long)v, n_nodes);
+    ++nstart[(size_t)nd + 1];
+  }
+  for (int32_t k = 0; k < n_nodes; ++k) nstart[k + 1] += nstart[k];
+  std::vector<int32_t> nvis((size_t)std::max<int64_t>(nv, 1));
+  {
+    std::vector<int32_t> fill(nstart.begin(), nstart.end() - 1);
+    for (int64_t v = 0; v < nv; ++v) nvis[fill[b->nodes[v]]++] = (int32_t)v;
+  }
+  std::vector<int32_t> chunks, chunk_first((size_t)n_nodes + 1);
+  for (int32_t k = 0; k < n_nodes; ++k) {
+    chunk_first[k] = (int32_t)(chunks.size() / 2);
+    for (int32_t c0 = nstart[k]; c0 < nstart[k + 1]; c0 += kVisitChunk) {
+      chunks.push_back(c0);
+      chunks.push_back(std::min(c0 + kVisitChunk, nstart[k + 1]));
+    }
+  }
+  chunk_first[n_nodes] = (int32_t)(chunks.size() / 2);
+  if (chunks.empty()) chunks.assign(2, 0);
+  const int32_t n_ids = b->n_ids;
+  std::vector<int32_t> dstart((size_t)n_ids + 1, 0), dvis((size_t)std::max<int64_t>(b->n_direct, 1));
+  for (const gc_task& tk : b->tasks)
+    for (int32_t r = 0; r < tk.j_nranges; ++r) {
+      const int32_t g0 = b->ranges[2 * (tk.j_first + r)], gn = b->ranges[2 * (tk.j_first + r) + 1];
+      for (int32_t k = 0; k < gn; ++k) ++dstart[(size_t)g0 + k + 1];
+    }
+  for (int32_t k = 0; k < n_ids; ++k) dstart[k + 1] += dstart[k];
+  {
+    std::vector<int32_t> fill(dstart.begin(), dstart.end() - 1);
+    int32_t v = 0;
+    for (const gc_task& tk : b->tasks)
+      for (int32_t r = 0; r < tk.j_nranges; ++r) {
+        const int32_t g0 = b->ranges[2 * (tk.j_first + r)], gn = b->ranges[2 * (tk.j_first + r) + 1];
+        for (int32_t k = 0; k < gn; ++k) dvis[fill[g0 + k]++] = v++;
+      }
+  }
+  const int nq = 3;  // room for the quadrupole records, so one build serves both orders
+  hipError_t e = b->vnode.ensure(sizeof(float4) * nq * (size_t)std::max<int64_t>(nv, 1));
+  if (e == hipSuccess) e = b->vdir.ensure(sizeof(float4) * (size_t)std::max<int64_t>(b->n_direct, 1));
+  if (e == hipSuccess) e = b->npart.ensure(sizeof(float4) * nq * (chunks.size() / 2));
+  auto up = [&](DevBuf& d, const std::vector<int32_t>& h) {
+    if (e == hipSuccess) e = d.ensure(sizeof(int32_t) * h.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(d.p, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, s);
+  };
+  up(b->nvis, nvis);
+  up(b->nchunks, chunks);
+  up(b->nchunk_first, chunk_first);
+  up(b->dstart, dstart);
+  up(b->dvis, dvis);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors go out of scope
+  if (e != hipSuccess) return hip_fail(c, e, "gc_backward: visit indices");
+  b->adj_nodes = n_nodes;
+  b->adj_chunks = chunk_first[n_nodes];
+  return GC_OK;
+}
 
 static hipError_t build_ranks(gc_batch b, hipStream_t s) {
   // union rank of every address-list entry: targets in task order, then direct entries
@@ -999,13 +1072,12 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
   const bool packed = (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT);
   if (b->kind == GC_KIND_GRAV) {
     const int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
-    const int ns = order == 2 ? 10 : 4;
     if (!b->nodes.empty() && (!nodes_dev || !node_range_dev || n_nodes <= 0))
       return set_err(c, GC_E_INVAL, "gc_backward: node table and node ranges needed");
-    const int64_t gstride = ns * (int64_t)n_nodes;
-    if (n_nodes > 0 && b->gnode.ensure(sizeof(float) * kGradCopies * (size_t)gstride) != hipSuccess)
-      return set_err(c, GC_E_NOMEM, "gc_backward: node gradients");
-    if (n_nodes > 0) GC_HIP(c, launch_fill_f32(b->gnode.as<float>(), 0.f, kGradCopies * gstride, s));
+    if (b->adj_nodes != std::max<int32_t>(n_nodes, 0)) {
+      gc_status bst = build_adj_index(b, std::max<int32_t>(n_nodes, 0), s);
+      if (bst != GC_OK) return bst;
+    }
     GravAdjArgs a{};
     a.f.tasks = b->d_tasks.as<gc_task>();
     a.f.n_tasks = T;
@@ -1020,12 +1092,20 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
     a.gpos = reinterpret_cast<float4*>(gpos_dev);
     a.gmass = gmass_dev;
     a.src_id = packed ? b->d_U.as<int32_t>() : nullptr;
-    a.gnode = b->gnode.as<float>();
-    a.gstride = gstride;
+    a.joff = b->d_joff.as<int32_t>();
+    a.vnode = b->vnode.as<float4>();
+    a.vdir = b->vdir.as<float4>();
     GC_HIP(c, launch_grav_adjoint(packed, order, a, 4, s));
-    if (n_nodes > 0)
+    if (b->n_direct > 0)
+      GC_HIP(c, launch_direct_sums(a.vdir, b->dstart.as<int32_t>(), b->dvis.as<int32_t>(), b->n_ids, a.gpos,
+                                   gmass_dev, s));
+    if (!b->nodes.empty()) {
+      GC_HIP(c, launch_visit_sums(order, a.vnode, b->nvis.as<int32_t>(), b->nchunks.as<int2>(), b->adj_chunks,
+                                  b->npart.as<float4>(), s));
       GC_HIP(c, launch_node_chain(order, node_range_dev, n_nodes, reinterpret_cast<const float4*>(nodes_dev),
-                                  b->gnode.as<float>(), gstride, b->pool->src, a.gpos, gmass_dev, s));
+                                  b->npart.as<float4>(), b->nchunk_first.as<int32_t>(), b->pool->src, a.gpos,
+                                  gmass_dev, s));
+    }
     return GC_OK;
   }
   if (!gparam_dev) return set_err(c, GC_E_INVAL, "gc_backward: Lennard-Jones needs gparam");

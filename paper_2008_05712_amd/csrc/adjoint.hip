@@ -350,22 +350,38 @@ __global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_n
   }
 }
 
-// One lane per particle id: the sum of its direct visits, in index order, added to its gradients.
-__global__ void __launch_bounds__(256) k_direct_sum(const float4* __restrict__ vdir, const int32_t* __restrict__ dstart,
-                                                    const int32_t* __restrict__ dvis, int32_t n_ids,
+// One wavefront per 64 consecutive entries of the direct visits sorted by source id: a segmented
+// inclusive scan (ids are sorted, so equal neighbours mean one run) sums each id's run within the
+// wavefront, and the run's last lane adds it to the gradients.  A particle whose visits span several
+// wavefronts gets one addition from each, so no lane walks a long list.
+__global__ void __launch_bounds__(256) k_direct_sum(const float4* __restrict__ vdir, const int32_t* __restrict__ dvis,
+                                                    const int32_t* __restrict__ dkey, int32_t n_vis,
                                                     float4* __restrict__ gpos, float* __restrict__ gmass) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n_ids) return;
-  const int v0 = gld(dstart + id), v1 = gld(dstart + id + 1);
-  if (v0 == v1) return;
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int v = v0; v < v1; ++v) acc += gld(vdir + gld(dvis + v));
-  float4 g = gld(gpos + id);
-  g.x += acc.x;
-  g.y += acc.y;
-  g.z += acc.z;
-  gst(gpos + id, g);
-  gmass[id] += acc.w;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n_vis;
+  int key = valid ? gld(dkey + i) : -1 - lane;  // distinct negative keys: past-the-end lanes form no run
+  float4 v = valid ? gld(vdir + gld(dvis + i)) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int ku = __shfl_up(key, d, 64);
+    const float ux = __shfl_up(v.x, d, 64), uy = __shfl_up(v.y, d, 64), uz = __shfl_up(v.z, d, 64),
+                uw = __shfl_up(v.w, d, 64);
+    if (lane >= d && ku == key) {
+      v.x += ux;
+      v.y += uy;
+      v.z += uz;
+      v.w += uw;
+    }
+  }
+  const int kn = __shfl_down(key, 1, 64);
+  if (valid && (lane == 63 || kn != key)) {
+    float4* q = gpos + key;
+    unsafeAtomicAdd(&q->x, v.x);
+    unsafeAtomicAdd(&q->y, v.y);
+    unsafeAtomicAdd(&q->z, v.z);
+    unsafeAtomicAdd(gmass + key, v.w);
+  }
 }
 
 constexpr int kMaxTypes = 8;
@@ -866,10 +882,10 @@ hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nod
   return hipGetLastError();
 }
 
-hipError_t launch_direct_sums(const float4* vdir, const int32_t* dstart, const int32_t* dvis, int32_t n_ids,
+hipError_t launch_direct_sums(const float4* vdir, const int32_t* dvis, const int32_t* dkey, int32_t n_vis,
                               float4* gpos, float* gmass, hipStream_t s) {
-  if (n_ids <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_direct_sum, dim3((n_ids + 255) / 256), dim3(256), 0, s, vdir, dstart, dvis, n_ids, gpos, gmass);
+  if (n_vis <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_direct_sum, dim3((n_vis + 255) / 256), dim3(256), 0, s, vdir, dvis, dkey, n_vis, gpos, gmass);
   return hipGetLastError();
 }
 

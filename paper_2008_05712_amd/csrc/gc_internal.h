@@ -205,13 +205,14 @@ constexpr int kVisitChunk = 256;
 hipError_t launch_grav_adjoint(bool packed, int order, const GravAdjArgs& a, int waves_per_block, hipStream_t s);
 // The gradients of the visits, gathered through the visit indices built on the host: node visits
 // summed per chunk into `part` (chunks of each node contiguous, chunk_first per node), then per node
-// and pushed to the member particles; direct visits summed per particle id into gpos / gmass.
+// and pushed to the member particles; direct visits, sorted by source id (dkey), summed per id in
+// runs of a wavefront and added to gpos / gmass.
 hipError_t launch_visit_sums(int order, const float4* vnode, const int32_t* nvis, const int2* chunks,
                              int32_t n_chunks, float4* part, hipStream_t s);
 hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nodes, const float4* nodes,
                              const float4* part, const int32_t* chunk_first, const float4* rec_by_id, float4* gpos,
                              float* gmass, hipStream_t s);
-hipError_t launch_direct_sums(const float4* vdir, const int32_t* dstart, const int32_t* dvis, int32_t n_ids,
+hipError_t launch_direct_sums(const float4* vdir, const int32_t* dvis, const int32_t* dkey, int32_t n_vis,
                               float4* gpos, float* gmass, hipStream_t s);
 struct LJAdjArgs {
   LJArgs f;

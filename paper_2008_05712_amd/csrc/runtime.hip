@@ -118,7 +118,7 @@ struct gc_batch_ {
   DevBuf force, ppart;  // adjoint scratch: recomputed LJ forces, LJ parameter partials
   // gravity adjoint: per-visit gradient records, the node visits grouped by node and cut into chunks,
   // the chunk sums, and the direct visits grouped by source id (built on the first backward call)
-  DevBuf vnode, vdir, nvis, nchunks, nchunk_first, npart, dstart, dvis;
+  DevBuf vnode, vdir, nvis, nchunks, nchunk_first, npart, dvis, dkey;
   int32_t adj_nodes = -1, adj_chunks = 0;  // node count the indices were built for (-1: none)
   // state of the last reorganisation
   int32_t mode = -1;
@@ -300,7 +300,7 @@ extern "C" gc_status gc_batch_destroy(gc_batch b) {
   for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs, &b->d_U,
                     &b->pranges, &b->pibeg, &b->d_irank, &b->d_jrank, &b->uslot, &b->missing, &b->mslot, &b->free_list,
                     &b->state, &b->packed, &b->ilist, &b->jlist, &b->queue, &b->force, &b->ppart, &b->vnode, &b->vdir, &b->nvis,
-                    &b->nchunks, &b->nchunk_first, &b->npart, &b->dstart, &b->dvis, &b->d_ljtgt, &b->d_ljent})
+                    &b->nchunks, &b->nchunk_first, &b->npart, &b->dvis, &b->dkey, &b->d_ljtgt, &b->d_ljent})
     d->release();
   delete b;
   return GC_OK;
@@ -580,7 +580,8 @@ static gc_status build_adj_index(gc_batch b, int32_t n_nodes, hipStream_t s) {
   chunk_first[n_nodes] = (int32_t)(chunks.size() / 2);
   if (chunks.empty()) chunks.assign(2, 0);
   const int32_t n_ids = b->n_ids;
-  std::vector<int32_t> dstart((size_t)n_ids + 1, 0), dvis((size_t)std::max<int64_t>(b->n_direct, 1));
+  std::vector<int32_t> dstart((size_t)n_ids + 1, 0), dvis((size_t)std::max<int64_t>(b->n_direct, 1)),
+      dkey((size_t)std::max<int64_t>(b->n_direct, 1));
   for (const gc_task& tk : b->tasks)
     for (int32_t r = 0; r < tk.j_nranges; ++r) {
       const int32_t g0 = b->ranges[2 * (tk.j_first + r)], gn = b->ranges[2 * (tk.j_first + r) + 1];
@@ -593,7 +594,10 @@ static gc_status build_adj_index(gc_batch b, int32_t n_nodes, hipStream_t s) {
     for (const gc_task& tk : b->tasks)
       for (int32_t r = 0; r < tk.j_nranges; ++r) {
         const int32_t g0 = b->ranges[2 * (tk.j_first + r)], gn = b->ranges[2 * (tk.j_first + r) + 1];
-        for (int32_t k = 0; k < gn; ++k) dvis[fill[g0 + k]++] = v++;
+        for (int32_t k = 0; k < gn; ++k) {
+          dkey[fill[g0 + k]] = g0 + k;
+          dvis[fill[g0 + k]++] = v++;
+        }
       }
   }
   const int nq = 3;  // room for the quadrupole records, so one build serves both orders
@@ -607,8 +611,8 @@ static gc_status build_adj_index(gc_batch b, int32_t n_nodes, hipStream_t s) {
   up(b->nvis, nvis);
   up(b->nchunks, chunks);
   up(b->nchunk_first, chunk_first);
-  up(b->dstart, dstart);
   up(b->dvis, dvis);
+  up(b->dkey, dkey);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors go out of scope
   if (e != hipSuccess) return hip_fail(c, e, "gc_backward: visit indices");
   b->adj_nodes = n_nodes;
@@ -1097,8 +1101,8 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
     a.vdir = b->vdir.as<float4>();
     GC_HIP(c, launch_grav_adjoint(packed, order, a, 4, s));
     if (b->n_direct > 0)
-      GC_HIP(c, launch_direct_sums(a.vdir, b->dstart.as<int32_t>(), b->dvis.as<int32_t>(), b->n_ids, a.gpos,
-                                   gmass_dev, s));
+      GC_HIP(c, launch_direct_sums(a.vdir, b->dvis.as<int32_t>(), b->dkey.as<int32_t>(), (int32_t)b->n_direct,
+                                   a.gpos, gmass_dev, s));
     if (!b->nodes.empty()) {
       GC_HIP(c, launch_visit_sums(order, a.vnode, b->nvis.as<int32_t>(), b->nchunks.as<int2>(), b->adj_chunks,
                                   b->npart.as<float4>(), s));

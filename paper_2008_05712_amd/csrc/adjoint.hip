@@ -18,7 +18,7 @@
 //
 // Schedule: one workgroup of 4 wavefronts per task, splitting its sources;
 // lanes are sources (nodes, then direct particles), the loop runs over
-// blocks of 8 targets held in registers
+// blocks of 8 targets (6 with quadrupole nodes) held in registers
 // (LDS broadcast), so each lane accumulates its source's gradient across
 // the block and each target's gradient is reduced across the wavefront once
 // per block (then added with an FP32 atomic: order-dependent rounding).  A
@@ -48,7 +48,6 @@ namespace {
 using dev::gld;
 using dev::gst;
 
-constexpr int kTB = 8;  // targets per register block
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -80,7 +79,8 @@ __device__ __forceinline__ int wave_excl_scan(int v, int* total) {
 // target gradients are added with atomics, so the waves need no reduction among themselves.
 template <bool PACKED, int ORDER>
 __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
-  constexpr int NS = ORDER == 2 ? 10 : 4;  // node gradient floats: dL/dcom, dL/dM (and sym(dL/dS))
+  // targets per register block: six with quadrupole nodes keep the kernel at three wavefronts per SIMD
+  constexpr int kTB = ORDER == 2 ? 6 : 8;
   const GravArgs& a = A.f;
   __shared__ float4 tpos[4][kTB], tcot[4][kTB];
   __shared__ int ro[4][64], rb[4][64];
@@ -296,15 +296,15 @@ __global__ void __launch_bounds__(256) k_visit_sum(const float4* __restrict__ vn
   }
 }
 
-// One wavefront per node: its gradient (the sum of its chunks' sums) pushed to the member particles:
+// One workgroup per node (its member loop spread over 256 lanes: a top node holds tens of thousands of
+// particles): its gradient (the sum of its chunks' sums, formed by each wavefront) pushed to the members:
 // dx_k += (m_k / M) dL/dcom + 2 m_k H e_k, dm_k += dL/dM + e_k . dL/dcom / M + e_k.H e_k, e_k = x_k - com.
 template <int NQ>
-__global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_nodes, const float4* __restrict__ nodes,
+__global__ void __launch_bounds__(256) k_node_chain(const int32_t* __restrict__ node_range, int32_t n_nodes, const float4* __restrict__ nodes,
                              const float4* __restrict__ part, const int32_t* __restrict__ chunk_first,
                              const float4* __restrict__ rec_by_id, float4* __restrict__ gpos, float* __restrict__ gmass) {
   const int lane = threadIdx.x & 63;
-  const int waves = gridDim.x * (blockDim.x >> 6);
-  for (int nd = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); nd < n_nodes; nd += waves) {
+  for (int nd = blockIdx.x; nd < n_nodes; nd += gridDim.x) {
     const int c0 = gld(chunk_first + nd), c1 = gld(chunk_first + nd + 1);
     if (c0 == c1) continue;  // the node is in no task's list
     float4 acc[NQ];
@@ -325,7 +325,7 @@ __global__ void k_node_chain(const int32_t* __restrict__ node_range, int32_t n_n
     const float4 c = nodes[3 * nd];
     const float invM = 1.f / c.w;
     const int b = node_range[2 * nd], n = node_range[2 * nd + 1];
-    for (int k = lane; k < n; k += 64) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
       const float4 r = rec_by_id[b + k];
       const float f = r.w * invM;
       const float ex = r.x - c.x, ey = r.y - c.y, ez = r.z - c.z;
@@ -871,8 +871,7 @@ hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nod
                              const float4* part, const int32_t* chunk_first, const float4* rec_by_id, float4* gpos,
                              float* gmass, hipStream_t s) {
   if (n_nodes <= 0) return hipSuccess;
-  int g = (n_nodes + 3) / 4;
-  if (g > 16384) g = 16384;
+  const int g = n_nodes < 65536 ? n_nodes : 65536;
   if (order == 2)
     hipLaunchKernelGGL(k_node_chain<3>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, part, chunk_first,
                        rec_by_id, gpos, gmass);

@@ -321,7 +321,14 @@ gc_status gc_zero_f32(gc_ctx ctx, float* dev, int64_t n, void* stream);
  * with quadrupoles, S = sum m_k (x_k - com)(x_k - com)^T (node_range_dev: int32
  * [2 * n_nodes] (first id, count) of each node's members; members are read
  * in place from the pool's source, which must be device memory).  Lists and
- * cutoff decisions are those of the forward pass.  Asynchronous.
+ * cutoff decisions are those of the forward pass.  Gravity keeps each task's
+ * gradient for each node-list entry and each direct source in a record of its
+ * own and sums the records per node and per particle in a fixed order; the
+ * first gravity call on a batch (and any call with another n_nodes) builds the
+ * node -> entries and particle -> entries indices on the host and uploads them,
+ * waiting on `stream` (GC_E_INVAL if a node index is >= n_nodes).  The batch
+ * then holds 52 bytes per node-list entry, 24 per direct source entry and a
+ * few bytes per node until it is destroyed.  Otherwise asynchronous.
  */
 gc_status gc_backward(gc_batch batch, const gc_force_params* prm, const float* nodes_dev,
                       const int32_t* node_range_dev, int32_t n_nodes, const float* cot_dev, float* gpos_dev,

@@ -74,6 +74,39 @@ def test_quadrupole_vjp_matches_oracle(ctx, mode):
     assert ok, ("masses", e)
 
 
+def test_grav_vjp_repeated_calls_and_both_orders_on_one_batch(ctx):
+    # The per-entry gradient records are rewritten by every call (a second call adds the same
+    # gradients again), and one visit index serves monopole and quadrupole calls alike.
+    import torch
+    w = W.build_grav(W.plummer(4096, 63), bucket=16, theta=0.7)
+    g = np.random.default_rng(64).normal(size=(w.n, 3)).astype(np.float32).astype(np.float64)
+    print(f"[gpu] gravity adjoint, repeated calls, Plummer 4096, {w.n_tasks} tasks", flush=True)
+    rig = GravRig(ctx, w)
+    b = rig.batch(whole(w))
+    cot = torch.zeros((w.n, 4), dtype=torch.float32, device="cuda")
+    cot[:, :3] = torch.from_numpy(g.astype(np.float32)).cuda()
+    nr = torch.from_numpy(np.ascontiguousarray(w.node_range)).cuda()
+    n_nodes = w.nodes.shape[0]
+    for order in (1, 2):
+        rig.run(b, gc.REORG_NONE, order=order)
+        gpos = torch.zeros((w.n, 4), dtype=torch.float32, device="cuda")
+        gmass = torch.zeros(w.n, dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            b.backward(gc.grav_params(order=order), rig.nodes, nr, n_nodes, cot, gpos, gmass)
+        torch.cuda.synchronize()
+        rp, rm = O.vjp_grav(w, g, order=order)
+        ok, e = close(gpos.cpu().numpy()[:, :3] / 2, rp)
+        assert ok, (order, "positions", e)
+        ok, e = close(gmass.cpu().numpy() / 2, rm)
+        assert ok, (order, "masses", e)
+    # a node index beyond n_nodes is refused on the host, before anything is launched
+    with pytest.raises(gc.GcError) as ei:
+        b.backward(gc.grav_params(order=2), rig.nodes, nr, int(w.node_idx.max()), cot, gpos, gmass)
+    assert ei.value.status == gc.GC_E_INVAL
+    b.destroy()
+    rig.close()
+
+
 def test_grav_vjp_matches_finite_differences_512(ctx):
     w = W.build_grav(W.plummer(512, 51), bucket=16, theta=0.7)
     rng = np.random.default_rng(52)

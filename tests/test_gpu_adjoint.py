@@ -48,7 +48,7 @@ def grav_vjp_gpu(ctx, w, g, mode=gc.REORG_NONE, order=1):
     return out
 
 
-@pytest.mark.parametrize("mode", [gc.REORG_NONE, gc.REORG_PACK])
+@pytest.mark.parametrize("mode", [gc.REORG_NONE, gc.REORG_PACK, gc.REORG_REDUNDANT])
 def test_grav_vjp_matches_oracle_tiny(ctx, mode):
     w = W.nbody_tiny()
     g = np.random.default_rng(11).normal(size=(w.n, 3)).astype(np.float32).astype(np.float64)
@@ -60,7 +60,7 @@ def test_grav_vjp_matches_oracle_tiny(ctx, mode):
     assert ok, ("masses", e)
 
 
-@pytest.mark.parametrize("mode", [gc.REORG_NONE, gc.REORG_PACK])
+@pytest.mark.parametrize("mode", [gc.REORG_NONE, gc.REORG_PACK, gc.REORG_REDUNDANT])
 def test_quadrupole_vjp_matches_oracle(ctx, mode):
     # Plummer 4,096, bucket 16, theta 0.7: quadrupole nodes, chained to members through S
     w = W.build_grav(W.plummer(4096, 61), bucket=16, theta=0.7)

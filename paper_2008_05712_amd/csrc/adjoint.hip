@@ -48,7 +48,6 @@ namespace {
 using dev::gld;
 using dev::gst;
 
-
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();

@@ -58,6 +58,7 @@ def _load():
     lib.or_lj_tasks.argtypes = [i32, I32, I32, I32, I32, I32, F32, F32, i64, i32, F64, F64, F64, dbl, F64, F64, I64]
     lib.or_lj_brute.argtypes = [i64, F32, F64, F64, F64, F64, dbl, F64, F64]
     lib.or_ewald.argtypes = [i64, F64, dbl, dbl, dbl, F64, dbl, i32, i32, F64, F64]
+    lib.or_bh_walk.argtypes = [i32, I32, I32, F64, F64, F32, i32, I32, dbl, I32, I32, I64, I64, I32, I32]
     lib.or_vjp_grav_mono.argtypes = [i32, I32, I32, I32, I32, I32, I32, I32, I32, i32, I32, F64, F64, F64, dbl, dbl,
                                      F64, i64, F64, F64]
     lib.or_vjp_grav.argtypes = [i32, I32, I32, I32, I32, I32, I32, I32, I32, i32, I32, F64, F64, F64, i32, dbl, dbl,
@@ -348,3 +349,36 @@ def per_task_rel_l2(acc_test, acc_ref, i_begin, i_count, floor_frac: float = 0.0
     if floor_frac > 0 and den.size:
         den = np.maximum(den, floor_frac * np.median(den))
     return np.sqrt(err2) / np.where(den > 0, den, 1.0)
+
+
+# ---------------------------------------------------------------- interaction lists
+
+def bh_walk(node_range, node_parent, node_side, node_com, rec, bucket_node, theta: float):
+    """Barnes-Hut lists of each bucket (see oracle.c): (n_first (nb + 1), node_idx, r_first (nb + 1),
+    ranges (n x 2)), in the walk's order."""
+    lib = _load()
+    nr = _c(node_range, np.int32)
+    par = _c(node_parent, np.int32)
+    side = _d(node_side)
+    com = _d(node_com)
+    rec = _c(rec, np.float32)
+    bn = _c(bucket_node, np.int32)
+    nn, nb = nr.shape[0], bn.shape[0]
+    nc = np.zeros(max(nb, 1), np.int32)
+    rc = np.zeros(max(nb, 1), np.int32)
+    lib.or_bh_walk(nn, _p(nr, I32), _p(par, I32), _p(side, F64), _p(com, F64), _p(rec, F32), nb, _p(bn, I32),
+                   float(theta), _p(nc, I32), _p(rc, I32), None, None, None, None)
+    nf = np.concatenate([[0], np.cumsum(nc[:nb], dtype=np.int64)])
+    rf = np.concatenate([[0], np.cumsum(rc[:nb], dtype=np.int64)])
+    node_idx = np.zeros(max(int(nf[-1]), 1), np.int32)
+    ranges = np.zeros((max(int(rf[-1]), 1), 2), np.int32)
+    nf64, rf64 = _c(nf, np.int64), _c(rf, np.int64)
+    lib.or_bh_walk(nn, _p(nr, I32), _p(par, I32), _p(side, F64), _p(com, F64), _p(rec, F32), nb, _p(bn, I32),
+                   float(theta), None, None, _p(nf64, I64), _p(rf64, I64), _p(node_idx, I32), _p(ranges, I32))
+    return nf.astype(np.int32), node_idx[:int(nf[-1])], rf.astype(np.int32), ranges[:int(rf[-1])]
+
+
+def bh_walk_workload(w, theta: float | None = None):
+    """bh_walk over a gravity workload's tree (theta defaults to the workload's)."""
+    return bh_walk(w.node_range, w.node_parent, w.node_side, w.node_mom64[:, :3], w.rec, w.meta["leaf"],
+                   w.theta if theta is None else theta)

@@ -21,6 +21,8 @@
  *    kernel, Sec. 4.1, Sec. 4.3): the pull of every periodic image of the box's
  *    total mass M at its centre of mass c, plus the neutralising background,
  *    minus the direct 1/r of the central copy that the tree walk computes.
+ *  - the Barnes-Hut interaction lists of each bucket's work request (Sec. 4.1),
+ *    a recursive descent from the definition of the opening test.
  *
  * Ewald (cubic box of side L, splitting parameter alpha; r = x - c taken to
  * the nearest image; real-space images n in {-nrep..nrep}^3; wave vectors
@@ -677,4 +679,92 @@ void or_ewald(int64_t n, const double* pos, double L, double G, double M, const 
     for (int d = 0; d < 3; ++d) acc[3 * i + d] = G * M * a[d];
     if (pot) pot[i] = -G * M * p;
   }
+}
+
+/* ---- Barnes-Hut interaction lists: the lists of a bucket's work request (Sec. 4.1) ----
+ *
+ * A bucket is a leaf of the tree; its work request holds a node list and a direct list of id
+ * ranges.  From the root, children in ascending node index (their octant order), a node N is
+ * taken into bucket B's node list when theta > 0, N's id range does not overlap B's and
+ * side(N) < theta * dist(com(N), box(B)) strictly; box(B) is the tight bounding box of B's
+ * positions (FP32 values taken exactly into FP64) and dist the Euclidean distance from a point
+ * to the box (zero inside), per axis e = lo - c below, c - hi above, else 0, summed as
+ * (e_x^2 + e_y^2) + e_z^2 before the square root.  A node that is not taken is, if a leaf, added
+ * to the direct list as its id range, and otherwise opened.  Children come from the parent array.
+ * Without node_idx / ranges the walk only counts (n_count, r_count per bucket); with them it
+ * writes each bucket's lists at n_off[b] and r_off[b].
+ */
+typedef struct {
+  const int32_t* range;
+  const double* side;
+  const double* com;
+  const int32_t* cfirst;
+  const int32_t* clist;
+  double theta;
+  int32_t bf, bc;
+  double lo[3], hi[3];
+  int32_t* nodes;
+  int32_t* ranges;
+  int64_t nn, nr;
+} walk_state;
+
+static void walk_visit(walk_state* w, int32_t k) {
+  const int32_t f = w->range[2 * k], c = w->range[2 * k + 1];
+  const int disjoint = f + c <= w->bf || w->bf + w->bc <= f;
+  double s = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double x = w->com[3 * (size_t)k + d];
+    double e = 0.0;
+    if (x < w->lo[d]) e = w->lo[d] - x;
+    else if (x > w->hi[d]) e = x - w->hi[d];
+    s += e * e;
+  }
+  if (w->theta > 0 && disjoint && w->side[k] < w->theta * sqrt(s)) {
+    if (w->nodes) w->nodes[w->nn] = k;
+    w->nn++;
+  } else if (w->cfirst[k] == w->cfirst[k + 1]) {
+    if (w->ranges) {
+      w->ranges[2 * w->nr] = f;
+      w->ranges[2 * w->nr + 1] = c;
+    }
+    w->nr++;
+  } else {
+    for (int32_t q = w->cfirst[k]; q < w->cfirst[k + 1]; ++q) walk_visit(w, w->clist[q]);
+  }
+}
+
+void or_bh_walk(int32_t n_nodes, const int32_t* node_range, const int32_t* node_parent, const double* side,
+                const double* com, const float* rec, int32_t n_buckets, const int32_t* bucket_node, double theta,
+                int32_t* n_count, int32_t* r_count, const int64_t* n_off, const int64_t* r_off, int32_t* node_idx,
+                int32_t* ranges) {
+  int32_t* cfirst = (int32_t*)calloc((size_t)n_nodes + 1, sizeof(int32_t));
+  int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_nodes > 1 ? n_nodes : 1));
+  int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_nodes > 0 ? n_nodes : 1));
+  for (int32_t k = 1; k < n_nodes; ++k) cfirst[node_parent[k] + 1]++;
+  for (int32_t k = 0; k < n_nodes; ++k) cfirst[k + 1] += cfirst[k];
+  for (int32_t k = 0; k < n_nodes; ++k) fill[k] = cfirst[k];
+  for (int32_t k = 1; k < n_nodes; ++k) clist[fill[node_parent[k]]++] = k;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t b = 0; b < n_buckets; ++b) {
+    walk_state w;
+    w.range = node_range; w.side = side; w.com = com; w.cfirst = cfirst; w.clist = clist; w.theta = theta;
+    w.bf = node_range[2 * bucket_node[b]];
+    w.bc = node_range[2 * bucket_node[b] + 1];
+    for (int d = 0; d < 3; ++d) { w.lo[d] = INFINITY; w.hi[d] = -INFINITY; }
+    for (int32_t i = w.bf; i < w.bf + w.bc; ++i)
+      for (int d = 0; d < 3; ++d) {
+        const double v = rec[4 * (size_t)i + d];
+        if (v < w.lo[d]) w.lo[d] = v;
+        if (v > w.hi[d]) w.hi[d] = v;
+      }
+    w.nodes = node_idx ? node_idx + n_off[b] : NULL;
+    w.ranges = ranges ? ranges + 2 * r_off[b] : NULL;
+    w.nn = w.nr = 0;
+    if (n_nodes > 0) walk_visit(&w, 0);
+    if (n_count) n_count[b] = (int32_t)w.nn;
+    if (r_count) r_count[b] = (int32_t)w.nr;
+  }
+  free(cfirst);
+  free(clist);
+  free(fill);
 }

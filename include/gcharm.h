@@ -334,6 +334,36 @@ gc_status gc_backward(gc_batch batch, const gc_force_params* prm, const float* n
                       const int32_t* node_range_dev, int32_t n_nodes, const float* cot_dev, float* gpos_dev,
                       float* gmass_dev, float* gparam_dev, void* stream);
 
+/* ---------------------------------------------------------------- interaction lists */
+
+/*
+ * Barnes-Hut interaction lists of every bucket's work request (Sec. 4.1: the
+ * particles of a bucket share one node list and one direct list), built on the
+ * device.  Tree contract: nodes numbered in pre-order, children in ascending
+ * index, every node's ids contiguous (node_range_dev: int32 [2 * n_nodes]
+ * (first id, count), count >= 1); node_com_dev: double [3 * n_nodes] centres of
+ * mass; node_side_dev: double [n_nodes] cube sides; rec_dev: float4 [n_ids]
+ * (x, y, z, m); bucket_node_dev: int32 [n_buckets], each bucket's leaf.
+ * Opening test, in FP64 with correctly rounded operations: bucket B takes node
+ * N when theta > 0, N's id range does not overlap B's and side(N) < theta *
+ * dist(com(N), box(B)), box(B) the tight bounding box of B's positions, dist
+ * from (e_x^2 + e_y^2) + e_z^2 with e the per-axis distance outside the box;
+ * a leaf that is not taken goes to the direct list as its id range, any other
+ * node is opened.  Lists follow the descent order (children ascending).
+ * Outputs (device, caller-owned): n_first_dev / r_first_dev int32
+ * [n_buckets + 1] offsets into node_idx_dev (int32 [node_cap]) and ranges_dev
+ * (int32 [2 * range_cap], (first id, count) pairs); totals (host) receives the
+ * node-entry and range totals.  GC_E_FULL when a capacity is short (offsets
+ * and totals are then set, the lists not written: call again with room);
+ * GC_E_INVAL for a bucket whose leaf index or id range is out of bounds.  The
+ * call waits on `stream` (twice: for the totals and at the end).
+ */
+gc_status gc_tree_walk(gc_ctx ctx, int32_t n_nodes, const int32_t* node_range_dev, const double* node_com_dev,
+                       const double* node_side_dev, const float* rec_dev, int32_t n_ids, int32_t n_buckets,
+                       const int32_t* bucket_node_dev, double theta, int32_t* n_first_dev, int32_t* r_first_dev,
+                       int32_t* node_idx_dev, int64_t node_cap, int32_t* ranges_dev, int64_t range_cap,
+                       int64_t* totals, void* stream);
+
 /* ---------------------------------------------------------------- graphs */
 
 /*

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "gc_internal.h"
+#include "walk.h"
 
 using namespace gc;
 
@@ -1547,4 +1548,75 @@ extern "C" gc_status gc_autotune(gc_batch b, const gc_force_params* base, const 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return st;
+}
+
+// ===================================================================== interaction lists (tree walk)
+
+namespace {
+struct ScopedBuf {  // device scratch of one call, freed on every return path
+  DevBuf d;
+  ~ScopedBuf() { d.release(); }
+};
+}  // namespace
+
+extern "C" gc_status gc_tree_walk(gc_ctx c, int32_t n_nodes, const int32_t* node_range_dev, const double* node_com_dev,
+                                  const double* node_side_dev, const float* rec_dev, int32_t n_ids, int32_t n_buckets,
+                                  const int32_t* bucket_node_dev, double theta, int32_t* n_first_dev,
+                                  int32_t* r_first_dev, int32_t* node_idx_dev, int64_t node_cap, int32_t* ranges_dev,
+                                  int64_t range_cap, int64_t* totals, void* stream) {
+  if (!c) return GC_E_INVAL;
+  GC_ENTER(c);
+  if (!totals) return set_err(c, GC_E_INVAL, "gc_tree_walk: NULL totals");
+  totals[0] = totals[1] = 0;
+  if (n_nodes < 0 || n_buckets < 0 || n_ids < 0 || node_cap < 0 || range_cap < 0 || !(theta >= 0.0))
+    return set_err(c, GC_E_INVAL, "gc_tree_walk: negative size or theta");
+  if (n_buckets > 0 && (!n_first_dev || !r_first_dev || !bucket_node_dev))
+    return set_err(c, GC_E_INVAL, "gc_tree_walk: NULL bucket argument");
+  if (n_nodes > 0 && (!node_range_dev || !node_com_dev || !node_side_dev || (n_ids > 0 && !rec_dev)))
+    return set_err(c, GC_E_INVAL, "gc_tree_walk: NULL node argument");
+  hipStream_t s = S(stream);
+  if (n_buckets == 0) return GC_OK;
+  if (n_nodes == 0) {  // no tree: every bucket's lists are empty
+    GC_HIP(c, launch_fill_i32(n_first_dev, 0, (int64_t)n_buckets + 1, s));
+    GC_HIP(c, launch_fill_i32(r_first_dev, 0, (int64_t)n_buckets + 1, s));
+    return GC_OK;
+  }
+  ScopedBuf skip, tot;
+  if (skip.d.ensure(sizeof(int32_t) * (size_t)n_nodes) != hipSuccess || tot.d.ensure(256) != hipSuccess)
+    return set_err(c, GC_E_NOMEM, "gc_tree_walk: scratch");
+  long long* dtot = tot.d.as<long long>();  // totals[0..1], then the invalid-bucket count
+  GC_HIP(c, launch_fill_i32(tot.d.as<int32_t>(), 0, 6, s));
+  WalkArgs a{};
+  a.range = reinterpret_cast<const int2*>(node_range_dev);
+  a.com = node_com_dev;
+  a.side = node_side_dev;
+  a.skip = skip.d.as<int32_t>();
+  a.rec = reinterpret_cast<const float4*>(rec_dev);
+  a.bucket_node = bucket_node_dev;
+  a.n_nodes = n_nodes;
+  a.n_buckets = n_buckets;
+  a.n_ids = n_ids;
+  a.theta = theta;
+  a.n_first = n_first_dev;
+  a.r_first = r_first_dev;
+  a.node_idx = node_idx_dev;
+  a.ranges = ranges_dev;
+  a.bad = reinterpret_cast<unsigned long long*>(dtot + 2);
+  GC_HIP(c, launch_subtree_end(a.range, n_nodes, skip.d.as<int32_t>(), s));
+  GC_HIP(c, launch_walk(false, a, s));
+  GC_HIP(c, launch_scan_counts(n_first_dev, r_first_dev, n_buckets, dtot, s));
+  long long h[3] = {0, 0, 0};
+  GC_HIP(c, hipMemcpyAsync(h, dtot, sizeof h, hipMemcpyDeviceToHost, s));
+  GC_HIP(c, hipStreamSynchronize(s));
+  totals[0] = h[0];
+  totals[1] = h[1];
+  if (h[2] != 0) return set_err(c, GC_E_INVAL, "gc_tree_walk: %lld buckets with a leaf index or id range out of bounds", h[2]);
+  if (h[0] > INT32_MAX || h[1] > INT32_MAX)
+    return set_err(c, GC_E_UNSUPPORTED, "gc_tree_walk: %lld node entries / %lld ranges exceed int32 offsets", h[0], h[1]);
+  if (h[0] > node_cap || h[1] > range_cap || (h[0] > 0 && !node_idx_dev) || (h[1] > 0 && !ranges_dev))
+    return set_err(c, GC_E_FULL, "gc_tree_walk: need %lld node entries and %lld ranges (capacity %lld, %lld)", h[0],
+                   h[1], (long long)node_cap, (long long)range_cap);
+  GC_HIP(c, launch_walk(true, a, s));
+  GC_HIP(c, hipStreamSynchronize(s));  // the scratch is freed on return
+  return GC_OK;
 }

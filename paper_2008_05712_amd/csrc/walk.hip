@@ -1,0 +1,172 @@
+// Barnes-Hut interaction lists of the buckets' work requests (Sec. 4.1: a bucket's particles share
+// one node list and one direct list), built on the device.
+//
+// Opening test (FP64, no contraction, correctly rounded square root): bucket B takes node N when
+// theta > 0, N's id range does not overlap B's and side(N) < theta * dist(com(N), box(B)); box(B) is
+// the tight bounding box of B's FP32 positions and dist the distance from a point to the box, per
+// axis e = lo - c below, c - hi above, else 0, summed as (e_x^2 + e_y^2) + e_z^2.  A node that is not
+// taken goes, if a leaf, to the direct list as its id range and is otherwise opened.
+//
+// Nodes are numbered in pre-order with every node's ids contiguous, so a node's subtree is the
+// index range [k, skip[k]) and the walk is one forward pass over the indices: a taken node or a leaf
+// continues at skip[k], an opened node at k + 1.  Every step moves forward, so each lane ends within
+// n_nodes steps.  One lane per bucket; a count pass, a scan of the counts and a fill pass.
+#include "walk.h"
+
+#include "mem_dev.h"
+
+namespace gc {
+namespace {
+
+using dev::gld;
+
+// First node after k's subtree: the first later node whose id range starts at or after the end of
+// k's (first ids never decrease along a pre-order numbering with contiguous id ranges), else n.
+__global__ void __launch_bounds__(256) k_subtree_end(const int2* __restrict__ range, int32_t n,
+                                                     int32_t* __restrict__ skip) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int2 r = gld(range + k);
+  const int end = r.x + r.y;
+  int lo = k + 1, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (gld(range + mid).x >= end) hi = mid;
+    else lo = mid + 1;
+  }
+  skip[k] = lo;
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.n_buckets) return;
+  const int leaf = gld(a.bucket_node + b);
+  int2 br = make_int2(0, 0);
+  bool ok = leaf >= 0 && leaf < a.n_nodes;
+  if (ok) {
+    br = gld(a.range + leaf);
+    ok = br.x >= 0 && br.y >= 0 && br.x <= a.n_ids - br.y;
+  }
+  if (!ok) {  // an invalid bucket gets empty lists and is counted
+    if (!FILL) {
+      a.n_first[b] = 0;
+      a.r_first[b] = 0;
+      atomicAdd(a.bad, 1ull);
+    }
+    return;
+  }
+  double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
+  double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
+  for (int i = br.x; i < br.x + br.y; ++i) {
+    const float4 p = gld(a.rec + i);
+    const double v[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = v[d] < lo[d] ? v[d] : lo[d];
+      hi[d] = v[d] > hi[d] ? v[d] : hi[d];
+    }
+  }
+  int n_lim = 0, r_lim = 0, n_at = 0, r_at = 0;
+  if (FILL) {  // the fill pass never writes past the bucket's counted share
+    n_at = gld(a.n_first + b);
+    n_lim = gld(a.n_first + b + 1) - n_at;
+    r_at = gld(a.r_first + b);
+    r_lim = gld(a.r_first + b + 1) - r_at;
+  }
+  int cn = 0, cr = 0;
+  for (int k = 0; k < a.n_nodes;) {
+    const int2 nr = gld(a.range + k);
+    const bool disjoint = nr.x + nr.y <= br.x || br.x + br.y <= nr.x;
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double c = a.com[3 * (int64_t)k + d];
+      double e = 0.0;
+      if (c < lo[d]) e = __dsub_rn(lo[d], c);
+      else if (c > hi[d]) e = __dsub_rn(c, hi[d]);
+      s = __dadd_rn(s, __dmul_rn(e, e));
+    }
+    const int nxt = gld(a.skip + k);
+    if (a.theta > 0.0 && disjoint && a.side[k] < __dmul_rn(a.theta, __dsqrt_rn(s))) {
+      if (FILL && cn < n_lim) a.node_idx[n_at + cn] = k;
+      ++cn;
+      k = nxt;
+    } else if (nxt == k + 1) {
+      if (FILL && cr < r_lim) {
+        a.ranges[2 * (int64_t)(r_at + cr)] = nr.x;
+        a.ranges[2 * (int64_t)(r_at + cr) + 1] = nr.y;
+      }
+      ++cr;
+      k = nxt;
+    } else {
+      k = k + 1;
+    }
+  }
+  if (!FILL) {
+    a.n_first[b] = cn;
+    a.r_first[b] = cr;
+  }
+}
+
+// One workgroup of 1024 threads: each thread sums a contiguous chunk of both arrays, the chunk sums
+// are scanned in LDS, and each thread writes its chunk's exclusive prefixes.
+__global__ void __launch_bounds__(1024) k_scan_counts(int32_t* __restrict__ a, int32_t* __restrict__ b, int32_t n,
+                                                      long long* __restrict__ totals) {
+  __shared__ long long sa[1024], sb[1024];
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int i0 = t * chunk < n ? t * chunk : n, i1 = i0 + chunk < n ? i0 + chunk : n;
+  long long ta = 0, tb = 0;
+  for (int i = i0; i < i1; ++i) {
+    ta += a[i];
+    tb += b[i];
+  }
+  sa[t] = ta;
+  sb[t] = tb;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const long long ua = t >= d ? sa[t - d] : 0, ub = t >= d ? sb[t - d] : 0;
+    __syncthreads();
+    sa[t] += ua;
+    sb[t] += ub;
+    __syncthreads();
+  }
+  long long pa = sa[t] - ta, pb = sb[t] - tb;  // exclusive prefix of the chunk
+  for (int i = i0; i < i1; ++i) {
+    const int32_t va = a[i], vb = b[i];
+    a[i] = (int32_t)pa;
+    b[i] = (int32_t)pb;
+    pa += va;
+    pb += vb;
+  }
+  if (t == 1023) {
+    a[n] = (int32_t)sa[1023];
+    b[n] = (int32_t)sb[1023];
+    totals[0] = sa[1023];
+    totals[1] = sb[1023];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_subtree_end(const int2* range, int32_t n_nodes, int32_t* skip, hipStream_t s) {
+  if (n_nodes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_subtree_end, dim3((n_nodes + 255) / 256), dim3(256), 0, s, range, n_nodes, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk(bool fill, const WalkArgs& a, hipStream_t s) {
+  if (a.n_buckets <= 0) return hipSuccess;
+  const dim3 g((a.n_buckets + 255) / 256);
+  if (fill) hipLaunchKernelGGL(k_walk<true>, g, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_walk<false>, g, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_counts(int32_t* a, int32_t* b, int32_t n, long long* totals, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, a, b, n, totals);
+  return hipGetLastError();
+}
+
+}  // namespace gc

@@ -19,6 +19,7 @@ Prints one JSON line on stdout; diagnostics go to stderr.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -221,6 +222,32 @@ def leg_ewald(gc, W, torch, ctx):
     pool.destroy()
     return {"workload": f"uniform-{w.n} periodic unit box ({w.n_tasks} bucket tasks), nrep 1, |h|^2 <= 10",
             "ms": round(ms, 4), "targets_per_s_G": round(w.n / (ms * 1e-3) / 1e9, 3)}
+
+
+def leg_walk(gc, W, torch, ctx, w):
+    """Device Barnes-Hut list walk of every bucket of the step's workload (gc_tree_walk: count pass,
+    scan, fill; outputs already sized), wall time of the call, which waits for its own results."""
+    dev = torch.device("cuda")
+    args = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in
+            (w.node_range.astype(np.int32), w.node_mom64[:, :3], w.node_side, w.rec, w.meta["leaf"].astype(np.int32))]
+    nf, nidx, rf, rng = gc.tree_walk(ctx, *args, w.theta)  # sizes the outputs
+    nb = int(args[4].numel())
+    totals = (ctypes.c_int64 * 2)()
+    call = lambda: ctx.check(gc.lib().gc_tree_walk(
+        ctx.h, int(args[0].shape[0]), args[0].data_ptr(), args[1].data_ptr(), args[2].data_ptr(), args[3].data_ptr(),
+        int(args[3].shape[0]), nb, args[4].data_ptr(), float(w.theta), nf.data_ptr(), rf.data_ptr(), nidx.data_ptr(),
+        int(nidx.numel()), rng.data_ptr(), int(rng.shape[0]), totals, torch.cuda.current_stream().cuda_stream),
+        "gc_tree_walk")
+    for _ in range(3):
+        call()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    return {"workload": f"nbody-plummer-{w.n}: {nb} buckets, theta {w.theta}", "ms": round(ms, 4),
+            "node_entries": int(totals[0]), "direct_ranges": int(totals[1]),
+            "buckets_per_s_M": round(nb / (ms * 1e-3) / 1e6, 3)}
 
 
 def leg_adjoint(gc, W, torch, ctx):
@@ -596,6 +623,7 @@ def main():
         extra["lj"] = leg_lj(gc, W, torch, ctx)
         extra["ewald"] = leg_ewald(gc, W, torch, ctx)
         extra["adjoint"] = leg_adjoint(gc, W, torch, ctx)
+        extra["tree_walk"] = leg_walk(gc, W, torch, ctx, w)
 
     form_text = {"step": "one whole-step persistent launch (HIP graph) per step",
                  "rounds": "one HIP graph of per-round launches per step", "eager": "per-round launches"}[form]

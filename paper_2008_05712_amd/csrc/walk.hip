@@ -158,9 +158,10 @@ hipError_t launch_subtree_end(const int2* range, int32_t n_nodes, int32_t* skip,
 
 hipError_t launch_walk(bool fill, const WalkArgs& a, hipStream_t s) {
   if (a.n_buckets <= 0) return hipSuccess;
-  const dim3 g((a.n_buckets + 255) / 256);
-  if (fill) hipLaunchKernelGGL(k_walk<true>, g, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_walk<false>, g, dim3(256), 0, s, a);
+  // one wavefront per workgroup: tens of thousands of buckets then spread over every CU
+  const dim3 g((a.n_buckets + 63) / 64);
+  if (fill) hipLaunchKernelGGL(k_walk<true>, g, dim3(64), 0, s, a);
+  else hipLaunchKernelGGL(k_walk<false>, g, dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

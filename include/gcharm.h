@@ -356,7 +356,10 @@ gc_status gc_backward(gc_batch batch, const gc_force_params* prm, const float* n
  * node-entry and range totals.  GC_E_FULL when a capacity is short (offsets
  * and totals are then set, the lists not written: call again with room);
  * GC_E_INVAL for a bucket whose leaf index or id range is out of bounds.  The
- * call waits on `stream` (twice: for the totals and at the end).
+ * call waits on `stream` (twice: for the totals and at the end).  The context
+ * keeps room for up to 2,048 node entries and 128 ranges per bucket (9 KB per
+ * bucket of the largest call) until gc_finalize; a bucket with more is walked
+ * twice.
  */
 gc_status gc_tree_walk(gc_ctx ctx, int32_t n_nodes, const int32_t* node_range_dev, const double* node_com_dev,
                        const double* node_side_dev, const float* rec_dev, int32_t n_ids, int32_t n_buckets,

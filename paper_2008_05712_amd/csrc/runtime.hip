@@ -15,11 +15,41 @@
 
 using namespace gc;
 
+namespace {
+// Device buffer that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes && p) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    size_t b = want < 256 ? 256 : want;
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace
+
 struct gc_ctx_ {
   int device = 0;
   int n_cu = 0;
   bool poisoned = false;
   std::string err;
+  DevBuf walk_keep;  // the list walk's per-bucket room, kept between calls
 };
 
 namespace {
@@ -53,32 +83,6 @@ gc_status hip_fail(gc_ctx c, hipError_t e, const char* what) {
   } while (0)
 
 inline int64_t pad_to(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
-
-// Device buffer that only grows.
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  hipError_t ensure(size_t want) {
-    if (want <= bytes && p) return hipSuccess;
-    if (p) {
-      hipError_t e = hipFree(p);
-      p = nullptr;
-      bytes = 0;
-      if (e != hipSuccess) return e;
-    }
-    size_t b = want < 256 ? 256 : want;
-    hipError_t e = hipMalloc(&p, b);
-    if (e == hipSuccess) bytes = b;
-    return e;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  template <class T>
-  T* as() const { return static_cast<T*>(p); }
-};
 
 hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 
@@ -163,6 +167,7 @@ extern "C" gc_status gc_init(int device, gc_ctx* out) {
 
 extern "C" gc_status gc_finalize(gc_ctx ctx) {
   if (!ctx) return GC_E_INVAL;
+  ctx->walk_keep.release();
   delete ctx;
   return GC_OK;
 }
@@ -1584,6 +1589,12 @@ extern "C" gc_status gc_tree_walk(gc_ctx c, int32_t n_nodes, const int32_t* node
   ScopedBuf skip, tot;
   if (skip.d.ensure(sizeof(int32_t) * (size_t)n_nodes) != hipSuccess || tot.d.ensure(256) != hipSuccess)
     return set_err(c, GC_E_NOMEM, "gc_tree_walk: scratch");
+  // room for each bucket's lists in the count pass, kept by the context (without it every bucket is
+  // walked twice)
+  DevBuf& keep = c->walk_keep;
+  const size_t keep_n = sizeof(int32_t) * kWalkCapNodes * (size_t)n_buckets;
+  const bool kept = keep.ensure(keep_n + sizeof(int2) * kWalkCapRanges * (size_t)n_buckets) == hipSuccess;
+  if (!kept) (void)hipGetLastError();
   long long* dtot = tot.d.as<long long>();  // totals[0..1], then the invalid-bucket count
   GC_HIP(c, launch_fill_i32(tot.d.as<int32_t>(), 0, 6, s));
   WalkArgs a{};
@@ -1602,6 +1613,8 @@ extern "C" gc_status gc_tree_walk(gc_ctx c, int32_t n_nodes, const int32_t* node
   a.node_idx = node_idx_dev;
   a.ranges = ranges_dev;
   a.bad = reinterpret_cast<unsigned long long*>(dtot + 2);
+  a.sn = kept ? keep.as<int32_t>() : nullptr;
+  a.sr = kept ? reinterpret_cast<int2*>(keep.as<char>() + keep_n) : nullptr;
   GC_HIP(c, launch_subtree_end(a.range, n_nodes, skip.d.as<int32_t>(), s));
   GC_HIP(c, launch_walk(false, a, s));
   GC_HIP(c, launch_scan_counts(n_first_dev, r_first_dev, n_buckets, dtot, s));
@@ -1616,6 +1629,7 @@ extern "C" gc_status gc_tree_walk(gc_ctx c, int32_t n_nodes, const int32_t* node
   if (h[0] > node_cap || h[1] > range_cap || (h[0] > 0 && !node_idx_dev) || (h[1] > 0 && !ranges_dev))
     return set_err(c, GC_E_FULL, "gc_tree_walk: need %lld node entries and %lld ranges (capacity %lld, %lld)", h[0],
                    h[1], (long long)node_cap, (long long)range_cap);
+  GC_HIP(c, launch_walk_copy(a, s));
   GC_HIP(c, launch_walk(true, a, s));
   GC_HIP(c, hipStreamSynchronize(s));  // the scratch is freed on return
   return GC_OK;

@@ -22,10 +22,17 @@ struct WalkArgs {
   int32_t* node_idx;          // fill pass outputs
   int32_t* ranges;            // (first, count) pairs
   unsigned long long* bad;    // count of buckets whose leaf index or id range is invalid
+  int32_t* sn;                // count pass: each bucket's first kWalkCapNodes node entries (or nullptr)
+  int2* sr;                   // and first kWalkCapRanges ranges
 };
+// Per-bucket room of the count pass's copy of the lists; a bucket with more is walked again.
+constexpr int kWalkCapNodes = 2048;
+constexpr int kWalkCapRanges = 128;
 
 hipError_t launch_subtree_end(const int2* range, int32_t n_nodes, int32_t* skip, hipStream_t s);
 hipError_t launch_walk(bool fill, const WalkArgs& a, hipStream_t s);
+// After the scan: the lists of every bucket that fit the count pass's room, copied to their offsets.
+hipError_t launch_walk_copy(const WalkArgs& a, hipStream_t s);
 // In-place exclusive scan of two count arrays of n entries (entry n receives the total); the two
 // totals, as 64-bit sums, go to totals[0] and totals[1].
 hipError_t launch_scan_counts(int32_t* a, int32_t* b, int32_t n, long long* totals, hipStream_t s);

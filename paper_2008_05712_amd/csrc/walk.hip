@@ -10,7 +10,9 @@
 // Nodes are numbered in pre-order with every node's ids contiguous, so a node's subtree is the
 // index range [k, skip[k]) and the walk is one forward pass over the indices: a taken node or a leaf
 // continues at skip[k], an opened node at k + 1.  Every step moves forward, so each lane ends within
-// n_nodes steps.  One lane per bucket; a count pass, a scan of the counts and a fill pass.
+// n_nodes steps.  One lane per bucket.  The count pass also keeps each bucket's lists, up to a fixed
+// room; after the scan of the counts they are copied to their offsets, and only a bucket that did
+// not fit is walked again.
 #include "walk.h"
 
 #include "mem_dev.h"
@@ -73,7 +75,10 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     n_lim = gld(a.n_first + b + 1) - n_at;
     r_at = gld(a.r_first + b);
     r_lim = gld(a.r_first + b + 1) - r_at;
+    if (a.sn && n_lim <= kWalkCapNodes && r_lim <= kWalkCapRanges) return;  // copied from the count pass
   }
+  int32_t* keep_n = (!FILL && a.sn) ? a.sn + (int64_t)kWalkCapNodes * b : nullptr;
+  int2* keep_r = (!FILL && a.sn) ? a.sr + (int64_t)kWalkCapRanges * b : nullptr;
   int cn = 0, cr = 0;
   for (int k = 0; k < a.n_nodes;) {
     const int2 nr = gld(a.range + k);
@@ -90,6 +95,7 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     const int nxt = gld(a.skip + k);
     if (a.theta > 0.0 && disjoint && a.side[k] < __dmul_rn(a.theta, __dsqrt_rn(s))) {
       if (FILL && cn < n_lim) a.node_idx[n_at + cn] = k;
+      if (!FILL && keep_n && cn < kWalkCapNodes) keep_n[cn] = k;
       ++cn;
       k = nxt;
     } else if (nxt == k + 1) {
@@ -97,6 +103,7 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
         a.ranges[2 * (int64_t)(r_at + cr)] = nr.x;
         a.ranges[2 * (int64_t)(r_at + cr) + 1] = nr.y;
       }
+      if (!FILL && keep_r && cr < kWalkCapRanges) keep_r[cr] = nr;
       ++cr;
       k = nxt;
     } else {
@@ -106,6 +113,25 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
   if (!FILL) {
     a.n_first[b] = cn;
     a.r_first[b] = cr;
+  }
+}
+
+// One wavefront per bucket: a bucket whose lists fit the count pass's room has them copied to its
+// offsets (lanes over entries).
+__global__ void __launch_bounds__(256) k_walk_copy(WalkArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (b >= a.n_buckets) return;
+  const int n_at = gld(a.n_first + b), n_cnt = gld(a.n_first + b + 1) - n_at;
+  const int r_at = gld(a.r_first + b), r_cnt = gld(a.r_first + b + 1) - r_at;
+  if (n_cnt > kWalkCapNodes || r_cnt > kWalkCapRanges) return;  // walked again by the fill pass
+  const int32_t* src_n = a.sn + (int64_t)kWalkCapNodes * b;
+  for (int i = lane; i < n_cnt; i += 64) a.node_idx[n_at + i] = gld(src_n + i);
+  const int2* src_r = a.sr + (int64_t)kWalkCapRanges * b;
+  for (int i = lane; i < r_cnt; i += 64) {
+    const int2 v = gld(src_r + i);
+    a.ranges[2 * (int64_t)(r_at + i)] = v.x;
+    a.ranges[2 * (int64_t)(r_at + i) + 1] = v.y;
   }
 }
 
@@ -162,6 +188,12 @@ hipError_t launch_walk(bool fill, const WalkArgs& a, hipStream_t s) {
   const dim3 g((a.n_buckets + 63) / 64);
   if (fill) hipLaunchKernelGGL(k_walk<true>, g, dim3(64), 0, s, a);
   else hipLaunchKernelGGL(k_walk<false>, g, dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_copy(const WalkArgs& a, hipStream_t s) {
+  if (a.n_buckets <= 0 || !a.sn) return hipSuccess;
+  hipLaunchKernelGGL(k_walk_copy, dim3((a.n_buckets + 3) / 4), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -135,42 +135,54 @@ __global__ void __launch_bounds__(256) k_walk_copy(WalkArgs a) {
   }
 }
 
-// One workgroup of 1024 threads: each thread sums a contiguous chunk of both arrays, the chunk sums
-// are scanned in LDS, and each thread writes its chunk's exclusive prefixes.
+// One workgroup of 1024 threads over tiles of 4096 entries of both arrays: each thread takes four
+// consecutive entries, the threads' sums are scanned in LDS, and a carry runs from tile to tile.
 __global__ void __launch_bounds__(1024) k_scan_counts(int32_t* __restrict__ a, int32_t* __restrict__ b, int32_t n,
                                                       long long* __restrict__ totals) {
   __shared__ long long sa[1024], sb[1024];
   const int t = threadIdx.x;
-  const int chunk = (n + 1023) / 1024;
-  const int i0 = t * chunk < n ? t * chunk : n, i1 = i0 + chunk < n ? i0 + chunk : n;
-  long long ta = 0, tb = 0;
-  for (int i = i0; i < i1; ++i) {
-    ta += a[i];
-    tb += b[i];
-  }
-  sa[t] = ta;
-  sb[t] = tb;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const long long ua = t >= d ? sa[t - d] : 0, ub = t >= d ? sb[t - d] : 0;
+  long long carry_a = 0, carry_b = 0;
+  for (int base = 0; base < n; base += 4096) {
+    int va[4], vb[4];
+    long long ta = 0, tb = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = base + 4 * t + q;
+      va[q] = i < n ? a[i] : 0;
+      vb[q] = i < n ? b[i] : 0;
+      ta += va[q];
+      tb += vb[q];
+    }
+    sa[t] = ta;
+    sb[t] = tb;
     __syncthreads();
-    sa[t] += ua;
-    sb[t] += ub;
-    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const long long ua = t >= d ? sa[t - d] : 0, ub = t >= d ? sb[t - d] : 0;
+      __syncthreads();
+      sa[t] += ua;
+      sb[t] += ub;
+      __syncthreads();
+    }
+    long long pa = carry_a + sa[t] - ta, pb = carry_b + sb[t] - tb;  // exclusive prefix of the thread's entries
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = base + 4 * t + q;
+      if (i < n) {
+        a[i] = (int32_t)pa;
+        b[i] = (int32_t)pb;
+      }
+      pa += va[q];
+      pb += vb[q];
+    }
+    carry_a += sa[1023];
+    carry_b += sb[1023];
+    __syncthreads();  // sa / sb are rewritten by the next tile
   }
-  long long pa = sa[t] - ta, pb = sb[t] - tb;  // exclusive prefix of the chunk
-  for (int i = i0; i < i1; ++i) {
-    const int32_t va = a[i], vb = b[i];
-    a[i] = (int32_t)pa;
-    b[i] = (int32_t)pb;
-    pa += va;
-    pb += vb;
-  }
-  if (t == 1023) {
-    a[n] = (int32_t)sa[1023];
-    b[n] = (int32_t)sb[1023];
-    totals[0] = sa[1023];
-    totals[1] = sb[1023];
+  if (t == 0) {
+    a[n] = (int32_t)carry_a;
+    b[n] = (int32_t)carry_b;
+    totals[0] = carry_a;
+    totals[1] = carry_b;
   }
 }
 

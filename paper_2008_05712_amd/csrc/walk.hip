@@ -39,6 +39,32 @@ __global__ void __launch_bounds__(256) k_subtree_end(const int2* __restrict__ ra
   skip[k] = lo;
 }
 
+struct WalkNode {
+  int2 range;
+  double com[3];
+  double side;
+  int skip;
+};
+
+// Node k's walk data; past the last node, a record that is never used (the walk stops there).
+__device__ __forceinline__ WalkNode load_node(const WalkArgs& a, int k) {
+  WalkNode w;
+  if (k < a.n_nodes) {
+    w.range = gld(a.range + k);
+    w.com[0] = a.com[3 * (int64_t)k];
+    w.com[1] = a.com[3 * (int64_t)k + 1];
+    w.com[2] = a.com[3 * (int64_t)k + 2];
+    w.side = a.side[k];
+    w.skip = gld(a.skip + k);
+  } else {
+    w.range = make_int2(0, 0);
+    w.com[0] = w.com[1] = w.com[2] = 0.0;
+    w.side = 0.0;
+    w.skip = k + 1;
+  }
+  return w;
+}
+
 template <bool FILL>
 __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,24 +106,29 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
   int32_t* keep_n = (!FILL && a.sn) ? a.sn + (int64_t)kWalkCapNodes * b : nullptr;
   int2* keep_r = (!FILL && a.sn) ? a.sr + (int64_t)kWalkCapRanges * b : nullptr;
   int cn = 0, cr = 0;
+  // both possible successors (k + 1 when k is opened, the end of k's subtree otherwise) are loaded at
+  // the top of each step, so their latency overlaps the opening test of k
+  WalkNode cur = load_node(a, 0);
   for (int k = 0; k < a.n_nodes;) {
-    const int2 nr = gld(a.range + k);
+    const int nxt = cur.skip;
+    const WalkNode on_open = load_node(a, k + 1), on_skip = load_node(a, nxt);
+    const int2 nr = cur.range;
     const bool disjoint = nr.x + nr.y <= br.x || br.x + br.y <= nr.x;
     double s = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double c = a.com[3 * (int64_t)k + d];
+      const double c = cur.com[d];
       double e = 0.0;
       if (c < lo[d]) e = __dsub_rn(lo[d], c);
       else if (c > hi[d]) e = __dsub_rn(c, hi[d]);
       s = __dadd_rn(s, __dmul_rn(e, e));
     }
-    const int nxt = gld(a.skip + k);
-    if (a.theta > 0.0 && disjoint && a.side[k] < __dmul_rn(a.theta, __dsqrt_rn(s))) {
+    if (a.theta > 0.0 && disjoint && cur.side < __dmul_rn(a.theta, __dsqrt_rn(s))) {
       if (FILL && cn < n_lim) a.node_idx[n_at + cn] = k;
       if (!FILL && keep_n && cn < kWalkCapNodes) keep_n[cn] = k;
       ++cn;
       k = nxt;
+      cur = on_skip;
     } else if (nxt == k + 1) {
       if (FILL && cr < r_lim) {
         a.ranges[2 * (int64_t)(r_at + cr)] = nr.x;
@@ -106,8 +137,10 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
       if (!FILL && keep_r && cr < kWalkCapRanges) keep_r[cr] = nr;
       ++cr;
       k = nxt;
+      cur = on_skip;
     } else {
       k = k + 1;
+      cur = on_open;
     }
   }
   if (!FILL) {

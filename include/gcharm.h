@@ -60,7 +60,10 @@ typedef struct gc_graph_* gc_graph;
 
 /* ---------------------------------------------------------------- context */
 
-/* Open a context on HIP device `device` (makes it current for the calling thread). */
+/* Open a context on HIP device `device` (makes it current for the calling thread).
+ * A context and everything made from it are used from one host thread at a
+ * time: calls on one context must not overlap (the context holds the last
+ * error and the list walk's scratch). */
 gc_status gc_init(int device, gc_ctx* out);
 /* Release everything the context owns (pools and batches must be destroyed first or are leaked). */
 gc_status gc_finalize(gc_ctx ctx);

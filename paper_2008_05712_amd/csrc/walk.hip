@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
   int32_t* keep_n = (!FILL && a.sn) ? a.sn + (int64_t)kWalkCapNodes * b : nullptr;
   int2* keep_r = (!FILL && a.sn) ? a.sr + (int64_t)kWalkCapRanges * b : nullptr;
   int cn = 0, cr = 0;
+  int kb0 = 0, kb1 = 0, kb2 = 0;  // node entries not yet kept (the last cn % 4)
   // both possible successors (k + 1 when k is opened, the end of k's subtree otherwise) are loaded at
   // the top of each step, so their latency overlaps the opening test of k
   WalkNode cur = load_node(a, 0);
@@ -125,7 +126,13 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
     }
     if (a.theta > 0.0 && disjoint && cur.side < __dmul_rn(a.theta, __dsqrt_rn(s))) {
       if (FILL && cn < n_lim) a.node_idx[n_at + cn] = k;
-      if (!FILL && keep_n && cn < kWalkCapNodes) keep_n[cn] = k;
+      if (!FILL && keep_n) {  // kept four at a time: one aligned 16-byte store per four entries
+        const int slot = cn & 3;
+        kb0 = slot == 0 ? k : kb0;
+        kb1 = slot == 1 ? k : kb1;
+        kb2 = slot == 2 ? k : kb2;
+        if (slot == 3 && cn < kWalkCapNodes) *reinterpret_cast<int4*>(keep_n + (cn - 3)) = make_int4(kb0, kb1, kb2, k);
+      }
       ++cn;
       k = nxt;
       cur = on_skip;
@@ -142,6 +149,12 @@ __global__ void __launch_bounds__(256) k_walk(WalkArgs a) {
       k = k + 1;
       cur = on_open;
     }
+  }
+  if (!FILL && keep_n) {  // the last cn % 4 entries
+    const int tail = cn & 3, at = cn - tail;
+    if (tail > 0 && at < kWalkCapNodes) keep_n[at] = kb0;
+    if (tail > 1 && at + 1 < kWalkCapNodes) keep_n[at + 1] = kb1;
+    if (tail > 2 && at + 2 < kWalkCapNodes) keep_n[at + 2] = kb2;
   }
   if (!FILL) {
     a.n_first[b] = cn;

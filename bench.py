@@ -36,7 +36,20 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6
 N_SIMD, CLOCK_GHZ = 256 * 4, 2.4   # MI355X: 256 CUs x 4 SIMDs at 2.4 GHz
 LJ_VALU_PER_EVAL = 20.5            # Lennard-Jones gather loop: 41 VALU instructions per two pair evaluations
 PEAK_HBM_GBPS = 8000.0
-FLOPS_PAIR, FLOPS_QUAD = 19, 51   # per interaction, from the implemented formulas
+# launch shapes (tile, targets per lane) of the whole-step form that the bench may time; the GPU tests
+# check every one of them against the per-round launches and the oracle
+STEP_SHAPES = ((256, 1), (256, 2), (320, 1), (320, 2), (384, 1), (384, 2))
+
+
+def flop_counts() -> dict:
+    """Algorithmic flop per interaction, read from the library's header (one place for the counts)."""
+    import re
+    txt = open(os.path.join(ROOT, "paper_2008_05712_amd", "csrc", "gc_internal.h")).read()
+    return {k: int(v) for k, v in re.findall(r"constexpr int (kFlops\w+) = (\d+);", txt)}
+
+
+_FLOPS = flop_counts()
+FLOPS_PAIR, FLOPS_QUAD, FLOPS_LJ = _FLOPS["kFlopsPair"], _FLOPS["kFlopsQuad"], _FLOPS["kFlopsLJ"]
 # algorithmic bytes of one reorganisation: per union entry the id, its slot_of entry, its slot out,
 # the record read and the packed write; per missing record the pool write, the slot_of and occupancy
 # updates and the missing list (id and slot); per pool slot the occupancy read of the free-slot scan
@@ -488,18 +501,22 @@ def main():
     forms["round_graph_ms"] = round(time_kernel(lambda: round_graph.launch(stream=stream), stream, reps=10), 4)
     sprm, step_graph, step_shapes, best_ms = None, None, {}, None
     if mode == gc.REORG_PACK:
-        for tl in ((args.step_tile,) if args.step_tile else (256, 320, 384)):
-            for tp in ((args.step_tpl,) if args.step_tpl else (1, 2)):
-                p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=gc.SCHED_STEP, tile=tl, targets_per_lane=tp)
-                g = capture("step", p)
-                ms = round(time_kernel(lambda: g.launch(stream=stream), stream, reps=10), 4)
-                step_shapes[f"tile{tl}_tpl{tp}"] = ms
-                if best_ms is None or ms < best_ms:
-                    if step_graph is not None:
-                        step_graph.destroy()
-                    sprm, step_graph, best_ms = p, g, ms
-                else:
-                    g.destroy()
+        shapes = [sh for sh in STEP_SHAPES if (not args.step_tile or sh[0] == args.step_tile) and
+                  (not args.step_tpl or sh[1] == args.step_tpl)]
+        if not shapes:
+            log(f"[bench] --step-tile {args.step_tile} --step-tpl {args.step_tpl}: not a tested shape {STEP_SHAPES}")
+            sys.exit(2)
+        for tl, tp in shapes:
+            p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=gc.SCHED_STEP, tile=tl, targets_per_lane=tp)
+            g = capture("step", p)
+            ms = round(time_kernel(lambda: g.launch(stream=stream), stream, reps=10), 4)
+            step_shapes[f"tile{tl}_tpl{tp}"] = ms
+            if best_ms is None or ms < best_ms:
+                if step_graph is not None:
+                    step_graph.destroy()
+                sprm, step_graph, best_ms = p, g, ms
+            else:
+                g.destroy()
         forms["step_graph_ms_by_shape"] = step_shapes
     log(f"[bench] forms: {forms}")
     form = args.form if (args.form != "step" or step_graph is not None) else "rounds"
@@ -514,14 +531,32 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # HIP events on the launch stream bracket every step inside the timed region: the device time of
+    # each step's launch (for the whole-step form, the eviction kernel and the k_step launch)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t1 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        evs[k][0].record(stream)
         step()
+        evs[k][1].record(stream)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ms_step = (t2 - t1) * 1e3 / args.steps
+    launch_ms = [a.elapsed_time(b) for a, b in evs]
+    avg_launch_ms = float(np.mean(launch_ms))
     value = interactions / (ms_step * 1e-3) / 1e9
-    log(f"[bench] step {ms_step:.4f} ms  {value:.1f} G-interactions/s ({form})")
+    log(f"[bench] step {ms_step:.4f} ms  {value:.1f} G-interactions/s ({form}); launch {avg_launch_ms:.4f} ms "
+        f"(min {min(launch_ms):.4f}, max {max(launch_ms):.4f})")
+    # the device-side error words of every batch the timed launches used: a bounded wait that gave up
+    # would have left unspecified accelerations in the timed region
+    try:
+        if graph is not None:
+            graph.status(stream=stream)
+        for b in batches:
+            b.status(stream=stream)
+    except gc.GcError as e:
+        log(f"[bench] FAILED: {e}")
+        sys.exit(3)
     # the eager form's step time, for comparison
     torch.cuda.synchronize()
     te = time.perf_counter()
@@ -542,7 +577,7 @@ def main():
     pool.evict_staged(batches[-1])
     forms["timed_vs_eager_indirect"] = round(forms["eager_indirect_ms"] / ms_step, 3)
     if graph is not None and form == "step":
-        step_kernel_ms = time_kernel(lambda: graph.launch(stream=stream), stream, reps=10)
+        step_kernel_ms = avg_launch_ms
     # the same whole-step launch with the source records in pinned host memory: the staging of the
     # missing records reads them across PCIe (the boundary's host-buffer path; never the bench value)
     if not args.quick and sprm is not None:

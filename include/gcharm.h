@@ -60,17 +60,39 @@ typedef struct gc_graph_* gc_graph;
 
 /* ---------------------------------------------------------------- context */
 
+/*
+ * The caller's device allocator.  alloc_fn returns `bytes` of device memory of
+ * device `device` (aligned to at least 256 bytes) or NULL; free_fn takes back a
+ * pointer alloc_fn returned.  Both receive the `user` pointer given to gc_init.
+ * They are called from the host thread that makes the library call (never
+ * during graph capture), and free_fn only after the device is idle, so a
+ * stream-ordered caching allocator (torch's) may reuse the memory at once.
+ */
+typedef void* (*gc_alloc_fn)(size_t bytes, void* user);
+typedef void (*gc_free_fn)(void* ptr, void* user);
+
 /* Open a context on HIP device `device` (makes it current for the calling thread).
+ * Every device buffer the library owns (pool records and chare table, batch
+ * buffers, graph and list-walk scratch) is taken from alloc_fn / free_fn;
+ * both NULL: hipMalloc / hipFree (one NULL and not the other: GC_E_INVAL).
  * A context and everything made from it are used from one host thread at a
  * time: calls on one context must not overlap (the context holds the last
  * error and the list walk's scratch). */
-gc_status gc_init(int device, gc_ctx* out);
+gc_status gc_init(int device, gc_alloc_fn alloc_fn, gc_free_fn free_fn, void* user, gc_ctx* out);
 /* Release everything the context owns (pools and batches must be destroyed first or are leaked). */
 gc_status gc_finalize(gc_ctx ctx);
 /* Last error message of the context ("" if none). Owned by the context. */
 const char* gc_last_error(gc_ctx ctx);
 /* Library version string, static. */
 const char* gc_version(void);
+
+/*
+ * Test hook: the next call on `ctx` that reaches the device-error check
+ * behaves as if an asynchronous device error with HIP code `hip_error` (!= 0)
+ * had surfaced: it returns GC_E_HIP and poisons the context.  Host state only;
+ * nothing is sent to the device.
+ */
+gc_status gc_debug_inject_error(gc_ctx ctx, int hip_error);
 
 /* ---------------------------------------------------------------- pool (chare table) */
 
@@ -171,8 +193,11 @@ gc_status gc_batch_reset(gc_batch batch);
  * (begin, count) pairs; node_idx holds n_node_refs node indices; tasks index
  * into these arrays relative to this call.  Validation (host side, strong
  * guarantee: on error nothing is appended): ids and ranges inside [0, n_ids),
- * counts >= 0, list slices inside the given arrays, node indices >= 0,
- * Lennard-Jones tasks with exactly one j range and no nodes.
+ * counts >= 0, list slices inside the given arrays, node indices >= 0 (and
+ * below the node table's size, checked where the table is given),
+ * no two nonempty direct ranges of one task overlapping (a source listed
+ * twice would be summed twice), Lennard-Jones tasks with exactly one j range
+ * and no nodes.
  */
 gc_status gc_submit_tasks(gc_batch batch, const gc_task* tasks, int32_t n_tasks, const int32_t* j_ranges,
                           int32_t n_ranges, const int32_t* node_idx, int32_t n_node_refs);
@@ -190,6 +215,18 @@ gc_status gc_batch_commit(gc_batch batch, void* stream);
 
 /* Number of tasks, ranges, node refs, direct entries (sum of range counts) and targets. */
 gc_status gc_batch_sizes(gc_batch batch, int64_t* out5);
+
+/*
+ * Device-side error words of a batch, read after waiting on `stream`:
+ * GC_E_HIP if a bounded wait of one of its reorganisations (per-batch or
+ * whole-step) gave up since the reorganisation state was last cleared (at
+ * the first reorganisation after a commit, and at graph capture): its maps
+ * and the forces of the pass that read them are then unspecified;
+ * GC_E_INVAL if a backward call met node ranges outside [0, n_ids) (those
+ * nodes' gradients were not pushed to members; sticky until the next
+ * commit); else GC_OK.  The context is not poisoned.
+ */
+gc_status gc_batch_status(gc_batch batch, void* stream);
 
 /*
  * Reorganisation (Sec. 3.2) of a committed batch against a pool, on `stream`:
@@ -287,6 +324,13 @@ typedef struct {
   int32_t targets_per_lane; /* gravity: 0 or 1 = one target per lane; 2 = each lane
                                holds two targets of its task, so every record read
                                from LDS serves two interactions (same results) */
+  int32_t n_nodes;          /* gravity: node records in nodes_dev; every node index the
+                               batch holds must be below it (GC_E_INVAL otherwise) */
+  int32_t want_potential;   /* 1: also write the potential in acc.w (gravity: phi_i of
+                               the lists' terms; Lennard-Jones: half the pair energies
+                               of the atom's pairs, shifted at the cutoff: see below) */
+  int32_t deterministic;    /* 1: results must be the same bits on every call; a path
+                               that sums with atomics then returns GC_E_UNSUPPORTED */
 } gc_force_params;
 
 /*
@@ -402,6 +446,27 @@ gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* batches, gc_po
                            const int32_t* place_n, void* stream, gc_graph* out);
 gc_status gc_graph_launch(gc_graph graph, void* stream);
 gc_status gc_graph_destroy(gc_graph graph);
+
+/*
+ * Waits on `stream`, then reads the error words of every batch the graph
+ * reorganises: GC_E_HIP if a bounded wait of a reorganisation, or of the
+ * whole-step schedule's dependencies, gave up in any launch since capture
+ * (the results of those launches are unspecified), else GC_OK.  The words
+ * are sticky until the next capture; the context is not poisoned.
+ */
+gc_status gc_graph_status(gc_graph graph, void* stream);
+
+/*
+ * Test hook for the whole-step schedule, taken by every later gc_graph_capture
+ * on `ctx` until changed: with fail_round >= 0 the combined-pass items of that
+ * step wait for one more finished reorganisation part than the step has, so
+ * their waits give up after fail_spins probes (0: the default bound, about a
+ * second); fail_round < 0 turns the hook off.  Other waits keep their bound.
+ * Every wave still ends normally and reads only buffers of its step; the
+ * launch reports through gc_graph_status, and that step's accelerations are
+ * unspecified.
+ */
+gc_status gc_debug_step_waits(gc_ctx ctx, uint32_t fail_spins, int32_t fail_round);
 
 /* ---------------------------------------------------------------- tuning and introspection */
 

@@ -35,7 +35,8 @@ SCHED_TASKS, SCHED_QUEUE, SCHED_STEP = 0, 1, 2
 TASK_DTYPE = np.dtype([("i_begin", "<i4"), ("i_count", "<i4"), ("j_first", "<i4"), ("j_nranges", "<i4"),
                        ("n_first", "<i4"), ("n_count", "<i4"), ("flags", "<i4"), ("shift", "<f4", (3,))])
 
-EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_pool_create", "gc_pool_destroy",
+EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_debug_inject_error", "gc_debug_step_waits",
+            "gc_batch_status", "gc_graph_status", "gc_pool_create", "gc_pool_destroy",
             "gc_pool_set_source", "gc_pool_place", "gc_pool_reset", "gc_pool_evict", "gc_pool_evict_staged",
             "gc_pool_query", "gc_pool_device_ptrs",
             "gc_batch_create", "gc_batch_destroy", "gc_batch_reset", "gc_submit_tasks", "gc_batch_commit",
@@ -72,7 +73,8 @@ class ForceParams(ctypes.Structure):
                 ("n_types", ctypes.c_int32), ("eps_t", ctypes.c_void_p), ("sig_t", ctypes.c_void_p),
                 ("mass_t", ctypes.c_void_p), ("r_cut", ctypes.c_float), ("schedule", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("targets_per_lane", ctypes.c_int32)]
+                ("targets_per_lane", ctypes.c_int32), ("n_nodes", ctypes.c_int32), ("want_potential", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,7 +103,11 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     sig = {
         "gc_version": (ctypes.c_char_p, []),
-        "gc_init": (I32, [ctypes.c_int, ctypes.POINTER(VP)]),
+        "gc_init": (I32, [ctypes.c_int, VP, VP, VP, ctypes.POINTER(VP)]),
+        "gc_debug_inject_error": (I32, [VP, ctypes.c_int]),
+        "gc_debug_step_waits": (I32, [VP, ctypes.c_uint32, I32]),
+        "gc_batch_status": (I32, [VP, VP]),
+        "gc_graph_status": (I32, [VP, VP]),
         "gc_finalize": (I32, [VP]),
         "gc_last_error": (ctypes.c_char_p, [VP]),
         "gc_pool_create": (I32, [VP, I32, I32, ctypes.POINTER(VP)]),
@@ -178,14 +184,53 @@ def _stream(s) -> int | None:
     return s.cuda_stream
 
 
-class Context:
-    """One device context (gc_init / gc_finalize)."""
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
-    def __init__(self, device: int = 0):
+
+def torch_allocator(device: int = 0):
+    """(alloc, free) hooks over torch's caching allocator (memory on the current stream of `device`)."""
+    import torch
+
+    def alloc(nbytes, _user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        except Exception:  # noqa: BLE001 - out of memory: the library reports GC_E_NOMEM
+            return None
+
+    def free(ptr, _user):
+        torch.cuda.caching_allocator_delete(ptr)
+    return alloc, free
+
+
+class Context:
+    """One device context (gc_init / gc_finalize).
+
+    allocator: None (the library's hipMalloc / hipFree), "torch" (torch's caching allocator), or a pair
+    of Python callables (alloc(nbytes, user) -> int address or None, free(address, user)).
+    """
+
+    def __init__(self, device: int = 0, allocator=None):
         self.h = VP()
-        st = lib().gc_init(device, ctypes.byref(self.h))
+        self._hooks = None
+        a = f = None
+        if allocator is not None:
+            pa, pf = torch_allocator(device) if allocator == "torch" else allocator
+            self._hooks = (ALLOC_FN(pa), FREE_FN(pf))  # kept alive as long as the context
+            a, f = ctypes.cast(self._hooks[0], VP), ctypes.cast(self._hooks[1], VP)
+        st = lib().gc_init(device, a, f, None, ctypes.byref(self.h))
         if st != GC_OK:
             raise GcError(st, f"gc_init({device}) failed")
+
+    def inject_error(self, hip_error: int = 1):
+        """Test hook: the next call reports an asynchronous device error (gc_debug_inject_error)."""
+        st = lib().gc_debug_inject_error(self.h, int(hip_error))
+        if st != GC_OK:
+            raise GcError(st, "gc_debug_inject_error")
+
+    def step_waits(self, fail_spins: int = 0, fail_round: int = -1):
+        """Test hook for later whole-step captures (gc_debug_step_waits); fail_round -1 turns it off."""
+        self.check(lib().gc_debug_step_waits(self.h, int(fail_spins), int(fail_round)), "gc_debug_step_waits")
 
     def check(self, st: int, what: str = ""):
         if st != GC_OK:
@@ -426,8 +471,13 @@ class Batch:
                     pi_begin=pib[:sz["tasks"]], ilist=il[:sz["targets"]], jlist=jl[:sz["direct"]])
 
     def launch(self, prm: ForceParams, nodes, acc, stream=None):
-        self.ctx.check(lib().gc_launch_combined(self.h, ctypes.byref(prm), _ptr(nodes), _ptr(acc), _stream(stream)),
+        p = with_nodes(prm, nodes)
+        self.ctx.check(lib().gc_launch_combined(self.h, ctypes.byref(p), _ptr(nodes), _ptr(acc), _stream(stream)),
                        "gc_launch_combined")
+
+    def status(self, stream=None):
+        """Raises GcError if a device-side wait gave up or a backward met bad node ranges (gc_batch_status)."""
+        self.ctx.check(lib().gc_batch_status(self.h, _stream(stream)), "gc_batch_status")
 
     def ewald(self, prm: "EwaldParams", acc, stream=None):
         """acc += the Ewald correction at every target of the batch (gc_launch_ewald)."""
@@ -435,6 +485,7 @@ class Batch:
 
     def backward(self, prm: ForceParams, nodes, node_range, n_nodes: int, cot, gpos, gmass, gparam=None,
                  stream=None):
+        prm = with_nodes(prm, nodes)
         self.ctx.check(lib().gc_backward(self.h, ctypes.byref(prm), _ptr(nodes), _ptr(node_range), int(n_nodes),
                                          _ptr(cot), _ptr(gpos), _ptr(gmass), _ptr(gparam), _stream(stream)),
                        "gc_backward")
@@ -442,6 +493,7 @@ class Batch:
     def autotune(self, base: ForceParams, nodes, acc, reps: int = 3, stream=None):
         times = np.zeros(36, np.float32)
         best = ForceParams()
+        base = with_nodes(base, nodes)
         self.ctx.check(lib().gc_autotune(self.h, ctypes.byref(base), _ptr(nodes), _ptr(acc), reps, times.ctypes.data,
                                          ctypes.byref(best), _stream(stream)), "gc_autotune")
         return best, times
@@ -476,6 +528,7 @@ class Graph:
         else:
             ids = sl = None
             pn_ptr = None
+        prm = with_nodes(prm, nodes)
         self.ctx.check(lib().gc_graph_capture(ctx.h, n, B, P, M.ctypes.data, ctypes.byref(prm), _ptr(nodes), _ptr(acc),
                                               fixture, ids, sl, pn_ptr, _stream(stream),
                                               ctypes.byref(self.h)), "gc_graph_capture")
@@ -483,23 +536,39 @@ class Graph:
     def launch(self, stream=None):
         self.ctx.check(lib().gc_graph_launch(self.h, _stream(stream)), "gc_graph_launch")
 
+    def status(self, stream=None):
+        """Raises GcError if a bounded wait gave up in a launch since capture (gc_graph_status)."""
+        self.ctx.check(lib().gc_graph_status(self.h, _stream(stream)), "gc_graph_status")
+
     def destroy(self):
         if self.h:
             lib().gc_graph_destroy(self.h)
             self.h = VP()
 
 
+def with_nodes(prm: ForceParams, nodes) -> ForceParams:
+    """A copy of prm whose n_nodes is the node table's record count (12 floats per node)."""
+    p = ForceParams.from_buffer_copy(prm)
+    if nodes is not None and prm.kind in (FORCE_GRAV_MONO, FORCE_GRAV_QUAD):
+        p.n_nodes = int(nodes.numel() if hasattr(nodes, "numel") else np.asarray(nodes).size) // 12
+    return p
+
+
 def grav_params(order: int = 2, G: float = 1.0, eps: float = 0.01, schedule: int = 0, tile: int = 0,
-                waves_per_block: int = 0, grid_blocks: int = 0, targets_per_lane: int = 0) -> ForceParams:
+                waves_per_block: int = 0, grid_blocks: int = 0, targets_per_lane: int = 0, want_potential: int = 0,
+                deterministic: int = 0) -> ForceParams:
+    """Gravity parameters; n_nodes is filled in from the node table by the calls that take one."""
     p = ForceParams()
     p.kind = FORCE_GRAV_QUAD if order == 2 else FORCE_GRAV_MONO
     p.G, p.soft_eps = G, eps
     p.schedule, p.tile, p.waves_per_block, p.grid_blocks = schedule, tile, waves_per_block, grid_blocks
     p.targets_per_lane = targets_per_lane
+    p.want_potential, p.deterministic = want_potential, deterministic
     return p
 
 
-def lj_params(eps_t, sig_t, mass_t, r_cut: float, schedule: int = 0, grid_blocks: int = 0) -> ForceParams:
+def lj_params(eps_t, sig_t, mass_t, r_cut: float, schedule: int = 0, grid_blocks: int = 0, want_potential: int = 0,
+              deterministic: int = 0) -> ForceParams:
     """eps_t, sig_t, mass_t: device float32 tensors (kept alive by the caller)."""
     p = ForceParams()
     p.kind = FORCE_LJ
@@ -507,4 +576,5 @@ def lj_params(eps_t, sig_t, mass_t, r_cut: float, schedule: int = 0, grid_blocks
     p.eps_t, p.sig_t, p.mass_t = _ptr(eps_t), _ptr(sig_t), _ptr(mass_t)
     p.r_cut = r_cut
     p.schedule, p.grid_blocks = schedule, grid_blocks
+    p.want_potential, p.deterministic = want_potential, deterministic
     return p

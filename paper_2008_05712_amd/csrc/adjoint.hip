@@ -298,14 +298,22 @@ __global__ void __launch_bounds__(256) k_visit_sum(const float4* __restrict__ vn
 // One workgroup per node (its member loop spread over 256 lanes: a top node holds tens of thousands of
 // particles): its gradient (the sum of its chunks' sums, formed by each wavefront) pushed to the members:
 // dx_k += (m_k / M) dL/dcom + 2 m_k H e_k, dm_k += dL/dM + e_k . dL/dcom / M + e_k.H e_k, e_k = x_k - com.
+// A node whose member range is not inside [0, n_ids) is skipped and counted in *bad (its gradient is
+// not pushed), so a malformed node table cannot make the member loop read or write out of bounds.
 template <int NQ>
 __global__ void __launch_bounds__(256) k_node_chain(const int32_t* __restrict__ node_range, int32_t n_nodes, const float4* __restrict__ nodes,
                              const float4* __restrict__ part, const int32_t* __restrict__ chunk_first,
-                             const float4* __restrict__ rec_by_id, float4* __restrict__ gpos, float* __restrict__ gmass) {
+                             const float4* __restrict__ rec_by_id, int32_t n_ids, float4* __restrict__ gpos,
+                             float* __restrict__ gmass, int32_t* __restrict__ bad) {
   const int lane = threadIdx.x & 63;
   for (int nd = blockIdx.x; nd < n_nodes; nd += gridDim.x) {
     const int c0 = gld(chunk_first + nd), c1 = gld(chunk_first + nd + 1);
     if (c0 == c1) continue;  // the node is in no task's list
+    const int b = node_range[2 * nd], n = node_range[2 * nd + 1];
+    if (b < 0 || n < 0 || b > n_ids - n) {
+      if (threadIdx.x == 0) atomicAdd(bad, 1);
+      continue;
+    }
     float4 acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -323,7 +331,6 @@ __global__ void __launch_bounds__(256) k_node_chain(const int32_t* __restrict__ 
     }
     const float4 c = nodes[3 * nd];
     const float invM = 1.f / c.w;
-    const int b = node_range[2 * nd], n = node_range[2 * nd + 1];
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
       const float4 r = rec_by_id[b + k];
       const float f = r.w * invM;
@@ -867,16 +874,16 @@ hipError_t launch_visit_sums(int order, const float4* vnode, const int32_t* nvis
 }
 
 hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nodes, const float4* nodes,
-                             const float4* part, const int32_t* chunk_first, const float4* rec_by_id, float4* gpos,
-                             float* gmass, hipStream_t s) {
+                             const float4* part, const int32_t* chunk_first, const float4* rec_by_id, int32_t n_ids,
+                             float4* gpos, float* gmass, int32_t* bad, hipStream_t s) {
   if (n_nodes <= 0) return hipSuccess;
   const int g = n_nodes < 65536 ? n_nodes : 65536;
   if (order == 2)
     hipLaunchKernelGGL(k_node_chain<3>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, part, chunk_first,
-                       rec_by_id, gpos, gmass);
+                       rec_by_id, n_ids, gpos, gmass, bad);
   else
     hipLaunchKernelGGL(k_node_chain<1>, dim3(g), dim3(256), 0, s, node_range, n_nodes, nodes, part, chunk_first,
-                       rec_by_id, gpos, gmass);
+                       rec_by_id, n_ids, gpos, gmass, bad);
   return hipGetLastError();
 }
 

@@ -17,9 +17,21 @@ constexpr int kMaxTile = 1024;                          // direct records per wa
 constexpr int kSortMax = 8192;                          // longest per-task list sorted in LDS
 constexpr int kLptChunk = 8192;                         // tasks per longest-first ordering run
 
-// Algorithmic work per interaction, counting add/sub/mul = 1, fma = 2, rsqrt = 1, from the
-// implemented formulas: pair or monopole 3 sub + 3 fma + rsqrt + 3 mul + 3 fma = 19;
-// quadrupole (monopole included) 51; Lennard-Jones in-cutoff pair 26 (both atoms updated).
+// Algorithmic work per interaction (add / sub / mul = 1, fma = 2, rsqrt / rcp = 1, compare and
+// select = 0), counted term by term on the implemented formulas:
+//   pair or monopole, 19: d = x_j - x_i (3 sub); r^2 = d.d + eps^2 (3 fma = 6); r^-1 (rsqrt, 1);
+//     m r^-1, r^-2, m r^-3 (3 mul); a += m r^-3 d (3 fma = 6).
+//   quadrupole node, monopole term included, 51: d = x - com (3 sub); r^2 (3 fma = 6); r^-1 (1);
+//     r^-2, r^-3, r^-5 (3 mul); S'd with S' = 3 S, stored in the node record (per component
+//     1 mul + 2 fma = 5, so 15); d.S'd (1 mul + 2 fma = 5); -2.5 r^-2 (1 mul);
+//     u = 1.5 T - 2.5 r^-2 d.S'd (1 fma = 2); v = r^-2 u - M (1 fma = 2); c = r^-3 v (1 mul);
+//     a += c d + r^-5 S'd (6 fma = 12).  The factors 3 on S and 1.5 on T are applied once per node
+//     record as it is staged, not per interaction, so they are not counted (an estimate that
+//     applies them per interaction comes to about 54).
+//   Lennard-Jones pair inside the cutoff, both atoms updated, 26: d = x_i - x_j - shift (the shift
+//     folded into the staged source; 3 sub); r^2 (1 mul + 2 fma = 5); r^-2 (rcp, 1);
+//     q = sigma^2 r^-2 (1 mul); q^3 (2 mul); f = 24 eps q^3 (2 q^3 - 1) r^-2 (1 fma + 3 mul = 5);
+//     f d (3 mul); F_i += f d (3 add); F_j -= f d (3 sub).
 constexpr int kFlopsPair = 19;
 constexpr int kFlopsQuad = 51;
 constexpr int kFlopsLJ = 26;
@@ -178,7 +190,13 @@ struct StepArgs {
                           // hits its bound sets the error word of its round's batch state
   uint64_t* fmeta;        // free-slot list of the launch: [0] its count, [1 + r] round r's offset into
                           // it, then the list (tagged words, tag = launch epoch + 1)
+  uint32_t spin_limit;    // probes after which a wait gives up and sets its round's error word
+  int32_t fail_round;     // test hook: this round's force items wait for one data part too many (-1: none)
+  uint32_t fail_spins;    // and give up after this many probes
 };
+// Dependencies complete within microseconds; the default bound (about a second) only keeps a broken
+// state from holding the grid.
+constexpr uint32_t kStepSpinLimit = 1u << 20;
 constexpr int kCtrStride = 32;  // one 256-byte line per step counter
 constexpr int kCtrTickets = 0, kCtrExits = 1, kCtrEpoch = 2, kCtrRounds = 3;  // then per round r:
                                 // kCtrRounds + 2r table parts (free-scan and union items) done,
@@ -209,9 +227,10 @@ hipError_t launch_grav_adjoint(bool packed, int order, const GravAdjArgs& a, int
 // runs of a wavefront and added to gpos / gmass.
 hipError_t launch_visit_sums(int order, const float4* vnode, const int32_t* nvis, const int2* chunks,
                              int32_t n_chunks, float4* part, hipStream_t s);
+// Nodes whose (first id, count) range is not inside [0, n_ids) are skipped and counted in *bad.
 hipError_t launch_node_chain(int order, const int32_t* node_range, int32_t n_nodes, const float4* nodes,
-                             const float4* part, const int32_t* chunk_first, const float4* rec_by_id, float4* gpos,
-                             float* gmass, hipStream_t s);
+                             const float4* part, const int32_t* chunk_first, const float4* rec_by_id, int32_t n_ids,
+                             float4* gpos, float* gmass, int32_t* bad, hipStream_t s);
 hipError_t launch_direct_sums(const float4* vdir, const int32_t* dvis, const int32_t* dkey, int32_t n_vis,
                               float4* gpos, float* gmass, hipStream_t s);
 struct LJAdjArgs {

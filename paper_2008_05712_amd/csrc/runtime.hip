@@ -16,28 +16,53 @@
 using namespace gc;
 
 namespace {
-// Device buffer that only grows.
+// The caller's device allocator (gc_init); both NULL: hipMalloc / hipFree.
+struct AllocHooks {
+  gc_alloc_fn alloc = nullptr;
+  gc_free_fn free = nullptr;
+  void* user = nullptr;
+};
+
+// Device buffer that only grows, allocated through its context's hooks.  Memory goes back to the
+// caller's allocator only after the device is idle, since a caching allocator may hand it out again
+// at once to work on another stream.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
-  hipError_t ensure(size_t want) {
-    if (want <= bytes && p) return hipSuccess;
+  const AllocHooks* h = nullptr;
+  hipError_t give_back() {
+    hipError_t e = hipSuccess;
     if (p) {
-      hipError_t e = hipFree(p);
-      p = nullptr;
-      bytes = 0;
-      if (e != hipSuccess) return e;
+      if (h && h->alloc) {
+        e = hipDeviceSynchronize();
+        h->free(p, h->user);
+      } else {
+        e = hipFree(p);
+      }
     }
-    size_t b = want < 256 ? 256 : want;
-    hipError_t e = hipMalloc(&p, b);
-    if (e == hipSuccess) bytes = b;
-    return e;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    return e;
   }
+  hipError_t ensure(size_t want) {
+    if (want <= bytes && p) return hipSuccess;
+    hipError_t e = give_back();
+    if (e != hipSuccess) return e;
+    size_t b = want < 256 ? 256 : want;
+    if (h && h->alloc) {
+      p = h->alloc(b, h->user);
+      if (!p) return hipErrorOutOfMemory;
+    } else {
+      e = hipMalloc(&p, b);
+      if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+      }
+    }
+    bytes = b;
+    return hipSuccess;
+  }
+  void release() { (void)give_back(); }
   template <class T>
   T* as() const { return static_cast<T*>(p); }
 };
@@ -48,8 +73,14 @@ struct gc_ctx_ {
   int device = 0;
   int n_cu = 0;
   bool poisoned = false;
+  hipError_t injected = hipSuccess;  // test hook: an error that the next call reports as asynchronous
   std::string err;
+  AllocHooks hooks;
   DevBuf walk_keep;  // the list walk's per-bucket room, kept between calls
+  // test hook for the whole-step schedule, taken by the next capture: a round whose force items wait
+  // for a count that is never reached (-1: none), and the bound on those waits (0: the default)
+  int32_t step_fail_round = -1;
+  uint32_t step_fail_spins = 0;
 };
 
 namespace {
@@ -80,6 +111,11 @@ gc_status hip_fail(gc_ctx c, hipError_t e, const char* what) {
     if (!(ctx)) return GC_E_INVAL;                                                      \
     if ((ctx)->poisoned) return set_err((ctx), GC_E_STATE, "context poisoned by an earlier device error"); \
     (ctx)->err.clear();                                                                 \
+    if ((ctx)->injected != hipSuccess) {                                                \
+      const hipError_t inj_ = (ctx)->injected;                                          \
+      (ctx)->injected = hipSuccess;                                                     \
+      return hip_fail((ctx), inj_, "asynchronous device error (injected)");             \
+    }                                                                                   \
   } while (0)
 
 inline int64_t pad_to(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
@@ -94,6 +130,7 @@ struct gc_pool_ {
   DevBuf rec, slot_of, occ;
   const float4* src = nullptr;
   bool src_device = false;
+  std::vector<DevBuf*> bufs() { return {&rec, &slot_of, &occ}; }
 };
 
 struct gc_batch_ {
@@ -125,10 +162,17 @@ struct gc_batch_ {
   // the chunk sums, and the direct visits grouped by source id (built on the first backward call)
   DevBuf vnode, vdir, nvis, nchunks, nchunk_first, npart, dvis, dkey;
   int32_t adj_nodes = -1, adj_chunks = 0;  // node count the indices were built for (-1: none)
+  DevBuf stat;  // device-side error words: [0] node ranges the adjoint found out of bounds
+  int32_t max_node = -1;  // largest node index submitted
   // state of the last reorganisation
   int32_t mode = -1;
   gc_pool pool = nullptr;
   const float4* rec = nullptr;
+  std::vector<DevBuf*> bufs() {
+    return {&d_tasks, &d_ranges, &d_nodes, &d_ioff, &d_joff, &d_order, &d_runs, &d_U, &pranges, &pibeg, &d_irank,
+            &d_jrank, &uslot, &missing, &mslot, &free_list, &state, &packed, &ilist, &jlist, &queue, &force, &ppart,
+            &vnode, &vdir, &nvis, &nchunks, &nchunk_first, &npart, &dvis, &dkey, &d_ljtgt, &d_ljent, &stat};
+  }
 };
 
 struct gc_graph_ {
@@ -138,17 +182,24 @@ struct gc_graph_ {
   DevBuf step_items, step_rounds, step_ctr, step_fl;  // whole-step persistent schedule
   std::vector<hipStream_t> side;   // capture-time side streams (combined passes of successive steps overlap)
   std::vector<hipEvent_t> events;
+  std::vector<const int32_t*> err_words;  // the error words of the batches the graph reorganises
+  std::vector<DevBuf*> bufs() { return {&step_items, &step_rounds, &step_ctr, &step_fl}; }
 };
 
 // ===================================================================== context
 
 extern "C" const char* gc_version(void) { return "gcharm-mi355x 0.1 (gfx950)"; }
 
-extern "C" gc_status gc_init(int device, gc_ctx* out) {
+extern "C" gc_status gc_init(int device, gc_alloc_fn alloc_fn, gc_free_fn free_fn, void* user, gc_ctx* out) {
   if (!out) return GC_E_INVAL;
   *out = nullptr;
+  if ((alloc_fn == nullptr) != (free_fn == nullptr)) return GC_E_INVAL;
   gc_ctx c = new gc_ctx_();
   c->device = device;
+  c->hooks.alloc = alloc_fn;
+  c->hooks.free = free_fn;
+  c->hooks.user = user;
+  c->walk_keep.h = &c->hooks;
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) {
     delete c;
@@ -174,6 +225,41 @@ extern "C" gc_status gc_finalize(gc_ctx ctx) {
 
 extern "C" const char* gc_last_error(gc_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+extern "C" gc_status gc_debug_inject_error(gc_ctx ctx, int hip_error) {
+  if (!ctx || hip_error == 0) return GC_E_INVAL;
+  ctx->injected = static_cast<hipError_t>(hip_error);
+  return GC_OK;
+}
+
+extern "C" gc_status gc_debug_step_waits(gc_ctx ctx, uint32_t fail_spins, int32_t fail_round) {
+  GC_ENTER(ctx);
+  ctx->step_fail_spins = fail_spins;
+  ctx->step_fail_round = fail_round < 0 ? -1 : fail_round;
+  return GC_OK;
+}
+
+namespace {
+// Reads device int32 words (each may be NULL) after waiting on the stream; returns the first nonzero
+// word's index, or -1.
+hipError_t first_set_word(const std::vector<const int32_t*>& words, hipStream_t s, int* hit) {
+  *hit = -1;
+  std::vector<int32_t> h(words.size(), 0);
+  for (size_t k = 0; k < words.size(); ++k) {
+    if (!words[k]) continue;
+    hipError_t e = hipMemcpyAsync(&h[k], words[k], sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  for (size_t k = 0; k < words.size(); ++k)
+    if (h[k] != 0) {
+      *hit = (int)k;
+      break;
+    }
+  return hipSuccess;
+}
+}  // namespace
+
 extern "C" gc_status gc_zero_f32(gc_ctx ctx, float* dev, int64_t n, void* stream) {
   GC_ENTER(ctx);
   if (n < 0 || (n > 0 && !dev)) return set_err(ctx, GC_E_INVAL, "gc_zero_f32: bad buffer");
@@ -190,6 +276,7 @@ extern "C" gc_status gc_pool_create(gc_ctx ctx, int32_t n_ids, int32_t capacity,
   p->ctx = ctx;
   p->n_ids = n_ids;
   p->cap = capacity;
+  for (DevBuf* d : p->bufs()) d->h = &ctx->hooks;
   hipError_t e = p->rec.ensure(sizeof(float4) * (size_t)capacity);
   if (e == hipSuccess) e = p->slot_of.ensure(sizeof(int32_t) * (size_t)n_ids);
   if (e == hipSuccess) e = p->occ.ensure(sizeof(uint32_t) * (size_t)occ_words(capacity));
@@ -296,6 +383,7 @@ extern "C" gc_status gc_batch_create(gc_ctx ctx, int32_t kind, int32_t n_ids, gc
   b->ctx = ctx;
   b->kind = kind;
   b->n_ids = n_ids;
+  for (DevBuf* d : b->bufs()) d->h = &ctx->hooks;
   *out = b;
   return GC_OK;
 }
@@ -303,11 +391,7 @@ extern "C" gc_status gc_batch_create(gc_ctx ctx, int32_t kind, int32_t n_ids, gc
 extern "C" gc_status gc_batch_destroy(gc_batch b) {
   if (!b) return GC_E_INVAL;
   (void)hipDeviceSynchronize();
-  for (DevBuf* d : {&b->d_tasks, &b->d_ranges, &b->d_nodes, &b->d_ioff, &b->d_joff, &b->d_order, &b->d_runs, &b->d_U,
-                    &b->pranges, &b->pibeg, &b->d_irank, &b->d_jrank, &b->uslot, &b->missing, &b->mslot, &b->free_list,
-                    &b->state, &b->packed, &b->ilist, &b->jlist, &b->queue, &b->force, &b->ppart, &b->vnode, &b->vdir, &b->nvis,
-                    &b->nchunks, &b->nchunk_first, &b->npart, &b->dvis, &b->dkey, &b->d_ljtgt, &b->d_ljent})
-    d->release();
+  for (DevBuf* d : b->bufs()) d->release();
   delete b;
   return GC_OK;
 }
@@ -319,6 +403,7 @@ extern "C" gc_status gc_batch_reset(gc_batch b) {
   b->ranges.clear();
   b->nodes.clear();
   b->n_direct = b->n_targets = 0;
+  b->max_node = -1;
   b->committed = false;
   b->ranks_ready = false;
   b->hU.clear();
@@ -343,8 +428,12 @@ extern "C" gc_status gc_submit_tasks(gc_batch b, const gc_task* tasks, int32_t n
       return set_err(c, GC_E_INVAL, "gc_submit_tasks: range %d (%lld, %lld) outside [0, %d)", r, (long long)s,
                      (long long)n, b->n_ids);
   }
-  for (int32_t k = 0; k < n_node_refs; ++k)
+  int32_t max_node = b->max_node;
+  for (int32_t k = 0; k < n_node_refs; ++k) {
     if (node_idx[k] < 0) return set_err(c, GC_E_INVAL, "gc_submit_tasks: negative node index at %d", k);
+    max_node = std::max(max_node, node_idx[k]);
+  }
+  std::vector<std::pair<int32_t, int32_t>> tr;  // one task's nonempty direct ranges, for the overlap test
   for (int32_t t = 0; t < n_tasks; ++t) {
     const gc_task& tk = tasks[t];
     if (tk.i_count < 0 || tk.i_begin < 0 || (int64_t)tk.i_begin + tk.i_count > b->n_ids)
@@ -364,6 +453,19 @@ extern "C" gc_status gc_submit_tasks(gc_batch b, const gc_task* tasks, int32_t n
     }
     for (int32_t r = 0; r < tk.j_nranges; ++r) add_direct += j_ranges[2 * (tk.j_first + r) + 1];
     add_targets += tk.i_count;
+    // a source listed twice would be counted twice: the direct ranges of a task must not overlap
+    if (tk.j_nranges > 1) {
+      tr.clear();
+      for (int32_t r = 0; r < tk.j_nranges; ++r) {
+        const int32_t* g = j_ranges + 2 * (tk.j_first + r);
+        if (g[1] > 0) tr.emplace_back(g[0], g[1]);
+      }
+      std::sort(tr.begin(), tr.end());
+      for (size_t q = 1; q < tr.size(); ++q)
+        if ((int64_t)tr[q - 1].first + tr[q - 1].second > tr[q].first)
+          return set_err(c, GC_E_INVAL, "gc_submit_tasks: task %d has overlapping direct ranges at ids %d and %d", t,
+                         tr[q - 1].first, tr[q].first);
+    }
   }
   if (b->n_direct + add_direct > INT32_MAX || b->n_targets + add_targets > INT32_MAX ||
       (int64_t)b->tasks.size() + n_tasks > INT32_MAX || (int64_t)b->ranges.size() / 2 + n_ranges > INT32_MAX)
@@ -379,6 +481,7 @@ extern "C" gc_status gc_submit_tasks(gc_batch b, const gc_task* tasks, int32_t n
   b->nodes.insert(b->nodes.end(), node_idx, node_idx + n_node_refs);
   b->n_direct += add_direct;
   b->n_targets += add_targets;
+  b->max_node = max_node;
   b->committed = false;
   b->ranks_ready = false;
   b->mode = -1;
@@ -392,6 +495,19 @@ extern "C" gc_status gc_batch_sizes(gc_batch b, int64_t* out5) {
   out5[2] = (int64_t)b->nodes.size();
   out5[3] = b->n_direct;
   out5[4] = b->n_targets;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_batch_status(gc_batch b, void* stream) {
+  if (!b) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  const int32_t* wait_word = b->state.p ? b->state.as<int32_t>() + GC_STATE_ERR : nullptr;
+  const int32_t* node_word = b->stat.p ? b->stat.as<int32_t>() : nullptr;
+  int hit = -1;
+  GC_HIP(c, first_set_word({wait_word, node_word}, S(stream), &hit));
+  if (hit == 0) return set_err(c, GC_E_HIP, "gc_batch_status: a bounded wait of a reorganisation gave up");
+  if (hit == 1) return set_err(c, GC_E_INVAL, "gc_batch_status: a backward call met node ranges outside [0, n_ids)");
   return GC_OK;
 }
 
@@ -536,6 +652,8 @@ extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
     up(b->d_ljtgt, ljtgt.data(), sizeof(int32_t) * ljtgt.size());
     up(b->d_ljent, ljent.data(), sizeof(int32_t) * ljent.size());
   }
+  if (e == hipSuccess) e = b->stat.ensure(sizeof(int32_t) * 4);
+  if (e == hipSuccess) e = launch_fill_i32(b->stat.as<int32_t>(), 0, 4, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors must outlive the copies
   if (e != hipSuccess) return hip_fail(c, e, "gc_batch_commit");
   order.resize((size_t)T);
@@ -850,6 +968,10 @@ static gc_status check_prm(gc_batch b, const gc_force_params* prm, int* tile, in
     return set_err(c, GC_E_INVAL, "schedule must be GC_SCHED_TASKS, GC_SCHED_QUEUE or GC_SCHED_STEP");
   if (prm->targets_per_lane < 0 || prm->targets_per_lane > 2)
     return set_err(c, GC_E_INVAL, "targets_per_lane must be 0, 1 or 2");
+  if (b->kind == GC_KIND_GRAV && b->max_node >= prm->n_nodes)
+    return set_err(c, GC_E_INVAL, "node index %d is not below n_nodes %d of the node table", b->max_node, prm->n_nodes);
+  if (prm->want_potential != 0 && prm->want_potential != 1) return set_err(c, GC_E_INVAL, "want_potential must be 0 or 1");
+  if (prm->deterministic != 0 && prm->deterministic != 1) return set_err(c, GC_E_INVAL, "deterministic must be 0 or 1");
   return GC_OK;
 }
 
@@ -863,6 +985,11 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
     return set_err(c, GC_E_UNSUPPORTED, "the whole-step schedule runs through gc_graph_capture only");
   if (b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_launch_combined: batch not reorganised");
   if (!acc_dev) return set_err(c, GC_E_INVAL, "gc_launch_combined: NULL acc");
+  if (prm->want_potential) return set_err(c, GC_E_UNSUPPORTED, "gc_launch_combined: potential output not built");
+  if (prm->deterministic && b->kind == GC_KIND_LJ && !b->lj_gather)
+    return set_err(c, GC_E_UNSUPPORTED,
+                   "gc_launch_combined: this Lennard-Jones batch (target ranges that partially overlap) sums with "
+                   "atomics; no deterministic form");
   const int32_t T = (int32_t)b->tasks.size();
   const bool packed = (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT);
   const bool lists = (b->mode == GC_REORG_INDIRECT || b->mode == GC_REORG_SORTED);
@@ -1073,6 +1200,9 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
   gc_status st = check_prm(b, prm, &tile, &wpb);
   if (st != GC_OK) return st;
   if (b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_backward: batch not reorganised");
+  if (prm->deterministic && (b->kind == GC_KIND_GRAV || !b->lj_gather))
+    return set_err(c, GC_E_UNSUPPORTED, "gc_backward: this adjoint adds target gradients with atomics; no "
+                                        "deterministic form");
   if (b->mode == GC_REORG_INDIRECT || b->mode == GC_REORG_SORTED)
     return set_err(c, GC_E_UNSUPPORTED, "gc_backward supports PACK, REDUNDANT and NONE reorganisations");
   if (!b->pool->src_device) return set_err(c, GC_E_INVAL, "gc_backward needs a device-resident source");
@@ -1113,8 +1243,8 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
       GC_HIP(c, launch_visit_sums(order, a.vnode, b->nvis.as<int32_t>(), b->nchunks.as<int2>(), b->adj_chunks,
                                   b->npart.as<float4>(), s));
       GC_HIP(c, launch_node_chain(order, node_range_dev, n_nodes, reinterpret_cast<const float4*>(nodes_dev),
-                                  b->npart.as<float4>(), b->nchunk_first.as<int32_t>(), b->pool->src, a.gpos,
-                                  gmass_dev, s));
+                                  b->npart.as<float4>(), b->nchunk_first.as<int32_t>(), b->pool->src, b->n_ids,
+                                  a.gpos, gmass_dev, b->stat.as<int32_t>(), s));
     }
     return GC_OK;
   }
@@ -1291,6 +1421,9 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   a.n_rounds = R;
   a.ctr = gr->step_ctr.as<uint64_t>();
   a.fmeta = fmeta;
+  a.spin_limit = kStepSpinLimit;
+  a.fail_round = ctx->step_fail_round < R ? ctx->step_fail_round : -1;
+  a.fail_spins = ctx->step_fail_spins ? ctx->step_fail_spins : kStepSpinLimit;
   hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamBeginCapture");
   hipError_t le = hipSuccess;
@@ -1313,6 +1446,7 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     batches[k]->mode = GC_REORG_PACK;
     batches[k]->pool = p;
     batches[k]->rec = batches[k]->packed.as<float4>();
+    gr->err_words.push_back(batches[k]->state.as<int32_t>() + GC_STATE_ERR);
   }
   return GC_OK;
 }
@@ -1352,6 +1486,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
   if (prm->schedule == GC_SCHED_STEP) {
     gc_graph gs = new gc_graph_();
     gs->ctx = ctx;
+    for (DevBuf* d : gs->bufs()) d->h = &ctx->hooks;
     gc_status st = capture_step(ctx, n_steps, batches, pools, modes, prm, nodes_dev, acc_dev, fixture, s, gs);
     if (st != GC_OK) {
       if (gs->exec) (void)hipGraphExecDestroy(gs->exec);
@@ -1377,6 +1512,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
   }
   gc_graph gr = new gc_graph_();
   gr->ctx = ctx;
+  for (DevBuf* d : gr->bufs()) d->h = &ctx->hooks;
   auto cleanup = [&]() {
     for (hipEvent_t e : gr->events) (void)hipEventDestroy(e);
     for (hipStream_t q : gr->side) (void)hipStreamDestroy(q);
@@ -1482,6 +1618,8 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
     cleanup();
     return hip_fail(ctx, e, "hipGraphInstantiate");
   }
+  for (int32_t k = 0; k < n_steps; ++k)
+    gr->err_words.push_back(modes[k] != GC_REORG_NONE ? batches[k]->state.as<int32_t>() + GC_STATE_ERR : nullptr);
   *out = gr;
   return GC_OK;
 }
@@ -1490,6 +1628,16 @@ extern "C" gc_status gc_graph_launch(gc_graph g, void* stream) {
   if (!g) return GC_E_INVAL;
   GC_ENTER(g->ctx);
   GC_HIP(g->ctx, hipGraphLaunch(g->exec, S(stream)));
+  return GC_OK;
+}
+
+extern "C" gc_status gc_graph_status(gc_graph g, void* stream) {
+  if (!g) return GC_E_INVAL;
+  GC_ENTER(g->ctx);
+  int hit = -1;
+  GC_HIP(g->ctx, first_set_word(g->err_words, S(stream), &hit));
+  if (hit >= 0)
+    return set_err(g->ctx, GC_E_HIP, "gc_graph_status: a bounded wait gave up (step %d of the capture)", hit);
   return GC_OK;
 }
 
@@ -1560,6 +1708,7 @@ extern "C" gc_status gc_autotune(gc_batch b, const gc_force_params* base, const 
 namespace {
 struct ScopedBuf {  // device scratch of one call, freed on every return path
   DevBuf d;
+  explicit ScopedBuf(gc_ctx c) { d.h = &c->hooks; }
   ~ScopedBuf() { d.release(); }
 };
 }  // namespace
@@ -1586,7 +1735,7 @@ extern "C" gc_status gc_tree_walk(gc_ctx c, int32_t n_nodes, const int32_t* node
     GC_HIP(c, launch_fill_i32(r_first_dev, 0, (int64_t)n_buckets + 1, s));
     return GC_OK;
   }
-  ScopedBuf skip, tot;
+  ScopedBuf skip(c), tot(c);
   if (skip.d.ensure(sizeof(int32_t) * (size_t)n_nodes) != hipSuccess || tot.d.ensure(256) != hipSuccess)
     return set_err(c, GC_E_NOMEM, "gc_tree_walk: scratch");
   // room for each bucket's lists in the count pass, kept by the context (without it every bucket is

@@ -190,7 +190,7 @@ def test_autograd_gravity_matches_backward(ctx):
     rig.close()
 
 
-def _lj_vjp_gpu(ctx, w, g, reps=1):
+def _lj_vjp_gpu(ctx, w, g, reps=1, mode=gc.REORG_PACK):
     """Forward then `reps` backward calls over w's tasks; returns gpos, gmass, gparam after each call."""
     import torch
     src = torch.from_numpy(np.ascontiguousarray(w.rec)).cuda()
@@ -204,7 +204,7 @@ def _lj_vjp_gpu(ctx, w, g, reps=1):
     b = gc.Batch(ctx, gc.KIND_LJ, w.n)
     b.submit(t, ranges)
     b.commit()
-    b.reorganize(pool, gc.REORG_PACK)
+    b.reorganize(pool, mode)
     prm = gc.lj_params(eps, sig, mass, w.rcut)
     acc = torch.zeros((w.n, 4), dtype=torch.float32, device="cuda")
     b.launch(prm, None, acc)
@@ -257,3 +257,27 @@ def test_lj_vjp_gather_form_accumulates(ctx):
     out = _lj_vjp_gpu(ctx, w, g, reps=2)
     _check_lj_vjp(out[0], w, g)
     assert np.array_equal(out[1][0], 2.0 * out[0][0])
+
+
+def test_quadrupole_vjp_full_size_plummer_262144(ctx):
+    # the size the bench times: 27,026 bucket tasks, 18.6 M node-list entries (a top node is in tens of
+    # thousands of lists and holds 37,166 members), core particles with about 2,000 direct visits; every
+    # particle's gradient against the oracle's VJP
+    w = W.nbody_plummer()
+    print(f"[gpu] quadrupole adjoint full size N={w.n} tasks={w.n_tasks}", flush=True)
+    g = np.random.default_rng(71).normal(size=(w.n, 3)).astype(np.float32).astype(np.float64)
+    gp, gm = grav_vjp_gpu(ctx, w, g, gc.REORG_NONE, order=2)
+    rp, rm = O.vjp_grav(w, g, order=2)
+    ok, e = close(gp, rp)
+    assert ok, ("positions", e)
+    ok, e = close(gm, rm)
+    assert ok, ("masses", e)
+
+
+def test_lj_vjp_full_size_two_types_1048576(ctx):
+    # the two-type Lennard-Jones adjoint at the size the bench times (1,048,576 atoms, 1,234,800 cell-pair
+    # tasks, gather form): positions, masses and eps / sigma against the oracle's VJP
+    w = W.lj_fcc(two_type=True)
+    print(f"[gpu] LJ adjoint full size N={w.n} tasks={w.n_tasks}", flush=True)
+    g = np.random.default_rng(72).normal(size=(w.n, 3)).astype(np.float32).astype(np.float64)
+    _check_lj_vjp(_lj_vjp_gpu(ctx, w, g, mode=gc.REORG_NONE)[0], w, g)

@@ -10,6 +10,7 @@ import pytest
 import oracle as O
 import paper_2008_05712_amd as gc
 import workloads as W
+from bench import STEP_SHAPES
 from gpu_helpers import GravRig, rel_l2_per_task, whole
 
 pytestmark = pytest.mark.gpu
@@ -475,17 +476,19 @@ def _set_base(rig, base):
     rig.place(*base)
 
 
-@pytest.mark.parametrize("order,tpl", [(1, 0), (2, 0), (2, 2)])
-def test_step_schedule_matches_per_round_launches(ctx, plum, order, tpl):
+@pytest.mark.parametrize("tile,tpl", STEP_SHAPES)
+@pytest.mark.parametrize("order", [1, 2])
+def test_step_schedule_matches_per_round_launches(ctx, plum, order, tile, tpl):
     # one persistent launch per step (every round's reorganisation, eviction of its staging, and pass)
     # gives bitwise the per-round launches' accelerations and the oracle's maps on the base state, and
-    # leaves the base residency in the pool; replays repeat it exactly
+    # leaves the base residency in the pool; replays repeat it exactly.  Every launch shape the bench
+    # may time is covered (tiles that are not powers of two change the tile and share splits)
     import torch
-    print(f"[gpu] whole-step schedule order={order} targets_per_lane={tpl}", flush=True)
+    print(f"[gpu] whole-step schedule order={order} tile={tile} targets_per_lane={tpl}", flush=True)
     rig, bts, bs, base = _rounds_rig(ctx, plum, 4, 500, 38, 0.4, 39)
     _set_base(rig, base)
     base_so = rig.pool.query()
-    prm = gc.grav_params(order=order, targets_per_lane=tpl)
+    prm = gc.grav_params(order=order, tile=tile, targets_per_lane=tpl)
     rig.acc.fill_(np.nan)
     for k, b in enumerate(bs):
         if k:
@@ -500,7 +503,7 @@ def test_step_schedule_matches_per_round_launches(ctx, plum, order, tpl):
     rig.pool.evict_staged(bs[-1])
     assert np.array_equal(rig.pool.query(), base_so)
     s = torch.cuda.Stream()
-    sprm = gc.grav_params(order=order, schedule=gc.SCHED_STEP, targets_per_lane=tpl)
+    sprm = gc.grav_params(order=order, schedule=gc.SCHED_STEP, tile=tile, targets_per_lane=tpl)
     g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), sprm, rig.nodes, rig.acc, stream=s,
                  fixture=gc.FIXTURE_EVICT_STAGED)
     for rep in range(4):
@@ -515,6 +518,7 @@ def test_step_schedule_matches_per_round_launches(ctx, plum, order, tpl):
             _check_maps(bs[k].maps(), O.maps(bts[k], plum.n, plum.n, base_so, gc.REORG_PACK), gc.REORG_PACK)
         # with the evicting fixture each round's staging leaves the table once packed: the base remains
         assert np.array_equal(rig.pool.query(), base_so), rep
+    g.status(stream=s)
     g.destroy()
     for b in bs:
         b.destroy()
@@ -630,15 +634,17 @@ def test_step_schedule_without_fixture_overflow_matches_eager(ctx, plum):
     rig.close()
 
 
-def test_step_schedule_full_size_rounds(ctx):
-    # 262,144-particle Plummer sphere, 6 Poisson(2048) rounds over half of all particles resident:
-    # the whole-step launch equals the per-round launches bitwise; sampled tasks match the oracle
+@pytest.mark.parametrize("tile,tpl", STEP_SHAPES)
+def test_step_schedule_full_size_rounds(ctx, tile, tpl):
+    # 262,144-particle Plummer sphere, 6 Poisson(2048) rounds over half of all particles resident, in
+    # every launch shape the bench may time: the whole-step launch equals the per-round launches of the
+    # same shape bitwise; sampled tasks match the oracle
     import torch
     w = W.nbody_plummer()
-    print(f"[gpu] whole-step full size N={w.n}", flush=True)
+    print(f"[gpu] whole-step full size N={w.n} tile={tile} targets_per_lane={tpl}", flush=True)
     rig, bts, bs, base = _rounds_rig(ctx, w, 6, 2048, 1002, 0.5, 5000)
     _set_base(rig, base)
-    prm = gc.grav_params(order=2)
+    prm = gc.grav_params(order=2, tile=tile, targets_per_lane=tpl)
     rig.acc.fill_(np.nan)
     for k, b in enumerate(bs):
         if k:
@@ -649,8 +655,9 @@ def test_step_schedule_full_size_rounds(ctx):
     torch.cuda.synchronize()
     eager = rig.acc.cpu().numpy()
     s = torch.cuda.Stream()
-    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), gc.grav_params(order=2, schedule=gc.SCHED_STEP),
-                 rig.nodes, rig.acc, stream=s, fixture=gc.FIXTURE_EVICT_STAGED)
+    sprm = gc.grav_params(order=2, schedule=gc.SCHED_STEP, tile=tile, targets_per_lane=tpl)
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), sprm, rig.nodes, rig.acc, stream=s,
+                 fixture=gc.FIXTURE_EVICT_STAGED)
     for rep in range(3):
         rig.acc.fill_(np.nan)
         torch.cuda.synchronize()
@@ -659,6 +666,7 @@ def test_step_schedule_full_size_rounds(ctx):
         got = rig.acc.cpu().numpy()
         assert np.array_equal(np.isnan(got), np.isnan(eager)), rep
         assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)]), rep
+    g.status(stream=s)
     sel = np.random.default_rng(3).choice(np.concatenate([np.asarray(r) for r in W.poisson_rounds(w.n_tasks, 2048, seed=1002)[:6]]),
                                           size=48, replace=False)
     sub = W.task_subset(w, np.sort(sel))

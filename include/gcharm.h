@@ -414,6 +414,26 @@ gc_status gc_tree_walk(gc_ctx ctx, int32_t n_nodes, const int32_t* node_range_de
                        int32_t* node_idx_dev, int64_t node_cap, int32_t* ranges_dev, int64_t range_cap,
                        int64_t* totals, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the walk of
+ * gc_tree_walk, with the same arguments, outputs, errors and results, that
+ * allocates nothing.  Its scratch (the subtree ends of the nodes, 4 bytes
+ * each, and the totals) lives in one fixed device array of the library,
+ * 8 MiB + 256 bytes, which each device holds until the process ends: trees of
+ * at most 2^21 nodes (GC_E_INVAL beyond).  It keeps no per-bucket room, so
+ * every bucket is walked twice (count, then fill).  Every call on a device
+ * shares that device's array, which keeps the last call's contents (the
+ * totals are cleared by a kernel at the start of each call): calls that
+ * overlap on one device race, whatever their contexts.  Waits on `stream`
+ * like gc_tree_walk.
+ */
+gc_status gc_tree_walk_noalloc(gc_ctx ctx, int32_t n_nodes, const int32_t* node_range_dev, const double* node_com_dev,
+                               const double* node_side_dev, const float* rec_dev, int32_t n_ids, int32_t n_buckets,
+                               const int32_t* bucket_node_dev, double theta, int32_t* n_first_dev,
+                               int32_t* r_first_dev, int32_t* node_idx_dev, int64_t node_cap, int32_t* ranges_dev,
+                               int64_t range_cap, int64_t* totals, void* stream);
+
 /* ---------------------------------------------------------------- graphs */
 
 /*

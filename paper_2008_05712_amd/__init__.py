@@ -44,7 +44,7 @@ EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_debug_i
             "gc_graph_capture", "gc_graph_launch", "gc_graph_destroy", "gc_autotune", "gc_occupancy",
             "gc_launch_ewald", "gc_hybrid_create", "gc_hybrid_destroy", "gc_hybrid_record", "gc_hybrid_split",
             "gc_hybrid_state", "gc_lj_forces_cpu", "gc_combiner_create", "gc_combiner_destroy", "gc_combiner_arrive", "gc_combiner_poll", "gc_combiner_state",
-            "gc_tree_walk"]
+            "gc_tree_walk", "gc_tree_walk_noalloc"]
 
 
 class EwaldParams(ctypes.Structure):
@@ -150,6 +150,8 @@ def lib():
         "gc_combiner_state": (I32, [VP, PI64, ctypes.POINTER(ctypes.c_double), PI64, PI64]),
         "gc_tree_walk": (I32, [VP, I32, VP, VP, VP, VP, I32, I32, VP, ctypes.c_double, VP, VP, VP, I64, VP, I64,
                                PI64, VP]),
+        "gc_tree_walk_noalloc": (I32, [VP, I32, VP, VP, VP, VP, I32, I32, VP, ctypes.c_double, VP, VP, VP, I64, VP,
+                                       I64, PI64, VP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -340,10 +342,14 @@ def lj_forces_cpu(tasks: np.ndarray, ranges: np.ndarray, rec: np.ndarray, eps_t,
         raise GcError(st, "gc_lj_forces_cpu")
 
 
-def tree_walk(ctx: "Context", node_range, node_com, node_side, rec, bucket_node, theta: float, stream=None):
-    """Barnes-Hut lists of every bucket on the device (gc_tree_walk); device tensors in, device tensors
-    out: (n_first int32 [nb + 1], node_idx int32, r_first int32 [nb + 1], ranges int32 [., 2])."""
+def tree_walk(ctx: "Context", node_range, node_com, node_side, rec, bucket_node, theta: float, stream=None,
+              noalloc: bool = False):
+    """Barnes-Hut lists of every bucket on the device (gc_tree_walk, or gc_tree_walk_noalloc); device
+    tensors in, device tensors out: (n_first int32 [nb + 1], node_idx int32, r_first int32 [nb + 1],
+    ranges int32 [., 2])."""
     import torch
+    fn = lib().gc_tree_walk_noalloc if noalloc else lib().gc_tree_walk
+    name = "gc_tree_walk_noalloc" if noalloc else "gc_tree_walk"
     dev = node_range.device
     nb = int(bucket_node.numel())
     n_first = torch.empty(nb + 1, dtype=torch.int32, device=dev)
@@ -351,16 +357,15 @@ def tree_walk(ctx: "Context", node_range, node_com, node_side, rec, bucket_node,
     totals = (ctypes.c_int64 * 2)()
     args = (ctx.h, int(node_range.shape[0]), _ptr(node_range), _ptr(node_com), _ptr(node_side), _ptr(rec),
             int(rec.shape[0]), nb, _ptr(bucket_node), float(theta), _ptr(n_first), _ptr(r_first))
-    st = lib().gc_tree_walk(*args, None, 0, None, 0, totals, _stream(stream))
+    st = fn(*args, None, 0, None, 0, totals, _stream(stream))
     if st == GC_E_FULL:  # sized by the first call's counts
         node_idx = torch.empty(max(totals[0], 1), dtype=torch.int32, device=dev)
         ranges = torch.empty((max(totals[1], 1), 2), dtype=torch.int32, device=dev)
-        st = lib().gc_tree_walk(*args, _ptr(node_idx), int(totals[0]), _ptr(ranges), int(totals[1]), totals,
-                                _stream(stream))
+        st = fn(*args, _ptr(node_idx), int(totals[0]), _ptr(ranges), int(totals[1]), totals, _stream(stream))
     else:
         node_idx = torch.empty(1, dtype=torch.int32, device=dev)
         ranges = torch.empty((1, 2), dtype=torch.int32, device=dev)
-    ctx.check(st, "gc_tree_walk")
+    ctx.check(st, name)
     return n_first, node_idx[:totals[0]], r_first, ranges[:totals[1]]
 
 

@@ -6,6 +6,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -77,6 +79,7 @@ struct gc_ctx_ {
   std::string err;
   AllocHooks hooks;
   DevBuf walk_keep;  // the list walk's per-bucket room, kept between calls
+  void* walk_scratch = nullptr;  // device address of this device's fixed walk scratch (no-allocation walk)
   // test hook for the whole-step schedule, taken by the next capture: a round whose force items wait
   // for a count that is never reached (-1: none), and the bound on those waits (0: the default)
   int32_t step_fail_round = -1;
@@ -188,6 +191,8 @@ struct gc_graph_ {
 
 // ===================================================================== context
 
+static hipError_t walk_scratch_address(void** out);
+
 extern "C" const char* gc_version(void) { return "gcharm-mi355x 0.1 (gfx950)"; }
 
 extern "C" gc_status gc_init(int device, gc_alloc_fn alloc_fn, gc_free_fn free_fn, void* user, gc_ctx* out) {
@@ -212,6 +217,11 @@ extern "C" gc_status gc_init(int device, gc_alloc_fn alloc_fn, gc_free_fn free_f
     return GC_E_HIP;
   }
   c->n_cu = p.multiProcessorCount;
+  e = walk_scratch_address(&c->walk_scratch);
+  if (e != hipSuccess) {
+    delete c;
+    return GC_E_HIP;
+  }
   *out = c;
   return GC_OK;
 }
@@ -1713,44 +1723,21 @@ struct ScopedBuf {  // device scratch of one call, freed on every return path
 };
 }  // namespace
 
-extern "C" gc_status gc_tree_walk(gc_ctx c, int32_t n_nodes, const int32_t* node_range_dev, const double* node_com_dev,
-                                  const double* node_side_dev, const float* rec_dev, int32_t n_ids, int32_t n_buckets,
-                                  const int32_t* bucket_node_dev, double theta, int32_t* n_first_dev,
-                                  int32_t* r_first_dev, int32_t* node_idx_dev, int64_t node_cap, int32_t* ranges_dev,
-                                  int64_t range_cap, int64_t* totals, void* stream) {
-  if (!c) return GC_E_INVAL;
-  GC_ENTER(c);
-  if (!totals) return set_err(c, GC_E_INVAL, "gc_tree_walk: NULL totals");
-  totals[0] = totals[1] = 0;
-  if (n_nodes < 0 || n_buckets < 0 || n_ids < 0 || node_cap < 0 || range_cap < 0 || !(theta >= 0.0))
-    return set_err(c, GC_E_INVAL, "gc_tree_walk: negative size or theta");
-  if (n_buckets > 0 && (!n_first_dev || !r_first_dev || !bucket_node_dev))
-    return set_err(c, GC_E_INVAL, "gc_tree_walk: NULL bucket argument");
-  if (n_nodes > 0 && (!node_range_dev || !node_com_dev || !node_side_dev || (n_ids > 0 && !rec_dev)))
-    return set_err(c, GC_E_INVAL, "gc_tree_walk: NULL node argument");
-  hipStream_t s = S(stream);
-  if (n_buckets == 0) return GC_OK;
-  if (n_nodes == 0) {  // no tree: every bucket's lists are empty
-    GC_HIP(c, launch_fill_i32(n_first_dev, 0, (int64_t)n_buckets + 1, s));
-    GC_HIP(c, launch_fill_i32(r_first_dev, 0, (int64_t)n_buckets + 1, s));
-    return GC_OK;
-  }
-  ScopedBuf skip(c), tot(c);
-  if (skip.d.ensure(sizeof(int32_t) * (size_t)n_nodes) != hipSuccess || tot.d.ensure(256) != hipSuccess)
-    return set_err(c, GC_E_NOMEM, "gc_tree_walk: scratch");
-  // room for each bucket's lists in the count pass, kept by the context (without it every bucket is
-  // walked twice)
-  DevBuf& keep = c->walk_keep;
-  const size_t keep_n = sizeof(int32_t) * kWalkCapNodes * (size_t)n_buckets;
-  const bool kept = keep.ensure(keep_n + sizeof(int2) * kWalkCapRanges * (size_t)n_buckets) == hipSuccess;
-  if (!kept) (void)hipGetLastError();
-  long long* dtot = tot.d.as<long long>();  // totals[0..1], then the invalid-bucket count
-  GC_HIP(c, launch_fill_i32(tot.d.as<int32_t>(), 0, 6, s));
+// The walk proper, on scratch the caller provides: skip (int32 [n_nodes]), tot (3 int64: the two
+// totals and the invalid-bucket count), and optionally each bucket's room of the count pass (sn / sr,
+// nullptr: every bucket is walked twice).
+static gc_status tree_walk_impl(gc_ctx c, int32_t n_nodes, const int32_t* node_range_dev,
+                                const double* node_com_dev, const double* node_side_dev, const float* rec_dev,
+                                int32_t n_ids, int32_t n_buckets, const int32_t* bucket_node_dev, double theta,
+                                int32_t* n_first_dev, int32_t* r_first_dev, int32_t* node_idx_dev, int64_t node_cap,
+                                int32_t* ranges_dev, int64_t range_cap, int64_t* totals, int32_t* skip,
+                                long long* dtot, int32_t* sn, int2* sr, hipStream_t s) {
+  GC_HIP(c, launch_fill_i32(reinterpret_cast<int32_t*>(dtot), 0, 6, s));
   WalkArgs a{};
   a.range = reinterpret_cast<const int2*>(node_range_dev);
   a.com = node_com_dev;
   a.side = node_side_dev;
-  a.skip = skip.d.as<int32_t>();
+  a.skip = skip;
   a.rec = reinterpret_cast<const float4*>(rec_dev);
   a.bucket_node = bucket_node_dev;
   a.n_nodes = n_nodes;
@@ -1762,9 +1749,9 @@ extern "C" gc_status gc_tree_walk(gc_ctx c, int32_t n_nodes, const int32_t* node
   a.node_idx = node_idx_dev;
   a.ranges = ranges_dev;
   a.bad = reinterpret_cast<unsigned long long*>(dtot + 2);
-  a.sn = kept ? keep.as<int32_t>() : nullptr;
-  a.sr = kept ? reinterpret_cast<int2*>(keep.as<char>() + keep_n) : nullptr;
-  GC_HIP(c, launch_subtree_end(a.range, n_nodes, skip.d.as<int32_t>(), s));
+  a.sn = sn;
+  a.sr = sr;
+  GC_HIP(c, launch_subtree_end(a.range, n_nodes, skip, s));
   GC_HIP(c, launch_walk(false, a, s));
   GC_HIP(c, launch_scan_counts(n_first_dev, r_first_dev, n_buckets, dtot, s));
   long long h[3] = {0, 0, 0};
@@ -1780,6 +1767,115 @@ extern "C" gc_status gc_tree_walk(gc_ctx c, int32_t n_nodes, const int32_t* node
                    h[1], (long long)node_cap, (long long)range_cap);
   GC_HIP(c, launch_walk_copy(a, s));
   GC_HIP(c, launch_walk(true, a, s));
-  GC_HIP(c, hipStreamSynchronize(s));  // the scratch is freed on return
+  GC_HIP(c, hipStreamSynchronize(s));  // the scratch is released or reused on return
   return GC_OK;
+}
+
+// Argument checks shared by both entry points; *done is set when there is nothing to walk.
+static gc_status tree_walk_args(gc_ctx c, int32_t n_nodes, const int32_t* node_range_dev, const double* node_com_dev,
+                                const double* node_side_dev, const float* rec_dev, int32_t n_ids, int32_t n_buckets,
+                                const int32_t* bucket_node_dev, double theta, int32_t* n_first_dev,
+                                int32_t* r_first_dev, int64_t node_cap, int64_t range_cap, int64_t* totals,
+                                hipStream_t s, bool* done) {
+  *done = false;
+  if (!totals) return set_err(c, GC_E_INVAL, "gc_tree_walk: NULL totals");
+  totals[0] = totals[1] = 0;
+  if (n_nodes < 0 || n_buckets < 0 || n_ids < 0 || node_cap < 0 || range_cap < 0 || !(theta >= 0.0))
+    return set_err(c, GC_E_INVAL, "gc_tree_walk: negative size or theta");
+  if (n_buckets > 0 && (!n_first_dev || !r_first_dev || !bucket_node_dev))
+    return set_err(c, GC_E_INVAL, "gc_tree_walk: NULL bucket argument");
+  if (n_nodes > 0 && (!node_range_dev || !node_com_dev || !node_side_dev || (n_ids > 0 && !rec_dev)))
+    return set_err(c, GC_E_INVAL, "gc_tree_walk: NULL node argument");
+  if (n_buckets == 0) {
+    *done = true;
+    return GC_OK;
+  }
+  if (n_nodes == 0) {  // no tree: every bucket's lists are empty
+    GC_HIP(c, launch_fill_i32(n_first_dev, 0, (int64_t)n_buckets + 1, s));
+    GC_HIP(c, launch_fill_i32(r_first_dev, 0, (int64_t)n_buckets + 1, s));
+    *done = true;
+  }
+  return GC_OK;
+}
+
+extern "C" gc_status gc_tree_walk(gc_ctx c, int32_t n_nodes, const int32_t* node_range_dev, const double* node_com_dev,
+                                  const double* node_side_dev, const float* rec_dev, int32_t n_ids, int32_t n_buckets,
+                                  const int32_t* bucket_node_dev, double theta, int32_t* n_first_dev,
+                                  int32_t* r_first_dev, int32_t* node_idx_dev, int64_t node_cap, int32_t* ranges_dev,
+                                  int64_t range_cap, int64_t* totals, void* stream) {
+  if (!c) return GC_E_INVAL;
+  GC_ENTER(c);
+  hipStream_t s = S(stream);
+  bool done = false;
+  gc_status st = tree_walk_args(c, n_nodes, node_range_dev, node_com_dev, node_side_dev, rec_dev, n_ids, n_buckets,
+                                bucket_node_dev, theta, n_first_dev, r_first_dev, node_cap, range_cap, totals, s, &done);
+  if (st != GC_OK || done) return st;
+  ScopedBuf skip(c), tot(c);
+  if (skip.d.ensure(sizeof(int32_t) * (size_t)n_nodes) != hipSuccess || tot.d.ensure(256) != hipSuccess)
+    return set_err(c, GC_E_NOMEM, "gc_tree_walk: scratch");
+  // room for each bucket's lists in the count pass, kept by the context (without it every bucket is
+  // walked twice)
+  DevBuf& keep = c->walk_keep;
+  const size_t keep_n = sizeof(int32_t) * kWalkCapNodes * (size_t)n_buckets;
+  const bool kept = keep.ensure(keep_n + sizeof(int2) * kWalkCapRanges * (size_t)n_buckets) == hipSuccess;
+  if (!kept) (void)hipGetLastError();
+  return tree_walk_impl(c, n_nodes, node_range_dev, node_com_dev, node_side_dev, rec_dev, n_ids, n_buckets,
+                        bucket_node_dev, theta, n_first_dev, r_first_dev, node_idx_dev, node_cap, ranges_dev,
+                        range_cap, totals, skip.d.as<int32_t>(), tot.d.as<long long>(),
+                        kept ? keep.as<int32_t>() : nullptr,
+                        kept ? reinterpret_cast<int2*>(keep.as<char>() + keep_n) : nullptr, s);
+}
+
+// ---------------------------------------------------------------- the walk without allocation
+
+// Scratch of gc_tree_walk_noalloc: the totals (bytes [0, 256)), then skip (int32 per node).  One copy
+// per device, held until the process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host it names a host-side stand-in): the context looks up its device address at gc_init.
+static __device__ __align__(256) unsigned char scratch[kWalkScratchBytes];
+
+// Device address of the current device's copy of `scratch`, looked up once per device (with that
+// device current) and kept for the life of the process.
+static hipError_t walk_scratch_address(void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> by_device;
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = by_device.find(dev);
+  if (it != by_device.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  by_device[dev] = ptr;
+  *out = ptr;
+  return hipSuccess;
+}
+
+extern "C" gc_status gc_tree_walk_noalloc(gc_ctx c, int32_t n_nodes, const int32_t* node_range_dev,
+                                          const double* node_com_dev, const double* node_side_dev,
+                                          const float* rec_dev, int32_t n_ids, int32_t n_buckets,
+                                          const int32_t* bucket_node_dev, double theta, int32_t* n_first_dev,
+                                          int32_t* r_first_dev, int32_t* node_idx_dev, int64_t node_cap,
+                                          int32_t* ranges_dev, int64_t range_cap, int64_t* totals, void* stream) {
+  if (!c) return GC_E_INVAL;
+  GC_ENTER(c);
+  if (n_nodes > kWalkNoAllocMaxNodes)
+    return set_err(c, GC_E_INVAL, "gc_tree_walk_noalloc: %d nodes exceed the fixed scratch (at most %d)", n_nodes,
+                   kWalkNoAllocMaxNodes);
+  if (!c->walk_scratch) return set_err(c, GC_E_STATE, "gc_tree_walk_noalloc: no scratch address for this device");
+  hipStream_t s = S(stream);
+  bool done = false;
+  gc_status st = tree_walk_args(c, n_nodes, node_range_dev, node_com_dev, node_side_dev, rec_dev, n_ids, n_buckets,
+                                bucket_node_dev, theta, n_first_dev, r_first_dev, node_cap, range_cap, totals, s, &done);
+  if (st != GC_OK || done) return st;
+  unsigned char* base = static_cast<unsigned char*>(c->walk_scratch);
+  return tree_walk_impl(c, n_nodes, node_range_dev, node_com_dev, node_side_dev, rec_dev, n_ids, n_buckets,
+                        bucket_node_dev, theta, n_first_dev, r_first_dev, node_idx_dev, node_cap, ranges_dev,
+                        range_cap, totals, reinterpret_cast<int32_t*>(base + 256), reinterpret_cast<long long*>(base),
+                        nullptr, nullptr, s);
 }

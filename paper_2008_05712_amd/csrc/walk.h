@@ -28,6 +28,10 @@ struct WalkArgs {
 // Per-bucket room of the count pass's copy of the lists; a bucket with more is walked again.
 constexpr int kWalkCapNodes = 2048;
 constexpr int kWalkCapRanges = 128;
+// The walk without allocation: its scratch (256 bytes of totals, then 4 bytes per node) is a fixed
+// device array of 8 MiB + 256 bytes, so trees of up to 2^21 nodes.
+constexpr int kWalkNoAllocMaxNodes = 1 << 21;
+constexpr size_t kWalkScratchBytes = 256 + sizeof(int32_t) * (size_t)kWalkNoAllocMaxNodes;
 
 hipError_t launch_subtree_end(const int2* range, int32_t n_nodes, int32_t* skip, hipStream_t s);
 hipError_t launch_walk(bool fill, const WalkArgs& a, hipStream_t s);

@@ -162,6 +162,11 @@ def leg_instances(gc, W, torch, ctx, args):
                          "ginteractions_per_s": round(inter / (best[0] * 1e-3) / 1e9, 3),
                          "tflops": round(flops / (best[0] * 1e-3) / 1e12, 3)},
                 "speedup_vs_per_instance": round(base / best[0], 3)})
+    bt = flops / (best[0] * 1e-3) / 1e12
+    res["roofline"] = {"bound": "alu", "achieved": round(bt, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(bt / PEAK_FP32_TFLOPS, 4), "flops_per_launch": int(flops),
+                       "kernel": f"best form: aggregation {best[1]}, schedule {best[2]} (all 64 instances per replay)",
+                       "frac_of_nonpacked_peak": round(bt / PEAK_FP32_NONPACKED_TFLOPS, 4)}
     pool.destroy()
     return res
 
@@ -205,6 +210,14 @@ def leg_lj(gc, W, torch, ctx):
     issue_ms = evals * LJ_VALU_PER_EVAL / 64 * 4 / (N_SIMD * CLOCK_GHZ * 1e9) * 1e3
     out.update({"pair_evaluations": evals, "valu_issue_ms": round(issue_ms, 4),
                 "valu_issue_frac": round(issue_ms / ms, 4)})
+    # the algorithmic work: pairs inside the cutoff (counted on the device with the pass's FP32
+    # decision), FLOPS_LJ flop each with both atoms updated
+    pairs = b.lj_count_pairs(w.rcut)
+    lj_tflops = pairs * FLOPS_LJ / (ms * 1e-3) / 1e12
+    out.update({"in_cutoff_pairs": pairs, "pairs_per_s_G": round(pairs / (ms * 1e-3) / 1e9, 3),
+                "evaluations_per_in_cutoff_pair": round(evals / pairs, 3),
+                "candidates_per_in_cutoff_pair": round(cand / pairs, 3),
+                "algorithmic_tflops": round(lj_tflops, 3), "algorithmic_frac": round(lj_tflops / PEAK_FP32_TFLOPS, 4)})
     b.destroy()
     pool.destroy()
     return out
@@ -338,6 +351,216 @@ def leg_adjoint(gc, W, torch, ctx):
     return res
 
 
+def leg_reorg_stress(gc, torch, ctx, log2_pool: int = 26, log2_union: int = 24, reps: int = 5):
+    """The reorganisation at HBM scale: a pool and id space of 2^26 records (1 GiB each for the pool and
+    the source), a request whose union is 2^24 ids (2^18 runs of 64 consecutive ids at uniformly random
+    run positions), half of it resident at uniformly random slots; each call stages the other half and
+    packs all 2^24 records (PACK), after the previous call's staging is evicted."""
+    n = 1 << log2_pool
+    nu = 1 << log2_union
+    run = 64
+    rng = np.random.default_rng(6000)
+    starts = np.sort(rng.choice(n // run, size=nu // run, replace=False)).astype(np.int64) * run
+    ic = np.full(starts.size, run, np.int32)
+    z = np.zeros(starts.size, np.int32)
+    t = gc.tasks_from_csr(starts.astype(np.int32), ic, z, z)
+    union = (starts[:, None] + np.arange(run)[None, :]).reshape(-1)
+    res_ids = np.sort(rng.choice(union, size=nu // 2, replace=False)).astype(np.int32)
+    res_slots = rng.choice(n, size=nu // 2, replace=False).astype(np.int32)
+    dev = torch.device("cuda")
+    src = torch.rand((n, 4), device=dev)
+    pool = gc.Pool(ctx, n, n)
+    pool.set_source(src)
+    pool.place(torch.from_numpy(res_ids).to(dev), torch.from_numpy(res_slots).to(dev))
+    b = gc.Batch(ctx, gc.KIND_GRAV, n)
+    b.submit(t, np.zeros((0, 2), np.int32))
+    b.commit()
+    stream = torch.cuda.current_stream()
+    b.reorganize(pool, gc.REORG_PACK, check_capacity=True)
+    torch.cuda.synchronize()
+    missing = int(b.maps()["missing"].size)
+    ms = 0.0
+    for _ in range(reps):
+        pool.evict_staged(b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.reorganize(pool, gc.REORG_PACK, check_capacity=False)
+        e1.record(stream)
+        e1.synchronize()
+        ms += e0.elapsed_time(e1) / reps
+    b.status()
+    # algorithmic bytes: per union entry the record read and the packed write (16 + 16), its id (4) and
+    # its chare-table entry (4); per missing record the staged write into its slot (16).  The
+    # occupancy scan, the chare-table and occupancy updates and the missing lists are implementation
+    # traffic, reported beside it
+    alg = nu * (16 + 16 + 4 + 4) + missing * 16
+    impl = nu * 4 + missing * (4 + 4 + 8) + n * 4
+    b.destroy()
+    pool.destroy()
+    del src
+    gbps = alg / (ms * 1e-3) / 1e9
+    return {"workload": f"pool 2^{log2_pool} records, union 2^{log2_union} ids (runs of {run}), half resident "
+                        f"at random slots, PACK", "kernel": "k_reorg", "ms": round(ms, 4), "union": nu,
+            "missing": missing, "algorithmic_bytes": int(alg), "implementation_bytes": int(impl),
+            "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                         "frac": round(gbps / PEAK_HBM_GBPS, 4)},
+            "gbps_incl_implementation_bytes": round((alg + impl) / (ms * 1e-3) / 1e9, 1)}
+
+
+def leg_staging(gc, W, torch, ctx, w, rounds, prm, nodes, steps: int = 10):
+    """The irregular workload with its records in ordinary host memory: every round the host finds the
+    missing records in its mirror of the chare table, packs them into pinned memory and copies them in
+    on a side stream (the copy of one round overlaps the pass of the round before); the same with the
+    copies on the compute stream (no overlap); and redundant transfers (every record of each round's
+    union copied each round).  Wall time per step, PCIe bytes per step."""
+    dev = torch.device("cuda")
+    host = np.ascontiguousarray(w.rec, dtype=np.float32)
+    acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
+    pool = gc.Pool(ctx, w.n, w.n)
+    pool.set_host_source(host)
+    bids, bslots = W.residency(np.arange(w.n, dtype=np.int32), w.n, 0.5, seed=5000)
+    pool.reset()
+    pool.place(torch.from_numpy(bids).to(dev), torch.from_numpy(bslots).to(dev))
+    batches = []
+    for r in rounds:
+        bt = W.task_subset(w, r)
+        b = gc.Batch(ctx, gc.KIND_GRAV, w.n)
+        b.submit(gc.tasks_from_csr(bt["i_begin"], bt["i_count"], bt["j_first"], bt["j_nr"], bt["n_first"],
+                                   bt["n_count"]), bt["ranges"], bt["node_idx"])
+        b.commit()
+        batches.append(b)
+    side = torch.cuda.Stream()
+
+    def one(mode, use_side):
+        for k, b in enumerate(batches):
+            pool.evict_staged(batches[k - 1])
+            b.reorganize(pool, mode, check_capacity=False, side=side if use_side else None)
+            b.launch(prm, nodes, acc)
+
+    out = {"workload": f"nbody-plummer-{w.n}, {len(rounds)} rounds, source records in pageable host memory"}
+    for name, mode, use_side in (("pack_side_stream", gc.REORG_PACK, True), ("pack_one_stream", gc.REORG_PACK, False),
+                                 ("redundant_side_stream", gc.REORG_REDUNDANT, True)):
+        for _ in range(2):
+            one(mode, use_side)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one(mode, use_side)
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+    sizes = []
+    for b in batches:
+        m = b.maps()
+        sizes.append((int(m["U"].size), int(m["missing"].size)))
+    pool.evict_staged(batches[-1])
+    # the last reorganisation of each batch above was REDUNDANT; one PACK pass for the missing counts
+    one(gc.REORG_PACK, True)
+    torch.cuda.synchronize()
+    miss = [int(b.maps()["missing"].size) for b in batches]
+    pool.evict_staged(batches[-1])
+    unions = [u for u, _ in sizes]
+    out.update({"pcie_bytes_per_step_pack": 16 * sum(miss), "pcie_bytes_per_step_redundant": 16 * sum(unions),
+                "transfer_reduction": round(1 - sum(miss) / sum(unions), 4),
+                "overlap_gain": round(out["pack_one_stream_ms"] / out["pack_side_stream_ms"], 3)})
+    for b in batches:
+        b.status()
+        b.destroy()
+    pool.destroy()
+    return out
+
+
+def leg_rebuild(gc, W, torch, ctx, w, rounds, prm, steps: int = 5):
+    """A step whose lists are rebuilt: the device list walk of every bucket, each round's tasks made
+    from the walk's output and committed on the device (union and positions by mark and scan), then
+    the rounds' reorganisations (PACK, half of all ids resident at random slots, each round evicting
+    the staging of the one before) and combined passes.  Against it: the same step with the walk's
+    lists copied to the host and each round submitted and committed there."""
+    dev = torch.device("cuda")
+    src = torch.from_numpy(w.rec).to(dev)
+    nodes = torch.from_numpy(w.nodes).to(dev)
+    acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
+    pool = gc.Pool(ctx, w.n, w.n)
+    pool.set_source(src)
+    bids, bslots = W.residency(np.arange(w.n, dtype=np.int32), w.n, 0.5, seed=5000)
+    pool.reset()
+    pool.place(torch.from_numpy(bids).to(dev), torch.from_numpy(bslots).to(dev))
+    targs = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in
+             (w.node_range.astype(np.int32), w.node_mom64[:, :3], w.node_side, w.rec, w.meta["leaf"].astype(np.int32))]
+    bounds_h = np.array([int(r[0]) for r in rounds] + [w.n_tasks], np.int64)
+    bounds = torch.from_numpy(bounds_h).to(dev)
+    n_nodes = int(w.nodes.shape[0])
+    batches = [gc.Batch(ctx, gc.KIND_GRAV, w.n) for _ in rounds]
+    phase = {"walk": 0.0, "commit": 0.0, "pass": 0.0}
+    # the walk's outputs, sized once (the tree does not change between steps)
+    nf, nidx, rf, rng = gc.tree_walk(ctx, *targs, w.theta)
+    nb = int(targs[4].numel())
+    totals = (ctypes.c_int64 * 2)()
+
+    def walk():
+        ctx.check(gc.lib().gc_tree_walk(
+            ctx.h, int(targs[0].shape[0]), targs[0].data_ptr(), targs[1].data_ptr(), targs[2].data_ptr(),
+            targs[3].data_ptr(), int(targs[3].shape[0]), nb, targs[4].data_ptr(), float(w.theta), nf.data_ptr(),
+            rf.data_ptr(), nidx.data_ptr(), int(nidx.numel()), rng.data_ptr(), int(rng.shape[0]), totals,
+            torch.cuda.current_stream().cuda_stream), "gc_tree_walk")
+
+    def passes():
+        for k, b in enumerate(batches):
+            if k:
+                pool.evict_staged(batches[k - 1])
+            b.reorganize(pool, gc.REORG_PACK, check_capacity=False)
+            b.launch(prm, nodes, acc)
+        pool.evict_staged(batches[-1])
+
+    def step_device(timed=False):
+        t0 = time.perf_counter()
+        walk()
+        bh = torch.stack([nf[bounds], rf[bounds]]).cpu().numpy()
+        t1 = time.perf_counter()
+        for k, b in enumerate(batches):
+            b0, b1 = int(bounds_h[k]), int(bounds_h[k + 1])
+            tasks = gc.walk_tasks(ctx, b0, b1, targs[4], targs[0], nf, rf)
+            b.reset()
+            b.submit_device(tasks, rng[bh[1, k]:bh[1, k + 1]], nidx[bh[0, k]:bh[0, k + 1]], n_nodes)
+            b.commit()
+        t2 = time.perf_counter()
+        passes()
+        torch.cuda.synchronize()
+        if timed:
+            phase["walk"] += t1 - t0
+            phase["commit"] += t2 - t1
+            phase["pass"] += time.perf_counter() - t2
+
+    def step_host():
+        walk()
+        nfh, rfh, nih, rgh = nf.cpu().numpy(), rf.cpu().numpy(), nidx.cpu().numpy(), rng.cpu().numpy()
+        leaf = w.meta["leaf"]
+        for k, b in enumerate(batches):
+            b0, b1 = int(bounds_h[k]), int(bounds_h[k + 1])
+            lv = leaf[b0:b1]
+            t = gc.tasks_from_csr(w.node_range[lv, 0], w.node_range[lv, 1], rfh[b0:b1] - rfh[b0],
+                                  np.diff(rfh[b0:b1 + 1]), nfh[b0:b1] - nfh[b0], np.diff(nfh[b0:b1 + 1]))
+            b.reset()
+            b.submit(t, rgh[rfh[b0]:rfh[b1]], nih[nfh[b0]:nfh[b1]])
+            b.commit()
+        passes()
+        torch.cuda.synchronize()
+
+    out = {"workload": f"nbody-plummer-{w.n}: {w.n_tasks} buckets in {len(rounds)} rounds, walk theta {w.theta}"}
+    for name, fn in (("device", step_device), ("host", step_host)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn(True) if name == "device" else fn()
+        out[f"step_with_rebuild_{name}_commit_ms"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+    out["device_phases_ms"] = {k: round(v * 1e3 / steps, 4) for k, v in phase.items()}
+    for b in batches:
+        b.status()
+        b.destroy()
+    pool.destroy()
+    return out
+
+
 def cpu_baseline(W, w, rounds, args):
     """The FP64 oracle on a bounded sample of the same rounds (host cores)."""
     import oracle as O
@@ -382,6 +605,8 @@ def main():
     ap.add_argument("--targets-per-lane", type=int, default=0, help="with --tile: 1 or 2 targets per lane")
     ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 256, 320 and 384")
     ap.add_argument("--step-tpl", type=int, default=0, help="fixed targets per lane of the whole-step launch instead of timing 1 and 2")
+    ap.add_argument("--leg", default="", choices=["", "reorg-stress", "staging", "rebuild", "lj", "instances"],
+                    help="run one measurement leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): there is no multi-GPU path", file=sys.stderr)
@@ -397,6 +622,13 @@ def main():
                  redundant=gc.REORG_REDUNDANT, none=gc.REORG_NONE)
     mode = modes[args.mode]
 
+    if args.leg in ("reorg-stress", "lj", "instances"):
+        ctx = gc.Context(0)
+        fn = {"reorg-stress": lambda: leg_reorg_stress(gc, torch, ctx), "lj": lambda: leg_lj(gc, W, torch, ctx),
+              "instances": lambda: leg_instances(gc, W, torch, ctx, args)}[args.leg]
+        print(json.dumps({"leg": args.leg, **fn()}), flush=True)
+        ctx.close()
+        return
     t0 = time.time()
     w = W.nbody_plummer(n=args.n, seed=1002)
     rounds = W.poisson_rounds(w.n_tasks, 2048, seed=1002)
@@ -409,6 +641,13 @@ def main():
     dev = torch.device("cuda")
     src = torch.from_numpy(w.rec).to(dev)
     nodes = torch.from_numpy(w.nodes).to(dev)
+    if args.leg in ("staging", "rebuild"):
+        p2 = gc.grav_params(order=2, G=1.0, eps=0.01, tile=320, targets_per_lane=2)
+        out = leg_staging(gc, W, torch, ctx, w, rounds, p2, nodes) if args.leg == "staging" else \
+            leg_rebuild(gc, W, torch, ctx, w, rounds, p2)
+        print(json.dumps({"leg": args.leg, **out}), flush=True)
+        ctx.close()
+        return
     acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
     cap = w.n
     pool = gc.Pool(ctx, w.n, cap)
@@ -448,13 +687,15 @@ def main():
         big = int(np.argmax([len(r) for r in rounds]))
         base_state()
         batches[big].reorganize(pool, mode, check_capacity=False)
-        best, times = batches[big].autotune(gc.grav_params(order=2, G=1.0, eps=0.01), nodes, acc, reps=3)
+        best, times, _ = batches[big].autotune(gc.grav_params(order=2, G=1.0, eps=0.01), nodes, acc, reps=3)
         prm = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=best.schedule, tile=best.tile,
-                             waves_per_block=best.waves_per_block, targets_per_lane=best.targets_per_lane)
+                             waves_per_block=best.waves_per_block, targets_per_lane=best.targets_per_lane,
+                             aggregation=best.aggregation)
         # candidate 16 is the default shape: tile 256, 4 waves, one block per task, one target per lane
         tuned = dict(tile=best.tile, waves_per_block=best.waves_per_block, schedule=best.schedule,
-                     targets_per_lane=best.targets_per_lane, ms=round(float(times.min()), 5),
-                     default_shape_ms=round(float(times[16]), 5))
+                     targets_per_lane=best.targets_per_lane, aggregation=best.aggregation,
+                     ms=round(float(np.nanmin(times)), 5), default_shape_ms=round(float(times[16]), 5),
+                     aggregation_ms=[round(float(x), 5) for x in times[36:]])
         log(f"[bench] autotuned: {tuned}")
 
     def one_pass(m, timed=None):
@@ -659,6 +900,9 @@ def main():
         extra["ewald"] = leg_ewald(gc, W, torch, ctx)
         extra["adjoint"] = leg_adjoint(gc, W, torch, ctx)
         extra["tree_walk"] = leg_walk(gc, W, torch, ctx, w)
+        extra["rebuild"] = leg_rebuild(gc, W, torch, ctx, w, rounds, prm)
+        extra["staging"] = leg_staging(gc, W, torch, ctx, w, rounds, prm, nodes)
+        extra["reorg_stress"] = leg_reorg_stress(gc, torch, ctx)
 
     form_text = {"step": "one whole-step persistent launch (HIP graph) per step",
                  "rounds": "one HIP graph of per-round launches per step", "eager": "per-round launches"}[form]

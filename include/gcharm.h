@@ -117,11 +117,41 @@ gc_status gc_pool_destroy(gc_pool pool);
 gc_status gc_pool_set_source(gc_pool pool, const void* records);
 
 /*
+ * Host source with staging copies (Sec. 2.2: the runtime copies to the
+ * device only the data a request needs that is not already there; Sec. 3.2:
+ * the chare table tells the runtime which buffers are resident).  `records`
+ * holds n_ids float4 records by id in ordinary host memory (pageable or
+ * pinned), caller-owned; it is read only during gc_pool_place and
+ * gc_reorganize calls, never afterwards.  Replaces a source set by
+ * gc_pool_set_source.  The pool then keeps a host mirror of its chare table,
+ * updated by every call in call order with the device's own allocation rule
+ * (the k-th missing id takes the k-th lowest free slot), so a reorganisation
+ * knows its missing records without reading the device; the host packs them
+ * into a pinned staging buffer that gc_reorganize copies in on its side
+ * stream.  The mirror is read back from the device once (synchronising) when
+ * the device changed the table without the host (a reorganisation from a
+ * device source, a graph launch, a place or evict issued before the host
+ * source was set).  Such a pool cannot be captured in a graph
+ * (GC_E_UNSUPPORTED), and NONE reorganisations, Lennard-Jones passes and
+ * backward calls need a device source.
+ */
+gc_status gc_pool_set_host_source(gc_pool pool, const void* records);
+
+/*
+ * The host mirror of a host-source pool's chare table (n_ids int32, -1 = not
+ * resident) copied to slot_of_host; equals gc_pool_query once the device has
+ * run every call made so far.  GC_E_STATE without a host source.
+ */
+gc_status gc_pool_query_mirror(gc_pool pool, int32_t* slot_of_host, void* stream);
+
+/*
  * Residency fixture: make ids[k] resident in slots[k] (device int32 arrays of
  * length n), copying their records from the source.  Ids must be distinct,
  * not yet resident, and slots distinct and free; violations are not detected
  * on the device (the host does not see the arrays) and leave the table
- * inconsistent.  Asynchronous on `stream`.
+ * inconsistent.  Asynchronous on `stream`, except with a host source: the
+ * host then reads ids and slots (synchronising `stream`), rejects ids or
+ * slots out of range with GC_E_INVAL, and copies the records in.
  */
 gc_status gc_pool_place(gc_pool pool, const int32_t* ids_dev, const int32_t* slots_dev, int32_t n, void* stream);
 
@@ -132,7 +162,8 @@ gc_status gc_pool_reset(gc_pool pool, void* stream);
  * Evict ids_dev[0, n) (device int32): each resident id leaves the table and
  * its slot becomes free; ids outside [0, n_ids) or not resident are skipped.
  * The record data stay in the slot until a later staging overwrites them.
- * Asynchronous on `stream`.
+ * Asynchronous on `stream` (a host-source pool with a current mirror reads
+ * the ids first, synchronising `stream`).
  */
 gc_status gc_pool_evict(gc_pool pool, const int32_t* ids_dev, int32_t n, void* stream);
 
@@ -206,12 +237,53 @@ gc_status gc_submit_tasks(gc_batch batch, const gc_task* tasks, int32_t n_tasks,
  * Fix the batch (once; later calls are no-ops until the next submit or
  * reset): the union U of the batch, i.e. the ids of every target and direct
  * range, ascending and without duplicates (Sec. 3.2: the runtime keeps the
- * request's indices sorted as they are inserted), is built on the host
- * together with each range's and each task's first position in U (a range
- * is contiguous in U), and uploaded with the tasks.  Synchronises `stream`
- * (the host arrays are released on return).
+ * request's indices sorted as they are inserted), together with each range's
+ * and each task's first position in U (a range is contiguous in U), the
+ * per-task offsets and the launch order (longest first within runs of 8,192
+ * tasks).  Host submissions: built on the host and uploaded with the tasks.
+ * Device submissions: built on the device (U by marking every range in a
+ * difference array and two prefix sums, so ids are never sorted), with only
+ * eight totals read back.  Synchronises `stream` in both cases.  Later calls
+ * that need the lists on the host (gc_batch_maps, address-list modes, host
+ * staging, gc_backward, gc_graph_capture) copy them from the device once.
  */
 gc_status gc_batch_commit(gc_batch batch, void* stream);
+
+/*
+ * Device-side submission (gravity batches): the request's tasks, ranges and
+ * node references are already in device memory -- typically the list walk's
+ * output (gc_tree_walk, gc_walk_tasks) -- in the layout of gc_submit_tasks
+ * (task slices relative to the given arrays).  The batch copies them device
+ * to device on `stream`; nothing is read on the host.  The batch must hold no
+ * other submission (GC_E_STATE: reset it first), and gc_submit_tasks is
+ * refused until the next reset.  Validation moves to gc_batch_commit, which
+ * then runs on the device: ids, counts and slices in bounds, each task's
+ * direct ranges in ascending id order and disjoint (as the walk emits them),
+ * node indices in [0, n_nodes), no id targeted by two tasks, no flags or
+ * shift.  A batch that breaks it is reported by gc_batch_commit with
+ * GC_E_INVAL and stays uncommitted.
+ */
+gc_status gc_submit_tasks_device(gc_batch batch, const gc_task* tasks_dev, int32_t n_tasks,
+                                 const int32_t* j_ranges_dev, int32_t n_ranges, const int32_t* node_idx_dev,
+                                 int32_t n_node_refs, int32_t n_nodes, void* stream);
+
+/*
+ * The tasks of buckets [b0, b1) (0 <= b0 <= b1 <= n_buckets, the walk's
+ * bucket count) of a list walk, written to tasks_dev (device,
+ * b1 - b0 gc_task records; Sec. 4.1: a bucket's particles form one work
+ * request that shares the bucket's lists): bucket b's targets are its leaf's
+ * id range (node_range_dev, int32 pairs (first id, count) per node), its
+ * direct ranges r_first_dev[b] .. r_first_dev[b + 1] and node references
+ * n_first_dev[b] .. n_first_dev[b + 1] of the walk's output, numbered from
+ * those of bucket b0, so that the walk's ranges_dev + 2 * r_first[b0] and
+ * node_idx_dev + n_first[b0] are the arrays to submit with them.  A leaf
+ * index outside [0, n_nodes) gives a task that gc_batch_commit refuses.
+ * Asynchronous on `stream`.
+ */
+gc_status gc_walk_tasks(gc_ctx ctx, int32_t n_buckets, int32_t b0, int32_t b1, const int32_t* bucket_node_dev,
+                        int32_t n_nodes,
+                        const int32_t* node_range_dev, const int32_t* n_first_dev, const int32_t* r_first_dev,
+                        gc_task* tasks_dev, void* stream);
 
 /* Number of tasks, ranges, node refs, direct entries (sum of range counts) and targets. */
 gc_status gc_batch_sizes(gc_batch batch, int64_t* out5);
@@ -255,10 +327,23 @@ gc_status gc_batch_status(gc_batch batch, void* stream);
  * synchronises; a missing record left without a slot is then still packed
  * from the source (PACK), gets slot 0 in address lists, is not made
  * resident, and gc_batch_maps reports GC_E_FULL.  Reorganisations of
- * batches sharing a pool must not run concurrently.
+ * batches sharing a pool must not run concurrently: issue them on one
+ * `stream`.
+ * Host source (gc_pool_set_host_source; Sec. 2.2, Sec. 3.2: host-issued
+ * copies of only the missing data): the host takes the missing ids from its
+ * mirror of the chare table, packs their records into the batch's pinned
+ * staging buffer (REDUNDANT: every record of U) and copies them to the device
+ * on `side_stream` (NULL: on `stream`); the kernel on `stream` waits for the
+ * copy, and the copy waits only for the work on `stream` that last read this
+ * batch's staged or packed records, so it overlaps the passes of other
+ * batches.  The capacity check then uses the mirror and does not
+ * synchronise.  The call blocks the host only while the batch's previous
+ * copy is still running (its pinned buffer is reused).  With a device
+ * source `side_stream` is not used.
  */
 enum { GC_REORG_REDUNDANT = 0, GC_REORG_INDIRECT = 1, GC_REORG_SORTED = 2, GC_REORG_PACK = 3, GC_REORG_NONE = 4 };
-gc_status gc_reorganize(gc_batch batch, gc_pool pool, int32_t mode, int32_t check_capacity, void* stream);
+gc_status gc_reorganize(gc_batch batch, gc_pool pool, int32_t mode, int32_t check_capacity, void* stream,
+                        void* side_stream);
 
 /*
  * Host copies of the last reorganisation's maps (synchronises `stream`):
@@ -331,6 +416,10 @@ typedef struct {
                                of the atom's pairs, shifted at the cutoff: see below) */
   int32_t deterministic;    /* 1: results must be the same bits on every call; a path
                                that sums with atomics then returns GC_E_UNSUPPORTED */
+  int32_t aggregation;      /* gravity: tasks combined per launch (Sec. 3.1: how many
+                               work requests one kernel takes); 0 = all tasks of the
+                               batch in one launch, k > 0 = consecutive launches of k
+                               tasks each in the batch's launch order (same results) */
 } gc_force_params;
 
 /*
@@ -491,16 +580,38 @@ gc_status gc_debug_step_waits(gc_ctx ctx, uint32_t fail_spins, int32_t fail_roun
 /* ---------------------------------------------------------------- tuning and introspection */
 
 /*
- * Time the combined pass of a reorganised batch for each candidate (tile,
- * waves_per_block, schedule, targets_per_lane) and return the fastest in
- * *best (prm fields other than those four are copied from `base`).
- * Synchronises `stream`.  times_ms (optional, n_cand floats) receives the
- * measured average per candidate; candidates are tiles {128, 256, 512} x
- * waves {2, 4, 8} x schedules {0, 1} x targets_per_lane {1, 2} in that
- * nesting order (n_cand = 36).
+ * Time the combined pass of a reorganised gravity batch for each candidate
+ * and return the fastest in *best (other prm fields are copied from `base`).
+ * Synchronises `stream`.  Two stages: the launch shape -- tiles {128, 256,
+ * 512} x waves {2, 4, 8} x schedules {0, 1} x targets_per_lane {1, 2}, in
+ * that nesting order, with every task in one launch -- then, with the best
+ * shape, the aggregation count (Sec. 3.1: the number of requests combined
+ * into one kernel): all tasks, twice, once and half the occupancy-sized
+ * count (resident workgroups per CU x CUs).  times_ms (optional, 40 floats)
+ * receives the average per candidate in that order (36 shapes, then 4
+ * counts).
+ * Tuning cache: with cache_path != NULL the result is kept in a JSON file
+ * keyed by device (gfx name and CU count), force kind and a hash of the
+ * batch's shape (tasks, targets, direct entries, node references and the
+ * histogram of tasks by target count).  A key found there is returned
+ * without timing (*from_cache = 1, times_ms untouched); otherwise the
+ * candidates are timed and the entry is added (the file is rewritten whole,
+ * other keys kept).  A file that is not such a cache gives GC_E_INVAL and is
+ * left alone.  from_cache may be NULL.
  */
 gc_status gc_autotune(gc_batch batch, const gc_force_params* base, const float* nodes_dev, float* acc_dev,
-                      int32_t reps, float* times_ms, gc_force_params* best, void* stream);
+                      int32_t reps, float* times_ms, gc_force_params* best, const char* cache_path,
+                      int32_t* from_cache, void* stream);
+
+/*
+ * In-cutoff pairs of a reorganised Lennard-Jones batch (Sec. 4.2: the pairs
+ * of a patch pair within the cutoff carry the force work): pairs with
+ * r^2 < r_cut^2 by the forward pass's FP32 decision, i < j in self tasks,
+ * each pair of a task counted once.  The measure of algorithmic work against
+ * which a pass's candidate evaluations are set.  Needs a device-resident
+ * source; synchronises `stream`.
+ */
+gc_status gc_lj_count_pairs(gc_batch batch, float r_cut, int64_t* pairs, void* stream);
 
 /* Occupancy of the combined gravity kernel: resident blocks per CU and CU count. */
 gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_t* blocks_per_cu, int32_t* n_cu);

@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 __all__ = ["GcError", "lib", "Context", "Pool", "Batch", "Graph", "Combiner", "ForceParams", "EwaldParams",
-           "ewald_params", "Hybrid", "lj_forces_cpu", "tree_walk", "DEVICE_CPU", "DEVICE_GPU", "TASK_DTYPE",
+           "ewald_params", "Hybrid", "lj_forces_cpu", "tree_walk", "walk_tasks", "DEVICE_CPU", "DEVICE_GPU", "TASK_DTYPE",
            "REORG_REDUNDANT", "REORG_INDIRECT", "REORG_SORTED", "REORG_PACK", "REORG_NONE",
            "FORCE_GRAV_MONO", "FORCE_GRAV_QUAD", "FORCE_LJ", "KIND_GRAV", "KIND_LJ", "TASK_SELF",
            "FIXTURE_NONE", "FIXTURE_RESET_PLACE", "FIXTURE_EVICT_STAGED", "SCHED_TASKS", "SCHED_QUEUE", "SCHED_STEP",
@@ -37,11 +37,12 @@ TASK_DTYPE = np.dtype([("i_begin", "<i4"), ("i_count", "<i4"), ("j_first", "<i4"
 
 EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_debug_inject_error", "gc_debug_step_waits",
             "gc_batch_status", "gc_graph_status", "gc_pool_create", "gc_pool_destroy",
-            "gc_pool_set_source", "gc_pool_place", "gc_pool_reset", "gc_pool_evict", "gc_pool_evict_staged",
+            "gc_pool_set_source", "gc_pool_set_host_source", "gc_pool_query_mirror", "gc_pool_place", "gc_pool_reset", "gc_pool_evict", "gc_pool_evict_staged",
             "gc_pool_query", "gc_pool_device_ptrs",
-            "gc_batch_create", "gc_batch_destroy", "gc_batch_reset", "gc_submit_tasks", "gc_batch_commit",
+            "gc_batch_create", "gc_batch_destroy", "gc_batch_reset", "gc_submit_tasks", "gc_submit_tasks_device",
+            "gc_walk_tasks", "gc_batch_commit",
             "gc_batch_sizes", "gc_reorganize", "gc_batch_maps", "gc_launch_combined", "gc_zero_f32", "gc_backward",
-            "gc_graph_capture", "gc_graph_launch", "gc_graph_destroy", "gc_autotune", "gc_occupancy",
+            "gc_graph_capture", "gc_graph_launch", "gc_graph_destroy", "gc_autotune", "gc_occupancy", "gc_lj_count_pairs",
             "gc_launch_ewald", "gc_hybrid_create", "gc_hybrid_destroy", "gc_hybrid_record", "gc_hybrid_split",
             "gc_hybrid_state", "gc_lj_forces_cpu", "gc_combiner_create", "gc_combiner_destroy", "gc_combiner_arrive", "gc_combiner_poll", "gc_combiner_state",
             "gc_tree_walk", "gc_tree_walk_noalloc"]
@@ -74,7 +75,7 @@ class ForceParams(ctypes.Structure):
                 ("mass_t", ctypes.c_void_p), ("r_cut", ctypes.c_float), ("schedule", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("waves_per_block", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
                 ("targets_per_lane", ctypes.c_int32), ("n_nodes", ctypes.c_int32), ("want_potential", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32)]
+                ("deterministic", ctypes.c_int32), ("aggregation", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -113,6 +114,8 @@ def lib():
         "gc_pool_create": (I32, [VP, I32, I32, ctypes.POINTER(VP)]),
         "gc_pool_destroy": (I32, [VP]),
         "gc_pool_set_source": (I32, [VP, VP]),
+        "gc_pool_set_host_source": (I32, [VP, VP]),
+        "gc_pool_query_mirror": (I32, [VP, VP, VP]),
         "gc_pool_place": (I32, [VP, VP, VP, I32, VP]),
         "gc_pool_reset": (I32, [VP, VP]),
         "gc_pool_evict": (I32, [VP, VP, I32, VP]),
@@ -123,9 +126,11 @@ def lib():
         "gc_batch_destroy": (I32, [VP]),
         "gc_batch_reset": (I32, [VP]),
         "gc_submit_tasks": (I32, [VP, VP, I32, VP, I32, VP, I32]),
+        "gc_submit_tasks_device": (I32, [VP, VP, I32, VP, I32, VP, I32, I32, VP]),
+        "gc_walk_tasks": (I32, [VP, I32, I32, I32, VP, I32, VP, VP, VP, VP, VP]),
         "gc_batch_commit": (I32, [VP, VP]),
         "gc_batch_sizes": (I32, [VP, PI64]),
-        "gc_reorganize": (I32, [VP, VP, I32, I32, VP]),
+        "gc_reorganize": (I32, [VP, VP, I32, I32, VP, VP]),
         "gc_batch_maps": (I32, [VP, PI64, VP, VP, VP, VP, VP, VP, VP, VP, VP]),
         "gc_launch_combined": (I32, [VP, ctypes.POINTER(ForceParams), VP, VP, VP]),
         "gc_zero_f32": (I32, [VP, VP, I64, VP]),
@@ -134,8 +139,10 @@ def lib():
                                    VP, VP, I32, ctypes.POINTER(VP), ctypes.POINTER(VP), VP, VP, ctypes.POINTER(VP)]),
         "gc_graph_launch": (I32, [VP, VP]),
         "gc_graph_destroy": (I32, [VP]),
-        "gc_autotune": (I32, [VP, ctypes.POINTER(ForceParams), VP, VP, I32, VP, ctypes.POINTER(ForceParams), VP]),
+        "gc_autotune": (I32, [VP, ctypes.POINTER(ForceParams), VP, VP, I32, VP, ctypes.POINTER(ForceParams),
+                              ctypes.c_char_p, PI32, VP]),
         "gc_occupancy": (I32, [VP, ctypes.POINTER(ForceParams), PI32, PI32]),
+        "gc_lj_count_pairs": (I32, [VP, ctypes.c_float, PI64, VP]),
         "gc_launch_ewald": (I32, [VP, ctypes.POINTER(EwaldParams), VP, VP]),
         "gc_hybrid_create": (I32, [ctypes.POINTER(VP)]),
         "gc_hybrid_destroy": (I32, [VP]),
@@ -369,6 +376,17 @@ def tree_walk(ctx: "Context", node_range, node_com, node_side, rec, bucket_node,
     return n_first, node_idx[:totals[0]], r_first, ranges[:totals[1]]
 
 
+def walk_tasks(ctx: "Context", b0: int, b1: int, bucket_node, node_range, n_first, r_first, stream=None):
+    """gc_task records of buckets [b0, b1) of a list walk, as a device uint8 tensor (gc_walk_tasks)."""
+    import torch
+    out = torch.empty(max(b1 - b0, 1) * TASK_DTYPE.itemsize, dtype=torch.uint8, device=bucket_node.device)
+    ctx.check(lib().gc_walk_tasks(ctx.h, int(bucket_node.numel()), int(b0), int(b1), _ptr(bucket_node),
+                                  int(node_range.shape[0]),
+                                  _ptr(node_range), _ptr(n_first), _ptr(r_first), _ptr(out), _stream(stream)),
+              "gc_walk_tasks")
+    return out[:(b1 - b0) * TASK_DTYPE.itemsize]
+
+
 class Pool:
     """Device record pool + chare table (gc_pool_*)."""
 
@@ -382,6 +400,19 @@ class Pool:
     def set_source(self, records):
         self._src = records  # keep alive
         self.ctx.check(lib().gc_pool_set_source(self.h, _ptr(records)), "gc_pool_set_source")
+
+    def set_host_source(self, records: np.ndarray):
+        """Host records (float32 [n_ids, 4], any host memory) staged by host-issued copies of the missing
+        records only (gc_pool_set_host_source)."""
+        assert records.dtype == np.float32 and records.flags.c_contiguous and records.shape == (self.n_ids, 4)
+        self._src = records  # keep alive
+        self.ctx.check(lib().gc_pool_set_host_source(self.h, records.ctypes.data), "gc_pool_set_host_source")
+
+    def query_mirror(self, stream=None) -> np.ndarray:
+        """The host mirror of the chare table of a host-source pool (gc_pool_query_mirror)."""
+        out = np.empty(self.n_ids, np.int32)
+        self.ctx.check(lib().gc_pool_query_mirror(self.h, out.ctypes.data, _stream(stream)), "gc_pool_query_mirror")
+        return out
 
     def place(self, ids_dev, slots_dev, stream=None):
         self.ctx.check(lib().gc_pool_place(self.h, _ptr(ids_dev), _ptr(slots_dev), int(ids_dev.numel()),
@@ -443,6 +474,19 @@ class Batch:
         self.ctx.check(lib().gc_submit_tasks(self.h, tasks.ctypes.data, len(tasks), ranges.ctypes.data,
                                              ranges.shape[0], node_idx.ctypes.data, node_idx.size), "gc_submit_tasks")
 
+    def reset(self):
+        """Drop every submitted task (gc_batch_reset)."""
+        self.ctx.check(lib().gc_batch_reset(self.h), "gc_batch_reset")
+
+    def submit_device(self, tasks_dev, ranges_dev, node_idx_dev, n_nodes: int, stream=None):
+        """Device tensors: tasks (uint8 / int32 view of gc_task records, n_tasks * 40 bytes), ranges int32
+        [n, 2], node_idx int32 (gc_submit_tasks_device)."""
+        n_tasks = (tasks_dev.numel() * tasks_dev.element_size()) // TASK_DTYPE.itemsize
+        self.ctx.check(lib().gc_submit_tasks_device(self.h, _ptr(tasks_dev), int(n_tasks), _ptr(ranges_dev),
+                                                    int(ranges_dev.numel() // 2), _ptr(node_idx_dev),
+                                                    int(node_idx_dev.numel()), int(n_nodes), _stream(stream)),
+                       "gc_submit_tasks_device")
+
     def commit(self, stream=None):
         self.ctx.check(lib().gc_batch_commit(self.h, _stream(stream)), "gc_batch_commit")
 
@@ -452,9 +496,10 @@ class Batch:
         return dict(tasks=int(out[0]), ranges=int(out[1]), node_refs=int(out[2]), direct=int(out[3]),
                     targets=int(out[4]))
 
-    def reorganize(self, pool: Pool, mode: int, check_capacity: bool = True, stream=None):
-        self.ctx.check(lib().gc_reorganize(self.h, pool.h, mode, 1 if check_capacity else 0, _stream(stream)),
-                       "gc_reorganize")
+    def reorganize(self, pool: Pool, mode: int, check_capacity: bool = True, stream=None, side=None):
+        """side: stream of the staging copies of a host-source pool (None: `stream`)."""
+        self.ctx.check(lib().gc_reorganize(self.h, pool.h, mode, 1 if check_capacity else 0, _stream(stream),
+                                           None if side is None else _stream(side)), "gc_reorganize")
 
     def maps(self, stream=None) -> dict:
         sz = self.sizes()
@@ -480,6 +525,13 @@ class Batch:
         self.ctx.check(lib().gc_launch_combined(self.h, ctypes.byref(p), _ptr(nodes), _ptr(acc), _stream(stream)),
                        "gc_launch_combined")
 
+    def lj_count_pairs(self, r_cut: float, stream=None) -> int:
+        """In-cutoff pairs of this Lennard-Jones batch (gc_lj_count_pairs)."""
+        n = ctypes.c_int64()
+        self.ctx.check(lib().gc_lj_count_pairs(self.h, float(r_cut), ctypes.byref(n), _stream(stream)),
+                       "gc_lj_count_pairs")
+        return n.value
+
     def status(self, stream=None):
         """Raises GcError if a device-side wait gave up or a backward met bad node ranges (gc_batch_status)."""
         self.ctx.check(lib().gc_batch_status(self.h, _stream(stream)), "gc_batch_status")
@@ -495,13 +547,17 @@ class Batch:
                                          _ptr(cot), _ptr(gpos), _ptr(gmass), _ptr(gparam), _stream(stream)),
                        "gc_backward")
 
-    def autotune(self, base: ForceParams, nodes, acc, reps: int = 3, stream=None):
-        times = np.zeros(36, np.float32)
+    def autotune(self, base: ForceParams, nodes, acc, reps: int = 3, stream=None, cache_path: str | None = None):
+        """(best parameters, times of the 36 shapes and 4 aggregation counts in ms (NaN: not timed), whether the
+        result came from the tuning cache) (gc_autotune)."""
+        times = np.full(40, np.nan, np.float32)
         best = ForceParams()
+        hit = ctypes.c_int32(0)
         base = with_nodes(base, nodes)
         self.ctx.check(lib().gc_autotune(self.h, ctypes.byref(base), _ptr(nodes), _ptr(acc), reps, times.ctypes.data,
-                                         ctypes.byref(best), _stream(stream)), "gc_autotune")
-        return best, times
+                                         ctypes.byref(best), None if cache_path is None else cache_path.encode(),
+                                         ctypes.byref(hit), _stream(stream)), "gc_autotune")
+        return best, times, bool(hit.value)
 
     def destroy(self):
         if self.h:
@@ -561,7 +617,7 @@ def with_nodes(prm: ForceParams, nodes) -> ForceParams:
 
 def grav_params(order: int = 2, G: float = 1.0, eps: float = 0.01, schedule: int = 0, tile: int = 0,
                 waves_per_block: int = 0, grid_blocks: int = 0, targets_per_lane: int = 0, want_potential: int = 0,
-                deterministic: int = 0) -> ForceParams:
+                deterministic: int = 0, aggregation: int = 0) -> ForceParams:
     """Gravity parameters; n_nodes is filled in from the node table by the calls that take one."""
     p = ForceParams()
     p.kind = FORCE_GRAV_QUAD if order == 2 else FORCE_GRAV_MONO
@@ -569,6 +625,7 @@ def grav_params(order: int = 2, G: float = 1.0, eps: float = 0.01, schedule: int
     p.schedule, p.tile, p.waves_per_block, p.grid_blocks = schedule, tile, waves_per_block, grid_blocks
     p.targets_per_lane = targets_per_lane
     p.want_potential, p.deterministic = want_potential, deterministic
+    p.aggregation = aggregation
     return p
 
 

@@ -97,6 +97,8 @@ struct ReorgArgs {
   const int32_t* U;        // sorted union, padded to whole union blocks
   int32_t u;
   const float4* src;       // source records by id
+  const float4* staged;    // non-null: the k-th missing record (ascending id) is staged[k], copied in
+                           // from the host before the launch; src is then not read
   float4* pool;
   int32_t* slot_of;
   uint32_t* occ;           // padded to whole free-scan blocks
@@ -130,7 +132,8 @@ hipError_t launch_count(const int32_t* U, int32_t u, const int32_t* slot_of, con
 hipError_t launch_evict(const int32_t* ids, const int32_t* n_dev, int32_t n_bound, int32_t* slot_of, int32_t n_ids,
                         uint32_t* occ, hipStream_t s);
 hipError_t launch_sort_lists(int32_t n_tasks, const int32_t* joff, int32_t* jlist, hipStream_t s);
-hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, float4* pool,
+// by_k: the k-th record is src[k] (staged from the host), else src[ids[k]]
+hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, bool by_k, float4* pool,
                         int32_t* slot_of, uint32_t* occ, hipStream_t s);
 // two: two targets per lane (each record read from LDS serves two interactions)
 hipError_t launch_grav(int order, bool lists, bool persistent, bool two, const GravArgs& a, int waves_per_block,
@@ -141,6 +144,39 @@ hipError_t launch_lj(bool persistent, const LJArgs& a, int waves_per_block, int 
 hipError_t launch_lj_gather(bool persistent, const LJArgs& a, int grid_blocks, hipStream_t s);
 hipError_t launch_lj_finish(float4* acc, const float* mass_t, const float4* rec_by_id, int32_t n,
                             hipStream_t s);
+// *out += the tasks' in-cutoff pairs (the forward kernels' FP32 decision; self tasks i < j)
+hipError_t launch_lj_count(const gc_task* tasks, int32_t n_tasks, const int2* ranges_id, const float4* rec_by_id,
+                           float rc2, unsigned long long* out, hipStream_t s);
+
+// ---------------------------------------------------------------- device-side commit
+
+// Totals of a device commit (int64 words, zeroed before the launch).
+constexpr int kDcUnion = 0, kDcDirect = 1, kDcTargets = 2, kDcMaxDirect = 3, kDcBad = 4, kDcBadTargets = 5,
+              kDcMaxNode = 6, kDcTot = 8;
+struct DevCommitArgs {
+  gc_task* tasks;          // the batch's copy (tasks that break the contract are emptied in place)
+  int32_t n_tasks;
+  const int2* ranges;      // (first id, count) pairs
+  int32_t n_ranges;
+  const int32_t* nodes;
+  int32_t n_node_refs, n_nodes;
+  int32_t n_ids;
+  int32_t* dc;             // per task: direct entries
+  int64_t* cost;           // per task: launch-order cost
+  int32_t* diff;           // 2 (n_ids + 1), zeroed: +1 / -1 at range starts / ends (all ids, target ids)
+  int32_t* bs;             // 2 per id block: block sums, then their exclusive prefixes
+  int32_t* ns;             // per id block: ids of U in the block, then their exclusive prefix
+  int32_t* U;              // room for n_ids entries (padded to whole union blocks)
+  int32_t* pos;            // n_ids: rank in U or -1
+  int2* pranges;
+  int32_t* pibeg, *ioff, *joff, *order;
+  int64_t* tot;            // kDcTot words
+};
+int dc_id_blocks(int32_t n_ids);
+hipError_t launch_dev_commit(const DevCommitArgs& a, hipStream_t s);
+hipError_t launch_walk_tasks(int32_t b0, int32_t b1, const int32_t* bucket_node, int32_t n_nodes,
+                             const int32_t* node_range, const int32_t* n_first, const int32_t* r_first, gc_task* out,
+                             hipStream_t s);
 
 // ---------------------------------------------------------------- Ewald correction
 

@@ -370,7 +370,48 @@ __global__ void k_lj_finish(float4* __restrict__ acc, const float* __restrict__ 
   }
 }
 
+// In-cutoff pairs of the tasks (self tasks: i < j), with the forward kernels' FP32 decision: one
+// wavefront per task at a time, lanes over the task's flattened (i, j) candidates.
+__global__ void __launch_bounds__(256) k_lj_count(const gc_task* __restrict__ tasks, int32_t n_tasks,
+                                                  const int2* __restrict__ ranges_id,
+                                                  const float4* __restrict__ rec_by_id, float rc2,
+                                                  unsigned long long* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long cnt = 0;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < n_tasks; t += (int64_t)gridDim.x * 4) {
+    const gc_task tk = tasks[t];
+    const int2 g = ranges_id[tk.j_first];
+    const bool self = (tk.flags & GC_TASK_SELF) != 0;
+    const float a0 = tk.shift[0] > 0.f ? tk.shift[0] : 0.f, b0 = tk.shift[0] < 0.f ? tk.shift[0] : 0.f;
+    const float a1 = tk.shift[1] > 0.f ? tk.shift[1] : 0.f, b1 = tk.shift[1] < 0.f ? tk.shift[1] : 0.f;
+    const float a2 = tk.shift[2] > 0.f ? tk.shift[2] : 0.f, b2 = tk.shift[2] < 0.f ? tk.shift[2] : 0.f;
+    const int64_t np = (int64_t)max(tk.i_count, 0) * max(g.y, 0);
+    for (int64_t p = lane; p < np; p += 64) {
+      const int i = (int)(p / g.y), j = (int)(p - (int64_t)i * g.y);
+      if (self && j <= i) continue;
+      const float4 xi = rec_by_id[tk.i_begin + i], xj = rec_by_id[g.x + j];
+      const float dx = (xi.x - a0) - (xj.x + b0);
+      const float dy = (xi.y - a1) - (xj.y + b1);
+      const float dz = (xi.z - a2) - (xj.z + b2);
+      const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+      cnt += r2 < rc2 ? 1ull : 0ull;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if (lane == 0 && cnt) atomicAdd(out, cnt);
+}
+
 }  // namespace
+
+hipError_t launch_lj_count(const gc_task* tasks, int32_t n_tasks, const int2* ranges_id, const float4* rec_by_id,
+                           float rc2, unsigned long long* out, hipStream_t s) {
+  if (n_tasks <= 0) return hipSuccess;
+  int g = (n_tasks + 3) / 4;
+  if (g > 16384) g = 16384;
+  hipLaunchKernelGGL(k_lj_count, dim3(g), dim3(256), 0, s, tasks, n_tasks, ranges_id, rec_by_id, rc2, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_lj(bool persistent, const LJArgs& a, int wpb, int grid, hipStream_t s) {
   if (a.n_runs <= 0) return hipSuccess;

@@ -148,11 +148,11 @@ __global__ void k_evict(const int32_t* __restrict__ ids, const int32_t* __restri
 }
 
 __global__ void k_place(const int32_t* __restrict__ ids, const int32_t* __restrict__ slots, int32_t n,
-                        const float4* __restrict__ src, float4* __restrict__ pool, int32_t* __restrict__ slot_of,
-                        uint32_t* __restrict__ occ) {
+                        const float4* __restrict__ src, int32_t by_k, float4* __restrict__ pool,
+                        int32_t* __restrict__ slot_of, uint32_t* __restrict__ occ) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     int id = ids[k], s = slots[k];
-    pool[s] = src[id];
+    pool[s] = src[by_k ? k : id];
     slot_of[id] = s;
     occ[s] = 1u;
   }
@@ -276,10 +276,11 @@ hipError_t launch_sort_lists(int32_t n_tasks, const int32_t* joff, int32_t* jlis
   return hipGetLastError();
 }
 
-hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, float4* pool,
+hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, bool by_k, float4* pool,
                         int32_t* slot_of, uint32_t* occ, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_place, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ids, slots, n, src, pool, slot_of, occ);
+  hipLaunchKernelGGL(k_place, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ids, slots, n, src, by_k ? 1 : 0, pool,
+                     slot_of, occ);
   return hipGetLastError();
 }
 

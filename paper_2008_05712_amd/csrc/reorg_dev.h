@@ -255,20 +255,26 @@ __device__ __forceinline__ void union_probe(uint64_t* flist, uint64_t* ftotal, u
 
 // Per-batch form of the union side: lookup, then every entry's record -- from the pool if resident,
 // from the source if missing -- is loaded before the ranks are known and its packed copy written at
-// once (neither waits for the scans); then the missing ranks, slot assignment and staging.
+// once (neither waits for the scans); then the missing ranks, slot assignment and staging.  With a
+// host-staged batch (a.staged) a missing record sits at its missing rank in a.staged, so it is
+// loaded, packed and staged once the rank is known.
 template <bool COH>
 __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t tag, int* sh, uint32_t* s_ex,
                                            const int32_t (&id)[kUItems]) {
   uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbf;
   const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
+  const bool stg = a.staged != nullptr;
   int32_t sl[kUItems];
   const uint32_t fm = union_lookup<COH>(a, b, id, sl);
   float rx[kUItems], ry[kUItems], rz[kUItems], rw[kUItems];
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if ((fm >> i) & 1u) v = gld(a.src + id[i]);
-    else if (k0 + i < a.u) v = ld_rec<COH>(a.pool + sl[i]);
+    if ((fm >> i) & 1u) {
+      if (!stg) v = gld(a.src + id[i]);
+    } else if (k0 + i < a.u) {
+      v = ld_rec<COH>(a.pool + sl[i]);
+    }
     rx[i] = v.x;
     ry[i] = v.y;
     rz[i] = v.z;
@@ -290,13 +296,28 @@ __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t t
   for (int i = 0; i < kUItems; ++i) {
     const int64_t k = k0 + i;
     if (k < a.u) {
-      if (!((fm >> i) & 1u)) gst(a.uslot + k, sl[i]);
-      if (a.pack) gst(a.packed + k, make_float4(rx[i], ry[i], rz[i], rw[i]));
+      const bool miss = (fm >> i) & 1u;
+      if (!miss) gst(a.uslot + k, sl[i]);
+      if (a.pack && !(stg && miss)) gst(a.packed + k, make_float4(rx[i], ry[i], rz[i], rw[i]));
     }
   }
   __syncthreads();
   if (!fm) return;
   rm += (int)*s_ex;
+  if (stg) {
+    int r = rm;
+#pragma unroll
+    for (int i = 0; i < kUItems; ++i)
+      if ((fm >> i) & 1u) {
+        const float4 v = gld(a.staged + r);
+        rx[i] = v.x;
+        ry[i] = v.y;
+        rz[i] = v.z;
+        rw[i] = v.w;
+        if (a.pack) gst(a.packed + k0 + i, v);
+        ++r;
+      }
+  }
   // the rm-th free slot for the rm-th missing record, once its free-scan block has listed it
   union_probe(a.free_list, a.ftotal, tag, rm, a.flimit, fm, sl, a.state + GC_STATE_ERR);
 #pragma unroll

@@ -2,6 +2,8 @@
 // chare table, batches (combined work requests), the reorganisation pipeline,
 // the combined launches, HIP graph capture and the autotuner.
 #include <algorithm>
+#include <cctype>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -69,6 +71,55 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned host buffer (hipHostMalloc) that only grows: the staging area of host-issued copies.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes && p) return hipSuccess;
+    release();
+    size_t b = want < 4096 ? 4096 : want + want / 4;
+    hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = b;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// An event created on first use (timing off), destroyed with its owner.
+struct Event {
+  hipEvent_t e = nullptr;
+  bool recorded = false;
+  hipError_t record(hipStream_t s) {
+    if (!e) {
+      hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+      if (r != hipSuccess) {
+        e = nullptr;
+        return r;
+      }
+    }
+    recorded = true;
+    return hipEventRecord(e, s);
+  }
+  hipError_t wait(hipStream_t s) const { return recorded ? hipStreamWaitEvent(s, e, 0) : hipSuccess; }
+  hipError_t sync() const { return recorded ? hipEventSynchronize(e) : hipSuccess; }
+  void destroy() {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+    recorded = false;
+  }
+};
+
 }  // namespace
 
 struct gc_ctx_ {
@@ -133,7 +184,18 @@ struct gc_pool_ {
   DevBuf rec, slot_of, occ;
   const float4* src = nullptr;
   bool src_device = false;
-  std::vector<DevBuf*> bufs() { return {&rec, &slot_of, &occ}; }
+  // host source (gc_pool_set_host_source): records staged by host-issued copies, and the host's
+  // mirror of the chare table that tells it which records are missing without asking the device
+  const float4* host_src = nullptr;
+  std::vector<int32_t> m_slot_of;  // by id, -1: not resident
+  std::vector<uint64_t> m_free;    // bit s of word s / 64: slot s free
+  int64_t m_nfree = 0;
+  size_t m_lo = 0;                 // no free slot below word m_lo
+  bool mirror_ok = false;          // false: the device changed the table without the host tracking it
+  PinnedBuf pin;                   // gc_pool_place staging
+  DevBuf tmp;
+  Event ev_pin;
+  std::vector<DevBuf*> bufs() { return {&rec, &slot_of, &occ, &tmp}; }
 };
 
 struct gc_batch_ {
@@ -144,7 +206,14 @@ struct gc_batch_ {
   std::vector<int32_t> ranges;   // pairs
   std::vector<int32_t> nodes;
   int64_t n_direct = 0, n_targets = 0;
+  int32_t nt = 0, nr = 0, nn = 0;  // tasks, ranges and node refs submitted (host or device)
   bool committed = false;
+  // device submission (gc_submit_tasks_device): tasks and lists arrive in d_tasks / d_ranges / d_nodes
+  // and the commit runs on the device; the host vectors (tasks, ranges, nodes, hU, h_order, h_pibeg)
+  // are filled from the device only when a host-side step needs them (host_lists)
+  bool dev_sub = false, host_lists = true;
+  int32_t dev_n_nodes = 0;
+  DevBuf dc_dc, dc_cost, dc_diff, dc_bs, dc_ns, dc_tot, d_pos;
   // fixed at commit: the sorted union U and the packed-space ranges and first targets
   std::vector<int32_t> hU;
   std::vector<int32_t> h_order, h_pibeg;  // launch order of the tasks and their first packed targets
@@ -171,15 +240,25 @@ struct gc_batch_ {
   int32_t mode = -1;
   gc_pool pool = nullptr;
   const float4* rec = nullptr;
+  // host-staged reorganisation: the missing records packed on the host (pin), their device copy
+  // (staged), the copy's completion (ev_copy) and the last compute-stream work that read this
+  // batch's staged or packed records (ev_use, which the next copy waits for)
+  PinnedBuf pin;
+  DevBuf staged;
+  Event ev_copy, ev_use;
+  bool host_staged = false;
+  std::vector<int32_t> h_missing, h_mslot;  // the last host-staged call's missing ids and their slots
   std::vector<DevBuf*> bufs() {
     return {&d_tasks, &d_ranges, &d_nodes, &d_ioff, &d_joff, &d_order, &d_runs, &d_U, &pranges, &pibeg, &d_irank,
             &d_jrank, &uslot, &missing, &mslot, &free_list, &state, &packed, &ilist, &jlist, &queue, &force, &ppart,
-            &vnode, &vdir, &nvis, &nchunks, &nchunk_first, &npart, &dvis, &dkey, &d_ljtgt, &d_ljent, &stat};
+            &vnode, &vdir, &nvis, &nchunks, &nchunk_first, &npart, &dvis, &dkey, &d_ljtgt, &d_ljent, &stat, &staged,
+            &dc_dc, &dc_cost, &dc_diff, &dc_bs, &dc_ns, &dc_tot, &d_pos};
   }
 };
 
 struct gc_graph_ {
   gc_ctx ctx = nullptr;
+  std::vector<gc_pool> pools;      // pools the graph changes (their host mirrors go stale at each launch)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   DevBuf step_items, step_rounds, step_ctr, step_fl;  // whole-step persistent schedule
@@ -310,11 +389,100 @@ extern "C" gc_status gc_pool_create(gc_ctx ctx, int32_t n_ids, int32_t capacity,
 extern "C" gc_status gc_pool_destroy(gc_pool pool) {
   if (!pool) return GC_E_INVAL;
   (void)hipDeviceSynchronize();
-  pool->rec.release();
-  pool->slot_of.release();
-  pool->occ.release();
+  for (DevBuf* d : pool->bufs()) d->release();
+  pool->pin.release();
+  pool->ev_pin.destroy();
   delete pool;
   return GC_OK;
+}
+
+// ---------------------------------------------------------------- host mirror of the chare table
+// A host-source pool keeps the chare table on the host too.  The device's allocator is
+// deterministic (the k-th missing id of a call takes the k-th lowest free slot), so every call the
+// host makes can be replayed on the mirror in call order, and the host knows each request's missing
+// set without reading the device.  Calls whose effect the host cannot see (a reorganisation from a
+// device source, a graph launch) mark the mirror stale; it is then read back once, before the next
+// host-staged call.
+
+static void mirror_clear(gc_pool p) {
+  p->m_slot_of.assign((size_t)p->n_ids, -1);
+  p->m_free.assign(((size_t)p->cap + 63) / 64, ~0ull);
+  if (p->cap % 64) p->m_free.back() = (1ull << (p->cap % 64)) - 1ull;
+  p->m_nfree = p->cap;
+  p->m_lo = 0;
+  p->mirror_ok = true;
+}
+
+static void mirror_take_slot(gc_pool p, int32_t id, int32_t slot) {
+  p->m_slot_of[id] = slot;
+  uint64_t& w = p->m_free[(size_t)slot >> 6];
+  const uint64_t bit = 1ull << (slot & 63);
+  if (w & bit) {
+    w &= ~bit;
+    --p->m_nfree;
+  }
+}
+
+static void mirror_free_id(gc_pool p, int32_t id) {
+  const int32_t s = p->m_slot_of[id];
+  if (s < 0) return;
+  p->m_slot_of[id] = -1;
+  uint64_t& w = p->m_free[(size_t)s >> 6];
+  const uint64_t bit = 1ull << (s & 63);
+  if (!(w & bit)) {
+    w |= bit;
+    ++p->m_nfree;
+    p->m_lo = std::min(p->m_lo, (size_t)s >> 6);
+  }
+}
+
+// The n lowest free slots, ascending, taken for ids[0, n) (fewer if the pool runs out: the rest
+// get -1 and stay missing).
+static void mirror_assign(gc_pool p, const int32_t* ids, int64_t n, int32_t* slots) {
+  size_t w = p->m_lo;
+  for (int64_t k = 0; k < n; ++k) {
+    while (w < p->m_free.size() && !p->m_free[w]) ++w;
+    if (w >= p->m_free.size()) {
+      for (; k < n; ++k) slots[k] = -1;
+      break;
+    }
+    const int32_t s = (int32_t)(w * 64 + (size_t)__builtin_ctzll(p->m_free[w]));
+    p->m_free[w] &= p->m_free[w] - 1ull;
+    --p->m_nfree;
+    p->m_slot_of[ids[k]] = s;
+    slots[k] = s;
+  }
+  p->m_lo = w;
+}
+
+// Reads the device's chare table and occupancy flags into the mirror (synchronises `s`).
+static hipError_t mirror_sync(gc_pool p, hipStream_t s) {
+  std::vector<uint32_t> occ((size_t)p->cap);
+  p->m_slot_of.resize((size_t)p->n_ids);
+  hipError_t e = hipMemcpyAsync(p->m_slot_of.data(), p->slot_of.p, sizeof(int32_t) * (size_t)p->n_ids,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(occ.data(), p->occ.p, sizeof(uint32_t) * (size_t)p->cap, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  p->m_free.assign(((size_t)p->cap + 63) / 64, 0ull);
+  p->m_nfree = 0;
+  for (int32_t k = 0; k < p->cap; ++k)
+    if (occ[k] == 0u) {
+      p->m_free[(size_t)k >> 6] |= 1ull << (k & 63);
+      ++p->m_nfree;
+    }
+  p->m_lo = 0;
+  p->mirror_ok = true;
+  return hipSuccess;
+}
+
+// Copies n device int32 values to the host (synchronises `s`).
+static hipError_t read_ids(const int32_t* dev, int32_t n, std::vector<int32_t>& out, hipStream_t s) {
+  out.resize((size_t)std::max(n, 0));
+  if (n <= 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(out.data(), dev, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s);
+  return e == hipSuccess ? hipStreamSynchronize(s) : e;
 }
 
 extern "C" gc_status gc_pool_set_source(gc_pool pool, const void* records) {
@@ -328,6 +496,7 @@ extern "C" gc_status gc_pool_set_source(gc_pool pool, const void* records) {
     return set_err(pool->ctx, GC_E_INVAL, "gc_pool_set_source: pointer is neither device memory nor pinned host memory");
   }
   pool->src_device = (at.type == hipMemoryTypeDevice);
+  pool->host_src = nullptr;
   if (at.type == hipMemoryTypeHost) {
     // pinned host memory: use its device-visible address
     void* dp = nullptr;
@@ -344,14 +513,50 @@ extern "C" gc_status gc_pool_set_source(gc_pool pool, const void* records) {
   return GC_OK;
 }
 
+extern "C" gc_status gc_pool_set_host_source(gc_pool pool, const void* records) {
+  if (!pool) return GC_E_INVAL;
+  GC_ENTER(pool->ctx);
+  if (!records) return set_err(pool->ctx, GC_E_INVAL, "gc_pool_set_host_source: NULL records");
+  pool->host_src = static_cast<const float4*>(records);
+  pool->src = nullptr;
+  pool->src_device = false;
+  pool->mirror_ok = false;  // read back before the first host-staged call
+  return GC_OK;
+}
+
 extern "C" gc_status gc_pool_place(gc_pool pool, const int32_t* ids_dev, const int32_t* slots_dev, int32_t n,
                                    void* stream) {
   if (!pool) return GC_E_INVAL;
-  GC_ENTER(pool->ctx);
-  if (n < 0 || (n > 0 && (!ids_dev || !slots_dev))) return set_err(pool->ctx, GC_E_INVAL, "gc_pool_place: bad arrays");
-  if (n > 0 && !pool->src) return set_err(pool->ctx, GC_E_STATE, "gc_pool_place: no source set");
-  GC_HIP(pool->ctx, launch_place(ids_dev, slots_dev, n, pool->src, pool->rec.as<float4>(), pool->slot_of.as<int32_t>(),
-                                 pool->occ.as<uint32_t>(), S(stream)));
+  gc_ctx c = pool->ctx;
+  GC_ENTER(c);
+  if (n < 0 || (n > 0 && (!ids_dev || !slots_dev))) return set_err(c, GC_E_INVAL, "gc_pool_place: bad arrays");
+  if (n > 0 && !pool->src && !pool->host_src) return set_err(c, GC_E_STATE, "gc_pool_place: no source set");
+  if (n == 0) return GC_OK;
+  hipStream_t s = S(stream);
+  if (!pool->host_src) {
+    pool->mirror_ok = false;
+    GC_HIP(c, launch_place(ids_dev, slots_dev, n, pool->src, false, pool->rec.as<float4>(),
+                           pool->slot_of.as<int32_t>(), pool->occ.as<uint32_t>(), s));
+    return GC_OK;
+  }
+  // host source: the host reads the fixture, packs the records and copies them in
+  std::vector<int32_t> ids, slots;
+  GC_HIP(c, read_ids(ids_dev, n, ids, s));
+  GC_HIP(c, read_ids(slots_dev, n, slots, s));
+  for (int32_t k = 0; k < n; ++k)
+    if (ids[k] < 0 || ids[k] >= pool->n_ids || slots[k] < 0 || slots[k] >= pool->cap)
+      return set_err(c, GC_E_INVAL, "gc_pool_place: id %d or slot %d out of range", ids[k], slots[k]);
+  if (!pool->mirror_ok) GC_HIP(c, mirror_sync(pool, s));
+  GC_HIP(c, pool->ev_pin.sync());
+  if (pool->pin.ensure(sizeof(float4) * (size_t)n) != hipSuccess || pool->tmp.ensure(sizeof(float4) * (size_t)n) != hipSuccess)
+    return set_err(c, GC_E_NOMEM, "gc_pool_place: staging buffers");
+  float4* pin = pool->pin.as<float4>();
+  for (int32_t k = 0; k < n; ++k) pin[k] = pool->host_src[ids[k]];
+  GC_HIP(c, hipMemcpyAsync(pool->tmp.p, pin, sizeof(float4) * (size_t)n, hipMemcpyHostToDevice, s));
+  GC_HIP(c, pool->ev_pin.record(s));
+  GC_HIP(c, launch_place(ids_dev, slots_dev, n, pool->tmp.as<float4>(), true, pool->rec.as<float4>(),
+                         pool->slot_of.as<int32_t>(), pool->occ.as<uint32_t>(), s));
+  for (int32_t k = 0; k < n; ++k) mirror_take_slot(pool, ids[k], slots[k]);
   return GC_OK;
 }
 
@@ -363,6 +568,18 @@ extern "C" gc_status gc_pool_reset(gc_pool pool, void* stream) {
   if (!pool) return GC_E_INVAL;
   GC_ENTER(pool->ctx);
   GC_HIP(pool->ctx, pool_reset_async(pool, S(stream)));
+  if (pool->host_src) mirror_clear(pool);
+  else pool->mirror_ok = false;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_pool_query_mirror(gc_pool pool, int32_t* slot_of_host, void* stream) {
+  if (!pool) return GC_E_INVAL;
+  GC_ENTER(pool->ctx);
+  if (!slot_of_host) return set_err(pool->ctx, GC_E_INVAL, "gc_pool_query_mirror: NULL output");
+  if (!pool->host_src) return set_err(pool->ctx, GC_E_STATE, "gc_pool_query_mirror: the pool has no host source");
+  if (!pool->mirror_ok) GC_HIP(pool->ctx, mirror_sync(pool, S(stream)));
+  std::memcpy(slot_of_host, pool->m_slot_of.data(), sizeof(int32_t) * (size_t)pool->n_ids);
   return GC_OK;
 }
 
@@ -402,6 +619,9 @@ extern "C" gc_status gc_batch_destroy(gc_batch b) {
   if (!b) return GC_E_INVAL;
   (void)hipDeviceSynchronize();
   for (DevBuf* d : b->bufs()) d->release();
+  b->pin.release();
+  b->ev_copy.destroy();
+  b->ev_use.destroy();
   delete b;
   return GC_OK;
 }
@@ -420,6 +640,12 @@ extern "C" gc_status gc_batch_reset(gc_batch b) {
   b->u = 0;
   b->mode = -1;
   b->pool = nullptr;
+  b->host_staged = false;
+  b->h_missing.clear();
+  b->h_mslot.clear();
+  b->nt = b->nr = b->nn = 0;
+  b->dev_sub = false;
+  b->host_lists = true;
   return GC_OK;
 }
 
@@ -428,6 +654,7 @@ extern "C" gc_status gc_submit_tasks(gc_batch b, const gc_task* tasks, int32_t n
   if (!b) return GC_E_INVAL;
   gc_ctx c = b->ctx;
   GC_ENTER(c);
+  if (b->dev_sub) return set_err(c, GC_E_STATE, "gc_submit_tasks: the batch holds a device submission (reset it first)");
   if (n_tasks < 0 || n_ranges < 0 || n_node_refs < 0) return set_err(c, GC_E_INVAL, "gc_submit_tasks: negative count");
   if ((n_tasks && !tasks) || (n_ranges && !j_ranges) || (n_node_refs && !node_idx))
     return set_err(c, GC_E_INVAL, "gc_submit_tasks: NULL array with nonzero count");
@@ -491,6 +718,9 @@ extern "C" gc_status gc_submit_tasks(gc_batch b, const gc_task* tasks, int32_t n
   b->nodes.insert(b->nodes.end(), node_idx, node_idx + n_node_refs);
   b->n_direct += add_direct;
   b->n_targets += add_targets;
+  b->nt = (int32_t)b->tasks.size();
+  b->nr = (int32_t)(b->ranges.size() / 2);
+  b->nn = (int32_t)b->nodes.size();
   b->max_node = max_node;
   b->committed = false;
   b->ranks_ready = false;
@@ -500,9 +730,9 @@ extern "C" gc_status gc_submit_tasks(gc_batch b, const gc_task* tasks, int32_t n
 
 extern "C" gc_status gc_batch_sizes(gc_batch b, int64_t* out5) {
   if (!b || !out5) return GC_E_INVAL;
-  out5[0] = (int64_t)b->tasks.size();
-  out5[1] = (int64_t)b->ranges.size() / 2;
-  out5[2] = (int64_t)b->nodes.size();
+  out5[0] = b->nt;
+  out5[1] = b->nr;
+  out5[2] = b->nn;
   out5[3] = b->n_direct;
   out5[4] = b->n_targets;
   return GC_OK;
@@ -521,11 +751,165 @@ extern "C" gc_status gc_batch_status(gc_batch b, void* stream) {
   return GC_OK;
 }
 
+// ---------------------------------------------------------------- device submission and commit
+
+extern "C" gc_status gc_submit_tasks_device(gc_batch b, const gc_task* tasks_dev, int32_t n_tasks,
+                                            const int32_t* j_ranges_dev, int32_t n_ranges,
+                                            const int32_t* node_idx_dev, int32_t n_node_refs, int32_t n_nodes,
+                                            void* stream) {
+  if (!b) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  if (b->kind != GC_KIND_GRAV) return set_err(c, GC_E_UNSUPPORTED, "gc_submit_tasks_device: gravity batches only");
+  if (b->nt || b->nr || b->nn || b->dev_sub)
+    return set_err(c, GC_E_STATE, "gc_submit_tasks_device: the batch already holds tasks (reset it first)");
+  if (n_tasks < 0 || n_ranges < 0 || n_node_refs < 0 || n_nodes < 0)
+    return set_err(c, GC_E_INVAL, "gc_submit_tasks_device: negative count");
+  if ((n_tasks && !tasks_dev) || (n_ranges && !j_ranges_dev) || (n_node_refs && !node_idx_dev))
+    return set_err(c, GC_E_INVAL, "gc_submit_tasks_device: NULL array with nonzero count");
+  hipStream_t s = S(stream);
+  hipError_t e = b->d_tasks.ensure(sizeof(gc_task) * (size_t)std::max(n_tasks, 1));
+  if (e == hipSuccess) e = b->d_ranges.ensure(sizeof(int32_t) * 2 * (size_t)std::max(n_ranges, 1));
+  if (e == hipSuccess) e = b->d_nodes.ensure(sizeof(int32_t) * (size_t)std::max(n_node_refs, 1));
+  if (e != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_submit_tasks_device: %s", hipGetErrorString(e));
+  if (n_tasks)
+    GC_HIP(c, hipMemcpyAsync(b->d_tasks.p, tasks_dev, sizeof(gc_task) * (size_t)n_tasks, hipMemcpyDeviceToDevice, s));
+  if (n_ranges)
+    GC_HIP(c, hipMemcpyAsync(b->d_ranges.p, j_ranges_dev, sizeof(int32_t) * 2 * (size_t)n_ranges,
+                             hipMemcpyDeviceToDevice, s));
+  if (n_node_refs)
+    GC_HIP(c, hipMemcpyAsync(b->d_nodes.p, node_idx_dev, sizeof(int32_t) * (size_t)n_node_refs,
+                             hipMemcpyDeviceToDevice, s));
+  b->nt = n_tasks;
+  b->nr = n_ranges;
+  b->nn = n_node_refs;
+  b->dev_n_nodes = n_nodes;
+  b->dev_sub = true;
+  b->host_lists = false;
+  b->committed = false;
+  b->mode = -1;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_walk_tasks(gc_ctx c, int32_t n_buckets, int32_t b0, int32_t b1, const int32_t* bucket_node_dev,
+                                   int32_t n_nodes, const int32_t* node_range_dev, const int32_t* n_first_dev,
+                                   const int32_t* r_first_dev, gc_task* tasks_dev, void* stream) {
+  GC_ENTER(c);
+  if (b0 < 0 || b1 < b0 || b1 > n_buckets || n_nodes < 0)
+    return set_err(c, GC_E_INVAL, "gc_walk_tasks: bucket range [%d, %d) not inside [0, %d), or n_nodes < 0", b0, b1,
+                   n_buckets);
+  if (b1 > b0 && (!bucket_node_dev || !node_range_dev || !n_first_dev || !r_first_dev || !tasks_dev))
+    return set_err(c, GC_E_INVAL, "gc_walk_tasks: NULL array");
+  GC_HIP(c, launch_walk_tasks(b0, b1, bucket_node_dev, n_nodes, node_range_dev, n_first_dev, r_first_dev, tasks_dev,
+                              S(stream)));
+  return GC_OK;
+}
+
+// The whole commit of a device submission runs on the device; the host reads back eight totals.
+static gc_status commit_device(gc_batch b, hipStream_t s) {
+  gc_ctx c = b->ctx;
+  const int32_t T = b->nt, n = b->n_ids;
+  const int nb = dc_id_blocks(n);
+  hipError_t e = b->dc_dc.ensure(sizeof(int32_t) * (size_t)std::max(T, 1));
+  if (e == hipSuccess) e = b->dc_cost.ensure(sizeof(int64_t) * (size_t)std::max(T, 1));
+  if (e == hipSuccess) e = b->dc_diff.ensure(sizeof(int32_t) * 2 * ((size_t)n + 1));
+  if (e == hipSuccess) e = b->dc_bs.ensure(sizeof(int32_t) * 2 * (size_t)nb);
+  if (e == hipSuccess) e = b->dc_ns.ensure(sizeof(int32_t) * (size_t)nb);
+  if (e == hipSuccess) e = b->dc_tot.ensure(sizeof(int64_t) * kDcTot);
+  if (e == hipSuccess) e = b->d_U.ensure(sizeof(int32_t) * (size_t)union_padded(n));
+  if (e == hipSuccess) e = b->d_pos.ensure(sizeof(int32_t) * (size_t)n);
+  if (e == hipSuccess) e = b->pranges.ensure(sizeof(int32_t) * 2 * (size_t)std::max(b->nr, 1));
+  if (e == hipSuccess) e = b->pibeg.ensure(sizeof(int32_t) * (size_t)std::max(T, 1));
+  if (e == hipSuccess) e = b->d_ioff.ensure(sizeof(int32_t) * (size_t)std::max(T, 1));
+  if (e == hipSuccess) e = b->d_joff.ensure(sizeof(int32_t) * ((size_t)T + 1));
+  if (e == hipSuccess) e = b->d_order.ensure(sizeof(int32_t) * (size_t)std::max(T, 1));
+  if (e == hipSuccess) e = b->stat.ensure(sizeof(int32_t) * 4);
+  if (e != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_batch_commit: %s", hipGetErrorString(e));
+  GC_HIP(c, launch_fill_i32(b->dc_diff.as<int32_t>(), 0, 2 * ((int64_t)n + 1), s));
+  GC_HIP(c, launch_fill_i32(b->dc_tot.as<int32_t>(), 0, 2 * kDcTot, s));
+  GC_HIP(c, launch_fill_i32(b->d_U.as<int32_t>(), 0, union_padded(n), s));
+  GC_HIP(c, launch_fill_i32(b->stat.as<int32_t>(), 0, 4, s));
+  DevCommitArgs a{};
+  a.tasks = b->d_tasks.as<gc_task>();
+  a.n_tasks = T;
+  a.ranges = b->d_ranges.as<int2>();
+  a.n_ranges = b->nr;
+  a.nodes = b->d_nodes.as<int32_t>();
+  a.n_node_refs = b->nn;
+  a.n_nodes = b->dev_n_nodes;
+  a.n_ids = n;
+  a.dc = b->dc_dc.as<int32_t>();
+  a.cost = b->dc_cost.as<int64_t>();
+  a.diff = b->dc_diff.as<int32_t>();
+  a.bs = b->dc_bs.as<int32_t>();
+  a.ns = b->dc_ns.as<int32_t>();
+  a.U = b->d_U.as<int32_t>();
+  a.pos = b->d_pos.as<int32_t>();
+  a.pranges = b->pranges.as<int2>();
+  a.pibeg = b->pibeg.as<int32_t>();
+  a.ioff = b->d_ioff.as<int32_t>();
+  a.joff = b->d_joff.as<int32_t>();
+  a.order = b->d_order.as<int32_t>();
+  a.tot = b->dc_tot.as<int64_t>();
+  GC_HIP(c, launch_dev_commit(a, s));
+  int64_t tot[kDcTot];
+  GC_HIP(c, hipMemcpyAsync(tot, b->dc_tot.p, sizeof tot, hipMemcpyDeviceToHost, s));
+  GC_HIP(c, hipStreamSynchronize(s));
+  if (tot[kDcBad] || tot[kDcBadTargets]) {
+    return set_err(c, GC_E_INVAL,
+                   "gc_batch_commit: device submission with %lld task(s) outside the contract (ids, slices, "
+                   "ranges not ascending and disjoint, node indices) and %lld id(s) targeted by two tasks",
+                   (long long)tot[kDcBad], (long long)tot[kDcBadTargets]);
+  }
+  if (tot[kDcDirect] > INT32_MAX || tot[kDcTargets] > INT32_MAX)
+    return set_err(c, GC_E_INVAL, "gc_batch_commit: batch exceeds 2^31 entries");
+  b->u = (int32_t)tot[kDcUnion];
+  b->n_direct = tot[kDcDirect];
+  b->n_targets = tot[kDcTargets];
+  b->max_direct = (int32_t)tot[kDcMaxDirect];
+  b->max_node = b->nn ? (int32_t)tot[kDcMaxNode] : -1;
+  b->n_runs = 0;
+  b->lj_gather = b->lj_cover = false;
+  b->n_ljtgt = 0;
+  b->host_lists = false;
+  b->committed = true;
+  b->ranks_ready = false;
+  b->adj_nodes = -1;
+  b->mode = -1;
+  return GC_OK;
+}
+
+// The host copies of a device-committed batch's tasks, lists, union and launch order, read from the
+// device when a host-side step first needs them (synchronises `s`).
+static gc_status need_host_lists(gc_batch b, hipStream_t s) {
+  if (b->host_lists) return GC_OK;
+  gc_ctx c = b->ctx;
+  b->tasks.resize((size_t)b->nt);
+  b->ranges.resize(2 * (size_t)b->nr);
+  b->nodes.resize((size_t)b->nn);
+  b->hU.resize((size_t)b->u);
+  b->h_order.resize((size_t)b->nt);
+  b->h_pibeg.resize((size_t)b->nt);
+  auto dn = [&](void* dst, const DevBuf& src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(dst, src.p, bytes, hipMemcpyDeviceToHost, s) : hipSuccess;
+  };
+  GC_HIP(c, dn(b->tasks.data(), b->d_tasks, sizeof(gc_task) * b->tasks.size()));
+  GC_HIP(c, dn(b->ranges.data(), b->d_ranges, sizeof(int32_t) * b->ranges.size()));
+  GC_HIP(c, dn(b->nodes.data(), b->d_nodes, sizeof(int32_t) * b->nodes.size()));
+  GC_HIP(c, dn(b->hU.data(), b->d_U, sizeof(int32_t) * b->hU.size()));
+  GC_HIP(c, dn(b->h_order.data(), b->d_order, sizeof(int32_t) * b->h_order.size()));
+  GC_HIP(c, dn(b->h_pibeg.data(), b->pibeg, sizeof(int32_t) * b->h_pibeg.size()));
+  GC_HIP(c, hipStreamSynchronize(s));
+  b->host_lists = true;
+  return GC_OK;
+}
+
 extern "C" gc_status gc_batch_commit(gc_batch b, void* stream) {
   if (!b) return GC_E_INVAL;
   gc_ctx c = b->ctx;
   GC_ENTER(c);
   if (b->committed) return GC_OK;
+  if (b->dev_sub) return commit_device(b, S(stream));
   const int32_t T = (int32_t)b->tasks.size();
   const int32_t R = (int32_t)(b->ranges.size() / 2);
   // targets written by at most one gravity task
@@ -689,6 +1073,8 @@ static bool lists_mode(int32_t mode) { return mode == GC_REORG_INDIRECT || mode 
 // are grouped the same way by source id.  Node ids must lie in [0, n_nodes).
 static gc_status build_adj_index(gc_batch b, int32_t n_nodes, hipStream_t s) {
   gc_ctx c = b->ctx;
+  gc_status hs = need_host_lists(b, s);
+  if (hs != GC_OK) return hs;
   const int64_t nv = (int64_t)b->nodes.size();
   std::vector<int32_t> nstart((size_t)n_nodes + 1, 0);
   for (int64_t v = 0; v < nv; ++v) {
@@ -809,16 +1195,23 @@ static hipError_t clear_reorg_state(gc_batch b, hipStream_t s) {
   return e;
 }
 
-// Device part of a reorganisation (buffers already sized).
-static gc_status reorganize_async(gc_batch b, gc_pool p, int32_t mode, hipStream_t s) {
+// Device part of a reorganisation (buffers already sized).  staged: the missing records, copied in
+// from the host in missing order (host-staged calls; REDUNDANT then has its records in `packed`
+// already).
+static gc_status reorganize_async(gc_batch b, gc_pool p, int32_t mode, hipStream_t s, const float4* staged = nullptr) {
   gc_ctx c = b->ctx;
   if (mode == GC_REORG_REDUNDANT) {
-    GC_HIP(c, launch_gather_src(b->d_U.as<int32_t>(), b->u, p->src, b->packed.as<float4>(), b->state.as<int32_t>(), s));
+    if (p->host_src)
+      GC_HIP(c, launch_fill_i32(b->state.as<int32_t>() + GC_STATE_UNION, b->u, 2, s));  // |U| and #missing
+    else
+      GC_HIP(c, launch_gather_src(b->d_U.as<int32_t>(), b->u, p->src, b->packed.as<float4>(), b->state.as<int32_t>(),
+                                  s));
   } else {
     ReorgArgs a{};
     a.U = b->d_U.as<int32_t>();
     a.u = b->u;
     a.src = p->src;
+    a.staged = staged;
     a.pool = p->rec.as<float4>();
     a.slot_of = p->slot_of.as<int32_t>();
     a.occ = p->occ.as<uint32_t>();
@@ -835,21 +1228,86 @@ static gc_status reorganize_async(gc_batch b, gc_pool p, int32_t mode, hipStream
       GC_HIP(c, launch_lists(b->d_irank.as<int32_t>(), b->n_targets, b->d_jrank.as<int32_t>(), b->n_direct,
                              b->uslot.as<int32_t>(), b->ilist.as<int32_t>(), b->jlist.as<int32_t>(), s));
       if (mode == GC_REORG_SORTED)
-        GC_HIP(c, launch_sort_lists((int32_t)b->tasks.size(), b->d_joff.as<int32_t>(), b->jlist.as<int32_t>(), s));
+        GC_HIP(c, launch_sort_lists(b->nt, b->d_joff.as<int32_t>(), b->jlist.as<int32_t>(), s));
     }
   }
   b->rec = (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT) ? b->packed.as<float4>() : p->rec.as<float4>();
   return GC_OK;
 }
 
-extern "C" gc_status gc_reorganize(gc_batch b, gc_pool p, int32_t mode, int32_t check_capacity, void* stream) {
+// Host-staged reorganisation (pool with a host source).  The host finds the missing records in its
+// mirror of the chare table, packs them into the batch's pinned buffer and copies them to the
+// device on `side` (REDUNDANT: every record of U, straight into the packed buffer); the kernel on
+// `s` waits for the copy.  The copy waits only for earlier work on `s` that read this batch's
+// staged or packed records, so it overlaps other batches' passes.
+static gc_status reorganize_host(gc_batch b, gc_pool p, int32_t mode, int32_t check_capacity, hipStream_t s,
+                                 hipStream_t side) {
+  gc_ctx c = b->ctx;
+  const bool redundant = mode == GC_REORG_REDUNDANT;
+  gc_status hs = need_host_lists(b, s);
+  if (hs != GC_OK) return hs;
+  if (!redundant && !p->mirror_ok) GC_HIP(c, mirror_sync(p, s));
+  std::vector<int32_t> miss;
+  if (!redundant)
+    for (int32_t id : b->hU)
+      if (p->m_slot_of[id] < 0) miss.push_back(id);
+  const int32_t* ids = redundant ? b->hU.data() : miss.data();
+  const int64_t m = redundant ? b->u : (int64_t)miss.size();
+  if (!redundant && check_capacity && m > p->m_nfree)
+    return set_err(c, GC_E_FULL, "gc_reorganize: %lld records missing but only %lld pool slots free", (long long)m,
+                   (long long)p->m_nfree);
+  b->mode = -1;
+  hipError_t e = ensure_reorg_buffers(b, p, mode, s);
+  // room for every union entry, so that the kernel's reads stay inside it whatever its own count
+  if (e == hipSuccess && !redundant) e = b->staged.ensure(sizeof(float4) * (size_t)std::max<int32_t>(b->u, 1));
+  if (e != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_reorganize: %s", hipGetErrorString(e));
+  GC_HIP(c, b->ev_copy.sync());  // the pinned buffer is free once its last copy has run
+  if (b->pin.ensure(sizeof(float4) * (size_t)std::max<int64_t>(m, 1)) != hipSuccess)
+    return set_err(c, GC_E_NOMEM, "gc_reorganize: pinned staging buffer");
+  float4* pin = b->pin.as<float4>();
+  for (int64_t k = 0; k < m; ++k) pin[k] = p->host_src[ids[k]];
+  hipStream_t cs = side ? side : s;
+  if (m > 0) {
+    if (cs != s) GC_HIP(c, b->ev_use.wait(cs));
+    GC_HIP(c, hipMemcpyAsync(redundant ? b->packed.p : b->staged.p, pin, sizeof(float4) * (size_t)m,
+                             hipMemcpyHostToDevice, cs));
+    GC_HIP(c, b->ev_copy.record(cs));
+    if (cs != s) GC_HIP(c, b->ev_copy.wait(s));
+  }
+  gc_status st = reorganize_async(b, p, mode, s, redundant ? nullptr : b->staged.as<float4>());
+  if (st != GC_OK) return st;
+  GC_HIP(c, b->ev_use.record(s));
+  b->h_missing.clear();
+  b->h_mslot.clear();
+  if (!redundant) {
+    b->h_mslot.resize((size_t)m);
+    mirror_assign(p, miss.data(), m, b->h_mslot.data());
+    b->h_missing = std::move(miss);
+  }
+  b->host_staged = true;
+  b->mode = mode;
+  b->pool = p;
+  return GC_OK;
+}
+
+extern "C" gc_status gc_reorganize(gc_batch b, gc_pool p, int32_t mode, int32_t check_capacity, void* stream,
+                                   void* side_stream) {
   if (!b || !p) return GC_E_INVAL;
   gc_ctx c = b->ctx;
   GC_ENTER(c);
   if (!b->committed) return set_err(c, GC_E_STATE, "gc_reorganize: batch not committed");
   if (p->n_ids != b->n_ids) return set_err(c, GC_E_INVAL, "gc_reorganize: pool and batch id spaces differ");
   if (mode < GC_REORG_REDUNDANT || mode > GC_REORG_NONE) return set_err(c, GC_E_INVAL, "gc_reorganize: bad mode %d", mode);
-  if (!p->src) return set_err(c, GC_E_STATE, "gc_reorganize: pool has no source");
+  if (!p->src && !p->host_src) return set_err(c, GC_E_STATE, "gc_reorganize: pool has no source");
+  if (mode == GC_REORG_SORTED && b->max_direct > kSortMax)
+    return set_err(c, GC_E_UNSUPPORTED, "gc_reorganize: SORTED supports at most %d direct entries per task (got %d)",
+                   kSortMax, b->max_direct);
+  if (p->host_src) {
+    if (mode == GC_REORG_NONE) return set_err(c, GC_E_INVAL, "gc_reorganize: NONE needs a device-resident source");
+    return reorganize_host(b, p, mode, check_capacity, S(stream), S(side_stream));
+  }
+  b->host_staged = false;
+  p->mirror_ok = false;
   if (mode == GC_REORG_NONE) {
     if (!p->src_device) return set_err(c, GC_E_INVAL, "gc_reorganize: NONE needs a device-resident source");
     b->mode = mode;
@@ -857,10 +1315,11 @@ extern "C" gc_status gc_reorganize(gc_batch b, gc_pool p, int32_t mode, int32_t 
     b->rec = p->src;
     return GC_OK;
   }
-  if (mode == GC_REORG_SORTED && b->max_direct > kSortMax)
-    return set_err(c, GC_E_UNSUPPORTED, "gc_reorganize: SORTED supports at most %d direct entries per task (got %d)",
-                   kSortMax, b->max_direct);
   hipStream_t s = S(stream);
+  if (lists_mode(mode)) {  // the address lists' union ranks are built on the host
+    gc_status hs = need_host_lists(b, s);
+    if (hs != GC_OK) return hs;
+  }
   b->mode = -1;
   hipError_t e = ensure_reorg_buffers(b, p, mode, s);
   if (e != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_reorganize: %s", hipGetErrorString(e));
@@ -889,6 +1348,12 @@ extern "C" gc_status gc_pool_evict(gc_pool pool, const int32_t* ids_dev, int32_t
   if (!pool) return GC_E_INVAL;
   GC_ENTER(pool->ctx);
   if (n < 0 || (n > 0 && !ids_dev)) return set_err(pool->ctx, GC_E_INVAL, "gc_pool_evict: bad arrays");
+  if (pool->host_src && pool->mirror_ok && n > 0) {
+    std::vector<int32_t> ids;
+    GC_HIP(pool->ctx, read_ids(ids_dev, n, ids, S(stream)));
+    for (int32_t id : ids)
+      if (id >= 0 && id < pool->n_ids) mirror_free_id(pool, id);
+  }
   GC_HIP(pool->ctx, launch_evict(ids_dev, nullptr, n, pool->slot_of.as<int32_t>(), pool->n_ids,
                                  pool->occ.as<uint32_t>(), S(stream)));
   return GC_OK;
@@ -896,6 +1361,14 @@ extern "C" gc_status gc_pool_evict(gc_pool pool, const int32_t* ids_dev, int32_t
 
 static gc_status evict_staged_async(gc_pool pool, gc_batch b, hipStream_t s) {
   if (b->mode != GC_REORG_PACK && b->mode != GC_REORG_INDIRECT && b->mode != GC_REORG_SORTED) return GC_OK;
+  if (pool->host_src && pool->mirror_ok) {
+    if (b->host_staged) {
+      for (size_t k = 0; k < b->h_missing.size(); ++k)
+        if (b->h_mslot[k] >= 0) mirror_free_id(pool, b->h_missing[k]);
+    } else {
+      pool->mirror_ok = false;
+    }
+  }
   GC_HIP(pool->ctx, launch_evict(b->missing.as<int32_t>(), b->state.as<int32_t>() + GC_STATE_MISSING,
                                  std::max<int32_t>(b->u, 1), pool->slot_of.as<int32_t>(), pool->n_ids,
                                  pool->occ.as<uint32_t>(), s));
@@ -918,6 +1391,8 @@ extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int3
   GC_ENTER(c);
   if (b->mode < 0 || b->mode == GC_REORG_NONE) return set_err(c, GC_E_STATE, "gc_batch_maps: no reorganisation");
   hipStream_t s = S(stream);
+  gc_status hs = need_host_lists(b, s);
+  if (hs != GC_OK) return hs;
   int32_t h[8];
   GC_HIP(c, hipMemcpyAsync(h, b->state.p, sizeof h, hipMemcpyDeviceToHost, s));
   GC_HIP(c, hipStreamSynchronize(s));
@@ -940,8 +1415,8 @@ extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int3
     GC_HIP(c, dn(new_slot, b->mslot.p, sizeof(int32_t) * (size_t)nm));
   }
   if (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT) {
-    GC_HIP(c, dn(pranges, b->pranges.p, sizeof(int32_t) * b->ranges.size()));
-    GC_HIP(c, dn(pi_begin, b->pibeg.p, sizeof(int32_t) * b->tasks.size()));
+    GC_HIP(c, dn(pranges, b->pranges.p, sizeof(int32_t) * 2 * (size_t)b->nr));
+    GC_HIP(c, dn(pi_begin, b->pibeg.p, sizeof(int32_t) * (size_t)b->nt));
   } else {
     GC_HIP(c, dn(ilist, b->ilist.p, sizeof(int32_t) * (size_t)b->n_targets));
     GC_HIP(c, dn(jlist, b->jlist.p, sizeof(int32_t) * (size_t)b->n_direct));
@@ -982,6 +1457,9 @@ static gc_status check_prm(gc_batch b, const gc_force_params* prm, int* tile, in
     return set_err(c, GC_E_INVAL, "node index %d is not below n_nodes %d of the node table", b->max_node, prm->n_nodes);
   if (prm->want_potential != 0 && prm->want_potential != 1) return set_err(c, GC_E_INVAL, "want_potential must be 0 or 1");
   if (prm->deterministic != 0 && prm->deterministic != 1) return set_err(c, GC_E_INVAL, "deterministic must be 0 or 1");
+  if (prm->aggregation < 0) return set_err(c, GC_E_INVAL, "aggregation must be >= 0");
+  if (prm->aggregation > 0 && b->kind != GC_KIND_GRAV)
+    return set_err(c, GC_E_UNSUPPORTED, "aggregation counts are for gravity batches (Lennard-Jones runs one launch)");
   return GC_OK;
 }
 
@@ -1000,14 +1478,14 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
     return set_err(c, GC_E_UNSUPPORTED,
                    "gc_launch_combined: this Lennard-Jones batch (target ranges that partially overlap) sums with "
                    "atomics; no deterministic form");
-  const int32_t T = (int32_t)b->tasks.size();
+  const int32_t T = b->nt;
   const bool packed = (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT);
   const bool lists = (b->mode == GC_REORG_INDIRECT || b->mode == GC_REORG_SORTED);
   const bool persistent = prm->schedule == 1;
   if (b->queue.ensure(16) != hipSuccess) return set_err(c, GC_E_NOMEM, "queue");
   if (persistent) GC_HIP(c, launch_fill_i32(b->queue.as<int32_t>(), 0, 1, s));
   if (b->kind == GC_KIND_GRAV) {
-    if (!nodes_dev && !b->nodes.empty()) return set_err(c, GC_E_INVAL, "gc_launch_combined: NULL nodes with node refs");
+    if (!nodes_dev && b->nn) return set_err(c, GC_E_INVAL, "gc_launch_combined: NULL nodes with node refs");
     GravArgs a{};
     a.tasks = b->d_tasks.as<gc_task>();
     a.n_tasks = T;
@@ -1034,7 +1512,22 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
       GC_HIP(c, grav_occupancy(order, lists, true, two, tile, wpb, &per));
       grid = std::max(1, per) * c->n_cu;
     }
-    GC_HIP(c, launch_grav(order, lists, persistent, two, a, wpb, grid, s));
+    // aggregation: consecutive launches over slices of the launch order (each slice's queue counter
+    // is its own word, so the persistent form needs no reset between them)
+    const int32_t agg = prm->aggregation > 0 && prm->aggregation < T ? prm->aggregation : T;
+    const int32_t n_launch = T > 0 ? (T + agg - 1) / agg : 0;
+    if (persistent && n_launch > 1) {
+      if (b->queue.ensure(sizeof(int32_t) * (size_t)(n_launch + 4)) != hipSuccess)
+        return set_err(c, GC_E_NOMEM, "queue");
+      GC_HIP(c, launch_fill_i32(b->queue.as<int32_t>(), 0, n_launch, s));
+    }
+    for (int32_t q = 0; q < n_launch; ++q) {
+      GravArgs aq = a;
+      aq.order = b->d_order.as<int32_t>() + (int64_t)q * agg;
+      aq.n_tasks = std::min<int32_t>(agg, T - q * agg);
+      aq.queue = b->queue.as<int32_t>() + (n_launch > 1 ? q : 0);
+      GC_HIP(c, launch_grav(order, lists, persistent, two, aq, wpb, grid, s));
+    }
   } else {
     if (lists) return set_err(c, GC_E_UNSUPPORTED, "Lennard-Jones supports PACK, REDUNDANT and NONE");
     if (!b->pool->src_device) return set_err(c, GC_E_INVAL, "Lennard-Jones needs a device-resident source");
@@ -1074,7 +1567,32 @@ extern "C" gc_status gc_launch_combined(gc_batch b, const gc_force_params* prm, 
                                         void* stream) {
   if (!b) return GC_E_INVAL;
   GC_ENTER(b->ctx);
-  return launch_combined_async(b, prm, nodes_dev, acc_dev, S(stream));
+  gc_status st = launch_combined_async(b, prm, nodes_dev, acc_dev, S(stream));
+  // a host-staged batch's next copy waits for this pass's reads of its records
+  if (st == GC_OK && b->host_staged) GC_HIP(b->ctx, b->ev_use.record(S(stream)));
+  return st;
+}
+
+extern "C" gc_status gc_lj_count_pairs(gc_batch b, float r_cut, int64_t* pairs, void* stream) {
+  if (!b) return GC_E_INVAL;
+  gc_ctx c = b->ctx;
+  GC_ENTER(c);
+  if (!pairs) return set_err(c, GC_E_INVAL, "gc_lj_count_pairs: NULL output");
+  if (b->kind != GC_KIND_LJ) return set_err(c, GC_E_INVAL, "gc_lj_count_pairs: Lennard-Jones batches only");
+  if (!(r_cut > 0.f)) return set_err(c, GC_E_INVAL, "gc_lj_count_pairs: r_cut must be > 0");
+  if (!b->committed || b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_lj_count_pairs: batch not reorganised");
+  if (!b->pool->src_device) return set_err(c, GC_E_INVAL, "gc_lj_count_pairs: needs a device-resident source");
+  hipStream_t s = S(stream);
+  if (b->queue.ensure(16) != hipSuccess) return set_err(c, GC_E_NOMEM, "gc_lj_count_pairs: counter");
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(b->queue.as<int32_t>() + 2);
+  GC_HIP(c, launch_fill_i32(b->queue.as<int32_t>() + 2, 0, 2, s));
+  GC_HIP(c, launch_lj_count(b->d_tasks.as<gc_task>(), b->nt, b->d_ranges.as<int2>(), b->pool->src, r_cut * r_cut, cnt,
+                            s));
+  unsigned long long h = 0;
+  GC_HIP(c, hipMemcpyAsync(&h, cnt, sizeof h, hipMemcpyDeviceToHost, s));
+  GC_HIP(c, hipStreamSynchronize(s));
+  *pairs = (int64_t)h;
+  return GC_OK;
 }
 
 extern "C" gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_t* blocks_per_cu, int32_t* n_cu) {
@@ -1109,7 +1627,7 @@ extern "C" gc_status gc_launch_ewald(gc_batch b, const gc_ewald_params* prm, flo
   const bool packed = (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT);
   EwaldArgs a{};
   a.tasks = b->d_tasks.as<gc_task>();
-  a.n_tasks = (int32_t)b->tasks.size();
+  a.n_tasks = b->nt;
   a.ioff = b->d_ioff.as<int32_t>();
   a.n_targets = b->n_targets;
   a.ibeg = packed ? b->pibeg.as<int32_t>() : nullptr;
@@ -1128,6 +1646,7 @@ extern "C" gc_status gc_launch_ewald(gc_batch b, const gc_ewald_params* prm, flo
   const double aL = (double)a.alpha * prm->L;
   a.kdecay = (float)(M_PI * M_PI / (aL * aL));
   GC_HIP(c, launch_ewald(a, S(stream)));
+  if (b->host_staged) GC_HIP(c, b->ev_use.record(S(stream)));
   return GC_OK;
 }
 
@@ -1218,11 +1737,11 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
   if (!b->pool->src_device) return set_err(c, GC_E_INVAL, "gc_backward needs a device-resident source");
   if (!cot_dev || !gpos_dev || !gmass_dev) return set_err(c, GC_E_INVAL, "gc_backward: NULL cotangent or gradient");
   hipStream_t s = S(stream);
-  const int32_t T = (int32_t)b->tasks.size();
+  const int32_t T = b->nt;
   const bool packed = (b->mode == GC_REORG_PACK || b->mode == GC_REORG_REDUNDANT);
   if (b->kind == GC_KIND_GRAV) {
     const int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
-    if (!b->nodes.empty() && (!nodes_dev || !node_range_dev || n_nodes <= 0))
+    if (b->nn && (!nodes_dev || !node_range_dev || n_nodes <= 0))
       return set_err(c, GC_E_INVAL, "gc_backward: node table and node ranges needed");
     if (b->adj_nodes != std::max<int32_t>(n_nodes, 0)) {
       gc_status bst = build_adj_index(b, std::max<int32_t>(n_nodes, 0), s);
@@ -1249,7 +1768,7 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
     if (b->n_direct > 0)
       GC_HIP(c, launch_direct_sums(a.vdir, b->dvis.as<int32_t>(), b->dkey.as<int32_t>(), (int32_t)b->n_direct,
                                    a.gpos, gmass_dev, s));
-    if (!b->nodes.empty()) {
+    if (b->nn) {
       GC_HIP(c, launch_visit_sums(order, a.vnode, b->nvis.as<int32_t>(), b->nchunks.as<int2>(), b->adj_chunks,
                                   b->npart.as<float4>(), s));
       GC_HIP(c, launch_node_chain(order, node_range_dev, n_nodes, reinterpret_cast<const float4*>(nodes_dev),
@@ -1315,7 +1834,7 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
       if (batches[q] == b) return set_err(ctx, GC_E_UNSUPPORTED, "whole-step schedule: distinct batches only");
     gc_status st = check_prm(b, prm, &tile, &wpb);
     if (st != GC_OK) return st;
-    if (!b->nodes.empty() && !nodes_dev) return set_err(ctx, GC_E_INVAL, "whole-step schedule: NULL nodes");
+    if (b->nn && !nodes_dev) return set_err(ctx, GC_E_INVAL, "whole-step schedule: NULL nodes");
   }
   if (!acc_dev) return set_err(ctx, GC_E_INVAL, "whole-step schedule: NULL acc");
   const int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
@@ -1475,6 +1994,8 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
   for (int32_t k = 0; k < n_steps; ++k) {
     if (!batches[k] || !pools[k] || !batches[k]->committed)
       return set_err(ctx, GC_E_STATE, "gc_graph_capture: step %d batch not committed", k);
+    gc_status hs = need_host_lists(batches[k], S(stream));  // the capture builds its items on the host
+    if (hs != GC_OK) return hs;
     if (modes[k] == GC_REORG_SORTED && batches[k]->max_direct > kSortMax)
       return set_err(ctx, GC_E_UNSUPPORTED, "gc_graph_capture: SORTED list too long in step %d", k);
     int tile, wpb;
@@ -1483,9 +2004,20 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
     // size buffers outside the capture (allocation is not capturable)
     if (modes[k] != GC_REORG_NONE && ensure_reorg_buffers(batches[k], pools[k], modes[k], S(stream)) != hipSuccess)
       return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: buffers");
-    if (batches[k]->queue.ensure(16) != hipSuccess) return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: queue");
+    {
+      // room for one queue word per aggregated launch (allocation is not capturable)
+      const int64_t T = batches[k]->nt, agg = prm->aggregation > 0 && prm->aggregation < T ? prm->aggregation : T;
+      const int64_t nl = T > 0 ? (T + agg - 1) / agg : 1;
+      if (batches[k]->queue.ensure(sizeof(int32_t) * (size_t)(nl + 4)) != hipSuccess)
+        return set_err(ctx, GC_E_NOMEM, "gc_graph_capture: queue");
+    }
     if (fixture == GC_FIXTURE_EVICT_STAGED && pools[k] != pools[(k + n_steps - 1) % n_steps])
       return set_err(ctx, GC_E_INVAL, "gc_graph_capture: evicting fixture needs one pool for all steps");
+    if (pools[k]->host_src)
+      return set_err(ctx, GC_E_UNSUPPORTED,
+                     "gc_graph_capture: step %d's pool has a host source (its staging is packed by the host per call)",
+                     k);
+    if (!pools[k]->src) return set_err(ctx, GC_E_STATE, "gc_graph_capture: step %d's pool has no source", k);
   }
   // every batch starts with a cleared state (so the first replay evicts nothing for the step before
   // step 0); the tags keep later replays apart without further clearing
@@ -1496,6 +2028,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
   if (prm->schedule == GC_SCHED_STEP) {
     gc_graph gs = new gc_graph_();
     gs->ctx = ctx;
+    gs->pools.assign(pools, pools + n_steps);
     for (DevBuf* d : gs->bufs()) d->h = &ctx->hooks;
     gc_status st = capture_step(ctx, n_steps, batches, pools, modes, prm, nodes_dev, acc_dev, fixture, s, gs);
     if (st != GC_OK) {
@@ -1522,6 +2055,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
   }
   gc_graph gr = new gc_graph_();
   gr->ctx = ctx;
+  gr->pools.assign(pools, pools + n_steps);
   for (DevBuf* d : gr->bufs()) d->h = &ctx->hooks;
   auto cleanup = [&]() {
     for (hipEvent_t e : gr->events) (void)hipEventDestroy(e);
@@ -1565,7 +2099,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
     if (fixture == GC_FIXTURE_RESET_PLACE) {
       if (pool_reset_async(p, s) != hipSuccess) st = set_err(ctx, GC_E_HIP, "capture: pool reset");
       if (st == GC_OK && place_n && place_n[k] > 0 &&
-          launch_place(place_ids[k], place_slots[k], place_n[k], p->src, p->rec.as<float4>(), p->slot_of.as<int32_t>(),
+          launch_place(place_ids[k], place_slots[k], place_n[k], p->src, false, p->rec.as<float4>(), p->slot_of.as<int32_t>(),
                        p->occ.as<uint32_t>(), s) != hipSuccess)
         st = set_err(ctx, GC_E_HIP, "capture: place");
     } else if (fixture == GC_FIXTURE_EVICT_STAGED) {
@@ -1637,6 +2171,7 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
 extern "C" gc_status gc_graph_launch(gc_graph g, void* stream) {
   if (!g) return GC_E_INVAL;
   GC_ENTER(g->ctx);
+  for (gc_pool p : g->pools) p->mirror_ok = false;
   GC_HIP(g->ctx, hipGraphLaunch(g->exec, S(stream)));
   return GC_OK;
 }
@@ -1667,50 +2202,218 @@ extern "C" gc_status gc_graph_destroy(gc_graph g) {
 
 // ===================================================================== autotune
 
+// ---------------------------------------------------------------- tuning cache
+// A flat JSON object of entries: {"key": {"tile": 256, ...}, ...}.  Only this layout is read.
+
+struct TuneEntry {
+  int32_t tile = 0, waves = 0, schedule = 0, tpl = 0, agg = 0;
+  double ms = 0.0;
+};
+
+static bool parse_cache(const std::string& txt, std::map<std::string, TuneEntry>& out) {
+  size_t i = 0;
+  auto ws = [&]() { while (i < txt.size() && std::isspace((unsigned char)txt[i])) ++i; };
+  auto str = [&](std::string& v) -> bool {
+    ws();
+    if (i >= txt.size() || txt[i] != '"') return false;
+    size_t j = txt.find('"', i + 1);
+    if (j == std::string::npos) return false;
+    v = txt.substr(i + 1, j - i - 1);
+    i = j + 1;
+    return true;
+  };
+  auto ch = [&](char want) -> bool {
+    ws();
+    if (i < txt.size() && txt[i] == want) {
+      ++i;
+      return true;
+    }
+    return false;
+  };
+  ws();
+  if (i == txt.size()) return true;  // empty file: no entries
+  if (!ch('{')) return false;
+  if (ch('}')) return true;
+  do {
+    std::string key;
+    if (!str(key) || !ch(':') || !ch('{')) return false;
+    TuneEntry e;
+    do {
+      std::string f;
+      if (!str(f) || !ch(':')) return false;
+      ws();
+      char* endp = nullptr;
+      const double v = std::strtod(txt.c_str() + i, &endp);
+      if (endp == txt.c_str() + i) return false;
+      i = (size_t)(endp - txt.c_str());
+      if (f == "tile") e.tile = (int32_t)v;
+      else if (f == "waves_per_block") e.waves = (int32_t)v;
+      else if (f == "schedule") e.schedule = (int32_t)v;
+      else if (f == "targets_per_lane") e.tpl = (int32_t)v;
+      else if (f == "aggregation") e.agg = (int32_t)v;
+      else if (f == "ms") e.ms = v;
+      else return false;
+    } while (ch(','));
+    if (!ch('}')) return false;
+    out[key] = e;
+  } while (ch(','));
+  return ch('}');
+}
+
+static bool write_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n");
+  size_t k = 0;
+  for (const auto& kv : m) {
+    const TuneEntry& e = kv.second;
+    std::fprintf(f,
+                 "  \"%s\": {\"tile\": %d, \"waves_per_block\": %d, \"schedule\": %d, \"targets_per_lane\": %d, "
+                 "\"aggregation\": %d, \"ms\": %.6f}%s\n",
+                 kv.first.c_str(), e.tile, e.waves, e.schedule, e.tpl, e.agg, e.ms, ++k < m.size() ? "," : "");
+  }
+  std::fprintf(f, "}\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+// The cache key of a batch: device, force kind and a 64-bit FNV-1a hash of the batch's shape.
+static std::string tune_key(gc_batch b, const gc_force_params* base) {
+  hipDeviceProp_t pr;
+  std::string arch = "gfx";
+  if (hipGetDeviceProperties(&pr, b->ctx->device) == hipSuccess) arch = pr.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(b->nt);
+  mix(b->n_targets);
+  mix(b->n_direct);
+  mix(b->nn);
+  int64_t hist[8] = {0};  // tasks by target count: 1, 2-3, 4-7, ..., 64-127, >= 128
+  for (const gc_task& t : b->tasks) {
+    int k = 0;
+    while (k < 7 && (1 << (k + 1)) <= t.i_count) ++k;
+    ++hist[k];
+  }
+  for (int64_t v : hist) mix(v);
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s:%dcu:%s:%016llx", arch.c_str(), b->ctx->n_cu,
+                base->kind == GC_FORCE_GRAV_QUAD ? "grav_quad" : "grav_mono", (unsigned long long)h);
+  return buf;
+}
+
 extern "C" gc_status gc_autotune(gc_batch b, const gc_force_params* base, const float* nodes_dev, float* acc_dev,
-                                 int32_t reps, float* times_ms, gc_force_params* best, void* stream) {
+                                 int32_t reps, float* times_ms, gc_force_params* best, const char* cache_path,
+                                 int32_t* from_cache, void* stream) {
   if (!b) return GC_E_INVAL;
   gc_ctx c = b->ctx;
   GC_ENTER(c);
   if (!base || !best || reps < 1) return set_err(c, GC_E_INVAL, "gc_autotune: bad arguments");
+  if (b->kind != GC_KIND_GRAV) return set_err(c, GC_E_UNSUPPORTED, "gc_autotune: gravity batches only");
+  if (from_cache) *from_cache = 0;
   hipStream_t s = S(stream);
+  std::map<std::string, TuneEntry> cache;
+  std::string key;
+  if (cache_path) {
+    gc_status hs = need_host_lists(b, s);  // the key hashes the task sizes
+    if (hs != GC_OK) return hs;
+    key = tune_key(b, base);
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      std::string txt;
+      char buf[4096];
+      size_t n;
+      while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+      std::fclose(f);
+      if (!parse_cache(txt, cache)) return set_err(c, GC_E_INVAL, "gc_autotune: %s is not a tuning cache", cache_path);
+    }
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      *best = *base;
+      best->tile = it->second.tile;
+      best->waves_per_block = it->second.waves;
+      best->schedule = it->second.schedule;
+      best->grid_blocks = 0;
+      best->targets_per_lane = it->second.tpl;
+      best->aggregation = it->second.agg;
+      if (from_cache) *from_cache = 1;
+      return GC_OK;
+    }
+  }
   hipEvent_t e0, e1;
   GC_HIP(c, hipEventCreate(&e0));
   GC_HIP(c, hipEventCreate(&e1));
-  const int tiles[3] = {128, 256, 512}, waves[3] = {2, 4, 8};
   float best_t = 1e30f;
-  int idx = 0;
   gc_status st = GC_OK;
+  auto time_one = [&](const gc_force_params& p, int idx) {
+    st = launch_combined_async(b, &p, nodes_dev, acc_dev, s);  // warm-up
+    if (st != GC_OK) return;
+    hipError_t e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == GC_OK && e == hipSuccess; ++r) st = launch_combined_async(b, &p, nodes_dev, acc_dev, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) st = hip_fail(c, e, "gc_autotune timing");
+    if (st != GC_OK) return;
+    ms /= reps;
+    if (times_ms) times_ms[idx] = ms;
+    if (ms < best_t) {
+      best_t = ms;
+      *best = p;
+    }
+  };
+  const int tiles[3] = {128, 256, 512}, waves[3] = {2, 4, 8};
+  int idx = 0;
   for (int ti = 0; ti < 3 && st == GC_OK; ++ti)
     for (int wi = 0; wi < 3 && st == GC_OK; ++wi)
       for (int sc = 0; sc < 2 && st == GC_OK; ++sc)
-      for (int tp = 1; tp <= 2 && st == GC_OK; ++tp, ++idx) {
-        gc_force_params p = *base;
-        p.tile = tiles[ti];
-        p.waves_per_block = waves[wi];
-        p.schedule = sc;
-        p.grid_blocks = 0;
-        p.targets_per_lane = tp;
-        st = launch_combined_async(b, &p, nodes_dev, acc_dev, s);  // warm-up
-        if (st != GC_OK) break;
-        hipError_t e = hipEventRecord(e0, s);
-        for (int r = 0; r < reps && st == GC_OK && e == hipSuccess; ++r) st = launch_combined_async(b, &p, nodes_dev, acc_dev, s);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) st = hip_fail(c, e, "gc_autotune timing");
-        if (st != GC_OK) break;
-        ms /= reps;
-        if (times_ms) times_ms[idx] = ms;
-        if (ms < best_t) {
-          best_t = ms;
-          *best = p;
+        for (int tp = 1; tp <= 2 && st == GC_OK; ++tp, ++idx) {
+          gc_force_params p = *base;
+          p.tile = tiles[ti];
+          p.waves_per_block = waves[wi];
+          p.schedule = sc;
+          p.grid_blocks = 0;
+          p.targets_per_lane = tp;
+          p.aggregation = 0;
+          time_one(p, idx);
         }
-      }
+  if (st == GC_OK) {
+    // the aggregation count, with the best shape: all tasks, then multiples of the occupancy-sized count
+    const gc_force_params shape = *best;
+    int per = 1;
+    const int order = base->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
+    const bool lists = b->mode == GC_REORG_INDIRECT || b->mode == GC_REORG_SORTED;
+    hipError_t e = grav_occupancy(order, lists, shape.schedule == 1, shape.targets_per_lane == 2,
+                                  shape.tile ? shape.tile : 256, shape.waves_per_block ? shape.waves_per_block : 4, &per);
+    if (e != hipSuccess) st = hip_fail(c, e, "gc_autotune occupancy");
+    const int32_t occ = std::max(1, per) * c->n_cu;
+    const int32_t counts[4] = {0, 2 * occ, occ, std::max(1, occ / 2)};
+    for (int k = 0; k < 4 && st == GC_OK; ++k) {
+      gc_force_params p = shape;
+      p.aggregation = counts[k];
+      time_one(p, 36 + k);
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return st;
+  if (st != GC_OK || !cache_path) return st;
+  TuneEntry te;
+  te.tile = best->tile;
+  te.waves = best->waves_per_block;
+  te.schedule = best->schedule;
+  te.tpl = best->targets_per_lane;
+  te.agg = best->aggregation;
+  te.ms = best_t;
+  cache[key] = te;
+  if (!write_cache(cache_path, cache)) return set_err(c, GC_E_INVAL, "gc_autotune: cannot write %s", cache_path);
+  return GC_OK;
 }
 
 // ===================================================================== interaction lists (tree walk)

@@ -198,3 +198,16 @@ def test_lj_gather_form_zeroes_untouched_atoms(ctx):
     cells = np.nonzero((nc > 0) & touched[np.minimum(w.cell_start[:-1], w.n - 1)])[0]
     err = O.per_task_rel_l2(acc[:, :3].astype(np.float64), ref, w.cell_start[cells], nc[cells], floor_frac=0.0)
     assert err.max() <= TOL, err.max()
+
+
+def test_lj_in_cutoff_pair_count_matches_oracle(ctx):
+    # the device count of pairs inside the cutoff (the algorithmic work of a pass) equals the oracle's
+    # count exactly: both take the cutoff decision in the same FP32 operations
+    xyz, v, L = W.fcc_modulated(16, 14, 14, 0.8442, 11000, seed=80)
+    w = W.build_lj(xyz, W.two_types(xyz.shape[0], 8), L, 2.5, **W.LJ_TWO_TYPES)
+    rig = LJRig(ctx, w)
+    rig.b.reorganize(rig.pool, gc.REORG_NONE)
+    got = rig.b.lj_count_pairs(w.rcut)
+    _, _, want = O.lj_tasks(w, potential=True)
+    assert got == want and got > 0
+    rig.close()

@@ -96,10 +96,12 @@ def time_kernel(fn, stream, reps: int = 10) -> float:
 
 
 def leg_instances(gc, W, torch, ctx, args):
-    """64 independent Plummer instances (sizes log-uniform in 2,048..262,144): the plain form (one
-    combined launch per instance, in order on one stream) versus graph-captured launches of 1, 8 or
-    64 instances each (aggregation count and schedule picked by timing; one instance per launch
-    there still overlaps on the graph's side streams)."""
+    """64 independent Plummer instances (sizes log-uniform in 2,048..262,144) in one id space.  Against
+    each other: the plain per-instance form (one combined launch per instance, in order on one stream,
+    default shape), a HIP graph of per-instance launches (tuned shape; launches overlap on the graph's
+    side streams), and every task of all instances in one batch: one launch with the autotuner's
+    shape (its aggregation count tuned too), captured in a graph.  Then the whole batch's
+    reorganisation (PACK) with half of all ids resident at random slots: the aggregated reorganise."""
     t0 = time.time()
     w = W.nbody_instances(k=64, seed=4000)
     inst = w.meta["instance_of_task"]
@@ -116,58 +118,86 @@ def leg_instances(gc, W, torch, ctx, args):
     stream = torch.cuda.current_stream()
     res = {"workload": f"nbody-plummer-x64 (N={w.n}, {w.n_tasks} tasks, {inter} interactions)"}
 
-    def batches_for(k):
-        out = []
-        for g0 in range(0, 64, k):
-            sel = np.nonzero((inst >= g0) & (inst < g0 + k))[0]
-            bt = W.task_subset(w, sel)
-            b = gc.Batch(ctx, gc.KIND_GRAV, w.n)
-            b.submit(gc.tasks_from_csr(bt["i_begin"], bt["i_count"], bt["j_first"], bt["j_nr"], bt["n_first"],
-                                       bt["n_count"]), bt["ranges"], bt["node_idx"])
-            b.commit()
-            b.reorganize(pool, gc.REORG_NONE)
-            out.append(b)
-        return out
+    def batch_of(sel, mode=gc.REORG_NONE, p=pool):
+        bt = W.task_subset(w, sel)
+        b = gc.Batch(ctx, gc.KIND_GRAV, w.n)
+        b.submit(gc.tasks_from_csr(bt["i_begin"], bt["i_count"], bt["j_first"], bt["j_nr"], bt["n_first"],
+                                   bt["n_count"]), bt["ranges"], bt["node_idx"])
+        b.commit()
+        b.reorganize(p, mode)
+        return b
 
-    best = None
-    per = {}
-    plain = None
-    for k in (1, 8, 64):
-        bs = batches_for(k)
-        if k == 1:
-            # the plain per-instance form: one combined launch per instance, in order on one stream
-            prm0 = gc.grav_params(order=2)
+    # one batch over every instance; the autotuner picks the shape, then the aggregation count
+    allb = batch_of(np.arange(w.n_tasks))
+    best, times, _ = allb.autotune(gc.grav_params(order=2), nodes, acc, reps=2)
+    shape = dict(tile=best.tile, waves_per_block=best.waves_per_block, schedule=best.schedule,
+                 targets_per_lane=best.targets_per_lane)
+    one = gc.grav_params(order=2, aggregation=0, **shape)
+    res["autotuned"] = dict(shape, aggregation=best.aggregation, one_launch_ms=round(float(times[36]), 4),
+                            aggregation_ms=[round(float(x), 4) for x in times[36:]])
+    # the plain per-instance form
+    per = [batch_of(np.nonzero(inst == k)[0]) for k in range(64)]
+    prm0 = gc.grav_params(order=2)
 
-            def run_plain():
-                for b in bs:
-                    b.launch(prm0, nodes, acc)
-            plain = time_kernel(run_plain, stream, reps=3)
-        for sched in (0, 1):
-            prm = gc.grav_params(order=2, schedule=sched)
-            side = torch.cuda.Stream()
-            g = gc.Graph(ctx, bs, [pool] * len(bs), [gc.REORG_NONE] * len(bs), prm, nodes, acc, stream=side)
-            torch.cuda.synchronize()
-            ms = time_kernel(lambda: g.launch(stream=stream), stream, reps=5)
-            g.destroy()
-            per[f"agg{k}_sched{sched}"] = round(ms, 4)
-            if best is None or ms < best[0]:
-                best = (ms, k, sched)
-        for b in bs:
-            b.destroy()
-    base = per["agg1_sched0"]
-    res.update({"plain_per_instance_ms": round(plain, 4), "speedup_vs_plain_per_instance": round(plain / best[0], 3),
-                "per_launch_ms": per, "per_instance_ms": base,
-                "per_instance_ginteractions_per_s": round(inter / (base * 1e-3) / 1e9, 3),
-                "best": {"aggregation": best[1], "schedule": best[2], "ms": round(best[0], 4),
-                         "ginteractions_per_s": round(inter / (best[0] * 1e-3) / 1e9, 3),
-                         "tflops": round(flops / (best[0] * 1e-3) / 1e12, 3)},
-                "speedup_vs_per_instance": round(base / best[0], 3)})
-    bt = flops / (best[0] * 1e-3) / 1e12
+    def run_plain():
+        for b in per:
+            b.launch(prm0, nodes, acc)
+    plain = time_kernel(run_plain, stream, reps=3)
+    # a graph of per-instance launches with the tuned shape
+    side = torch.cuda.Stream()
+    g = gc.Graph(ctx, per, [pool] * 64, [gc.REORG_NONE] * 64, gc.grav_params(order=2, **shape), nodes, acc,
+                 stream=side)
+    torch.cuda.synchronize()
+    per_graph = time_kernel(lambda: g.launch(stream=stream), stream, reps=5)
+    g.destroy()
+    for b in per:
+        b.destroy()
+    # the whole batch in one launch, captured
+    g1 = gc.Graph(ctx, [allb], [pool], [gc.REORG_NONE], one, nodes, acc, stream=side)
+    torch.cuda.synchronize()
+    one_ms = time_kernel(lambda: g1.launch(stream=stream), stream, reps=5)
+    g1.destroy()
+    forms = {"plain_per_instance_ms": round(plain, 4), "per_instance_graph_ms": round(per_graph, 4),
+             "one_launch_graph_ms": round(one_ms, 4)}
+    best_form = min(forms, key=forms.get)
+    res.update({"forms": forms, "best_form": best_form,
+                "one_launch_vs_plain_per_instance": round(plain / one_ms, 3),
+                "one_launch_vs_per_instance_graph": round(per_graph / one_ms, 3),
+                "one_launch_ginteractions_per_s": round(inter / (one_ms * 1e-3) / 1e9, 3)})
+    bt = flops / (one_ms * 1e-3) / 1e12
     res["roofline"] = {"bound": "alu", "achieved": round(bt, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(bt / PEAK_FP32_TFLOPS, 4), "flops_per_launch": int(flops),
-                       "kernel": f"best form: aggregation {best[1]}, schedule {best[2]} (all 64 instances per replay)",
+                       "avg_launch_ms": round(one_ms, 5),
+                       "kernel": f"k_grav<2> over all {w.n_tasks} tasks (tile {best.tile}, {best.waves_per_block} "
+                                 f"waves, schedule {best.schedule}, {best.targets_per_lane} targets per lane)",
                        "frac_of_nonpacked_peak": round(bt / PEAK_FP32_NONPACKED_TFLOPS, 4)}
+    allb.destroy()
     pool.destroy()
+    # the aggregated reorganisation: PACK of the whole batch's union, half of all ids resident at random
+    # slots of a pool of capacity N (each call stages the other half, after evicting the last call's)
+    pool2 = gc.Pool(ctx, w.n, w.n)
+    pool2.set_source(src)
+    bids, bslots = W.residency(np.arange(w.n, dtype=np.int32), w.n, 0.5, seed=4999)
+    pool2.place(torch.from_numpy(bids).to(dev), torch.from_numpy(bslots).to(dev))
+    rb = batch_of(np.arange(w.n_tasks), gc.REORG_PACK, pool2)
+    torch.cuda.synchronize()
+    nu, nm = int(rb.maps()["U"].size), int(rb.maps()["missing"].size)
+    ms = 0.0
+    for _ in range(5):
+        pool2.evict_staged(rb)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rb.reorganize(pool2, gc.REORG_PACK, check_capacity=False)
+        e1.record(stream)
+        e1.synchronize()
+        ms += e0.elapsed_time(e1) / 5
+    rb.status()
+    alg = nu * (16 + 16 + 4 + 4) + nm * 16
+    gbps = alg / (ms * 1e-3) / 1e9
+    res["aggregated_reorganize"] = {"union": nu, "missing": nm, "ms": round(ms, 4), "algorithmic_bytes": int(alg),
+                                    "gbps": round(gbps, 1), "frac_hbm": round(gbps / PEAK_HBM_GBPS, 4)}
+    rb.destroy()
+    pool2.destroy()
     return res
 
 
@@ -398,6 +428,13 @@ def leg_reorg_stress(gc, torch, ctx, log2_pool: int = 26, log2_union: int = 24, 
     b.destroy()
     pool.destroy()
     del src
+    # a plain copy of known size (256 MiB read + 256 MiB written) in the same run: the reference that
+    # scales a profiler's FETCH_SIZE / WRITE_SIZE counters to bytes
+    cx = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    cy = torch.empty_like(cx)
+    cy.copy_(cx)
+    torch.cuda.synchronize()
+    del cx, cy
     gbps = alg / (ms * 1e-3) / 1e9
     return {"workload": f"pool 2^{log2_pool} records, union 2^{log2_union} ids (runs of {run}), half resident "
                         f"at random slots, PACK", "kernel": "k_reorg", "ms": round(ms, 4), "union": nu,
@@ -431,11 +468,20 @@ def leg_staging(gc, W, torch, ctx, w, rounds, prm, nodes, steps: int = 10):
         batches.append(b)
     side = torch.cuda.Stream()
 
-    def one(mode, use_side):
+    host = {"evict": 0.0, "reorganize": 0.0, "launch": 0.0}
+
+    def one(mode, use_side, clock=False):
         for k, b in enumerate(batches):
+            t0 = time.perf_counter()
             pool.evict_staged(batches[k - 1])
+            t1 = time.perf_counter()
             b.reorganize(pool, mode, check_capacity=False, side=side if use_side else None)
+            t2 = time.perf_counter()
             b.launch(prm, nodes, acc)
+            if clock:
+                host["evict"] += t1 - t0
+                host["reorganize"] += t2 - t1
+                host["launch"] += time.perf_counter() - t2
 
     out = {"workload": f"nbody-plummer-{w.n}, {len(rounds)} rounds, source records in pageable host memory"}
     for name, mode, use_side in (("pack_side_stream", gc.REORG_PACK, True), ("pack_one_stream", gc.REORG_PACK, False),
@@ -445,9 +491,10 @@ def leg_staging(gc, W, torch, ctx, w, rounds, prm, nodes, steps: int = 10):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            one(mode, use_side)
+            one(mode, use_side, clock=name == "pack_side_stream")
         torch.cuda.synchronize()
         out[f"{name}_ms"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+    out["host_ms_per_step_pack_side_stream"] = {k: round(v * 1e3 / steps, 4) for k, v in host.items()}
     sizes = []
     for b in batches:
         m = b.maps()
@@ -605,7 +652,8 @@ def main():
     ap.add_argument("--targets-per-lane", type=int, default=0, help="with --tile: 1 or 2 targets per lane")
     ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 256, 320 and 384")
     ap.add_argument("--step-tpl", type=int, default=0, help="fixed targets per lane of the whole-step launch instead of timing 1 and 2")
-    ap.add_argument("--leg", default="", choices=["", "reorg-stress", "staging", "rebuild", "lj", "instances"],
+    ap.add_argument("--leg", default="", choices=["", "reorg-stress", "staging", "rebuild", "lj", "instances",
+                                                  "combined"],
                     help="run one measurement leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -641,6 +689,23 @@ def main():
     dev = torch.device("cuda")
     src = torch.from_numpy(w.rec).to(dev)
     nodes = torch.from_numpy(w.nodes).to(dev)
+    if args.leg == "combined":
+        # every task of the step in one launch, no reorganisation: the autotuner's shapes
+        allb = gc.Batch(ctx, gc.KIND_GRAV, w.n)
+        allb.submit(gc.tasks_from_csr(w.i_begin, w.i_count, w.j_first, w.j_nr, w.n_first, w.n_count), w.ranges,
+                    w.node_idx)
+        allb.commit()
+        pl = gc.Pool(ctx, w.n, 1)
+        pl.set_source(src)
+        allb.reorganize(pl, gc.REORG_NONE)
+        acc = torch.zeros((w.n, 4), dtype=torch.float32, device=dev)
+        b2, t2, _ = allb.autotune(gc.grav_params(order=2), nodes, acc, reps=5)
+        names = [f"t{t}_w{wv}_s{sc}_p{tp}" for t in (128, 256, 512) for wv in (2, 4, 8) for sc in (0, 1) for tp in (1, 2)]
+        print(json.dumps({"leg": "combined", "best": dict(tile=b2.tile, waves=b2.waves_per_block, schedule=b2.schedule,
+                                                          tpl=b2.targets_per_lane, aggregation=b2.aggregation),
+                          "ms": {n: round(float(x), 4) for n, x in zip(names, t2)},
+                          "aggregation_ms": [round(float(x), 4) for x in t2[36:]]}), flush=True)
+        return
     if args.leg in ("staging", "rebuild"):
         p2 = gc.grav_params(order=2, G=1.0, eps=0.01, tile=320, targets_per_lane=2)
         out = leg_staging(gc, W, torch, ctx, w, rounds, p2, nodes) if args.leg == "staging" else \
@@ -886,9 +951,17 @@ def main():
                     w.node_idx)
         allb.commit()
         allb.reorganize(pool, gc.REORG_NONE)
-        ms_all = time_kernel(lambda: allb.launch(prm, nodes, acc), stream)
+        ball, tall, _ = allb.autotune(gc.grav_params(order=2, G=1.0, eps=0.01), nodes, acc, reps=3)
+        pall = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=ball.schedule, tile=ball.tile,
+                              waves_per_block=ball.waves_per_block, targets_per_lane=ball.targets_per_lane)
+        ms_all = time_kernel(lambda: allb.launch(pall, nodes, acc), stream)
         combined_all = {"ms": round(ms_all, 4), "tflops": round(flops_step / (ms_all * 1e-3) / 1e12, 3),
-                        "ginteractions_per_s": round(interactions / (ms_all * 1e-3) / 1e9, 3)}
+                        "ginteractions_per_s": round(interactions / (ms_all * 1e-3) / 1e9, 3),
+                        "shape": dict(tile=ball.tile, waves_per_block=ball.waves_per_block, schedule=ball.schedule,
+                                      targets_per_lane=ball.targets_per_lane),
+                        "shape_ms": {f"t{t}_w{wv}_s{sc}_p{tp}": round(float(tall[i]), 4) for i, (t, wv, sc, tp) in
+                                     enumerate((t, wv, sc, tp) for t in (128, 256, 512) for wv in (2, 4, 8)
+                                               for sc in (0, 1) for tp in (1, 2))}}
         allb.destroy()
     occ_blocks, n_cu = ctx.occupancy(prm)
     step_occ = ctx.occupancy(sprm)[0] if sprm is not None else None

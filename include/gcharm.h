@@ -411,9 +411,15 @@ typedef struct {
                                from LDS serves two interactions (same results) */
   int32_t n_nodes;          /* gravity: node records in nodes_dev; every node index the
                                batch holds must be below it (GC_E_INVAL otherwise) */
-  int32_t want_potential;   /* 1: also write the potential in acc.w (gravity: phi_i of
-                               the lists' terms; Lennard-Jones: half the pair energies
-                               of the atom's pairs, shifted at the cutoff: see below) */
+  int32_t want_potential;   /* gravity, 1: also write in acc.w the potential of the
+                               target's terms, phi_i = -G [sum over its direct sources
+                               j != i of m_j / (|x_j - x_i|^2 + eps^2)^{1/2} + sum over
+                               its nodes of M/r + 3/2 d.S.d / r^5 - T / (2 r^3)], the
+                               function whose negative gradient is the acceleration
+                               (one workgroup per task and one target per lane: the
+                               schedule and targets_per_lane fields are not used);
+                               GC_E_UNSUPPORTED for Lennard-Jones, address-list modes
+                               and the whole-step schedule */
   int32_t deterministic;    /* 1: results must be the same bits on every call; a path
                                that sums with atomics then returns GC_E_UNSUPPORTED */
   int32_t aggregation;      /* gravity: tasks combined per launch (Sec. 3.1: how many

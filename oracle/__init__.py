@@ -46,7 +46,7 @@ def _load():
         build_native(force=False)
     lib = ctypes.CDLL(_LIB_PATH)
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
-    lib.or_grav_lists.argtypes = [i32, I32, I32, I32, I32, I32, I32, I32, I32, F64, F64, F64, i32, dbl, dbl, F64]
+    lib.or_grav_lists.argtypes = [i32, I32, I32, I32, I32, I32, I32, I32, I32, F64, F64, F64, i32, dbl, dbl, F64, F64]
     lib.or_grav_brute.argtypes = [i64, F64, F64, dbl, dbl, F64, F64]
     lib.or_node_acc_points.argtypes = [i64, F64, F64, i32, dbl, dbl, F64]
     lib.or_node_moments.argtypes = [i32, I32, F64, F64, F64]
@@ -95,18 +95,21 @@ def moments_from_nodes32(nodes32: np.ndarray) -> np.ndarray:
 
 # ---------------------------------------------------------------- gravity
 
-def grav_lists(tasks: dict, pos, mass, mom, order: int, G: float = 1.0, eps: float = 0.01, n: int | None = None):
-    """Acceleration (n x 3, FP64) of every target id over its task's lists; rows of ids not targeted stay NaN."""
+def grav_lists(tasks: dict, pos, mass, mom, order: int, G: float = 1.0, eps: float = 0.01, n: int | None = None,
+               potential: bool = False):
+    """Acceleration (n x 3, FP64) of every target id over its task's lists; rows of ids not targeted stay NaN.
+    With potential: (acc, pot) with pot (n) the potential of the same terms."""
     lib = _load()
     pos, mass, mom = _d(pos), _d(mass), _d(mom)
     n = pos.shape[0] if n is None else n
     acc = np.full((n, 3), np.nan)
+    pot = np.full(n, np.nan) if potential else None
     t = {k: _i(v) for k, v in tasks.items()}
     lib.or_grav_lists(int(t["i_begin"].shape[0]), _p(t["i_begin"], I32), _p(t["i_count"], I32), _p(t["n_first"], I32),
                       _p(t["n_count"], I32), _p(t["j_first"], I32), _p(t["j_nr"], I32), _p(t["node_idx"], I32),
                       _p(t["ranges"], I32), _p(pos, F64), _p(mass, F64), _p(mom, F64), int(order), G, eps,
-                      _p(acc, F64))
-    return acc
+                      _p(acc, F64), _p(pot, F64) if potential else None)
+    return (acc, pot) if potential else acc
 
 
 def grav_brute(pos, mass, G: float = 1.0, eps: float = 0.01, potential: bool = False):
@@ -140,11 +143,13 @@ def workload_tasks(w) -> dict:
                 j_nr=w.j_nr, node_idx=w.node_idx, ranges=w.ranges)
 
 
-def grav_workload(w, order: int, G: float = 1.0, eps: float = 0.01, tasks: dict | None = None):
-    """Oracle accelerations for a GravWorkload's FP32 records and FP32 node table (promoted)."""
+def grav_workload(w, order: int, G: float = 1.0, eps: float = 0.01, tasks: dict | None = None,
+                  potential: bool = False):
+    """Oracle accelerations (and with potential, (acc, pot)) for a GravWorkload's FP32 records and FP32
+    node table (promoted)."""
     rec = w.rec.astype(np.float64)
     return grav_lists(tasks if tasks is not None else workload_tasks(w), rec[:, :3], rec[:, 3],
-                      moments_from_nodes32(w.nodes), order, G, eps)
+                      moments_from_nodes32(w.nodes), order, G, eps, potential=potential)
 
 
 # ---------------------------------------------------------------- maps

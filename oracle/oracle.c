@@ -99,27 +99,61 @@ static void node_acc(const double* x, const double* mom, int order, double G, do
   }
 }
 
+/* Potential at x of a source (xs, m), Plummer softening: -G m / sqrt(|xs - x|^2 + eps^2). */
+static double pair_pot(const double* x, const double* xs, double m, double G, double eps2) {
+  double u0 = xs[0] - x[0], u1 = xs[1] - x[1], u2 = xs[2] - x[2];
+  return -G * m / sqrt(u0 * u0 + u1 * u1 + u2 * u2 + eps2);
+}
+
+/* Potential of a node term, the function whose negative gradient node_acc adds: the second-order
+ * Taylor expansion of the members' softened potential about their centre of mass,
+ * -G [M / r + (3/2) d.S.d / r^5 - (1/2) T / r^3] (order 1: -G M / r). */
+static double node_pot(const double* x, const double* mom, int order, double G, double eps2) {
+  double d0 = x[0] - mom[0], d1 = x[1] - mom[1], d2 = x[2] - mom[2];
+  double r2 = d0 * d0 + d1 * d1 + d2 * d2 + eps2;
+  double r = sqrt(r2);
+  double r3 = r2 * r, r5 = r3 * r2;
+  double phi = mom[3] / r;
+  if (order >= 2) {
+    double Sxx = mom[4], Syy = mom[5], Szz = mom[6], Sxy = mom[7], Sxz = mom[8], Syz = mom[9];
+    double dSd = d0 * (Sxx * d0 + Sxy * d1 + Sxz * d2) + d1 * (Sxy * d0 + Syy * d1 + Syz * d2) +
+                 d2 * (Sxz * d0 + Syz * d1 + Szz * d2);
+    double T = Sxx + Syy + Szz;
+    phi += 1.5 * dSd / r5 - 0.5 * T / r3;
+  }
+  return -G * phi;
+}
+
 /* Sum over each task's lists.  pos: n x 3, mass: n, mom: nnodes x 10.
- * acc (n x 3) is written for every id in every task's target range. */
+ * acc (n x 3) is written for every id in every task's target range; pot (optional, n) gets the
+ * potential of the same terms (sources j != i). */
 void or_grav_lists(int32_t ntasks, const int32_t* i_begin, const int32_t* i_count, const int32_t* n_first,
                    const int32_t* n_count, const int32_t* j_first, const int32_t* j_nr, const int32_t* node_idx,
                    const int32_t* ranges, const double* pos, const double* mass, const double* mom, int32_t order,
-                   double G, double eps, double* acc) {
+                   double G, double eps, double* acc, double* pot) {
   double eps2 = eps * eps;
 #pragma omp parallel for schedule(dynamic, 4)
   for (int32_t t = 0; t < ntasks; ++t) {
     for (int32_t i = i_begin[t]; i < i_begin[t] + i_count[t]; ++i) {
       double a[3] = {0, 0, 0};
-      for (int32_t k = 0; k < n_count[t]; ++k)
-        node_acc(pos + 3 * (size_t)i, mom + 10 * (size_t)node_idx[n_first[t] + k], order, G, eps2, a);
+      double phi = 0.0;
+      for (int32_t k = 0; k < n_count[t]; ++k) {
+        const double* m = mom + 10 * (size_t)node_idx[n_first[t] + k];
+        node_acc(pos + 3 * (size_t)i, m, order, G, eps2, a);
+        if (pot) phi += node_pot(pos + 3 * (size_t)i, m, order, G, eps2);
+      }
       for (int32_t r = 0; r < j_nr[t]; ++r) {
         int32_t b = ranges[2 * (size_t)(j_first[t] + r)], c = ranges[2 * (size_t)(j_first[t] + r) + 1];
         for (int32_t j = b; j < b + c; ++j)
-          if (j != i) pair_acc(pos + 3 * (size_t)i, pos + 3 * (size_t)j, mass[j], G, eps2, a);
+          if (j != i) {
+            pair_acc(pos + 3 * (size_t)i, pos + 3 * (size_t)j, mass[j], G, eps2, a);
+            if (pot) phi += pair_pot(pos + 3 * (size_t)i, pos + 3 * (size_t)j, mass[j], G, eps2);
+          }
       }
       acc[3 * (size_t)i] = a[0];
       acc[3 * (size_t)i + 1] = a[1];
       acc[3 * (size_t)i + 2] = a[2];
+      if (pot) pot[i] = phi;
     }
   }
 }

@@ -139,6 +139,9 @@ hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, con
 hipError_t launch_grav(int order, bool lists, bool persistent, bool two, const GravArgs& a, int waves_per_block,
                        int grid_blocks, hipStream_t s);
 hipError_t grav_occupancy(int order, bool lists, bool persistent, bool two, int tile, int waves_per_block, int* blocks);
+// the same pass with the potential in acc.w: one workgroup per task, one target per lane, records in
+// position space (not address lists)
+hipError_t launch_grav_potential(int order, const GravArgs& a, int waves_per_block, hipStream_t s);
 hipError_t launch_lj(bool persistent, const LJArgs& a, int waves_per_block, int grid_blocks, hipStream_t s);
 // gather form: every target range's atoms written once (F / m), no atomics
 hipError_t launch_lj_gather(bool persistent, const LJArgs& a, int grid_blocks, hipStream_t s);

@@ -10,25 +10,36 @@ using dev::grav_lds_per_wave;
 using dev::grav_task;
 using dev::uniform;
 
-template <int ORDER, bool LISTS, bool PERSIST, bool TWO>
+// Tasks a persistent block takes per grab of the shared counter (consecutive tasks of the
+// longest-first order have similar costs, so a grab of a few keeps the blocks balanced while the
+// counter, one address for the whole grid, sees a few times fewer atomics).
+constexpr int kGrabTasks = 4;
+
+template <int ORDER, bool LISTS, bool PERSIST, bool TWO, bool POT = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k_grav(GravArgs a) {
   extern __shared__ float4 smem[];
   __shared__ int s_task;
   int iter = 0;
+  int chunk = 0, left = 0;
   while (true) {
     // Tasks run in longest-first order: block b starts with order[b]; in the persistent
-    // schedule later tasks come from a device counter (offset by the grid size), so the
-    // first wave of grabs needs no atomics.
+    // schedule block b first takes tasks [b k, b k + k) (k = kGrabTasks) and later grabs of k come
+    // from a device counter (offset by the grid's first grabs), so the first grabs need no atomics.
     int got;
     if (PERSIST) {
-      if (iter == 0) {
-        got = blockIdx.x;
-      } else {
-        if (threadIdx.x == 0) s_task = (int)gridDim.x + atomicAdd(a.queue, 1);
-        __syncthreads();
-        got = uniform(s_task);
-        __syncthreads();
+      if (left == 0) {
+        if (iter == 0) {
+          chunk = (int)blockIdx.x * kGrabTasks;
+        } else {
+          if (threadIdx.x == 0) s_task = (int)gridDim.x * kGrabTasks + atomicAdd(a.queue, kGrabTasks);
+          __syncthreads();
+          chunk = uniform(s_task);
+          __syncthreads();
+        }
+        left = kGrabTasks;
       }
+      got = chunk + (kGrabTasks - left);
+      --left;
       ++iter;
     } else {
       if (iter++) break;
@@ -40,7 +51,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k
     const dev::TaskDesc td{uniform(g.i_begin), uniform(g.i_count), uniform(g.j_first), uniform(g.j_nranges),
                            uniform(g.n_first), uniform(g.n_count), uniform(a.ibeg ? a.ibeg[t] : g.i_begin)};
     dev::NodePrefetch<ORDER> pf;
-    grav_task<ORDER, LISTS, TWO>(a, t, td, smem, pf, false, [] {}, [](int) {});
+    grav_task<ORDER, LISTS, TWO, POT>(a, t, td, smem, pf, false, [] {}, [](int) {});
   }
 }
 
@@ -81,7 +92,25 @@ hipError_t occ_two(bool two, int tile, int wpb, int* blocks) {
              : occ_one<ORDER, LISTS, PERSIST, false>(tile, wpb, blocks);
 }
 
+// The potential variant: one workgroup per task, one target per lane, records in position space.
+template <int ORDER>
+hipError_t launch_pot(const GravArgs& a, int wpb, hipStream_t s) {
+  const size_t lds = (size_t)wpb * grav_lds_per_wave(a.tile, true) * sizeof(float4);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, false, false, false, true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_grav<ORDER, false, false, false, true>), dim3(a.n_tasks), dim3(64 * wpb), lds, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_grav_potential(int order, const GravArgs& a, int wpb, hipStream_t s) {
+  if (a.n_tasks <= 0) return hipSuccess;
+  return order == 1 ? launch_pot<1>(a, wpb, s) : launch_pot<2>(a, wpb, s);
+}
 
 hipError_t launch_grav(int order, bool lists, bool persistent, bool two, const GravArgs& a, int wpb, int grid,
                        hipStream_t s) {

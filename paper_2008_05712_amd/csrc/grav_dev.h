@@ -111,6 +111,50 @@ __device__ __forceinline__ void tile_quads(const float4* __restrict__ p, int C, 
   }
 }
 
+// The same tiles with the potential: ph accumulates m r^-1 (pair, monopole) and, for a quadrupole
+// node, M r^-1 + 1/2 (d.S'.d) r^-5 - (1.5 T / 3) r^-3 with S' = 3 S, i.e. M/r + 3/2 d.S.d/r^5 - T/(2r^3);
+// the caller scales by -G.
+__device__ __forceinline__ void tile_pairs_pot(const float4* __restrict__ p, int C, float xi, float yi, float zi,
+                                               float eps2, float& ax, float& ay, float& az, float& ph) {
+  for (int k = 0; k < C; ++k) {
+    float4 j = p[k];
+    float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
+    float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+    float ri = __builtin_amdgcn_rsqf(r2);
+    float mr = j.w * ri;
+    float ri2 = ri * ri;
+    float sc = mr * ri2;
+    ax = __builtin_fmaf(dx, sc, ax);
+    ay = __builtin_fmaf(dy, sc, ay);
+    az = __builtin_fmaf(dz, sc, az);
+    ph += mr;
+  }
+}
+
+__device__ __forceinline__ void tile_quads_pot(const float4* __restrict__ p, int C, float xi, float yi, float zi,
+                                               float eps2, float& ax, float& ay, float& az, float& ph) {
+  for (int k = 0; k < C; ++k) {
+    float4 a = p[3 * k], b = p[3 * k + 1], c = p[3 * k + 2];
+    float dx = xi - a.x, dy = yi - a.y, dz = zi - a.z;
+    float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+    float ri = __builtin_amdgcn_rsqf(r2);
+    float q = ri * ri;
+    float r3 = ri * q;
+    float r5 = r3 * q;
+    float sx = __builtin_fmaf(c.x, dz, __builtin_fmaf(b.w, dy, b.x * dx));
+    float sy = __builtin_fmaf(c.y, dz, __builtin_fmaf(b.y, dy, b.w * dx));
+    float sz = __builtin_fmaf(b.z, dz, __builtin_fmaf(c.y, dy, c.x * dx));
+    float dsd = __builtin_fmaf(dz, sz, __builtin_fmaf(dy, sy, dx * sx));
+    float u = __builtin_fmaf(dsd, q * -2.5f, c.z);
+    float v = __builtin_fmaf(q, u, -a.w);
+    float cf = r3 * v;
+    ax = __builtin_fmaf(r5, sx, __builtin_fmaf(cf, dx, ax));
+    ay = __builtin_fmaf(r5, sy, __builtin_fmaf(cf, dy, ay));
+    az = __builtin_fmaf(r5, sz, __builtin_fmaf(cf, dz, az));
+    ph += __builtin_fmaf(0.5f * dsd, r5, __builtin_fmaf(a.w, ri, c.z * (-1.f / 3.f) * r3));
+  }
+}
+
 // One pair or monopole term and one quadrupole term for one target (the same arithmetic as the
 // loops above), used by the two-targets-per-lane tiles below.
 __device__ __forceinline__ void pair_term(const float4 j, float xi, float yi, float zi, float eps2, float& ax,
@@ -239,7 +283,10 @@ __device__ __forceinline__ void node_prefetch(const float4* __restrict__ nodes, 
 __host__ __device__ __forceinline__ int grav_rec_cap(int tile) {
   return tile > 3 * kNodeTile ? tile : 3 * kNodeTile;
 }
-__host__ __device__ __forceinline__ int grav_lds_per_wave(int tile) { return grav_rec_cap(tile) + 96; }
+// With the potential (POT) the reduction scratch holds four sums per lane: 128 records.
+__host__ __device__ __forceinline__ int grav_lds_per_wave(int tile, bool pot = false) {
+  return grav_rec_cap(tile) + (pot ? 128 : 96);
+}
 
 // A task as the force code reads it: the submitted fields and the first target's position in the
 // record array (its packed position, or i_begin when records are read in place).
@@ -260,16 +307,21 @@ struct TaskDesc {
 // written).  In the last target chunk next(0) and, after a block barrier, next(1) are called by
 // every thread before the cross-wave sum; next(1) may load the following task's first node tile
 // into pf.  The last barrier is the caller's: it must sync the block before the LDS is reused.
-template <int ORDER, bool LISTS, bool TWO, class Ready, class Next>
+// POT (one target per lane, records in position space): acc.w also receives the potential of the
+// task's terms, -G times the sum above, without the target's own direct term (a target found in its
+// task's direct ranges has contributed m r^-1 at r = eps, which is taken out again).
+template <int ORDER, bool LISTS, bool TWO, bool POT = false, class Ready, class Next>
 __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const TaskDesc& tk,
                                           float4* __restrict__ smem, NodePrefetch<ORDER>& pf, bool have_pf,
                                           Ready&& ready, Next&& next) {
+  static_assert(!POT || (!TWO && !LISTS), "the potential runs one target per lane in position space");
+  constexpr int NC = POT ? 4 : 3;  // sums per target
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
   const int W = blockDim.x >> 6;
   const int tile = a.tile;
   const int rec_cap = grav_rec_cap(tile);
-  const int per_wave = rec_cap + 96;
+  const int per_wave = grav_lds_per_wave(tile, POT);
   float4* L = smem + wid * per_wave;
   double* red = reinterpret_cast<double*>(L + rec_cap);
   // the range tables of the direct phase share the reduction scratch (live at different times)
@@ -304,7 +356,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
         B = make_float3(q.x, q.y, q.z);
       }
     }
-    double Ax = 0.0, Ay = 0.0, Az = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0;
+    double Ax = 0.0, Ay = 0.0, Az = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0, Ap = 0.0;
     // one tile of C records per slice starting at L + rec_stride * sl * C: accumulate it
     auto tile_sum = [&](int C, bool quads) {
       if (!active) return;
@@ -314,6 +366,11 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
         else tile_pairs2(L + sl * C, C, A, B, a.eps2, r);
         Ax += r.ax; Ay += r.ay; Az += r.az;
         Bx += r.bx; By += r.by; Bz += r.bz;
+      } else if (POT) {
+        float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+        if (quads) tile_quads_pot(L + 3 * sl * C, C, A.x, A.y, A.z, a.eps2, ax, ay, az, ph);
+        else tile_pairs_pot(L + sl * C, C, A.x, A.y, A.z, a.eps2, ax, ay, az, ph);
+        Ax += ax; Ay += ay; Az += az; Ap += ph;
       } else {
         float ax = 0.f, ay = 0.f, az = 0.f;
         if (quads) tile_quads(L + 3 * sl * C, C, A.x, A.y, A.z, a.eps2, ax, ay, az);
@@ -404,7 +461,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
     }
 
     // ---- reduce: slices within the wave, then the W waves, in a fixed order
-    double sx = 0.0, sy = 0.0, sz = 0.0;
+    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
     if (TWO) {
       // 6 sums per lane: the tile area is free now
       double* R2 = reinterpret_cast<double*>(L);
@@ -419,33 +476,49 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
         }
       }
     } else {
-      red[3 * lane] = Ax;
-      red[3 * lane + 1] = Ay;
-      red[3 * lane + 2] = Az;
+      red[NC * lane] = Ax;
+      red[NC * lane + 1] = Ay;
+      red[NC * lane + 2] = Az;
+      if (POT) red[NC * lane + 3] = Ap;
       wave_sync();
       if (lane < icc) {
         for (int s = 0; s < S; ++s) {
-          const double* q = red + 3 * (s * icc + lane);
+          const double* q = red + NC * (s * icc + lane);
           sx += q[0]; sy += q[1]; sz += q[2];
+          if (POT) sp += q[3];
         }
       }
     }
     wave_sync();
     if (lane < icc) {
-      red[3 * lane] = sx;
-      red[3 * lane + 1] = sy;
-      red[3 * lane + 2] = sz;
+      red[NC * lane] = sx;
+      red[NC * lane + 1] = sy;
+      red[NC * lane + 2] = sz;
+      if (POT) red[NC * lane + 3] = sp;
     }
     if (last) next(0);
     __syncthreads();
     if (last) next(1);
     if (wid == 0 && lane < icc) {
-      double tx = 0.0, ty = 0.0, tz = 0.0;
+      double tx = 0.0, ty = 0.0, tz = 0.0, tp = 0.0;
       for (int w = 0; w < W; ++w) {
-        const double* q = reinterpret_cast<const double*>(smem + w * per_wave + rec_cap) + 3 * lane;
+        const double* q = reinterpret_cast<const double*>(smem + w * per_wave + rec_cap) + NC * lane;
         tx += q[0]; ty += q[1]; tz += q[2];
+        if (POT) tp += q[3];
       }
-      a.acc[tk.i_begin + i0 + lane] = make_float4((float)(a.G * tx), (float)(a.G * ty), (float)(a.G * tz), 0.f);
+      float phi = 0.f;
+      if (POT) {
+        // the target's own direct term, if its position lies in one of the task's ranges
+        const int pos = tk.ibeg + i0 + lane;
+        bool self = false;
+        for (int r = 0; r < tk.j_nranges; ++r) {
+          const int2 g = a.ranges[tk.j_first + r];
+          self = self || (pos >= g.x && pos < g.x + g.y);
+        }
+        if (self) tp -= (double)(a.rec[pos].w * __builtin_amdgcn_rsqf(a.eps2));
+        phi = (float)(-a.G * tp);
+      }
+      a.acc[tk.i_begin + i0 + lane] = make_float4((float)(a.G * tx), (float)(a.G * ty), (float)(a.G * tz), phi);
     }
     if (!last) __syncthreads();
   }

@@ -1473,7 +1473,10 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
     return set_err(c, GC_E_UNSUPPORTED, "the whole-step schedule runs through gc_graph_capture only");
   if (b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_launch_combined: batch not reorganised");
   if (!acc_dev) return set_err(c, GC_E_INVAL, "gc_launch_combined: NULL acc");
-  if (prm->want_potential) return set_err(c, GC_E_UNSUPPORTED, "gc_launch_combined: potential output not built");
+  if (prm->want_potential && b->kind == GC_KIND_LJ)
+    return set_err(c, GC_E_UNSUPPORTED, "gc_launch_combined: the potential is written for gravity only");
+  if (prm->want_potential && (b->mode == GC_REORG_INDIRECT || b->mode == GC_REORG_SORTED))
+    return set_err(c, GC_E_UNSUPPORTED, "gc_launch_combined: the potential needs PACK, REDUNDANT or NONE");
   if (prm->deterministic && b->kind == GC_KIND_LJ && !b->lj_gather)
     return set_err(c, GC_E_UNSUPPORTED,
                    "gc_launch_combined: this Lennard-Jones batch (target ranges that partially overlap) sums with "
@@ -1520,6 +1523,15 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
       if (b->queue.ensure(sizeof(int32_t) * (size_t)(n_launch + 4)) != hipSuccess)
         return set_err(c, GC_E_NOMEM, "queue");
       GC_HIP(c, launch_fill_i32(b->queue.as<int32_t>(), 0, n_launch, s));
+    }
+    if (prm->want_potential) {
+      for (int32_t q = 0; q < n_launch; ++q) {
+        GravArgs aq = a;
+        aq.order = b->d_order.as<int32_t>() + (int64_t)q * agg;
+        aq.n_tasks = std::min<int32_t>(agg, T - q * agg);
+        GC_HIP(c, launch_grav_potential(order, aq, wpb, s));
+      }
+      return GC_OK;
     }
     for (int32_t q = 0; q < n_launch; ++q) {
       GravArgs aq = a;
@@ -1824,6 +1836,8 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   gc_pool p = pools[0];
   if (fixture != GC_FIXTURE_NONE && fixture != GC_FIXTURE_EVICT_STAGED)
     return set_err(ctx, GC_E_UNSUPPORTED, "whole-step schedule: fixture must be NONE or EVICT_STAGED");
+  if (prm->want_potential)
+    return set_err(ctx, GC_E_UNSUPPORTED, "whole-step schedule: no potential output (use the per-round passes)");
   int tile = 256, wpb = 4;
   for (int32_t k = 0; k < R; ++k) {
     gc_batch b = batches[k];

@@ -693,3 +693,74 @@ def test_step_schedule_is_rejected_where_unsupported(ctx, plum):
     assert e.value.status == gc.GC_E_UNSUPPORTED
     b.destroy()
     rig.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("mode", [gc.REORG_PACK, gc.REORG_NONE, gc.REORG_REDUNDANT])
+def test_potential_output(ctx, plum, mode, order):
+    # want_potential: acc.w is the potential of the target's terms (its own direct term left out); per
+    # task relative L2 of the potential and of the acceleration against the oracle
+    print(f"[gpu] potential mode={mode} order={order}", flush=True)
+    rig = GravRig(ctx, plum)
+    bt = W.task_subset(plum, np.arange(0, 2500))
+    b = rig.batch(bt)
+    rig.pool.reset()
+    if mode != gc.REORG_NONE:
+        ids, slots = W.residency(W.batch_union(bt), plum.n, 0.5, seed=41)
+        rig.place(ids, slots)
+    acc = rig.run(b, mode, order=order, want_potential=1, aggregation=700)
+    ref, pot = O.grav_workload(plum, order=order, tasks=bt, potential=True)
+    err = rel_l2_per_task(acc, ref, bt)
+    assert err.max() <= TOL, err.max()
+    perr = O.per_task_rel_l2(acc[:, 3:4].astype(np.float64), pot[:, None], bt["i_begin"], bt["i_count"])
+    assert perr.max() <= TOL, perr.max()
+    b.destroy()
+    rig.close()
+
+
+def test_potential_refusals(ctx, plum):
+    import torch
+    rig = GravRig(ctx, plum)
+    b = rig.batch(W.task_subset(plum, np.arange(0, 50)))
+    b.reorganize(rig.pool, gc.REORG_INDIRECT)
+    with pytest.raises(gc.GcError) as e:
+        b.launch(gc.grav_params(order=2, want_potential=1), rig.nodes, rig.acc)
+    assert e.value.status == gc.GC_E_UNSUPPORTED
+    with pytest.raises(gc.GcError) as e:
+        gc.Graph(ctx, [b], [rig.pool], [gc.REORG_PACK], gc.grav_params(order=2, schedule=gc.SCHED_STEP, want_potential=1),
+                 rig.nodes, rig.acc, stream=torch.cuda.Stream())
+    assert e.value.status == gc.GC_E_UNSUPPORTED
+    b.destroy()
+    rig.close()
+
+
+@pytest.mark.parametrize("shape", [dict(tile=256, targets_per_lane=1, schedule=0),
+                                   dict(tile=256, targets_per_lane=2, schedule=1),
+                                   dict(tile=512, targets_per_lane=2, schedule=0, aggregation=5000)])
+def test_sixty_four_instances_in_one_launch_sampled(ctx, shape):
+    # every task of the 64 instances (4.2 M particles, 450 k tasks) in one launch, with the launch
+    # shapes the autotuner chooses from: sampled tasks against the oracle, and the same bits as the
+    # per-instance launches of those instances
+    import torch
+    w = W.nbody_instances(k=64, seed=4000)
+    inst = w.meta["instance_of_task"]
+    print(f"[gpu] 64 instances N={w.n} tasks={w.n_tasks} shape={shape}", flush=True)
+    rig = GravRig(ctx, w, capacity=1)
+    b = rig.batch(whole(w))
+    acc = rig.run(b, gc.REORG_NONE, order=2, **shape)
+    rng = np.random.default_rng(3)
+    sample = np.sort(rng.choice(w.n_tasks, 256, replace=False))
+    bt = W.task_subset(w, sample)
+    ref = O.grav_workload(w, order=2, tasks=bt)
+    err = rel_l2_per_task(acc, ref, bt)
+    assert err.max() <= TOL, err.max()
+    for k in (int(inst[sample[0]]), int(inst[sample[-1]])):
+        sel = np.nonzero(inst == k)[0]
+        bk = rig.batch(W.task_subset(w, sel))
+        one = rig.run(bk, gc.REORG_NONE, order=2, **shape)
+        tgt = np.concatenate([np.arange(w.i_begin[t], w.i_begin[t] + w.i_count[t]) for t in sel])
+        assert np.array_equal(one[tgt], acc[tgt]), k
+        bk.destroy()
+    b.destroy()
+    rig.close()
+    torch.cuda.empty_cache()

@@ -55,7 +55,7 @@ def test_aggregated_launches_are_bitwise_equal(ctx, plum, schedule, mode):
 def test_autotune_cache(ctx, plum, tmp_path):
     torch = torch_cuda()
     rig = GravRig(ctx, plum)
-    bt = W.task_subset(plum, np.arange(0, 3000))
+    bt = W.task_subset(plum, np.arange(0, 2000))
     b = rig.batch(bt)
     b.reorganize(rig.pool, gc.REORG_PACK)
     path = str(tmp_path / "tune.json")
@@ -78,7 +78,7 @@ def test_autotune_cache(ctx, plum, tmp_path):
     err = rel_l2_per_task(rig.acc.cpu().numpy(), O.grav_workload(plum, order=2, tasks=bt), bt)
     assert err.max() <= TOL
     # another batch shape and the monopole kernel get keys of their own; the first entry is kept
-    b2 = rig.batch(W.task_subset(plum, np.arange(3000, 4000)))
+    b2 = rig.batch(W.task_subset(plum, np.arange(2000, 3000)))
     b2.reorganize(rig.pool, gc.REORG_PACK)
     _, _, hit3 = b2.autotune(gc.grav_params(order=1), rig.nodes, rig.acc, reps=1, cache_path=path)
     assert not hit3

@@ -157,3 +157,76 @@ def test_energy_conservation_and_reversibility_leapfrog():
     assert abs(E1 - E0) <= 1e-5 * abs(E0)
     x2, v2 = run(x1, -v1, steps)
     assert np.abs(x2 - x).max() <= 1e-9
+
+
+# ---------------------------------------------------------------- potential of the list terms
+
+def _one_target(x, mom, order, G, eps):
+    """(acc, pot) at point x of one node term through the list sum."""
+    t = dict(i_begin=np.array([0]), i_count=np.array([1]), n_first=np.array([0]), n_count=np.array([1]),
+             j_first=np.array([0]), j_nr=np.array([0]), node_idx=np.array([0]), ranges=np.zeros((0, 2), np.int32))
+    acc, pot = O.grav_lists(t, np.array([x], float), np.array([1.0]), np.array([mom], float), order, G, eps,
+                            potential=True)
+    return acc[0], pot[0]
+
+
+def test_two_body_potential_closed_form():
+    rng = np.random.default_rng(11)
+    for _ in range(10):
+        r, eps, G = 10 ** rng.uniform(-2, 1), 10 ** rng.uniform(-3, 0), rng.uniform(0.5, 2.0)
+        m = rng.uniform(0.1, 3.0, size=2)
+        pos = np.array([[0.0, 0.0, 0.0], [0.0, r, 0.0]])
+        _, pot = O.grav_brute(pos, m, G, eps, potential=True)
+        want = -G / math.sqrt(r * r + eps * eps)
+        np.testing.assert_allclose(pot, want * m[::-1], rtol=1e-14)
+        # the list sum with each body's direct range covering both ids (the self term is skipped)
+        t = dict(i_begin=np.array([0, 1]), i_count=np.array([1, 1]), n_first=np.array([0, 0]),
+                 n_count=np.array([0, 0]), j_first=np.array([0, 1]), j_nr=np.array([1, 1]),
+                 node_idx=np.zeros(0, np.int32), ranges=np.array([[0, 2], [0, 2]]))
+        _, lp = O.grav_lists(t, pos, m, np.zeros((1, 10)), 1, G, eps, potential=True)
+        np.testing.assert_allclose(lp, want * m[::-1], rtol=1e-14)
+
+
+@pytest.mark.parametrize("G,m,s", [(1.0, 1.0, 0.5), (2.5, 0.3, 0.1)])
+def test_quadrupole_potential_axial_closed_form(G, m, s):
+    # eps = 0, masses m at +-s z-hat: on the z axis Phi = -2Gm/z - 2Gm s^2/z^3, on the x axis
+    # Phi = -2Gm/x + Gm s^2/x^3 (exact to second order); the monopole keeps -2Gm/r only
+    mom = np.array([0, 0, 0, 2 * m, 0, 0, 2 * m * s * s, 0, 0, 0], float)
+    for z in [3.0, 7.0, 20.0]:
+        _, p = _one_target([0, 0, z], mom, 2, G, 0.0)
+        np.testing.assert_allclose(p, -2 * G * m / z - 2 * G * m * s * s / z**3, rtol=1e-14)
+        _, p = _one_target([z, 0, 0], mom, 2, G, 0.0)
+        np.testing.assert_allclose(p, -2 * G * m / z + G * m * s * s / z**3, rtol=1e-14)
+        _, p = _one_target([z, 0, 0], mom, 1, G, 0.0)
+        np.testing.assert_allclose(p, -2 * G * m / z, rtol=1e-14)
+
+
+def test_list_potential_at_theta_zero_equals_brute_force():
+    w = W.build_grav(W.plummer(1500, 91), bucket=16, theta=0.0)
+    assert w.node_idx.size == 0
+    rec = w.rec.astype(np.float64)
+    _, pot = O.grav_lists(O.workload_tasks(w), rec[:, :3], rec[:, 3], O.moments_from_nodes32(w.nodes), 2,
+                          potential=True)
+    _, want = O.grav_brute(rec[:, :3], rec[:, 3], potential=True)
+    np.testing.assert_allclose(pot, want, rtol=1e-13)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_list_force_is_minus_gradient_of_list_potential(order):
+    # lists and node moments frozen: a_i = -grad_i phi_i by central differences (a sign or factor
+    # slip in either the quadrupole potential or its force would fail this)
+    w = W.build_grav(W.plummer(4096, 92), bucket=16, theta=0.7)
+    rec = w.rec.astype(np.float64)
+    pos, mass, mom = rec[:, :3].copy(), rec[:, 3], O.moments_from_nodes32(w.nodes)
+    tasks = O.workload_tasks(w)
+    acc = O.grav_lists(tasks, pos, mass, mom, order)
+    rng = np.random.default_rng(5)
+    h = 1e-5
+    for i in rng.choice(w.n, 12, replace=False):
+        g = np.zeros(3)
+        for d in range(3):
+            pp = pos.copy(); pp[i, d] += h
+            pm = pos.copy(); pm[i, d] -= h
+            g[d] = (O.grav_lists(tasks, pp, mass, mom, order, potential=True)[1][i] -
+                    O.grav_lists(tasks, pm, mass, mom, order, potential=True)[1][i]) / (2 * h)
+        np.testing.assert_allclose(-g, acc[i], rtol=2e-6, atol=1e-8 * np.linalg.norm(acc[i]))

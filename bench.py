@@ -39,6 +39,9 @@ PEAK_HBM_GBPS = 8000.0
 # launch shapes (tile, targets per lane) of the whole-step form that the bench may time; the GPU tests
 # check every one of them against the per-round launches and the oracle
 STEP_SHAPES = ((256, 1), (256, 2), (320, 1), (320, 2), (384, 1), (384, 2))
+# launch shapes (tile, targets per lane, waves per task) of the rounds form's combined pass that the bench may
+# time; the GPU tests check every one of them against the per-round launches and the oracle
+ROUNDS_SHAPES = ((256, 1, 2), (256, 2, 2), (256, 2, 4), (512, 2, 2))
 
 
 def flop_counts() -> dict:
@@ -652,6 +655,8 @@ def main():
     ap.add_argument("--targets-per-lane", type=int, default=0, help="with --tile: 1 or 2 targets per lane")
     ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 256, 320 and 384")
     ap.add_argument("--step-tpl", type=int, default=0, help="fixed targets per lane of the whole-step launch instead of timing 1 and 2")
+    ap.add_argument("--step-schedule", default="", choices=["", "step", "rounds"],
+                    help="only the whole-step launch or only the rounds form (default: the faster)")
     ap.add_argument("--leg", default="", choices=["", "reorg-stress", "staging", "rebuild", "lj", "instances",
                                                   "combined"],
                     help="run one measurement leg alone and print its JSON (for profiling)")
@@ -807,16 +812,23 @@ def main():
     forms["round_graph_ms"] = round(time_kernel(lambda: round_graph.launch(stream=stream), stream, reps=10), 4)
     sprm, step_graph, step_shapes, best_ms = None, None, {}, None
     if mode == gc.REORG_PACK:
-        shapes = [sh for sh in STEP_SHAPES if (not args.step_tile or sh[0] == args.step_tile) and
-                  (not args.step_tpl or sh[1] == args.step_tpl)]
-        if not shapes:
-            log(f"[bench] --step-tile {args.step_tile} --step-tpl {args.step_tpl}: not a tested shape {STEP_SHAPES}")
+        # the whole-step launch (4 waves per task) and the rounds form (one persistent launch for every
+        # round's reorganisation, then one combined pass over all rounds' tasks), in their tested shapes
+        cands = [(gc.SCHED_STEP, tl, tp, 4) for tl, tp in STEP_SHAPES] + \
+                [(gc.SCHED_ROUNDS, tl, tp, wv) for tl, tp, wv in ROUNDS_SHAPES]
+        cands = [c for c in cands if (not args.step_tile or c[1] == args.step_tile) and
+                 (not args.step_tpl or c[2] == args.step_tpl) and
+                 (not args.step_schedule or c[0] == {"step": gc.SCHED_STEP, "rounds": gc.SCHED_ROUNDS}[args.step_schedule])]
+        if not cands:
+            log(f"[bench] --step-tile {args.step_tile} --step-tpl {args.step_tpl} --step-schedule {args.step_schedule}: "
+                f"not a tested shape {STEP_SHAPES} / {ROUNDS_SHAPES}")
             sys.exit(2)
-        for tl, tp in shapes:
-            p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=gc.SCHED_STEP, tile=tl, targets_per_lane=tp)
+        for sc, tl, tp, wv in cands:
+            p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=sc, tile=tl, targets_per_lane=tp, waves_per_block=wv)
             g = capture("step", p)
             ms = round(time_kernel(lambda: g.launch(stream=stream), stream, reps=10), 4)
-            step_shapes[f"tile{tl}_tpl{tp}"] = ms
+            name = "step" if sc == gc.SCHED_STEP else f"rounds_w{wv}"
+            step_shapes[f"{name}_tile{tl}_tpl{tp}"] = ms
             if best_ms is None or ms < best_ms:
                 if step_graph is not None:
                     step_graph.destroy()
@@ -994,9 +1006,14 @@ def main():
                     "frac": round(step_tflops / PEAK_FP32_TFLOPS, 4),
                     "traffic": profiled_traffic("k_step_quad_plummer262144_traffic",
                                                 {"tile": sprm.tile, "targets_per_lane": sprm.targets_per_lane}),
-                    "kernel": f"k_step<2, {'true' if sprm.targets_per_lane == 2 else 'false'}> (every round's "
-                              f"reorganisation, with the eviction of what it staged, and combined quadrupole pass; "
-                              f"tile {sprm.tile}, 4 waves per task, {sprm.targets_per_lane} targets per lane)",
+                    "kernel": (f"k_step<2, {'true' if sprm.targets_per_lane == 2 else 'false'}> (every round's "
+                               f"reorganisation, with the eviction of what it staged, and combined quadrupole pass; "
+                               f"tile {sprm.tile}, 4 waves per task, {sprm.targets_per_lane} targets per lane)")
+                    if sprm.schedule == gc.SCHED_STEP else
+                    (f"k_step<2, {'true' if sprm.targets_per_lane == 2 else 'false'}> (every round's reorganisation "
+                     f"and eviction) + k_grav_rounds<2, {'true' if sprm.targets_per_lane == 2 else 'false'}> (one "
+                     f"combined quadrupole pass over every round's tasks; tile {sprm.tile}, {sprm.waves_per_block} "
+                     f"waves per task, {sprm.targets_per_lane} targets per lane), timed together"),
                     "flops_per_launch": flops_step, "avg_launch_ms": round(step_kernel_ms, 5),
                     "frac_of_nonpacked_peak": round(step_tflops / PEAK_FP32_NONPACKED_TFLOPS, 4)}
     else:

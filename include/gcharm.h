@@ -391,8 +391,16 @@ enum { GC_FORCE_GRAV_MONO = 1, GC_FORCE_GRAV_QUAD = 2, GC_FORCE_LJ = 3 };
  * those kept by earlier ones); 4 waves per task; results bitwise equal to the
  * per-step launches.  With the evicting fixture a small kernel ahead of the
  * launch evicts what the last step left staged before it.
+ * GC_SCHED_ROUNDS (graph capture only, same conditions as GC_SCHED_STEP):
+ * the captured steps' reorganisations run as the work items of one
+ * persistent launch (with the evicting fixture side by side, each step seeing
+ * the pool as the first found it; otherwise in a chain), then one combined
+ * launch runs every task of every step from its step's packed records
+ * (Sec. 3.1: all of the combined requests in one kernel), tasks in each
+ * step's launch order, steps in order, waves_per_block waves per task;
+ * results bitwise equal to the per-step launches of the same shape.
  */
-enum { GC_SCHED_TASKS = 0, GC_SCHED_QUEUE = 1, GC_SCHED_STEP = 2 };
+enum { GC_SCHED_TASKS = 0, GC_SCHED_QUEUE = 1, GC_SCHED_STEP = 2, GC_SCHED_ROUNDS = 3 };
 
 typedef struct {
   int32_t kind;             /* GC_FORCE_* */

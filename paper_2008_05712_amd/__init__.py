@@ -18,6 +18,7 @@ __all__ = ["GcError", "lib", "Context", "Pool", "Batch", "Graph", "Combiner", "F
            "REORG_REDUNDANT", "REORG_INDIRECT", "REORG_SORTED", "REORG_PACK", "REORG_NONE",
            "FORCE_GRAV_MONO", "FORCE_GRAV_QUAD", "FORCE_LJ", "KIND_GRAV", "KIND_LJ", "TASK_SELF",
            "FIXTURE_NONE", "FIXTURE_RESET_PLACE", "FIXTURE_EVICT_STAGED", "SCHED_TASKS", "SCHED_QUEUE", "SCHED_STEP",
+           "SCHED_ROUNDS",
            "LIB_PATH", "EXPORTED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,7 +30,7 @@ TASK_SELF = 1
 REORG_REDUNDANT, REORG_INDIRECT, REORG_SORTED, REORG_PACK, REORG_NONE = 0, 1, 2, 3, 4
 FORCE_GRAV_MONO, FORCE_GRAV_QUAD, FORCE_LJ = 1, 2, 3
 FIXTURE_NONE, FIXTURE_RESET_PLACE, FIXTURE_EVICT_STAGED = 0, 1, 2
-SCHED_TASKS, SCHED_QUEUE, SCHED_STEP = 0, 1, 2
+SCHED_TASKS, SCHED_QUEUE, SCHED_STEP, SCHED_ROUNDS = 0, 1, 2, 3
 
 # gc_task: 7 int32 + 3 float32 = 40 bytes
 TASK_DTYPE = np.dtype([("i_begin", "<i4"), ("i_count", "<i4"), ("j_first", "<i4"), ("j_nranges", "<i4"),

@@ -218,8 +218,12 @@ struct StepRound {
   GravArgs grav;          // the round's combined pass over its packed records
   ReorgArgs reorg;        // the round's reorganisation (nbf: free-scan items, 0 after round 0; nbu)
   int32_t n_chain;        // free-slot + union items of the round
-  int32_t prev;           // the latest earlier round with chain items (-1: none)
+  int32_t prev;           // the latest earlier round with chain items (-1: none; kPrevFreeList: none, but
+                          // the round reads round 0's free-slot list and count)
 };
+// An independent round (the evicting fixture): its reorganisation needs nothing of earlier rounds but
+// the launch's free-slot list, which round 0's free-scan items write.
+constexpr int32_t kPrevFreeList = -2;
 struct StepArgs {
   const StepItem* items;  // by ticket
   int32_t n_items;
@@ -232,6 +236,7 @@ struct StepArgs {
   uint32_t spin_limit;    // probes after which a wait gives up and sets its round's error word
   int32_t fail_round;     // test hook: this round's force items wait for one data part too many (-1: none)
   uint32_t fail_spins;    // and give up after this many probes
+  int32_t has_force;      // the launch runs the force items (0: reorganisation items only)
 };
 // Dependencies complete within microseconds; the default bound (about a second) only keeps a broken
 // state from holding the grid.
@@ -242,6 +247,10 @@ constexpr int kCtrTickets = 0, kCtrExits = 1, kCtrEpoch = 2, kCtrRounds = 3;  //
                                 // + 1 data parts (union items) done
 constexpr int kStepLead = 3;    // rounds by which the reorganisation items precede the passes
 hipError_t launch_step(int order, bool two, const StepArgs& a, int grid, int tile, hipStream_t s);
+// The combined pass over the tasks of several rounds in one launch: items[b] (kind = round index,
+// idx = first packed target) with rounds[kind]; waves_per_block waves per task.
+hipError_t launch_grav_rounds(int order, bool two, const StepItem* items, int32_t n_items, const GravArgs* rounds,
+                              int tile, int waves_per_block, hipStream_t s);
 hipError_t step_occupancy(int order, bool two, int tile, int* blocks);
 
 struct GravAdjArgs {

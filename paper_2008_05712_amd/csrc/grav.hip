@@ -92,6 +92,49 @@ hipError_t occ_two(bool two, int tile, int wpb, int* blocks) {
              : occ_one<ORDER, LISTS, PERSIST, false>(tile, wpb, blocks);
 }
 
+// Per-round arguments read through the constant address space: with a uniform index they come in by
+// scalar loads into scalar registers.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* cst(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ T cload(const __attribute__((address_space(4))) T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word copy");
+  T v;
+  const __attribute__((address_space(4))) uint32_t* q = (const __attribute__((address_space(4))) uint32_t*)p;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
+  return v;
+}
+
+// Every task of several rounds in one launch: block b runs item b (its round's index in `kind`, its
+// task's fields and first packed target), with that round's arguments.
+template <int ORDER, bool TWO>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
+    k_grav_rounds(const StepItem* __restrict__ items, const GravArgs* __restrict__ rounds) {
+  extern __shared__ float4 smem[];
+  const StepItem it = cload(&cst(items)[blockIdx.x]);
+  const GravArgs ga = cload(&cst(rounds)[it.kind]);
+  const dev::TaskDesc td{it.i_begin, it.i_count, it.j_first, it.j_nranges, it.n_first, it.n_count, it.idx};
+  dev::NodePrefetch<ORDER> pf;
+  grav_task<ORDER, false, TWO>(ga, 0, td, smem, pf, false, [] {}, [](int) {});
+}
+
+template <int ORDER, bool TWO>
+hipError_t launch_rounds_one(const StepItem* items, int32_t n_items, const GravArgs* rounds, int tile, int wpb,
+                             hipStream_t s) {
+  const size_t lds = (size_t)wpb * grav_lds_per_wave(tile) * sizeof(float4);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav_rounds<ORDER, TWO>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_grav_rounds<ORDER, TWO>), dim3(n_items), dim3(64 * wpb), lds, s, items, rounds);
+  return hipGetLastError();
+}
+
 // The potential variant: one workgroup per task, one target per lane, records in position space.
 template <int ORDER>
 hipError_t launch_pot(const GravArgs& a, int wpb, hipStream_t s) {
@@ -106,6 +149,15 @@ hipError_t launch_pot(const GravArgs& a, int wpb, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t launch_grav_rounds(int order, bool two, const StepItem* items, int32_t n_items, const GravArgs* rounds,
+                              int tile, int wpb, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (order == 1) return two ? launch_rounds_one<1, true>(items, n_items, rounds, tile, wpb, s)
+                             : launch_rounds_one<1, false>(items, n_items, rounds, tile, wpb, s);
+  return two ? launch_rounds_one<2, true>(items, n_items, rounds, tile, wpb, s)
+             : launch_rounds_one<2, false>(items, n_items, rounds, tile, wpb, s);
+}
 
 hipError_t launch_grav_potential(int order, const GravArgs& a, int wpb, hipStream_t s) {
   if (a.n_tasks <= 0) return hipSuccess;

@@ -25,6 +25,7 @@
 #pragma once
 
 #include "gc_internal.h"
+#include "mem_dev.h"
 
 namespace gc {
 namespace dev {
@@ -235,10 +236,10 @@ __device__ __forceinline__ NodeRegs<ORDER> load_node(const float4* __restrict__ 
   r.v0 = z; r.v1 = z; r.v2 = z;
   if (idx >= 0) {
     const float4* nd = nodes + 3 * idx;
-    r.v0 = nd[0];
+    r.v0 = gld(nd);
     if (ORDER == 2) {
-      r.v1 = nd[1];
-      r.v2 = nd[2];
+      r.v1 = gld(nd + 1);
+      r.v2 = gld_xyz(nd + 2);  // (its fourth word is padding)
     }
   }
   return r;
@@ -271,8 +272,8 @@ __device__ __forceinline__ void node_prefetch(const float4* __restrict__ nodes, 
   const int W = blockDim.x >> 6;
   const int nw = n_count > wid ? (n_count - wid + W - 1) / W : 0;
   const int* nl = node_idx + n_first + wid;
-  pf.idx_next = (64 < nw && 64 + lane < nw) ? nl[(64 + lane) * W] : -1;
-  pf.cur = load_node<ORDER>(nodes, lane < nw ? nl[lane * W] : -1);
+  pf.idx_next = (64 < nw && 64 + lane < nw) ? gld(nl + (64 + lane) * W) : -1;
+  pf.cur = load_node<ORDER>(nodes, lane < nw ? gld(nl + lane * W) : -1);
 }
 
 // Records of LDS per wavefront for a direct tile of `tile` records: the larger of a direct tile and
@@ -349,10 +350,10 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
     float3 A = make_float3(0.f, 0.f, 0.f), B = A;
     if (active) {
       const int pb = LISTS ? 0 : tk.ibeg + i0;
-      const float4 r = a.rec[LISTS ? a.ilist[a.ioff[t] + i0 + il] : pb + il];
+      const float4 r = gld(a.rec + (LISTS ? gld(a.ilist + gld(a.ioff + t) + i0 + il) : pb + il));
       A = make_float3(r.x, r.y, r.z);
       if (TWO) {
-        const float4 q = a.rec[LISTS ? a.ilist[a.ioff[t] + i0 + ib] : pb + ib];
+        const float4 q = gld(a.rec + (LISTS ? gld(a.ilist + gld(a.ioff + t) + i0 + ib) : pb + ib));
         B = make_float3(q.x, q.y, q.z);
       }
     }
@@ -383,7 +384,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
     {
       // the prefetched first tile holds nodes 0..63 and the index of node 64 + lane; with NT < 64
       // its lanes >= NT are left out and the next tile starts at node NT
-      if (NT < kNodeTile) pf.idx_next = (lane < NT && NT + lane < nw) ? nl[(NT + lane) * W] : -1;
+      if (NT < kNodeTile) pf.idx_next = (lane < NT && NT + lane < nw) ? gld(nl + (NT + lane) * W) : -1;
       for (int nb = 0; nb < nw; nb += NT) {
         const int cnt = nw - nb < NT ? nw - nb : NT;
         const int C = (cnt + S - 1) / S;
@@ -392,7 +393,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
         if (nb + NT < nw) {
           pf.cur = load_node<ORDER>(a.nodes, pf.idx_next);
           const int e2 = nb + 2 * NT + lane;
-          pf.idx_next = (lane < NT && e2 < nw) ? nl[e2 * W] : -1;
+          pf.idx_next = (lane < NT && e2 < nw) ? gld(nl + e2 * W) : -1;
         }
         wave_sync();
         // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
@@ -403,14 +404,14 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
 
     // ---- direct terms
     if (LISTS) {
-      const int jb = a.joff[t], jn = a.joff[t + 1] - jb;
+      const int jb = gld(a.joff + t), jn = gld(a.joff + t + 1) - jb;
       for (int ws = wid * DT; ws < jn; ws += W * DT) {
         const int cnt = jn - ws < DT ? jn - ws : DT;
         const int C = (cnt + S - 1) / S;
         const int padded = S * C;
         for (int e = lane; e < padded; e += 64) {
           float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (e < cnt) v = a.rec[a.jlist[jb + ws + e]];
+          if (e < cnt) v = gld(a.rec + gld(a.jlist + jb + ws + e));
           L[e] = v;
         }
         wave_sync();
@@ -425,7 +426,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
       for (int rg = 0; rg < tk.j_nranges; rg += 64) {
         const int nr = tk.j_nranges - rg < 64 ? tk.j_nranges - rg : 64;
         int2 g = make_int2(0, 0);
-        if (lane < nr) g = rl[rg + lane];
+        if (lane < nr) g = gld(rl + rg + lane);
         int total;
         const int o = wave_excl_scan(g.y, &total);
         total = uniform(total);
@@ -449,7 +450,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
                 if (RO[mid] <= f) lo = mid;
                 else hi = mid - 1;
               }
-              v = a.rec[RB[lo] + (f - RO[lo])];
+              v = gld(a.rec + RB[lo] + (f - RO[lo]));
             }
             L[e] = v;
           }
@@ -512,13 +513,13 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
         const int pos = tk.ibeg + i0 + lane;
         bool self = false;
         for (int r = 0; r < tk.j_nranges; ++r) {
-          const int2 g = a.ranges[tk.j_first + r];
+          const int2 g = gld(a.ranges + tk.j_first + r);
           self = self || (pos >= g.x && pos < g.x + g.y);
         }
-        if (self) tp -= (double)(a.rec[pos].w * __builtin_amdgcn_rsqf(a.eps2));
+        if (self) tp -= (double)(gld(a.rec + pos).w * __builtin_amdgcn_rsqf(a.eps2));
         phi = (float)(-a.G * tp);
       }
-      a.acc[tk.i_begin + i0 + lane] = make_float4((float)(a.G * tx), (float)(a.G * ty), (float)(a.G * tz), phi);
+      gst(a.acc + tk.i_begin + i0 + lane, make_float4((float)(a.G * tx), (float)(a.G * ty), (float)(a.G * tz), phi));
     }
     if (!last) __syncthreads();
   }

@@ -33,6 +33,13 @@ __device__ __forceinline__ int2 gld(const int2* p) {
   const gc_vi2 v = *(const GC_GLOBAL(gc_vi2)*)p;
   return make_int2(v.x, v.y);
 }
+// The first three words of a record, its fourth left zero (a load of three words: no register is
+// written that nothing reads, which would make later reuse of that register wait for the load).
+typedef float gc_vf3 __attribute__((ext_vector_type(3)));
+__device__ __forceinline__ float4 gld_xyz(const float4* p) {
+  const gc_vf3 v = *(const GC_GLOBAL(gc_vf3)*)p;
+  return make_float4(v.x, v.y, v.z, 0.f);
+}
 __device__ __forceinline__ int32_t gld(const int32_t* p) { return *(const GC_GLOBAL(int32_t)*)p; }
 __device__ __forceinline__ uint32_t gld(const uint32_t* p) { return *(const GC_GLOBAL(uint32_t)*)p; }
 

@@ -20,7 +20,10 @@ namespace gc {
 namespace dev {
 
 constexpr int kRThreads = 256;                      // threads of every reorganisation block
-constexpr int kUItems = 8;                          // union entries per thread
+#ifndef GC_UITEMS
+#define GC_UITEMS 8
+#endif
+constexpr int kUItems = GC_UITEMS;                  // union entries per thread (a multiple of 4)
 constexpr int kUBlock = kRThreads * kUItems;        // union entries per block
 constexpr int kFItems = 16;                         // occupancy entries per thread
 constexpr int kFBlock = kRThreads * kFItems;        // pool slots per free-scan block
@@ -181,9 +184,11 @@ __device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t ta
 __device__ __forceinline__ void union_ids(const ReorgArgs& a, int b, int32_t (&id)[kUItems]) {
   const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
   const int4* u4 = reinterpret_cast<const int4*>(a.U + k0);  // U is padded to whole blocks
-  const int4 x = gld(u4), y = gld(u4 + 1);
-  id[0] = x.x; id[1] = x.y; id[2] = x.z; id[3] = x.w;
-  id[4] = y.x; id[5] = y.y; id[6] = y.z; id[7] = y.w;
+#pragma unroll
+  for (int q = 0; q < kUItems / 4; ++q) {
+    const int4 x = gld(u4 + q);
+    id[4 * q] = x.x; id[4 * q + 1] = x.y; id[4 * q + 2] = x.z; id[4 * q + 3] = x.w;
+  }
 }
 
 // Chare-table lookup of this thread's entries: resident slot (sl) and the missing mask.
@@ -344,12 +349,16 @@ __device__ __forceinline__ void union_role(const ReorgArgs& a, int b, uint32_t t
 // it runs after the table part has been published.  slot[i] leaves the table part as the entry's
 // slot (resident: its slot; missing: the assigned slot or -1) and fm as the missing mask.
 // Returns the round's missing count on the last union block's thread 0 (0 elsewhere).
+// coh: the chare table and resident records are read with device-scope coherent loads, as earlier
+// rounds of the launch may have changed them; with evict_after no round changes a value of either
+// (a staged id's entry and slot flag are rewritten with what they hold, and staged slots are free
+// slots that no lookup reaches), so plain loads read the same values.
 __device__ __forceinline__ uint32_t union_table(const ReorgArgs& a, int b, uint32_t tag, uint32_t ltag,
                                                 int64_t fbase, int* sh, uint32_t* s_ex, const int32_t (&id)[kUItems],
-                                                int32_t (&slot)[kUItems], uint32_t& fm) {
+                                                int32_t (&slot)[kUItems], uint32_t& fm, bool coh) {
   uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbf;
   const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
-  fm = union_lookup<true>(a, b, id, slot);
+  fm = coh ? union_lookup<true>(a, b, id, slot) : union_lookup<false>(a, b, id, slot);
   int tot;
   int rm = block_excl_scan(__popc(fm), sh, &tot);
   uint32_t m = 0;
@@ -389,14 +398,14 @@ __device__ __forceinline__ uint32_t union_table(const ReorgArgs& a, int b, uint3
 }
 
 __device__ __forceinline__ void union_data(const ReorgArgs& a, int b, const int32_t (&id)[kUItems],
-                                           const int32_t (&slot)[kUItems], uint32_t fm) {
+                                           const int32_t (&slot)[kUItems], uint32_t fm, bool coh) {
   const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
   float4 v[kUItems];
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {
     v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     if ((fm >> i) & 1u) v[i] = gld(a.src + id[i]);
-    else if (k0 + i < a.u) v[i] = ld_rec<true>(a.pool + slot[i]);
+    else if (k0 + i < a.u) v[i] = coh ? ld_rec<true>(a.pool + slot[i]) : ld_rec<false>(a.pool + slot[i]);
   }
 #pragma unroll
   for (int i = 0; i < kUItems; ++i) {

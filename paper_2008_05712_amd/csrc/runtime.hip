@@ -262,10 +262,11 @@ struct gc_graph_ {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   DevBuf step_items, step_rounds, step_ctr, step_fl;  // whole-step persistent schedule
+  DevBuf round_items, round_args;  // rounds schedule: the combined pass's items and per-round arguments
   std::vector<hipStream_t> side;   // capture-time side streams (combined passes of successive steps overlap)
   std::vector<hipEvent_t> events;
   std::vector<const int32_t*> err_words;  // the error words of the batches the graph reorganises
-  std::vector<DevBuf*> bufs() { return {&step_items, &step_rounds, &step_ctr, &step_fl}; }
+  std::vector<DevBuf*> bufs() { return {&step_items, &step_rounds, &step_ctr, &step_fl, &round_items, &round_args}; }
 };
 
 // ===================================================================== context
@@ -1247,15 +1248,31 @@ static gc_status reorganize_host(gc_batch b, gc_pool p, int32_t mode, int32_t ch
   gc_status hs = need_host_lists(b, s);
   if (hs != GC_OK) return hs;
   if (!redundant && !p->mirror_ok) GC_HIP(c, mirror_sync(p, s));
-  std::vector<int32_t> miss;
-  if (!redundant)
-    for (int32_t id : b->hU)
-      if (p->m_slot_of[id] < 0) miss.push_back(id);
+  // the missing ids, into the batch's own vector (kept across calls: its storage is reused, so the
+  // call allocates no host memory once the batch has been reorganised)
+  std::vector<int32_t>& miss = b->h_missing;
+  miss.clear();
+  if (!redundant) {
+    // branch-free: about half of a round's ids are missing, in no predictable pattern
+    miss.resize((size_t)b->u);
+    const int32_t* so = p->m_slot_of.data();
+    int32_t* out = miss.data();
+    size_t n = 0;
+    for (int32_t id : b->hU) {
+      out[n] = id;
+      n += so[id] < 0 ? 1 : 0;
+    }
+    miss.resize(n);
+  }
   const int32_t* ids = redundant ? b->hU.data() : miss.data();
   const int64_t m = redundant ? b->u : (int64_t)miss.size();
-  if (!redundant && check_capacity && m > p->m_nfree)
+  if (!redundant && check_capacity && m > p->m_nfree) {
+    miss.clear();
+    b->host_staged = false;
+    b->mode = -1;
     return set_err(c, GC_E_FULL, "gc_reorganize: %lld records missing but only %lld pool slots free", (long long)m,
                    (long long)p->m_nfree);
+  }
   b->mode = -1;
   hipError_t e = ensure_reorg_buffers(b, p, mode, s);
   // room for every union entry, so that the kernel's reads stay inside it whatever its own count
@@ -1277,13 +1294,9 @@ static gc_status reorganize_host(gc_batch b, gc_pool p, int32_t mode, int32_t ch
   gc_status st = reorganize_async(b, p, mode, s, redundant ? nullptr : b->staged.as<float4>());
   if (st != GC_OK) return st;
   GC_HIP(c, b->ev_use.record(s));
-  b->h_missing.clear();
-  b->h_mslot.clear();
-  if (!redundant) {
-    b->h_mslot.resize((size_t)m);
-    mirror_assign(p, miss.data(), m, b->h_mslot.data());
-    b->h_missing = std::move(miss);
-  }
+  b->h_mslot.resize((size_t)m);
+  if (!redundant) mirror_assign(p, miss.data(), m, b->h_mslot.data());
+  else miss.clear();
   b->host_staged = true;
   b->mode = mode;
   b->pool = p;
@@ -1449,8 +1462,8 @@ static gc_status check_prm(gc_batch b, const gc_force_params* prm, int* tile, in
     if (!(prm->r_cut > 0.f)) return set_err(c, GC_E_INVAL, "r_cut must be > 0");
     *wpb = 4;
   }
-  if (prm->schedule < GC_SCHED_TASKS || prm->schedule > GC_SCHED_STEP)
-    return set_err(c, GC_E_INVAL, "schedule must be GC_SCHED_TASKS, GC_SCHED_QUEUE or GC_SCHED_STEP");
+  if (prm->schedule < GC_SCHED_TASKS || prm->schedule > GC_SCHED_ROUNDS)
+    return set_err(c, GC_E_INVAL, "schedule must be GC_SCHED_TASKS, GC_SCHED_QUEUE, GC_SCHED_STEP or GC_SCHED_ROUNDS");
   if (prm->targets_per_lane < 0 || prm->targets_per_lane > 2)
     return set_err(c, GC_E_INVAL, "targets_per_lane must be 0, 1 or 2");
   if (b->kind == GC_KIND_GRAV && b->max_node >= prm->n_nodes)
@@ -1469,8 +1482,8 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
   int tile, wpb;
   gc_status st = check_prm(b, prm, &tile, &wpb);
   if (st != GC_OK) return st;
-  if (prm->schedule == GC_SCHED_STEP)
-    return set_err(c, GC_E_UNSUPPORTED, "the whole-step schedule runs through gc_graph_capture only");
+  if (prm->schedule == GC_SCHED_STEP || prm->schedule == GC_SCHED_ROUNDS)
+    return set_err(c, GC_E_UNSUPPORTED, "the whole-step and rounds schedules run through gc_graph_capture only");
   if (b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_launch_combined: batch not reorganised");
   if (!acc_dev) return set_err(c, GC_E_INVAL, "gc_launch_combined: NULL acc");
   if (prm->want_potential && b->kind == GC_KIND_LJ)
@@ -1830,9 +1843,11 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
 
 // The whole-step schedule: every step's reorganisation and combined pass in one persistent launch
 // (k_step).  Gravity, PACK, one pool, fixture NONE or EVICT_STAGED, distinct batches.
+// combined_pass (GC_SCHED_ROUNDS): the persistent launch runs only the reorganisation items, and one
+// combined launch after it runs every task of every round.
 static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool* pools, const int32_t* modes,
                               const gc_force_params* prm, const float* nodes_dev, float* acc_dev, int32_t fixture,
-                              hipStream_t s, gc_graph gr) {
+                              hipStream_t s, gc_graph gr, bool combined_pass) {
   gc_pool p = pools[0];
   if (fixture != GC_FIXTURE_NONE && fixture != GC_FIXTURE_EVICT_STAGED)
     return set_err(ctx, GC_E_UNSUPPORTED, "whole-step schedule: fixture must be NONE or EVICT_STAGED");
@@ -1917,6 +1932,12 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     sr.prev = -1;
     for (int32_t q = k - 1; q >= 0 && sr.prev < 0; --q)
       if (rounds[q].n_chain > 0) sr.prev = q;
+    // With the evicting fixture every round sees the pool as round 0 found it: a round's table part
+    // leaves the chare table and occupancy as they were (it writes for its staged ids the values
+    // they already hold), and the records it stages go into free slots that no lookup reads.  Its
+    // reorganisation then depends only on round 0's free-slot list and count, not on any earlier
+    // round's table or data parts: the rounds' reorganisations run side by side.
+    if (fixture == GC_FIXTURE_EVICT_STAGED && k > 0 && rounds[0].reorg.nbf > 0) sr.prev = kPrevFreeList;
     // the evicting fixture: each round's union blocks evict what they stage (the same table updates
     // as an eviction before the next round, off its critical path); what the previous launch's last
     // round left (nothing, unless the pool was used between launches) is evicted by a kernel before
@@ -1924,10 +1945,33 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     r.evict_after = fixture == GC_FIXTURE_EVICT_STAGED ? 1 : 0;
     seg(kItemFree, k, r.nbf);
     seg(kItemUnion, k, r.nbu);
-    if (k >= kStepLead) seg(kItemForce, k - kStepLead, (int32_t)batches[k - kStepLead]->tasks.size());
+    if (!combined_pass && k >= kStepLead) seg(kItemForce, k - kStepLead, (int32_t)batches[k - kStepLead]->tasks.size());
   }
-  for (int32_t k = std::max<int32_t>(R - kStepLead, 0); k < R; ++k)
-    seg(kItemForce, k, (int32_t)batches[k]->tasks.size());
+  if (!combined_pass)
+    for (int32_t k = std::max<int32_t>(R - kStepLead, 0); k < R; ++k)
+      seg(kItemForce, k, (int32_t)batches[k]->tasks.size());
+  // the combined pass of the rounds schedule: every round's tasks in its launch order, rounds in
+  // order, each with its round index and first packed target
+  std::vector<StepItem> fitems;
+  if (combined_pass) {
+    for (int32_t k = 0; k < R; ++k) {
+      const gc_batch fb = batches[k];
+      for (size_t i = 0; i < fb->tasks.size(); ++i) {
+        const int32_t t = fb->h_order[i];
+        const gc_task& tk = fb->tasks[(size_t)t];
+        StepItem it{};
+        it.kind = k;
+        it.idx = fb->h_pibeg[(size_t)t];
+        it.i_begin = tk.i_begin;
+        it.i_count = tk.i_count;
+        it.j_first = tk.j_first;
+        it.j_nranges = tk.j_nranges;
+        it.n_first = tk.n_first;
+        it.n_count = tk.n_count;
+        fitems.push_back(it);
+      }
+    }
+  }
   const int32_t n_ctr = kCtrStride * (kCtrRounds + 2 * R);
   // the launch's free-slot list: entries up to the most any round can reach (with the evicting
   // fixture every round reads from the start of the list, otherwise after what earlier rounds kept)
@@ -1948,6 +1992,17 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     rounds[k].reorg.ftotal = fmeta;
     rounds[k].reorg.flimit = (int32_t)flimit;
   }
+  std::vector<GravArgs> gargs;
+  if (combined_pass) {
+    for (int32_t k = 0; k < R; ++k) gargs.push_back(rounds[k].grav);
+    hipError_t e2 = gr->round_items.ensure(sizeof(StepItem) * std::max<size_t>(fitems.size(), 1));
+    if (e2 == hipSuccess) e2 = gr->round_args.ensure(sizeof(GravArgs) * (size_t)R);
+    if (e2 != hipSuccess) return set_err(ctx, GC_E_NOMEM, "rounds schedule: %s", hipGetErrorString(e2));
+    if (!fitems.empty())
+      GC_HIP(ctx, hipMemcpyAsync(gr->round_items.p, fitems.data(), sizeof(StepItem) * fitems.size(),
+                                 hipMemcpyHostToDevice, s));
+    GC_HIP(ctx, hipMemcpyAsync(gr->round_args.p, gargs.data(), sizeof(GravArgs) * (size_t)R, hipMemcpyHostToDevice, s));
+  }
   GC_HIP(ctx, hipMemcpyAsync(gr->step_items.p, items.data(), sizeof(StepItem) * items.size(), hipMemcpyHostToDevice, s));
   GC_HIP(ctx, hipMemcpyAsync(gr->step_rounds.p, rounds.data(), sizeof(StepRound) * (size_t)R, hipMemcpyHostToDevice, s));
   GC_HIP(ctx, launch_fill_i32(gr->step_ctr.as<int32_t>(), 0, 2 * (int64_t)n_ctr, s));
@@ -1956,7 +2011,10 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   int per = 0;
   const bool two = prm->targets_per_lane == 2;
   GC_HIP(ctx, step_occupancy(order, two, tile, &per));
-  const int grid = std::max(1, per) * ctx->n_cu;
+  // the reorganisation items alone (rounds schedule) are a few hundred: one block each, so that the
+  // launch's ticket and exit counters see no more requests than there are items
+  const int grid = combined_pass ? std::min(std::max(1, per) * ctx->n_cu, std::max(1, nt))
+                                 : std::max(1, per) * ctx->n_cu;
   StepArgs a{};
   a.items = gr->step_items.as<StepItem>();
   a.n_items = nt;
@@ -1967,6 +2025,7 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   a.spin_limit = kStepSpinLimit;
   a.fail_round = ctx->step_fail_round < R ? ctx->step_fail_round : -1;
   a.fail_spins = ctx->step_fail_spins ? ctx->step_fail_spins : kStepSpinLimit;
+  a.has_force = combined_pass ? 0 : 1;
   hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamBeginCapture");
   hipError_t le = hipSuccess;
@@ -1976,6 +2035,9 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
                       p->slot_of.as<int32_t>(), p->n_ids, p->occ.as<uint32_t>(), s);
   }
   if (le == hipSuccess) le = launch_step(order, two, a, grid, tile, s);
+  if (le == hipSuccess && combined_pass)
+    le = launch_grav_rounds(order, two, gr->round_items.as<StepItem>(), (int32_t)fitems.size(),
+                            gr->round_args.as<GravArgs>(), tile, wpb, s);
   hipGraph_t g = nullptr;
   ce = hipStreamEndCapture(s, &g);
   if (le != hipSuccess || ce != hipSuccess) {
@@ -2039,12 +2101,13 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
     if (modes[k] != GC_REORG_NONE) GC_HIP(ctx, clear_reorg_state(batches[k], S(stream)));
   GC_HIP(ctx, hipStreamSynchronize(S(stream)));
   hipStream_t s = S(stream);
-  if (prm->schedule == GC_SCHED_STEP) {
+  if (prm->schedule == GC_SCHED_STEP || prm->schedule == GC_SCHED_ROUNDS) {
     gc_graph gs = new gc_graph_();
     gs->ctx = ctx;
     gs->pools.assign(pools, pools + n_steps);
     for (DevBuf* d : gs->bufs()) d->h = &ctx->hooks;
-    gc_status st = capture_step(ctx, n_steps, batches, pools, modes, prm, nodes_dev, acc_dev, fixture, s, gs);
+    gc_status st = capture_step(ctx, n_steps, batches, pools, modes, prm, nodes_dev, acc_dev, fixture, s, gs,
+                                prm->schedule == GC_SCHED_ROUNDS);
     if (st != GC_OK) {
       if (gs->exec) (void)hipGraphExecDestroy(gs->exec);
       if (gs->graph) (void)hipGraphDestroy(gs->graph);
@@ -2052,6 +2115,8 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
       gs->step_rounds.release();
       gs->step_ctr.release();
       gs->step_fl.release();
+      gs->round_items.release();
+      gs->round_args.release();
       delete gs;
       return st;
     }

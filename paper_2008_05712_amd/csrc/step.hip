@@ -33,6 +33,11 @@
 //   union(r) data     waits for the previous round's data parts (pool records
 //                     it stages may be read or its slots reused);
 //   force(r)          waits for the data parts of round r.
+// With the evicting fixture a round changes no value of the chare table, the occupancy or the resident
+// records (a staged id's entry and its slot's flag are rewritten with what they held, and the records
+// go into free slots that no lookup reaches), so every round sees the pool as the launch found it:
+// rounds after the first wait for nothing but round 0's free-slot count, probe its list entries as
+// they appear, and read the table and records with plain loads.
 // The unfinished item with the smallest ticket therefore always progresses (its
 // dependencies are finished), so the grid never deadlocks whatever the order
 // in which its blocks run; every wait is bounded anyway and raises an error
@@ -78,14 +83,16 @@ __device__ __forceinline__ void wait_ge(uint64_t* p, uint64_t target, int32_t* e
   }
 }
 
-// Every wave waits for its own stores to reach the L2, then one thread writes the L2 back
-// (device-scope release) and counts the item done.
-__device__ __forceinline__ uint64_t publish_done(uint64_t* ctr) {
-  __builtin_amdgcn_s_waitcnt(0);
+// Counts the item done.  With `release` every wave first waits for its own stores to reach the L2,
+// then one thread writes the L2 back (device-scope release), so that an item that waits for the count
+// reads what this one wrote.  Without it only the count is published (nothing in the launch reads the
+// item's plain stores; tagged words are device-scope atomics and need no release).
+__device__ __forceinline__ uint64_t publish_done(uint64_t* ctr, bool release) {
+  if (release) __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   uint64_t old = 0;
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (release) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     old = atomicAdd(reinterpret_cast<unsigned long long*>(ctr), 1ull);
   }
   return old;
@@ -111,8 +118,11 @@ __device__ __forceinline__ T cload(const __attribute__((address_space(4))) T* p)
   return v;
 }
 
+#ifndef GC_STEP_WPE
+#define GC_STEP_WPE 5
+#endif
 template <int ORDER, bool TWO>
-__global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_per_eu(5))) k_step(StepArgs s) {
+__global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_per_eu(GC_STEP_WPE))) k_step(StepArgs s) {
   extern __shared__ float4 smem[];
   __shared__ int sh[dev::kRThreads / 64];
   __shared__ uint32_t s_ex, s_tag;
@@ -236,6 +246,8 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
           }
           favail = F - fbase;
         }
+        // an independent round (pr == kPrevFreeList) waits for nothing here: its list entries are
+        // probed as they appear, and its last union item records the launch's free count at its end
         s_base = fbase;
         s_avail = favail;
         s_tag = (uint32_t)dev::iload(R.reorg.state + dev::kTag) + 1u;
@@ -243,27 +255,46 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
       __syncthreads();
       const uint32_t tag = s_tag;
       if (type == kItemFree) {
-        dev::free_role<true>(ra, idx, tag, ltag, sh, &s_ex);
-        const uint64_t old = publish_done(ch_done);
+        // plain loads: no item of the launch writes the occupancy of a slot before its free-scan item
+        // has listed it (slots are taken from the list), and the launch starts after every earlier write
+        dev::free_role<false>(ra, idx, tag, ltag, sh, &s_ex);
+        // without the fixture later rounds wait for this count, then read the list's count (a tagged
+        // word; the release orders it before the count), else they poll that word itself
+        const uint64_t old = publish_done(ch_done, !ra.evict_after);
         if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
       } else {
         int32_t slot[dev::kUItems];
         uint32_t fm;
         const int64_t fbase = s_base;
-        (void)dev::union_table(ra, idx, tag, ltag, fbase, sh, &s_ex, ids, slot, fm);
+        (void)dev::union_table(ra, idx, tag, ltag, fbase, sh, &s_ex, ids, slot, fm, !ra.evict_after);
         if (tid == 0 && idx == ra.nbu - 1) {
           dev::tstore(s.fmeta + 1 + k, dev::tword(ltag, 0, (uint32_t)fbase));
           if (s_avail >= 0) dev::istore(R.reorg.state + GC_STATE_FREE, (int32_t)s_avail);
+          if (pr == kPrevFreeList) {
+            // the launch's free count, which round 0's last free-scan item writes (tagged); the probes
+            // above have found their entries, so it is written or about to be
+            uint64_t ft = dev::tload(s.fmeta);
+            for (uint32_t spins = 0; (uint32_t)(ft >> 32) != ltag; ft = dev::tload(s.fmeta)) {
+              if (++spins > s.spin_limit) {
+                dev::istore(err, 1);
+                break;
+              }
+              __builtin_amdgcn_s_sleep(2);
+            }
+            dev::istore(R.reorg.state + GC_STATE_FREE, (int32_t)(ft & 0x7fffffffu));
+          }
         }
-        const uint64_t old = publish_done(ch_done);
+        // later rounds read this round's table writes unless the fixture leaves the table unchanged
+        const uint64_t old = publish_done(ch_done, !ra.evict_after);
         if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
         // data part: after the previous round's (its staging may be read here, its slots reused)
         if (tid == 0 && pr >= 0)
           wait_ge(s.ctr + kCtrStride * (kCtrRounds + 2 * pr + 1), goal * (uint64_t)cst(s.rounds)[pr].reorg.nbu, err,
                   s.spin_limit);
         __syncthreads();
-        dev::union_data(ra, idx, ids, slot, fm);
-        (void)publish_done(dt_done);
+        dev::union_data(ra, idx, ids, slot, fm, !ra.evict_after);
+        // read by this round's force items, and without the fixture by later rounds' data parts
+        (void)publish_done(dt_done, s.has_force || !ra.evict_after);
       }
       __builtin_amdgcn_s_setprio(0);
       fetch_next();

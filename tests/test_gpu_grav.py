@@ -764,3 +764,129 @@ def test_sixty_four_instances_in_one_launch_sampled(ctx, shape):
     b.destroy()
     rig.close()
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- the rounds schedule
+from bench import ROUNDS_SHAPES  # noqa: E402
+
+
+def _eager_rounds(rig, bs, prm, evict=True):
+    import torch
+    rig.acc.fill_(np.nan)
+    for k, b in enumerate(bs):
+        if k and evict:
+            rig.pool.evict_staged(bs[k - 1])
+        b.reorganize(rig.pool, gc.REORG_PACK, check_capacity=False)
+        b.launch(prm, rig.nodes, rig.acc)
+    if evict:
+        rig.pool.evict_staged(bs[-1])
+    torch.cuda.synchronize()
+    return rig.acc.cpu().numpy()
+
+
+@pytest.mark.parametrize("tile,tpl,waves", ROUNDS_SHAPES)
+@pytest.mark.parametrize("order", [1, 2])
+def test_rounds_schedule_matches_per_round_launches(ctx, plum, order, tile, tpl, waves):
+    # every round's reorganisation in one persistent launch (side by side under the evicting fixture),
+    # then one combined pass over every round's tasks: bitwise the per-round launches of the same shape,
+    # the oracle's maps on the base state, the base residency left in the pool; replays repeat it
+    import torch
+    print(f"[gpu] rounds schedule order={order} tile={tile} tpl={tpl} waves={waves}", flush=True)
+    rig, bts, bs, base = _rounds_rig(ctx, plum, 4, 500, 38, 0.4, 39)
+    _set_base(rig, base)
+    base_so = rig.pool.query()
+    eager = _eager_rounds(rig, bs, gc.grav_params(order=order, tile=tile, targets_per_lane=tpl, waves_per_block=waves))
+    ref = O.grav_workload(plum, order=order)
+    for bt in bts:
+        assert rel_l2_per_task(eager, ref, bt).max() <= TOL
+    assert np.array_equal(rig.pool.query(), base_so)
+    s = torch.cuda.Stream()
+    rprm = gc.grav_params(order=order, schedule=gc.SCHED_ROUNDS, tile=tile, targets_per_lane=tpl, waves_per_block=waves)
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), rprm, rig.nodes, rig.acc, stream=s,
+                 fixture=gc.FIXTURE_EVICT_STAGED)
+    for rep in range(3):
+        rig.acc.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        got = rig.acc.cpu().numpy()
+        assert np.array_equal(np.isnan(got), np.isnan(eager)), rep
+        assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)]), rep
+        for k in range(len(bs)):
+            _check_maps(bs[k].maps(), O.maps(bts[k], plum.n, plum.n, base_so, gc.REORG_PACK), gc.REORG_PACK)
+        assert np.array_equal(rig.pool.query(), base_so), rep
+    g.status(stream=s)
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()
+
+
+def test_rounds_schedule_without_fixture_accumulates_residency(ctx, plum):
+    # fixture NONE: the reorganisations chain (each round reuses what earlier rounds staged), then one
+    # combined pass: maps, pool and accelerations equal the eager sequence's
+    import torch
+    rig, bts, bs, base = _rounds_rig(ctx, plum, 5, 400, 48, 0.3, 49)
+    _set_base(rig, base)
+    so = rig.pool.query()
+    maps_eager = []
+    for k in range(len(bs)):
+        want = O.maps(bts[k], plum.n, plum.n, so, gc.REORG_PACK)
+        so = want["slot_of"]
+        maps_eager.append(want)
+    eager = _eager_rounds(rig, bs, gc.grav_params(order=2, waves_per_block=2), evict=False)
+    assert np.array_equal(rig.pool.query(), so)
+    _set_base(rig, base)
+    s = torch.cuda.Stream()
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs),
+                 gc.grav_params(order=2, schedule=gc.SCHED_ROUNDS, waves_per_block=2), rig.nodes, rig.acc, stream=s,
+                 fixture=gc.FIXTURE_NONE)
+    rig.acc.fill_(np.nan)
+    torch.cuda.synchronize()
+    g.launch(stream=s)
+    s.synchronize()
+    got = rig.acc.cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(eager))
+    assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)])
+    assert np.array_equal(rig.pool.query(), so)
+    for k in range(len(bs)):
+        _check_maps(bs[k].maps(), maps_eager[k], gc.REORG_PACK)
+    g.status(stream=s)
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()
+
+
+@pytest.mark.parametrize("tile,tpl,waves", ROUNDS_SHAPES)
+def test_rounds_schedule_full_size(ctx, tile, tpl, waves):
+    # 262,144 particles, 6 Poisson(2048) rounds, half of all particles resident: the rounds schedule in
+    # every shape the bench may time equals the per-round launches bitwise; sampled tasks match the oracle
+    import torch
+    w = W.nbody_plummer()
+    print(f"[gpu] rounds schedule full size tile={tile} tpl={tpl} waves={waves}", flush=True)
+    rig, bts, bs, base = _rounds_rig(ctx, w, 6, 2048, 1002, 0.5, 5000)
+    _set_base(rig, base)
+    eager = _eager_rounds(rig, bs, gc.grav_params(order=2, tile=tile, targets_per_lane=tpl, waves_per_block=waves))
+    s = torch.cuda.Stream()
+    rprm = gc.grav_params(order=2, schedule=gc.SCHED_ROUNDS, tile=tile, targets_per_lane=tpl, waves_per_block=waves)
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), rprm, rig.nodes, rig.acc, stream=s,
+                 fixture=gc.FIXTURE_EVICT_STAGED)
+    for rep in range(2):
+        rig.acc.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        got = rig.acc.cpu().numpy()
+        assert np.array_equal(np.isnan(got), np.isnan(eager)), rep
+        assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)]), rep
+    g.status(stream=s)
+    sel = np.random.default_rng(4).choice(np.concatenate([np.asarray(r) for r in W.poisson_rounds(w.n_tasks, 2048, seed=1002)[:6]]),
+                                          size=48, replace=False)
+    sub = W.task_subset(w, np.sort(sel))
+    err = rel_l2_per_task(got, O.grav_workload(w, order=2, tasks=sub), sub)
+    assert err.max() <= TOL, err.max()
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()

@@ -41,7 +41,9 @@ PEAK_HBM_GBPS = 8000.0
 STEP_SHAPES = ((256, 1), (256, 2), (320, 1), (320, 2), (384, 1), (384, 2))
 # launch shapes (tile, targets per lane, waves per task) of the rounds form's combined pass that the bench may
 # time; the GPU tests check every one of them against the per-round launches and the oracle
-ROUNDS_SHAPES = ((256, 1, 2), (256, 2, 2), (256, 2, 4), (512, 2, 2))
+TPL_TEXT = {0: "one target per lane", 1: "one target per lane", 2: "two targets per lane",
+            3: "one or two targets per lane, whichever fills more lanes for the task"}
+ROUNDS_SHAPES = ((256, 1, 2), (256, 2, 2), (256, 3, 2), (256, 2, 4), (512, 2, 2))
 
 
 def flop_counts() -> dict:
@@ -652,9 +654,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="fixed force-kernel shape instead of the autotuner's")
     ap.add_argument("--waves", type=int, default=4)
     ap.add_argument("--schedule", type=int, default=0)
-    ap.add_argument("--targets-per-lane", type=int, default=0, help="with --tile: 1 or 2 targets per lane")
+    ap.add_argument("--targets-per-lane", type=int, default=0, help="with --tile: 1, 2 or 3 (per task) targets per lane")
     ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 256, 320 and 384")
-    ap.add_argument("--step-tpl", type=int, default=0, help="fixed targets per lane of the whole-step launch instead of timing 1 and 2")
+    ap.add_argument("--step-tpl", type=int, default=0, help="fixed targets per lane of the step forms instead of timing the tested ones")
     ap.add_argument("--step-schedule", default="", choices=["", "step", "rounds"],
                     help="only the whole-step launch or only the rounds form (default: the faster)")
     ap.add_argument("--leg", default="", choices=["", "reorg-stress", "staging", "rebuild", "lj", "instances",
@@ -991,6 +993,9 @@ def main():
 
     form_text = {"step": "one whole-step persistent launch (HIP graph) per step",
                  "rounds": "one HIP graph of per-round launches per step", "eager": "per-round launches"}[form]
+    if form == "step" and sprm is not None and sprm.schedule == gc.SCHED_ROUNDS:
+        form_text = ("one HIP graph per step: every round's reorganisation in one persistent launch, then one "
+                     "combined pass over all rounds' tasks")
     tpl = max(1, prm.targets_per_lane)
     per_round = {"kernel": f"k_grav<2, false, {'true' if prm.schedule else 'false'}, {'true' if tpl == 2 else 'false'}> "
                            f"(tile {prm.tile}, {prm.waves_per_block} waves per task, {tpl} targets per lane)",
@@ -1005,15 +1010,19 @@ def main():
         roofline = {"bound": "alu", "achieved": round(step_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(step_tflops / PEAK_FP32_TFLOPS, 4),
                     "traffic": profiled_traffic("k_step_quad_plummer262144_traffic",
-                                                {"tile": sprm.tile, "targets_per_lane": sprm.targets_per_lane}),
+                                                {"tile": sprm.tile, "targets_per_lane": sprm.targets_per_lane})
+                    if sprm.schedule == gc.SCHED_STEP else
+                    profiled_traffic("k_grav_rounds_quad_plummer262144_traffic",
+                                     {"tile": sprm.tile, "targets_per_lane": sprm.targets_per_lane,
+                                      "waves_per_block": sprm.waves_per_block}),
                     "kernel": (f"k_step<2, {'true' if sprm.targets_per_lane == 2 else 'false'}> (every round's "
                                f"reorganisation, with the eviction of what it staged, and combined quadrupole pass; "
                                f"tile {sprm.tile}, 4 waves per task, {sprm.targets_per_lane} targets per lane)")
                     if sprm.schedule == gc.SCHED_STEP else
-                    (f"k_step<2, {'true' if sprm.targets_per_lane == 2 else 'false'}> (every round's reorganisation "
-                     f"and eviction) + k_grav_rounds<2, {'true' if sprm.targets_per_lane == 2 else 'false'}> (one "
-                     f"combined quadrupole pass over every round's tasks; tile {sprm.tile}, {sprm.waves_per_block} "
-                     f"waves per task, {sprm.targets_per_lane} targets per lane), timed together"),
+                    (f"k_step<2, 1, false> (every round's reorganisation and eviction; no force code) + "
+                     f"k_grav_rounds<2, {sprm.targets_per_lane}> (one combined quadrupole pass over every round's "
+                     f"tasks; tile {sprm.tile}, {sprm.waves_per_block} waves per task, {TPL_TEXT[sprm.targets_per_lane]}), "
+                     f"timed together: the step's whole device time"),
                     "flops_per_launch": flops_step, "avg_launch_ms": round(step_kernel_ms, 5),
                     "frac_of_nonpacked_peak": round(step_tflops / PEAK_FP32_NONPACKED_TFLOPS, 4)}
     else:

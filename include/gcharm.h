@@ -416,7 +416,12 @@ typedef struct {
   int32_t grid_blocks;      /* persistent schedule: 0 = CUs x occupancy */
   int32_t targets_per_lane; /* gravity: 0 or 1 = one target per lane; 2 = each lane
                                holds two targets of its task, so every record read
-                               from LDS serves two interactions (same results) */
+                               from LDS serves two interactions; 3 = per chunk of n
+                               <= 64 targets, two where floor(64 / ceil(n / 2)) >
+                               2 floor(64 / n) (more lanes busy), else one.  The
+                               modes split the sources over different slices, so
+                               they agree to rounding; each gives the same bits on
+                               every launch, schedule and aggregation */
   int32_t n_nodes;          /* gravity: node records in nodes_dev; every node index the
                                batch holds must be below it (GC_E_INVAL otherwise) */
   int32_t want_potential;   /* gravity, 1: also write in acc.w the potential of the

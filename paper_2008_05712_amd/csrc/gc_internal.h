@@ -49,6 +49,7 @@ struct GravArgs {
   const int32_t* jlist;
   const int32_t* node_idx;
   const float4* nodes;     // 3 float4 per node
+  int32_t n_nodes;         // nodes in the table (reads past it return zero records)
   const float4* rec;       // records (packed, pool or source)
   float4* acc;             // output, by target id
   float G, eps2;
@@ -135,10 +136,11 @@ hipError_t launch_sort_lists(int32_t n_tasks, const int32_t* joff, int32_t* jlis
 // by_k: the k-th record is src[k] (staged from the host), else src[ids[k]]
 hipError_t launch_place(const int32_t* ids, const int32_t* slots, int32_t n, const float4* src, bool by_k, float4* pool,
                         int32_t* slot_of, uint32_t* occ, hipStream_t s);
-// two: two targets per lane (each record read from LDS serves two interactions)
-hipError_t launch_grav(int order, bool lists, bool persistent, bool two, const GravArgs& a, int waves_per_block,
+// tpl: targets per lane, 1 or 2 (each record read from LDS serves two interactions), or 3: per chunk
+// of targets, whichever fills more lanes
+hipError_t launch_grav(int order, bool lists, bool persistent, int tpl, const GravArgs& a, int waves_per_block,
                        int grid_blocks, hipStream_t s);
-hipError_t grav_occupancy(int order, bool lists, bool persistent, bool two, int tile, int waves_per_block, int* blocks);
+hipError_t grav_occupancy(int order, bool lists, bool persistent, int tpl, int tile, int waves_per_block, int* blocks);
 // the same pass with the potential in acc.w: one workgroup per task, one target per lane, records in
 // position space (not address lists)
 hipError_t launch_grav_potential(int order, const GravArgs& a, int waves_per_block, hipStream_t s);
@@ -246,12 +248,14 @@ constexpr int kCtrTickets = 0, kCtrExits = 1, kCtrEpoch = 2, kCtrRounds = 3;  //
                                 // kCtrRounds + 2r table parts (free-scan and union items) done,
                                 // + 1 data parts (union items) done
 constexpr int kStepLead = 3;    // rounds by which the reorganisation items precede the passes
-hipError_t launch_step(int order, bool two, const StepArgs& a, int grid, int tile, hipStream_t s);
+hipError_t launch_step(int order, int tpl, const StepArgs& a, int grid, int tile, hipStream_t s);
+// the same schedule with reorganisation items only (a.has_force = 0), in a kernel without force code
+hipError_t launch_step_reorg(const StepArgs& a, int grid, hipStream_t s);
 // The combined pass over the tasks of several rounds in one launch: items[b] (kind = round index,
 // idx = first packed target) with rounds[kind]; waves_per_block waves per task.
-hipError_t launch_grav_rounds(int order, bool two, const StepItem* items, int32_t n_items, const GravArgs* rounds,
+hipError_t launch_grav_rounds(int order, int tpl, const StepItem* items, int32_t n_items, const GravArgs* rounds,
                               int tile, int waves_per_block, hipStream_t s);
-hipError_t step_occupancy(int order, bool two, int tile, int* blocks);
+hipError_t step_occupancy(int order, int tpl, int tile, int* blocks);
 
 struct GravAdjArgs {
   GravArgs f;              // forward arguments (lists, records, nodes)

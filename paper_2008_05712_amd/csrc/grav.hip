@@ -15,7 +15,7 @@ using dev::uniform;
 // counter, one address for the whole grid, sees a few times fewer atomics).
 constexpr int kGrabTasks = 4;
 
-template <int ORDER, bool LISTS, bool PERSIST, bool TWO, bool POT = false>
+template <int ORDER, bool LISTS, bool PERSIST, int TPL, bool POT = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k_grav(GravArgs a) {
   extern __shared__ float4 smem[];
   __shared__ int s_task;
@@ -51,45 +51,47 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k
     const dev::TaskDesc td{uniform(g.i_begin), uniform(g.i_count), uniform(g.j_first), uniform(g.j_nranges),
                            uniform(g.n_first), uniform(g.n_count), uniform(a.ibeg ? a.ibeg[t] : g.i_begin)};
     dev::NodePrefetch<ORDER> pf;
-    grav_task<ORDER, LISTS, TWO, POT>(a, t, td, smem, pf, false, [] {}, [](int) {});
+    grav_task<ORDER, LISTS, TPL, POT>(a, t, td, smem, pf, false, [] {}, [](int) {});
   }
 }
 
-template <int ORDER, bool LISTS, bool PERSIST, bool TWO>
+template <int ORDER, bool LISTS, bool PERSIST, int TPL>
 hipError_t launch_one(const GravArgs& a, int wpb, int grid, hipStream_t s) {
   size_t lds = (size_t)wpb * grav_lds_per_wave(a.tile) * sizeof(float4);
   if (!PERSIST) grid = a.n_tasks;
   if (grid < 1) return hipSuccess;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST, TWO>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST, TPL>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_grav<ORDER, LISTS, PERSIST, TWO>), dim3(grid), dim3(64 * wpb), lds, s, a);
+  hipLaunchKernelGGL((k_grav<ORDER, LISTS, PERSIST, TPL>), dim3(grid), dim3(64 * wpb), lds, s, a);
   return hipGetLastError();
 }
 
-template <int ORDER, bool LISTS, bool PERSIST, bool TWO>
+template <int ORDER, bool LISTS, bool PERSIST, int TPL>
 hipError_t occ_one(int tile, int wpb, int* blocks) {
   size_t lds = (size_t)wpb * grav_lds_per_wave(tile) * sizeof(float4);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST, TWO>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, LISTS, PERSIST, TPL>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_grav<ORDER, LISTS, PERSIST, TWO>, 64 * wpb, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_grav<ORDER, LISTS, PERSIST, TPL>, 64 * wpb, lds);
 }
 
 template <int ORDER, bool LISTS, bool PERSIST>
-hipError_t launch_two(bool two, const GravArgs& a, int wpb, int grid, hipStream_t s) {
-  return two ? launch_one<ORDER, LISTS, PERSIST, true>(a, wpb, grid, s)
-             : launch_one<ORDER, LISTS, PERSIST, false>(a, wpb, grid, s);
+hipError_t launch_two(int tpl, const GravArgs& a, int wpb, int grid, hipStream_t s) {
+  if (tpl == 2) return launch_one<ORDER, LISTS, PERSIST, 2>(a, wpb, grid, s);
+  if (tpl == 3) return launch_one<ORDER, LISTS, PERSIST, 3>(a, wpb, grid, s);
+  return launch_one<ORDER, LISTS, PERSIST, 1>(a, wpb, grid, s);
 }
 
 template <int ORDER, bool LISTS, bool PERSIST>
-hipError_t occ_two(bool two, int tile, int wpb, int* blocks) {
-  return two ? occ_one<ORDER, LISTS, PERSIST, true>(tile, wpb, blocks)
-             : occ_one<ORDER, LISTS, PERSIST, false>(tile, wpb, blocks);
+hipError_t occ_two(int tpl, int tile, int wpb, int* blocks) {
+  if (tpl == 2) return occ_one<ORDER, LISTS, PERSIST, 2>(tile, wpb, blocks);
+  if (tpl == 3) return occ_one<ORDER, LISTS, PERSIST, 3>(tile, wpb, blocks);
+  return occ_one<ORDER, LISTS, PERSIST, 1>(tile, wpb, blocks);
 }
 
 // Per-round arguments read through the constant address space: with a uniform index they come in by
@@ -111,7 +113,7 @@ __device__ __forceinline__ T cload(const __attribute__((address_space(4))) T* p)
 
 // Every task of several rounds in one launch: block b runs item b (its round's index in `kind`, its
 // task's fields and first packed target), with that round's arguments.
-template <int ORDER, bool TWO>
+template <int ORDER, int TPL>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
     k_grav_rounds(const StepItem* __restrict__ items, const GravArgs* __restrict__ rounds) {
   extern __shared__ float4 smem[];
@@ -119,19 +121,19 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
   const GravArgs ga = cload(&cst(rounds)[it.kind]);
   const dev::TaskDesc td{it.i_begin, it.i_count, it.j_first, it.j_nranges, it.n_first, it.n_count, it.idx};
   dev::NodePrefetch<ORDER> pf;
-  grav_task<ORDER, false, TWO>(ga, 0, td, smem, pf, false, [] {}, [](int) {});
+  grav_task<ORDER, false, TPL>(ga, 0, td, smem, pf, false, [] {}, [](int) {});
 }
 
-template <int ORDER, bool TWO>
+template <int ORDER, int TPL>
 hipError_t launch_rounds_one(const StepItem* items, int32_t n_items, const GravArgs* rounds, int tile, int wpb,
                              hipStream_t s) {
   const size_t lds = (size_t)wpb * grav_lds_per_wave(tile) * sizeof(float4);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav_rounds<ORDER, TWO>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav_rounds<ORDER, TPL>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_grav_rounds<ORDER, TWO>), dim3(n_items), dim3(64 * wpb), lds, s, items, rounds);
+  hipLaunchKernelGGL((k_grav_rounds<ORDER, TPL>), dim3(n_items), dim3(64 * wpb), lds, s, items, rounds);
   return hipGetLastError();
 }
 
@@ -140,23 +142,27 @@ template <int ORDER>
 hipError_t launch_pot(const GravArgs& a, int wpb, hipStream_t s) {
   const size_t lds = (size_t)wpb * grav_lds_per_wave(a.tile, true) * sizeof(float4);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, false, false, false, true>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_grav<ORDER, false, false, 1, true>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_grav<ORDER, false, false, false, true>), dim3(a.n_tasks), dim3(64 * wpb), lds, s, a);
+  hipLaunchKernelGGL((k_grav<ORDER, false, false, 1, true>), dim3(a.n_tasks), dim3(64 * wpb), lds, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_grav_rounds(int order, bool two, const StepItem* items, int32_t n_items, const GravArgs* rounds,
+hipError_t launch_grav_rounds(int order, int tpl, const StepItem* items, int32_t n_items, const GravArgs* rounds,
                               int tile, int wpb, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (order == 1) return two ? launch_rounds_one<1, true>(items, n_items, rounds, tile, wpb, s)
-                             : launch_rounds_one<1, false>(items, n_items, rounds, tile, wpb, s);
-  return two ? launch_rounds_one<2, true>(items, n_items, rounds, tile, wpb, s)
-             : launch_rounds_one<2, false>(items, n_items, rounds, tile, wpb, s);
+  if (order == 1) {
+    if (tpl == 2) return launch_rounds_one<1, 2>(items, n_items, rounds, tile, wpb, s);
+    if (tpl == 3) return launch_rounds_one<1, 3>(items, n_items, rounds, tile, wpb, s);
+    return launch_rounds_one<1, 1>(items, n_items, rounds, tile, wpb, s);
+  }
+  if (tpl == 2) return launch_rounds_one<2, 2>(items, n_items, rounds, tile, wpb, s);
+  if (tpl == 3) return launch_rounds_one<2, 3>(items, n_items, rounds, tile, wpb, s);
+  return launch_rounds_one<2, 1>(items, n_items, rounds, tile, wpb, s);
 }
 
 hipError_t launch_grav_potential(int order, const GravArgs& a, int wpb, hipStream_t s) {
@@ -164,24 +170,24 @@ hipError_t launch_grav_potential(int order, const GravArgs& a, int wpb, hipStrea
   return order == 1 ? launch_pot<1>(a, wpb, s) : launch_pot<2>(a, wpb, s);
 }
 
-hipError_t launch_grav(int order, bool lists, bool persistent, bool two, const GravArgs& a, int wpb, int grid,
+hipError_t launch_grav(int order, bool lists, bool persistent, int tpl, const GravArgs& a, int wpb, int grid,
                        hipStream_t s) {
   if (a.n_tasks <= 0) return hipSuccess;
   if (order == 1) {
-    if (lists) return persistent ? launch_two<1, true, true>(two, a, wpb, grid, s) : launch_two<1, true, false>(two, a, wpb, grid, s);
-    return persistent ? launch_two<1, false, true>(two, a, wpb, grid, s) : launch_two<1, false, false>(two, a, wpb, grid, s);
+    if (lists) return persistent ? launch_two<1, true, true>(tpl, a, wpb, grid, s) : launch_two<1, true, false>(tpl, a, wpb, grid, s);
+    return persistent ? launch_two<1, false, true>(tpl, a, wpb, grid, s) : launch_two<1, false, false>(tpl, a, wpb, grid, s);
   }
-  if (lists) return persistent ? launch_two<2, true, true>(two, a, wpb, grid, s) : launch_two<2, true, false>(two, a, wpb, grid, s);
-  return persistent ? launch_two<2, false, true>(two, a, wpb, grid, s) : launch_two<2, false, false>(two, a, wpb, grid, s);
+  if (lists) return persistent ? launch_two<2, true, true>(tpl, a, wpb, grid, s) : launch_two<2, true, false>(tpl, a, wpb, grid, s);
+  return persistent ? launch_two<2, false, true>(tpl, a, wpb, grid, s) : launch_two<2, false, false>(tpl, a, wpb, grid, s);
 }
 
-hipError_t grav_occupancy(int order, bool lists, bool persistent, bool two, int tile, int wpb, int* blocks) {
+hipError_t grav_occupancy(int order, bool lists, bool persistent, int tpl, int tile, int wpb, int* blocks) {
   if (order == 1) {
-    if (lists) return persistent ? occ_two<1, true, true>(two, tile, wpb, blocks) : occ_two<1, true, false>(two, tile, wpb, blocks);
-    return persistent ? occ_two<1, false, true>(two, tile, wpb, blocks) : occ_two<1, false, false>(two, tile, wpb, blocks);
+    if (lists) return persistent ? occ_two<1, true, true>(tpl, tile, wpb, blocks) : occ_two<1, true, false>(tpl, tile, wpb, blocks);
+    return persistent ? occ_two<1, false, true>(tpl, tile, wpb, blocks) : occ_two<1, false, false>(tpl, tile, wpb, blocks);
   }
-  if (lists) return persistent ? occ_two<2, true, true>(two, tile, wpb, blocks) : occ_two<2, true, false>(two, tile, wpb, blocks);
-  return persistent ? occ_two<2, false, true>(two, tile, wpb, blocks) : occ_two<2, false, false>(two, tile, wpb, blocks);
+  if (lists) return persistent ? occ_two<2, true, true>(tpl, tile, wpb, blocks) : occ_two<2, true, false>(tpl, tile, wpb, blocks);
+  return persistent ? occ_two<2, false, true>(tpl, tile, wpb, blocks) : occ_two<2, false, false>(tpl, tile, wpb, blocks);
 }
 
 }  // namespace gc

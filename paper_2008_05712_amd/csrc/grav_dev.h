@@ -229,18 +229,28 @@ struct NodeRegs {
   float4 v0, v1, v2;
 };
 
+// The node table as a raw buffer (three records, 48 bytes, a node).  A load past its end returns
+// zeros, so a lane without a node (index < 0) loads a zero record with no branch and no zeroing.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t node_rsrc(const float4* nodes, int32_t n_nodes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(nodes), (short)0, n_nodes * 48, 0x00020000);
+}
+
+__device__ __forceinline__ float4 u4f(const __attribute__((ext_vector_type(4))) unsigned v) {
+  return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
+}
+
 template <int ORDER>
-__device__ __forceinline__ NodeRegs<ORDER> load_node(const float4* __restrict__ nodes, int idx) {
+__device__ __forceinline__ NodeRegs<ORDER> load_node(__amdgpu_buffer_rsrc_t nodes, int idx) {
   NodeRegs<ORDER> r;
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  r.v0 = z; r.v1 = z; r.v2 = z;
-  if (idx >= 0) {
-    const float4* nd = nodes + 3 * idx;
-    r.v0 = gld(nd);
-    if (ORDER == 2) {
-      r.v1 = gld(nd + 1);
-      r.v2 = gld_xyz(nd + 2);  // (its fourth word is padding)
-    }
+  const int off = idx >= 0 ? idx * 48 : 0x7ffffff0;  // past the end of any node table
+  r.v0 = u4f(__builtin_amdgcn_raw_buffer_load_b128(nodes, off, 0, 0));
+  if (ORDER == 2) {
+    r.v1 = u4f(__builtin_amdgcn_raw_buffer_load_b128(nodes, off + 16, 0, 0));
+    // the third record's fourth word is padding: three words
+    const __attribute__((ext_vector_type(3))) unsigned c = __builtin_amdgcn_raw_buffer_load_b96(nodes, off + 32, 0, 0);
+    r.v2 = make_float4(__uint_as_float(c[0]), __uint_as_float(c[1]), __uint_as_float(c[2]), 0.f);
+  } else {
+    r.v1 = r.v2 = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   return r;
 }
@@ -265,7 +275,7 @@ struct NodePrefetch {
 };
 
 template <int ORDER>
-__device__ __forceinline__ void node_prefetch(const float4* __restrict__ nodes, const int* __restrict__ node_idx,
+__device__ __forceinline__ void node_prefetch(__amdgpu_buffer_rsrc_t nodes, const int* __restrict__ node_idx,
                                               int n_first, int n_count, NodePrefetch<ORDER>& pf) {
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
@@ -289,6 +299,15 @@ __host__ __device__ __forceinline__ int grav_lds_per_wave(int tile, bool pot = f
   return grav_rec_cap(tile) + (pot ? 128 : 96);
 }
 
+// Two targets per lane fill more of the wavefront than one for a task of n targets (n = i_count,
+// at most 64 counted) when floor(64 / ceil(n / 2)) slices of lane pairs hold more than twice
+// floor(64 / n) slices of single lanes (n = 6, 13, 14, 17, 18, 22, 23, 24 and 33 to 42); otherwise
+// one target per lane is at least as full and reads no duplicate target.
+__host__ __device__ __forceinline__ bool two_fills_more(int n) {
+  n = n < 64 ? n : 64;
+  return n > 0 && 64 / ((n + 1) >> 1) > 2 * (64 / n);
+}
+
 // A task as the force code reads it: the submitted fields and the first target's position in the
 // record array (its packed position, or i_begin when records are read in place).
 struct TaskDesc {
@@ -298,8 +317,8 @@ struct TaskDesc {
 // One task on one workgroup of W = blockDim.x / 64 wavefronts.  Wave w takes the task's nodes
 // w, w + W, ... and the w-th of W contiguous, nearly equal shares of its direct records (address
 // lists: windows w, w + W, ...), so W waves share one task's lists.  Within a wave the lanes are (lane-target j) x (slice s): with
-// TWO each lane carries targets j and j + h (h = ceil(i_count / 2)), otherwise target j (h =
-// i_count); S = floor(64 / h) slices.  The per-target sums are reduced across slices within each
+// two targets per lane (TPL 2) each lane carries targets j and j + h (h = ceil(i_count / 2)),
+// otherwise (TPL 1) target j (h = i_count); S = floor(64 / h) slices.  The per-target sums are reduced across slices within each
 // wave and then across the W waves, in a fixed order.  `smem` is the block's dynamic LDS of
 // W * grav_lds_per_wave(tile) records; the call starts and ends with every wave of the block
 // converged (it contains block barriers).  pf holds the task's first node tile when `have_pf`
@@ -311,11 +330,12 @@ struct TaskDesc {
 // POT (one target per lane, records in position space): acc.w also receives the potential of the
 // task's terms, -G times the sum above, without the target's own direct term (a target found in its
 // task's direct ranges has contributed m r^-1 at r = eps, which is taken out again).
-template <int ORDER, bool LISTS, bool TWO, bool POT = false, class Ready, class Next>
-__device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const TaskDesc& tk,
+template <int ORDER, bool LISTS, int TPL, bool POT = false, class Ready, class Next>
+__device__ __forceinline__ void grav_task_body(const GravArgs& a, const int t, const TaskDesc& tk,
                                           float4* __restrict__ smem, NodePrefetch<ORDER>& pf, bool have_pf,
                                           Ready&& ready, Next&& next) {
-  static_assert(!POT || (!TWO && !LISTS), "the potential runs one target per lane in position space");
+  static_assert(TPL == 1 || TPL == 2, "one or two targets per lane");
+  static_assert(!POT || (TPL == 1 && !LISTS), "the potential runs one target per lane in position space");
   constexpr int NC = POT ? 4 : 3;  // sums per target
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
@@ -332,13 +352,15 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
   // this wave's nodes; the first tile does not depend on the records, so its loads go out first
   const int nw = tk.n_count > wid ? (tk.n_count - wid + W - 1) / W : 0;
   const int* nl = a.node_idx + tk.n_first + wid;
-  if (!have_pf) node_prefetch<ORDER>(a.nodes, a.node_idx, tk.n_first, tk.n_count, pf);
+  const __amdgpu_buffer_rsrc_t nodes = node_rsrc(a.nodes, a.n_nodes);
+  if (!have_pf) node_prefetch<ORDER>(nodes, a.node_idx, tk.n_first, tk.n_count, pf);
   ready();
   for (int i0 = 0; i0 < ic; i0 += 64) {
-    if (i0 > 0) node_prefetch<ORDER>(a.nodes, a.node_idx, tk.n_first, tk.n_count, pf);
+    if (i0 > 0) node_prefetch<ORDER>(nodes, a.node_idx, tk.n_first, tk.n_count, pf);
     const bool last = i0 + 64 >= ic;
     const int icc = ic - i0 < 64 ? ic - i0 : 64;
-    const int h = TWO ? (icc + 1) >> 1 : icc;
+    constexpr bool two = TPL == 2;
+    const int h = two ? (icc + 1) >> 1 : icc;
     const int S = 64 / h;
     const int il = lane % h;
     const int sl = lane / h;
@@ -346,13 +368,13 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
     // tiles hold a multiple of S records, so that only a share's last tile is padded
     const int NT = S * (kNodeTile / S);  // nodes per node tile
     const int DT = S * (tile / S);       // records per direct tile
-    const int ib = il + h < icc ? il + h : il;  // TWO: second target (a copy of the first if absent)
+    const int ib = il + h < icc ? il + h : il;  // two: second target (a copy of the first if absent)
     float3 A = make_float3(0.f, 0.f, 0.f), B = A;
     if (active) {
       const int pb = LISTS ? 0 : tk.ibeg + i0;
       const float4 r = gld(a.rec + (LISTS ? gld(a.ilist + gld(a.ioff + t) + i0 + il) : pb + il));
       A = make_float3(r.x, r.y, r.z);
-      if (TWO) {
+      if (two) {
         const float4 q = gld(a.rec + (LISTS ? gld(a.ilist + gld(a.ioff + t) + i0 + ib) : pb + ib));
         B = make_float3(q.x, q.y, q.z);
       }
@@ -361,7 +383,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
     // one tile of C records per slice starting at L + rec_stride * sl * C: accumulate it
     auto tile_sum = [&](int C, bool quads) {
       if (!active) return;
-      if (TWO) {
+      if (two) {
         Acc2 r{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (quads) tile_quads2(L + 3 * sl * C, C, A, B, a.eps2, r);
         else tile_pairs2(L + sl * C, C, A, B, a.eps2, r);
@@ -383,15 +405,19 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
     // ---- node terms: this wave's nodes are list entries w, w + W, ...
     {
       // the prefetched first tile holds nodes 0..63 and the index of node 64 + lane; with NT < 64
-      // its lanes >= NT are left out and the next tile starts at node NT
-      if (NT < kNodeTile) pf.idx_next = (lane < NT && NT + lane < nw) ? gld(nl + (NT + lane) * W) : -1;
+      // its lanes >= NT are left out (zero records) and the next tile starts at node NT.  Every
+      // tile's lanes past its last node then hold zero records: the padding of the tile
+      if (NT < kNodeTile) {
+        pf.idx_next = (lane < NT && NT + lane < nw) ? gld(nl + (NT + lane) * W) : -1;
+        if (lane >= NT) pf.cur = load_node<ORDER>(nodes, -1);
+      }
       for (int nb = 0; nb < nw; nb += NT) {
         const int cnt = nw - nb < NT ? nw - nb : NT;
         const int C = (cnt + S - 1) / S;
-        store_node<ORDER>(L, lane, lane < cnt ? pf.cur : load_node<ORDER>(a.nodes, -1));  // padding: zero records
+        store_node<ORDER>(L, lane, pf.cur);
         // prefetch the next tile's records and the index of the one after
         if (nb + NT < nw) {
-          pf.cur = load_node<ORDER>(a.nodes, pf.idx_next);
+          pf.cur = load_node<ORDER>(nodes, pf.idx_next);
           const int e2 = nb + 2 * NT + lane;
           pf.idx_next = (lane < NT && e2 < nw) ? gld(nl + e2 * W) : -1;
         }
@@ -463,7 +489,7 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
 
     // ---- reduce: slices within the wave, then the W waves, in a fixed order
     double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-    if (TWO) {
+    if (two) {
       // 6 sums per lane: the tile area is free now
       double* R2 = reinterpret_cast<double*>(L);
       R2[6 * lane] = Ax; R2[6 * lane + 1] = Ay; R2[6 * lane + 2] = Az;
@@ -522,6 +548,22 @@ __device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const 
       gst(a.acc + tk.i_begin + i0 + lane, make_float4((float)(a.G * tx), (float)(a.G * ty), (float)(a.G * tz), phi));
     }
     if (!last) __syncthreads();
+  }
+}
+
+// A task in targets-per-lane mode TPL: 1 or 2 as above; 3 chooses per task, two where they fill more
+// lanes (two_fills_more), so that each form's registers are live only in its own branch.
+template <int ORDER, bool LISTS, int TPL, bool POT = false, class Ready, class Next>
+__device__ __forceinline__ void grav_task(const GravArgs& a, const int t, const TaskDesc& tk,
+                                          float4* __restrict__ smem, NodePrefetch<ORDER>& pf, bool have_pf,
+                                          Ready&& ready, Next&& next) {
+  if constexpr (TPL == 3) {
+    if (two_fills_more(tk.i_count))
+      grav_task_body<ORDER, LISTS, 2, POT>(a, t, tk, smem, pf, have_pf, ready, next);
+    else
+      grav_task_body<ORDER, LISTS, 1, POT>(a, t, tk, smem, pf, have_pf, ready, next);
+  } else {
+    grav_task_body<ORDER, LISTS, TPL, POT>(a, t, tk, smem, pf, have_pf, ready, next);
   }
 }
 

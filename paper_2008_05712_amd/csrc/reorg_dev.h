@@ -397,6 +397,55 @@ __device__ __forceinline__ uint32_t union_table(const ReorgArgs& a, int b, uint3
   return m;
 }
 
+// Whole-step form of the union side with evict_after, both parts in one pass: no round of the launch
+// changes a value of the chare table, the occupancy or a resident record, so the records are loaded
+// right after the lookup, and arrive while the missing ranks and slot assignment are found; then the
+// packed copies and the staging.  A staged id's chare-table entry and slot flag end as they
+// were, so neither is written.
+__device__ __forceinline__ void union_fused(const ReorgArgs& a, int b, uint32_t tag, uint32_t ltag, int64_t fbase,
+                                            int* sh, uint32_t* s_ex, const int32_t (&id)[kUItems]) {
+  uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbf;
+  const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;
+  int32_t slot[kUItems];
+  const uint32_t fm = union_lookup<false>(a, b, id, slot);
+  float4 v[kUItems];
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if ((fm >> i) & 1u) v[i] = gld(a.src + id[i]);
+    else if (k0 + i < a.u) v[i] = gld(a.pool + slot[i]);
+  }
+  int tot;
+  int rm = block_excl_scan(__popc(fm), sh, &tot);
+  if (threadIdx.x < 64) {
+    const uint32_t ex = look_back(flags, b, tag, (uint32_t)tot, a.state + GC_STATE_ERR);
+    if (threadIdx.x == 0) {
+      *s_ex = ex;
+      if (b == a.nbu - 1) {
+        istore(a.state + GC_STATE_UNION, a.u);
+        istore(a.state + GC_STATE_MISSING, (int32_t)(ex + (uint32_t)tot));
+      }
+    }
+  }
+  __syncthreads();
+  rm += (int)*s_ex;
+  if (fm) union_probe(a.free_list, a.ftotal, ltag, fbase + rm, a.flimit, fm, slot, a.state + GC_STATE_ERR);
+#pragma unroll
+  for (int i = 0; i < kUItems; ++i) {
+    const int64_t k = k0 + i;
+    if (k >= a.u) continue;
+    const int32_t s = slot[i];
+    gst(a.uslot + k, s);
+    gst(a.packed + k, v[i]);
+    if ((fm >> i) & 1u) {
+      gst(a.missing + rm, id[i]);
+      gst(a.mslot + rm, s);
+      ++rm;
+      if (s >= 0) gst(a.pool + s, v[i]);
+    }
+  }
+}
+
 __device__ __forceinline__ void union_data(const ReorgArgs& a, int b, const int32_t (&id)[kUItems],
                                            const int32_t (&slot)[kUItems], uint32_t fm, bool coh) {
   const int64_t k0 = (int64_t)b * kUBlock + (int64_t)threadIdx.x * kUItems;

@@ -1464,8 +1464,8 @@ static gc_status check_prm(gc_batch b, const gc_force_params* prm, int* tile, in
   }
   if (prm->schedule < GC_SCHED_TASKS || prm->schedule > GC_SCHED_ROUNDS)
     return set_err(c, GC_E_INVAL, "schedule must be GC_SCHED_TASKS, GC_SCHED_QUEUE, GC_SCHED_STEP or GC_SCHED_ROUNDS");
-  if (prm->targets_per_lane < 0 || prm->targets_per_lane > 2)
-    return set_err(c, GC_E_INVAL, "targets_per_lane must be 0, 1 or 2");
+  if (prm->targets_per_lane < 0 || prm->targets_per_lane > 3)
+    return set_err(c, GC_E_INVAL, "targets_per_lane must be 0, 1, 2 or 3");
   if (b->kind == GC_KIND_GRAV && b->max_node >= prm->n_nodes)
     return set_err(c, GC_E_INVAL, "node index %d is not below n_nodes %d of the node table", b->max_node, prm->n_nodes);
   if (prm->want_potential != 0 && prm->want_potential != 1) return set_err(c, GC_E_INVAL, "want_potential must be 0 or 1");
@@ -1513,6 +1513,7 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
     a.jlist = b->jlist.as<int32_t>();
     a.node_idx = b->d_nodes.as<int32_t>();
     a.nodes = reinterpret_cast<const float4*>(nodes_dev);
+    a.n_nodes = prm->n_nodes;
     a.rec = b->rec;
     a.acc = reinterpret_cast<float4*>(acc_dev);
     a.G = prm->G;
@@ -1521,11 +1522,11 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
     a.queue = b->queue.as<int32_t>();
     a.order = b->d_order.as<int32_t>();
     int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
-    const bool two = prm->targets_per_lane == 2;
+    const int tpl = prm->targets_per_lane == 0 ? 1 : prm->targets_per_lane;
     int grid = prm->grid_blocks;
     if (persistent && grid <= 0) {
       int per = 0;
-      GC_HIP(c, grav_occupancy(order, lists, true, two, tile, wpb, &per));
+      GC_HIP(c, grav_occupancy(order, lists, true, tpl, tile, wpb, &per));
       grid = std::max(1, per) * c->n_cu;
     }
     // aggregation: consecutive launches over slices of the launch order (each slice's queue counter
@@ -1551,7 +1552,7 @@ static gc_status launch_combined_async(gc_batch b, const gc_force_params* prm, c
       aq.order = b->d_order.as<int32_t>() + (int64_t)q * agg;
       aq.n_tasks = std::min<int32_t>(agg, T - q * agg);
       aq.queue = b->queue.as<int32_t>() + (n_launch > 1 ? q : 0);
-      GC_HIP(c, launch_grav(order, lists, persistent, two, aq, wpb, grid, s));
+      GC_HIP(c, launch_grav(order, lists, persistent, tpl, aq, wpb, grid, s));
     }
   } else {
     if (lists) return set_err(c, GC_E_UNSUPPORTED, "Lennard-Jones supports PACK, REDUNDANT and NONE");
@@ -1625,11 +1626,11 @@ extern "C" gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_
   if (!prm || !blocks_per_cu) return set_err(ctx, GC_E_INVAL, "gc_occupancy: NULL argument");
   int tile = prm->tile ? prm->tile : 256, wpb = prm->waves_per_block ? prm->waves_per_block : 4, per = 0;
   const int order = prm->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
-  const bool two = prm->targets_per_lane == 2;
+  const int tpl = prm->targets_per_lane == 0 ? 1 : prm->targets_per_lane;
   if (prm->schedule == GC_SCHED_STEP)
-    GC_HIP(ctx, step_occupancy(order, two, tile, &per));
+    GC_HIP(ctx, step_occupancy(order, tpl, tile, &per));
   else
-    GC_HIP(ctx, grav_occupancy(order, false, prm->schedule == GC_SCHED_QUEUE, two, tile, wpb, &per));
+    GC_HIP(ctx, grav_occupancy(order, false, prm->schedule == GC_SCHED_QUEUE, tpl, tile, wpb, &per));
   *blocks_per_cu = per;
   if (n_cu) *n_cu = ctx->n_cu;
   return GC_OK;
@@ -1779,6 +1780,7 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
     a.f.ibeg = packed ? b->pibeg.as<int32_t>() : nullptr;
     a.f.node_idx = b->d_nodes.as<int32_t>();
     a.f.nodes = reinterpret_cast<const float4*>(nodes_dev);
+    a.f.n_nodes = prm->n_nodes;
     a.f.rec = b->rec;
     a.f.G = prm->G;
     a.f.eps2 = prm->soft_eps * prm->soft_eps;
@@ -1903,6 +1905,7 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     g.joff = b->d_joff.as<int32_t>();
     g.node_idx = b->d_nodes.as<int32_t>();
     g.nodes = reinterpret_cast<const float4*>(nodes_dev);
+    g.n_nodes = prm->n_nodes;
     g.rec = b->packed.as<float4>();
     g.acc = reinterpret_cast<float4*>(acc_dev);
     g.G = prm->G;
@@ -2009,8 +2012,8 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   GC_HIP(ctx, launch_fill_i32(gr->step_fl.as<int32_t>(), 0, 2 * fl_words, s));  // tag 0: never a launch's
   GC_HIP(ctx, hipStreamSynchronize(s));  // the host vectors go out of scope
   int per = 0;
-  const bool two = prm->targets_per_lane == 2;
-  GC_HIP(ctx, step_occupancy(order, two, tile, &per));
+  const int tpl = prm->targets_per_lane == 0 ? 1 : prm->targets_per_lane;
+  GC_HIP(ctx, step_occupancy(order, tpl, tile, &per));
   // the reorganisation items alone (rounds schedule) are a few hundred: one block each, so that the
   // launch's ticket and exit counters see no more requests than there are items
   const int grid = combined_pass ? std::min(std::max(1, per) * ctx->n_cu, std::max(1, nt))
@@ -2034,9 +2037,10 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
     le = launch_evict(pb->missing.as<int32_t>(), pb->state.as<int32_t>() + GC_STATE_MISSING, std::max<int32_t>(pb->u, 1),
                       p->slot_of.as<int32_t>(), p->n_ids, p->occ.as<uint32_t>(), s);
   }
-  if (le == hipSuccess) le = launch_step(order, two, a, grid, tile, s);
+  if (le == hipSuccess)
+    le = combined_pass ? launch_step_reorg(a, grid, s) : launch_step(order, tpl, a, grid, tile, s);
   if (le == hipSuccess && combined_pass)
-    le = launch_grav_rounds(order, two, gr->round_items.as<StepItem>(), (int32_t)fitems.size(),
+    le = launch_grav_rounds(order, tpl, gr->round_items.as<StepItem>(), (int32_t)fitems.size(),
                             gr->round_args.as<GravArgs>(), tile, wpb, s);
   hipGraph_t g = nullptr;
   ce = hipStreamEndCapture(s, &g);
@@ -2469,7 +2473,7 @@ extern "C" gc_status gc_autotune(gc_batch b, const gc_force_params* base, const 
     int per = 1;
     const int order = base->kind == GC_FORCE_GRAV_QUAD ? 2 : 1;
     const bool lists = b->mode == GC_REORG_INDIRECT || b->mode == GC_REORG_SORTED;
-    hipError_t e = grav_occupancy(order, lists, shape.schedule == 1, shape.targets_per_lane == 2,
+    hipError_t e = grav_occupancy(order, lists, shape.schedule == 1, shape.targets_per_lane == 0 ? 1 : shape.targets_per_lane,
                                   shape.tile ? shape.tile : 256, shape.waves_per_block ? shape.waves_per_block : 4, &per);
     if (e != hipSuccess) st = hip_fail(c, e, "gc_autotune occupancy");
     const int32_t occ = std::max(1, per) * c->n_cu;

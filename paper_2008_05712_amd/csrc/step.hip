@@ -118,11 +118,11 @@ __device__ __forceinline__ T cload(const __attribute__((address_space(4))) T* p)
   return v;
 }
 
-#ifndef GC_STEP_WPE
-#define GC_STEP_WPE 5
-#endif
-template <int ORDER, bool TWO>
-__global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_per_eu(GC_STEP_WPE))) k_step(StepArgs s) {
+// FORCE: the launch runs force items (5 waves per SIMD: at most 96 VGPRs for the force code);
+// without (the rounds schedule's reorganisation launch) no force code is compiled in and the
+// reorganisation items get the registers they use.
+template <int ORDER, int TPL, bool FORCE>
+__global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_per_eu(FORCE ? 5 : 1))) k_step(StepArgs s) {
   extern __shared__ float4 smem[];
   __shared__ int sh[dev::kRThreads / 64];
   __shared__ uint32_t s_ex, s_tag;
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
     uint64_t* ch_done = s.ctr + kCtrStride * (kCtrRounds + 2 * k);
     uint64_t* dt_done = ch_done + kCtrStride;
     const int pr = uniform(R.prev);
-    if (type == kItemForce) {
+    if (FORCE && type == kItemForce) {
       const GravArgs ga = cload(&R.grav);
       const dev::TaskDesc td{uni(s_item[cb].i_begin), uni(s_item[cb].i_count), uni(s_item[cb].j_first),
                              uni(s_item[cb].j_nranges), uni(s_item[cb].n_first), uni(s_item[cb].n_count), idx};
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
       const uint64_t target = goal * (uint64_t)R.reorg.nbu + (k == s.fail_round ? 1u : 0u);
       bool pf_next = false;
       // the round's packed records are read only once its data parts are done
-      dev::grav_task<ORDER, false, TWO>(ga, 0, td, smem, pf, have_pf, [&] {
+      dev::grav_task<ORDER, false, TPL>(ga, 0, td, smem, pf, have_pf, [&] {
         if (k > ready) {
           if (tid == 0 && !(poll_k == k && poll_v >= target))
             wait_ge(dt_done, target, err, k == s.fail_round ? s.fail_spins : s.spin_limit);
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
         if ((kind2 & 3) != kItemForce) return;
         const int k2 = kind2 >> 2;
         const __attribute__((address_space(4))) StepRound& R2 = cst(s.rounds)[k2];
-        dev::node_prefetch<ORDER>(R2.grav.nodes, R2.grav.node_idx, uni(s_item[cb ^ 1].n_first),
+        dev::node_prefetch<ORDER>(dev::node_rsrc(R2.grav.nodes, R2.grav.n_nodes), R2.grav.node_idx, uni(s_item[cb ^ 1].n_first),
                                   uni(s_item[cb ^ 1].n_count), pf);
         pf_next = true;
         if (tid == 0 && k2 > ready) {
@@ -264,9 +264,13 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
         if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
       } else {
         int32_t slot[dev::kUItems];
-        uint32_t fm;
+        uint32_t fm = 0;
         const int64_t fbase = s_base;
-        (void)dev::union_table(ra, idx, tag, ltag, fbase, sh, &s_ex, ids, slot, fm, !ra.evict_after);
+        // with the fixture and no force items in the launch, both parts in one pass (in a kernel with
+        // force code its registers would spill); otherwise the table part first
+        const bool fused = !FORCE && ra.evict_after;
+        if (fused) dev::union_fused(ra, idx, tag, ltag, fbase, sh, &s_ex, ids);
+        else (void)dev::union_table(ra, idx, tag, ltag, fbase, sh, &s_ex, ids, slot, fm, !ra.evict_after);
         if (tid == 0 && idx == ra.nbu - 1) {
           dev::tstore(s.fmeta + 1 + k, dev::tword(ltag, 0, (uint32_t)fbase));
           if (s_avail >= 0) dev::istore(R.reorg.state + GC_STATE_FREE, (int32_t)s_avail);
@@ -284,17 +288,25 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
             dev::istore(R.reorg.state + GC_STATE_FREE, (int32_t)(ft & 0x7fffffffu));
           }
         }
-        // later rounds read this round's table writes unless the fixture leaves the table unchanged
-        const uint64_t old = publish_done(ch_done, !ra.evict_after);
-        if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
-        // data part: after the previous round's (its staging may be read here, its slots reused)
-        if (tid == 0 && pr >= 0)
-          wait_ge(s.ctr + kCtrStride * (kCtrRounds + 2 * pr + 1), goal * (uint64_t)cst(s.rounds)[pr].reorg.nbu, err,
-                  s.spin_limit);
-        __syncthreads();
-        dev::union_data(ra, idx, ids, slot, fm, !ra.evict_after);
-        // read by this round's force items, and without the fixture by later rounds' data parts
-        (void)publish_done(dt_done, s.has_force || !ra.evict_after);
+        if (fused) {
+          // both parts are done; nothing in the launch reads the records, and the table part's count
+          // only advances the batch's tag
+          (void)publish_done(dt_done, false);
+          const uint64_t old = publish_done(ch_done, false);
+          if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
+        } else {
+          // later rounds read this round's table writes unless the fixture leaves the table unchanged
+          const uint64_t old = publish_done(ch_done, !ra.evict_after);
+          if (tid == 0 && old + 1 == goal * (uint64_t)R.n_chain) dev::istore(R.reorg.state + dev::kTag, (int32_t)tag);
+          // data part: after the previous round's (its staging may be read here, its slots reused)
+          if (tid == 0 && pr >= 0)
+            wait_ge(s.ctr + kCtrStride * (kCtrRounds + 2 * pr + 1), goal * (uint64_t)cst(s.rounds)[pr].reorg.nbu, err,
+                    s.spin_limit);
+          __syncthreads();
+          dev::union_data(ra, idx, ids, slot, fm, !ra.evict_after);
+          // read by this round's force items, and without the fixture by later rounds' data parts
+          (void)publish_done(dt_done, s.has_force || !ra.evict_after);
+        }
       }
       __builtin_amdgcn_s_setprio(0);
       fetch_next();
@@ -313,40 +325,58 @@ __global__ void __launch_bounds__(dev::kRThreads) __attribute__((amdgpu_waves_pe
 
 size_t step_lds(int tile) { return (size_t)(dev::kRThreads / 64) * grav_lds_per_wave(tile) * sizeof(float4); }
 
-template <int ORDER, bool TWO>
+template <int ORDER, int TPL>
 hipError_t step_attr(int tile) {
   const size_t lds = step_lds(tile);
   if (lds <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_step<ORDER, TWO>), hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_step<ORDER, TPL, true>), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds);
 }
 
-template <int ORDER, bool TWO>
+template <int ORDER, int TPL>
 hipError_t step_launch_one(const StepArgs& a, int grid, int tile, hipStream_t s) {
-  hipError_t e = step_attr<ORDER, TWO>(tile);
+  hipError_t e = step_attr<ORDER, TPL>(tile);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_step<ORDER, TWO>), dim3(grid), dim3(dev::kRThreads), step_lds(tile), s, a);
+  hipLaunchKernelGGL((k_step<ORDER, TPL, true>), dim3(grid), dim3(dev::kRThreads), step_lds(tile), s, a);
   return hipGetLastError();
 }
 
-template <int ORDER, bool TWO>
+template <int ORDER, int TPL>
 hipError_t step_occ_one(int tile, int* blocks) {
-  hipError_t e = step_attr<ORDER, TWO>(tile);
+  hipError_t e = step_attr<ORDER, TPL>(tile);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<ORDER, TWO>, dev::kRThreads, step_lds(tile));
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_step<ORDER, TPL, true>, dev::kRThreads, step_lds(tile));
 }
 
 }  // namespace
 
-hipError_t launch_step(int order, bool two, const StepArgs& a, int grid, int tile, hipStream_t s) {
+hipError_t launch_step_reorg(const StepArgs& a, int grid, hipStream_t s) {
   if (grid < 1 || a.n_items <= 0) return hipSuccess;
-  if (order == 1) return two ? step_launch_one<1, true>(a, grid, tile, s) : step_launch_one<1, false>(a, grid, tile, s);
-  return two ? step_launch_one<2, true>(a, grid, tile, s) : step_launch_one<2, false>(a, grid, tile, s);
+  hipLaunchKernelGGL((k_step<2, 1, false>), dim3(grid), dim3(dev::kRThreads), 0, s, a);
+  return hipGetLastError();
 }
 
-hipError_t step_occupancy(int order, bool two, int tile, int* blocks) {
-  if (order == 1) return two ? step_occ_one<1, true>(tile, blocks) : step_occ_one<1, false>(tile, blocks);
-  return two ? step_occ_one<2, true>(tile, blocks) : step_occ_one<2, false>(tile, blocks);
+hipError_t launch_step(int order, int tpl, const StepArgs& a, int grid, int tile, hipStream_t s) {
+  if (grid < 1 || a.n_items <= 0) return hipSuccess;
+  if (order == 1) {
+    if (tpl == 2) return step_launch_one<1, 2>(a, grid, tile, s);
+    if (tpl == 3) return step_launch_one<1, 3>(a, grid, tile, s);
+    return step_launch_one<1, 1>(a, grid, tile, s);
+  }
+  if (tpl == 2) return step_launch_one<2, 2>(a, grid, tile, s);
+  if (tpl == 3) return step_launch_one<2, 3>(a, grid, tile, s);
+  return step_launch_one<2, 1>(a, grid, tile, s);
+}
+
+hipError_t step_occupancy(int order, int tpl, int tile, int* blocks) {
+  if (order == 1) {
+    if (tpl == 2) return step_occ_one<1, 2>(tile, blocks);
+    if (tpl == 3) return step_occ_one<1, 3>(tile, blocks);
+    return step_occ_one<1, 1>(tile, blocks);
+  }
+  if (tpl == 2) return step_occ_one<2, 2>(tile, blocks);
+  if (tpl == 3) return step_occ_one<2, 3>(tile, blocks);
+  return step_occ_one<2, 1>(tile, blocks);
 }
 
 }  // namespace gc

@@ -132,20 +132,48 @@ def test_persistent_schedule_and_tiles_are_bitwise_equal(ctx, plum):
     rig.close()
 
 
+@pytest.mark.parametrize("tpl", [2, 3])
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("mode", [gc.REORG_PACK, gc.REORG_SORTED, gc.REORG_NONE])
-def test_two_targets_per_lane_matches_oracle(ctx, plum, mode, order):
-    # each lane holds two targets of its task (odd and even bucket sizes, one-target tasks); the result
-    # meets the oracle bar for every shape, and the persistent queue is bitwise the per-task launch
-    print(f"[gpu] two targets per lane mode={mode} order={order}", flush=True)
+def test_two_targets_per_lane_matches_oracle(ctx, plum, mode, order, tpl):
+    # each lane holds two targets of its task (odd and even bucket sizes, one-target tasks), or, with
+    # mode 3, whichever of one or two fills more lanes; the result meets the oracle bar for every
+    # shape, and the persistent queue is bitwise the per-task launch
+    print(f"[gpu] two targets per lane mode={mode} order={order} tpl={tpl}", flush=True)
     rig = GravRig(ctx, plum)
     b = rig.batch(whole(plum))
     ref = O.grav_workload(plum, order=order)
     for tile, wpb in [(256, 4), (128, 2), (512, 8), (64, 1)]:
-        base = rig.run(b, mode, order=order, tile=tile, waves_per_block=wpb, targets_per_lane=2)
+        base = rig.run(b, mode, order=order, tile=tile, waves_per_block=wpb, targets_per_lane=tpl)
         assert rel_l2_per_task(base, ref, whole(plum)).max() <= TOL, (tile, wpb)
-        got = rig.run(b, mode, order=order, tile=tile, waves_per_block=wpb, schedule=1, targets_per_lane=2)
+        got = rig.run(b, mode, order=order, tile=tile, waves_per_block=wpb, schedule=1, targets_per_lane=tpl)
         assert np.array_equal(got, base), (tile, wpb)
+    b.destroy()
+    rig.close()
+
+
+def _two_fills_more(n):
+    # two targets per lane fill more lanes than one: floor(64 / ceil(n / 2)) > 2 floor(64 / n)
+    return 64 // ((n + 1) // 2) > 2 * (64 // n)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_per_chunk_choice_is_one_of_the_two_forms(ctx, plum, order):
+    # mode 3 takes, for each task (at most 32 targets here: one chunk), exactly the bits of the one- or
+    # the two-target form, as the lane rule picks; both forms occur
+    rig = GravRig(ctx, plum)
+    b = rig.batch(whole(plum))
+    one = rig.run(b, gc.REORG_PACK, order=order, targets_per_lane=1)
+    two = rig.run(b, gc.REORG_PACK, order=order, targets_per_lane=2)
+    auto = rig.run(b, gc.REORG_PACK, order=order, targets_per_lane=3)
+    picks = set()
+    for t in range(plum.n_tasks):
+        s, c = int(plum.i_begin[t]), int(plum.i_count[t])
+        assert c <= 64
+        pick = _two_fills_more(c)
+        picks.add(pick)
+        assert np.array_equal(auto[s:s + c], (two if pick else one)[s:s + c]), (t, c)
+    assert picks == {False, True}
     b.destroy()
     rig.close()
 
@@ -160,8 +188,9 @@ def test_two_targets_per_lane_edge_cases(ctx):
         b = rig.batch(whole(w))
         for order in (1, 2):
             ref = O.grav_workload(w, order=order)
-            acc = rig.run(b, gc.REORG_PACK, order=order, targets_per_lane=2)
-            assert rel_l2_per_task(acc, ref, whole(w)).max() <= TOL, (bucket, order)
+            for tpl in (2, 3):
+                acc = rig.run(b, gc.REORG_PACK, order=order, targets_per_lane=tpl)
+                assert rel_l2_per_task(acc, ref, whole(w)).max() <= TOL, (bucket, order, tpl)
         b.destroy()
         rig.close()
 
@@ -170,7 +199,7 @@ def test_targets_per_lane_is_validated(ctx, plum):
     rig = GravRig(ctx, plum)
     b = rig.batch(W.task_subset(plum, np.arange(10)))
     b.reorganize(rig.pool, gc.REORG_PACK)
-    for bad in (-1, 3):
+    for bad in (-1, 4):
         with pytest.raises(gc.GcError):
             b.launch(gc.grav_params(order=2, targets_per_lane=bad), rig.nodes, rig.acc)
     b.destroy()

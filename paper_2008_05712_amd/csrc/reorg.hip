@@ -32,7 +32,6 @@ namespace {
 using dev::block_excl_scan;
 using dev::iload;
 using dev::istore;
-using dev::kDone;
 using dev::kFBlock;
 using dev::kLookBack;
 using dev::kRThreads;
@@ -76,15 +75,42 @@ __global__ void __launch_bounds__(kRThreads) k_reorg(ReorgArgs a) {
     dev::union_ids(a, t - a.nbf, id);
     dev::union_role<false>(a, t - a.nbf, tag, sh, &s_ex, id);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // the last block out rewinds the counters and makes this call's tag the current one
-    if (atomicAdd(a.state + kDone, 1) == a.nbf + a.nbu - 1) {
-      istore(a.state + kTicket, 0);
-      istore(a.state + kDone, 0);
-      istore(a.state + kTag, (int32_t)tag);
+  // The block with the last ticket rewinds the ticket counter and makes this call's tag the current
+  // one: every block has taken its ticket, and has read the tag, since its look-back has seen a tagged
+  // word of every earlier union block, and (with free-slot blocks in the launch) the free count, which
+  // the last free-slot block writes after seeing one of every earlier free-slot block.
+  if (threadIdx.x == 0 && t == a.nbf + a.nbu - 1) {
+    if (a.nbf > 0) {
+      uint32_t spins = 0;
+      while ((uint32_t)(dev::tload(a.ftotal) >> 32) != tag) {
+        if (++spins > dev::kSpinLimit) {
+          istore(a.state + GC_STATE_ERR, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
     }
+    istore(a.state + kTicket, 0);
+    istore(a.state + kTag, (int32_t)tag);
   }
+}
+
+// The wide free-slot scan of a large pool, launched ahead of k_reorg (which then has no free-slot
+// blocks): blocks take tickets from their own counter; its look-back words follow the union blocks'.
+__global__ void __launch_bounds__(kRThreads) k_free_wide(ReorgArgs a, int32_t nb) {
+  __shared__ int sh[kRThreads / 64];
+  __shared__ int s_ticket;
+  __shared__ uint32_t s_tag, s_ex;
+  if (threadIdx.x == 0) {
+    s_ticket = atomicAdd(a.state + dev::kWTicket, 1);
+    s_tag = (uint32_t)iload(a.state + kTag) + 1u;
+  }
+  __syncthreads();
+  uint64_t* flags = reinterpret_cast<uint64_t*>(a.state + kLookBack) + a.nbu;
+  dev::free_role_wide(a, flags, s_ticket, nb, s_tag, sh, &s_ex);
+  // the block with the last ticket has seen a look-back word of every other block: all have taken
+  // their tickets
+  if (threadIdx.x == 0 && s_ticket == nb - 1) istore(a.state + dev::kWTicket, 0);
 }
 
 // Redundant transfers: every union record is gathered from the source, the pool is not used.
@@ -207,9 +233,19 @@ int free_blocks(int32_t cap) {
   return b > 0 ? (int)b : 1;
 }
 
+// Pools of at least this many narrow free-scan blocks are scanned by the wide form (k_free_wide) in a
+// launch of its own: a quarter of the blocks, each at the occupancy of a kernel without union code.
+constexpr int kWideFreeBlocks = 512;
+
+static int free_blocks_wide(int32_t cap) {
+  int64_t b = ((int64_t)cap + dev::kFWBlock - 1) / dev::kFWBlock;
+  return b > 0 ? (int)b : 1;
+}
+
 int64_t occ_words(int32_t cap) {
-  // one int per slot, padded so that every free-scan thread's 16-slot load stays inside the allocation
-  return (int64_t)free_blocks(cap) * kFBlock;
+  // one int per slot, padded so that every free-scan thread's load (16 slots, or 64 in the wide form)
+  // stays inside the allocation
+  return (int64_t)free_blocks_wide(cap) * dev::kFWBlock;
 }
 
 int32_t reorg_state_ints(int32_t u, int32_t cap) { return kLookBack + 2 * (union_blocks(u) + free_blocks(cap)); }
@@ -237,6 +273,12 @@ hipError_t launch_reorg(ReorgArgs a, hipStream_t s) {
   a.nbf = free_blocks(a.cap);
   a.ftotal = reinterpret_cast<uint64_t*>(a.state + dev::kFreeTotal);
   a.flimit = a.u;
+  if (a.nbf >= kWideFreeBlocks) {
+    // large pool: the free-slot list first, in its own launch; k_reorg then runs union blocks only
+    const int32_t nbw = free_blocks_wide(a.cap);
+    hipLaunchKernelGGL(k_free_wide, dim3(nbw), dim3(kRThreads), 0, s, a, nbw);
+    a.nbf = 0;
+  }
   hipLaunchKernelGGL(k_reorg, dim3(a.nbu + a.nbf), dim3(kRThreads), 0, s, a);
   return hipGetLastError();
 }

@@ -27,10 +27,15 @@ constexpr int kUItems = GC_UITEMS;                  // union entries per thread 
 constexpr int kUBlock = kRThreads * kUItems;        // union entries per block
 constexpr int kFItems = 16;                         // occupancy entries per thread
 constexpr int kFBlock = kRThreads * kFItems;        // pool slots per free-scan block
+constexpr int kFWItems = 64;                        // occupancy entries per thread, wide free scan
+constexpr int kFWBlock = kRThreads * kFWItems;      // pool slots per wide free-scan block
 constexpr uint32_t kSpinLimit = 1u << 22;           // bound on every wait: each wave exits
 
-// state[] layout (int32 units); see gc_internal.h for the host-visible part
-constexpr int kTicket = 8, kDone = 9, kTag = 10, kFreeTotal = 12, kLookBack = 16;
+// state[] layout (int32 units): the host-visible words (gc_internal.h), the call tag and the free
+// count on the first 128-byte line; each ticket counter on a line of its own (every block of a call
+// adds to its counter, and atomics on one line are serialised where they are performed); the
+// look-back words from the fourth line on.
+constexpr int kTag = 10, kFreeTotal = 12, kTicket = 32, kWTicket = 64, kLookBack = 96;
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -175,6 +180,48 @@ __device__ __forceinline__ void free_role(const ReorgArgs& a, int b, uint32_t ta
       if (r < a.flimit) tstore(a.free_list + r, tword(ltag, 0, (uint32_t)(s0 + k)));
       ++r;
     }
+}
+
+// Wide form of the free-slot side, for large pools, in a launch of its own ahead of the union side:
+// 64 slots a thread, so a quarter of the blocks (each a chain step of the look-back) and no union
+// code's registers.  flags: this launch's look-back words (nb of them).  The list and its count are
+// the same as the narrow form's.
+__device__ __forceinline__ void free_role_wide(const ReorgArgs& a, uint64_t* flags, int b, int nb, uint32_t tag,
+                                               int* sh, uint32_t* s_ex) {
+  const int64_t s0 = (int64_t)b * kFWBlock + (int64_t)threadIdx.x * kFWItems;
+  uint64_t f = 0;
+  if (s0 < a.cap) {
+    const int4* o4 = reinterpret_cast<const int4*>(a.occ + s0);  // occ is padded to whole wide blocks
+#pragma unroll
+    for (int q = 0; q < kFWItems / 4; ++q) {
+      const int4 o = gld(o4 + q);
+      const uint32_t ov[4] = {(uint32_t)o.x, (uint32_t)o.y, (uint32_t)o.z, (uint32_t)o.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (ov[k] == 0u && s0 + 4 * q + k < a.cap) f |= 1ull << (4 * q + k);
+    }
+  }
+  int tot;
+  int r = block_excl_scan(__popcll(f), sh, &tot);
+  if (threadIdx.x < 64) {
+    const uint32_t ex = look_back(flags, b, tag, (uint32_t)tot, a.state + GC_STATE_ERR);
+    if (threadIdx.x == 0) {
+      *s_ex = ex;
+      if (b == nb - 1) {
+        tstore(a.ftotal, tword(tag, 0, ex + (uint32_t)tot));
+        istore(a.state + GC_STATE_FREE, (int32_t)(ex + (uint32_t)tot));
+      }
+    }
+  }
+  __syncthreads();
+  r += (int)*s_ex;
+  // only the first flimit free slots are listed (no request takes more)
+  while (f && r < a.flimit) {
+    const int k = __builtin_ctzll(f);
+    f &= f - 1;
+    tstore(a.free_list + r, tword(tag, 0, (uint32_t)(s0 + k)));
+    ++r;
+  }
 }
 
 // Union side: residency of this block's chunk of U, the missing ranks, then slot assignment,

@@ -115,6 +115,8 @@ struct ReorgArgs {
   int32_t* state;
   int32_t nbf, nbu;        // set by the launcher
   int32_t evict_after;     // whole-step kernel: a union block evicts what it stages at once
+  int32_t list_ready;      // the free-slot list and count were completed by an earlier launch (plain
+                           // loads, no waits)
 };
 
 // occupancy entries (one per slot, padded) allocated for a pool of `cap` slots

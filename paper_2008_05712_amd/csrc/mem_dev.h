@@ -47,6 +47,8 @@ __device__ __forceinline__ void gst(float4* p, const float4 v) {
   const gc_vf4 w = {v.x, v.y, v.z, v.w};
   *(GC_GLOBAL(gc_vf4)*)p = w;
 }
+__device__ __forceinline__ uint64_t gld(const uint64_t* p) { return *(const GC_GLOBAL(uint64_t)*)p; }
+__device__ __forceinline__ void gst(uint64_t* p, uint64_t v) { *(GC_GLOBAL(uint64_t)*)p = v; }
 __device__ __forceinline__ void gst(int32_t* p, int32_t v) { *(GC_GLOBAL(int32_t)*)p = v; }
 __device__ __forceinline__ void gst(uint32_t* p, uint32_t v) { *(GC_GLOBAL(uint32_t)*)p = v; }
 

@@ -278,6 +278,7 @@ hipError_t launch_reorg(ReorgArgs a, hipStream_t s) {
     const int32_t nbw = free_blocks_wide(a.cap);
     hipLaunchKernelGGL(k_free_wide, dim3(nbw), dim3(kRThreads), 0, s, a, nbw);
     a.nbf = 0;
+    a.list_ready = 1;
   }
   hipLaunchKernelGGL(k_reorg, dim3(a.nbu + a.nbf), dim3(kRThreads), 0, s, a);
   return hipGetLastError();

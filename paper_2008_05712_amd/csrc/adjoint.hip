@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
   const int ibase = PACKED ? a.ibeg[t] : tk.i_begin;
   const float G = a.G, eps2 = a.eps2;
   for (int tb0 = 0; tb0 < ic; tb0 += kTB) {
-    const int tb = ic - tb0 < kTB ? ic - tb0 : kTB;
+    const int tb = uniform(ic - tb0 < kTB ? ic - tb0 : kTB);
     if (lane < kTB) {
       float4 p = make_float4(0.f, 0.f, 0.f, 0.f), g = p;
       if (lane < tb) {
@@ -134,6 +134,7 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
       float hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;  // sym(dL/dS) / G
 #pragma unroll
       for (int k = 0; k < kTB; ++k) {
+        if (k >= tb) break;  // (uniform) targets past the block's last do no work
         float dx = xt[k] - c.x, dy = yt[k] - c.y, dz = zt[k] - c.z;
         float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
         float ri = __builtin_amdgcn_rsqf(r2);
@@ -230,6 +231,7 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
         float gsx = 0.f, gsy = 0.f, gsz = 0.f, gms = 0.f;
 #pragma unroll
         for (int k = 0; k < kTB; ++k) {
+          if (k >= tb) break;  // (uniform) targets past the block's last do no work
           float ux = s.x - xt[k], uy = s.y - yt[k], uz = s.z - zt[k];
           float s2 = __builtin_fmaf(uz, uz, __builtin_fmaf(uy, uy, __builtin_fmaf(ux, ux, eps2)));
           float ri = __builtin_amdgcn_rsqf(s2);

@@ -423,7 +423,9 @@ typedef struct {
                                they agree to rounding; each gives the same bits on
                                every launch, schedule and aggregation */
   int32_t n_nodes;          /* gravity: node records in nodes_dev; every node index the
-                               batch holds must be below it (GC_E_INVAL otherwise) */
+                               batch holds must be below it (GC_E_INVAL otherwise);
+                               at most 2^24 nodes, and fewer than 2^28 direct records
+                               per task (GC_E_UNSUPPORTED otherwise) */
   int32_t want_potential;   /* gravity, 1: also write in acc.w the potential of the
                                target's terms, phi_i = -G [sum over its direct sources
                                j != i of m_j / (|x_j - x_i|^2 + eps^2)^{1/2} + sum over

@@ -242,7 +242,8 @@ __device__ __forceinline__ float4 u4f(const __attribute__((ext_vector_type(4))) 
 template <int ORDER>
 __device__ __forceinline__ NodeRegs<ORDER> load_node(__amdgpu_buffer_rsrc_t nodes, int idx) {
   NodeRegs<ORDER> r;
-  const int off = idx >= 0 ? idx * 48 : 0x7ffffff0;  // past the end of any node table
+  // (node indices are below 2^24, checked on the host: a full-rate 24-bit multiply)
+  const int off = idx >= 0 ? (int)__umul24((unsigned)idx, 48u) : 0x7ffffff0;  // past the end of any node table
   r.v0 = u4f(__builtin_amdgcn_raw_buffer_load_b128(nodes, off, 0, 0));
   if (ORDER == 2) {
     r.v1 = u4f(__builtin_amdgcn_raw_buffer_load_b128(nodes, off + 16, 0, 0));
@@ -282,8 +283,9 @@ __device__ __forceinline__ void node_prefetch(__amdgpu_buffer_rsrc_t nodes, cons
   const int W = blockDim.x >> 6;
   const int nw = n_count > wid ? (n_count - wid + W - 1) / W : 0;
   const int* nl = node_idx + n_first + wid;
-  pf.idx_next = (64 < nw && 64 + lane < nw) ? gld(nl + (64 + lane) * W) : -1;
-  pf.cur = load_node<ORDER>(nodes, lane < nw ? gld(nl + lane * W) : -1);
+  const int lw = lane * W;
+  pf.idx_next = (64 < nw && 64 + lane < nw) ? gld(nl + (lw + 64 * W)) : -1;
+  pf.cur = load_node<ORDER>(nodes, lane < nw ? gld(nl + lw) : -1);
 }
 
 // Records of LDS per wavefront for a direct tile of `tile` records: the larger of a direct tile and
@@ -352,6 +354,7 @@ __device__ __forceinline__ void grav_task_body(const GravArgs& a, const int t, c
   // this wave's nodes; the first tile does not depend on the records, so its loads go out first
   const int nw = tk.n_count > wid ? (tk.n_count - wid + W - 1) / W : 0;
   const int* nl = a.node_idx + tk.n_first + wid;
+  const int lw = lane * W;  // nl[lw + e * W] is this lane's entry e + lane
   const __amdgpu_buffer_rsrc_t nodes = node_rsrc(a.nodes, a.n_nodes);
   if (!have_pf) node_prefetch<ORDER>(nodes, a.node_idx, tk.n_first, tk.n_count, pf);
   ready();
@@ -361,13 +364,17 @@ __device__ __forceinline__ void grav_task_body(const GravArgs& a, const int t, c
     const int icc = ic - i0 < 64 ? ic - i0 : 64;
     constexpr bool two = TPL == 2;
     const int h = two ? (icc + 1) >> 1 : icc;
-    const int S = 64 / h;
-    const int il = lane % h;
-    const int sl = lane / h;
+    const int S = uniform(64 / h);
+    // lane / h and lane % h by a multiply: floor(lane * ceil(2^16 / h) / 2^16) = floor(lane / h) for
+    // lane < 64 and h <= 64 (the rounding error stays below 1 / h)
+    const uint32_t mh = (uint32_t)uniform((65536 + h - 1) / h);
+    const int sl = (int)(((uint32_t)lane * mh) >> 16);
+    const int il = lane - sl * h;
+    const int sl3 = 3 * sl;
     const bool active = sl < S;
     // tiles hold a multiple of S records, so that only a share's last tile is padded
-    const int NT = S * (kNodeTile / S);  // nodes per node tile
-    const int DT = S * (tile / S);       // records per direct tile
+    const int NT = uniform(S * (kNodeTile / S));  // nodes per node tile
+    const int DT = uniform(S * (tile / S));       // records per direct tile
     const int ib = il + h < icc ? il + h : il;  // two: second target (a copy of the first if absent)
     float3 A = make_float3(0.f, 0.f, 0.f), B = A;
     if (active) {
@@ -385,19 +392,19 @@ __device__ __forceinline__ void grav_task_body(const GravArgs& a, const int t, c
       if (!active) return;
       if (two) {
         Acc2 r{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (quads) tile_quads2(L + 3 * sl * C, C, A, B, a.eps2, r);
-        else tile_pairs2(L + sl * C, C, A, B, a.eps2, r);
+        if (quads) tile_quads2(L + __mul24(sl3, C), C, A, B, a.eps2, r);
+        else tile_pairs2(L + __mul24(sl, C), C, A, B, a.eps2, r);
         Ax += r.ax; Ay += r.ay; Az += r.az;
         Bx += r.bx; By += r.by; Bz += r.bz;
       } else if (POT) {
         float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-        if (quads) tile_quads_pot(L + 3 * sl * C, C, A.x, A.y, A.z, a.eps2, ax, ay, az, ph);
-        else tile_pairs_pot(L + sl * C, C, A.x, A.y, A.z, a.eps2, ax, ay, az, ph);
+        if (quads) tile_quads_pot(L + __mul24(sl3, C), C, A.x, A.y, A.z, a.eps2, ax, ay, az, ph);
+        else tile_pairs_pot(L + __mul24(sl, C), C, A.x, A.y, A.z, a.eps2, ax, ay, az, ph);
         Ax += ax; Ay += ay; Az += az; Ap += ph;
       } else {
         float ax = 0.f, ay = 0.f, az = 0.f;
-        if (quads) tile_quads(L + 3 * sl * C, C, A.x, A.y, A.z, a.eps2, ax, ay, az);
-        else tile_pairs(L + sl * C, C, A.x, A.y, A.z, a.eps2, ax, ay, az);
+        if (quads) tile_quads(L + __mul24(sl3, C), C, A.x, A.y, A.z, a.eps2, ax, ay, az);
+        else tile_pairs(L + __mul24(sl, C), C, A.x, A.y, A.z, a.eps2, ax, ay, az);
         Ax += ax; Ay += ay; Az += az;
       }
     };
@@ -408,18 +415,18 @@ __device__ __forceinline__ void grav_task_body(const GravArgs& a, const int t, c
       // its lanes >= NT are left out (zero records) and the next tile starts at node NT.  Every
       // tile's lanes past its last node then hold zero records: the padding of the tile
       if (NT < kNodeTile) {
-        pf.idx_next = (lane < NT && NT + lane < nw) ? gld(nl + (NT + lane) * W) : -1;
+        pf.idx_next = (lane < NT && NT + lane < nw) ? gld(nl + (lw + NT * W)) : -1;
         if (lane >= NT) pf.cur = load_node<ORDER>(nodes, -1);
       }
       for (int nb = 0; nb < nw; nb += NT) {
         const int cnt = nw - nb < NT ? nw - nb : NT;
-        const int C = (cnt + S - 1) / S;
+        const int C = uniform((cnt + S - 1) / S);
         store_node<ORDER>(L, lane, pf.cur);
         // prefetch the next tile's records and the index of the one after
         if (nb + NT < nw) {
           pf.cur = load_node<ORDER>(nodes, pf.idx_next);
           const int e2 = nb + 2 * NT + lane;
-          pf.idx_next = (lane < NT && e2 < nw) ? gld(nl + e2 * W) : -1;
+          pf.idx_next = (lane < NT && e2 < nw) ? gld(nl + (lw + (nb + 2 * NT) * W)) : -1;
         }
         wave_sync();
         // monopole: a = -M d / r^3 with d = x_i - com, the same as a pair term from a source at com
@@ -433,7 +440,7 @@ __device__ __forceinline__ void grav_task_body(const GravArgs& a, const int t, c
       const int jb = gld(a.joff + t), jn = gld(a.joff + t + 1) - jb;
       for (int ws = wid * DT; ws < jn; ws += W * DT) {
         const int cnt = jn - ws < DT ? jn - ws : DT;
-        const int C = (cnt + S - 1) / S;
+        const int C = uniform((cnt + S - 1) / S);
         const int padded = S * C;
         for (int e = lane; e < padded; e += 64) {
           float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -460,11 +467,13 @@ __device__ __forceinline__ void grav_task_body(const GravArgs& a, const int t, c
         RB[lane] = g.x;
         wave_sync();
         // share boundaries rounded down to multiples of S (the last share ends at the total)
-        const int lo = (int)((int64_t)total * wid / W / S) * S;
-        const int hi = wid + 1 == W ? total : (int)((int64_t)total * (wid + 1) / W / S) * S;
+        // (32-bit: a task's direct records stay below 2^28)
+        const int lo = uniform((int)((uint32_t)total * (uint32_t)wid / (uint32_t)W / (uint32_t)S) * S);
+        const int hi = wid + 1 == W ? total
+                                    : uniform((int)((uint32_t)total * (uint32_t)(wid + 1) / (uint32_t)W / (uint32_t)S) * S);
         for (int ws = lo; ws < hi; ws += DT) {
           const int cnt = hi - ws < DT ? hi - ws : DT;
-          const int C = (cnt + S - 1) / S;
+          const int C = uniform((cnt + S - 1) / S);
           const int padded = S * C;
           for (int e = lane; e < padded; e += 64) {
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -1468,6 +1468,12 @@ static gc_status check_prm(gc_batch b, const gc_force_params* prm, int* tile, in
     return set_err(c, GC_E_INVAL, "targets_per_lane must be 0, 1, 2 or 3");
   if (b->kind == GC_KIND_GRAV && b->max_node >= prm->n_nodes)
     return set_err(c, GC_E_INVAL, "node index %d is not below n_nodes %d of the node table", b->max_node, prm->n_nodes);
+  // the force code forms node offsets with 24-bit multiplies and splits a task's direct records in
+  // 32-bit arithmetic
+  if (b->kind == GC_KIND_GRAV && prm->n_nodes > (1 << 24))
+    return set_err(c, GC_E_UNSUPPORTED, "node tables of more than 2^24 nodes are not supported (got %d)", prm->n_nodes);
+  if (b->kind == GC_KIND_GRAV && b->max_direct >= (1 << 28))
+    return set_err(c, GC_E_UNSUPPORTED, "a task with 2^28 or more direct records is not supported");
   if (prm->want_potential != 0 && prm->want_potential != 1) return set_err(c, GC_E_INVAL, "want_potential must be 0 or 1");
   if (prm->deterministic != 0 && prm->deterministic != 1) return set_err(c, GC_E_INVAL, "deterministic must be 0 or 1");
   if (prm->aggregation < 0) return set_err(c, GC_E_INVAL, "aggregation must be >= 0");

@@ -200,6 +200,10 @@ struct gc_pool_ {
 
 struct gc_batch_ {
   gc_ctx ctx = nullptr;
+  // host-side: the batch's last reorganisation may have left staged records in its pool (cleared by
+  // gc_pool_evict_staged and by a whole-step or rounds launch under the evicting fixture, which
+  // stages nothing that outlives its round)
+  bool staged_live = false;
   int32_t kind = GC_KIND_GRAV;
   int32_t n_ids = 0;
   std::vector<gc_task> tasks;
@@ -261,6 +265,13 @@ struct gc_graph_ {
   std::vector<gc_pool> pools;      // pools the graph changes (their host mirrors go stale at each launch)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // whole-step / rounds schedule under the evicting fixture: the same graph without the kernel that
+  // evicts what the last batch left staged, launched when the host knows nothing is staged
+  hipGraph_t graph_noevict = nullptr;
+  hipGraphExec_t exec_noevict = nullptr;
+  std::vector<gc_batch> batches;  // the captured batches (staging bookkeeping)
+  int32_t fixture = GC_FIXTURE_NONE;
+  bool step_form = false;
   DevBuf step_items, step_rounds, step_ctr, step_fl;  // whole-step persistent schedule
   DevBuf round_items, round_args;  // rounds schedule: the combined pass's items and per-round arguments
   std::vector<hipStream_t> side;   // capture-time side streams (combined passes of successive steps overlap)
@@ -1233,6 +1244,7 @@ static gc_status reorganize_async(gc_batch b, gc_pool p, int32_t mode, hipStream
     }
   }
   b->rec = (mode == GC_REORG_PACK || mode == GC_REORG_REDUNDANT) ? b->packed.as<float4>() : p->rec.as<float4>();
+  b->staged_live = mode != GC_REORG_REDUNDANT;  // (REDUNDANT stages nothing into the pool)
   return GC_OK;
 }
 
@@ -1393,7 +1405,9 @@ extern "C" gc_status gc_pool_evict_staged(gc_pool pool, gc_batch b, void* stream
   GC_ENTER(pool->ctx);
   if (b->mode < 0 || !b->pool) return GC_OK;  // nothing staged yet
   if (b->pool != pool) return set_err(pool->ctx, GC_E_STATE, "gc_pool_evict_staged: batch last reorganised against another pool");
-  return evict_staged_async(pool, b, S(stream));
+  gc_status st = evict_staged_async(pool, b, S(stream));
+  if (st == GC_OK) b->staged_live = false;
+  return st;
 }
 
 extern "C" gc_status gc_batch_maps(gc_batch b, int64_t* counts, int32_t* U, int32_t* pos, int32_t* missing,
@@ -2035,28 +2049,33 @@ static gc_status capture_step(gc_ctx ctx, int32_t R, gc_batch* batches, gc_pool*
   a.fail_round = ctx->step_fail_round < R ? ctx->step_fail_round : -1;
   a.fail_spins = ctx->step_fail_spins ? ctx->step_fail_spins : kStepSpinLimit;
   a.has_force = combined_pass ? 0 : 1;
-  hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-  if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamBeginCapture");
-  hipError_t le = hipSuccess;
-  if (fixture == GC_FIXTURE_EVICT_STAGED) {
-    const gc_batch pb = batches[R - 1];
-    le = launch_evict(pb->missing.as<int32_t>(), pb->state.as<int32_t>() + GC_STATE_MISSING, std::max<int32_t>(pb->u, 1),
-                      p->slot_of.as<int32_t>(), p->n_ids, p->occ.as<uint32_t>(), s);
+  // with the evicting fixture two graphs: one that first evicts what the last batch left staged,
+  // one without that kernel (nothing staged: the host knows, gc_graph_launch picks)
+  for (int v = 0; v < (fixture == GC_FIXTURE_EVICT_STAGED ? 2 : 1); ++v) {
+    hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (ce != hipSuccess) return hip_fail(ctx, ce, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    if (fixture == GC_FIXTURE_EVICT_STAGED && v == 0) {
+      const gc_batch pb = batches[R - 1];
+      le = launch_evict(pb->missing.as<int32_t>(), pb->state.as<int32_t>() + GC_STATE_MISSING, std::max<int32_t>(pb->u, 1),
+                        p->slot_of.as<int32_t>(), p->n_ids, p->occ.as<uint32_t>(), s);
+    }
+    if (le == hipSuccess)
+      le = combined_pass ? launch_step_reorg(a, grid, s) : launch_step(order, tpl, a, grid, tile, s);
+    if (le == hipSuccess && combined_pass)
+      le = launch_grav_rounds(order, tpl, gr->round_items.as<StepItem>(), (int32_t)fitems.size(),
+                              gr->round_args.as<GravArgs>(), tile, wpb, s);
+    hipGraph_t g = nullptr;
+    ce = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(ctx, le != hipSuccess ? le : ce, "whole-step capture");
+    }
+    (v == 0 ? gr->graph : gr->graph_noevict) = g;
+    ce = hipGraphInstantiate(v == 0 ? &gr->exec : &gr->exec_noevict, g, nullptr, nullptr, 0);
+    if (ce != hipSuccess) return hip_fail(ctx, ce, "hipGraphInstantiate");
   }
-  if (le == hipSuccess)
-    le = combined_pass ? launch_step_reorg(a, grid, s) : launch_step(order, tpl, a, grid, tile, s);
-  if (le == hipSuccess && combined_pass)
-    le = launch_grav_rounds(order, tpl, gr->round_items.as<StepItem>(), (int32_t)fitems.size(),
-                            gr->round_args.as<GravArgs>(), tile, wpb, s);
-  hipGraph_t g = nullptr;
-  ce = hipStreamEndCapture(s, &g);
-  if (le != hipSuccess || ce != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return hip_fail(ctx, le != hipSuccess ? le : ce, "whole-step capture");
-  }
-  gr->graph = g;
-  ce = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
-  if (ce != hipSuccess) return hip_fail(ctx, ce, "hipGraphInstantiate");
+  gr->step_form = true;
   for (int32_t k = 0; k < R; ++k) {
     batches[k]->mode = GC_REORG_PACK;
     batches[k]->pool = p;
@@ -2115,12 +2134,16 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
     gc_graph gs = new gc_graph_();
     gs->ctx = ctx;
     gs->pools.assign(pools, pools + n_steps);
+    gs->batches.assign(batches, batches + n_steps);
+    gs->fixture = fixture;
     for (DevBuf* d : gs->bufs()) d->h = &ctx->hooks;
     gc_status st = capture_step(ctx, n_steps, batches, pools, modes, prm, nodes_dev, acc_dev, fixture, s, gs,
                                 prm->schedule == GC_SCHED_ROUNDS);
     if (st != GC_OK) {
       if (gs->exec) (void)hipGraphExecDestroy(gs->exec);
       if (gs->graph) (void)hipGraphDestroy(gs->graph);
+      if (gs->exec_noevict) (void)hipGraphExecDestroy(gs->exec_noevict);
+      if (gs->graph_noevict) (void)hipGraphDestroy(gs->graph_noevict);
       gs->step_items.release();
       gs->step_rounds.release();
       gs->step_ctr.release();
@@ -2130,6 +2153,8 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
       delete gs;
       return st;
     }
+    // the cleared states hold no missing list: nothing a replay could evict is staged
+    for (int32_t k = 0; k < n_steps; ++k) batches[k]->staged_live = false;
     *out = gs;
     return GC_OK;
   }
@@ -2145,6 +2170,8 @@ extern "C" gc_status gc_graph_capture(gc_ctx ctx, int32_t n_steps, gc_batch* bat
   gc_graph gr = new gc_graph_();
   gr->ctx = ctx;
   gr->pools.assign(pools, pools + n_steps);
+  gr->batches.assign(batches, batches + n_steps);
+  gr->fixture = fixture;
   for (DevBuf* d : gr->bufs()) d->h = &ctx->hooks;
   auto cleanup = [&]() {
     for (hipEvent_t e : gr->events) (void)hipEventDestroy(e);
@@ -2261,7 +2288,16 @@ extern "C" gc_status gc_graph_launch(gc_graph g, void* stream) {
   if (!g) return GC_E_INVAL;
   GC_ENTER(g->ctx);
   for (gc_pool p : g->pools) p->mirror_ok = false;
+  if (g->step_form && g->fixture == GC_FIXTURE_EVICT_STAGED) {
+    // the eviction kernel only removes what the last batch left staged: skipped when it left nothing
+    const bool evict = g->batches.back()->staged_live || !g->exec_noevict;
+    GC_HIP(g->ctx, hipGraphLaunch(evict ? g->exec : g->exec_noevict, S(stream)));
+    for (gc_batch b : g->batches) b->staged_live = false;  // each round's staging is evicted in it
+    return GC_OK;
+  }
   GC_HIP(g->ctx, hipGraphLaunch(g->exec, S(stream)));
+  // other graphs may leave their batches' staging in the pools
+  for (gc_batch b : g->batches) b->staged_live = true;
   return GC_OK;
 }
 
@@ -2279,6 +2315,8 @@ extern "C" gc_status gc_graph_destroy(gc_graph g) {
   if (!g) return GC_E_INVAL;
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->exec_noevict) (void)hipGraphExecDestroy(g->exec_noevict);
+  if (g->graph_noevict) (void)hipGraphDestroy(g->graph_noevict);
   for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
   for (hipStream_t q : g->side) (void)hipStreamDestroy(q);
   g->step_items.release();

@@ -206,6 +206,27 @@ def test_targets_per_lane_is_validated(ctx, plum):
     rig.close()
 
 
+def test_node_table_and_direct_limits_are_refused(ctx, plum):
+    # a node table of more than 2^24 nodes is refused before anything is launched (the count is
+    # forged: the check needs no table of that size) and the batch stays usable
+    import ctypes
+    rig = GravRig(ctx, plum)
+    b = rig.batch(W.task_subset(plum, np.arange(10)))
+    b.reorganize(rig.pool, gc.REORG_PACK)
+    p = gc.with_nodes(gc.grav_params(order=2), rig.nodes)
+    p.n_nodes = (1 << 24) + 1
+    rc = gc.lib().gc_launch_combined(b.h, ctypes.byref(p), gc._ptr(rig.nodes), gc._ptr(rig.acc), None)
+    assert rc == gc.GC_E_UNSUPPORTED
+    rig.acc.fill_(np.nan)
+    b.launch(gc.grav_params(order=2), rig.nodes, rig.acc)
+    import torch
+    torch.cuda.synchronize()
+    bt = W.task_subset(plum, np.arange(10))
+    assert rel_l2_per_task(rig.acc.cpu().numpy(), O.grav_workload(plum, order=2, tasks=bt), bt).max() <= TOL
+    b.destroy()
+    rig.close()
+
+
 def test_task_order_does_not_change_results(ctx, plum):
     rig = GravRig(ctx, plum)
     t = whole(plum)
@@ -915,6 +936,44 @@ def test_rounds_schedule_full_size(ctx, tile, tpl, waves):
     sub = W.task_subset(w, np.sort(sel))
     err = rel_l2_per_task(got, O.grav_workload(w, order=2, tasks=sub), sub)
     assert err.max() <= TOL, err.max()
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()
+
+
+@pytest.mark.parametrize("schedule", [gc.SCHED_STEP, gc.SCHED_ROUNDS])
+def test_step_forms_evict_staging_left_between_launches(ctx, plum, schedule):
+    # under the evicting fixture a launch first evicts what the last batch left staged, and skips that
+    # kernel when the host knows nothing is staged: a launch after an eager reorganisation of the last
+    # batch (which stages its missing records) gives the same bits and leaves the base residency
+    import torch
+    rig, bts, bs, base = _rounds_rig(ctx, plum, 4, 500, 58, 0.4, 59)
+    _set_base(rig, base)
+    base_so = rig.pool.query()
+    s = torch.cuda.Stream()
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs),
+                 gc.grav_params(order=2, schedule=schedule), rig.nodes, rig.acc, stream=s,
+                 fixture=gc.FIXTURE_EVICT_STAGED)
+    outs = []
+    for rep in range(3):
+        if rep == 1:
+            # the last batch staged against the pool between launches
+            bs[-1].reorganize(rig.pool, gc.REORG_PACK, stream=s)
+            s.synchronize()
+            assert not np.array_equal(rig.pool.query(), base_so)
+        rig.acc.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        outs.append(rig.acc.cpu().numpy())
+        assert np.array_equal(rig.pool.query(), base_so), rep
+    for o in outs[1:]:
+        assert np.array_equal(np.isnan(o), np.isnan(outs[0]))
+        assert np.array_equal(o[~np.isnan(o)], outs[0][~np.isnan(outs[0])])
+    for bt in bts:
+        assert rel_l2_per_task(outs[0], O.grav_workload(plum, order=2, tasks=bt), bt).max() <= TOL
+    g.status(stream=s)
     g.destroy()
     for b in bs:
         b.destroy()

@@ -3,8 +3,8 @@
 Workload (the irregular N-body configuration with reuse): 262,144 particles from
 a Plummer sphere (scale radius 1, cut at 10), FP32 records, octree buckets of
 32, Barnes-Hut theta = 0.7 with monopole + quadrupole nodes, Plummer softening
-0.01.  The 27k bucket tasks arrive in rounds of Poisson(2048) consecutive
-buckets.  Half of all particles are resident at uniformly random pool slots
+0.01.  The 27k bucket tasks arrive in 32 rounds of Poisson(2048) consecutive
+buckets (tree order, wrapping: about 2.4 passes over the buckets).  Half of all particles are resident at uniformly random pool slots
 (the base residency); each round finds about half of its particle union
 resident and the reorganisation stages the rest from the particle array in
 HBM; the next round first evicts what this one staged, so the base holds.
@@ -649,6 +649,7 @@ def main():
     ap.add_argument("--cpu-sample-rounds", type=int, default=1000, help="rounds of the step timed on the CPU")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="about how long the CPU baseline repeats its sample")
     ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--rounds", type=int, default=32, help="Poisson(2048) rounds per step (wrapping the tree order)")
     ap.add_argument("--quick", action="store_true",
                     help="skip the mode comparison, the single-launch measurement and the batched, LJ and adjoint legs")
     ap.add_argument("--tile", type=int, default=0, help="fixed force-kernel shape instead of the autotuner's")
@@ -686,11 +687,21 @@ def main():
         return
     t0 = time.time()
     w = W.nbody_plummer(n=args.n, seed=1002)
-    rounds = W.poisson_rounds(w.n_tasks, 2048, seed=1002)
+    # the step: args.rounds Poisson(2048) rounds of consecutive buckets, wrapping around the tree order
+    # (32: about 2.4 passes over the buckets); the host-source and list-rebuild legs take one pass
+    rounds = W.poisson_rounds(w.n_tasks, 2048, seed=1002, n_rounds=args.rounds)
+    rounds_pass = W.poisson_rounds(w.n_tasks, 2048, seed=1002)
     log(f"[bench] workload N={w.n} tasks={w.n_tasks} rounds={len(rounds)} build {time.time() - t0:.1f}s")
-    n_direct, n_node = w.split_interactions()
+    # interactions of the step (a task in several rounds counts once per round) and of one pass
+    ic_all = w.i_count.astype(np.int64)
+    dir_t = ic_all * (w.direct_counts().astype(np.int64) - 1)
+    node_t = ic_all * w.n_count.astype(np.int64)
+    step_tasks = np.concatenate(rounds)
+    n_direct, n_node = int(dir_t[step_tasks].sum()), int(node_t[step_tasks].sum())
     interactions = n_direct + n_node
     flops_step = n_direct * FLOPS_PAIR + n_node * FLOPS_QUAD
+    interactions_all = int(dir_t.sum() + node_t.sum())
+    flops_all = int(dir_t.sum()) * FLOPS_PAIR + int(node_t.sum()) * FLOPS_QUAD
 
     ctx = gc.Context(0)
     dev = torch.device("cuda")
@@ -715,8 +726,8 @@ def main():
         return
     if args.leg in ("staging", "rebuild"):
         p2 = gc.grav_params(order=2, G=1.0, eps=0.01, tile=320, targets_per_lane=2)
-        out = leg_staging(gc, W, torch, ctx, w, rounds, p2, nodes) if args.leg == "staging" else \
-            leg_rebuild(gc, W, torch, ctx, w, rounds, p2)
+        out = leg_staging(gc, W, torch, ctx, w, rounds_pass, p2, nodes) if args.leg == "staging" else \
+            leg_rebuild(gc, W, torch, ctx, w, rounds_pass, p2)
         print(json.dumps({"leg": args.leg, **out}), flush=True)
         ctx.close()
         return
@@ -969,8 +980,8 @@ def main():
         pall = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=ball.schedule, tile=ball.tile,
                               waves_per_block=ball.waves_per_block, targets_per_lane=ball.targets_per_lane)
         ms_all = time_kernel(lambda: allb.launch(pall, nodes, acc), stream)
-        combined_all = {"ms": round(ms_all, 4), "tflops": round(flops_step / (ms_all * 1e-3) / 1e12, 3),
-                        "ginteractions_per_s": round(interactions / (ms_all * 1e-3) / 1e9, 3),
+        combined_all = {"ms": round(ms_all, 4), "tflops": round(flops_all / (ms_all * 1e-3) / 1e12, 3),
+                        "ginteractions_per_s": round(interactions_all / (ms_all * 1e-3) / 1e9, 3),
                         "shape": dict(tile=ball.tile, waves_per_block=ball.waves_per_block, schedule=ball.schedule,
                                       targets_per_lane=ball.targets_per_lane),
                         "shape_ms": {f"t{t}_w{wv}_s{sc}_p{tp}": round(float(tall[i]), 4) for i, (t, wv, sc, tp) in
@@ -987,8 +998,8 @@ def main():
         extra["ewald"] = leg_ewald(gc, W, torch, ctx)
         extra["adjoint"] = leg_adjoint(gc, W, torch, ctx)
         extra["tree_walk"] = leg_walk(gc, W, torch, ctx, w)
-        extra["rebuild"] = leg_rebuild(gc, W, torch, ctx, w, rounds, prm)
-        extra["staging"] = leg_staging(gc, W, torch, ctx, w, rounds, prm, nodes)
+        extra["rebuild"] = leg_rebuild(gc, W, torch, ctx, w, rounds_pass, prm)
+        extra["staging"] = leg_staging(gc, W, torch, ctx, w, rounds_pass, prm, nodes)
         extra["reorg_stress"] = leg_reorg_stress(gc, torch, ctx)
 
     form_text = {"step": "one whole-step persistent launch (HIP graph) per step",
@@ -1045,9 +1056,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"nbody-plummer-{w.n}: bucket 32, theta 0.7, monopole+quadrupole, eps 0.01, "
-                               f"{R} Poisson(2048) rounds, half of all particles resident at random slots "
-                               f"(each round evicts the previous round's staging), {args.mode} reorganisation, "
-                               f"{form_text}",
+                               f"{R} Poisson(2048) rounds of consecutive buckets (wrapping the tree order), "
+                               f"half of all particles resident at random slots "
+                               f"(each round evicts the previous round's staging), the missing records staged "
+                               f"from a copy of every record in HBM (host-source rates: forms and staging), "
+                               f"{args.mode} reorganisation, {form_text}",
                    "n": w.n, "tasks": w.n_tasks, "rounds": R, "interactions_per_step": interactions,
                    "mode": args.mode, "form": form},
         "roofline": roofline,

@@ -978,3 +978,51 @@ def test_step_forms_evict_staging_left_between_launches(ctx, plum, schedule):
     for b in bs:
         b.destroy()
     rig.close()
+
+
+_BENCH_SHAPES = [(gc.SCHED_STEP, t, p, 4) for t, p in STEP_SHAPES] + [(gc.SCHED_ROUNDS, t, p, wv) for t, p, wv in ROUNDS_SHAPES]
+
+
+@pytest.fixture(scope="module")
+def plum_full():
+    return W.nbody_plummer()
+
+
+@pytest.mark.parametrize("schedule,tile,tpl,waves", _BENCH_SHAPES)
+def test_bench_configuration_every_timed_shape(ctx, plum_full, schedule, tile, tpl, waves):
+    # the timed step exactly: Plummer 262,144, 32 Poisson(2048) rounds wrapping the tree order, half of
+    # all particles resident at random slots (seed 5000), PACK, evicting fixture; every shape the bench
+    # may time gives bitwise the per-round launches of that shape, and sampled tasks match the oracle
+    import torch
+    w = plum_full
+    print(f"[gpu] bench configuration schedule={schedule} tile={tile} tpl={tpl} waves={waves}", flush=True)
+    rig = GravRig(ctx, w)
+    rounds = W.poisson_rounds(w.n_tasks, 2048, seed=1002, n_rounds=32)
+    bts = [W.task_subset(w, r) for r in rounds]
+    bs = [rig.batch(bt) for bt in bts]
+    _set_base(rig, W.residency(np.arange(w.n), w.n, 0.5, seed=5000))
+    base_so = rig.pool.query()
+    eager = _eager_rounds(rig, bs, gc.grav_params(order=2, tile=tile, targets_per_lane=tpl, waves_per_block=waves))
+    assert np.array_equal(rig.pool.query(), base_so)
+    s = torch.cuda.Stream()
+    prm = gc.grav_params(order=2, schedule=schedule, tile=tile, targets_per_lane=tpl, waves_per_block=waves)
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), prm, rig.nodes, rig.acc, stream=s,
+                 fixture=gc.FIXTURE_EVICT_STAGED)
+    for rep in range(2):
+        rig.acc.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        got = rig.acc.cpu().numpy()
+        assert np.array_equal(np.isnan(got), np.isnan(eager)), rep
+        assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)]), rep
+        assert np.array_equal(rig.pool.query(), base_so), rep
+    g.status(stream=s)
+    sel = np.random.default_rng(9).choice(np.concatenate(rounds), size=48, replace=False)
+    sub = W.task_subset(w, np.unique(sel))
+    err = rel_l2_per_task(got, O.grav_workload(w, order=2, tasks=sub), sub)
+    assert err.max() <= TOL, err.max()
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()

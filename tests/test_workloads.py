@@ -100,3 +100,19 @@ def test_rounds_and_residency():
     ids, slots = W.residency(U, 500, 0.5, seed=6)
     assert ids.size == 50 and np.unique(ids).size == 50 and np.all(np.isin(ids, U))
     assert np.unique(slots).size == 50 and slots.max() < 500
+
+
+def test_wrapped_rounds_are_consecutive_modulo_the_task_count():
+    one = W.poisson_rounds(27026, 2048, seed=1002)
+    many = W.poisson_rounds(27026, 2048, seed=1002, n_rounds=32)
+    assert len(many) == 32
+    flat = np.concatenate(many)
+    # consecutive tasks in tree order, wrapping from the last task to the first
+    assert np.all(np.diff(flat) % 27026 == 1)
+    assert flat[0] == 0
+    # the rounds before the first wrap are those of the single pass
+    k = 0
+    while many[k][-1] >= many[k][0] and k + 1 < len(one):
+        assert np.array_equal(many[k], one[k])
+        k += 1
+    assert k >= 12

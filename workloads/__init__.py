@@ -263,14 +263,23 @@ def task_subset(w: GravWorkload, sel: np.ndarray) -> dict:
                 ranges=np.ascontiguousarray(ranges, np.int32).reshape(-1, 2))
 
 
-def poisson_rounds(n_tasks: int, mean: float, seed: int) -> list[np.ndarray]:
-    """Consecutive task rounds (tree order) of Poisson(mean) size (at least 1) covering every task once."""
+def poisson_rounds(n_tasks: int, mean: float, seed: int, n_rounds: int | None = None) -> list[np.ndarray]:
+    """Consecutive task rounds (tree order) of Poisson(mean) size (at least 1).  Without n_rounds: rounds
+    until every task is covered once.  With n_rounds: exactly that many, wrapping from the last task to
+    the first (a round that wraps holds the tail and then the head of the order); the first rounds are
+    the same as without it."""
     rng = np.random.default_rng(seed)
     out, t = [], 0
-    while t < n_tasks:
-        k = max(1, int(rng.poisson(mean)))
-        out.append(np.arange(t, min(n_tasks, t + k), dtype=np.int64))
-        t += k
+    if n_rounds is None:
+        while t < n_tasks:
+            k = max(1, int(rng.poisson(mean)))
+            out.append(np.arange(t, min(n_tasks, t + k), dtype=np.int64))
+            t += k
+        return out
+    for _ in range(n_rounds):
+        k = min(max(1, int(rng.poisson(mean))), n_tasks)
+        out.append((t + np.arange(k, dtype=np.int64)) % n_tasks)
+        t = (t + k) % n_tasks
     return out
 
 

@@ -57,7 +57,7 @@ def _load():
                             I32, I32, I64]
     lib.or_lj_tasks.argtypes = [i32, I32, I32, I32, I32, I32, F32, F32, i64, i32, F64, F64, F64, dbl, F64, F64, I64]
     lib.or_lj_brute.argtypes = [i64, F32, F64, F64, F64, F64, dbl, F64, F64]
-    lib.or_ewald.argtypes = [i64, F64, dbl, dbl, dbl, F64, dbl, i32, i32, F64, F64]
+    lib.or_ewald.argtypes = [i64, F64, dbl, dbl, dbl, F64, F64, dbl, i32, i32, F64, F64]
     lib.or_bh_walk.argtypes = [i32, I32, I32, F64, F64, F32, i32, I32, dbl, I32, I32, I64, I64, I32, I32]
     lib.or_vjp_grav_mono.argtypes = [i32, I32, I32, I32, I32, I32, I32, I32, I32, i32, I32, F64, F64, F64, dbl, dbl,
                                      F64, i64, F64, F64]
@@ -219,15 +219,18 @@ def lj_tasks(w, potential: bool = False, tasks: dict | None = None):
     return (acc, pot, int(cnt[0])) if potential else acc
 
 
-def ewald(pos, L: float, G: float, M: float, com, alpha: float, nrep: int, hmax2: int, potential: bool = False):
-    """Ewald correction of periodic gravity at each position (see oracle.c): acc (n x 3) [, phi (n)]."""
+def ewald(pos, L: float, G: float, M: float, com, alpha: float, nrep: int, hmax2: int, potential: bool = False,
+          S=None):
+    """Ewald correction of periodic gravity at each position (see oracle.c): acc (n x 3) [, phi (n)].
+    S: the box's second moment about com (xx, yy, zz, xy, xz, yz), or None for the monopole alone."""
     lib = _load()
     pos = _d(pos)
     n = pos.shape[0]
     acc = np.empty((n, 3))
     pot = np.empty(n) if potential else None
-    lib.or_ewald(n, _p(pos, F64), float(L), float(G), float(M), _p(_d(com), F64), float(alpha), int(nrep), int(hmax2),
-                 _p(acc, F64), _p(pot, F64) if potential else None)
+    Sd = None if S is None else _d(np.asarray(S, dtype=np.float64).reshape(6))
+    lib.or_ewald(n, _p(pos, F64), float(L), float(G), float(M), _p(_d(com), F64), _p(Sd, F64) if S is not None else None,
+                 float(alpha), int(nrep), int(hmax2), _p(acc, F64), _p(pot, F64) if potential else None)
     return (acc, pot) if potential else acc
 
 

@@ -19,8 +19,9 @@
  *    masses, per-type eps/sigma);
  *  - the Ewald correction of periodic gravity (ChaNGa's second combined
  *    kernel, Sec. 4.1, Sec. 4.3): the pull of every periodic image of the box's
- *    total mass M at its centre of mass c, plus the neutralising background,
- *    minus the direct 1/r of the central copy that the tree walk computes.
+ *    total mass M at its centre of mass c (optionally expanded to the box's
+ *    second moment about c), plus the neutralising background, minus the
+ *    direct pull of the central copy that the tree walk computes.
  *  - the Barnes-Hut interaction lists of each bucket's work request (Sec. 4.1),
  *    a recursive descent from the definition of the opening test.
  *
@@ -33,6 +34,9 @@
  *   a(x) = -grad phi = G M [ sum_{n != 0} -(erfc(alpha s)/s^3 + 2 alpha/sqrt(pi) e^{-alpha^2 s^2}/s^2) s_vec
  *                           + (erf(alpha s)/s^3 - 2 alpha/sqrt(pi) e^{-alpha^2 s^2}/s^2) s_vec   (n = 0)
  *                           - 2/L^2 sum_h exp(-pi^2 |h|^2/(alpha L)^2)/|h|^2 sin(2 pi h.r/L) h ].
+ * With the box's second moment S about c (optional), psi~ = -phi / (G M) above is expanded to
+ * second order: phi -= G/2 S_ab d_a d_b psi~ and a += G/2 S_ab grad d_a d_b psi~, every image and
+ * wave vector differentiated termwise.
  * The n = 0 terms take their Taylor series near s = 0 (erf(x)/x^3 - 2/sqrt(pi)
  * e^{-x^2}/x^2 = 2/sqrt(pi) (2/3 - 2/5 x^2 + 1/7 x^4 - 1/27 x^6 + 1/132 x^8 - ...),
  * (erfc(x) - 1)/x = -2/sqrt(pi) (1 - x^2/3 + x^4/10 - x^6/42 + ...)), where the
@@ -666,9 +670,51 @@ static double ew_g0(double x) {
   return (erfc(x) - 1.0) / x;
 }
 
-/* acc (n x 3) = the Ewald correction at each position; pot (optional, n) its potential phi. */
-void or_ewald(int64_t n, const double* pos, double L, double G, double M, const double* c, double alpha, int32_t nrep,
-              int32_t hmax2, double* acc, double* pot) {
+/* v_out = S v for a symmetric S stored as (xx, yy, zz, xy, xz, yz). */
+static void quad_apply(const double* S, const double* v, double* out) {
+  out[0] = S[0] * v[0] + S[3] * v[1] + S[4] * v[2];
+  out[1] = S[3] * v[0] + S[1] * v[1] + S[5] * v[2];
+  out[2] = S[4] * v[0] + S[5] * v[1] + S[2] * v[2];
+}
+
+/* Radial derivatives of the Ewald kernels, B_l = (-(1/s) d/ds)^l B_0 for l = 1..3, so that
+ * d_a B_0 = -B_1 s_a, d_a d_b B_0 = -delta_ab B_1 + s_a s_b B_2 and
+ * d_a d_b d_c B_0 = (delta_ab s_c + delta_ac s_b + delta_bc s_a) B_2 - s_a s_b s_c B_3.
+ * Differentiating B_0 = erfc(alpha s)/s once more each time gives the recursion
+ * B_l = ((2l - 1) B_{l-1} + (2 alpha^2)^l / (alpha sqrt(pi)) e^{-alpha^2 s^2}) / s^2.
+ * For the central copy the kernel is -erf(alpha s)/s (erfc - 1: its direct 1/s removed), which
+ * obeys the same recursion (1/s alone obeys it without the exponential) but cancels near s = 0;
+ * there it takes its series, from erf's: -(2/sqrt(pi)) 2^l alpha^{2l+1}
+ * sum_j (-1)^j x^{2j} / (j! (2j + 2l + 1)), x = alpha s. */
+static void ew_radial(double s, double alpha, int central, double B[4]) {
+  const double x = alpha * s;
+  if (central && x < 1.0) {
+    for (int l = 0; l < 4; ++l) {
+      double sum = 0.0, term = 1.0; /* term = (-1)^j x^{2j} / j! */
+      for (int j = 0; j < 40; ++j) {
+        sum += term / (2 * j + 2 * l + 1);
+        term *= -x * x / (j + 1);
+      }
+      B[l] = -(2.0 / sqrt(M_PI)) * pow(2.0, l) * pow(alpha, 2 * l + 1) * sum;
+    }
+    return;
+  }
+  const double e = exp(-x * x) / (alpha * sqrt(M_PI));
+  B[0] = central ? -erf(x) / s : erfc(x) / s;
+  double t = 1.0;
+  for (int l = 1; l < 4; ++l) {
+    t *= 2.0 * alpha * alpha;
+    B[l] = ((2 * l - 1) * B[l - 1] + t * e) / (s * s);
+  }
+}
+
+/* acc (n x 3) = the Ewald correction at each position; pot (optional, n) its potential phi.
+ * S (optional, xx yy zz xy xz yz) = the box's second moment about c, sum_j m_j d_j d_j^T: the
+ * potential kernel psi~ (the sum above, per unit mass) is expanded to second order about c,
+ * phi = -G (M psi~ + 1/2 S_ab d_a d_b psi~), a = G grad(M psi~ + 1/2 S_ab d_a d_b psi~), the
+ * images taking the derivatives of the same real-space and wave-vector terms. */
+void or_ewald(int64_t n, const double* pos, double L, double G, double M, const double* c, const double* S,
+              double alpha, int32_t nrep, int32_t hmax2, double* acc, double* pot) {
   const double sp = 2.0 / sqrt(M_PI);
   int hm = 0;
   while ((hm + 1) * (hm + 1) <= hmax2) ++hm;
@@ -680,6 +726,7 @@ void or_ewald(int64_t n, const double* pos, double L, double G, double M, const 
       r[d] -= L * nearbyint(r[d] / L);
     }
     double a[3] = {0, 0, 0}, p = 0;
+    double aq[3] = {0, 0, 0}, pq = 0; /* the second-moment terms, without G */
     for (int nx = -nrep; nx <= nrep; ++nx)
       for (int ny = -nrep; ny <= nrep; ++ny)
         for (int nz = -nrep; nz <= nrep; ++nz) {
@@ -695,6 +742,15 @@ void or_ewald(int64_t n, const double* pos, double L, double G, double M, const 
           }
           for (int d = 0; d < 3; ++d) a[d] += k * sv[d];
           p += q;
+          if (S) {
+            double B[4];
+            ew_radial(s, alpha, nx == 0 && ny == 0 && nz == 0, B);
+            double Ss[3];
+            quad_apply(S, sv, Ss);
+            const double sSs = sv[0] * Ss[0] + sv[1] * Ss[1] + sv[2] * Ss[2], tr = S[0] + S[1] + S[2];
+            for (int d = 0; d < 3; ++d) aq[d] += 0.5 * (tr * sv[d] + 2.0 * Ss[d]) * B[2] - 0.5 * sSs * sv[d] * B[3];
+            pq += 0.5 * (-tr * B[1] + sSs * B[2]);
+          }
         }
     for (int hx = -hm; hx <= hm; ++hx)
       for (int hy = -hm; hy <= hm; ++hy)
@@ -708,10 +764,18 @@ void or_ewald(int64_t n, const double* pos, double L, double G, double M, const 
           a[1] += -2.0 / (L * L) * w * sn * hy;
           a[2] += -2.0 / (L * L) * w * sn * hz;
           p += w * cos(th) / (M_PI * L);
+          if (S) {
+            const double hv[3] = {hx, hy, hz};
+            double Sh[3];
+            quad_apply(S, hv, Sh);
+            const double hSh = hx * Sh[0] + hy * Sh[1] + hz * Sh[2];
+            for (int d = 0; d < 3; ++d) aq[d] += 4.0 * M_PI * M_PI / (L * L * L * L) * w * hSh * sn * hv[d];
+            pq += -2.0 * M_PI / (L * L * L) * w * hSh * cos(th);
+          }
         }
     p -= M_PI / (alpha * alpha * L * L * L);
-    for (int d = 0; d < 3; ++d) acc[3 * i + d] = G * M * a[d];
-    if (pot) pot[i] = -G * M * p;
+    for (int d = 0; d < 3; ++d) acc[3 * i + d] = G * M * a[d] + G * aq[d];
+    if (pot) pot[i] = -G * M * p - G * pq;
   }
 }
 

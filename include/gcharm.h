@@ -650,8 +650,21 @@ gc_status gc_occupancy(gc_ctx ctx, const gc_force_params* prm, int32_t* blocks_p
  *           + (erf(alpha s)/s^3 - 2 alpha/sqrt(pi) e^{-alpha^2 s^2}/s^2) s_vec   (n = 0)
  *           - 2/L^2 sum_h e^{-pi^2 |h|^2/(alpha L)^2}/|h|^2 sin(2 pi h.r/L) h ],
  * s_vec = r + n L over images n in {-nrep..nrep}^3 and wave vectors h in Z^3
- * with 0 < |h|^2 <= hmax2.  alpha = 0 takes 2 / L.  Valid: L > 0, alpha >= 0,
- * 0 <= nrep <= 4, 0 <= hmax2 <= 64 (GC_E_INVAL otherwise).
+ * with 0 < |h|^2 <= hmax2.  alpha = 0 takes 2 / L.
+ *
+ * S (xx, yy, zz, xy, xz, yz) is the box's second moment about com,
+ * sum_j m_j (x_j - com)(x_j - com)^T; all zeros (the default) gives the
+ * monopole alone.  Otherwise the same kernel psi~ (a = G M grad psi~ above)
+ * is expanded to second order about com: a += G/2 S_ab grad d_a d_b psi~,
+ * which per real-space image s_vec adds
+ *   G [ 1/2 (tr(S) s_vec + 2 S s_vec) B_2(s) - 1/2 (s_vec.S.s_vec) s_vec B_3(s) ],
+ *   B_l = ((2l - 1) B_{l-1} + (2 alpha^2)^l / (alpha sqrt(pi)) e^{-alpha^2 s^2}) / s^2,
+ *   B_0 = erfc(alpha s)/s for n != 0 and -erf(alpha s)/s for n = 0 (there from
+ *   its series below alpha s = 1),
+ * and per wave vector
+ *   G 4 pi^2 / L^4 e^{-pi^2 |h|^2/(alpha L)^2}/|h|^2 (h.S.h) sin(2 pi h.r/L) h.
+ * Valid: L > 0, alpha >= 0, 0 <= nrep <= 4, 0 <= hmax2 <= 64, S finite
+ * (GC_E_INVAL otherwise).
  */
 typedef struct {
   float L, G, M;
@@ -659,6 +672,7 @@ typedef struct {
   float alpha;
   int32_t nrep;
   int32_t hmax2;
+  float S[6];
 } gc_ewald_params;
 
 /*

@@ -50,17 +50,22 @@ EXPORTED = ["gc_version", "gc_init", "gc_finalize", "gc_last_error", "gc_debug_i
 
 
 class EwaldParams(ctypes.Structure):
-    """gc_ewald_params: box side, G, total mass, centre of mass, alpha (0: 2 / L), images, |h|^2 bound."""
+    """gc_ewald_params: box side, G, total mass, centre of mass, alpha (0: 2 / L), images, |h|^2 bound,
+    second moment about the centre of mass (xx, yy, zz, xy, xz, yz; zeros: monopole only)."""
     _fields_ = [("L", ctypes.c_float), ("G", ctypes.c_float), ("M", ctypes.c_float), ("com", ctypes.c_float * 3),
-                ("alpha", ctypes.c_float), ("nrep", ctypes.c_int32), ("hmax2", ctypes.c_int32)]
+                ("alpha", ctypes.c_float), ("nrep", ctypes.c_int32), ("hmax2", ctypes.c_int32),
+                ("S", ctypes.c_float * 6)]
 
 
 def ewald_params(L: float, M: float, com, G: float = 1.0, alpha: float = 0.0, nrep: int = 1,
-                 hmax2: int = 10) -> EwaldParams:
+                 hmax2: int = 10, S=None) -> EwaldParams:
     p = EwaldParams()
     p.L, p.G, p.M, p.alpha, p.nrep, p.hmax2 = float(L), float(G), float(M), float(alpha), int(nrep), int(hmax2)
     for d in range(3):
         p.com[d] = float(com[d])
+    if S is not None:
+        for k in range(6):
+            p.S[k] = float(S[k])
     return p
 
 

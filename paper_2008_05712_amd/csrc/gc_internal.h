@@ -202,6 +202,9 @@ struct EwaldArgs {
   int32_t nrep, hmax, hmax2;
   float kcoef;             // -2 G M / L^2
   float kdecay;            // pi^2 / (alpha L)^2
+  bool quad;               // second-moment terms (S not all zero)
+  float GS[6];             // G S: xx yy zz xy xz yz
+  float qcoef;             // 4 pi^2 / L^4
 };
 hipError_t launch_ewald(const EwaldArgs& a, hipStream_t s);
 

@@ -1664,9 +1664,12 @@ extern "C" gc_status gc_launch_ewald(gc_batch b, const gc_ewald_params* prm, flo
   GC_ENTER(c);
   if (!prm || !acc_dev) return set_err(c, GC_E_INVAL, "gc_launch_ewald: NULL argument");
   if (b->kind != GC_KIND_GRAV) return set_err(c, GC_E_INVAL, "gc_launch_ewald: gravity batches only");
+  bool s_finite = true;
+  for (int k = 0; k < 6; ++k) s_finite = s_finite && std::isfinite(prm->S[k]);
   if (!(prm->L > 0.f) || !(prm->alpha >= 0.f) || prm->nrep < 0 || prm->nrep > 4 || prm->hmax2 < 0 ||
-      prm->hmax2 > kEwaldMaxHmax2)
-    return set_err(c, GC_E_INVAL, "gc_launch_ewald: need L > 0, alpha >= 0, 0 <= nrep <= 4, 0 <= hmax2 <= %d",
+      prm->hmax2 > kEwaldMaxHmax2 || !s_finite)
+    return set_err(c, GC_E_INVAL,
+                   "gc_launch_ewald: need L > 0, alpha >= 0, 0 <= nrep <= 4, 0 <= hmax2 <= %d, finite S",
                    kEwaldMaxHmax2);
   if (b->mode < 0 || !b->pool) return set_err(c, GC_E_STATE, "gc_launch_ewald: batch not reorganised");
   if (lists_mode(b->mode)) return set_err(c, GC_E_UNSUPPORTED, "gc_launch_ewald: PACK, REDUNDANT or NONE");
@@ -1691,6 +1694,13 @@ extern "C" gc_status gc_launch_ewald(gc_batch b, const gc_ewald_params* prm, flo
   a.kcoef = -2.f * a.GM / (prm->L * prm->L);
   const double aL = (double)a.alpha * prm->L;
   a.kdecay = (float)(M_PI * M_PI / (aL * aL));
+  a.quad = false;
+  for (int k = 0; k < 6; ++k) {
+    a.GS[k] = prm->G * prm->S[k];
+    a.quad = a.quad || prm->S[k] != 0.f;
+  }
+  const double L2 = (double)prm->L * prm->L;
+  a.qcoef = (float)(4.0 * M_PI * M_PI / (L2 * L2));
   GC_HIP(c, launch_ewald(a, S(stream)));
   if (b->host_staged) GC_HIP(c, b->ev_use.record(S(stream)));
   return GC_OK;

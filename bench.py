@@ -640,7 +640,37 @@ def cpu_baseline(W, w, rounds, args):
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     return {"value": nint * reps / dt / 1e9, "unit": "G-interactions/s", "cores": min(cores, threads), "kind": "oracle",
             "sample": f"first {ns} of {len(rounds)} rounds ({len(sample)} bucket tasks, {nint} interactions), "
-                      f"FP64, evaluated {reps} times in {dt:.1f} s"}
+                      f"FP64, evaluated {reps} times in {dt:.1f} s",
+            "one_thread_uniform_4096": cpu_one_thread_small()}
+
+
+# run in a child process so that its OpenMP runtime starts with one thread; it touches no GPU
+_ONE_THREAD = """
+import json, time, numpy as np, oracle as O, workloads as W
+w = W.nbody_tiny()
+ic = w.i_count.astype(np.int64)
+nint = int(np.sum(ic * (w.direct_counts().astype(np.int64) - 1 + w.n_count)))
+reps, dt = 0, 0.0
+while reps == 0 or (dt < 2.0 and reps < 200):
+    tc = time.perf_counter()
+    O.grav_workload(w, order=1)
+    dt += time.perf_counter() - tc
+    reps += 1
+print(json.dumps({"value": nint * reps / dt / 1e9, "reps": reps, "seconds": dt, "interactions": nint}))
+"""
+
+
+def cpu_one_thread_small():
+    """The oracle on one thread over every task of nbody-uniform-4096 (monopole)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-c", _ONE_THREAD], env=env, capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-300:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": round(d["value"], 4), "unit": "G-interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"every task of nbody-uniform-4096 ({d['interactions']} interactions, monopole), FP64, "
+                      f"evaluated {d['reps']} times in {d['seconds']:.1f} s"}
 
 
 def main():

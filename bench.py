@@ -698,7 +698,7 @@ def main():
     ap.add_argument("--step-schedule", default="", choices=["", "step", "rounds"],
                     help="only the whole-step launch or only the rounds form (default: the faster)")
     ap.add_argument("--leg", default="", choices=["", "reorg-stress", "staging", "rebuild", "lj", "instances",
-                                                  "combined", "ewald"],
+                                                  "combined", "ewald", "adjoint"],
                     help="run one measurement leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -715,11 +715,11 @@ def main():
                  redundant=gc.REORG_REDUNDANT, none=gc.REORG_NONE)
     mode = modes[args.mode]
 
-    if args.leg in ("reorg-stress", "lj", "instances", "ewald"):
+    if args.leg in ("reorg-stress", "lj", "instances", "ewald", "adjoint"):
         ctx = gc.Context(0)
         fn = {"reorg-stress": lambda: leg_reorg_stress(gc, torch, ctx), "lj": lambda: leg_lj(gc, W, torch, ctx),
               "instances": lambda: leg_instances(gc, W, torch, ctx, args),
-              "ewald": lambda: leg_ewald(gc, W, torch, ctx)}[args.leg]
+              "ewald": lambda: leg_ewald(gc, W, torch, ctx), "adjoint": lambda: leg_adjoint(gc, W, torch, ctx)}[args.leg]
         print(json.dumps({"leg": args.leg, **fn()}), flush=True)
         ctx.close()
         return

@@ -695,6 +695,7 @@ def main():
     ap.add_argument("--targets-per-lane", type=int, default=0, help="with --tile: 1, 2 or 3 (per task) targets per lane")
     ap.add_argument("--step-tile", type=int, default=0, help="fixed tile of the whole-step launch instead of timing 256, 320 and 384")
     ap.add_argument("--step-tpl", type=int, default=0, help="fixed targets per lane of the step forms instead of timing the tested ones")
+    ap.add_argument("--step-waves", type=int, default=0, help="fixed waves per task of the step forms instead of timing the tested ones")
     ap.add_argument("--step-schedule", default="", choices=["", "step", "rounds"],
                     help="only the whole-step launch or only the rounds form (default: the faster)")
     ap.add_argument("--leg", default="", choices=["", "reorg-stress", "staging", "rebuild", "lj", "instances",
@@ -868,23 +869,29 @@ def main():
         cands = [(gc.SCHED_STEP, tl, tp, 4) for tl, tp in STEP_SHAPES] + \
                 [(gc.SCHED_ROUNDS, tl, tp, wv) for tl, tp, wv in ROUNDS_SHAPES]
         cands = [c for c in cands if (not args.step_tile or c[1] == args.step_tile) and
-                 (not args.step_tpl or c[2] == args.step_tpl) and
+                 (not args.step_tpl or c[2] == args.step_tpl) and (not args.step_waves or c[3] == args.step_waves) and
                  (not args.step_schedule or c[0] == {"step": gc.SCHED_STEP, "rounds": gc.SCHED_ROUNDS}[args.step_schedule])]
         if not cands:
-            log(f"[bench] --step-tile {args.step_tile} --step-tpl {args.step_tpl} --step-schedule {args.step_schedule}: "
+            log(f"[bench] --step-tile {args.step_tile} --step-tpl {args.step_tpl} --step-waves {args.step_waves} "
+                f"--step-schedule {args.step_schedule}: "
                 f"not a tested shape {STEP_SHAPES} / {ROUNDS_SHAPES}")
             sys.exit(2)
+        # every candidate captured, then timed in three interleaved passes (the best of the three per
+        # shape), so that a drift of the clock during the sweep does not pick the shape
+        graphs = []
         for sc, tl, tp, wv in cands:
             p = gc.grav_params(order=2, G=1.0, eps=0.01, schedule=sc, tile=tl, targets_per_lane=tp, waves_per_block=wv)
-            g = capture("step", p)
-            ms = round(time_kernel(lambda: g.launch(stream=stream), stream, reps=10), 4)
             name = "step" if sc == gc.SCHED_STEP else f"rounds_w{wv}"
-            step_shapes[f"{name}_tile{tl}_tpl{tp}"] = ms
-            if best_ms is None or ms < best_ms:
-                if step_graph is not None:
-                    step_graph.destroy()
-                sprm, step_graph, best_ms = p, g, ms
-            else:
+            graphs.append((f"{name}_tile{tl}_tpl{tp}", p, capture("step", p)))
+        for _ in range(3):
+            for name, p, g in graphs:
+                ms = round(time_kernel(lambda: g.launch(stream=stream), stream, reps=10), 4)
+                step_shapes[name] = min(ms, step_shapes.get(name, ms))
+        for name, p, g in graphs:
+            if best_ms is None or step_shapes[name] < best_ms:
+                sprm, step_graph, best_ms = p, g, step_shapes[name]
+        for name, p, g in graphs:
+            if g is not step_graph:
                 g.destroy()
         forms["step_graph_ms_by_shape"] = step_shapes
     log(f"[bench] forms: {forms}")
@@ -1050,17 +1057,14 @@ def main():
                            f"(tile {prm.tile}, {prm.waves_per_block} waves per task, {tpl} targets per lane)",
                  "kernel_ms_per_step": round(kern_ms, 4), "avg_launch_ms": round(kern_ms / R, 5),
                  "tflops": round(achieved_tflops, 3), "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-                 "traffic": profiled_traffic("k_grav_quad_plummer262144_traffic",
-                                             {"tile": prm.tile, "waves_per_block": prm.waves_per_block,
-                                              "schedule": prm.schedule, "targets_per_lane": tpl})}
+                 "traffic": None}  # counters are taken for the timed form's kernels only
     if form == "step":
         # the dominant (and only) kernel of a step: algorithmic flop of the whole step over its duration
         step_tflops = flops_step / (step_kernel_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(step_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(step_tflops / PEAK_FP32_TFLOPS, 4),
-                    "traffic": profiled_traffic("k_step_quad_plummer262144_traffic",
-                                                {"tile": sprm.tile, "targets_per_lane": sprm.targets_per_lane})
-                    if sprm.schedule == gc.SCHED_STEP else
+                    # counters are taken for the rounds form, the one timed on this workload
+                    "traffic": None if sprm.schedule == gc.SCHED_STEP else
                     profiled_traffic("k_grav_rounds_quad_plummer262144_traffic",
                                      {"tile": sprm.tile, "targets_per_lane": sprm.targets_per_lane,
                                       "waves_per_block": sprm.waves_per_block}),

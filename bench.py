@@ -699,7 +699,7 @@ def main():
     ap.add_argument("--step-schedule", default="", choices=["", "step", "rounds"],
                     help="only the whole-step launch or only the rounds form (default: the faster)")
     ap.add_argument("--leg", default="", choices=["", "reorg-stress", "staging", "rebuild", "lj", "instances",
-                                                  "combined", "ewald", "adjoint"],
+                                                  "combined", "ewald", "adjoint", "walk"],
                     help="run one measurement leg alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -762,6 +762,10 @@ def main():
                                                           tpl=b2.targets_per_lane, aggregation=b2.aggregation),
                           "ms": {n: round(float(x), 4) for n, x in zip(names, t2)},
                           "aggregation_ms": [round(float(x), 4) for x in t2[36:]]}), flush=True)
+        return
+    if args.leg == "walk":
+        print(json.dumps({"leg": "walk", **leg_walk(gc, W, torch, ctx, w)}), flush=True)
+        ctx.close()
         return
     if args.leg in ("staging", "rebuild"):
         p2 = gc.grav_params(order=2, G=1.0, eps=0.01, tile=320, targets_per_lane=2)

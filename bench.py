@@ -43,7 +43,7 @@ STEP_SHAPES = ((256, 1), (256, 2), (320, 1), (320, 2), (384, 1), (384, 2))
 # time; the GPU tests check every one of them against the per-round launches and the oracle
 TPL_TEXT = {0: "one target per lane", 1: "one target per lane", 2: "two targets per lane",
             3: "one or two targets per lane, whichever fills more lanes for the task"}
-ROUNDS_SHAPES = ((256, 1, 2), (256, 2, 2), (256, 3, 2), (256, 2, 4), (512, 2, 2))
+ROUNDS_SHAPES = ((256, 1, 2), (256, 2, 2), (256, 3, 2), (256, 3, 1), (256, 2, 4), (512, 2, 2))
 
 
 def flop_counts() -> dict:

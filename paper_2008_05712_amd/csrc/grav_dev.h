@@ -13,8 +13,9 @@
 // exactly C iterations with no per-iteration bounds test; a lane reads its
 // slice's records from LDS (lanes of one slice read the same address: an LDS
 // broadcast).  Node records of the next tile are prefetched into registers
-// while the current tile is computed.  Per tile each lane sums its slice in
-// FP32 and adds the tile's partial to an FP64 running sum; at the end the
+// while the current tile is computed.  Each lane sums its slices in FP32 and
+// adds that partial to an FP64 running sum once it holds 64 or more terms (a
+// tile of more terms on its own), and at the end of the chunk; at the end the
 // slices and then the waves of each target are reduced in FP64 through LDS in
 // a fixed order and the target's float4 is written once.  No atomics: results
 // are bitwise independent of task order and of the schedule.
@@ -190,6 +191,9 @@ __device__ __forceinline__ void quad_term(const float4 a, const float4 b, const 
   ay = __builtin_fmaf(r5, sy, __builtin_fmaf(cf, dy, ay));
   az = __builtin_fmaf(r5, sz, __builtin_fmaf(cf, dz, az));
 }
+
+// Terms per lane summed in FP32 before they are added into the FP64 sums of a target chunk.
+constexpr int kFlushTerms = 64;
 
 // Two targets per lane: each record read from LDS serves both (half the LDS reads per interaction,
 // two independent dependency chains per lane).
@@ -387,26 +391,38 @@ __device__ __forceinline__ void grav_task_body(const GravArgs& a, const int t, c
       }
     }
     double Ax = 0.0, Ay = 0.0, Az = 0.0, Bx = 0.0, By = 0.0, Bz = 0.0, Ap = 0.0;
+    // FP32 sums carried across tiles and added into the FP64 ones once they hold kFlushTerms terms
+    // or more per lane (a run stays below kFlushTerms + C terms, and a tile of C >= kFlushTerms
+    // terms is added on its own), and before the reduction
+    Acc2 f{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float fp = 0.f;
+    int fcnt = 0;  // uniform
+    auto flush = [&]() {
+      Ax += f.ax; Ay += f.ay; Az += f.az;
+      if (two) {
+        Bx += f.bx; By += f.by; Bz += f.bz;
+      }
+      if (POT) Ap += fp;
+      f = Acc2{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      fp = 0.f;
+      fcnt = 0;
+    };
     // one tile of C records per slice starting at L + rec_stride * sl * C: accumulate it
     auto tile_sum = [&](int C, bool quads) {
-      if (!active) return;
-      if (two) {
-        Acc2 r{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (quads) tile_quads2(L + __mul24(sl3, C), C, A, B, a.eps2, r);
-        else tile_pairs2(L + __mul24(sl, C), C, A, B, a.eps2, r);
-        Ax += r.ax; Ay += r.ay; Az += r.az;
-        Bx += r.bx; By += r.by; Bz += r.bz;
-      } else if (POT) {
-        float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-        if (quads) tile_quads_pot(L + __mul24(sl3, C), C, A.x, A.y, A.z, a.eps2, ax, ay, az, ph);
-        else tile_pairs_pot(L + __mul24(sl, C), C, A.x, A.y, A.z, a.eps2, ax, ay, az, ph);
-        Ax += ax; Ay += ay; Az += az; Ap += ph;
-      } else {
-        float ax = 0.f, ay = 0.f, az = 0.f;
-        if (quads) tile_quads(L + __mul24(sl3, C), C, A.x, A.y, A.z, a.eps2, ax, ay, az);
-        else tile_pairs(L + __mul24(sl, C), C, A.x, A.y, A.z, a.eps2, ax, ay, az);
-        Ax += ax; Ay += ay; Az += az;
+      if (active) {
+        if (two) {
+          if (quads) tile_quads2(L + __mul24(sl3, C), C, A, B, a.eps2, f);
+          else tile_pairs2(L + __mul24(sl, C), C, A, B, a.eps2, f);
+        } else if (POT) {
+          if (quads) tile_quads_pot(L + __mul24(sl3, C), C, A.x, A.y, A.z, a.eps2, f.ax, f.ay, f.az, fp);
+          else tile_pairs_pot(L + __mul24(sl, C), C, A.x, A.y, A.z, a.eps2, f.ax, f.ay, f.az, fp);
+        } else {
+          if (quads) tile_quads(L + __mul24(sl3, C), C, A.x, A.y, A.z, a.eps2, f.ax, f.ay, f.az);
+          else tile_pairs(L + __mul24(sl, C), C, A.x, A.y, A.z, a.eps2, f.ax, f.ay, f.az);
+        }
       }
+      fcnt += C;
+      if (fcnt >= kFlushTerms) flush();
     };
 
     // ---- node terms: this wave's nodes are list entries w, w + W, ...
@@ -497,6 +513,7 @@ __device__ __forceinline__ void grav_task_body(const GravArgs& a, const int t, c
     }
 
     // ---- reduce: slices within the wave, then the W waves, in a fixed order
+    flush();
     double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
     if (two) {
       // 6 sums per lane: the tile area is free now

@@ -1078,7 +1078,8 @@ def main():
                     if sprm.schedule == gc.SCHED_STEP else
                     (f"k_step<2, 1, false> (every round's reorganisation and eviction; no force code) + "
                      f"k_grav_rounds<2, {sprm.targets_per_lane}> (one combined quadrupole pass over every round's "
-                     f"tasks; tile {sprm.tile}, {sprm.waves_per_block} waves per task, {TPL_TEXT[sprm.targets_per_lane]}), "
+                     f"tasks; tile {sprm.tile}, {sprm.waves_per_block} wave{'s' if sprm.waves_per_block > 1 else ''} per task, "
+                     f"{TPL_TEXT[sprm.targets_per_lane]}), "
                      f"timed together: the step's whole device time"),
                     "flops_per_launch": flops_step, "avg_launch_ms": round(step_kernel_ms, 5),
                     "frac_of_nonpacked_peak": round(step_tflops / PEAK_FP32_NONPACKED_TFLOPS, 4)}

@@ -73,9 +73,9 @@ __device__ __forceinline__ int wave_excl_scan(int v, int* total) {
   return inc - v;
 }
 
-// One workgroup of 4 wavefronts per task: wave w takes the task's nodes w, w + 4, ... and the
-// flat direct positions of every fourth group of 64; source gradients go to the visits' records and
-// target gradients are added with atomics, so the waves need no reduction among themselves.
+// One workgroup of W wavefronts per task (1 to 4): wave w takes the task's nodes w, w + W, ... and
+// the flat direct positions of every W-th group of 64; source gradients go to the visits' records
+// and target gradients are added with atomics, so the waves need no reduction among themselves.
 template <bool PACKED, int ORDER>
 __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
   // targets per register block: six with quadrupole nodes keep the kernel at three wavefronts per SIMD
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) k_grav_adj(GravAdjArgs A) {
   __shared__ int ro[4][64], rb[4][64];
   const int lane = threadIdx.x & 63;
   const int wid = uniform(threadIdx.x >> 6);
-  const int W = 4;
+  const int W = uniform(blockDim.x >> 6);  // 1 to 4
   const int t = uniform(blockIdx.x);
   if (t >= a.n_tasks) return;
   const gc_task tk = a.tasks[t];
@@ -851,15 +851,16 @@ __global__ void k_lj_mass_grad(const float4* __restrict__ cot, const float4* __r
 }  // namespace
 
 hipError_t launch_grav_adjoint(bool packed, int order, const GravAdjArgs& a, int wpb, hipStream_t s) {
-  (void)wpb;
   if (a.f.n_tasks <= 0) return hipSuccess;
+  if (wpb < 1 || wpb > 4) return hipErrorInvalidValue;
   const int grid = a.f.n_tasks;
+  const dim3 block(64 * wpb);
   if (order == 2) {
-    if (packed) hipLaunchKernelGGL((k_grav_adj<true, 2>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_grav_adj<false, 2>), dim3(grid), dim3(256), 0, s, a);
+    if (packed) hipLaunchKernelGGL((k_grav_adj<true, 2>), dim3(grid), block, 0, s, a);
+    else hipLaunchKernelGGL((k_grav_adj<false, 2>), dim3(grid), block, 0, s, a);
   } else {
-    if (packed) hipLaunchKernelGGL((k_grav_adj<true, 1>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_grav_adj<false, 1>), dim3(grid), dim3(256), 0, s, a);
+    if (packed) hipLaunchKernelGGL((k_grav_adj<true, 1>), dim3(grid), block, 0, s, a);
+    else hipLaunchKernelGGL((k_grav_adj<false, 1>), dim3(grid), block, 0, s, a);
   }
   return hipGetLastError();
 }

@@ -1821,7 +1821,8 @@ extern "C" gc_status gc_backward(gc_batch b, const gc_force_params* prm, const f
     a.joff = b->d_joff.as<int32_t>();
     a.vnode = b->vnode.as<float4>();
     a.vdir = b->vdir.as<float4>();
-    GC_HIP(c, launch_grav_adjoint(packed, order, a, 4, s));
+    // waves per task, measured on Plummer 262,144 (quadrupole) and uniform 4,096 (monopole)
+    GC_HIP(c, launch_grav_adjoint(packed, order, a, order == 2 ? 2 : 4, s));
     if (b->n_direct > 0)
       GC_HIP(c, launch_direct_sums(a.vdir, b->dvis.as<int32_t>(), b->dkey.as<int32_t>(), (int32_t)b->n_direct,
                                    a.gpos, gmass_dev, s));

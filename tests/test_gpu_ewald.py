@@ -100,3 +100,31 @@ def test_ewald_rejects_bad_parameters(ctx):
         assert e.value.status == 1
     b.destroy()
     rig.close()
+
+
+@pytest.mark.parametrize("mode", [gc.REORG_NONE, gc.REORG_PACK])
+def test_ewald_full_size_uniform_262144_sampled(ctx, mode):
+    # the workload the bench times (262,144 uniform targets, buckets of 32, nrep 1, |h|^2 <= 10, the box's
+    # own second moment), checked on 4,096 sampled targets against the oracle
+    print(f"[gpu] ewald uniform-262144 mode {mode} sampled", flush=True)
+    w = W.build_grav(W.uniform_cube(262144, 1005), bucket=32, theta=0.7)
+    m = w.rec[:, 3].astype(np.float64)
+    com = ((w.rec[:, :3].astype(np.float64) * m[:, None]).sum(0) / m.sum()).astype(np.float32)
+    d = w.rec[:, :3].astype(np.float64) - com.astype(np.float64)
+    S2 = np.einsum("j,ja,jb->ab", m, d, d)
+    S = np.array([S2[0, 0], S2[1, 1], S2[2, 2], S2[0, 1], S2[0, 2], S2[1, 2]], dtype=np.float32)
+    M = float(np.float32(m.sum()))
+    rig = GravRig(ctx, w)
+    b = rig.batch(whole(w))
+    b.reorganize(rig.pool, mode)
+    rig.acc.zero_()
+    b.ewald(gc.ewald_params(1.0, M, com, nrep=1, hmax2=10, S=S), rig.acc)
+    rig.torch.cuda.synchronize()
+    acc = rig.acc.cpu().numpy()[:, :3].astype(np.float64)
+    ids = np.random.default_rng(77).choice(w.n, size=4096, replace=False)
+    ref = O.ewald(w.rec[ids, :3], 1.0, 1.0, M, com.astype(np.float64), 2.0, 1, 10, S=S.astype(np.float64))
+    err = np.linalg.norm(acc[ids] - ref) / np.linalg.norm(ref)
+    assert err <= TOL, err
+    assert np.abs(acc[ids] - ref).max() <= TOL * np.abs(ref).max()
+    b.destroy()
+    rig.close()

@@ -786,6 +786,7 @@ def test_potential_refusals(ctx, plum):
 
 @pytest.mark.parametrize("shape", [dict(tile=256, targets_per_lane=1, schedule=0),
                                    dict(tile=256, targets_per_lane=2, schedule=1),
+                                   dict(tile=128, waves_per_block=2, targets_per_lane=1, schedule=1),
                                    dict(tile=512, targets_per_lane=2, schedule=0, aggregation=5000)])
 def test_sixty_four_instances_in_one_launch_sampled(ctx, shape):
     # every task of the 64 instances (4.2 M particles, 450 k tasks) in one launch, with the launch

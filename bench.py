@@ -206,6 +206,49 @@ def leg_instances(gc, W, torch, ctx, args):
     return res
 
 
+def lj_kept_evaluations(w) -> int:
+    """Pair evaluations of the gather form after its candidate pruning, counted on the host with the
+    kernel's rule: per target cell, the sources (the other cell of each of its tasks, in the cell's
+    frame: x_j + shift on the i side, x_i - shift on the j side) within r_c of the bounding box of the
+    cell's atoms (squared distance at most 1.001 r_c^2), times the cell's atom count; a self task
+    evaluates all its atoms.  Padding slots of the tiles are not counted."""
+    pos = w.rec[:, :3].astype(np.float64)
+    ic = w.i_count.astype(np.int64)
+    jc = w.j_count.astype(np.int64)
+    selfm = w.self_flag != 0
+    # each cell's bounding box, from its self task's range
+    cb, cn = w.i_begin[selfm].astype(np.int64), ic[selfm]
+    starts = np.zeros(w.n, np.int64) - 1
+    starts[cb] = np.arange(cb.size)
+    cell_of = np.maximum.accumulate(starts)  # cells are contiguous id ranges in id order
+    lo = np.full((cb.size, 3), np.inf)
+    hi = np.full((cb.size, 3), -np.inf)
+    np.minimum.at(lo, cell_of, pos)
+    np.maximum.at(hi, cell_of, pos)
+    rc2 = float(w.rcut) ** 2 * 1.001
+    total = int(np.sum(ic[selfm] * ic[selfm]))
+    cross = np.nonzero(~selfm)[0]
+    sh = w.shift.astype(np.float64)
+    for side in (0, 1):  # 0: the i cell is the target, sources from j; 1: the reverse
+        tb = (w.i_begin if side == 0 else w.j_begin)[cross].astype(np.int64)
+        tn = (ic if side == 0 else jc)[cross]
+        sb = (w.j_begin if side == 0 else w.i_begin)[cross].astype(np.int64)
+        sn = (jc if side == 0 else ic)[cross]
+        sgn = 1.0 if side == 0 else -1.0
+        for c0 in range(0, cross.size, 200000):
+            sl = slice(c0, c0 + 200000)
+            n = sn[sl]
+            task = np.repeat(np.arange(n.size), n)
+            first = np.repeat(np.cumsum(n) - n, n)
+            atom = np.repeat(sb[sl], n) + (np.arange(task.size) - first)
+            p = pos[atom] + sgn * sh[cross[sl]][task]
+            cell = cell_of[tb[sl]][task]
+            d = np.maximum(np.maximum(lo[cell] - p, p - hi[cell]), 0.0)
+            kept = np.bincount(task, weights=((d * d).sum(1) <= rc2).astype(np.float64), minlength=n.size)
+            total += int(np.sum(kept.astype(np.int64) * tn[sl]))
+    return total
+
+
 def leg_lj(gc, W, torch, ctx):
     """1,048,576 LJ atoms (FCC, half-box thinned), one combined cell-pair launch per step."""
     t0 = time.time()
@@ -236,15 +279,17 @@ def leg_lj(gc, W, torch, ctx):
     cand = w.candidates()
     out.update({"candidates": cand, "candidates_per_s_G": round(cand / (ms * 1e-3) / 1e9, 3), "ms": ms})
     # the gather form evaluates a pair of two different cells from both sides and a cell's self task
-    # over all its atoms (the atom itself gives a zero separation): pair evaluations per launch, and
-    # the VALU issue they take at LJ_VALU_PER_EVAL wavefront-lane slots each (the one-type loop) as a
-    # fraction of the chip's issue rate, 4 cycles per wavefront instruction per SIMD
+    # over all its atoms (the atom itself gives a zero separation), less what its pruning leaves out:
+    # pair evaluations per launch, and the VALU issue they take at LJ_VALU_PER_EVAL wavefront-lane
+    # slots each (the one-type loop) as a fraction of the chip's issue rate, 4 cycles per wavefront
+    # instruction per SIMD
     ic = w.i_count.astype(np.int64)
     jc = w.j_count.astype(np.int64)
-    evals = int(np.sum(np.where(w.self_flag != 0, ic * ic, 2 * ic * jc)))
+    unpruned = int(np.sum(np.where(w.self_flag != 0, ic * ic, 2 * ic * jc)))
+    evals = lj_kept_evaluations(w)
     issue_ms = evals * LJ_VALU_PER_EVAL / 64 * 4 / (N_SIMD * CLOCK_GHZ * 1e9) * 1e3
-    out.update({"pair_evaluations": evals, "valu_issue_ms": round(issue_ms, 4),
-                "valu_issue_frac": round(issue_ms / ms, 4)})
+    out.update({"pair_evaluations": evals, "pair_evaluations_unpruned": unpruned,
+                "valu_issue_ms": round(issue_ms, 4), "valu_issue_frac": round(issue_ms / ms, 4)})
     # the algorithmic work: pairs inside the cutoff (counted on the device with the pass's FP32
     # decision), FLOPS_LJ flop each with both atoms updated
     pairs = b.lj_count_pairs(w.rcut)

@@ -38,6 +38,17 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 template <bool PERSIST>
 __global__ void __launch_bounds__(256) k_lj(LJArgs a) {
   __shared__ float2 tab[kMaxTypes * kMaxTypes];              // (24 eps_ij, sigma_ij^2)
@@ -185,6 +196,13 @@ __global__ void __launch_bounds__(256) k_lj(LJArgs a) {
 // The per-task shift sits on the source when staged (x_j + b, or x_i + (-a)); on the target side
 // it is added per pair, only in cells that have tasks across the periodic boundary (x + (-a) and
 // x - a round alike).  A zero separation is the atom itself (a cell's self task) and adds nothing.
+//
+// Candidates are pruned as they are staged: a source whose distance from the bounding box of the
+// wavefront's target atoms (in the targets' frame, the source's position less its task's target
+// shift) exceeds r_c is within r_c of none of them and is left out; the survivors of each staged
+// group of up to 64 sources are compacted into the tile in their order.  The test keeps a source
+// up to (1 + 1e-3) r_c^2 from the box, far beyond FP32 rounding, so no pair that the cutoff
+// decision accepts is dropped; the decision itself is unchanged.
 constexpr int kGTile = 64;   // source records per LDS tile per wavefront
 constexpr int kEGroup = 32;  // tasks whose sources a wavefront stages at a time
 constexpr float kFar = 1e18f;  // padding sources: r^2 ~ 3e36, finite and outside any cutoff
@@ -273,6 +291,12 @@ __global__ void __launch_bounds__(256) k_lj_gather(LJArgs a) {
       const float2* trow = tab + ti * a.n_types;
       float Fx = 0.f, Fy = 0.f, Fz = 0.f;
       const int DT = S * (kGTile / S);
+      // the targets' bounding box (lanes without a target are neutral)
+      const float blx = wave_min(active ? tx : kFar), bly = wave_min(active ? ty : kFar),
+                  blz = wave_min(active ? tz : kFar);
+      const float bhx = wave_max(active ? tx : -kFar), bhy = wave_max(active ? ty : -kFar),
+                  bhz = wave_max(active ? tz : -kFar);
+      const float keep2 = a.rc2 * 1.001f;
       for (int eg = 0; eg < ne; eg += kEGroup) {
         const int nen = ne - eg < kEGroup ? ne - eg : kEGroup;
         int n = 0, sb = 0;
@@ -310,29 +334,43 @@ __global__ void __launch_bounds__(256) k_lj_gather(LJArgs a) {
         }
         wave_sync();
         for (int ws = 0; ws < total; ws += DT) {
+          // one source per lane (DT <= 64): staged, tested, and the survivors compacted
           const int c = total - ws < DT ? total - ws : DT;
-          const int C = (c + S - 1) / S;
-          const int padded = S * C;
-          for (int e = lane; e < padded; e += 64) {
-            float4 v = make_float4(kFar, kFar, kFar, 0.f), o = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (e < c) {
-              const int f = ws + e;
-              int lo = 0, hi = nen - 1;
-              while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (eoff[wid][mid] <= f) lo = mid;
-                else hi = mid - 1;
-              }
-              const float4 r = gld(a.rec + ebeg[wid][lo] + (f - eoff[wid][lo]));
-              const float4 q = esh[wid][lo];
-              v = make_float4(r.x + q.x, r.y + q.y, r.z + q.z, r.w);
-              o = eto[wid][lo];
+          float4 v = make_float4(kFar, kFar, kFar, 0.f), o = make_float4(0.f, 0.f, 0.f, 0.f);
+          bool keep = false;
+          if (lane < c) {
+            const int f = ws + lane;
+            int lo = 0, hi = nen - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (eoff[wid][mid] <= f) lo = mid;
+              else hi = mid - 1;
             }
-            src[wid][e] = v;
-            if (shifted) tof[wid][e] = o;
+            const float4 r = gld(a.rec + ebeg[wid][lo] + (f - eoff[wid][lo]));
+            const float4 q = esh[wid][lo];
+            v = make_float4(r.x + q.x, r.y + q.y, r.z + q.z, r.w);
+            o = eto[wid][lo];
+            const float px = v.x - o.x, py = v.y - o.y, pz = v.z - o.z;
+            const float dx = fmaxf(fmaxf(blx - px, px - bhx), 0.f);
+            const float dy = fmaxf(fmaxf(bly - py, py - bhy), 0.f);
+            const float dz = fmaxf(fmaxf(blz - pz, pz - bhz), 0.f);
+            keep = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)) <= keep2;
+          }
+          const uint64_t km = __ballot(keep);
+          const int kc = uniform(__popcll(km));
+          const int C = (kc + S - 1) / S;
+          const int padded = S * C;
+          if (keep) {
+            const int k = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+            src[wid][k] = v;
+            if (shifted) tof[wid][k] = o;
+          }
+          if (lane >= kc && lane < padded) {
+            src[wid][lane] = make_float4(kFar, kFar, kFar, 0.f);
+            if (shifted) tof[wid][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
           }
           wave_sync();
-          if (active) {
+          if (active && C > 0) {
             if (shifted)
               gather_tile<true, ONE>(&src[wid][sl * C], &tof[wid][sl * C], C, tx, ty, tz, trow, p0, a.rc2, Fx, Fy, Fz);
             else

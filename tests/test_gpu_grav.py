@@ -835,6 +835,59 @@ def _eager_rounds(rig, bs, prm, evict=True):
     return rig.acc.cpu().numpy()
 
 
+@pytest.mark.parametrize("schedule", [gc.SCHED_STEP, gc.SCHED_ROUNDS])
+def test_step_forms_with_an_empty_round_and_a_fully_resident_round(ctx, plum, schedule):
+    # degenerate rounds inside one captured step: round 1 has no tasks at all, round 3's every record
+    # is resident (nothing missing, nothing staged); both one-graph forms give the per-round
+    # launches' bits and the oracle's maps, and leave the base residency in the pool
+    import torch
+    print(f"[gpu] degenerate rounds schedule={schedule}", flush=True)
+    rig = GravRig(ctx, plum)
+    rounds = W.poisson_rounds(plum.n_tasks, 500, seed=42)[:3]
+    bts = [W.task_subset(plum, r) for r in rounds]
+    empty = gc.Batch(ctx, gc.KIND_GRAV, plum.n)
+    empty.submit(np.zeros(0, gc.TASK_DTYPE), np.zeros((0, 2), np.int32), np.zeros(0, np.int32))
+    empty.commit()
+    bs = [rig.batch(bts[0]), empty, rig.batch(bts[1]), rig.batch(bts[2])]
+    # base residency: 40 % of all ids at random slots, plus every id of the last round
+    ids, slots = W.residency(np.arange(plum.n), plum.n, 0.4, seed=43)
+    extra = np.setdiff1d(W.batch_union(bts[2]), ids).astype(np.int32)
+    free = np.setdiff1d(np.arange(plum.n), slots)
+    extra_slots = np.random.default_rng(44).choice(free, size=extra.size, replace=False).astype(np.int32)
+    order_ = np.argsort(np.concatenate([ids, extra]))
+    base = (np.concatenate([ids, extra])[order_], np.concatenate([slots, extra_slots])[order_])
+    _set_base(rig, base)
+    base_so = rig.pool.query()
+    prm = dict(order=2, tile=256, targets_per_lane=3 if schedule == gc.SCHED_ROUNDS else 2,
+               waves_per_block=1 if schedule == gc.SCHED_ROUNDS else 4)
+    eager = _eager_rounds(rig, bs, gc.grav_params(**prm))
+    ref = O.grav_workload(plum, order=2)
+    for bt in bts:
+        assert rel_l2_per_task(eager, ref, bt).max() <= TOL
+    assert np.array_equal(rig.pool.query(), base_so)
+    s = torch.cuda.Stream()
+    g = gc.Graph(ctx, bs, [rig.pool] * len(bs), [gc.REORG_PACK] * len(bs), gc.grav_params(schedule=schedule, **prm),
+                 rig.nodes, rig.acc, stream=s, fixture=gc.FIXTURE_EVICT_STAGED)
+    for rep in range(2):
+        rig.acc.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.launch(stream=s)
+        s.synchronize()
+        got = rig.acc.cpu().numpy()
+        assert np.array_equal(np.isnan(got), np.isnan(eager)), rep
+        assert np.array_equal(got[~np.isnan(got)], eager[~np.isnan(eager)]), rep
+        for k, bt in ((0, bts[0]), (2, bts[1]), (3, bts[2])):
+            want = O.maps(bt, plum.n, plum.n, base_so, gc.REORG_PACK)
+            _check_maps(bs[k].maps(), want, gc.REORG_PACK)
+        assert bs[3].maps()["missing"].size == 0
+        assert np.array_equal(rig.pool.query(), base_so), rep
+    g.status(stream=s)
+    g.destroy()
+    for b in bs:
+        b.destroy()
+    rig.close()
+
+
 @pytest.mark.parametrize("tile,tpl,waves", ROUNDS_SHAPES)
 @pytest.mark.parametrize("order", [1, 2])
 def test_rounds_schedule_matches_per_round_launches(ctx, plum, order, tile, tpl, waves):

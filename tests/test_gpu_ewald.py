@@ -35,7 +35,7 @@ S_ANISO = np.array([0.021, 0.008, 0.013, 0.004, -0.006, 0.0025], dtype=np.float3
 
 
 @pytest.mark.parametrize("mode", [gc.REORG_NONE, gc.REORG_PACK])
-@pytest.mark.parametrize("alpha,nrep,hmax2", [(0.0, 1, 10), (2.6, 2, 20), (3.0, 0, 4)])
+@pytest.mark.parametrize("alpha,nrep,hmax2", [(0.0, 1, 10), (2.6, 2, 20), (3.0, 0, 4), (2.0, 4, 64)])
 @pytest.mark.parametrize("second_moment", [False, True])
 def test_ewald_matches_oracle(ctx, mode, alpha, nrep, hmax2, second_moment):
     print(f"[gpu] ewald uniform-4096 mode {mode} alpha {alpha} nrep {nrep} hmax2 {hmax2} S {second_moment}",

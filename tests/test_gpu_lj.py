@@ -89,6 +89,22 @@ def test_lj_fcc_modulated_medium_and_persistent(ctx):
     rig.close()
 
 
+def test_lj_cells_of_more_than_64_atoms(ctx):
+    # r_c = 5 puts 93 to 165 atoms in a cell: the gather form takes each cell's targets in chunks of
+    # 64, each chunk with its own bounding box for the candidate pruning
+    xyz, v, L = W.fcc_modulated(16, 14, 14, 0.8442, 11000, seed=81)
+    w = W.build_lj(xyz, W.two_types(xyz.shape[0], 12), L, 5.0, **W.LJ_TWO_TYPES)
+    nc = np.diff(w.cell_start)
+    assert nc.max() > 128 and nc[nc > 0].min() > 64
+    rig = LJRig(ctx, w)
+    ref = O.lj_tasks(w)
+    for mode, sched in ((gc.REORG_NONE, 0), (gc.REORG_NONE, 1), (gc.REORG_PACK, 0)):
+        acc = rig.run(mode, schedule=sched)
+        err = per_cell(acc, ref, w)
+        assert err.max() <= TOL, (mode, sched, err.max())
+    rig.close()
+
+
 def test_lj_full_size_one_step(ctx):
     w = W.lj_fcc()
     print(f"[gpu] lj full N={w.n} tasks={w.n_tasks}", flush=True)

@@ -55,6 +55,17 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -738,6 +749,13 @@ __global__ void __launch_bounds__(256) k_lj_adj_gather(LJAdjArgs A) {
       pa.zero();
       float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       const int DT = S * (kGTile / S);
+      // candidates pruned against the targets' bounding box as in the forward gather (every term of a
+      // pair outside the cutoff is zero, so a source beyond r_c of the box adds nothing)
+      const float blx = wave_min(active ? tx : kFar), bly = wave_min(active ? ty : kFar),
+                  blz = wave_min(active ? tz : kFar);
+      const float bhx = wave_max(active ? tx : -kFar), bhy = wave_max(active ? ty : -kFar),
+                  bhz = wave_max(active ? tz : -kFar);
+      const float keep2 = a.rc2 * 1.001f;
       for (int eg = 0; eg < ne; eg += kEGroup) {
         const int nen = ne - eg < kEGroup ? ne - eg : kEGroup;
         int n = 0, sb = 0, sid = 0;
@@ -779,34 +797,51 @@ __global__ void __launch_bounds__(256) k_lj_adj_gather(LJAdjArgs A) {
         }
         wave_sync();
         for (int ws = 0; ws < total; ws += DT) {
+          // one source per lane (DT <= 64): staged, tested, and the survivors compacted
           const int c = total - ws < DT ? total - ws : DT;
-          const int C = (c + S - 1) / S;
-          const int padded = S * C;
-          for (int e = lane; e < padded; e += 64) {
-            float4 v = make_float4(kFar, kFar, kFar, 0.f), hv = make_float4(0.f, 0.f, 0.f, 0.f), o = hv;
-            if (e < c) {
-              const int f = ws + e;
-              int lo = 0, hi = nen - 1;
-              while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (eoff[wid][mid] <= f) lo = mid;
-                else hi = mid - 1;
-              }
-              const int k = f - eoff[wid][lo];
-              const float4 r = dev::gld(a.rec + ebeg[wid][lo] + k);
-              const float4 q = esh[wid][lo];
-              v = make_float4(r.x + q.x, r.y + q.y, r.z + q.z, r.w);
+          float4 v = make_float4(kFar, kFar, kFar, 0.f), hv = make_float4(0.f, 0.f, 0.f, 0.f), o = hv;
+          bool keep = false;
+          if (lane < c) {
+            const int f = ws + lane;
+            int lo = 0, hi = nen - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (eoff[wid][mid] <= f) lo = mid;
+              else hi = mid - 1;
+            }
+            const int k = f - eoff[wid][lo];
+            const float4 r = dev::gld(a.rec + ebeg[wid][lo] + k);
+            const float4 q = esh[wid][lo];
+            v = make_float4(r.x + q.x, r.y + q.y, r.z + q.z, r.w);
+            o = eto[wid][lo];
+            const float px = v.x - o.x, py = v.y - o.y, pz = v.z - o.z;
+            const float dx = fmaxf(fmaxf(blx - px, px - bhx), 0.f);
+            const float dy = fmaxf(fmaxf(bly - py, py - bhy), 0.f);
+            const float dz = fmaxf(fmaxf(blz - pz, pz - bhz), 0.f);
+            keep = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)) <= keep2;
+            if (keep) {
               const float4 gs = dev::gld(A.cot + ebid[wid][lo] + k);
               const float ms = A.mass_t[(int)r.w];
               hv = make_float4(gs.x / ms, gs.y / ms, gs.z / ms, 0.f);
-              o = eto[wid][lo];
             }
-            src[e] = v;
-            hsr[e] = hv;
-            if (shifted) tof[e] = o;
+          }
+          const uint64_t km = __ballot(keep);
+          const int kc = uniform(__popcll(km));
+          const int C = (kc + S - 1) / S;
+          const int padded = S * C;
+          if (keep) {
+            const int kk = __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u));
+            src[kk] = v;
+            hsr[kk] = hv;
+            if (shifted) tof[kk] = o;
+          }
+          if (lane >= kc && lane < padded) {
+            src[lane] = make_float4(kFar, kFar, kFar, 0.f);
+            hsr[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (shifted) tof[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
           }
           wave_sync();
-          if (active) {
+          if (active && C > 0) {
             if (shifted)
               adj_gather_tile<NT, true>(src + sl * C, hsr + sl * C, tof + sl * C, C, tx, ty, tz, hx,
                                         hy, hz, trow, p0, a.rc2, acc, pa, pg_row);
